@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Benchmark of the NMC hot path on one MI355X.
+
+One step = the whole path on the random 4-SAT workload N = 50,000 variables,
+alpha = 9.9 (M = 495,000 clauses), 1024 replicas: replica init and energy
+count, a homogeneous anneal of 2000 sweeps (beta 0.1 -> 4.0), then 3 rounds of
+[backbone estimate (|magnetization| >= 0.9, frozen variables and their clause
+neighbours hot) -> reanneal of 1000 sweeps (cold at beta 4.0, hot ramped
+0.5 -> 4.0)], then the best-energy tally.  The instance is uploaded to HBM
+before the timed region.
+
+Prints one JSON line: attempts/s of the whole step, the sweep kernel's
+roofline figures (kernel time from HIP events on the launch stream), the
+time-to-target against plain simulated annealing on the same GPU, and the CPU
+oracle's rate on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2111_13628_amd import instances  # noqa: E402
+
+N, ALPHA, K, R = 50000, "9.9", 4, 1024
+S_ANNEAL, ROUNDS, S_RE = 2000, 3, 1000
+BETA0, BETA1, BETA_HOT = 0.1, 4.0, 0.5
+CLASS_CAP = 1024
+# VALU lane-operations the sweep kernel issues per (variable, clause slot) for
+# its 4 replicas, and per variable for the acceptance step; see the design doc.
+OPS_PER_SLOT = 10.0
+OPS_PER_VAR = 48.0
+PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock
+
+
+def reanneal_profile(S):
+    return instances.profile_schedule(np.full(S, BETA1), instances.linear_schedule(BETA_HOT, BETA1, S))
+
+
+def run_path(inst, seed, target, nmc, stream=None, profile=False):
+    rep = nmc.Replicas(inst, R, seed, stream)
+    rep.set_profiling(profile)
+    rep.anneal(instances.linear_schedule(BETA0, BETA1, S_ANNEAL)[None, :], target=target, stream=stream)
+    hot = []
+    for _ in range(ROUNDS):
+        rep.estimate_backbone_device(9, 10, True, stream=stream)
+        rep.reanneal(reanneal_profile(S_RE), "backbone", target=target, stream=stream)
+    be = rep.best_energy(stream=stream)
+    return rep, be
+
+
+def cpu_baseline(cp, lits, seed):
+    import oracle
+
+    threads = max(1, min(16, os.cpu_count() or 1))
+    ok = oracle.KSat(N, cp, lits)
+    _, order, _ = ok.color(CLASS_CAP)
+    Rs = 4 * threads
+    rep = oracle.KSatReplicas(ok, Rs, seed, order, threads=threads, snapshot=True)
+    sweeps = 2
+    t0 = time.perf_counter()
+    rep.anneal(instances.linear_schedule(BETA0, BETA1, S_ANNEAL)[None, :sweeps])
+    dt = time.perf_counter() - t0
+    att = Rs * N * sweeps
+    return {"value": att / dt, "unit": "attempts/s", "cores": threads, "kind": "oracle",
+            "sample": f"{Rs} replicas x {sweeps} anneal sweeps of the N=50000 instance ({att:.3g} attempts, "
+                      f"{dt:.1f} s wall on {threads} threads, {platform.processor() or platform.machine()})"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ttt", action="store_true")
+    ap.add_argument("--block-threads", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the replica-parallel path "
+              f"shards by replicas, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2111_13628_amd import nmc
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    seed = instances.DEFAULT_SEED
+    cp, lits = instances.gen_ksat(N, ALPHA, K, seed)
+    inst = nmc.Instance.ksat(N, cp, lits, CLASS_CAP).bind()
+    M = inst.info.n_clauses
+    attempts = float(R) * N * (S_ANNEAL + ROUNDS * S_RE)
+
+    for w in range(args.warmup):
+        run_path(inst, seed + 1000 + w, -1, nmc)
+    torch.cuda.synchronize()
+
+    times = []
+    last = None
+    for s in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep, be = run_path(inst, seed + s, -1, nmc)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        last = (rep, be)
+    ms_per_step = 1000.0 * float(np.mean(times))
+
+    # sweep-kernel time from HIP events on the launch stream (separate pass)
+    prep, _ = run_path(inst, seed, -1, nmc, profile=True)
+    kt = prep.kernel_time()
+    kern_ms = kt["ms"] / max(1, kt["launches"])
+    att_per_launch = kt["attempts"] / max(1, kt["launches"])
+    deg_mean = K * M / N
+    ops_per_attempt = (OPS_PER_SLOT * deg_mean + OPS_PER_VAR) / 4.0
+    achieved = att_per_launch * ops_per_attempt / (kern_ms / 1000.0)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                "unit": "T lane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                "kernel": "ksat_sweep_kernel", "kernel_ms_per_launch": kern_ms,
+                "kernel_attempts_per_s": kt["attempts"] / (kt["ms"] / 1000.0),
+                "launches": kt["launches"]}
+    del prep
+
+    out = {
+        "metric": "spin-flip attempts/s (whole NMC path) + time-to-target vs plain SA on 1 GPU",
+        "value": attempts / (ms_per_step / 1000.0),
+        "unit": "attempts/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "NMC random 4-SAT N=50000 alpha=9.9 M=495000, 1024 replicas, "
+                               "anneal 2000 + 3x(backbone + reanneal 1000)",
+                   "n_vars": N, "n_clauses": M, "k": K, "replicas": R,
+                   "sweeps": S_ANNEAL + ROUNDS * S_RE, "class_cap": CLASS_CAP,
+                   "colors": inst.info.n_colors, "parallelism": "replicas"},
+        "best_energy": last[1]["best"], "replicas_at_zero": last[1]["n_at_zero"],
+        "roofline": roofline,
+    }
+
+    if not args.no_ttt:
+        # time-to-target: target = 10th percentile of final energies of a
+        # calibration plain-SA run (other seed); plain SA = homogeneous
+        # 0.1 -> 4.0 over the same 5000 sweeps and replicas.
+        S_tot = S_ANNEAL + ROUNDS * S_RE
+        cal = nmc.Replicas(inst, R, seed + 777)
+        cal.anneal(instances.linear_schedule(BETA0, BETA1, S_tot)[None, :])
+        target = int(np.percentile(cal.best_energy()["energy"], 10))
+        del cal
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sa = nmc.Replicas(inst, R, seed)
+        sa.set_profiling(True)
+        sa.anneal(instances.linear_schedule(BETA0, BETA1, S_tot)[None, :], target=target)
+        sbe = sa.best_energy()
+        sa_s = time.perf_counter() - t0
+        nrep, nbe = run_path(inst, seed, target, nmc)
+        torch.cuda.synchronize()
+        def ttt(fh, s_per_sweep):
+            hit = fh[fh >= 0]
+            return None if hit.size == 0 else float(hit.min()) * s_per_sweep
+        out["time_to_target"] = {
+            "target_energy": target, "target_rule": "10th percentile of calibration plain-SA final energies",
+            "nmc_s": ttt(nbe["first_hit"], ms_per_step / 1000.0 / S_tot),
+            "plain_sa_s": ttt(sbe["first_hit"], sa_s / S_tot),
+            "time_rule": "first sweep boundary with a replica at or below target x measured seconds per sweep",
+            "nmc_first_hit_sweep": int(nbe["first_hit"][nbe["first_hit"] >= 0].min()) if (nbe["first_hit"] >= 0).any() else None,
+            "sa_first_hit_sweep": int(sbe["first_hit"][sbe["first_hit"] >= 0].min()) if (sbe["first_hit"] >= 0).any() else None,
+            "nmc_best": nbe["best"], "plain_sa_best": sbe["best"],
+            "nmc_replicas_hit": int((nbe["first_hit"] >= 0).sum()), "sa_replicas_hit": int((sbe["first_hit"] >= 0).sum()),
+            "ratio_ref": f"paper target ratio 1e-4 * M = {int(1e-4 * M)} violations",
+        }
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cp, lits, seed)
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

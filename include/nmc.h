@@ -1,0 +1,254 @@
+/*
+ * nmc.h -- C ABI of the MI355X (gfx950) Nonequilibrium Monte Carlo hot path.
+ *
+ * Paper: "Nonequilibrium Monte Carlo for unfreezing variables in hard
+ * combinatorial optimization" (arXiv 2111.13628).  The library runs many
+ * independent replicas of single-variable (k-SAT) or pairwise-swap (QAP)
+ * Metropolis Markov chains on the GPU, with one inverse temperature per
+ * variable class; estimates frozen ("backbone") variables from statistics
+ * across replicas; turns them into a two-class temperature profile; and
+ * re-anneals from the current states (Algorithm 1 "Nonequilibrium Monte
+ * Carlo", section "Nonequilibrium inhomogeneous sampling over subgraphs",
+ * appendix B "Sampling localized replicas by Monte Carlo").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every function returns an int status: NMC_OK (0) or a negative NMC_ERR_*
+ *    code; nmc_last_error() then returns a message for the calling thread.
+ *    No C++ exception crosses the ABI.
+ *  - Host arrays passed in are read during the call only (the library copies
+ *    what it keeps).  Host arrays passed out are written before the call
+ *    returns; such calls synchronize the given stream.
+ *  - Device memory for instances and replica sets is owned by the caller:
+ *    nmc_footprint() gives the byte sizes, the caller allocates (e.g. torch
+ *    tensors on cuda:0) and passes raw device pointers.  The library never
+ *    frees caller memory.  The library owns only a small per-replica-set
+ *    table buffer (acceptance thresholds), released by nmc_replicas_free().
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on
+ *    it in call order; calls on one replica set must not overlap in time.
+ *  - Energies are exact integers: the k-SAT energy is the number of violated
+ *    clauses, the QAP cost is sum_ij F_ij D_{p_i p_j} (int64 at the ABI).
+ *  - Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key = the
+ *    replica set's 64-bit seed (low word first) and counter = (item, sweep,
+ *    replica / 4, stream); replica r uses output word r mod 4.  Streams:
+ *    0 k-SAT sweep (item = variable), 1 k-SAT init (item = variable, sweep 0),
+ *    2 QAP sweep (item = pair rank), 3 QAP init (item = Fisher-Yates step).
+ *    Results are a deterministic function of (instance, seed, schedule,
+ *    profile, call sequence): no result depends on tuning, launch shape or on
+ *    other work sharing the GPU.
+ */
+#ifndef NMC_H
+#define NMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum nmc_status {
+    NMC_OK = 0,
+    NMC_ERR_INVALID = -1,     /* malformed argument (bad literal, NULL pointer, bad range) */
+    NMC_ERR_SIZE = -2,        /* a buffer is smaller than required */
+    NMC_ERR_DEVICE = -3,      /* a HIP runtime call failed */
+    NMC_ERR_STATE = -4,       /* call not valid in the object's current state */
+    NMC_ERR_CAPACITY = -5,    /* does not fit (LDS or configured memory cap) */
+    NMC_ERR_UNSUPPORTED = -6  /* valid input outside what this build supports */
+};
+
+enum nmc_kind { NMC_KIND_KSAT = 1, NMC_KIND_QAP = 2 };
+
+/* Where nmc_anneal takes the class of each variable (k-SAT) or facility (QAP). */
+enum nmc_profile {
+    NMC_PROFILE_HOMOGENEOUS = 0, /* every item in class 0 (plain simulated annealing) */
+    NMC_PROFILE_HOST = 1,        /* class_of[] host array, values < n_classes */
+    NMC_PROFILE_BACKBONE = 2     /* the classes of the last nmc_estimate_backbone() */
+};
+
+/* Which state nmc_get_state() returns. */
+enum nmc_which { NMC_STATE_CURRENT = 0, NMC_STATE_BEST = 1 };
+
+typedef struct nmc_instance nmc_instance;
+typedef struct nmc_replicas nmc_replicas;
+
+typedef struct nmc_instance_info {
+    int32_t kind;            /* NMC_KIND_* */
+    int32_t n_items;         /* k-SAT: variables N; QAP: facilities n */
+    int32_t n_clauses;       /* k-SAT: clauses M; QAP: 0 */
+    int32_t max_clause_len;  /* k-SAT: k_max; QAP: 0 */
+    int32_t max_degree;      /* k-SAT: most clauses on one variable; QAP: n-2 */
+    int32_t n_colors;        /* k-SAT: sweep classes of the colouring; QAP: 1 */
+    int64_t delta_bound;     /* largest |energy change| of one move */
+} nmc_instance_info;
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *nmc_last_error(void);
+/* ABI version (major * 100 + minor). */
+int32_t nmc_version(void);
+
+/* ---------------------------------------------------------------------------
+ * load_instance
+ * ------------------------------------------------------------------------- */
+
+/* Load a CNF formula (subsection "4-SAT Problems Near Computational Phase
+ * Transitions": k-SAT as a conjunction of clauses, each a disjunction of
+ * literals; energy = number of violated clauses).
+ *   n_vars      N >= 1 variables, N <= 65534 (spin tables live in LDS)
+ *   n_clauses   M >= 0
+ *   clause_ptr  M+1 offsets into lits, non-decreasing, clause_ptr[0] = 0
+ *   lits        DIMACS literals: +(v+1) means x_v, -(v+1) means NOT x_v;
+ *               1 <= clause length <= 4, variables distinct within a clause
+ *   class_cap   0 = plain greedy colouring; > 0 caps each colour class at
+ *               that many variables.  The sweep order is the colour-major
+ *               order of this colouring (see nmc_instance_order).
+ * Errors: INVALID (literal 0 or out of range, repeated variable, empty
+ * clause, bad offsets), UNSUPPORTED (clause longer than 4, N > 65534). */
+int nmc_ksat_load(int32_t n_vars, int32_t n_clauses, const int32_t *clause_ptr, const int32_t *lits,
+                  int32_t class_cap, nmc_instance **out);
+
+/* Load a QAP instance (subsection "Quadratic Assignment Problems"):
+ * facilities f are assigned locations p_f, cost sum_ij F_ij D_{p_i p_j}.
+ *   n           2 <= n <= 255
+ *   flow, dist  n*n row-major int32, symmetric, zero diagonal, entries in
+ *               [0, 255] (the device kernels use the symmetric swap formula
+ *               and byte-packed matrices)
+ * Errors: INVALID (asymmetric, nonzero diagonal), UNSUPPORTED (n or an entry
+ * out of range). */
+int nmc_qap_load(int32_t n, const int32_t *flow, const int32_t *dist, nmc_instance **out);
+
+int nmc_instance_get_info(const nmc_instance *inst, nmc_instance_info *out);
+
+/* The k-SAT sweep order: order[p] = variable visited at position p (N
+ * entries); class_ptr[c]..class_ptr[c+1] delimit colour class c (n_colors+1
+ * entries).  Either output may be NULL.  No two variables of one class share
+ * a clause, so the device updates a class in parallel with results identical
+ * to visiting it in this order.  QAP: UNSUPPORTED. */
+int nmc_instance_order(const nmc_instance *inst, int32_t *order, int32_t *class_ptr, int32_t *n_colors);
+
+/* Device bytes the instance needs (bind buffer) and that a replica set of
+ * n_replicas needs (replicas_create buffer). */
+int nmc_footprint(const nmc_instance *inst, int32_t n_replicas, size_t *instance_bytes, size_t *replica_bytes);
+
+/* Upload the instance's device layout into caller memory dev_buf (>= the
+ * footprint's instance_bytes, 256-byte aligned).  Must precede
+ * nmc_replicas_create.  Errors: SIZE, INVALID (misaligned), DEVICE. */
+int nmc_instance_bind(nmc_instance *inst, void *dev_buf, size_t bytes, void *stream);
+
+/* Frees host-side metadata.  Replica sets of the instance must be freed first. */
+void nmc_instance_free(nmc_instance *inst);
+
+/* ---------------------------------------------------------------------------
+ * replicas
+ * ------------------------------------------------------------------------- */
+
+/* Create n_replicas independent chains in dev_buf (>= replica_bytes, 256-byte
+ * aligned).  k-SAT: x_i of replica r is the top bit of its init word for
+ * item i; QAP: Fisher-Yates from the identity with its init words.  Energies
+ * are counted in full; best = energy; first_hit = -1; sweeps_done = 0.
+ * 1 <= n_replicas <= 2^20. */
+int nmc_replicas_create(nmc_instance *inst, int32_t n_replicas, uint64_t seed, void *dev_buf, size_t bytes,
+                        void *stream, nmc_replicas **out);
+void nmc_replicas_free(nmc_replicas *rep);
+
+/* ---------------------------------------------------------------------------
+ * anneal / reanneal
+ * ------------------------------------------------------------------------- */
+
+/* Run n_sweeps Metropolis sweeps on every replica (section "Nonequilibrium
+ * Nonlocal Monte Carlo": simulated annealing when the profile is
+ * homogeneous; section "Nonequilibrium inhomogeneous sampling over
+ * subgraphs" when classes differ).
+ *   beta[c * n_sweeps + s]  inverse temperature of class c at sweep s of this
+ *                           call (host doubles, finite, >= 0)
+ *   n_classes               1..8 rows in beta
+ *   profile, class_of       see nmc_profile; class_of is N (k-SAT) or n (QAP)
+ *                           bytes, used only with NMC_PROFILE_HOST
+ *   target                  first_hit[r] records the first sweep boundary
+ *                           (number of sweeps done) at which replica r's
+ *                           energy is <= target, checked at this call's start
+ *                           and after each sweep; -1 until hit
+ * One sweep: k-SAT visits the variables in nmc_instance_order; QAP proposes
+ * every pair (a < b) in lexicographic order.  A move with energy change
+ * d <= 0 is taken; otherwise the replica's sweep word u is compared with
+ * T = min(2^32-1, floor(2^32 exp(-beta d))) (QAP: the two-level product
+ * (A[d>>10] * B[d&1023]) >> 32 of such thresholds) and the move is taken iff
+ * u < T.  The thresholds are computed on the host in IEEE double.  Energies
+ * are tracked exactly; best energy and the best-state snapshot are updated at
+ * sweep boundaries.  The sweep counter continues across calls, so splitting a
+ * schedule over several calls gives identical results.
+ * Errors: INVALID, STATE (unbound instance; BACKBONE profile without an
+ * estimate), CAPACITY, DEVICE. */
+int nmc_anneal(nmc_replicas *rep, const double *beta, int32_t n_classes, int32_t n_sweeps, int32_t profile,
+               const uint8_t *class_of, int64_t target, void *stream);
+
+/* The reanneal round of Algorithm 1 (inhomogeneous exploration followed by
+ * homogeneous "unlearning"): identical to nmc_anneal, continuing from the
+ * current states and sweep counter; kept as its own name for the API. */
+int nmc_reanneal(nmc_replicas *rep, const double *beta, int32_t n_classes, int32_t n_sweeps, int32_t profile,
+                 const uint8_t *class_of, int64_t target, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * estimate_backbone
+ * ------------------------------------------------------------------------- */
+
+/* Backbone from the current states of all replicas (appendix B: empirical
+ * averages over independent clones; section "Generating backbones of rigid
+ * variables").
+ * k-SAT: c_i = #{r : x_i = 1}; i is frozen iff thr_den * |2 c_i - R| >=
+ *   thr_num * R (|magnetization| >= thr_num / thr_den, inclusive); with
+ *   expand != 0 every variable sharing a clause with a frozen one is also hot.
+ *   counts_out (optional) receives c_i (N int32).
+ * QAP: freq[f][l] = #{r : p_f = l}; facility f is frozen (hot) iff
+ *   thr_den * max_l freq[f][l] >= thr_num * R; expand is ignored.
+ *   counts_out (optional) receives freq (n*n int32, row-major).
+ * class_out (optional, N or n bytes) receives 1 = hot, 0 = cold.  The classes
+ * stay on the device for NMC_PROFILE_BACKBONE.  0 < thr_num <= thr_den. */
+int nmc_estimate_backbone(nmc_replicas *rep, int32_t thr_num, int32_t thr_den, int32_t expand, uint8_t *class_out,
+                          int32_t *counts_out, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * best_energy and state access
+ * ------------------------------------------------------------------------- */
+
+/* best: lowest energy any replica has reached at a sweep boundary;
+ * n_at_zero: replicas whose best energy is 0; per-replica arrays (R entries,
+ * each optional): best energies, current energies, first-hit sweeps. */
+int nmc_best_energy(nmc_replicas *rep, int64_t *best, int32_t *n_at_zero, int64_t *best_per_replica,
+                    int64_t *energy_per_replica, int32_t *first_hit, void *stream);
+
+/* Full recount of every replica's current energy on the device (R int64),
+ * independent of the incrementally tracked energies. */
+int nmc_recount(nmc_replicas *rep, int64_t *energy_out, void *stream);
+
+/* Copy a state out as R rows: k-SAT x[r][i] in {0,1} (R*N bytes); QAP
+ * p[r][f] (R*n bytes).  which = NMC_STATE_CURRENT or NMC_STATE_BEST. */
+int nmc_get_state(nmc_replicas *rep, int32_t which, uint8_t *host_out, size_t bytes, void *stream);
+
+/* Replace the current state (same layout as nmc_get_state) and the sweep
+ * counter, for checkpoint/resume.  Energies are recounted; best energies and
+ * snapshots restart from the restored state; first_hit resets to -1. */
+int nmc_set_state(nmc_replicas *rep, const uint8_t *host_in, size_t bytes, uint32_t sweeps_done, void *stream);
+
+int nmc_replicas_info(const nmc_replicas *rep, int32_t *n_replicas, uint64_t *seed, uint32_t *sweeps_done);
+
+/* ---------------------------------------------------------------------------
+ * tuning and timing (results never depend on these)
+ * ------------------------------------------------------------------------- */
+
+/* block_threads: threads per workgroup of the sweep kernels (64..1024,
+ * multiple of 64; 0 = default). */
+int nmc_set_tuning(nmc_replicas *rep, int32_t block_threads);
+
+/* When enabled, every sweep-kernel launch is bracketed by HIP events on the
+ * launch stream; nmc_kernel_time() then returns the summed kernel time (ms),
+ * the number of sweep-kernel launches and the Metropolis attempts they made
+ * since the last reset.  Enabling it adds a stream synchronization per call. */
+int nmc_set_profiling(nmc_replicas *rep, int32_t enable);
+int nmc_kernel_time(nmc_replicas *rep, double *ms, int64_t *launches, double *attempts, int32_t reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NMC_H */

@@ -1,0 +1,991 @@
+// Host side of the NMC library: argument validation, the instance layouts
+// the kernels read, acceptance-threshold tables, handles, and the C ABI
+// declared in include/nmc.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/nmc.h"
+#include "nmc_internal.h"
+
+using namespace nmc;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int ok() {
+    g_err.clear();
+    return NMC_OK;
+}
+
+#define HIP_OR_FAIL(expr)                                                                                  \
+    do {                                                                                                   \
+        hipError_t e_ = (expr);                                                                            \
+        if (e_ != hipSuccess)                                                                              \
+            return fail(NMC_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));                  \
+    } while (0)
+
+// Acceptance threshold for an energy rise d > 0 at inverse temperature beta:
+// min(2^32 - 1, floor(2^32 exp(-beta d))) evaluated in IEEE double.
+uint32_t threshold(double beta, int64_t d) {
+    const double v = std::ldexp(std::exp(-(beta * static_cast<double>(d))), 32);
+    if (!(v < 4294967295.0))
+        return 0xFFFFFFFFu;
+    return static_cast<uint32_t>(std::floor(v));
+}
+
+struct Arena {
+    size_t size = 0;
+    size_t take(size_t bytes) {
+        size = align_up(size, 256);
+        const size_t off = size;
+        size += bytes;
+        return off;
+    }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// instance
+// ---------------------------------------------------------------------------
+
+struct nmc_instance {
+    int kind = 0;
+    // k-SAT host data
+    int32_t n = 0, m = 0, kmax = 0, dmax = 0, n_colors = 0, n_chunks = 0;
+    std::vector<int32_t> order, color_ptr;
+    // layout offsets into the device arena
+    size_t off_rec = 0, off_chunk_var = 0, off_chunk_info = 0, off_color_chunk = 0, off_clause_addr = 0,
+           off_var_ptr = 0, off_var_cl = 0;
+    // QAP host data
+    int64_t delta_bound = 0;
+    int32_t qap_ha = 0;
+    size_t off_F = 0, off_D = 0;
+    // packed host image of the device arena
+    std::vector<uint8_t> image;
+    size_t arena_bytes = 0;
+    uint8_t *dev = nullptr;
+    int live_replicas = 0;
+
+    KsatDev ksat_dev() const {
+        KsatDev d{};
+        d.rec = reinterpret_cast<const uint64_t *>(dev + off_rec);
+        d.chunk_var = reinterpret_cast<const int32_t *>(dev + off_chunk_var);
+        d.chunk_info = reinterpret_cast<const int2 *>(dev + off_chunk_info);
+        d.color_chunk = reinterpret_cast<const int32_t *>(dev + off_color_chunk);
+        d.clause_addr = reinterpret_cast<const uint32_t *>(dev + off_clause_addr);
+        d.var_ptr = reinterpret_cast<const int32_t *>(dev + off_var_ptr);
+        d.var_cl = reinterpret_cast<const int32_t *>(dev + off_var_cl);
+        d.n = n;
+        d.m = m;
+        d.n_colors = n_colors;
+        d.n_chunks = n_chunks;
+        d.dmax = dmax;
+        return d;
+    }
+    QapDev qap_dev() const {
+        QapDev d{};
+        d.F = dev + off_F;
+        d.D = dev + off_D;
+        d.n = n;
+        d.ha = qap_ha;
+        return d;
+    }
+};
+
+namespace {
+
+// Greedy colouring: variables in index order take the smallest colour that
+// no already-coloured variable sharing a clause holds and (cap > 0) that is
+// not full.  Returns the colour of every variable.
+std::vector<int32_t> greedy_colors(int32_t n, const std::vector<int32_t> &vptr, const std::vector<int32_t> &vcl,
+                                   const int32_t *cptr, const int32_t *lits, int32_t cap, int32_t *n_colors) {
+    std::vector<int32_t> color(n, -1), seen(n + 1, -1), fill;
+    int32_t ncol = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        for (int32_t q = vptr[v]; q < vptr[v + 1]; ++q) {
+            const int32_t a = vcl[q];
+            for (int32_t p = cptr[a]; p < cptr[a + 1]; ++p) {
+                const int32_t w = std::abs(lits[p]) - 1;
+                if (color[w] >= 0)
+                    seen[color[w]] = v;
+            }
+        }
+        int32_t c = 0;
+        while (seen[c] == v || (cap > 0 && c < (int32_t)fill.size() && fill[c] >= cap))
+            ++c;
+        if (c >= (int32_t)fill.size())
+            fill.resize(c + 1, 0);
+        fill[c]++;
+        color[v] = c;
+        ncol = std::max(ncol, c + 1);
+    }
+    *n_colors = ncol;
+    return color;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *nmc_last_error(void) { return g_err.c_str(); }
+
+int32_t nmc_version(void) { return 100; }
+
+int nmc_ksat_load(int32_t n_vars, int32_t n_clauses, const int32_t *clause_ptr, const int32_t *lits,
+                  int32_t class_cap, nmc_instance **out) {
+    try {
+        if (!out)
+            return fail(NMC_ERR_INVALID, "out is NULL");
+        *out = nullptr;
+        if (n_vars < 1)
+            return fail(NMC_ERR_INVALID, "n_vars must be >= 1");
+        if (n_vars > kMaxVars)
+            return fail(NMC_ERR_UNSUPPORTED, "n_vars %d exceeds %d", n_vars, kMaxVars);
+        if (n_clauses < 0)
+            return fail(NMC_ERR_INVALID, "n_clauses must be >= 0");
+        if (!clause_ptr || (n_clauses > 0 && !lits))
+            return fail(NMC_ERR_INVALID, "clause_ptr/lits is NULL");
+        if (class_cap < 0)
+            return fail(NMC_ERR_INVALID, "class_cap must be >= 0");
+        if (clause_ptr[0] != 0)
+            return fail(NMC_ERR_INVALID, "clause_ptr[0] must be 0");
+        int32_t kmax = 0;
+        for (int32_t a = 0; a < n_clauses; ++a) {
+            const int32_t len = clause_ptr[a + 1] - clause_ptr[a];
+            if (len < 1)
+                return fail(NMC_ERR_INVALID, "clause %d is empty or offsets decrease", a);
+            if (len > 4)
+                return fail(NMC_ERR_UNSUPPORTED, "clause %d has %d literals (at most 4 supported)", a, len);
+            kmax = std::max(kmax, len);
+            for (int32_t p = clause_ptr[a]; p < clause_ptr[a + 1]; ++p) {
+                const int32_t l = lits[p];
+                if (l == 0 || l > n_vars || l < -n_vars)
+                    return fail(NMC_ERR_INVALID, "clause %d: literal %d out of range", a, l);
+                for (int32_t p2 = clause_ptr[a]; p2 < p; ++p2)
+                    if (std::abs(lits[p2]) == std::abs(l))
+                        return fail(NMC_ERR_INVALID, "clause %d repeats variable %d", a, std::abs(l));
+            }
+        }
+        std::unique_ptr<nmc_instance> I(new nmc_instance());
+        I->kind = NMC_KIND_KSAT;
+        I->n = n_vars;
+        I->m = n_clauses;
+        I->kmax = kmax;
+        const int32_t n = n_vars, m = n_clauses;
+
+        // variable -> clause incidence (clause ids ascending per variable)
+        std::vector<int32_t> vptr(n + 1, 0), vcl, vpos;
+        for (int32_t p = 0; p < clause_ptr[m]; ++p)
+            vptr[std::abs(lits[p])]++;
+        for (int32_t v = 0; v < n; ++v)
+            vptr[v + 1] += vptr[v];
+        vcl.resize(vptr[n]);
+        vpos.resize(vptr[n]);
+        {
+            std::vector<int32_t> fill(vptr.begin(), vptr.end() - 1);
+            for (int32_t a = 0; a < m; ++a)
+                for (int32_t p = clause_ptr[a]; p < clause_ptr[a + 1]; ++p) {
+                    const int32_t v = std::abs(lits[p]) - 1;
+                    vcl[fill[v]] = a;
+                    vpos[fill[v]] = p;
+                    fill[v]++;
+                }
+        }
+        int32_t dmax = 0;
+        for (int32_t v = 0; v < n; ++v)
+            dmax = std::max(dmax, vptr[v + 1] - vptr[v]);
+        if (dmax > 127)
+            return fail(NMC_ERR_UNSUPPORTED, "a variable occurs in %d clauses (at most 127 supported)", dmax);
+        I->dmax = dmax;
+
+        // colouring and colour-major order
+        int32_t ncol = 0;
+        std::vector<int32_t> color = greedy_colors(n, vptr, vcl, clause_ptr, lits, class_cap, &ncol);
+        I->n_colors = ncol;
+        I->color_ptr.assign(ncol + 1, 0);
+        for (int32_t v = 0; v < n; ++v)
+            I->color_ptr[color[v] + 1]++;
+        for (int32_t c = 0; c < ncol; ++c)
+            I->color_ptr[c + 1] += I->color_ptr[c];
+        I->order.resize(n);
+        {
+            std::vector<int32_t> fill(I->color_ptr.begin(), I->color_ptr.end() - 1);
+            for (int32_t v = 0; v < n; ++v)
+                I->order[fill[color[v]]++] = v;
+        }
+
+        // chunks: within a class, variables by degree (descending) in groups of 64
+        const uint32_t ZERO = 2u * n, ONES = 2u * n + 1;
+        auto lit_addr = [&](int32_t l) -> uint32_t {
+            return l > 0 ? (uint32_t)(l - 1) : (uint32_t)(n + (-l - 1));
+        };
+        std::vector<int32_t> chunk_var, color_chunk(ncol + 1, 0);
+        std::vector<int2> chunk_info;
+        std::vector<uint64_t> rec;
+        int32_t slot_rows = 0;
+        for (int32_t c = 0; c < ncol; ++c) {
+            std::vector<int32_t> vs(I->order.begin() + I->color_ptr[c], I->order.begin() + I->color_ptr[c + 1]);
+            std::stable_sort(vs.begin(), vs.end(), [&](int32_t x, int32_t y) {
+                return (vptr[x + 1] - vptr[x]) > (vptr[y + 1] - vptr[y]);
+            });
+            for (size_t b = 0; b < vs.size(); b += kChunk) {
+                const size_t e = std::min(vs.size(), b + kChunk);
+                int32_t nslot = 0;
+                for (size_t i = b; i < e; ++i)
+                    nslot = std::max(nslot, vptr[vs[i] + 1] - vptr[vs[i]]);
+                chunk_info.push_back(make_int2(slot_rows, nslot));
+                const size_t base = rec.size();
+                rec.resize(base + (size_t)nslot * kChunk);
+                for (int32_t s = 0; s < nslot; ++s)
+                    for (int lane = 0; lane < kChunk; ++lane) {
+                        uint64_t r = (uint64_t)ONES | ((uint64_t)ZERO << kAddrBits) | ((uint64_t)ZERO << (2 * kAddrBits));
+                        const size_t i = b + lane;
+                        if (i < e) {
+                            const int32_t v = vs[i];
+                            if (s < vptr[v + 1] - vptr[v]) {
+                                const int32_t a = vcl[vptr[v] + s];
+                                const int32_t own = vpos[vptr[v] + s];
+                                uint32_t ad[3] = {ZERO, ZERO, ZERO};
+                                int k = 0;
+                                for (int32_t p = clause_ptr[a]; p < clause_ptr[a + 1]; ++p)
+                                    if (p != own)
+                                        ad[k++] = lit_addr(lits[p]);
+                                const uint64_t neg = lits[own] < 0 ? 1u : 0u;
+                                r = (uint64_t)ad[0] | ((uint64_t)ad[1] << kAddrBits) |
+                                    ((uint64_t)ad[2] << (2 * kAddrBits)) | (neg << (3 * kAddrBits));
+                            }
+                        }
+                        rec[base + (size_t)s * kChunk + lane] = r;
+                    }
+                slot_rows += nslot;
+                for (int lane = 0; lane < kChunk; ++lane)
+                    chunk_var.push_back(b + lane < e ? vs[b + lane] : -1);
+            }
+            color_chunk[c + 1] = (int32_t)chunk_info.size();
+        }
+        I->n_chunks = (int32_t)chunk_info.size();
+
+        std::vector<uint32_t> clause_addr((size_t)m * 4, ZERO);
+        for (int32_t a = 0; a < m; ++a) {
+            int k = 0;
+            for (int32_t p = clause_ptr[a]; p < clause_ptr[a + 1]; ++p)
+                clause_addr[(size_t)a * 4 + k++] = lit_addr(lits[p]);
+        }
+
+        Arena ar;
+        I->off_rec = ar.take(rec.size() * 8);
+        I->off_chunk_var = ar.take(chunk_var.size() * 4);
+        I->off_chunk_info = ar.take(chunk_info.size() * 8);
+        I->off_color_chunk = ar.take(color_chunk.size() * 4);
+        I->off_clause_addr = ar.take(std::max<size_t>(clause_addr.size() * 4, 16));
+        I->off_var_ptr = ar.take(vptr.size() * 4);
+        I->off_var_cl = ar.take(std::max<size_t>(vcl.size() * 4, 4));
+        I->arena_bytes = align_up(ar.size, 256);
+        I->image.assign(I->arena_bytes, 0);
+        auto put = [&](size_t off, const void *src, size_t bytes) {
+            if (bytes)
+                std::memcpy(I->image.data() + off, src, bytes);
+        };
+        put(I->off_rec, rec.data(), rec.size() * 8);
+        put(I->off_chunk_var, chunk_var.data(), chunk_var.size() * 4);
+        put(I->off_chunk_info, chunk_info.data(), chunk_info.size() * 8);
+        put(I->off_color_chunk, color_chunk.data(), color_chunk.size() * 4);
+        put(I->off_clause_addr, clause_addr.data(), clause_addr.size() * 4);
+        put(I->off_var_ptr, vptr.data(), vptr.size() * 4);
+        put(I->off_var_cl, vcl.data(), vcl.size() * 4);
+        *out = I.release();
+        return ok();
+    } catch (const std::bad_alloc &) {
+        return fail(NMC_ERR_CAPACITY, "host allocation failed");
+    } catch (...) {
+        return fail(NMC_ERR_INVALID, "unexpected failure in nmc_ksat_load");
+    }
+}
+
+int nmc_qap_load(int32_t n, const int32_t *flow, const int32_t *dist, nmc_instance **out) {
+    try {
+        if (!out)
+            return fail(NMC_ERR_INVALID, "out is NULL");
+        *out = nullptr;
+        if (!flow || !dist)
+            return fail(NMC_ERR_INVALID, "flow/dist is NULL");
+        if (n < 2 || n > kQapMaxN)
+            return fail(NMC_ERR_UNSUPPORTED, "n = %d outside [2, %d]", n, kQapMaxN);
+        int32_t fmax = 0, dmax = 0;
+        for (int32_t i = 0; i < n; ++i)
+            for (int32_t j = 0; j < n; ++j) {
+                const int32_t f = flow[(size_t)i * n + j], d = dist[(size_t)i * n + j];
+                if (f < 0 || f > 255 || d < 0 || d > 255)
+                    return fail(NMC_ERR_UNSUPPORTED, "entry (%d,%d) outside [0, 255]", i, j);
+                if (f != flow[(size_t)j * n + i] || d != dist[(size_t)j * n + i])
+                    return fail(NMC_ERR_INVALID, "flow/dist must be symmetric (entry %d,%d)", i, j);
+                if (i == j && (f != 0 || d != 0))
+                    return fail(NMC_ERR_INVALID, "flow/dist must have a zero diagonal");
+                fmax = std::max(fmax, f);
+                dmax = std::max(dmax, d);
+            }
+        std::unique_ptr<nmc_instance> I(new nmc_instance());
+        I->kind = NMC_KIND_QAP;
+        I->n = n;
+        I->delta_bound = 2ll * (n - 2) * fmax * dmax;
+        I->qap_ha = (int32_t)(I->delta_bound >> kQapLowBits) + 1;
+        Arena ar;
+        I->off_F = ar.take((size_t)n * n);
+        I->off_D = ar.take((size_t)n * n);
+        I->arena_bytes = align_up(ar.size, 256);
+        I->image.assign(I->arena_bytes, 0);
+        for (size_t i = 0; i < (size_t)n * n; ++i) {
+            I->image[I->off_F + i] = (uint8_t)flow[i];
+            I->image[I->off_D + i] = (uint8_t)dist[i];
+        }
+        *out = I.release();
+        return ok();
+    } catch (const std::bad_alloc &) {
+        return fail(NMC_ERR_CAPACITY, "host allocation failed");
+    } catch (...) {
+        return fail(NMC_ERR_INVALID, "unexpected failure in nmc_qap_load");
+    }
+}
+
+int nmc_instance_get_info(const nmc_instance *I, nmc_instance_info *out) {
+    if (!I || !out)
+        return fail(NMC_ERR_INVALID, "NULL argument");
+    out->kind = I->kind;
+    out->n_items = I->n;
+    if (I->kind == NMC_KIND_KSAT) {
+        out->n_clauses = I->m;
+        out->max_clause_len = I->kmax;
+        out->max_degree = I->dmax;
+        out->n_colors = I->n_colors;
+        out->delta_bound = I->dmax;
+    } else {
+        out->n_clauses = 0;
+        out->max_clause_len = 0;
+        out->max_degree = I->n - 2;
+        out->n_colors = 1;
+        out->delta_bound = I->delta_bound;
+    }
+    return ok();
+}
+
+int nmc_instance_order(const nmc_instance *I, int32_t *order, int32_t *class_ptr, int32_t *n_colors) {
+    if (!I)
+        return fail(NMC_ERR_INVALID, "NULL instance");
+    if (I->kind != NMC_KIND_KSAT)
+        return fail(NMC_ERR_UNSUPPORTED, "sweep order exists for k-SAT instances only");
+    if (order)
+        std::memcpy(order, I->order.data(), I->order.size() * 4);
+    if (class_ptr)
+        std::memcpy(class_ptr, I->color_ptr.data(), I->color_ptr.size() * 4);
+    if (n_colors)
+        *n_colors = I->n_colors;
+    return ok();
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// replicas
+// ---------------------------------------------------------------------------
+
+struct nmc_replicas {
+    nmc_instance *inst = nullptr;
+    int32_t R = 0, G = 0;
+    uint64_t seed = 0;
+    uint32_t sweeps_done = 0;
+    uint8_t *dev = nullptr;
+    size_t bytes = 0;
+    KsatRepDev k{};
+    QapRepDev q{};
+    int32_t *scratch_energy = nullptr;  // [4G] or [R] (int64 for QAP)
+    bool has_backbone = false;
+    int32_t block_threads = 1024;
+    // library-owned threshold / class upload buffer
+    uint8_t *tab_dev = nullptr;
+    size_t tab_cap = 0;
+    // profiling
+    bool profiling = false;
+    double prof_ms = 0;
+    int64_t prof_launches = 0;
+    double prof_attempts = 0;
+};
+
+namespace {
+
+struct ReplicaLayout {
+    size_t off_xs, off_best_xs, off_energy, off_best, off_first_hit, off_cls, off_counts, off_frozen, off_tally,
+        off_scratch, total;
+};
+
+ReplicaLayout replica_layout(const nmc_instance *I, int32_t R) {
+    ReplicaLayout L{};
+    Arena ar;
+    if (I->kind == NMC_KIND_KSAT) {
+        const size_t G = (size_t)(R + kGroup - 1) / kGroup;
+        L.off_xs = ar.take(G * I->n);
+        L.off_best_xs = ar.take(G * I->n);
+        L.off_energy = ar.take(G * kGroup * 4);
+        L.off_best = ar.take(G * kGroup * 4);
+        L.off_first_hit = ar.take(G * kGroup * 4);
+        L.off_cls = ar.take(I->n);
+        L.off_counts = ar.take((size_t)I->n * 4);
+        L.off_frozen = ar.take(I->n);
+        L.off_tally = ar.take(64);
+        L.off_scratch = ar.take(G * kGroup * 8);
+    } else {
+        const size_t n = I->n;
+        L.off_xs = ar.take((size_t)R * n);
+        L.off_best_xs = ar.take((size_t)R * n);
+        L.off_energy = ar.take((size_t)R * 8);
+        L.off_best = ar.take((size_t)R * 8);
+        L.off_first_hit = ar.take((size_t)R * 4);
+        L.off_cls = ar.take(n);
+        L.off_counts = ar.take(n * n * 4);
+        L.off_frozen = ar.take(16);
+        L.off_tally = ar.take(64);
+        L.off_scratch = ar.take((size_t)R * 8);
+    }
+    L.total = align_up(ar.size, 256);
+    return L;
+}
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+int ensure_tab(nmc_replicas *P, size_t bytes) {
+    if (bytes <= P->tab_cap)
+        return NMC_OK;
+    if (P->tab_dev) {
+        HIP_OR_FAIL(hipDeviceSynchronize());
+        HIP_OR_FAIL(hipFree(P->tab_dev));
+        P->tab_dev = nullptr;
+        P->tab_cap = 0;
+    }
+    size_t cap = std::max<size_t>(bytes, 1 << 20);
+    HIP_OR_FAIL(hipMalloc(&P->tab_dev, cap));
+    P->tab_cap = cap;
+    return NMC_OK;
+}
+
+int reset_after_state(nmc_replicas *P, hipStream_t s) {
+    nmc_instance *I = P->inst;
+    if (I->kind == NMC_KIND_KSAT) {
+        HIP_OR_FAIL(ksat_launch_recount(I->ksat_dev(), P->k.xs, P->G, P->R, P->k.energy, s));
+        HIP_OR_FAIL(ksat_launch_reset_tallies(P->k, I->n, s));
+    } else {
+        HIP_OR_FAIL(qap_launch_cost(I->qap_dev(), P->q.perm, P->R, P->q.cost, s));
+        HIP_OR_FAIL(qap_launch_reset_tallies(P->q, I->n, s));
+    }
+    return NMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nmc_footprint(const nmc_instance *I, int32_t n_replicas, size_t *instance_bytes, size_t *replica_bytes) {
+    if (!I)
+        return fail(NMC_ERR_INVALID, "NULL instance");
+    if (n_replicas < 1 || n_replicas > (1 << 20))
+        return fail(NMC_ERR_INVALID, "n_replicas %d outside [1, 2^20]", n_replicas);
+    if (instance_bytes)
+        *instance_bytes = I->arena_bytes;
+    if (replica_bytes)
+        *replica_bytes = replica_layout(I, n_replicas).total;
+    return ok();
+}
+
+int nmc_instance_bind(nmc_instance *I, void *dev_buf, size_t bytes, void *stream) {
+    if (!I || !dev_buf)
+        return fail(NMC_ERR_INVALID, "NULL argument");
+    if (bytes < I->arena_bytes)
+        return fail(NMC_ERR_SIZE, "instance buffer has %zu bytes, needs %zu", bytes, I->arena_bytes);
+    if (reinterpret_cast<uintptr_t>(dev_buf) % 256)
+        return fail(NMC_ERR_INVALID, "instance buffer must be 256-byte aligned");
+    if (I->live_replicas)
+        return fail(NMC_ERR_STATE, "instance has live replica sets");
+    hipStream_t s = as_stream(stream);
+    HIP_OR_FAIL(hipMemcpyAsync(dev_buf, I->image.data(), I->arena_bytes, hipMemcpyHostToDevice, s));
+    HIP_OR_FAIL(hipStreamSynchronize(s));
+    I->dev = static_cast<uint8_t *>(dev_buf);
+    return ok();
+}
+
+void nmc_instance_free(nmc_instance *I) { delete I; }
+
+int nmc_replicas_create(nmc_instance *I, int32_t n_replicas, uint64_t seed, void *dev_buf, size_t bytes,
+                        void *stream, nmc_replicas **out) {
+    try {
+        if (!out)
+            return fail(NMC_ERR_INVALID, "out is NULL");
+        *out = nullptr;
+        if (!I || !dev_buf)
+            return fail(NMC_ERR_INVALID, "NULL argument");
+        if (!I->dev)
+            return fail(NMC_ERR_STATE, "instance is not bound to device memory");
+        if (n_replicas < 1 || n_replicas > (1 << 20))
+            return fail(NMC_ERR_INVALID, "n_replicas %d outside [1, 2^20]", n_replicas);
+        if (reinterpret_cast<uintptr_t>(dev_buf) % 256)
+            return fail(NMC_ERR_INVALID, "replica buffer must be 256-byte aligned");
+        const ReplicaLayout L = replica_layout(I, n_replicas);
+        if (bytes < L.total)
+            return fail(NMC_ERR_SIZE, "replica buffer has %zu bytes, needs %zu", bytes, L.total);
+        std::unique_ptr<nmc_replicas> P(new nmc_replicas());
+        P->inst = I;
+        P->R = n_replicas;
+        P->G = (n_replicas + kGroup - 1) / kGroup;
+        P->seed = seed;
+        P->dev = static_cast<uint8_t *>(dev_buf);
+        P->bytes = bytes;
+        uint8_t *b = P->dev;
+        hipStream_t s = as_stream(stream);
+        const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
+        if (I->kind == NMC_KIND_KSAT) {
+            KsatRepDev &k = P->k;
+            k.xs = b + L.off_xs;
+            k.best_xs = b + L.off_best_xs;
+            k.energy = reinterpret_cast<int32_t *>(b + L.off_energy);
+            k.best = reinterpret_cast<int32_t *>(b + L.off_best);
+            k.first_hit = reinterpret_cast<int32_t *>(b + L.off_first_hit);
+            k.cls = b + L.off_cls;
+            k.counts = reinterpret_cast<int32_t *>(b + L.off_counts);
+            k.frozen = b + L.off_frozen;
+            k.tally = reinterpret_cast<int32_t *>(b + L.off_tally);
+            k.n_rep = n_replicas;
+            k.n_groups = P->G;
+            P->scratch_energy = reinterpret_cast<int32_t *>(b + L.off_scratch);
+            HIP_OR_FAIL(hipMemsetAsync(b + L.off_energy, 0, L.off_first_hit + (size_t)P->G * kGroup * 4 - L.off_energy, s));
+            HIP_OR_FAIL(ksat_launch_init(I->ksat_dev(), k, key0, key1, s));
+        } else {
+            QapRepDev &q = P->q;
+            q.perm = b + L.off_xs;
+            q.best_perm = b + L.off_best_xs;
+            q.cost = reinterpret_cast<int64_t *>(b + L.off_energy);
+            q.best = reinterpret_cast<int64_t *>(b + L.off_best);
+            q.first_hit = reinterpret_cast<int32_t *>(b + L.off_first_hit);
+            q.cls = b + L.off_cls;
+            q.freq = reinterpret_cast<int32_t *>(b + L.off_counts);
+            q.tally = reinterpret_cast<int32_t *>(b + L.off_tally);
+            q.n_rep = n_replicas;
+            P->scratch_energy = reinterpret_cast<int32_t *>(b + L.off_scratch);
+            HIP_OR_FAIL(qap_launch_init(I->qap_dev(), q, key0, key1, s));
+        }
+        int rc = reset_after_state(P.get(), s);
+        if (rc)
+            return rc;
+        HIP_OR_FAIL(hipStreamSynchronize(s));
+        I->live_replicas++;
+        *out = P.release();
+        return ok();
+    } catch (const std::bad_alloc &) {
+        return fail(NMC_ERR_CAPACITY, "host allocation failed");
+    }
+}
+
+void nmc_replicas_free(nmc_replicas *P) {
+    if (!P)
+        return;
+    if (P->tab_dev) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(P->tab_dev);
+    }
+    if (P->inst)
+        P->inst->live_replicas--;
+    delete P;
+}
+
+static int anneal_impl(nmc_replicas *P, const double *beta, int32_t n_classes, int32_t n_sweeps, int32_t profile,
+                       const uint8_t *class_of, int64_t target, void *stream) {
+    if (!P || !beta)
+        return fail(NMC_ERR_INVALID, "NULL argument");
+    nmc_instance *I = P->inst;
+    if (!I->dev)
+        return fail(NMC_ERR_STATE, "instance is not bound");
+    if (n_classes < 1 || n_classes > kMaxClasses)
+        return fail(NMC_ERR_INVALID, "n_classes %d outside [1, %d]", n_classes, kMaxClasses);
+    if (n_sweeps < 0)
+        return fail(NMC_ERR_INVALID, "n_sweeps must be >= 0");
+    if ((uint64_t)P->sweeps_done + (uint64_t)n_sweeps > 0xFFFFFFFFull)
+        return fail(NMC_ERR_INVALID, "sweep counter would pass 2^32 - 1");
+    for (int64_t i = 0; i < (int64_t)n_classes * n_sweeps; ++i)
+        if (!std::isfinite(beta[i]) || beta[i] < 0)
+            return fail(NMC_ERR_INVALID, "beta[%lld] = %g is not finite and >= 0", (long long)i, beta[i]);
+    const int32_t nitems = I->n;
+    if (profile == NMC_PROFILE_HOST) {
+        if (!class_of)
+            return fail(NMC_ERR_INVALID, "class_of is NULL for NMC_PROFILE_HOST");
+        for (int32_t i = 0; i < nitems; ++i)
+            if (class_of[i] >= n_classes)
+                return fail(NMC_ERR_INVALID, "class_of[%d] = %d >= n_classes", i, class_of[i]);
+    } else if (profile == NMC_PROFILE_BACKBONE) {
+        if (!P->has_backbone)
+            return fail(NMC_ERR_STATE, "no backbone estimate yet");
+        if (n_classes < 2)
+            return fail(NMC_ERR_INVALID, "the backbone profile needs n_classes >= 2");
+    } else if (profile != NMC_PROFILE_HOMOGENEOUS) {
+        return fail(NMC_ERR_INVALID, "unknown profile %d", profile);
+    }
+    hipStream_t s = as_stream(stream);
+    const bool ksat = I->kind == NMC_KIND_KSAT;
+    const int32_t stride = ksat ? I->dmax + 1 : I->qap_ha + (1 << kQapLowBits);
+    const size_t lds = ksat ? ksat_sweep_lds_bytes(I->n, n_classes, stride) : qap_sweep_lds_bytes(I->n, n_classes, stride);
+    if (lds > kLdsBytes)
+        return fail(NMC_ERR_CAPACITY, "sweep needs %zu bytes of LDS (limit %zu)", lds, kLdsBytes);
+    if (ksat && I->n > 0 && target > INT32_MAX)
+        target = INT32_MAX;
+
+    // thresholds for every (sweep, class) of this call
+    const size_t words = (size_t)n_sweeps * n_classes * stride;
+    const size_t tab_bytes = align_up(std::max<size_t>(words * 4, 4), 256);
+    const size_t cls_bytes = profile == NMC_PROFILE_HOST ? align_up(nitems, 256) : 0;
+    int rc = ensure_tab(P, tab_bytes + cls_bytes);
+    if (rc)
+        return rc;
+    std::vector<uint32_t> tab(std::max<size_t>(words, 1));
+    for (int32_t sw = 0; sw < n_sweeps; ++sw)
+        for (int32_t c = 0; c < n_classes; ++c) {
+            const double b = beta[(size_t)c * n_sweeps + sw];
+            uint32_t *row = tab.data() + ((size_t)sw * n_classes + c) * stride;
+            if (ksat) {
+                row[0] = 0xFFFFFFFFu;
+                for (int32_t d = 1; d < stride; ++d)
+                    row[d] = threshold(b, d);
+            } else {
+                const int32_t ha = I->qap_ha, lo = 1 << kQapLowBits;
+                row[0] = 0xFFFFFFFFu;
+                for (int32_t h = 1; h < ha; ++h)
+                    row[h] = threshold(b, (int64_t)h << kQapLowBits);
+                row[ha] = 0xFFFFFFFFu;
+                for (int32_t l = 1; l < lo; ++l)
+                    row[ha + l] = threshold(b, l);
+            }
+        }
+    // the upload waits for earlier work on the stream that still reads the
+    // buffer: pageable host-to-device copies are ordered in the stream
+    HIP_OR_FAIL(hipMemcpyAsync(P->tab_dev, tab.data(), words * 4, hipMemcpyHostToDevice, s));
+    const uint8_t *cls_dev = nullptr;
+    if (profile == NMC_PROFILE_HOST) {
+        HIP_OR_FAIL(hipMemcpyAsync(P->tab_dev + tab_bytes, class_of, nitems, hipMemcpyHostToDevice, s));
+        cls_dev = P->tab_dev + tab_bytes;
+    } else if (profile == NMC_PROFILE_BACKBONE) {
+        cls_dev = ksat ? P->k.cls : P->q.cls;
+    }
+
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (P->profiling) {
+        HIP_OR_FAIL(hipEventCreate(&e0));
+        HIP_OR_FAIL(hipEventCreate(&e1));
+        HIP_OR_FAIL(hipEventRecord(e0, s));
+    }
+    if (ksat) {
+        SweepCall C{};
+        C.tab = reinterpret_cast<const uint32_t *>(P->tab_dev);
+        C.var_cls = cls_dev;
+        C.n_classes = n_classes;
+        C.stride = stride;
+        C.n_sweeps = n_sweeps;
+        C.t0 = P->sweeps_done;
+        C.target = (int32_t)std::max<int64_t>(std::min<int64_t>(target, INT32_MAX), INT32_MIN);
+        C.check_start = 1;
+        C.key0 = (uint32_t)P->seed;
+        C.key1 = (uint32_t)(P->seed >> 32);
+        HIP_OR_FAIL(ksat_launch_sweep(I->ksat_dev(), P->k, C, P->block_threads, s));
+    } else {
+        QapCall C{};
+        C.tab = reinterpret_cast<const uint32_t *>(P->tab_dev);
+        C.fac_cls = cls_dev;
+        C.n_classes = n_classes;
+        C.stride = stride;
+        C.n_sweeps = n_sweeps;
+        C.t0 = P->sweeps_done;
+        C.target = target;
+        C.check_start = 1;
+        C.key0 = (uint32_t)P->seed;
+        C.key1 = (uint32_t)(P->seed >> 32);
+        HIP_OR_FAIL(qap_launch_sweep(I->qap_dev(), P->q, C, 256, s));
+    }
+    if (P->profiling) {
+        HIP_OR_FAIL(hipEventRecord(e1, s));
+        HIP_OR_FAIL(hipEventSynchronize(e1));
+        float ms = 0;
+        HIP_OR_FAIL(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        P->prof_ms += ms;
+        P->prof_launches += 1;
+        const double per_sweep = ksat ? (double)P->R * I->n : (double)P->R * I->n * (I->n - 1) / 2.0;
+        P->prof_attempts += per_sweep * n_sweeps;
+    }
+    P->sweeps_done += (uint32_t)n_sweeps;
+    return ok();
+}
+
+int nmc_anneal(nmc_replicas *P, const double *beta, int32_t n_classes, int32_t n_sweeps, int32_t profile,
+               const uint8_t *class_of, int64_t target, void *stream) {
+    try {
+        return anneal_impl(P, beta, n_classes, n_sweeps, profile, class_of, target, stream);
+    } catch (const std::bad_alloc &) {
+        return fail(NMC_ERR_CAPACITY, "host allocation failed");
+    }
+}
+
+int nmc_reanneal(nmc_replicas *P, const double *beta, int32_t n_classes, int32_t n_sweeps, int32_t profile,
+                 const uint8_t *class_of, int64_t target, void *stream) {
+    return nmc_anneal(P, beta, n_classes, n_sweeps, profile, class_of, target, stream);
+}
+
+int nmc_estimate_backbone(nmc_replicas *P, int32_t thr_num, int32_t thr_den, int32_t expand, uint8_t *class_out,
+                          int32_t *counts_out, void *stream) {
+    if (!P)
+        return fail(NMC_ERR_INVALID, "NULL replicas");
+    if (thr_den <= 0 || thr_num <= 0 || thr_num > thr_den)
+        return fail(NMC_ERR_INVALID, "need 0 < thr_num <= thr_den");
+    nmc_instance *I = P->inst;
+    hipStream_t s = as_stream(stream);
+    if (I->kind == NMC_KIND_KSAT) {
+        HIP_OR_FAIL(ksat_launch_backbone(I->ksat_dev(), P->k, thr_num, thr_den, expand ? 1 : 0, s));
+        if (class_out)
+            HIP_OR_FAIL(hipMemcpyAsync(class_out, P->k.cls, I->n, hipMemcpyDeviceToHost, s));
+        if (counts_out)
+            HIP_OR_FAIL(hipMemcpyAsync(counts_out, P->k.counts, (size_t)I->n * 4, hipMemcpyDeviceToHost, s));
+    } else {
+        HIP_OR_FAIL(qap_launch_backbone(I->qap_dev(), P->q, thr_num, thr_den, s));
+        if (class_out)
+            HIP_OR_FAIL(hipMemcpyAsync(class_out, P->q.cls, I->n, hipMemcpyDeviceToHost, s));
+        if (counts_out)
+            HIP_OR_FAIL(hipMemcpyAsync(counts_out, P->q.freq, (size_t)I->n * I->n * 4, hipMemcpyDeviceToHost, s));
+    }
+    if (class_out || counts_out)
+        HIP_OR_FAIL(hipStreamSynchronize(s));
+    P->has_backbone = true;
+    return ok();
+}
+
+int nmc_best_energy(nmc_replicas *P, int64_t *best, int32_t *n_at_zero, int64_t *best_per_replica,
+                    int64_t *energy_per_replica, int32_t *first_hit, void *stream) {
+    if (!P)
+        return fail(NMC_ERR_INVALID, "NULL replicas");
+    try {
+        nmc_instance *I = P->inst;
+        hipStream_t s = as_stream(stream);
+        const int32_t R = P->R;
+        if (I->kind == NMC_KIND_KSAT) {
+            HIP_OR_FAIL(ksat_launch_tally(P->k, s));
+            int32_t t[2];
+            std::vector<int32_t> b(R), e(R), f(R);
+            HIP_OR_FAIL(hipMemcpyAsync(t, P->k.tally, 8, hipMemcpyDeviceToHost, s));
+            if (best_per_replica)
+                HIP_OR_FAIL(hipMemcpyAsync(b.data(), P->k.best, (size_t)R * 4, hipMemcpyDeviceToHost, s));
+            if (energy_per_replica)
+                HIP_OR_FAIL(hipMemcpyAsync(e.data(), P->k.energy, (size_t)R * 4, hipMemcpyDeviceToHost, s));
+            if (first_hit)
+                HIP_OR_FAIL(hipMemcpyAsync(f.data(), P->k.first_hit, (size_t)R * 4, hipMemcpyDeviceToHost, s));
+            HIP_OR_FAIL(hipStreamSynchronize(s));
+            if (best)
+                *best = t[0];
+            if (n_at_zero)
+                *n_at_zero = t[1];
+            for (int32_t r = 0; r < R; ++r) {
+                if (best_per_replica)
+                    best_per_replica[r] = b[r];
+                if (energy_per_replica)
+                    energy_per_replica[r] = e[r];
+                if (first_hit)
+                    first_hit[r] = f[r];
+            }
+        } else {
+            HIP_OR_FAIL(qap_launch_tally(P->q, s));
+            int32_t t[4];
+            HIP_OR_FAIL(hipMemcpyAsync(t, P->q.tally, 16, hipMemcpyDeviceToHost, s));
+            if (best_per_replica)
+                HIP_OR_FAIL(hipMemcpyAsync(best_per_replica, P->q.best, (size_t)R * 8, hipMemcpyDeviceToHost, s));
+            if (energy_per_replica)
+                HIP_OR_FAIL(hipMemcpyAsync(energy_per_replica, P->q.cost, (size_t)R * 8, hipMemcpyDeviceToHost, s));
+            if (first_hit)
+                HIP_OR_FAIL(hipMemcpyAsync(first_hit, P->q.first_hit, (size_t)R * 4, hipMemcpyDeviceToHost, s));
+            HIP_OR_FAIL(hipStreamSynchronize(s));
+            int64_t mn;
+            std::memcpy(&mn, t, 8);
+            if (best)
+                *best = mn;
+            if (n_at_zero)
+                *n_at_zero = t[2];
+        }
+        return ok();
+    } catch (const std::bad_alloc &) {
+        return fail(NMC_ERR_CAPACITY, "host allocation failed");
+    }
+}
+
+int nmc_recount(nmc_replicas *P, int64_t *energy_out, void *stream) {
+    if (!P || !energy_out)
+        return fail(NMC_ERR_INVALID, "NULL argument");
+    try {
+        nmc_instance *I = P->inst;
+        hipStream_t s = as_stream(stream);
+        if (I->kind == NMC_KIND_KSAT) {
+            HIP_OR_FAIL(ksat_launch_recount(I->ksat_dev(), P->k.xs, P->G, P->R, P->scratch_energy, s));
+            std::vector<int32_t> e(P->R);
+            HIP_OR_FAIL(hipMemcpyAsync(e.data(), P->scratch_energy, (size_t)P->R * 4, hipMemcpyDeviceToHost, s));
+            HIP_OR_FAIL(hipStreamSynchronize(s));
+            for (int32_t r = 0; r < P->R; ++r)
+                energy_out[r] = e[r];
+        } else {
+            int64_t *tmp = reinterpret_cast<int64_t *>(P->scratch_energy);
+            HIP_OR_FAIL(qap_launch_cost(I->qap_dev(), P->q.perm, P->R, tmp, s));
+            HIP_OR_FAIL(hipMemcpyAsync(energy_out, tmp, (size_t)P->R * 8, hipMemcpyDeviceToHost, s));
+            HIP_OR_FAIL(hipStreamSynchronize(s));
+        }
+        return ok();
+    } catch (const std::bad_alloc &) {
+        return fail(NMC_ERR_CAPACITY, "host allocation failed");
+    }
+}
+
+int nmc_get_state(nmc_replicas *P, int32_t which, uint8_t *host_out, size_t bytes, void *stream) {
+    if (!P || !host_out)
+        return fail(NMC_ERR_INVALID, "NULL argument");
+    if (which != NMC_STATE_CURRENT && which != NMC_STATE_BEST)
+        return fail(NMC_ERR_INVALID, "which must be NMC_STATE_CURRENT or NMC_STATE_BEST");
+    try {
+        nmc_instance *I = P->inst;
+        const size_t need = (size_t)P->R * I->n;
+        if (bytes < need)
+            return fail(NMC_ERR_SIZE, "state buffer has %zu bytes, needs %zu", bytes, need);
+        hipStream_t s = as_stream(stream);
+        if (I->kind == NMC_KIND_KSAT) {
+            const uint8_t *src = which == NMC_STATE_BEST ? P->k.best_xs : P->k.xs;
+            std::vector<uint8_t> packed((size_t)P->G * I->n);
+            HIP_OR_FAIL(hipMemcpyAsync(packed.data(), src, packed.size(), hipMemcpyDeviceToHost, s));
+            HIP_OR_FAIL(hipStreamSynchronize(s));
+            for (int32_t r = 0; r < P->R; ++r) {
+                const uint8_t *row = packed.data() + (size_t)(r / kGroup) * I->n;
+                uint8_t *dst = host_out + (size_t)r * I->n;
+                for (int32_t v = 0; v < I->n; ++v)
+                    dst[v] = (row[v] >> (r % kGroup)) & 1u;
+            }
+        } else {
+            const uint8_t *src = which == NMC_STATE_BEST ? P->q.best_perm : P->q.perm;
+            HIP_OR_FAIL(hipMemcpyAsync(host_out, src, need, hipMemcpyDeviceToHost, s));
+            HIP_OR_FAIL(hipStreamSynchronize(s));
+        }
+        return ok();
+    } catch (const std::bad_alloc &) {
+        return fail(NMC_ERR_CAPACITY, "host allocation failed");
+    }
+}
+
+int nmc_set_state(nmc_replicas *P, const uint8_t *host_in, size_t bytes, uint32_t sweeps_done, void *stream) {
+    if (!P || !host_in)
+        return fail(NMC_ERR_INVALID, "NULL argument");
+    try {
+        nmc_instance *I = P->inst;
+        const size_t need = (size_t)P->R * I->n;
+        if (bytes < need)
+            return fail(NMC_ERR_SIZE, "state buffer has %zu bytes, needs %zu", bytes, need);
+        hipStream_t s = as_stream(stream);
+        if (I->kind == NMC_KIND_KSAT) {
+            for (size_t i = 0; i < need; ++i)
+                if (host_in[i] > 1)
+                    return fail(NMC_ERR_INVALID, "k-SAT state entries must be 0 or 1");
+            std::vector<uint8_t> packed((size_t)P->G * I->n, 0);
+            for (int32_t r = 0; r < P->R; ++r) {
+                uint8_t *row = packed.data() + (size_t)(r / kGroup) * I->n;
+                const uint8_t *src = host_in + (size_t)r * I->n;
+                for (int32_t v = 0; v < I->n; ++v)
+                    row[v] |= (uint8_t)((src[v] & 1u) << (r % kGroup));
+            }
+            HIP_OR_FAIL(hipMemcpyAsync(P->k.xs, packed.data(), packed.size(), hipMemcpyHostToDevice, s));
+        } else {
+            std::vector<uint8_t> seen(I->n);
+            for (int32_t r = 0; r < P->R; ++r) {
+                std::fill(seen.begin(), seen.end(), 0);
+                for (int32_t f = 0; f < I->n; ++f) {
+                    const uint8_t l = host_in[(size_t)r * I->n + f];
+                    if (l >= I->n || seen[l])
+                        return fail(NMC_ERR_INVALID, "row %d is not a permutation", r);
+                    seen[l] = 1;
+                }
+            }
+            HIP_OR_FAIL(hipMemcpyAsync(P->q.perm, host_in, need, hipMemcpyHostToDevice, s));
+        }
+        int rc = reset_after_state(P, s);
+        if (rc)
+            return rc;
+        HIP_OR_FAIL(hipStreamSynchronize(s));
+        P->sweeps_done = sweeps_done;
+        return ok();
+    } catch (const std::bad_alloc &) {
+        return fail(NMC_ERR_CAPACITY, "host allocation failed");
+    }
+}
+
+int nmc_replicas_info(const nmc_replicas *P, int32_t *n_replicas, uint64_t *seed, uint32_t *sweeps_done) {
+    if (!P)
+        return fail(NMC_ERR_INVALID, "NULL replicas");
+    if (n_replicas)
+        *n_replicas = P->R;
+    if (seed)
+        *seed = P->seed;
+    if (sweeps_done)
+        *sweeps_done = P->sweeps_done;
+    return ok();
+}
+
+int nmc_set_tuning(nmc_replicas *P, int32_t block_threads) {
+    if (!P)
+        return fail(NMC_ERR_INVALID, "NULL replicas");
+    if (block_threads == 0)
+        block_threads = 1024;
+    if (block_threads < 64 || block_threads > 1024 || block_threads % 64)
+        return fail(NMC_ERR_INVALID, "block_threads must be a multiple of 64 in [64, 1024]");
+    P->block_threads = block_threads;
+    return ok();
+}
+
+int nmc_set_profiling(nmc_replicas *P, int32_t enable) {
+    if (!P)
+        return fail(NMC_ERR_INVALID, "NULL replicas");
+    P->profiling = enable != 0;
+    return ok();
+}
+
+int nmc_kernel_time(nmc_replicas *P, double *ms, int64_t *launches, double *attempts, int32_t reset) {
+    if (!P)
+        return fail(NMC_ERR_INVALID, "NULL replicas");
+    if (ms)
+        *ms = P->prof_ms;
+    if (launches)
+        *launches = P->prof_launches;
+    if (attempts)
+        *attempts = P->prof_attempts;
+    if (reset) {
+        P->prof_ms = 0;
+        P->prof_launches = 0;
+        P->prof_attempts = 0;
+    }
+    return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,127 @@
+// Internal definitions shared by the host side of the library (nmc_api.cpp)
+// and the device kernels (nmc_ksat.hip, nmc_qap.hip).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace nmc {
+
+// Philox stream identifiers (fourth counter word).
+constexpr uint32_t kStreamKsatSweep = 0;
+constexpr uint32_t kStreamKsatInit = 1;
+constexpr uint32_t kStreamQapSweep = 2;
+constexpr uint32_t kStreamQapInit = 3;
+
+// k-SAT: replicas are handled in groups of 4; group g holds replicas
+// 4g..4g+3 as bits 0..3 of one byte per variable.
+constexpr int kGroup = 4;
+// Largest variable count: spin-table byte addresses use 17 bits and the
+// "always false" / "always true" entries sit at 2N and 2N+1.
+constexpr int kMaxVars = 65534;
+constexpr int kAddrBits = 17;
+constexpr uint32_t kAddrMask = (1u << kAddrBits) - 1;
+constexpr int kMaxClasses = 8;
+constexpr int kChunk = 64;  // variables per sweep chunk = lanes of one wave
+
+// LDS available to one workgroup on gfx950.
+constexpr size_t kLdsBytes = 160 * 1024;
+
+__host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Device view of a bound k-SAT instance.
+struct KsatDev {
+    const uint64_t *rec;         // chunk records, [slot-row][64 lanes]
+    const int32_t *chunk_var;    // [n_chunks][64] variable of each lane, -1 = empty
+    const int2 *chunk_info;      // [n_chunks] (first slot-row, slot count)
+    const int32_t *color_chunk;  // [n_colors + 1] chunk range of each colour class
+    const uint32_t *clause_addr; // [M][4] spin-table addresses of the clause's literals
+    const int32_t *var_ptr;      // [N + 1] variable -> clause incidence
+    const int32_t *var_cl;       // [sum deg]
+    int32_t n, m, n_colors, n_chunks, dmax;
+};
+
+// Device view of a k-SAT replica set.
+struct KsatRepDev {
+    uint8_t *xs;       // [G][N] current spins, group-major nibbles
+    uint8_t *best_xs;  // [G][N] best-state snapshot
+    int32_t *energy;   // [4G]
+    int32_t *best;     // [4G]
+    int32_t *first_hit;// [4G]
+    uint8_t *cls;      // [N] backbone classes (device profile)
+    int32_t *counts;   // [N] replicas with x_i = 1
+    uint8_t *frozen;   // [N]
+    int32_t *tally;    // [4] scratch for per-set reductions
+    int32_t n_rep, n_groups;
+};
+
+struct SweepCall {
+    const uint32_t *tab;    // [n_sweeps][n_classes][stride] thresholds
+    const uint8_t *var_cls; // per-variable class or nullptr
+    int32_t n_classes, stride, n_sweeps;
+    uint32_t t0;
+    int32_t target;
+    int32_t check_start;
+    uint32_t key0, key1;
+};
+
+// QAP: permutations as bytes, pair ranks in lexicographic order.
+constexpr int kQapMaxN = 255;
+constexpr int kQapLanesPerRep = 16;   // k-parts per replica inside a wave
+constexpr int kQapRepPerWave = 4;
+constexpr int kQapLowBits = 10;       // low digit of the two-level threshold
+
+struct QapDev {
+    const uint8_t *F;  // [n][n]
+    const uint8_t *D;  // [n][n]
+    int32_t n;
+    int32_t ha;        // entries of the high-digit threshold table
+};
+
+struct QapRepDev {
+    uint8_t *perm;      // [R][n]
+    uint8_t *best_perm; // [R][n]
+    int64_t *cost;      // [R]
+    int64_t *best;      // [R]
+    int32_t *first_hit; // [R]
+    uint8_t *cls;       // [n]
+    int32_t *freq;      // [n][n]
+    int32_t *tally;     // scratch
+    int32_t n_rep;
+};
+
+struct QapCall {
+    const uint32_t *tab;   // [n_sweeps][n_classes][ha + 1024]
+    const uint8_t *fac_cls;// per-facility class or nullptr
+    int32_t n_classes, stride, n_sweeps;
+    uint32_t t0;
+    int64_t target;
+    int32_t check_start;
+    uint32_t key0, key1;
+};
+
+// ---- launchers (nmc_ksat.hip) ----
+size_t ksat_sweep_lds_bytes(int n, int n_classes, int stride);
+hipError_t ksat_launch_init(const KsatDev &I, const KsatRepDev &R, uint32_t key0, uint32_t key1, hipStream_t s);
+hipError_t ksat_launch_recount(const KsatDev &I, const uint8_t *xs, int n_groups, int n_rep, int32_t *energy_out,
+                               hipStream_t s);
+hipError_t ksat_launch_reset_tallies(const KsatRepDev &R, int n, hipStream_t s);
+hipError_t ksat_launch_sweep(const KsatDev &I, const KsatRepDev &R, const SweepCall &C, int block_threads,
+                             hipStream_t s);
+hipError_t ksat_launch_backbone(const KsatDev &I, const KsatRepDev &R, int thr_num, int thr_den, int expand,
+                                hipStream_t s);
+hipError_t ksat_launch_tally(const KsatRepDev &R, hipStream_t s);
+hipError_t ksat_launch_unpack(const uint8_t *xs, int n, int n_groups, int n_rep, uint8_t *x_rows, hipStream_t s);
+hipError_t ksat_launch_pack(const uint8_t *x_rows, int n, int n_groups, int n_rep, uint8_t *xs, hipStream_t s);
+
+// ---- launchers (nmc_qap.hip) ----
+size_t qap_sweep_lds_bytes(int n, int n_classes, int stride);
+hipError_t qap_launch_init(const QapDev &I, const QapRepDev &R, uint32_t key0, uint32_t key1, hipStream_t s);
+hipError_t qap_launch_cost(const QapDev &I, const uint8_t *perm, int n_rep, int64_t *cost_out, hipStream_t s);
+hipError_t qap_launch_reset_tallies(const QapRepDev &R, int n, hipStream_t s);
+hipError_t qap_launch_sweep(const QapDev &I, const QapRepDev &R, const QapCall &C, int block_threads, hipStream_t s);
+hipError_t qap_launch_backbone(const QapDev &I, const QapRepDev &R, int thr_num, int thr_den, hipStream_t s);
+hipError_t qap_launch_tally(const QapRepDev &R, hipStream_t s);
+
+}  // namespace nmc

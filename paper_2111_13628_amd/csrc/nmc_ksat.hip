@@ -1,0 +1,443 @@
+// k-SAT kernels for gfx950.
+//
+// Work decomposition.  One workgroup owns one group of 4 replicas for the
+// whole launch.  Their spins live in LDS as a byte per variable (bit j =
+// replica j of the group), next to the complement table, so "literal is
+// true" is a single byte load whatever the literal's sign:
+//   lds[v]       = x_v        (positive literal of v)
+//   lds[N + v]   = NOT x_v    (negative literal of v)
+//   lds[2N]      = 0          (absent literal: never true)
+//   lds[2N + 1]  = all ones   (padding slot: clause counts as satisfied)
+// The energy change of flipping x_i (section "Nonequilibrium inhomogeneous
+// sampling over subgraphs" uses single-variable Metropolis moves; CNF energy
+// as in subsection "4-SAT Problems Near Computational Phase Transitions") is
+//   dE = sum over clauses a of i with every other literal false of
+//        (+1 if i's literal in a is currently true, -1 otherwise),
+// computed for the 4 replicas at once: the OR of the other literals' bytes
+// is a 4-bit "satisfied by others" mask, spread into four byte lanes of a
+// 32-bit accumulator (SIMD within a register).
+// A wave handles 64 variables of one colour class (one lane per variable);
+// classes are conflict-free, so all lanes update concurrently and the result
+// equals the sequential colour-major order.  The instance (per-variable
+// clause records) streams from L2/MALL, shared by every workgroup.
+#include <climits>
+
+#include "nmc_internal.h"
+#include "nmc_philox.h"
+
+namespace nmc {
+
+namespace {
+
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t spread4(uint32_t f) {
+    // bit j of f (j < 4) -> bit 8j; no carries for f < 16
+    return (f * 0x00204081u) & 0x01010101u;
+}
+
+__global__ void ksat_init_kernel(KsatDev I, KsatRepDev R, uint32_t key0, uint32_t key1) {
+    const size_t total = (size_t)R.n_groups * I.n;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        const int g = (int)(idx / I.n);
+        const int v = (int)(idx % I.n);
+        const int nact = min(kGroup, R.n_rep - g * kGroup);
+        const uint4 u = philox4x32_10((uint32_t)v, 0u, (uint32_t)g, kStreamKsatInit, key0, key1);
+        uint32_t b = (u.x >> 31) | ((u.y >> 31) << 1) | ((u.z >> 31) << 2) | ((u.w >> 31) << 3);
+        b &= (1u << nact) - 1u;
+        R.xs[idx] = (uint8_t)b;
+        R.best_xs[idx] = (uint8_t)b;
+    }
+}
+
+// Full energy count of every replica of one group (one workgroup per group).
+__global__ void ksat_recount_kernel(KsatDev I, const uint8_t *xs, int n_rep, int32_t *energy_out) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int n = I.n, g = blockIdx.x, tid = threadIdx.x;
+    const int nact = min(kGroup, n_rep - g * kGroup);
+    const uint32_t amask = (1u << nact) - 1u;
+    uint8_t *xt = smem;
+    int *red = (int *)(smem + align_up(2 * n + 2, 16));
+    for (int v = tid; v < n; v += blockDim.x) {
+        const uint32_t b = xs[(size_t)g * n + v] & amask;
+        xt[v] = (uint8_t)b;
+        xt[n + v] = (uint8_t)(~b & amask);
+    }
+    if (tid == 0) {
+        xt[2 * n] = 0;
+        xt[2 * n + 1] = (uint8_t)amask;
+    }
+    if (tid < kGroup)
+        red[tid] = 0;
+    __syncthreads();
+    int c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+    for (int a = tid; a < I.m; a += blockDim.x) {
+        const uint4 ad = reinterpret_cast<const uint4 *>(I.clause_addr)[a];
+        const uint32_t sat = xt[ad.x] | xt[ad.y] | xt[ad.z] | xt[ad.w];
+        const uint32_t f = ~sat & amask;
+        c0 += f & 1;
+        c1 += (f >> 1) & 1;
+        c2 += (f >> 2) & 1;
+        c3 += (f >> 3) & 1;
+    }
+    c0 = wave_sum(c0);
+    c1 = wave_sum(c1);
+    c2 = wave_sum(c2);
+    c3 = wave_sum(c3);
+    if ((tid & 63) == 0) {
+        atomicAdd(&red[0], c0);
+        atomicAdd(&red[1], c1);
+        atomicAdd(&red[2], c2);
+        atomicAdd(&red[3], c3);
+    }
+    __syncthreads();
+    if (tid < nact)
+        energy_out[g * kGroup + tid] = red[tid];
+}
+
+__global__ void ksat_reset_tallies_kernel(KsatRepDev R) {
+    const int total = R.n_groups * kGroup;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < total; r += gridDim.x * blockDim.x) {
+        R.best[r] = R.energy[r];
+        R.first_hit[r] = -1;
+    }
+}
+
+// The sweep kernel: n_sweeps full sweeps of every colour class for the 4
+// replicas of group blockIdx.x.
+__global__ void __launch_bounds__(1024) ksat_sweep_kernel(KsatDev I, KsatRepDev R, SweepCall C) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int n = I.n;
+    const int g = blockIdx.x;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
+    const int tab_words = C.n_classes * C.stride;
+
+    uint8_t *xt = smem;
+    uint32_t *tl = (uint32_t *)(smem + align_up(2 * n + 2, 16));
+    int *red = (int *)(tl + align_up(tab_words, 4));  // [0..3] dE sums, [4] improved mask
+
+    const int r0 = g * kGroup;
+    const int nact = min(kGroup, R.n_rep - r0);
+    const uint32_t amask = (1u << nact) - 1u;
+
+    uint8_t *xg = R.xs + (size_t)g * n;
+    for (int v = tid; v < n; v += nthr) {
+        const uint32_t b = xg[v] & amask;
+        xt[v] = (uint8_t)b;
+        xt[n + v] = (uint8_t)(~b & amask);
+    }
+    if (tid == 0) {
+        xt[2 * n] = 0;
+        xt[2 * n + 1] = (uint8_t)amask;
+    }
+    if (tid < 8)
+        red[tid] = 0;
+    int E = 0, best = 0, fh = -1;
+    if (tid < nact) {
+        E = R.energy[r0 + tid];
+        best = R.best[r0 + tid];
+        fh = R.first_hit[r0 + tid];
+        if (C.check_start && fh < 0 && E <= C.target)
+            fh = (int)C.t0;
+    }
+    __syncthreads();
+
+    for (int s = 0; s < C.n_sweeps; ++s) {
+        const uint32_t t = C.t0 + (uint32_t)s;
+        const uint32_t *tg = C.tab + (size_t)s * tab_words;
+        for (int i = tid; i < tab_words; i += nthr)
+            tl[i] = tg[i];
+        __syncthreads();
+
+        int d0 = 0, d1 = 0, d2 = 0, d3 = 0;
+        for (int c = 0; c < I.n_colors; ++c) {
+            const int h0 = I.color_chunk[c], h1 = I.color_chunk[c + 1];
+            for (int h = h0 + wave; h < h1; h += nwaves) {
+                const int2 info = I.chunk_info[h];
+                const int v = I.chunk_var[(size_t)h * kChunk + lane];
+                const uint64_t *rp = I.rec + (size_t)info.x * kChunk + lane;
+                uint32_t acc = 0x80808080u;
+#pragma unroll 4
+                for (int k = 0; k < info.y; ++k) {
+                    const uint64_t r = rp[(size_t)k * kChunk];
+                    const uint32_t a0 = (uint32_t)r & kAddrMask;
+                    const uint32_t a1 = (uint32_t)(r >> kAddrBits) & kAddrMask;
+                    const uint32_t a2 = (uint32_t)(r >> (2 * kAddrBits)) & kAddrMask;
+                    const uint32_t sm = 0u - (uint32_t)((r >> (3 * kAddrBits)) & 1u);
+                    const uint32_t sat = xt[a0] | xt[a1] | xt[a2];
+                    const uint32_t sp = spread4(~sat & 0xFu);
+                    acc += (sp ^ sm) - sm;
+                }
+                if (v >= 0) {
+                    const uint32_t xi = xt[v];
+                    const int cl = C.var_cls ? (int)C.var_cls[v] : 0;
+                    const uint32_t *T = tl + cl * C.stride;
+                    int de[kGroup];
+                    uint32_t thr[kGroup];
+                    uint32_t flip = 0, need = 0;
+#pragma unroll
+                    for (int j = 0; j < kGroup; ++j) {
+                        const int S = (int)((acc >> (8 * j)) & 0xFFu) - 128;
+                        de[j] = ((xi >> j) & 1u) ? S : -S;
+                        thr[j] = 0;
+                        if ((amask >> j) & 1u) {
+                            if (de[j] <= 0) {
+                                flip |= 1u << j;
+                            } else {
+                                thr[j] = T[de[j]];
+                                if (thr[j])
+                                    need |= 1u << j;
+                            }
+                        }
+                    }
+                    if (need) {
+                        const uint4 u = philox4x32_10((uint32_t)v, t, (uint32_t)g, kStreamKsatSweep, C.key0, C.key1);
+                        if ((need & 1u) && u.x < thr[0]) flip |= 1u;
+                        if ((need & 2u) && u.y < thr[1]) flip |= 2u;
+                        if ((need & 4u) && u.z < thr[2]) flip |= 4u;
+                        if ((need & 8u) && u.w < thr[3]) flip |= 8u;
+                    }
+                    if (flip) {
+                        const uint32_t nx = xi ^ flip;
+                        xt[v] = (uint8_t)nx;
+                        xt[n + v] = (uint8_t)(~nx & amask);
+                        if (flip & 1u) d0 += de[0];
+                        if (flip & 2u) d1 += de[1];
+                        if (flip & 4u) d2 += de[2];
+                        if (flip & 8u) d3 += de[3];
+                    }
+                }
+            }
+            __syncthreads();
+        }
+
+        // sweep end: exact energies, best, first hit, snapshot
+        d0 = wave_sum(d0);
+        d1 = wave_sum(d1);
+        d2 = wave_sum(d2);
+        d3 = wave_sum(d3);
+        if (lane == 0) {
+            if (d0) atomicAdd(&red[0], d0);
+            if (d1) atomicAdd(&red[1], d1);
+            if (d2) atomicAdd(&red[2], d2);
+            if (d3) atomicAdd(&red[3], d3);
+        }
+        __syncthreads();
+        if (tid < nact) {
+            E += red[tid];
+            if (E < best) {
+                best = E;
+                atomicOr(&red[4], 1 << tid);
+            }
+            if (fh < 0 && E <= C.target)
+                fh = (int)(t + 1);
+        }
+        __syncthreads();
+        const uint32_t imp = (uint32_t)red[4];
+        if (imp) {
+            uint8_t *bg = R.best_xs + (size_t)g * n;
+            for (int v = tid; v < n; v += nthr)
+                bg[v] = (uint8_t)((bg[v] & ~imp) | (xt[v] & imp));
+        }
+        __syncthreads();
+        if (tid < 8)
+            red[tid] = 0;
+    }
+
+    __syncthreads();
+    for (int v = tid; v < n; v += nthr)
+        xg[v] = xt[v];
+    if (tid < nact) {
+        R.energy[r0 + tid] = E;
+        R.best[r0 + tid] = best;
+        R.first_hit[r0 + tid] = fh;
+    }
+}
+
+// c_i = replicas with x_i = 1; frozen_i per the |magnetization| threshold.
+__global__ void ksat_magnetization_kernel(KsatDev I, KsatRepDev R, int thr_num, int thr_den, int expand) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= I.n)
+        return;
+    int c = 0;
+    for (int g = 0; g < R.n_groups; ++g)
+        c += __popc((uint32_t)R.xs[(size_t)g * I.n + v]);
+    R.counts[v] = c;
+    long long dev = 2ll * c - R.n_rep;
+    if (dev < 0)
+        dev = -dev;
+    const uint8_t fz = (long long)thr_den * dev >= (long long)thr_num * R.n_rep;
+    R.frozen[v] = fz;
+    if (!expand)
+        R.cls[v] = fz;
+}
+
+// hot_i = frozen_i or some clause of i holds a frozen variable.
+__global__ void ksat_expand_kernel(KsatDev I, KsatRepDev R) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= I.n)
+        return;
+    uint8_t hot = R.frozen[v];
+    for (int q = I.var_ptr[v]; q < I.var_ptr[v + 1] && !hot; ++q) {
+        const uint4 ad = reinterpret_cast<const uint4 *>(I.clause_addr)[I.var_cl[q]];
+        const uint32_t a[4] = {ad.x, ad.y, ad.z, ad.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (a[j] < (uint32_t)(2 * I.n)) {
+                const uint32_t w = a[j] < (uint32_t)I.n ? a[j] : a[j] - I.n;
+                hot |= R.frozen[w];
+            }
+        }
+    }
+    R.cls[v] = hot;
+}
+
+// tally[0] = lowest best energy, tally[1] = replicas with best energy 0.
+__global__ void ksat_tally_kernel(KsatRepDev R) {
+    __shared__ int smin[16], scnt[16];
+    int mn = INT_MAX, cnt = 0;
+    for (int r = threadIdx.x; r < R.n_rep; r += blockDim.x) {
+        const int b = R.best[r];
+        mn = min(mn, b);
+        cnt += b == 0;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        mn = min(mn, __shfl_xor(mn, off, 64));
+        cnt += __shfl_xor(cnt, off, 64);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        smin[w] = mn;
+        scnt[w] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
+            mn = min(mn, smin[i]);
+            cnt += scnt[i];
+        }
+        R.tally[0] = mn;
+        R.tally[1] = cnt;
+    }
+}
+
+__global__ void ksat_unpack_kernel(const uint8_t *xs, int n, int n_rep, uint8_t *rows) {
+    const size_t total = (size_t)n_rep * n;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        const int r = (int)(idx / n), v = (int)(idx % n);
+        rows[idx] = (xs[(size_t)(r / kGroup) * n + v] >> (r % kGroup)) & 1u;
+    }
+}
+
+__global__ void ksat_pack_kernel(const uint8_t *rows, int n, int n_groups, int n_rep, uint8_t *xs) {
+    const size_t total = (size_t)n_groups * n;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        const int g = (int)(idx / n), v = (int)(idx % n);
+        uint32_t b = 0;
+        for (int j = 0; j < kGroup; ++j) {
+            const int r = g * kGroup + j;
+            if (r < n_rep)
+                b |= (rows[(size_t)r * n + v] & 1u) << j;
+        }
+        xs[idx] = (uint8_t)b;
+    }
+}
+
+int grid_for(size_t total, int block) {
+    size_t g = (total + block - 1) / block;
+    if (g > 65536)
+        g = 65536;
+    return (int)(g < 1 ? 1 : g);
+}
+
+}  // namespace
+
+size_t ksat_sweep_lds_bytes(int n, int n_classes, int stride) {
+    return align_up(2 * (size_t)n + 2, 16) + align_up((size_t)n_classes * stride, 4) * 4 + 8 * sizeof(int);
+}
+
+hipError_t ksat_launch_init(const KsatDev &I, const KsatRepDev &R, uint32_t key0, uint32_t key1, hipStream_t s) {
+    const size_t total = (size_t)R.n_groups * I.n;
+    hipLaunchKernelGGL(ksat_init_kernel, dim3(grid_for(total, 256)), dim3(256), 0, s, I, R, key0, key1);
+    return hipGetLastError();
+}
+
+hipError_t ksat_launch_recount(const KsatDev &I, const uint8_t *xs, int n_groups, int n_rep, int32_t *energy_out,
+                               hipStream_t s) {
+    const size_t lds = align_up(2 * (size_t)I.n + 2, 16) + 16 * sizeof(int);
+    static bool attr = false;
+    if (!attr) {
+        const hipError_t ea = hipFuncSetAttribute((const void *)ksat_recount_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                  (int)kLdsBytes);
+        if (ea != hipSuccess)
+            return ea;
+        attr = true;
+    }
+    hipLaunchKernelGGL(ksat_recount_kernel, dim3(n_groups), dim3(1024), lds, s, I, xs, n_rep, energy_out);
+    return hipGetLastError();
+}
+
+hipError_t ksat_launch_reset_tallies(const KsatRepDev &R, int n, hipStream_t s) {
+    hipLaunchKernelGGL(ksat_reset_tallies_kernel, dim3(grid_for((size_t)R.n_groups * kGroup, 256)), dim3(256), 0, s,
+                       R);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    return hipMemcpyAsync(R.best_xs, R.xs, (size_t)R.n_groups * n, hipMemcpyDeviceToDevice, s);
+}
+
+hipError_t ksat_launch_sweep(const KsatDev &I, const KsatRepDev &R, const SweepCall &C, int block_threads,
+                             hipStream_t s) {
+    const size_t lds = ksat_sweep_lds_bytes(I.n, C.n_classes, C.stride);
+    static bool attr = false;
+    if (!attr) {
+        const hipError_t ea = hipFuncSetAttribute((const void *)ksat_sweep_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                  (int)kLdsBytes);
+        if (ea != hipSuccess)
+            return ea;
+        attr = true;
+    }
+    hipLaunchKernelGGL(ksat_sweep_kernel, dim3(R.n_groups), dim3(block_threads), lds, s, I, R, C);
+    return hipGetLastError();
+}
+
+hipError_t ksat_launch_backbone(const KsatDev &I, const KsatRepDev &R, int thr_num, int thr_den, int expand,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(ksat_magnetization_kernel, dim3((I.n + 255) / 256), dim3(256), 0, s, I, R, thr_num, thr_den,
+                       expand);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !expand)
+        return e;
+    hipLaunchKernelGGL(ksat_expand_kernel, dim3((I.n + 255) / 256), dim3(256), 0, s, I, R);
+    return hipGetLastError();
+}
+
+hipError_t ksat_launch_tally(const KsatRepDev &R, hipStream_t s) {
+    hipLaunchKernelGGL(ksat_tally_kernel, dim3(1), dim3(1024), 0, s, R);
+    return hipGetLastError();
+}
+
+hipError_t ksat_launch_unpack(const uint8_t *xs, int n, int n_groups, int n_rep, uint8_t *rows, hipStream_t s) {
+    (void)n_groups;
+    hipLaunchKernelGGL(ksat_unpack_kernel, dim3(grid_for((size_t)n_rep * n, 256)), dim3(256), 0, s, xs, n, n_rep,
+                       rows);
+    return hipGetLastError();
+}
+
+hipError_t ksat_launch_pack(const uint8_t *rows, int n, int n_groups, int n_rep, uint8_t *xs, hipStream_t s) {
+    hipLaunchKernelGGL(ksat_pack_kernel, dim3(grid_for((size_t)n_groups * n, 256)), dim3(256), 0, s, rows, n,
+                       n_groups, n_rep, xs);
+    return hipGetLastError();
+}
+
+}  // namespace nmc

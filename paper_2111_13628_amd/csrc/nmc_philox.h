@@ -1,0 +1,31 @@
+// Device Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers:
+// as easy as 1, 2, 3", SC'11): ten rounds of the 4-word S-box with
+// multipliers 0xD2511F53 / 0xCD9E8D57 and Weyl key increments 0x9E3779B9 /
+// 0xBB67AE85.  When every argument is wave-uniform the compiler keeps the
+// whole generator on the scalar unit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nmc {
+
+__device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                               uint32_t k1) {
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t lo0 = c0 * 0xD2511F53u;
+        const uint32_t hi0 = __umulhi(c0, 0xD2511F53u);
+        const uint32_t lo1 = c2 * 0xCD9E8D57u;
+        const uint32_t hi1 = __umulhi(c2, 0xCD9E8D57u);
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+}  // namespace nmc

@@ -1,0 +1,305 @@
+// QAP kernels for gfx950.
+//
+// A workgroup of 4 waves owns 16 replicas; each wave runs 4 replicas in
+// lockstep through the lexicographic pair sequence, 16 lanes per replica
+// splitting the sum over facilities k.  Flow F, distance D (bytes), the 16
+// permutations and the current sweep's threshold tables sit in LDS.
+// For symmetric, zero-diagonal F and D (subsection "Quadratic Assignment
+// Problems"; cost sum_ij F_ij D_{p_i p_j}) exchanging the locations of
+// facilities a and b changes the cost by
+//   dC = 2 * sum_{k != a,b} (F_ak - F_bk) * (D_{p_b p_k} - D_{p_a p_k}).
+// The 4 replicas of a wave form one Philox group, so one wave-uniform
+// generator call serves all of them.
+#include <climits>
+
+#include "nmc_internal.h"
+#include "nmc_philox.h"
+
+namespace nmc {
+
+namespace {
+
+constexpr int kRepPerBlock = kQapRepPerWave * 4;  // 4 waves
+
+__global__ void qap_init_kernel(QapDev I, QapRepDev R, uint32_t key0, uint32_t key1) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R.n_rep)
+        return;
+    const int n = I.n;
+    uint8_t *p = R.perm + (size_t)r * n;
+    for (int i = 0; i < n; ++i)
+        p[i] = (uint8_t)i;
+    for (int j = n - 1; j >= 1; --j) {
+        const uint4 u4 = philox4x32_10((uint32_t)j, 0u, (uint32_t)(r >> 2), kStreamQapInit, key0, key1);
+        const uint32_t w = (r & 3) == 0 ? u4.x : (r & 3) == 1 ? u4.y : (r & 3) == 2 ? u4.z : u4.w;
+        const int k = (int)(((uint64_t)w * (uint64_t)(j + 1)) >> 32);
+        const uint8_t tmp = p[j];
+        p[j] = p[k];
+        p[k] = tmp;
+    }
+    for (int i = 0; i < n; ++i)
+        R.best_perm[(size_t)r * n + i] = p[i];
+}
+
+// Full cost of every replica: one workgroup per replica.
+__global__ void qap_cost_kernel(QapDev I, const uint8_t *perm, int64_t *cost_out) {
+    __shared__ uint8_t p[kQapMaxN + 1];
+    __shared__ long long part[16];
+    const int r = blockIdx.x, n = I.n, tid = threadIdx.x;
+    for (int i = tid; i < n; i += blockDim.x)
+        p[i] = perm[(size_t)r * n + i];
+    __syncthreads();
+    long long c = 0;
+    for (int idx = tid; idx < n * n; idx += blockDim.x) {
+        const int i = idx / n, j = idx % n;
+        c += (long long)I.F[idx] * I.D[p[i] * n + p[j]];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        c += __shfl_xor(c, off, 64);
+    if ((tid & 63) == 0)
+        part[tid >> 6] = c;
+    __syncthreads();
+    if (tid == 0) {
+        long long s = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w)
+            s += part[w];
+        cost_out[r] = s;
+    }
+}
+
+__global__ void qap_reset_tallies_kernel(QapRepDev R) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < R.n_rep) {
+        R.best[r] = R.cost[r];
+        R.first_hit[r] = -1;
+    }
+}
+
+__global__ void __launch_bounds__(256) qap_sweep_kernel(QapDev I, QapRepDev R, QapCall C) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int n = I.n, nn = n * n;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int sub = lane >> 4, q = lane & 15;
+    const int npad = (int)align_up(n, 4);
+
+    uint8_t *F = smem;
+    uint8_t *D = F + align_up(nn, 16);
+    uint8_t *P = D + align_up(nn, 16);
+    uint8_t *cls = P + kRepPerBlock * npad;
+    uint32_t *tl = (uint32_t *)(cls + align_up(n, 16));
+    const int tab_words = C.n_classes * C.stride;
+
+    for (int i = tid; i < nn; i += blockDim.x) {
+        F[i] = I.F[i];
+        D[i] = I.D[i];
+    }
+    for (int i = tid; i < n; i += blockDim.x)
+        cls[i] = C.fac_cls ? C.fac_cls[i] : 0;
+    const int rbase = blockIdx.x * kRepPerBlock;
+    for (int i = tid; i < kRepPerBlock * n; i += blockDim.x) {
+        const int rl = i / n, f = i % n;
+        const int rep = rbase + rl;
+        P[rl * npad + f] = rep < R.n_rep ? R.perm[(size_t)rep * n + f] : (uint8_t)f;
+    }
+
+    const int rl = wave * kQapRepPerWave + sub;
+    const int rep = rbase + rl;
+    const bool active = rep < R.n_rep;
+    uint8_t *pr = P + rl * npad;
+    const uint32_t group = (uint32_t)((rbase + wave * kQapRepPerWave) >> 2);
+
+    long long cost = 0, best = 0;
+    int fh = -1;
+    if (active) {
+        cost = R.cost[rep];
+        best = R.best[rep];
+        fh = R.first_hit[rep];
+        if (C.check_start && fh < 0 && cost <= C.target)
+            fh = (int)C.t0;
+    }
+    __syncthreads();
+
+    for (int s = 0; s < C.n_sweeps; ++s) {
+        const uint32_t t = C.t0 + (uint32_t)s;
+        const uint32_t *tg = C.tab + (size_t)s * tab_words;
+        for (int i = tid; i < tab_words; i += blockDim.x)
+            tl[i] = tg[i];
+        __syncthreads();
+
+        uint32_t qidx = 0;
+        for (int a = 0; a < n - 1; ++a) {
+            const int ca = cls[a];
+            for (int b = a + 1; b < n; ++b, ++qidx) {
+                const int pa = pr[a], pb = pr[b];
+                int part = 0;
+                for (int k = q; k < n; k += kQapLanesPerRep) {
+                    if (k == a || k == b)
+                        continue;
+                    const int pk = pr[k];
+                    part += ((int)F[a * n + k] - (int)F[b * n + k]) * ((int)D[pb * n + pk] - (int)D[pa * n + pk]);
+                }
+                part += __shfl_xor(part, 8, 16);
+                part += __shfl_xor(part, 4, 16);
+                part += __shfl_xor(part, 2, 16);
+                part += __shfl_xor(part, 1, 16);
+                const int dc = 2 * part;
+                bool accept = dc <= 0;
+                const bool need = active && !accept;
+                if (__any(need)) {
+                    const uint4 u4 = philox4x32_10(qidx, t, group, kStreamQapSweep, C.key0, C.key1);
+                    const uint32_t u = sub == 0 ? u4.x : sub == 1 ? u4.y : sub == 2 ? u4.z : u4.w;
+                    const int cl = max(ca, (int)cls[b]);
+                    const uint32_t *T = tl + cl * C.stride;
+                    const int h = dc >> kQapLowBits, l = dc & ((1 << kQapLowBits) - 1);
+                    uint32_t thr = 0;
+                    if (need && h < I.ha)
+                        thr = (uint32_t)(((uint64_t)T[h] * (uint64_t)T[I.ha + l]) >> 32);
+                    if (need)
+                        accept = u < thr;
+                }
+                if (active && accept) {
+                    if (q == 0) {
+                        pr[a] = (uint8_t)pb;
+                        pr[b] = (uint8_t)pa;
+                    }
+                    cost += dc;
+                }
+            }
+        }
+        // sweep end
+        bool imp = false;
+        if (active) {
+            if (cost < best) {
+                best = cost;
+                imp = true;
+            }
+            if (fh < 0 && cost <= C.target)
+                fh = (int)(t + 1);
+        }
+        if (imp) {
+            for (int f = q; f < n; f += kQapLanesPerRep)
+                R.best_perm[(size_t)rep * n + f] = pr[f];
+        }
+        __syncthreads();
+    }
+
+    if (active) {
+        for (int f = q; f < n; f += kQapLanesPerRep)
+            R.perm[(size_t)rep * n + f] = pr[f];
+        if (q == 0) {
+            R.cost[rep] = cost;
+            R.best[rep] = best;
+            R.first_hit[rep] = fh;
+        }
+    }
+}
+
+// Assignment frequencies and the per-facility frozen test: one workgroup per facility.
+__global__ void qap_backbone_kernel(QapDev I, QapRepDev R, int thr_num, int thr_den) {
+    __shared__ int hist[kQapMaxN + 1];
+    __shared__ int mx;
+    const int f = blockIdx.x, n = I.n;
+    for (int l = threadIdx.x; l < n; l += blockDim.x)
+        hist[l] = 0;
+    if (threadIdx.x == 0)
+        mx = 0;
+    __syncthreads();
+    for (int r = threadIdx.x; r < R.n_rep; r += blockDim.x)
+        atomicAdd(&hist[R.perm[(size_t)r * n + f]], 1);
+    __syncthreads();
+    for (int l = threadIdx.x; l < n; l += blockDim.x) {
+        R.freq[(size_t)f * n + l] = hist[l];
+        atomicMax(&mx, hist[l]);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        R.cls[f] = (long long)thr_den * mx >= (long long)thr_num * R.n_rep;
+}
+
+__global__ void qap_tally_kernel(QapRepDev R) {
+    __shared__ long long smin[16];
+    __shared__ int scnt[16];
+    long long mn = LLONG_MAX;
+    int cnt = 0;
+    for (int r = threadIdx.x; r < R.n_rep; r += blockDim.x) {
+        const long long b = R.best[r];
+        mn = b < mn ? b : mn;
+        cnt += b == 0;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const long long o = __shfl_xor(mn, off, 64);
+        mn = o < mn ? o : mn;
+        cnt += __shfl_xor(cnt, off, 64);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        smin[w] = mn;
+        scnt[w] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
+            mn = smin[i] < mn ? smin[i] : mn;
+            cnt += scnt[i];
+        }
+        reinterpret_cast<long long *>(R.tally)[0] = mn;
+        R.tally[2] = cnt;
+    }
+}
+
+}  // namespace
+
+size_t qap_sweep_lds_bytes(int n, int n_classes, int stride) {
+    const size_t nn = (size_t)n * n;
+    return 2 * align_up(nn, 16) + kRepPerBlock * align_up(n, 4) + align_up(n, 16) +
+           (size_t)n_classes * stride * sizeof(uint32_t);
+}
+
+hipError_t qap_launch_init(const QapDev &I, const QapRepDev &R, uint32_t key0, uint32_t key1, hipStream_t s) {
+    hipLaunchKernelGGL(qap_init_kernel, dim3((R.n_rep + 127) / 128), dim3(128), 0, s, I, R, key0, key1);
+    return hipGetLastError();
+}
+
+hipError_t qap_launch_cost(const QapDev &I, const uint8_t *perm, int n_rep, int64_t *cost_out, hipStream_t s) {
+    hipLaunchKernelGGL(qap_cost_kernel, dim3(n_rep), dim3(256), 0, s, I, perm, cost_out);
+    return hipGetLastError();
+}
+
+hipError_t qap_launch_reset_tallies(const QapRepDev &R, int n, hipStream_t s) {
+    hipLaunchKernelGGL(qap_reset_tallies_kernel, dim3((R.n_rep + 255) / 256), dim3(256), 0, s, R);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    return hipMemcpyAsync(R.best_perm, R.perm, (size_t)R.n_rep * n, hipMemcpyDeviceToDevice, s);
+}
+
+hipError_t qap_launch_sweep(const QapDev &I, const QapRepDev &R, const QapCall &C, int block_threads, hipStream_t s) {
+    (void)block_threads;
+    const size_t lds = qap_sweep_lds_bytes(I.n, C.n_classes, C.stride);
+    static bool attr = false;
+    if (!attr) {
+        const hipError_t ea = hipFuncSetAttribute((const void *)qap_sweep_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                  (int)kLdsBytes);
+        if (ea != hipSuccess)
+            return ea;
+        attr = true;
+    }
+    const int blocks = (R.n_rep + kRepPerBlock - 1) / kRepPerBlock;
+    hipLaunchKernelGGL(qap_sweep_kernel, dim3(blocks), dim3(256), lds, s, I, R, C);
+    return hipGetLastError();
+}
+
+hipError_t qap_launch_backbone(const QapDev &I, const QapRepDev &R, int thr_num, int thr_den, hipStream_t s) {
+    hipLaunchKernelGGL(qap_backbone_kernel, dim3(I.n), dim3(256), 0, s, I, R, thr_num, thr_den);
+    return hipGetLastError();
+}
+
+hipError_t qap_launch_tally(const QapRepDev &R, hipStream_t s) {
+    hipLaunchKernelGGL(qap_tally_kernel, dim3(1), dim3(1024), 0, s, R);
+    return hipGetLastError();
+}
+
+}  // namespace nmc

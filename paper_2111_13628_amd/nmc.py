@@ -1,0 +1,302 @@
+"""ctypes binding of the NMC C ABI (include/nmc.h).
+
+Argument marshalling only: every step of the Monte Carlo path runs in the
+HIP kernels of libnmc.so.  PyTorch supplies device memory (uint8 tensors on
+cuda:0) and streams.  There is no fallback: if libnmc.so is missing or a
+GPU call fails, the call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnmc.so")
+HEADER_PATH = os.path.join(_HERE, "..", "include", "nmc.h")
+
+NMC_OK = 0
+KIND_KSAT, KIND_QAP = 1, 2
+PROFILE = {"homogeneous": 0, "host": 1, "backbone": 2}
+STATE = {"current": 0, "best": 1}
+ERRORS = {-1: "INVALID", -2: "SIZE", -3: "DEVICE", -4: "STATE", -5: "CAPACITY", -6: "UNSUPPORTED"}
+
+
+class NmcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"NMC_ERR_{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class InstanceInfo(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n_items", ctypes.c_int32), ("n_clauses", ctypes.c_int32),
+                ("max_clause_len", ctypes.c_int32), ("max_degree", ctypes.c_int32),
+                ("n_colors", ctypes.c_int32), ("delta_bound", ctypes.c_int64)]
+
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_U32 = ctypes.c_uint32
+_I64 = ctypes.c_int64
+_U64 = ctypes.c_uint64
+_SZ = ctypes.c_size_t
+_PP = ctypes.POINTER(ctypes.c_void_p)
+
+_SIGS = {
+    "nmc_last_error": ([], ctypes.c_char_p),
+    "nmc_version": ([], _I32),
+    "nmc_ksat_load": ([_I32, _I32, _P, _P, _I32, _PP], ctypes.c_int),
+    "nmc_qap_load": ([_I32, _P, _P, _PP], ctypes.c_int),
+    "nmc_instance_get_info": ([_P, ctypes.POINTER(InstanceInfo)], ctypes.c_int),
+    "nmc_instance_order": ([_P, _P, _P, _P], ctypes.c_int),
+    "nmc_footprint": ([_P, _I32, ctypes.POINTER(_SZ), ctypes.POINTER(_SZ)], ctypes.c_int),
+    "nmc_instance_bind": ([_P, _P, _SZ, _P], ctypes.c_int),
+    "nmc_instance_free": ([_P], None),
+    "nmc_replicas_create": ([_P, _I32, _U64, _P, _SZ, _P, _PP], ctypes.c_int),
+    "nmc_replicas_free": ([_P], None),
+    "nmc_anneal": ([_P, _P, _I32, _I32, _I32, _P, _I64, _P], ctypes.c_int),
+    "nmc_reanneal": ([_P, _P, _I32, _I32, _I32, _P, _I64, _P], ctypes.c_int),
+    "nmc_estimate_backbone": ([_P, _I32, _I32, _I32, _P, _P, _P], ctypes.c_int),
+    "nmc_best_energy": ([_P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "nmc_recount": ([_P, _P, _P], ctypes.c_int),
+    "nmc_get_state": ([_P, _I32, _P, _SZ, _P], ctypes.c_int),
+    "nmc_set_state": ([_P, _P, _SZ, _U32, _P], ctypes.c_int),
+    "nmc_replicas_info": ([_P, _P, _P, _P], ctypes.c_int),
+    "nmc_set_tuning": ([_P, _I32], ctypes.c_int),
+    "nmc_set_profiling": ([_P, _I32], ctypes.c_int),
+    "nmc_kernel_time": ([_P, _P, _P, _P, _I32], ctypes.c_int),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libnmc.so (built by __graft_entry__.build()); raise if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        # torch ships its own HIP runtime with the same soname; loading it first
+        # makes libnmc.so bind to that one runtime, so torch streams and device
+        # pointers are valid handles inside the library.
+        import torch  # noqa: F401
+        L = ctypes.CDLL(LIB_PATH)
+        _check_single_hip_runtime()
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check_single_hip_runtime():
+    try:
+        maps = open("/proc/self/maps").read().split("\n")
+    except OSError:
+        return
+    paths = {os.path.realpath(l.split()[-1]) for l in maps if "libamdhip64" in l and "/" in l}
+    if len(paths) > 1:
+        raise ImportError("two HIP runtimes are mapped in this process: " + ", ".join(sorted(paths)))
+
+
+def header_functions():
+    """Names of the functions include/nmc.h declares."""
+    text = open(HEADER_PATH).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nmc_[a-z0-9_]+)\s*\(", text)))
+
+
+def _check(rc):
+    if rc != NMC_OK:
+        raise NmcError(rc, lib().nmc_last_error().decode())
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _device_buffer(nbytes: int):
+    import torch
+    if not torch.cuda.is_available():
+        raise NmcError(-3, "no GPU visible to torch")
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device="cuda")
+
+
+class Instance:
+    """A loaded k-SAT or QAP instance.  Host metadata lives in the library;
+    the device layout is uploaded into a torch buffer by bind()."""
+
+    def __init__(self, handle, kind):
+        self._h = handle
+        self.kind = kind
+        self._buf = None
+        self.info = InstanceInfo()
+        _check(lib().nmc_instance_get_info(self._h, ctypes.byref(self.info)))
+
+    @classmethod
+    def ksat(cls, n_vars, clause_ptr, lits, class_cap=0):
+        cp = np.ascontiguousarray(clause_ptr, np.int32)
+        li = np.ascontiguousarray(lits, np.int32)
+        h = ctypes.c_void_p()
+        _check(lib().nmc_ksat_load(int(n_vars), len(cp) - 1, _ptr(cp), _ptr(li), int(class_cap), ctypes.byref(h)))
+        return cls(h, KIND_KSAT)
+
+    @classmethod
+    def qap(cls, flow, dist):
+        F = np.ascontiguousarray(flow, np.int32)
+        D = np.ascontiguousarray(dist, np.int32)
+        h = ctypes.c_void_p()
+        _check(lib().nmc_qap_load(int(F.shape[0]), _ptr(F), _ptr(D), ctypes.byref(h)))
+        return cls(h, KIND_QAP)
+
+    @property
+    def n(self):
+        return self.info.n_items
+
+    def order(self):
+        n = self.info.n_items
+        order = np.zeros(n, np.int32)
+        cptr = np.zeros(self.info.n_colors + 1, np.int32)
+        nc = ctypes.c_int32()
+        _check(lib().nmc_instance_order(self._h, _ptr(order), _ptr(cptr), ctypes.byref(nc)))
+        return order, cptr
+
+    def footprint(self, n_replicas):
+        ib, rb = _SZ(), _SZ()
+        _check(lib().nmc_footprint(self._h, int(n_replicas), ctypes.byref(ib), ctypes.byref(rb)))
+        return ib.value, rb.value
+
+    def bind(self, stream=None):
+        ib, _ = self.footprint(1)
+        self._buf = _device_buffer(ib)
+        _check(lib().nmc_instance_bind(self._h, ctypes.c_void_p(self._buf.data_ptr()), self._buf.numel(),
+                                       _stream(stream)))
+        return self
+
+    def free(self):
+        if self._h:
+            lib().nmc_instance_free(self._h)
+            self._h = None
+        self._buf = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Replicas:
+    """R independent chains of one bound instance (nmc_replicas_create)."""
+
+    def __init__(self, inst: Instance, n_replicas: int, seed: int, stream=None):
+        self.inst = inst
+        self.R = int(n_replicas)
+        self.seed = int(seed)
+        _, rb = inst.footprint(self.R)
+        self._buf = _device_buffer(rb)
+        h = ctypes.c_void_p()
+        _check(lib().nmc_replicas_create(inst._h, self.R, ctypes.c_uint64(self.seed),
+                                         ctypes.c_void_p(self._buf.data_ptr()), self._buf.numel(),
+                                         _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    # -- schedule calls
+    def _run(self, fn, beta, profile, class_of, target, stream):
+        b = np.atleast_2d(np.ascontiguousarray(beta, np.float64))
+        nc, S = b.shape
+        b = np.ascontiguousarray(b)
+        cls = None if class_of is None else np.ascontiguousarray(class_of, np.uint8)
+        if isinstance(profile, str):
+            profile = PROFILE[profile]
+        if cls is not None and profile == 0:
+            profile = PROFILE["host"]
+        _check(fn(self._h, _ptr(b), nc, S, int(profile), _ptr(cls), ctypes.c_int64(int(target)), _stream(stream)))
+
+    def anneal(self, beta, profile="homogeneous", class_of=None, target=-1, stream=None):
+        self._run(lib().nmc_anneal, beta, profile, class_of, target, stream)
+
+    def reanneal(self, beta, profile="backbone", class_of=None, target=-1, stream=None):
+        self._run(lib().nmc_reanneal, beta, profile, class_of, target, stream)
+
+    def estimate_backbone(self, thr_num=9, thr_den=10, expand=True, stream=None):
+        n = self.inst.n
+        cls = np.zeros(n, np.uint8)
+        counts = np.zeros(n * n if self.inst.kind == KIND_QAP else n, np.int32)
+        _check(lib().nmc_estimate_backbone(self._h, int(thr_num), int(thr_den), int(bool(expand)), _ptr(cls),
+                                           _ptr(counts), _stream(stream)))
+        if self.inst.kind == KIND_QAP:
+            counts = counts.reshape(n, n)
+        return cls, counts
+
+    def estimate_backbone_device(self, thr_num=9, thr_den=10, expand=True, stream=None):
+        """Backbone classes kept on the device only (no host copy, no sync)."""
+        _check(lib().nmc_estimate_backbone(self._h, int(thr_num), int(thr_den), int(bool(expand)), None, None,
+                                           _stream(stream)))
+
+    def best_energy(self, stream=None):
+        R = self.R
+        best = ctypes.c_int64()
+        nz = ctypes.c_int32()
+        bpr = np.zeros(R, np.int64)
+        e = np.zeros(R, np.int64)
+        fh = np.zeros(R, np.int32)
+        _check(lib().nmc_best_energy(self._h, ctypes.byref(best), ctypes.byref(nz), _ptr(bpr), _ptr(e), _ptr(fh),
+                                     _stream(stream)))
+        return dict(best=best.value, n_at_zero=nz.value, best_per_replica=bpr, energy=e, first_hit=fh)
+
+    def recount(self, stream=None):
+        e = np.zeros(self.R, np.int64)
+        _check(lib().nmc_recount(self._h, _ptr(e), _stream(stream)))
+        return e
+
+    def get_state(self, which="current", stream=None):
+        out = np.zeros((self.R, self.inst.n), np.uint8)
+        _check(lib().nmc_get_state(self._h, STATE[which], _ptr(out), out.nbytes, _stream(stream)))
+        return out
+
+    def set_state(self, x, sweeps_done, stream=None):
+        x = np.ascontiguousarray(x, np.uint8)
+        _check(lib().nmc_set_state(self._h, _ptr(x), x.nbytes, ctypes.c_uint32(int(sweeps_done)), _stream(stream)))
+
+    def sweeps_done(self):
+        r, s, t = _I32(), _U64(), _U32()
+        _check(lib().nmc_replicas_info(self._h, ctypes.byref(r), ctypes.byref(s), ctypes.byref(t)))
+        return t.value
+
+    def set_tuning(self, block_threads=0):
+        _check(lib().nmc_set_tuning(self._h, int(block_threads)))
+
+    def set_profiling(self, enable=True):
+        _check(lib().nmc_set_profiling(self._h, int(bool(enable))))
+
+    def kernel_time(self, reset=False):
+        ms = ctypes.c_double()
+        launches = ctypes.c_int64()
+        att = ctypes.c_double()
+        _check(lib().nmc_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(launches), ctypes.byref(att),
+                                     int(bool(reset))))
+        return dict(ms=ms.value, launches=launches.value, attempts=att.value)
+
+    def free(self):
+        if getattr(self, "_h", None):
+            lib().nmc_replicas_free(self._h)
+            self._h = None
+        self._buf = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

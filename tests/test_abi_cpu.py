@@ -1,0 +1,105 @@
+"""Host-side checks of the C ABI that run without a GPU: every declared
+symbol is exported, input validation and error codes, footprints, and the
+library's sweep order equals the oracle's colouring."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2111_13628_amd import instances, nmc
+
+
+def test_library_exports_every_header_symbol():
+    L = nmc.lib()
+    names = nmc.header_functions()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(L, name), name
+    assert L.nmc_version() >= 100
+
+
+def _load(n, cp, lits, cap=0):
+    return nmc.Instance.ksat(n, cp, lits, cap)
+
+
+@pytest.mark.parametrize("cp,lits,code", [
+    ([0, 2], [1, 0], -1),              # literal 0
+    ([0, 2], [1, 4], -1),              # variable out of range
+    ([0, 2], [2, -2], -1),             # repeated variable
+    ([0, 0, 2], [1, 2], -1),           # empty clause
+    ([0, 4], [1, 2, 3, -1], -1),       # repeated variable in a 4-literal clause
+    ([0, 1, 0], [1], -1),              # decreasing offsets
+])
+def test_ksat_validation_errors(cp, lits, code):
+    with pytest.raises(nmc.NmcError) as e:
+        _load(3, np.array(cp), np.array(lits))
+    assert e.value.code == code
+
+
+def test_ksat_unsupported():
+    with pytest.raises(nmc.NmcError) as e:
+        _load(6, np.array([0, 5]), np.array([1, 2, 3, 4, 5]))
+    assert e.value.code == -6
+    with pytest.raises(nmc.NmcError) as e:
+        _load(70000, np.array([0, 1]), np.array([1]))
+    assert e.value.code == -6
+    # a variable in 128 clauses exceeds the per-variable accumulator range
+    cp = np.arange(0, 129 * 2, 2)
+    lits = np.array([[1, v + 2] for v in range(128)]).ravel()
+    with pytest.raises(nmc.NmcError) as e:
+        _load(200, cp, lits)
+    assert e.value.code == -6
+
+
+def test_qap_validation_errors():
+    F, D = instances.gen_qap(6, 1)
+    bad = F.copy()
+    bad[0, 1] += 1
+    with pytest.raises(nmc.NmcError) as e:
+        nmc.Instance.qap(bad, D)
+    assert e.value.code == -1
+    bad = D.copy()
+    bad[2, 2] = 3
+    with pytest.raises(nmc.NmcError) as e:
+        nmc.Instance.qap(F, bad)
+    assert e.value.code == -1
+    big = F.copy()
+    big[0, 1] = big[1, 0] = 300
+    with pytest.raises(nmc.NmcError) as e:
+        nmc.Instance.qap(big, D)
+    assert e.value.code == -6
+    with pytest.raises(nmc.NmcError):
+        nmc.Instance.qap(np.zeros((1, 1)), np.zeros((1, 1)))
+
+
+@pytest.mark.parametrize("n,alpha,k,cap", [(200, "9.6", 4, 0), (300, "4.15", 3, 0), (1000, "9.8", 4, 64),
+                                           (5000, "9.9", 4, 1024), (5000, "9.9", 4, 0)])
+def test_order_equals_oracle_colouring(n, alpha, k, cap):
+    cp, lits = instances.gen_ksat(n, alpha, k, 20211126)
+    inst = _load(n, cp, lits, cap)
+    order, cptr = inst.order()
+    _, o_order, o_cptr = oracle.KSat(n, cp, lits).color(cap)
+    assert (order == o_order).all()
+    assert (cptr == o_cptr).all()
+    assert inst.info.n_colors == len(o_cptr) - 1
+    assert inst.info.max_degree == np.bincount(np.abs(lits) - 1, minlength=n).max()
+
+
+def test_footprints_scale():
+    cp, lits = instances.gen_ksat(1000, "9.6", 4, 1)
+    inst = _load(1000, cp, lits)
+    ib, r64 = inst.footprint(64)
+    _, r128 = inst.footprint(128)
+    assert ib > 1000 * 38 * 8   # chunk records dominate
+    assert r128 > r64 >= 2 * 16 * 1000
+    with pytest.raises(nmc.NmcError):
+        inst.footprint(0)
+
+
+def test_unbound_instance_rejects_replicas():
+    cp, lits = instances.gen_ksat(50, "9.6", 4, 1)
+    inst = _load(50, cp, lits)
+    h = ctypes.c_void_p()
+    rc = nmc.lib().nmc_replicas_create(inst._h, 4, 1, ctypes.c_void_p(256), 1 << 20, None, ctypes.byref(h))
+    assert rc == -4

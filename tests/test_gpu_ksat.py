@@ -1,0 +1,148 @@
+"""GPU k-SAT path vs the CPU oracle: bit-exact states, energies, best
+energies, first-hit sweeps, best-state snapshots, magnetization counts and
+backbone classes."""
+import numpy as np
+import pytest
+
+from gpu_util import KsatPair, say
+from paper_2111_13628_amd import instances, nmc
+
+pytestmark = pytest.mark.gpu
+
+SEED = instances.DEFAULT_SEED
+
+
+def reanneal_profile(S, beta_hot=0.5, beta_end=4.0):
+    cold = np.full(S, beta_end)
+    hot = instances.linear_schedule(beta_hot, beta_end, S)
+    return instances.profile_schedule(cold, hot)
+
+
+def test_plain_sa_n200_r64_1000_sweeps():
+    """Plain simulated annealing: random 4-SAT N=200, M=1920, 64 replicas,
+    1000 sweeps with beta 0.1 -> 4.0."""
+    say("case: plain SA N=200 R=64 S=1000")
+    cp, lits = instances.gen_ksat(200, "9.6", 4, SEED)
+    p = KsatPair(200, cp, lits, 64, SEED)
+    p.anneal(instances.linear_schedule(0.1, 4.0, 1000)[None, :], target=3)
+    p.compare()
+
+
+@pytest.mark.parametrize("n,alpha,k,R,cap", [(300, "9.6", 4, 38, 0), (700, "4.15", 3, 21, 64),
+                                             (2100, "9.9", 4, 12, 128)])
+def test_nmc_rounds_ragged(n, alpha, k, R, cap):
+    """anneal -> backbone -> reanneal -> backbone -> reanneal, with replica
+    counts that leave a partial group and several tiles per colour class."""
+    say(f"case: nmc rounds n={n} k={k} R={R} cap={cap}")
+    cp, lits = instances.gen_ksat(n, alpha, k, SEED + n)
+    p = KsatPair(n, cp, lits, R, SEED + 1, cap=cap)
+    p.anneal(instances.linear_schedule(0.1, 4.0, 60)[None, :], target=2)
+    p.compare()
+    for rnd in range(2):
+        cls = p.backbone(9, 10, expand=True)
+        say(f"  round {rnd}: hot = {int(cls.sum())}")
+        p.anneal(reanneal_profile(25), profile="backbone", class_of=cls, target=1)
+        p.compare()
+
+
+def test_host_profile_three_classes():
+    say("case: host profile, 3 classes")
+    n = 900
+    cp, lits = instances.gen_ksat(n, "9.6", 4, 5)
+    p = KsatPair(n, cp, lits, 16, 77)
+    rng = np.random.Generator(np.random.PCG64(1))
+    cls = rng.integers(0, 3, n).astype(np.uint8)
+    beta = np.stack([instances.linear_schedule(0.1, 4.0, 30), np.full(30, 0.7), np.full(30, 9.0)])
+    p.anneal(beta, class_of=cls, target=0)
+    p.compare()
+
+
+def test_threshold_without_expansion_and_other_ratio():
+    n = 1200
+    cp, lits = instances.gen_ksat(n, "9.9", 4, 8)
+    p = KsatPair(n, cp, lits, 40, 3)
+    p.anneal(instances.linear_schedule(0.5, 5.0, 80)[None, :])
+    p.backbone(4, 5, expand=False)
+    p.backbone(1, 1, expand=True)
+    p.backbone(9, 10, expand=True)
+
+
+def test_chunked_calls_equal_one_call_and_block_shapes():
+    say("case: chunking and block shapes")
+    n = 1500
+    cp, lits = instances.gen_ksat(n, "9.9", 4, 12)
+    beta = instances.linear_schedule(0.1, 4.0, 48)[None, :]
+    ref = KsatPair(n, cp, lits, 24, 9)
+    ref.anneal(beta, target=5)
+    ref.compare()
+    for bt in (64, 256, 512):
+        inst = nmc.Instance.ksat(n, cp, lits).bind()
+        rep = nmc.Replicas(inst, 24, 9)
+        rep.set_tuning(bt)
+        for s in range(0, 48, 7):
+            rep.anneal(beta[:, s:s + 7], target=5)
+        assert (rep.get_state() == ref.orep.x).all(), bt
+        be = rep.best_energy()
+        assert (be["best_per_replica"] == ref.orep.best).all()
+        assert (be["first_hit"] == ref.orep.first_hit).all()
+
+
+def test_edge_cases():
+    say("case: edge cases")
+    # one variable, no clauses: every move has dE = 0 and is taken
+    p = KsatPair(1, np.array([0], np.int32), np.zeros(0, np.int32), 5, 1)
+    p.anneal(np.full((1, 3), 1.0))
+    p.compare()
+    assert (p.orep.x == (p.orep.x * 0 + (p.oinst.init(5, 1) ^ 1))).all()
+    # unit clauses and mixed clause lengths, one replica
+    cp = np.array([0, 1, 3, 6, 10, 11], np.int32)
+    lits = np.array([1, -1, 2, 3, -4, 5, -2, 4, -5, 6, -6], np.int32)
+    p = KsatPair(6, cp, lits, 1, 4)
+    p.anneal(instances.linear_schedule(0.1, 3.0, 20)[None, :], target=1)
+    p.compare()
+    # zero-sweep call records a hit at the call's start when the target is easy
+    cp2, lits2 = instances.gen_ksat(100, "9.6", 4, 2)
+    p = KsatPair(100, cp2, lits2, 7, 2)
+    p.anneal(np.zeros((1, 0)), target=10**6)
+    p.compare()
+    assert (p.orep.first_hit == 0).all()
+    # beta = 0 flips everything (all-accept table), huge beta never rises
+    p = KsatPair(100, cp2, lits2, 9, 3)
+    p.anneal(np.zeros((1, 2)))
+    p.anneal(np.full((1, 5), 60.0))
+    p.compare()
+
+
+def test_set_state_resume_matches_continuation():
+    n = 800
+    cp, lits = instances.gen_ksat(n, "9.9", 4, 4)
+    beta = instances.linear_schedule(0.1, 4.0, 40)[None, :]
+    a = KsatPair(n, cp, lits, 20, 6)
+    a.anneal(beta[:, :20])
+    x = a.rep.get_state()
+    a.anneal(beta[:, 20:])
+    inst = nmc.Instance.ksat(n, cp, lits).bind()
+    b = nmc.Replicas(inst, 20, 6)
+    b.set_state(x, 20)
+    assert (b.best_energy()["energy"] == b.recount()).all()
+    b.anneal(beta[:, 20:])
+    assert (b.get_state() == a.orep.x).all()
+    assert (b.best_energy()["energy"] == a.orep.energy).all()
+
+
+def test_full_size_n50000_r1024_short_schedule():
+    """The benchmark's instance and launch configuration (N=50,000, M=495,000,
+    1024 replicas, colour-class cap 1024) on the first sweeps of the anneal,
+    the backbone estimate and the first reanneal sweep, bit-exact on every
+    replica."""
+    say("case: full size N=50000 R=1024 (2 anneal sweeps, backbone, 1 reanneal sweep)")
+    n = 50000
+    cp, lits = instances.gen_ksat(n, "9.9", 4, SEED)
+    p = KsatPair(n, cp, lits, 1024, SEED, cap=1024)
+    p.anneal(instances.linear_schedule(0.1, 4.0, 2000)[None, :2], target=0)
+    say("  anneal done")
+    p.compare(check_best_state=False)
+    cls = p.backbone(9, 10, expand=True)
+    say(f"  backbone hot = {int(cls.sum())}")
+    p.anneal(reanneal_profile(1000)[:, :1], profile="backbone", class_of=cls)
+    p.compare()

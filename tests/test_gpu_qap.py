@@ -1,0 +1,82 @@
+"""GPU QAP path vs the CPU oracle: bit-exact permutations, costs, best costs,
+first hits, best permutations, assignment frequencies and backbone classes."""
+import numpy as np
+import pytest
+
+from gpu_util import QapPair, say
+from paper_2111_13628_amd import instances
+
+pytestmark = pytest.mark.gpu
+
+SEED = instances.DEFAULT_SEED
+
+
+def beta_scale(F, D, seed=1, samples=2000):
+    """1 / median positive swap change on random assignments (schedule units)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = F.shape[0]
+    F = F.astype(np.int64)
+    D = D.astype(np.int64)
+    vals = []
+    for _ in range(samples):
+        p = rng.permutation(n)
+        a, b = rng.choice(n, 2, replace=False)
+        k = np.array([i for i in range(n) if i not in (a, b)])
+        d = 2 * int(((F[a, k] - F[b, k]) * (D[p[b], p[k]] - D[p[a], p[k]])).sum())
+        if d > 0:
+            vals.append(d)
+    return 1.0 / float(np.median(vals))
+
+
+def reanneal_profile(S, scale, beta_hot=0.5, beta_end=4.0):
+    return instances.profile_schedule(np.full(S, beta_end * scale),
+                                      instances.linear_schedule(beta_hot * scale, beta_end * scale, S))
+
+
+@pytest.mark.parametrize("n,R", [(12, 20), (37, 45), (64, 16)])
+def test_qap_nmc_rounds(n, R):
+    say(f"case: qap n={n} R={R}")
+    F, D = instances.gen_qap(n, SEED + n)
+    sc = beta_scale(F, D)
+    p = QapPair(F, D, R, SEED + 1)
+    p.anneal(instances.linear_schedule(0.1 * sc, 4.0 * sc, 20)[None, :], target=0)
+    p.compare()
+    cls = p.backbone(9, 10)
+    p.anneal(reanneal_profile(8, sc), profile="backbone", class_of=cls)
+    p.compare()
+    cls = p.backbone(1, 2)
+    p.anneal(reanneal_profile(5, sc), profile="backbone", class_of=cls, target=int(p.orep.best.min()))
+    p.compare()
+
+
+def test_qap_edges_and_host_profile():
+    say("case: qap edges")
+    for n in (2, 3):
+        F, D = instances.gen_qap(n, 3)
+        p = QapPair(F, D, 6, 2)
+        p.anneal(np.full((1, 4), 0.01))
+        p.compare()
+    F, D = instances.gen_qap(20, 4)
+    sc = beta_scale(F, D)
+    p = QapPair(F, D, 9, 5)
+    cls = (np.arange(20) % 3).astype(np.uint8)
+    beta = np.stack([np.full(6, 3.0 * sc), np.full(6, 0.3 * sc), np.zeros(6)])
+    p.anneal(beta, class_of=cls)
+    p.compare()
+    p.anneal(np.zeros((1, 0)), target=10**12)
+    p.compare()
+
+
+def test_qap_full_size_n100_r4096_short_schedule():
+    """The QAP benchmark's size: n = 100, 4096 replicas, on the first anneal
+    sweeps, the frequency backbone and the first reanneal sweep."""
+    say("case: qap full size n=100 R=4096")
+    F, D = instances.gen_qap(100, SEED)
+    sc = beta_scale(F, D)
+    p = QapPair(F, D, 4096, SEED)
+    p.anneal(instances.linear_schedule(0.1 * sc, 4.0 * sc, 5000)[None, :2])
+    say("  anneal done")
+    p.compare()
+    cls = p.backbone(9, 10)
+    p.anneal(reanneal_profile(1000, sc)[:, :1], profile="backbone", class_of=cls)
+    p.compare()
