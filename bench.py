@@ -34,6 +34,7 @@ N, ALPHA, K, R = 50000, "9.9", 4, 1024
 S_ANNEAL, ROUNDS, S_RE = 2000, 3, 1000
 BETA0, BETA1, BETA_HOT = 0.1, 4.0, 0.5
 CLASS_CAP = 1024
+BLOCK_THREADS = 0
 # VALU lane-operations the sweep kernel issues per (variable, clause slot) for
 # its 4 replicas, and per variable for the acceptance step; see the design doc.
 OPS_PER_SLOT = 10.0
@@ -47,9 +48,10 @@ def reanneal_profile(S):
 
 def run_path(inst, seed, target, nmc, stream=None, profile=False):
     rep = nmc.Replicas(inst, R, seed, stream)
+    if BLOCK_THREADS:
+        rep.set_tuning(BLOCK_THREADS)
     rep.set_profiling(profile)
     rep.anneal(instances.linear_schedule(BETA0, BETA1, S_ANNEAL)[None, :], target=target, stream=stream)
-    hot = []
     for _ in range(ROUNDS):
         rep.estimate_backbone_device(9, 10, True, stream=stream)
         rep.reanneal(reanneal_profile(S_RE), "backbone", target=target, stream=stream)
@@ -76,6 +78,7 @@ def cpu_baseline(cp, lits, seed):
 
 
 def main():
+    global BLOCK_THREADS, CLASS_CAP
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
@@ -83,6 +86,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ttt", action="store_true")
     ap.add_argument("--block-threads", type=int, default=0)
+    ap.add_argument("--class-cap", type=int, default=CLASS_CAP)
+    ap.add_argument("--sweeps-only", type=int, default=0,
+                    help="only time one homogeneous anneal of this many sweeps (for counter profiles) and exit")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain elementwise copy of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the replica-parallel path "
@@ -93,12 +101,33 @@ def main():
 
     from paper_2111_13628_amd import nmc
 
+    BLOCK_THREADS = args.block_threads
+    CLASS_CAP = args.class_cap
+
     torch.cuda.set_device(0)
+    if args.copy_probe_mib:
+        # one read + one write of a known byte count, to scale HBM byte counters
+        a = torch.ones(args.copy_probe_mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": a.numel() * 4, "copy_probe_bytes_written": b.numel() * 4}))
+        return
     stream = torch.cuda.current_stream()
     seed = instances.DEFAULT_SEED
     cp, lits = instances.gen_ksat(N, ALPHA, K, seed)
     inst = nmc.Instance.ksat(N, cp, lits, CLASS_CAP).bind()
     M = inst.info.n_clauses
+    if args.sweeps_only:
+        rep = nmc.Replicas(inst, R, seed)
+        if BLOCK_THREADS:
+            rep.set_tuning(BLOCK_THREADS)
+        rep.set_profiling(True)
+        rep.anneal(instances.linear_schedule(BETA0, BETA1, S_ANNEAL)[None, :args.sweeps_only])
+        kt = rep.kernel_time()
+        print(json.dumps({"sweeps": args.sweeps_only, "kernel_ms": kt["ms"],
+                          "attempts_per_s": kt["attempts"] / (kt["ms"] / 1000.0)}))
+        return
     attempts = float(R) * N * (S_ANNEAL + ROUNDS * S_RE)
 
     for w in range(args.warmup):

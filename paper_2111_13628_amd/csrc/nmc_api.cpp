@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -145,6 +146,75 @@ std::vector<int32_t> greedy_colors(int32_t n, const std::vector<int32_t> &vptr, 
     return color;
 }
 
+
+// LDS bank-aware placement of one chunk's clause records into slots.  In a
+// slot, every lane issues three byte gathers (its record's three addresses)
+// as three wave-wide LDS reads.  gfx950 serves such a read 32 lanes at a time
+// over 32 four-byte banks, so two lanes of one half-wave that hit different
+// dwords of one bank serialize.  A lane's records may be visited in any slot
+// order and a record's three addresses may be issued in any order without
+// changing any result (integer sums), so the records are placed greedily,
+// slot by slot, to keep each half-wave's addresses on distinct banks.
+struct ChunkRec {
+    uint32_t a[3];
+    uint32_t neg;
+};
+
+void schedule_chunk(std::vector<std::vector<ChunkRec>> &lanes, int32_t nslot, bool optimize,
+                    std::vector<ChunkRec> &out /* [nslot][64] */, const ChunkRec &dummy) {
+    static const int perms[6][3] = {{0, 1, 2}, {1, 2, 0}, {2, 0, 1}, {0, 2, 1}, {1, 0, 2}, {2, 1, 0}};
+    out.assign((size_t)nslot * kChunk, dummy);
+    if (!optimize) {
+        for (int l = 0; l < kChunk; ++l)
+            for (size_t s = 0; s < lanes[l].size(); ++s)
+                out[s * kChunk + l] = lanes[l][s];
+        return;
+    }
+    std::vector<int> order(kChunk);
+    for (int32_t s = 0; s < nslot; ++s) {
+        int32_t owner[3][2][32];
+        for (int j = 0; j < 3; ++j)
+            for (int h = 0; h < 2; ++h)
+                for (int b = 0; b < 32; ++b)
+                    owner[j][h][b] = -1;
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int x, int y) { return lanes[x].size() > lanes[y].size(); });
+        for (int l : order) {
+            std::vector<ChunkRec> &rem = lanes[l];
+            if (rem.empty())
+                continue;
+            const int h = l / 32;
+            int best_i = 0, best_p = 0, best_c = 1 << 30;
+            for (size_t i = 0; i < rem.size() && best_c > 0; ++i)
+                for (int p = 0; p < 6 && best_c > 0; ++p) {
+                    int c = 0;
+                    for (int j = 0; j < 3; ++j) {
+                        const int32_t d = (int32_t)(rem[i].a[perms[p][j]] >> 2);
+                        const int32_t o = owner[j][h][d & 31];
+                        c += (o >= 0 && o != d);
+                    }
+                    if (c < best_c) {
+                        best_c = c;
+                        best_i = (int)i;
+                        best_p = p;
+                    }
+                }
+            ChunkRec r = rem[best_i];
+            ChunkRec placed = r;
+            for (int j = 0; j < 3; ++j) {
+                placed.a[j] = r.a[perms[best_p][j]];
+                const int32_t d = (int32_t)(placed.a[j] >> 2);
+                if (owner[j][h][d & 31] < 0)
+                    owner[j][h][d & 31] = d;
+            }
+            out[(size_t)s * kChunk + l] = placed;
+            rem[best_i] = rem.back();
+            rem.pop_back();
+        }
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -241,6 +311,8 @@ int nmc_ksat_load(int32_t n_vars, int32_t n_clauses, const int32_t *clause_ptr, 
         auto lit_addr = [&](int32_t l) -> uint32_t {
             return l > 0 ? (uint32_t)(l - 1) : (uint32_t)(n + (-l - 1));
         };
+        const char *sched_env = std::getenv("NMC_KSAT_BANK_SCHEDULE");
+        const bool bank_schedule = !(sched_env && sched_env[0] == '0');
         std::vector<int32_t> chunk_var, color_chunk(ncol + 1, 0);
         std::vector<int2> chunk_info;
         std::vector<uint64_t> rec;
@@ -255,33 +327,42 @@ int nmc_ksat_load(int32_t n_vars, int32_t n_clauses, const int32_t *clause_ptr, 
                 int32_t nslot = 0;
                 for (size_t i = b; i < e; ++i)
                     nslot = std::max(nslot, vptr[vs[i] + 1] - vptr[vs[i]]);
+                nslot = std::max<int32_t>(kSlotUnroll, (int32_t)align_up(nslot, kSlotUnroll));  // padding slots are inert
                 chunk_info.push_back(make_int2(slot_rows, nslot));
+                std::vector<std::vector<ChunkRec>> lanes(kChunk);
+                int32_t n1[kChunk] = {0};
+                for (size_t i = b; i < e; ++i) {
+                    const int lane = (int)(i - b);
+                    const int32_t v = vs[i];
+                    for (int32_t q = vptr[v]; q < vptr[v + 1]; ++q) {
+                        const int32_t a = vcl[q], own = vpos[q];
+                        ChunkRec r{{ZERO, ZERO, ZERO}, lits[own] < 0 ? 1u : 0u};
+                        int k = 0;
+                        for (int32_t p = clause_ptr[a]; p < clause_ptr[a + 1]; ++p)
+                            if (p != own)
+                                r.a[k++] = lit_addr(lits[p]);
+                        n1[lane] += (int32_t)r.neg;
+                        lanes[lane].push_back(r);
+                    }
+                }
+                std::vector<ChunkRec> placed;
+                schedule_chunk(lanes, nslot, bank_schedule, placed, ChunkRec{{ONES, ZERO, ZERO}, 0u});
                 const size_t base = rec.size();
                 rec.resize(base + (size_t)nslot * kChunk);
-                for (int32_t s = 0; s < nslot; ++s)
+                // slots are stored in pairs: [slot / 2][lane][slot % 2], so one
+                // 16-byte load gives a lane two consecutive slots
+                for (int32_t sl = 0; sl < nslot; ++sl)
                     for (int lane = 0; lane < kChunk; ++lane) {
-                        uint64_t r = (uint64_t)ONES | ((uint64_t)ZERO << kAddrBits) | ((uint64_t)ZERO << (2 * kAddrBits));
-                        const size_t i = b + lane;
-                        if (i < e) {
-                            const int32_t v = vs[i];
-                            if (s < vptr[v + 1] - vptr[v]) {
-                                const int32_t a = vcl[vptr[v] + s];
-                                const int32_t own = vpos[vptr[v] + s];
-                                uint32_t ad[3] = {ZERO, ZERO, ZERO};
-                                int k = 0;
-                                for (int32_t p = clause_ptr[a]; p < clause_ptr[a + 1]; ++p)
-                                    if (p != own)
-                                        ad[k++] = lit_addr(lits[p]);
-                                const uint64_t neg = lits[own] < 0 ? 1u : 0u;
-                                r = (uint64_t)ad[0] | ((uint64_t)ad[1] << kAddrBits) |
-                                    ((uint64_t)ad[2] << (2 * kAddrBits)) | (neg << (3 * kAddrBits));
-                            }
-                        }
-                        rec[base + (size_t)s * kChunk + lane] = r;
+                        const ChunkRec &r = placed[(size_t)sl * kChunk + lane];
+                        rec[base + (size_t)(sl / 2) * 2 * kChunk + (size_t)lane * 2 + (sl & 1)] =
+                            (uint64_t)r.a[0] | ((uint64_t)r.a[1] << kAddrBits) |
+                            ((uint64_t)r.a[2] << (2 * kAddrBits)) | ((uint64_t)r.neg << (3 * kAddrBits));
                     }
                 slot_rows += nslot;
+                // lane word: variable in bits 0..19 and its count of clauses
+                // holding it negated in bits 20..27; -1 = empty lane
                 for (int lane = 0; lane < kChunk; ++lane)
-                    chunk_var.push_back(b + lane < e ? vs[b + lane] : -1);
+                    chunk_var.push_back(b + lane < e ? (vs[b + lane] | (n1[lane] << 20)) : -1);
             }
             color_chunk[c + 1] = (int32_t)chunk_info.size();
         }

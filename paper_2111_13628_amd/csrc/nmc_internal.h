@@ -24,6 +24,7 @@ constexpr int kAddrBits = 17;
 constexpr uint32_t kAddrMask = (1u << kAddrBits) - 1;
 constexpr int kMaxClasses = 8;
 constexpr int kChunk = 64;  // variables per sweep chunk = lanes of one wave
+constexpr int kSlotUnroll = 4;  // clause slots per chunk are padded to a multiple of this
 
 // LDS available to one workgroup on gfx950.
 constexpr size_t kLdsBytes = 160 * 1024;
@@ -33,7 +34,7 @@ __host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a -
 // Device view of a bound k-SAT instance.
 struct KsatDev {
     const uint64_t *rec;         // chunk records, [slot-row][64 lanes]
-    const int32_t *chunk_var;    // [n_chunks][64] variable of each lane, -1 = empty
+    const int32_t *chunk_var;    // [n_chunks][64] lane word: variable | negated-count << 20, -1 = empty
     const int2 *chunk_info;      // [n_chunks] (first slot-row, slot count)
     const int32_t *color_chunk;  // [n_colors + 1] chunk range of each colour class
     const uint32_t *clause_addr; // [M][4] spin-table addresses of the clause's literals

@@ -41,6 +41,30 @@ __device__ __forceinline__ uint32_t spread4(uint32_t f) {
     return (f * 0x00204081u) & 0x01010101u;
 }
 
+// Compiler-only barrier: memory operations are not moved across it, so
+// prefetch loads stay where they are issued and their waits stay at first use.
+__device__ __forceinline__ void issue_fence() { __asm__ volatile("" ::: "memory"); }
+
+typedef __attribute__((address_space(3))) const uint8_t lds_cu8;
+typedef __attribute__((address_space(3))) uint8_t lds_u8;
+
+// Byte at LDS address a.  The sweep kernel declares no static LDS, so its
+// dynamic LDS block starts at address 0 and spin-table offsets are addresses.
+__device__ __forceinline__ uint32_t lds_load_u8(uint32_t a) { return *(lds_cu8 *)(uintptr_t)a; }
+__device__ __forceinline__ void lds_store_u8(uint32_t a, uint32_t v) { *(lds_u8 *)(uintptr_t)a = (uint8_t)v; }
+
+// One clause slot: r.x bits 0..16 and r.y bits 0..1 / 2..18 hold the spin-table
+// addresses of the clause's three other literals, r.y bit 19 whether the
+// lane's own literal in the clause is negated.  Adds spread(sat) xor sign.
+__device__ __forceinline__ uint32_t slot_step(uint32_t acc, uint2 r) {
+    const uint32_t a0 = r.x & kAddrMask;
+    const uint32_t a1 = __builtin_amdgcn_alignbit(r.y, r.x, kAddrBits) & kAddrMask;
+    const uint32_t a2 = __builtin_amdgcn_ubfe(r.y, 2 * kAddrBits - 32, kAddrBits);
+    const uint32_t sm = (uint32_t)__builtin_amdgcn_sbfe(r.y, 3 * kAddrBits - 32, 1);
+    const uint32_t sat = lds_load_u8(a0) | lds_load_u8(a1) | lds_load_u8(a2);
+    return (spread4(sat) ^ sm) + acc;
+}
+
 __global__ void ksat_init_kernel(KsatDev I, KsatRepDev R, uint32_t key0, uint32_t key1) {
     const size_t total = (size_t)R.n_groups * I.n;
     for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
@@ -116,7 +140,8 @@ __global__ void __launch_bounds__(1024) ksat_sweep_kernel(KsatDev I, KsatRepDev 
     const int n = I.n;
     const int g = blockIdx.x;
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
+    const int lane = tid & 63, nwaves = nthr >> 6;
+    const int wave_u = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int tab_words = C.n_classes * C.stride;
 
     uint8_t *xt = smem;
@@ -159,25 +184,56 @@ __global__ void __launch_bounds__(1024) ksat_sweep_kernel(KsatDev I, KsatRepDev 
         int d0 = 0, d1 = 0, d2 = 0, d3 = 0;
         for (int c = 0; c < I.n_colors; ++c) {
             const int h0 = I.color_chunk[c], h1 = I.color_chunk[c + 1];
-            for (int h = h0 + wave; h < h1; h += nwaves) {
+            // chunks of a class are sorted by slot count (descending); rounds
+            // alternate direction so heavy and light chunks pair up per wave
+            const int nch = h1 - h0;
+            for (int rnd = 0; rnd * nwaves < nch; ++rnd) {
+                const int idx = rnd * nwaves + ((rnd & 1) ? nwaves - 1 - wave_u : wave_u);
+                if (idx >= nch)
+                    continue;
+                const int h = h0 + idx;
                 const int2 info = I.chunk_info[h];
-                const int v = I.chunk_var[(size_t)h * kChunk + lane];
-                const uint64_t *rp = I.rec + (size_t)info.x * kChunk + lane;
-                uint32_t acc = 0x80808080u;
-#pragma unroll 4
-                for (int k = 0; k < info.y; ++k) {
-                    const uint64_t r = rp[(size_t)k * kChunk];
-                    const uint32_t a0 = (uint32_t)r & kAddrMask;
-                    const uint32_t a1 = (uint32_t)(r >> kAddrBits) & kAddrMask;
-                    const uint32_t a2 = (uint32_t)(r >> (2 * kAddrBits)) & kAddrMask;
-                    const uint32_t sm = 0u - (uint32_t)((r >> (3 * kAddrBits)) & 1u);
-                    const uint32_t sat = xt[a0] | xt[a1] | xt[a2];
-                    const uint32_t sp = spread4(~sat & 0xFu);
-                    acc += (sp ^ sm) - sm;
+                const int nslot = __builtin_amdgcn_readfirstlane(info.y);
+                const int lw = I.chunk_var[(size_t)h * kChunk + lane];
+                const int v = lw < 0 ? -1 : (lw & 0xFFFFF);
+                // the variable's class is needed after the slot loop; load it now
+                const int cl = (C.var_cls && v >= 0) ? (int)C.var_cls[v] : 0;
+                const uint4 *rp = reinterpret_cast<const uint4 *>(I.rec) +
+                                  (size_t)(__builtin_amdgcn_readfirstlane(info.x) / 2) * kChunk + lane;
+                // acc collects sum over slots of (spread(sat) xor signmask); the
+                // closed form below turns it into 128 + dE-part per byte lane.
+                // Slots come in 16-byte pairs; 8 slots of records are in flight
+                // while 4 are consumed (nslot is a multiple of 4, at least 4; the
+                // pair index is clamped so every load is in bounds).
+                uint32_t acc = 0;
+                const int lastp = nslot / 2 - 1;
+                uint4 q0 = rp[0], q1 = rp[(size_t)min(1, lastp) * kChunk];
+                uint4 q2 = rp[(size_t)min(2, lastp) * kChunk], q3 = rp[(size_t)min(3, lastp) * kChunk];
+                issue_fence();
+                for (int k = 0;; k += 2 * kSlotUnroll) {
+                    acc = slot_step(acc, make_uint2(q0.x, q0.y));
+                    acc = slot_step(acc, make_uint2(q0.z, q0.w));
+                    acc = slot_step(acc, make_uint2(q1.x, q1.y));
+                    acc = slot_step(acc, make_uint2(q1.z, q1.w));
+                    if (k + kSlotUnroll >= nslot)
+                        break;
+                    q0 = rp[(size_t)min(k / 2 + 4, lastp) * kChunk];
+                    q1 = rp[(size_t)min(k / 2 + 5, lastp) * kChunk];
+                    issue_fence();
+                    acc = slot_step(acc, make_uint2(q2.x, q2.y));
+                    acc = slot_step(acc, make_uint2(q2.z, q2.w));
+                    acc = slot_step(acc, make_uint2(q3.x, q3.y));
+                    acc = slot_step(acc, make_uint2(q3.z, q3.w));
+                    if (k + 2 * kSlotUnroll >= nslot)
+                        break;
+                    q2 = rp[(size_t)min(k / 2 + 6, lastp) * kChunk];
+                    q3 = rp[(size_t)min(k / 2 + 7, lastp) * kChunk];
+                    issue_fence();
                 }
+                const uint32_t nneg = lw < 0 ? 0u : ((uint32_t)lw >> 20) & 0xFFu;
+                acc = 0x80808080u + ((uint32_t)nslot - 2u * nneg) * 0x01010101u - nneg - acc;
                 if (v >= 0) {
-                    const uint32_t xi = xt[v];
-                    const int cl = C.var_cls ? (int)C.var_cls[v] : 0;
+                    const uint32_t xi = lds_load_u8((uint32_t)v);
                     const uint32_t *T = tl + cl * C.stride;
                     int de[kGroup];
                     uint32_t thr[kGroup];
@@ -186,32 +242,26 @@ __global__ void __launch_bounds__(1024) ksat_sweep_kernel(KsatDev I, KsatRepDev 
                     for (int j = 0; j < kGroup; ++j) {
                         const int S = (int)((acc >> (8 * j)) & 0xFFu) - 128;
                         de[j] = ((xi >> j) & 1u) ? S : -S;
-                        thr[j] = 0;
-                        if ((amask >> j) & 1u) {
-                            if (de[j] <= 0) {
-                                flip |= 1u << j;
-                            } else {
-                                thr[j] = T[de[j]];
-                                if (thr[j])
-                                    need |= 1u << j;
-                            }
-                        }
+                        thr[j] = T[max(de[j], 0)];
+                        const uint32_t on = (amask >> j) & 1u;
+                        flip |= (on & (uint32_t)(de[j] <= 0)) << j;
+                        need |= (on & (uint32_t)(de[j] > 0) & (uint32_t)(thr[j] != 0)) << j;
                     }
                     if (need) {
                         const uint4 u = philox4x32_10((uint32_t)v, t, (uint32_t)g, kStreamKsatSweep, C.key0, C.key1);
-                        if ((need & 1u) && u.x < thr[0]) flip |= 1u;
-                        if ((need & 2u) && u.y < thr[1]) flip |= 2u;
-                        if ((need & 4u) && u.z < thr[2]) flip |= 4u;
-                        if ((need & 8u) && u.w < thr[3]) flip |= 8u;
+                        flip |= ((need & 1u) && u.x < thr[0]) ? 1u : 0u;
+                        flip |= ((need & 2u) && u.y < thr[1]) ? 2u : 0u;
+                        flip |= ((need & 4u) && u.z < thr[2]) ? 4u : 0u;
+                        flip |= ((need & 8u) && u.w < thr[3]) ? 8u : 0u;
                     }
                     if (flip) {
                         const uint32_t nx = xi ^ flip;
-                        xt[v] = (uint8_t)nx;
-                        xt[n + v] = (uint8_t)(~nx & amask);
-                        if (flip & 1u) d0 += de[0];
-                        if (flip & 2u) d1 += de[1];
-                        if (flip & 4u) d2 += de[2];
-                        if (flip & 8u) d3 += de[3];
+                        lds_store_u8((uint32_t)v, nx);
+                        lds_store_u8((uint32_t)(n + v), ~nx & amask);
+                        d0 += (flip & 1u) ? de[0] : 0;
+                        d1 += (flip & 2u) ? de[1] : 0;
+                        d2 += (flip & 4u) ? de[2] : 0;
+                        d3 += (flip & 8u) ? de[3] : 0;
                     }
                 }
             }

@@ -14,10 +14,10 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
                                                uint32_t k1) {
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        const uint32_t lo0 = c0 * 0xD2511F53u;
-        const uint32_t hi0 = __umulhi(c0, 0xD2511F53u);
-        const uint32_t lo1 = c2 * 0xCD9E8D57u;
-        const uint32_t hi1 = __umulhi(c2, 0xCD9E8D57u);
+        const uint64_t p0 = (uint64_t)c0 * 0xD2511F53u;  // one 32x32->64 multiply each
+        const uint64_t p1 = (uint64_t)c2 * 0xCD9E8D57u;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         c0 = hi1 ^ c1 ^ k0;
         c1 = lo1;
         c2 = hi0 ^ c3 ^ k1;

@@ -146,3 +146,21 @@ def test_full_size_n50000_r1024_short_schedule():
     say(f"  backbone hot = {int(cls.sum())}")
     p.anneal(reanneal_profile(1000)[:, :1], profile="backbone", class_of=cls)
     p.compare()
+
+
+def test_layout_schedule_does_not_change_results(monkeypatch):
+    """The bank-aware record placement only reorders additions: states and
+    energies are identical with and without it."""
+    n = 3000
+    cp, lits = instances.gen_ksat(n, "9.9", 4, 31)
+    beta = instances.linear_schedule(0.1, 4.0, 30)[None, :]
+    out = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("NMC_KSAT_BANK_SCHEDULE", flag)
+        inst = nmc.Instance.ksat(n, cp, lits, 256).bind()
+        rep = nmc.Replicas(inst, 36, 5)
+        rep.anneal(beta, target=3)
+        out.append((rep.get_state(), rep.best_energy()))
+    assert (out[0][0] == out[1][0]).all()
+    for key in ("energy", "best_per_replica", "first_hit"):
+        assert (out[0][1][key] == out[1][1][key]).all()
