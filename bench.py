@@ -37,8 +37,8 @@ CLASS_CAP = 1024
 BLOCK_THREADS = 0
 # VALU lane-operations the sweep kernel issues per (variable, clause slot) for
 # its 4 replicas, and per variable for the acceptance step; see the design doc.
-OPS_PER_SLOT = 10.0
-OPS_PER_VAR = 48.0
+OPS_PER_SLOT = 9.0
+OPS_PER_VAR = 62.0
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock
 
 

@@ -247,6 +247,67 @@ int nmc_set_tuning(nmc_replicas *rep, int32_t block_threads);
 int nmc_set_profiling(nmc_replicas *rep, int32_t enable);
 int nmc_kernel_time(nmc_replicas *rep, double *ms, int64_t *launches, double *attempts, int32_t reset);
 
+
+/* ---------------------------------------------------------------------------
+ * batched launches (many replica sets of different instances at once)
+ * ------------------------------------------------------------------------- */
+
+typedef struct nmc_batch nmc_batch;
+
+/* One anneal -> [backbone -> reanneal] x rounds plan (Algorithm 1's loop of
+ * inhomogeneous exploration and homogeneous unlearning, with the backbone
+ * re-estimated before every round).
+ *   anneal_beta[s]                 s < anneal_sweeps, one class
+ *   reanneal_beta[c * S + s]       c = 0 cold, 1 hot; S = reanneal_sweeps
+ *   thr_num / thr_den, expand      as nmc_estimate_backbone */
+typedef struct nmc_plan {
+    const double *anneal_beta;
+    int32_t anneal_sweeps;
+    int32_t rounds;
+    const double *reanneal_beta;
+    int32_t reanneal_sweeps;
+    int32_t thr_num, thr_den, expand;
+} nmc_plan;
+
+/* Group n_sets distinct replica sets (k-SAT and QAP may be mixed) for batched
+ * calls.  The handle keeps the pointers; the sets must outlive it.  Results of
+ * every set are identical to running its calls alone (same seeds, same sweep
+ * counters): nothing a set computes depends on the other sets. */
+int nmc_batch_create(nmc_replicas *const *sets, int32_t n_sets, nmc_batch **out);
+void nmc_batch_free(nmc_batch *batch);
+
+/* k-SAT sweep workgroup size for this batch's launches (64..1024, multiple of
+ * 64; 0 = choose from the instances' colour-class sizes).  Results never
+ * depend on it. */
+int nmc_batch_set_tuning(nmc_batch *batch, int32_t block_threads);
+
+/* Time each candidate workgroup size (64, 128, 256, 512, 1024) on probe_sweeps
+ * sweeps run on copies of the sets' states (the sets themselves do not move),
+ * keep the fastest for this batch and return it in *chosen. */
+int nmc_batch_tune(nmc_batch *batch, int32_t probe_sweeps, int32_t *chosen, void *stream);
+
+/* nmc_anneal for every set of the batch in one launch per kernel kind: one
+ * persistent grid walks all (set, replica group) items, largest first.
+ * profile: NMC_PROFILE_HOMOGENEOUS or NMC_PROFILE_BACKBONE (HOST is
+ * UNSUPPORTED here).  targets: n_sets entries or NULL (no target).
+ * Synchronizes the stream before returning. */
+int nmc_batch_anneal(nmc_batch *batch, const double *beta, int32_t n_classes, int32_t n_sweeps, int32_t profile,
+                     const int64_t *targets, void *stream);
+
+/* nmc_estimate_backbone for every set (classes stay on the device). */
+int nmc_batch_estimate_backbone(nmc_batch *batch, int32_t thr_num, int32_t thr_den, int32_t expand, void *stream);
+
+/* The whole plan for every set.  With use_graph != 0 the plan's kernels
+ * (anneal, then per round the backbone kernels and the reanneal) are captured
+ * into one HIP graph and launched on `stream` as a unit.  Identical results
+ * either way.  Synchronizes the stream before returning. */
+int nmc_batch_run_plan(nmc_batch *batch, const nmc_plan *plan, const int64_t *targets, int32_t use_graph,
+                       void *stream);
+
+/* Kernel timing of batched sweeps, as nmc_set_profiling / nmc_kernel_time. */
+int nmc_batch_set_profiling(nmc_batch *batch, int32_t enable);
+int nmc_batch_kernel_time(nmc_batch *batch, double *ms, int64_t *launches, double *attempts, int32_t reset);
+
 #ifdef __cplusplus
 }
 #endif

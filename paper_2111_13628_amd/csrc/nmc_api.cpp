@@ -1070,3 +1070,691 @@ int nmc_kernel_time(nmc_replicas *P, double *ms, int64_t *launches, double *atte
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched launches (many replica sets, one grid per kernel kind)
+// ---------------------------------------------------------------------------
+
+struct nmc_batch {
+    std::vector<nmc_replicas *> sets;
+    int32_t block_threads = 0;  // k-SAT sweep workgroup size; 0 = heuristic
+    uint8_t *dev = nullptr;     // library-owned: job descriptors, items, tables
+    size_t cap = 0;
+    hipStream_t cap_stream = nullptr;  // stream used for graph capture
+    bool profiling = false;
+    double prof_ms = 0;
+    int64_t prof_launches = 0;
+    double prof_attempts = 0;
+};
+
+namespace {
+
+int device_cus() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                    hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
+
+struct Blob {
+    std::vector<uint8_t> host;
+    size_t take(size_t bytes) {
+        const size_t off = align_up(host.size(), 256);
+        host.resize(off + bytes);
+        return off;
+    }
+};
+
+struct PhaseSpec {
+    const double *beta;
+    int32_t n_classes, n_sweeps, profile;
+};
+
+struct BuiltPhase {
+    int32_t n_sweeps = 0;
+    size_t off_kjobs = 0, off_kitems = 0, off_qjobs = 0, off_qitems = 0;
+    int nk_items = 0, nq_items = 0;
+    size_t lds_k = 0, lds_q = 0;
+    int grid_k = 0, grid_q = 0, block_k = 0;
+    double attempts = 0;
+};
+
+struct BuiltBackbone {
+    size_t off_kjobs = 0, off_kitems = 0, off_qjobs = 0, off_qitems = 0;
+    int nk_items = 0, nq_items = 0;
+};
+
+int heuristic_block(const std::vector<nmc_replicas *> &ks) {
+    // enough waves for the typical chunk count of one colour class
+    std::vector<double> chunks;
+    for (auto *P : ks)
+        chunks.push_back((double)P->inst->n_chunks / std::max(1, P->inst->n_colors));
+    if (chunks.empty())
+        return 256;
+    std::nth_element(chunks.begin(), chunks.begin() + chunks.size() / 2, chunks.end());
+    const double c = chunks[chunks.size() / 2];
+    int b = 64;
+    while (b < 1024 && b / 64 < c)
+        b *= 2;
+    return b;
+}
+
+// Lay out, in one host blob, everything the batched kernels of the given
+// phases need (job descriptors whose device pointers point into the blob's
+// future device copy at dev_base).  Returns NMC_OK or an error code.
+int build_batch(nmc_batch *B, const std::vector<PhaseSpec> &phases, bool with_backbone, const int64_t *targets,
+                uint8_t *dev_base, Blob &blob, std::vector<BuiltPhase> &built, BuiltBackbone &bb,
+                std::vector<nmc_replicas *> *override_sets = nullptr) {
+    const std::vector<nmc_replicas *> &sets = override_sets ? *override_sets : B->sets;
+    std::vector<int> kidx, qidx;
+    for (size_t i = 0; i < sets.size(); ++i)
+        (sets[i]->inst->kind == NMC_KIND_KSAT ? kidx : qidx).push_back((int)i);
+    int32_t stride_k = 1, ha = 1;
+    for (int i : kidx)
+        stride_k = std::max(stride_k, sets[i]->inst->dmax + 1);
+    for (int i : qidx)
+        ha = std::max(ha, sets[i]->inst->qap_ha);
+    const int32_t stride_q = ha + (1 << kQapLowBits);
+    std::vector<nmc_replicas *> ks;
+    for (int i : kidx)
+        ks.push_back(sets[i]);
+    const int block_k = B->block_threads > 0 ? B->block_threads : heuristic_block(ks);
+    const int cus = device_cus();
+    uint32_t offset_sweeps = 0;
+    for (const PhaseSpec &ph : phases) {
+        BuiltPhase bp;
+        bp.n_sweeps = ph.n_sweeps;
+        bp.block_k = block_k;
+        // thresholds shared by the phase's jobs of one kind
+        size_t off_ktab = 0, off_qtab = 0;
+        if (!kidx.empty()) {
+            off_ktab = blob.take(std::max<size_t>((size_t)ph.n_sweeps * ph.n_classes * stride_k * 4, 4));
+            uint32_t *t = reinterpret_cast<uint32_t *>(blob.host.data() + off_ktab);
+            for (int32_t sw = 0; sw < ph.n_sweeps; ++sw)
+                for (int32_t c = 0; c < ph.n_classes; ++c) {
+                    uint32_t *row = t + ((size_t)sw * ph.n_classes + c) * stride_k;
+                    row[0] = 0xFFFFFFFFu;
+                    for (int32_t d = 1; d < stride_k; ++d)
+                        row[d] = threshold(ph.beta[(size_t)c * ph.n_sweeps + sw], d);
+                }
+        }
+        if (!qidx.empty()) {
+            off_qtab = blob.take(std::max<size_t>((size_t)ph.n_sweeps * ph.n_classes * stride_q * 4, 4));
+            for (int32_t sw = 0; sw < ph.n_sweeps; ++sw)
+                for (int32_t c = 0; c < ph.n_classes; ++c) {
+                    uint32_t *row = reinterpret_cast<uint32_t *>(blob.host.data() + off_qtab) +
+                                    ((size_t)sw * ph.n_classes + c) * stride_q;
+                    const double b = ph.beta[(size_t)c * ph.n_sweeps + sw];
+                    row[0] = 0xFFFFFFFFu;
+                    for (int32_t h = 1; h < ha; ++h)
+                        row[h] = threshold(b, (int64_t)h << kQapLowBits);
+                    row[ha] = 0xFFFFFFFFu;
+                    for (int32_t l = 1; l < (1 << kQapLowBits); ++l)
+                        row[ha + l] = threshold(b, l);
+                }
+        }
+        // k-SAT jobs and items
+        if (!kidx.empty()) {
+            bp.off_kjobs = blob.take(kidx.size() * sizeof(KsatJob));
+            std::vector<std::pair<double, int2>> items;
+            for (size_t j = 0; j < kidx.size(); ++j) {
+                nmc_replicas *P = sets[kidx[j]];
+                KsatJob J{};
+                J.I = P->inst->ksat_dev();
+                J.R = P->k;
+                J.C.tab = reinterpret_cast<const uint32_t *>(dev_base + off_ktab);
+                J.C.var_cls = ph.profile == NMC_PROFILE_BACKBONE ? P->k.cls : nullptr;
+                J.C.n_classes = ph.n_classes;
+                J.C.stride = stride_k;
+                J.C.n_sweeps = ph.n_sweeps;
+                J.C.t0 = P->sweeps_done + offset_sweeps;
+                const int64_t tg = targets ? targets[kidx[j]] : -1;
+                J.C.target = (int32_t)std::max<int64_t>(std::min<int64_t>(tg, INT32_MAX), INT32_MIN);
+                J.C.check_start = 1;
+                J.C.key0 = (uint32_t)P->seed;
+                J.C.key1 = (uint32_t)(P->seed >> 32);
+                std::memcpy(blob.host.data() + bp.off_kjobs + j * sizeof(KsatJob), &J, sizeof J);
+                const double cost = (double)P->inst->n * (P->inst->dmax + 1);
+                for (int g = 0; g < P->G; ++g)
+                    items.push_back({cost, make_int2((int)j, g)});
+                bp.lds_k = std::max(bp.lds_k, ksat_sweep_lds_bytes(P->inst->n, ph.n_classes, stride_k));
+                bp.attempts += (double)P->R * P->inst->n * ph.n_sweeps;
+            }
+            std::stable_sort(items.begin(), items.end(),
+                             [](const std::pair<double, int2> &a, const std::pair<double, int2> &b) { return a.first > b.first; });
+            bp.nk_items = (int)items.size();
+            bp.off_kitems = blob.take(items.size() * sizeof(int2));
+            for (size_t t = 0; t < items.size(); ++t)
+                std::memcpy(blob.host.data() + bp.off_kitems + t * sizeof(int2), &items[t].second, sizeof(int2));
+            if (bp.lds_k > kLdsBytes)
+                return fail(NMC_ERR_CAPACITY, "batched k-SAT sweep needs %zu bytes of LDS", bp.lds_k);
+            bp.grid_k = std::min(bp.nk_items, ksat_batch_occupancy(block_k, bp.lds_k) * cus);
+        }
+        if (!qidx.empty()) {
+            bp.off_qjobs = blob.take(qidx.size() * sizeof(QapJob));
+            std::vector<std::pair<double, int2>> items;
+            for (size_t j = 0; j < qidx.size(); ++j) {
+                nmc_replicas *P = sets[qidx[j]];
+                QapJob J{};
+                J.I = P->inst->qap_dev();
+                J.I.ha = ha;
+                J.R = P->q;
+                J.C.tab = reinterpret_cast<const uint32_t *>(dev_base + off_qtab);
+                J.C.fac_cls = ph.profile == NMC_PROFILE_BACKBONE ? P->q.cls : nullptr;
+                J.C.n_classes = ph.n_classes;
+                J.C.stride = stride_q;
+                J.C.n_sweeps = ph.n_sweeps;
+                J.C.t0 = P->sweeps_done + offset_sweeps;
+                J.C.target = targets ? targets[qidx[j]] : -1;
+                J.C.check_start = 1;
+                J.C.key0 = (uint32_t)P->seed;
+                J.C.key1 = (uint32_t)(P->seed >> 32);
+                std::memcpy(blob.host.data() + bp.off_qjobs + j * sizeof(QapJob), &J, sizeof J);
+                const double n = P->inst->n;
+                const int blocks = (P->R + kQapRepPerBlock - 1) / kQapRepPerBlock;
+                for (int b = 0; b < blocks; ++b)
+                    items.push_back({n * n * n, make_int2((int)j, b)});
+                bp.lds_q = std::max(bp.lds_q, qap_sweep_lds_bytes(P->inst->n, ph.n_classes, stride_q));
+                bp.attempts += (double)P->R * n * (n - 1) / 2.0 * ph.n_sweeps;
+            }
+            std::stable_sort(items.begin(), items.end(),
+                             [](const std::pair<double, int2> &a, const std::pair<double, int2> &b) { return a.first > b.first; });
+            bp.nq_items = (int)items.size();
+            bp.off_qitems = blob.take(items.size() * sizeof(int2));
+            for (size_t t = 0; t < items.size(); ++t)
+                std::memcpy(blob.host.data() + bp.off_qitems + t * sizeof(int2), &items[t].second, sizeof(int2));
+            if (bp.lds_q > kLdsBytes)
+                return fail(NMC_ERR_CAPACITY, "batched QAP sweep needs %zu bytes of LDS", bp.lds_q);
+            bp.grid_q = std::min(bp.nq_items, qap_batch_occupancy(bp.lds_q) * cus);
+        }
+        built.push_back(bp);
+        offset_sweeps += (uint32_t)ph.n_sweeps;
+    }
+    if (with_backbone) {
+        // descriptors without schedule fields; reuse of KsatRepDev/QapRepDev only
+        if (!kidx.empty()) {
+            bb.off_kjobs = blob.take(kidx.size() * sizeof(KsatJob));
+            std::vector<int2> items;
+            for (size_t j = 0; j < kidx.size(); ++j) {
+                nmc_replicas *P = sets[kidx[j]];
+                KsatJob J{};
+                J.I = P->inst->ksat_dev();
+                J.R = P->k;
+                std::memcpy(blob.host.data() + bb.off_kjobs + j * sizeof(KsatJob), &J, sizeof J);
+                for (int v0 = 0; v0 < P->inst->n; v0 += 256)
+                    items.push_back(make_int2((int)j, v0));
+            }
+            bb.nk_items = (int)items.size();
+            bb.off_kitems = blob.take(items.size() * sizeof(int2));
+            std::memcpy(blob.host.data() + bb.off_kitems, items.data(), items.size() * sizeof(int2));
+        }
+        if (!qidx.empty()) {
+            bb.off_qjobs = blob.take(qidx.size() * sizeof(QapJob));
+            std::vector<int2> items;
+            for (size_t j = 0; j < qidx.size(); ++j) {
+                nmc_replicas *P = sets[qidx[j]];
+                QapJob J{};
+                J.I = P->inst->qap_dev();
+                J.R = P->q;
+                std::memcpy(blob.host.data() + bb.off_qjobs + j * sizeof(QapJob), &J, sizeof J);
+                for (int f = 0; f < P->inst->n; ++f)
+                    items.push_back(make_int2((int)j, f));
+            }
+            bb.nq_items = (int)items.size();
+            bb.off_qitems = blob.take(items.size() * sizeof(int2));
+            std::memcpy(blob.host.data() + bb.off_qitems, items.data(), items.size() * sizeof(int2));
+        }
+    }
+    return NMC_OK;
+}
+
+int ensure_batch_mem(nmc_batch *B, size_t bytes) {
+    if (bytes <= B->cap)
+        return NMC_OK;
+    if (B->dev) {
+        HIP_OR_FAIL(hipDeviceSynchronize());
+        HIP_OR_FAIL(hipFree(B->dev));
+        B->dev = nullptr;
+        B->cap = 0;
+    }
+    const size_t cap = std::max<size_t>(align_up(bytes + bytes / 4, 1 << 20), 4 << 20);
+    HIP_OR_FAIL(hipMalloc(&B->dev, cap));
+    B->cap = cap;
+    return NMC_OK;
+}
+
+int enqueue_phase(nmc_batch *B, const BuiltPhase &bp, hipStream_t s) {
+    if (bp.nk_items)
+        HIP_OR_FAIL(ksat_launch_sweep_batch(reinterpret_cast<const KsatJob *>(B->dev + bp.off_kjobs),
+                                            reinterpret_cast<const int2 *>(B->dev + bp.off_kitems), bp.nk_items,
+                                            bp.lds_k, bp.block_k, bp.grid_k, s));
+    if (bp.nq_items)
+        HIP_OR_FAIL(qap_launch_sweep_batch(reinterpret_cast<const QapJob *>(B->dev + bp.off_qjobs),
+                                           reinterpret_cast<const int2 *>(B->dev + bp.off_qitems), bp.nq_items,
+                                           bp.lds_q, bp.grid_q, s));
+    return NMC_OK;
+}
+
+int enqueue_backbone(nmc_batch *B, const BuiltBackbone &bb, int thr_num, int thr_den, int expand, hipStream_t s) {
+    if (bb.nk_items)
+        HIP_OR_FAIL(ksat_launch_backbone_batch(reinterpret_cast<const KsatJob *>(B->dev + bb.off_kjobs),
+                                               reinterpret_cast<const int2 *>(B->dev + bb.off_kitems), bb.nk_items,
+                                               thr_num, thr_den, expand, s));
+    if (bb.nq_items)
+        HIP_OR_FAIL(qap_launch_backbone_batch(reinterpret_cast<const QapJob *>(B->dev + bb.off_qjobs),
+                                              reinterpret_cast<const int2 *>(B->dev + bb.off_qitems), bb.nq_items,
+                                              thr_num, thr_den, s));
+    return NMC_OK;
+}
+
+int validate_phase(nmc_batch *B, const PhaseSpec &ph, bool backbone_available) {
+    if (!ph.beta && ph.n_sweeps > 0)
+        return fail(NMC_ERR_INVALID, "beta is NULL");
+    if (ph.n_classes < 1 || ph.n_classes > kMaxClasses)
+        return fail(NMC_ERR_INVALID, "n_classes %d outside [1, %d]", ph.n_classes, kMaxClasses);
+    if (ph.n_sweeps < 0)
+        return fail(NMC_ERR_INVALID, "n_sweeps must be >= 0");
+    for (int64_t i = 0; i < (int64_t)ph.n_classes * ph.n_sweeps; ++i)
+        if (!std::isfinite(ph.beta[i]) || ph.beta[i] < 0)
+            return fail(NMC_ERR_INVALID, "beta[%lld] = %g is not finite and >= 0", (long long)i, ph.beta[i]);
+    if (ph.profile == NMC_PROFILE_BACKBONE) {
+        if (ph.n_classes < 2)
+            return fail(NMC_ERR_INVALID, "the backbone profile needs n_classes >= 2");
+        if (!backbone_available)
+            for (auto *P : B->sets)
+                if (!P->has_backbone)
+                    return fail(NMC_ERR_STATE, "a replica set has no backbone estimate yet");
+    } else if (ph.profile != NMC_PROFILE_HOMOGENEOUS) {
+        return fail(NMC_ERR_UNSUPPORTED, "batched calls take the homogeneous or backbone profile");
+    }
+    return NMC_OK;
+}
+
+int run_batch(nmc_batch *B, const std::vector<PhaseSpec> &phases, int rounds_with_backbone_before, int thr_num,
+              int thr_den, int expand, const int64_t *targets, bool use_graph, hipStream_t s) {
+    // phases[0] runs first; before each later phase, a backbone estimate
+    // (when rounds_with_backbone_before != 0)
+    for (size_t p = 0; p < phases.size(); ++p) {
+        const int rc = validate_phase(B, phases[p], p > 0 && rounds_with_backbone_before);
+        if (rc)
+            return rc;
+    }
+    uint64_t total = 0;
+    for (const auto &ph : phases)
+        total += (uint64_t)ph.n_sweeps;
+    for (auto *P : B->sets)
+        if ((uint64_t)P->sweeps_done + total > 0xFFFFFFFFull)
+            return fail(NMC_ERR_INVALID, "sweep counter would pass 2^32 - 1");
+    Blob blob;
+    std::vector<BuiltPhase> built;
+    BuiltBackbone bb;
+    // two passes: sizes first (device base unknown), then the real layout
+    int rc = build_batch(B, phases, rounds_with_backbone_before != 0, targets, nullptr, blob, built, bb);
+    if (rc)
+        return rc;
+    rc = ensure_batch_mem(B, blob.host.size());
+    if (rc)
+        return rc;
+    blob.host.clear();
+    built.clear();
+    bb = BuiltBackbone{};
+    rc = build_batch(B, phases, rounds_with_backbone_before != 0, targets, B->dev, blob, built, bb);
+    if (rc)
+        return rc;
+    HIP_OR_FAIL(hipMemcpyAsync(B->dev, blob.host.data(), blob.host.size(), hipMemcpyHostToDevice, s));
+    HIP_OR_FAIL(hipStreamSynchronize(s));
+
+    if (use_graph) {
+        if (!B->cap_stream)
+            HIP_OR_FAIL(hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking));
+        HIP_OR_FAIL(hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal));
+        int erc = NMC_OK;
+        for (size_t p = 0; p < built.size() && !erc; ++p) {
+            if (p > 0 && rounds_with_backbone_before)
+                erc = enqueue_backbone(B, bb, thr_num, thr_den, expand, B->cap_stream);
+            if (!erc)
+                erc = enqueue_phase(B, built[p], B->cap_stream);
+        }
+        hipGraph_t graph = nullptr;
+        const hipError_t ee = hipStreamEndCapture(B->cap_stream, &graph);
+        if (erc) {
+            if (graph)
+                (void)hipGraphDestroy(graph);
+            return erc;
+        }
+        if (ee != hipSuccess)
+            return fail(NMC_ERR_DEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(ee));
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess)
+            return fail(NMC_ERR_DEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(ei));
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (B->profiling) {
+            HIP_OR_FAIL(hipEventCreate(&e0));
+            HIP_OR_FAIL(hipEventCreate(&e1));
+            HIP_OR_FAIL(hipEventRecord(e0, s));
+        }
+        const hipError_t el = hipGraphLaunch(exec, s);
+        if (B->profiling)
+            HIP_OR_FAIL(hipEventRecord(e1, s));
+        const hipError_t es = hipStreamSynchronize(s);
+        (void)hipGraphExecDestroy(exec);
+        if (el != hipSuccess || es != hipSuccess)
+            return fail(NMC_ERR_DEVICE, "graph launch failed: %s", hipGetErrorString(el != hipSuccess ? el : es));
+        if (B->profiling) {
+            float ms = 0;
+            HIP_OR_FAIL(hipEventElapsedTime(&ms, e0, e1));
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            B->prof_ms += ms;
+            B->prof_launches += 1;
+            for (const auto &bp : built)
+                B->prof_attempts += bp.attempts;
+        }
+    } else {
+        for (size_t p = 0; p < built.size(); ++p) {
+            if (p > 0 && rounds_with_backbone_before) {
+                rc = enqueue_backbone(B, bb, thr_num, thr_den, expand, s);
+                if (rc)
+                    return rc;
+            }
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (B->profiling) {
+                HIP_OR_FAIL(hipEventCreate(&e0));
+                HIP_OR_FAIL(hipEventCreate(&e1));
+                HIP_OR_FAIL(hipEventRecord(e0, s));
+            }
+            rc = enqueue_phase(B, built[p], s);
+            if (rc)
+                return rc;
+            if (B->profiling) {
+                HIP_OR_FAIL(hipEventRecord(e1, s));
+                HIP_OR_FAIL(hipEventSynchronize(e1));
+                float ms = 0;
+                HIP_OR_FAIL(hipEventElapsedTime(&ms, e0, e1));
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                B->prof_ms += ms;
+                B->prof_launches += 1;
+                B->prof_attempts += built[p].attempts;
+            }
+        }
+        // the descriptor blob must outlive the kernels that read it
+        HIP_OR_FAIL(hipStreamSynchronize(s));
+    }
+    for (auto *P : B->sets) {
+        P->sweeps_done += (uint32_t)total;
+        if (rounds_with_backbone_before && phases.size() > 1)
+            P->has_backbone = true;
+    }
+    return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+int nmc_batch_create(nmc_replicas *const *sets, int32_t n_sets, nmc_batch **out) {
+    if (!out)
+        return fail(NMC_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!sets || n_sets < 1)
+        return fail(NMC_ERR_INVALID, "need at least one replica set");
+    try {
+        std::unique_ptr<nmc_batch> B(new nmc_batch());
+        for (int32_t i = 0; i < n_sets; ++i) {
+            if (!sets[i])
+                return fail(NMC_ERR_INVALID, "sets[%d] is NULL", i);
+            for (int32_t j = 0; j < i; ++j)
+                if (sets[j] == sets[i])
+                    return fail(NMC_ERR_INVALID, "replica set %d appears twice", i);
+            B->sets.push_back(sets[i]);
+        }
+        *out = B.release();
+        return ok();
+    } catch (const std::bad_alloc &) {
+        return fail(NMC_ERR_CAPACITY, "host allocation failed");
+    }
+}
+
+void nmc_batch_free(nmc_batch *B) {
+    if (!B)
+        return;
+    if (B->dev) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(B->dev);
+    }
+    if (B->cap_stream)
+        (void)hipStreamDestroy(B->cap_stream);
+    delete B;
+}
+
+int nmc_batch_set_tuning(nmc_batch *B, int32_t block_threads) {
+    if (!B)
+        return fail(NMC_ERR_INVALID, "NULL batch");
+    if (block_threads != 0 && (block_threads < 64 || block_threads > 1024 || block_threads % 64))
+        return fail(NMC_ERR_INVALID, "block_threads must be 0 or a multiple of 64 in [64, 1024]");
+    B->block_threads = block_threads;
+    return ok();
+}
+
+int nmc_batch_anneal(nmc_batch *B, const double *beta, int32_t n_classes, int32_t n_sweeps, int32_t profile,
+                     const int64_t *targets, void *stream) {
+    if (!B)
+        return fail(NMC_ERR_INVALID, "NULL batch");
+    try {
+        return run_batch(B, {PhaseSpec{beta, n_classes, n_sweeps, profile}}, 0, 0, 0, 0, targets, false,
+                         as_stream(stream));
+    } catch (const std::bad_alloc &) {
+        return fail(NMC_ERR_CAPACITY, "host allocation failed");
+    }
+}
+
+int nmc_batch_estimate_backbone(nmc_batch *B, int32_t thr_num, int32_t thr_den, int32_t expand, void *stream) {
+    if (!B)
+        return fail(NMC_ERR_INVALID, "NULL batch");
+    if (thr_den <= 0 || thr_num <= 0 || thr_num > thr_den)
+        return fail(NMC_ERR_INVALID, "need 0 < thr_num <= thr_den");
+    try {
+        Blob blob;
+        std::vector<BuiltPhase> built;
+        BuiltBackbone bb;
+        int rc = build_batch(B, {}, true, nullptr, nullptr, blob, built, bb);
+        if (rc)
+            return rc;
+        rc = ensure_batch_mem(B, blob.host.size());
+        if (rc)
+            return rc;
+        blob.host.clear();
+        bb = BuiltBackbone{};
+        rc = build_batch(B, {}, true, nullptr, B->dev, blob, built, bb);
+        if (rc)
+            return rc;
+        hipStream_t s = as_stream(stream);
+        HIP_OR_FAIL(hipMemcpyAsync(B->dev, blob.host.data(), blob.host.size(), hipMemcpyHostToDevice, s));
+        rc = enqueue_backbone(B, bb, thr_num, thr_den, expand ? 1 : 0, s);
+        if (rc)
+            return rc;
+        HIP_OR_FAIL(hipStreamSynchronize(s));
+        for (auto *P : B->sets)
+            P->has_backbone = true;
+        return ok();
+    } catch (const std::bad_alloc &) {
+        return fail(NMC_ERR_CAPACITY, "host allocation failed");
+    }
+}
+
+int nmc_batch_run_plan(nmc_batch *B, const nmc_plan *plan, const int64_t *targets, int32_t use_graph, void *stream) {
+    if (!B || !plan)
+        return fail(NMC_ERR_INVALID, "NULL argument");
+    if (plan->rounds < 0 || plan->anneal_sweeps < 0 || plan->reanneal_sweeps < 0)
+        return fail(NMC_ERR_INVALID, "negative plan field");
+    if (plan->rounds > 0 && (plan->thr_den <= 0 || plan->thr_num <= 0 || plan->thr_num > plan->thr_den))
+        return fail(NMC_ERR_INVALID, "need 0 < thr_num <= thr_den");
+    try {
+        std::vector<PhaseSpec> phases;
+        phases.push_back(PhaseSpec{plan->anneal_beta, 1, plan->anneal_sweeps, NMC_PROFILE_HOMOGENEOUS});
+        for (int32_t r = 0; r < plan->rounds; ++r)
+            phases.push_back(PhaseSpec{plan->reanneal_beta, 2, plan->reanneal_sweeps, NMC_PROFILE_BACKBONE});
+        return run_batch(B, phases, plan->rounds > 0 ? 1 : 0, plan->thr_num, plan->thr_den, plan->expand ? 1 : 0,
+                         targets, use_graph != 0, as_stream(stream));
+    } catch (const std::bad_alloc &) {
+        return fail(NMC_ERR_CAPACITY, "host allocation failed");
+    }
+}
+
+int nmc_batch_set_profiling(nmc_batch *B, int32_t enable) {
+    if (!B)
+        return fail(NMC_ERR_INVALID, "NULL batch");
+    B->profiling = enable != 0;
+    return ok();
+}
+
+int nmc_batch_kernel_time(nmc_batch *B, double *ms, int64_t *launches, double *attempts, int32_t reset) {
+    if (!B)
+        return fail(NMC_ERR_INVALID, "NULL batch");
+    if (ms)
+        *ms = B->prof_ms;
+    if (launches)
+        *launches = B->prof_launches;
+    if (attempts)
+        *attempts = B->prof_attempts;
+    if (reset) {
+        B->prof_ms = 0;
+        B->prof_launches = 0;
+        B->prof_attempts = 0;
+    }
+    return ok();
+}
+
+}  // extern "C"
+
+namespace {
+
+// A copy of a replica set's handle whose device pointers point into another
+// arena of the same layout (used to probe launch shapes without moving the
+// set itself).
+nmc_replicas rebased(const nmc_replicas *P, uint8_t *base) {
+    nmc_replicas C = *P;
+    auto mv = [&](auto *ptr) { return reinterpret_cast<decltype(ptr)>(base + (reinterpret_cast<uint8_t *>(ptr) - P->dev)); };
+    C.dev = base;
+    C.tab_dev = nullptr;
+    C.tab_cap = 0;
+    if (P->inst->kind == NMC_KIND_KSAT) {
+        C.k.xs = mv(P->k.xs);
+        C.k.best_xs = mv(P->k.best_xs);
+        C.k.energy = mv(P->k.energy);
+        C.k.best = mv(P->k.best);
+        C.k.first_hit = mv(P->k.first_hit);
+        C.k.cls = mv(P->k.cls);
+        C.k.counts = mv(P->k.counts);
+        C.k.frozen = mv(P->k.frozen);
+        C.k.tally = mv(P->k.tally);
+    } else {
+        C.q.perm = mv(P->q.perm);
+        C.q.best_perm = mv(P->q.best_perm);
+        C.q.cost = mv(P->q.cost);
+        C.q.best = mv(P->q.best);
+        C.q.first_hit = mv(P->q.first_hit);
+        C.q.cls = mv(P->q.cls);
+        C.q.freq = mv(P->q.freq);
+        C.q.tally = mv(P->q.tally);
+    }
+    C.scratch_energy = mv(P->scratch_energy);
+    return C;
+}
+
+}  // namespace
+
+extern "C" int nmc_batch_tune(nmc_batch *B, int32_t probe_sweeps, int32_t *chosen, void *stream) {
+    if (!B)
+        return fail(NMC_ERR_INVALID, "NULL batch");
+    if (probe_sweeps < 1 || probe_sweeps > 1000)
+        return fail(NMC_ERR_INVALID, "probe_sweeps must be in [1, 1000]");
+    try {
+        hipStream_t s = as_stream(stream);
+        std::vector<nmc_replicas *> ks;
+        for (auto *P : B->sets)
+            if (P->inst->kind == NMC_KIND_KSAT)
+                ks.push_back(P);
+        if (ks.empty()) {
+            if (chosen)
+                *chosen = 256;
+            return ok();
+        }
+        size_t total = 0;
+        std::vector<size_t> offs;
+        for (auto *P : ks) {
+            offs.push_back(total);
+            total += align_up(P->bytes, 256);
+        }
+        uint8_t *scratch = nullptr;
+        HIP_OR_FAIL(hipMalloc(&scratch, total));
+        std::vector<nmc_replicas> clones;
+        clones.reserve(ks.size());
+        for (size_t i = 0; i < ks.size(); ++i) {
+            HIP_OR_FAIL(hipMemcpyAsync(scratch + offs[i], ks[i]->dev, ks[i]->bytes, hipMemcpyDeviceToDevice, s));
+            clones.push_back(rebased(ks[i], scratch + offs[i]));
+        }
+        std::vector<nmc_replicas *> cptr;
+        for (auto &c : clones)
+            cptr.push_back(&c);
+        std::vector<double> beta((size_t)probe_sweeps, 1.0);
+        const int saved = B->block_threads;
+        int best_b = 0;
+        float best_ms = 0;
+        int rc = NMC_OK;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        HIP_OR_FAIL(hipEventCreate(&e0));
+        HIP_OR_FAIL(hipEventCreate(&e1));
+        for (int cand : {64, 128, 256, 512, 1024}) {
+            B->block_threads = cand;
+            Blob blob;
+            std::vector<BuiltPhase> built;
+            BuiltBackbone bb;
+            const std::vector<PhaseSpec> ph{PhaseSpec{beta.data(), 1, probe_sweeps, NMC_PROFILE_HOMOGENEOUS}};
+            rc = build_batch(B, ph, false, nullptr, nullptr, blob, built, bb, &cptr);
+            if (!rc)
+                rc = ensure_batch_mem(B, blob.host.size());
+            if (rc)
+                break;
+            blob.host.clear();
+            built.clear();
+            rc = build_batch(B, ph, false, nullptr, B->dev, blob, built, bb, &cptr);
+            if (rc)
+                break;
+            HIP_OR_FAIL(hipMemcpyAsync(B->dev, blob.host.data(), blob.host.size(), hipMemcpyHostToDevice, s));
+            HIP_OR_FAIL(hipEventRecord(e0, s));
+            rc = enqueue_phase(B, built[0], s);
+            if (rc)
+                break;
+            HIP_OR_FAIL(hipEventRecord(e1, s));
+            HIP_OR_FAIL(hipEventSynchronize(e1));
+            float ms = 0;
+            HIP_OR_FAIL(hipEventElapsedTime(&ms, e0, e1));
+            if (best_b == 0 || ms < best_ms) {
+                best_b = cand;
+                best_ms = ms;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(scratch);
+        if (rc) {
+            B->block_threads = saved;
+            return rc;
+        }
+        B->block_threads = best_b;
+        if (chosen)
+            *chosen = best_b;
+        return ok();
+    } catch (const std::bad_alloc &) {
+        return fail(NMC_ERR_CAPACITY, "host allocation failed");
+    }
+}

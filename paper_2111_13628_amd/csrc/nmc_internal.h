@@ -102,6 +102,19 @@ struct QapCall {
     uint32_t key0, key1;
 };
 
+// One replica set of a batched launch.
+struct KsatJob {
+    KsatDev I;
+    KsatRepDev R;
+    SweepCall C;
+};
+
+struct QapJob {
+    QapDev I;
+    QapRepDev R;
+    QapCall C;
+};
+
 // ---- launchers (nmc_ksat.hip) ----
 size_t ksat_sweep_lds_bytes(int n, int n_classes, int stride);
 hipError_t ksat_launch_init(const KsatDev &I, const KsatRepDev &R, uint32_t key0, uint32_t key1, hipStream_t s);
@@ -113,6 +126,11 @@ hipError_t ksat_launch_sweep(const KsatDev &I, const KsatRepDev &R, const SweepC
 hipError_t ksat_launch_backbone(const KsatDev &I, const KsatRepDev &R, int thr_num, int thr_den, int expand,
                                 hipStream_t s);
 hipError_t ksat_launch_tally(const KsatRepDev &R, hipStream_t s);
+hipError_t ksat_launch_sweep_batch(const KsatJob *jobs, const int2 *items, int n_items, size_t lds, int block_threads,
+                                   int grid, hipStream_t s);
+int ksat_batch_occupancy(int block_threads, size_t lds);
+hipError_t ksat_launch_backbone_batch(const KsatJob *jobs, const int2 *items, int n_items, int thr_num, int thr_den,
+                                      int expand, hipStream_t s);
 hipError_t ksat_launch_unpack(const uint8_t *xs, int n, int n_groups, int n_rep, uint8_t *x_rows, hipStream_t s);
 hipError_t ksat_launch_pack(const uint8_t *x_rows, int n, int n_groups, int n_rep, uint8_t *xs, hipStream_t s);
 
@@ -124,5 +142,11 @@ hipError_t qap_launch_reset_tallies(const QapRepDev &R, int n, hipStream_t s);
 hipError_t qap_launch_sweep(const QapDev &I, const QapRepDev &R, const QapCall &C, int block_threads, hipStream_t s);
 hipError_t qap_launch_backbone(const QapDev &I, const QapRepDev &R, int thr_num, int thr_den, hipStream_t s);
 hipError_t qap_launch_tally(const QapRepDev &R, hipStream_t s);
+hipError_t qap_launch_sweep_batch(const QapJob *jobs, const int2 *items, int n_items, size_t lds, int grid,
+                                  hipStream_t s);
+int qap_batch_occupancy(size_t lds);
+hipError_t qap_launch_backbone_batch(const QapJob *jobs, const int2 *items, int n_items, int thr_num, int thr_den,
+                                     hipStream_t s);
+constexpr int kQapRepPerBlock = 16;
 
 }  // namespace nmc

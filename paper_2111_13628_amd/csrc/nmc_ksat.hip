@@ -133,12 +133,11 @@ __global__ void ksat_reset_tallies_kernel(KsatRepDev R) {
     }
 }
 
-// The sweep kernel: n_sweeps full sweeps of every colour class for the 4
-// replicas of group blockIdx.x.
-__global__ void __launch_bounds__(1024) ksat_sweep_kernel(KsatDev I, KsatRepDev R, SweepCall C) {
-    extern __shared__ __align__(16) uint8_t smem[];
+// n_sweeps full sweeps of every colour class for the 4 replicas of group g,
+// by the whole workgroup, with smem = the workgroup's dynamic LDS block.
+__device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &R, const SweepCall &C, const int g,
+                                            uint8_t *smem) {
     const int n = I.n;
-    const int g = blockIdx.x;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & 63, nwaves = nthr >> 6;
     const int wave_u = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -311,6 +310,69 @@ __global__ void __launch_bounds__(1024) ksat_sweep_kernel(KsatDev I, KsatRepDev 
     }
 }
 
+// One replica group per workgroup (group = blockIdx.x).
+__global__ void __launch_bounds__(1024) ksat_sweep_kernel(KsatDev I, KsatRepDev R, SweepCall C) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    sweep_group(I, R, C, blockIdx.x, smem);
+}
+
+// Batched launch: many replica sets (jobs) of different instances in one
+// grid.  items[] lists (job, group) pairs in decreasing cost; workgroup b
+// runs items b, b + gridDim.x, ...  The dynamic LDS block is sized for the
+// largest job.
+__global__ void __launch_bounds__(1024) ksat_sweep_batch_kernel(const KsatJob *jobs, const int2 *items, int n_items) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 w = items[it];
+        const KsatJob &J = jobs[w.x];
+        sweep_group(J.I, J.R, J.C, w.y, smem);
+        __syncthreads();
+    }
+}
+
+// Backbone statistics for many jobs: items[] lists (job, first variable)
+// blocks of 256 variables.
+__global__ void ksat_magnetization_batch_kernel(const KsatJob *jobs, const int2 *items, int thr_num, int thr_den,
+                                                int expand) {
+    const int2 w = items[blockIdx.x];
+    const KsatJob &J = jobs[w.x];
+    const int v = w.y + threadIdx.x;
+    if (v >= J.I.n)
+        return;
+    int c = 0;
+    for (int g = 0; g < J.R.n_groups; ++g)
+        c += __popc((uint32_t)J.R.xs[(size_t)g * J.I.n + v]);
+    J.R.counts[v] = c;
+    long long dev = 2ll * c - J.R.n_rep;
+    if (dev < 0)
+        dev = -dev;
+    const uint8_t fz = (long long)thr_den * dev >= (long long)thr_num * J.R.n_rep;
+    J.R.frozen[v] = fz;
+    if (!expand)
+        J.R.cls[v] = fz;
+}
+
+__global__ void ksat_expand_batch_kernel(const KsatJob *jobs, const int2 *items) {
+    const int2 w = items[blockIdx.x];
+    const KsatJob &J = jobs[w.x];
+    const int v = w.y + threadIdx.x;
+    if (v >= J.I.n)
+        return;
+    uint8_t hot = J.R.frozen[v];
+    for (int q = J.I.var_ptr[v]; q < J.I.var_ptr[v + 1] && !hot; ++q) {
+        const uint4 ad = reinterpret_cast<const uint4 *>(J.I.clause_addr)[J.I.var_cl[q]];
+        const uint32_t a[4] = {ad.x, ad.y, ad.z, ad.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (a[j] < (uint32_t)(2 * J.I.n)) {
+                const uint32_t u = a[j] < (uint32_t)J.I.n ? a[j] : a[j] - J.I.n;
+                hot |= J.R.frozen[u];
+            }
+        }
+    }
+    J.R.cls[v] = hot;
+}
+
 // c_i = replicas with x_i = 1; frozen_i per the |magnetization| threshold.
 __global__ void ksat_magnetization_kernel(KsatDev I, KsatRepDev R, int thr_num, int thr_den, int expand) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
@@ -458,6 +520,39 @@ hipError_t ksat_launch_sweep(const KsatDev &I, const KsatRepDev &R, const SweepC
         attr = true;
     }
     hipLaunchKernelGGL(ksat_sweep_kernel, dim3(R.n_groups), dim3(block_threads), lds, s, I, R, C);
+    return hipGetLastError();
+}
+
+hipError_t ksat_launch_sweep_batch(const KsatJob *jobs, const int2 *items, int n_items, size_t lds, int block_threads,
+                                   int grid, hipStream_t s) {
+    static bool attr = false;
+    if (!attr) {
+        const hipError_t ea = hipFuncSetAttribute((const void *)ksat_sweep_batch_kernel,
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
+        if (ea != hipSuccess)
+            return ea;
+        attr = true;
+    }
+    hipLaunchKernelGGL(ksat_sweep_batch_kernel, dim3(grid), dim3(block_threads), lds, s, jobs, items, n_items);
+    return hipGetLastError();
+}
+
+int ksat_batch_occupancy(int block_threads, size_t lds) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)ksat_sweep_batch_kernel, block_threads, lds) !=
+        hipSuccess)
+        return 1;
+    return nb < 1 ? 1 : nb;
+}
+
+hipError_t ksat_launch_backbone_batch(const KsatJob *jobs, const int2 *items, int n_items, int thr_num, int thr_den,
+                                      int expand, hipStream_t s) {
+    hipLaunchKernelGGL(ksat_magnetization_batch_kernel, dim3(n_items), dim3(256), 0, s, jobs, items, thr_num, thr_den,
+                       expand);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !expand)
+        return e;
+    hipLaunchKernelGGL(ksat_expand_batch_kernel, dim3(n_items), dim3(256), 0, s, jobs, items);
     return hipGetLastError();
 }
 

@@ -76,8 +76,10 @@ __global__ void qap_reset_tallies_kernel(QapRepDev R) {
     }
 }
 
-__global__ void __launch_bounds__(256) qap_sweep_kernel(QapDev I, QapRepDev R, QapCall C) {
-    extern __shared__ __align__(16) uint8_t smem[];
+// n_sweeps sweeps for the 16 replicas of block `blk`, by the whole
+// 256-thread workgroup, with smem = the workgroup's dynamic LDS block.
+__device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev &R, const QapCall &C, const int blk,
+                                                uint8_t *smem) {
     const int n = I.n, nn = n * n;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
@@ -97,7 +99,7 @@ __global__ void __launch_bounds__(256) qap_sweep_kernel(QapDev I, QapRepDev R, Q
     }
     for (int i = tid; i < n; i += blockDim.x)
         cls[i] = C.fac_cls ? C.fac_cls[i] : 0;
-    const int rbase = blockIdx.x * kRepPerBlock;
+    const int rbase = blk * kRepPerBlock;
     for (int i = tid; i < kRepPerBlock * n; i += blockDim.x) {
         const int rl = i / n, f = i % n;
         const int rep = rbase + rl;
@@ -196,11 +198,28 @@ __global__ void __launch_bounds__(256) qap_sweep_kernel(QapDev I, QapRepDev R, Q
     }
 }
 
+__global__ void __launch_bounds__(256) qap_sweep_kernel(QapDev I, QapRepDev R, QapCall C) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    qap_sweep_block(I, R, C, blockIdx.x, smem);
+}
+
+// Batched launch over (job, block of 16 replicas) items in decreasing cost.
+__global__ void __launch_bounds__(256) qap_sweep_batch_kernel(const QapJob *jobs, const int2 *items, int n_items) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 w = items[it];
+        const QapJob &J = jobs[w.x];
+        qap_sweep_block(J.I, J.R, J.C, w.y, smem);
+        __syncthreads();
+    }
+}
+
 // Assignment frequencies and the per-facility frozen test: one workgroup per facility.
-__global__ void qap_backbone_kernel(QapDev I, QapRepDev R, int thr_num, int thr_den) {
+__device__ __forceinline__ void qap_backbone_facility(const QapDev &I, const QapRepDev &R, int thr_num, int thr_den,
+                                                      const int f) {
     __shared__ int hist[kQapMaxN + 1];
     __shared__ int mx;
-    const int f = blockIdx.x, n = I.n;
+    const int n = I.n;
     for (int l = threadIdx.x; l < n; l += blockDim.x)
         hist[l] = 0;
     if (threadIdx.x == 0)
@@ -216,6 +235,15 @@ __global__ void qap_backbone_kernel(QapDev I, QapRepDev R, int thr_num, int thr_
     __syncthreads();
     if (threadIdx.x == 0)
         R.cls[f] = (long long)thr_den * mx >= (long long)thr_num * R.n_rep;
+}
+
+__global__ void qap_backbone_kernel(QapDev I, QapRepDev R, int thr_num, int thr_den) {
+    qap_backbone_facility(I, R, thr_num, thr_den, blockIdx.x);
+}
+
+__global__ void qap_backbone_batch_kernel(const QapJob *jobs, const int2 *items, int thr_num, int thr_den) {
+    const int2 w = items[blockIdx.x];
+    qap_backbone_facility(jobs[w.x].I, jobs[w.x].R, thr_num, thr_den, w.y);
 }
 
 __global__ void qap_tally_kernel(QapRepDev R) {
@@ -289,6 +317,33 @@ hipError_t qap_launch_sweep(const QapDev &I, const QapRepDev &R, const QapCall &
     }
     const int blocks = (R.n_rep + kRepPerBlock - 1) / kRepPerBlock;
     hipLaunchKernelGGL(qap_sweep_kernel, dim3(blocks), dim3(256), lds, s, I, R, C);
+    return hipGetLastError();
+}
+
+hipError_t qap_launch_sweep_batch(const QapJob *jobs, const int2 *items, int n_items, size_t lds, int grid,
+                                  hipStream_t s) {
+    static bool attr = false;
+    if (!attr) {
+        const hipError_t ea = hipFuncSetAttribute((const void *)qap_sweep_batch_kernel,
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
+        if (ea != hipSuccess)
+            return ea;
+        attr = true;
+    }
+    hipLaunchKernelGGL(qap_sweep_batch_kernel, dim3(grid), dim3(256), lds, s, jobs, items, n_items);
+    return hipGetLastError();
+}
+
+int qap_batch_occupancy(size_t lds) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)qap_sweep_batch_kernel, 256, lds) != hipSuccess)
+        return 1;
+    return nb < 1 ? 1 : nb;
+}
+
+hipError_t qap_launch_backbone_batch(const QapJob *jobs, const int2 *items, int n_items, int thr_num, int thr_den,
+                                     hipStream_t s) {
+    hipLaunchKernelGGL(qap_backbone_batch_kernel, dim3(n_items), dim3(256), 0, s, jobs, items, thr_num, thr_den);
     return hipGetLastError();
 }
 

@@ -37,6 +37,12 @@ class InstanceInfo(ctypes.Structure):
                 ("n_colors", ctypes.c_int32), ("delta_bound", ctypes.c_int64)]
 
 
+class Plan(ctypes.Structure):
+    _fields_ = [("anneal_beta", ctypes.c_void_p), ("anneal_sweeps", ctypes.c_int32), ("rounds", ctypes.c_int32),
+                ("reanneal_beta", ctypes.c_void_p), ("reanneal_sweeps", ctypes.c_int32),
+                ("thr_num", ctypes.c_int32), ("thr_den", ctypes.c_int32), ("expand", ctypes.c_int32)]
+
+
 _P = ctypes.c_void_p
 _I32 = ctypes.c_int32
 _U32 = ctypes.c_uint32
@@ -68,6 +74,15 @@ _SIGS = {
     "nmc_set_tuning": ([_P, _I32], ctypes.c_int),
     "nmc_set_profiling": ([_P, _I32], ctypes.c_int),
     "nmc_kernel_time": ([_P, _P, _P, _P, _I32], ctypes.c_int),
+    "nmc_batch_create": ([_P, _I32, _PP], ctypes.c_int),
+    "nmc_batch_free": ([_P], None),
+    "nmc_batch_set_tuning": ([_P, _I32], ctypes.c_int),
+    "nmc_batch_tune": ([_P, _I32, _P, _P], ctypes.c_int),
+    "nmc_batch_anneal": ([_P, _P, _I32, _I32, _I32, _P, _P], ctypes.c_int),
+    "nmc_batch_estimate_backbone": ([_P, _I32, _I32, _I32, _P], ctypes.c_int),
+    "nmc_batch_run_plan": ([_P, ctypes.POINTER(Plan), _P, _I32, _P], ctypes.c_int),
+    "nmc_batch_set_profiling": ([_P, _I32], ctypes.c_int),
+    "nmc_batch_kernel_time": ([_P, _P, _P, _P, _I32], ctypes.c_int),
 }
 
 _lib = None
@@ -294,6 +309,73 @@ class Replicas:
             lib().nmc_replicas_free(self._h)
             self._h = None
         self._buf = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many replica sets run by one launch per kernel kind (nmc_batch_*)."""
+
+    def __init__(self, sets):
+        self.sets = list(sets)
+        arr = (ctypes.c_void_p * len(self.sets))(*[s._h for s in self.sets])
+        h = ctypes.c_void_p()
+        _check(lib().nmc_batch_create(arr, len(self.sets), ctypes.byref(h)))
+        self._h = h
+
+    def _targets(self, targets):
+        if targets is None:
+            return None
+        t = np.ascontiguousarray(np.broadcast_to(np.asarray(targets, np.int64), (len(self.sets),)))
+        return t
+
+    def set_tuning(self, block_threads=0):
+        _check(lib().nmc_batch_set_tuning(self._h, int(block_threads)))
+
+    def tune(self, probe_sweeps=3, stream=None):
+        chosen = ctypes.c_int32()
+        _check(lib().nmc_batch_tune(self._h, int(probe_sweeps), ctypes.byref(chosen), _stream(stream)))
+        return chosen.value
+
+    def anneal(self, beta, profile="homogeneous", targets=None, stream=None):
+        b = np.ascontiguousarray(np.atleast_2d(np.asarray(beta, np.float64)))
+        nc, S = b.shape
+        t = self._targets(targets)
+        _check(lib().nmc_batch_anneal(self._h, _ptr(b), nc, S, PROFILE[profile] if isinstance(profile, str) else profile,
+                                      _ptr(t), _stream(stream)))
+
+    def estimate_backbone(self, thr_num=9, thr_den=10, expand=True, stream=None):
+        _check(lib().nmc_batch_estimate_backbone(self._h, int(thr_num), int(thr_den), int(bool(expand)),
+                                                 _stream(stream)))
+
+    def run_plan(self, anneal_beta, rounds, reanneal_beta, thr_num=9, thr_den=10, expand=True, targets=None,
+                 use_graph=True, stream=None):
+        a = np.ascontiguousarray(np.asarray(anneal_beta, np.float64).reshape(-1))
+        r = np.ascontiguousarray(np.asarray(reanneal_beta, np.float64).reshape(2, -1))
+        plan = Plan(a.ctypes.data, a.size, int(rounds), r.ctypes.data, r.shape[1], int(thr_num), int(thr_den),
+                    int(bool(expand)))
+        t = self._targets(targets)
+        _check(lib().nmc_batch_run_plan(self._h, ctypes.byref(plan), _ptr(t), int(bool(use_graph)), _stream(stream)))
+
+    def set_profiling(self, enable=True):
+        _check(lib().nmc_batch_set_profiling(self._h, int(bool(enable))))
+
+    def kernel_time(self, reset=False):
+        ms = ctypes.c_double()
+        launches = ctypes.c_int64()
+        att = ctypes.c_double()
+        _check(lib().nmc_batch_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(launches), ctypes.byref(att),
+                                           int(bool(reset))))
+        return dict(ms=ms.value, launches=launches.value, attempts=att.value)
+
+    def free(self):
+        if getattr(self, "_h", None):
+            lib().nmc_batch_free(self._h)
+            self._h = None
 
     def __del__(self):
         try:

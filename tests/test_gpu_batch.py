@@ -1,0 +1,135 @@
+"""Batched launches (many replica sets of different instances in one grid,
+optionally one HIP graph for the whole anneal -> backbone -> reanneal plan):
+every set's results are bit-identical to running it alone, whatever the
+workgroup size the tuner picks."""
+import numpy as np
+import pytest
+
+from gpu_util import say
+from paper_2111_13628_amd import instances, nmc
+
+pytestmark = pytest.mark.gpu
+
+
+def _mix(seed=11):
+    specs = [("ksat", 1000, "4.15", 3, 64), ("ksat", 1700, "9.8", 4, 128), ("ksat", 3900, "9.8", 4, 38),
+             ("ksat", 700, "4.15", 3, 10), ("qap", 23, None, None, 40), ("ksat", 6000, "9.8", 4, 256),
+             ("qap", 57, None, None, 16)]
+    out = []
+    for i, (kind, n, alpha, k, R) in enumerate(specs):
+        if kind == "ksat":
+            cp, lits = instances.gen_ksat(n, alpha, k, seed + i)
+            out.append(("ksat", (n, cp, lits), R, seed + 100 + i))
+        else:
+            F, D = instances.gen_qap(n, seed + i)
+            out.append(("qap", (F, D), R, seed + 100 + i))
+    return out
+
+
+def _make(mix):
+    sets = []
+    for kind, data, R, sd in mix:
+        inst = nmc.Instance.ksat(*data) if kind == "ksat" else nmc.Instance.qap(*data)
+        inst.bind()
+        sets.append(nmc.Replicas(inst, R, sd))
+    return sets
+
+
+def _sched():
+    a = instances.linear_schedule(0.1, 4.0, 24)
+    r = instances.profile_schedule(np.full(10, 4.0), instances.linear_schedule(0.5, 4.0, 10))
+    return a, r
+
+
+def _scale(kind):
+    return 1.0 if kind == "ksat" else 2e-4
+
+
+def _compare(a, b):
+    assert (a.get_state() == b.get_state()).all()
+    assert (a.get_state("best") == b.get_state("best")).all()
+    ea, eb = a.best_energy(), b.best_energy()
+    for key in ("energy", "best_per_replica", "first_hit"):
+        assert (ea[key] == eb[key]).all(), key
+    assert a.sweeps_done() == b.sweeps_done()
+
+
+def test_batched_calls_equal_individual_calls():
+    say("case: batch vs alone, 7 sets (5 k-SAT, 2 QAP)")
+    mix = _mix()
+    alone = _make(mix)
+    batched = _make(mix)
+    a_beta, r_beta = _sched()
+    # the QAP sets take their own beta scale; a batch shares one schedule, so
+    # run QAP and k-SAT in separate batches of the same call sequence
+    groups = {"ksat": [i for i, m in enumerate(mix) if m[0] == "ksat"],
+              "qap": [i for i, m in enumerate(mix) if m[0] == "qap"]}
+    for kind, idx in groups.items():
+        sc = _scale(kind)
+        targets = [int(i * 3) for i in idx]
+        b = nmc.Batch([batched[i] for i in idx])
+        b.anneal(a_beta[None, :] * sc, targets=targets)
+        b.estimate_backbone(9, 10, True)
+        b.anneal(r_beta * sc, profile="backbone", targets=targets)
+        for j, i in enumerate(idx):
+            s = alone[i]
+            s.anneal(a_beta[None, :] * sc, target=targets[j])
+            s.estimate_backbone(9, 10, True)
+            s.reanneal(r_beta * sc, "backbone", target=targets[j])
+    for i in range(len(mix)):
+        _compare(alone[i], batched[i])
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_plan_equals_call_sequence(use_graph):
+    say(f"case: plan (graph={use_graph})")
+    mix = [m for m in _mix(23) if m[0] == "ksat"]
+    alone = _make(mix)
+    planned = _make(mix)
+    a_beta, r_beta = _sched()
+    b = nmc.Batch(planned)
+    b.run_plan(a_beta, 2, r_beta, 9, 10, True, targets=5, use_graph=use_graph)
+    for s in alone:
+        s.anneal(a_beta[None, :], target=5)
+        for _ in range(2):
+            s.estimate_backbone(9, 10, True)
+            s.reanneal(r_beta, "backbone", target=5)
+    for x, y in zip(alone, planned):
+        _compare(x, y)
+
+
+def test_qap_plan_in_graph():
+    mix = [m for m in _mix(31) if m[0] == "qap"]
+    alone = _make(mix)
+    planned = _make(mix)
+    a_beta, r_beta = _sched()
+    sc = _scale("qap")
+    nmc.Batch(planned).run_plan(a_beta * sc, 1, r_beta * sc, 9, 10, False, use_graph=True)
+    for s in alone:
+        s.anneal(a_beta[None, :] * sc)
+        s.estimate_backbone(9, 10, False)
+        s.reanneal(r_beta * sc, "backbone")
+    for x, y in zip(alone, planned):
+        _compare(x, y)
+
+
+def test_tuner_choice_does_not_change_results():
+    say("case: tuner invariance")
+    mix = [m for m in _mix(41) if m[0] == "ksat"]
+    a_beta, _ = _sched()
+    ref = None
+    for bt in (64, 256, 1024, "tuned"):
+        sets = _make(mix)
+        b = nmc.Batch(sets)
+        if bt == "tuned":
+            chosen = b.tune(2)
+            assert chosen in (64, 128, 256, 512, 1024)
+        else:
+            b.set_tuning(bt)
+        b.anneal(a_beta[None, :], targets=2)
+        got = [(s.get_state(), s.best_energy()["best_per_replica"]) for s in sets]
+        if ref is None:
+            ref = got
+        else:
+            for (x0, b0), (x1, b1) in zip(ref, got):
+                assert (x0 == x1).all() and (b0 == b1).all()
