@@ -59,6 +59,87 @@ def run_path(inst, seed, target, nmc, stream=None, profile=False):
     return rep, be
 
 
+def bench_batch(nmc, torch, seed):
+    """Batched NMC on 256 mixed k-SAT instances (k in {3,4}, N log-uniform in
+    [1000, 20000], replicas 64..512 by N) in one graph-captured plan, against
+    plain simulated annealing launched once per instance."""
+    S_A, RND, S_R, CHUNK = 1000, 2, 500, 50
+    S_TOT = S_A + RND * S_R
+    mix = instances.batch_mix(256, seed)
+    insts = []
+    for m in mix:
+        cp, lits = instances.gen_ksat(m["n"], m["alpha"], m["k"], m["seed"])
+        insts.append(nmc.Instance.ksat(m["n"], cp, lits, 0).bind())
+    sa_beta = instances.linear_schedule(BETA0, BETA1, S_TOT)
+    a_beta = instances.linear_schedule(BETA0, BETA1, S_A)
+    r_beta = instances.profile_schedule(np.full(S_R, BETA1), instances.linear_schedule(BETA_HOT, BETA1, S_R))
+    attempts = float(sum(m["replicas"] * m["n"] for m in mix)) * S_TOT
+
+    def make(offset):
+        return [nmc.Replicas(inst, m["replicas"], m["seed"] + offset) for inst, m in zip(insts, mix)]
+
+    # targets: 10th percentile of a calibration plain-SA run (other seeds)
+    cal = make(7777)
+    cb = nmc.Batch(cal)
+    cb.tune(2)
+    cb.anneal(sa_beta[None, :])
+    targets = np.array([int(np.percentile(s.best_energy()["energy"], 10)) for s in cal], np.int64)
+    cb.free()
+    del cal
+
+    out = {"instances": len(mix), "attempts": attempts, "sweeps": S_TOT, "chunk_sweeps": CHUNK}
+
+    # (1) plain SA, one launch per instance
+    sets = make(0)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    ttt = []
+    for s, tg in zip(sets, targets):
+        t0 = time.perf_counter()
+        s.anneal(sa_beta[None, :], target=int(tg))
+        fh = s.best_energy()["first_hit"]
+        t1 = time.perf_counter()
+        hit = fh[fh >= 0]
+        ttt.append((t0 - t_start) + (float(hit.min()) / S_TOT) * (t1 - t0) if hit.size else None)
+    wall = time.perf_counter() - t_start
+    out["per_instance_sa"] = summarize(wall, attempts, ttt)
+    del sets
+
+    # (2) plain SA, all instances in one batched launch sequence (lockstep chunks)
+    sets = make(0)
+    bt = nmc.Batch(sets)
+    block = bt.tune(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bt.run_plan(sa_beta, 0, r_beta, 9, 10, True, targets=targets, use_graph=True, chunk_sweeps=CHUNK)
+    wall = time.perf_counter() - t0
+    out["batched_sa"] = summarize(wall, attempts, [None if (fh := s.best_energy()["first_hit"])[fh >= 0].size == 0
+                                                   else float(fh[fh >= 0].min()) / S_TOT * wall for s in sets])
+    out["batched_sa"]["block_threads"] = block
+    bt.free()
+    del sets
+
+    # (3) NMC, all instances in one graph: anneal -> 2 x (backbone -> reanneal)
+    sets = make(0)
+    bn = nmc.Batch(sets)
+    bn.set_tuning(block)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bn.run_plan(a_beta, RND, r_beta, 9, 10, True, targets=targets, use_graph=True, chunk_sweeps=CHUNK)
+    wall = time.perf_counter() - t0
+    out["batched_nmc"] = summarize(wall, attempts, [None if (fh := s.best_energy()["first_hit"])[fh >= 0].size == 0
+                                                    else float(fh[fh >= 0].min()) / S_TOT * wall for s in sets])
+    bn.free()
+    return out
+
+
+def summarize(wall, attempts, ttt):
+    hit = [t for t in ttt if t is not None]
+    return {"wall_s": wall, "attempts_per_s": attempts / wall, "instances_hit": len(hit),
+            "ttt_all_s": max(hit) if len(hit) == len(ttt) else None,
+            "ttt_median_s": float(np.median(hit)) if hit else None}
+
+
 def cpu_baseline(cp, lits, seed):
     import oracle
 
@@ -87,6 +168,8 @@ def main():
     ap.add_argument("--no-ttt", action="store_true")
     ap.add_argument("--block-threads", type=int, default=0)
     ap.add_argument("--class-cap", type=int, default=CLASS_CAP)
+    ap.add_argument("--workload", choices=["nmc", "batch"], default="nmc",
+                    help="nmc: the N=50000 NMC path (default); batch: 256 mixed instances, batched vs per-instance")
     ap.add_argument("--sweeps-only", type=int, default=0,
                     help="only time one homogeneous anneal of this many sweeps (for counter profiles) and exit")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -115,6 +198,15 @@ def main():
         return
     stream = torch.cuda.current_stream()
     seed = instances.DEFAULT_SEED
+    if args.workload == "batch":
+        res = bench_batch(nmc, torch, seed)
+        print(json.dumps({"metric": "batched NMC vs one-launch-per-instance plain SA: attempts/s and time-to-target",
+                          "value": res["batched_nmc"]["attempts_per_s"], "unit": "attempts/s", "n_gpus": 1,
+                          "higher_is_better": True, "dtype": "int32", "data": "synthetic",
+                          "config": {"workload": "256 random k-SAT instances, k in {3,4}, N log-uniform "
+                                                 "[1000, 20000], 1000 anneal + 2x(backbone + 500 reanneal)"},
+                          "batch": res}), flush=True)
+        return
     cp, lits = instances.gen_ksat(N, ALPHA, K, seed)
     inst = nmc.Instance.ksat(N, cp, lits, CLASS_CAP).bind()
     M = inst.info.n_clauses

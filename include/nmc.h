@@ -259,7 +259,10 @@ typedef struct nmc_batch nmc_batch;
  * re-estimated before every round).
  *   anneal_beta[s]                 s < anneal_sweeps, one class
  *   reanneal_beta[c * S + s]       c = 0 cold, 1 hot; S = reanneal_sweeps
- *   thr_num / thr_den, expand      as nmc_estimate_backbone */
+ *   thr_num / thr_den, expand      as nmc_estimate_backbone
+ *   chunk_sweeps                   > 0: every phase runs as launches of at
+ *                                  most this many sweeps, so all sets advance
+ *                                  in lockstep; 0: one launch per phase */
 typedef struct nmc_plan {
     const double *anneal_beta;
     int32_t anneal_sweeps;
@@ -267,6 +270,7 @@ typedef struct nmc_plan {
     const double *reanneal_beta;
     int32_t reanneal_sweeps;
     int32_t thr_num, thr_den, expand;
+    int32_t chunk_sweeps;
 } nmc_plan;
 
 /* Group n_sets distinct replica sets (k-SAT and QAP may be mixed) for batched

@@ -1374,15 +1374,18 @@ int validate_phase(nmc_batch *B, const PhaseSpec &ph, bool backbone_available) {
     return NMC_OK;
 }
 
-int run_batch(nmc_batch *B, const std::vector<PhaseSpec> &phases, int rounds_with_backbone_before, int thr_num,
+int run_batch(nmc_batch *B, const std::vector<PhaseSpec> &phases, const std::vector<char> &bb_before, int thr_num,
               int thr_den, int expand, const int64_t *targets, bool use_graph, hipStream_t s) {
-    // phases[0] runs first; before each later phase, a backbone estimate
-    // (when rounds_with_backbone_before != 0)
+    // phases run in order; bb_before[p] != 0 puts a backbone estimate before phase p
+    bool any_bb = false, seen_bb = false;
     for (size_t p = 0; p < phases.size(); ++p) {
-        const int rc = validate_phase(B, phases[p], p > 0 && rounds_with_backbone_before);
+        seen_bb = seen_bb || bb_before[p];
+        any_bb = any_bb || bb_before[p];
+        const int rc = validate_phase(B, phases[p], seen_bb);
         if (rc)
             return rc;
     }
+    const int rounds_with_backbone_before = any_bb ? 1 : 0;
     uint64_t total = 0;
     for (const auto &ph : phases)
         total += (uint64_t)ph.n_sweeps;
@@ -1414,7 +1417,7 @@ int run_batch(nmc_batch *B, const std::vector<PhaseSpec> &phases, int rounds_wit
         HIP_OR_FAIL(hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal));
         int erc = NMC_OK;
         for (size_t p = 0; p < built.size() && !erc; ++p) {
-            if (p > 0 && rounds_with_backbone_before)
+            if (bb_before[p])
                 erc = enqueue_backbone(B, bb, thr_num, thr_den, expand, B->cap_stream);
             if (!erc)
                 erc = enqueue_phase(B, built[p], B->cap_stream);
@@ -1458,7 +1461,7 @@ int run_batch(nmc_batch *B, const std::vector<PhaseSpec> &phases, int rounds_wit
         }
     } else {
         for (size_t p = 0; p < built.size(); ++p) {
-            if (p > 0 && rounds_with_backbone_before) {
+            if (bb_before[p]) {
                 rc = enqueue_backbone(B, bb, thr_num, thr_den, expand, s);
                 if (rc)
                     return rc;
@@ -1489,7 +1492,7 @@ int run_batch(nmc_batch *B, const std::vector<PhaseSpec> &phases, int rounds_wit
     }
     for (auto *P : B->sets) {
         P->sweeps_done += (uint32_t)total;
-        if (rounds_with_backbone_before && phases.size() > 1)
+        if (any_bb)
             P->has_backbone = true;
     }
     return ok();
@@ -1548,7 +1551,7 @@ int nmc_batch_anneal(nmc_batch *B, const double *beta, int32_t n_classes, int32_
     if (!B)
         return fail(NMC_ERR_INVALID, "NULL batch");
     try {
-        return run_batch(B, {PhaseSpec{beta, n_classes, n_sweeps, profile}}, 0, 0, 0, 0, targets, false,
+        return run_batch(B, {PhaseSpec{beta, n_classes, n_sweeps, profile}}, {0}, 0, 0, 0, targets, false,
                          as_stream(stream));
     } catch (const std::bad_alloc &) {
         return fail(NMC_ERR_CAPACITY, "host allocation failed");
@@ -1597,12 +1600,35 @@ int nmc_batch_run_plan(nmc_batch *B, const nmc_plan *plan, const int64_t *target
     if (plan->rounds > 0 && (plan->thr_den <= 0 || plan->thr_num <= 0 || plan->thr_num > plan->thr_den))
         return fail(NMC_ERR_INVALID, "need 0 < thr_num <= thr_den");
     try {
+        if (plan->chunk_sweeps < 0)
+            return fail(NMC_ERR_INVALID, "chunk_sweeps must be >= 0");
+        // each phase splits into launches of at most chunk_sweeps sweeps, so
+        // every set advances in lockstep; the schedule rows are cut accordingly
+        std::vector<std::vector<double>> pieces;
         std::vector<PhaseSpec> phases;
-        phases.push_back(PhaseSpec{plan->anneal_beta, 1, plan->anneal_sweeps, NMC_PROFILE_HOMOGENEOUS});
+        std::vector<char> bb_before;
+        auto add_phase = [&](const double *beta, int32_t nc, int32_t S, int32_t profile, bool bb) {
+            const int32_t K = plan->chunk_sweeps > 0 ? plan->chunk_sweeps : std::max(S, 1);
+            for (int32_t s0 = 0; s0 < S || (S == 0 && s0 == 0); s0 += K) {
+                const int32_t len = std::min(K, S - s0);
+                std::vector<double> b((size_t)nc * std::max(len, 0));
+                for (int32_t c = 0; c < nc; ++c)
+                    for (int32_t t = 0; t < len; ++t)
+                        b[(size_t)c * len + t] = beta[(size_t)c * S + s0 + t];
+                pieces.push_back(std::move(b));
+                phases.push_back(PhaseSpec{nullptr, nc, std::max(len, 0), profile});
+                bb_before.push_back(bb && s0 == 0);
+                if (S == 0)
+                    break;
+            }
+        };
+        add_phase(plan->anneal_beta, 1, plan->anneal_sweeps, NMC_PROFILE_HOMOGENEOUS, false);
         for (int32_t r = 0; r < plan->rounds; ++r)
-            phases.push_back(PhaseSpec{plan->reanneal_beta, 2, plan->reanneal_sweeps, NMC_PROFILE_BACKBONE});
-        return run_batch(B, phases, plan->rounds > 0 ? 1 : 0, plan->thr_num, plan->thr_den, plan->expand ? 1 : 0,
-                         targets, use_graph != 0, as_stream(stream));
+            add_phase(plan->reanneal_beta, 2, plan->reanneal_sweeps, NMC_PROFILE_BACKBONE, true);
+        for (size_t p = 0; p < phases.size(); ++p)
+            phases[p].beta = pieces[p].data();
+        return run_batch(B, phases, bb_before, plan->thr_num, plan->thr_den, plan->expand ? 1 : 0, targets,
+                         use_graph != 0, as_stream(stream));
     } catch (const std::bad_alloc &) {
         return fail(NMC_ERR_CAPACITY, "host allocation failed");
     }

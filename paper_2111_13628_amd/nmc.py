@@ -40,7 +40,8 @@ class InstanceInfo(ctypes.Structure):
 class Plan(ctypes.Structure):
     _fields_ = [("anneal_beta", ctypes.c_void_p), ("anneal_sweeps", ctypes.c_int32), ("rounds", ctypes.c_int32),
                 ("reanneal_beta", ctypes.c_void_p), ("reanneal_sweeps", ctypes.c_int32),
-                ("thr_num", ctypes.c_int32), ("thr_den", ctypes.c_int32), ("expand", ctypes.c_int32)]
+                ("thr_num", ctypes.c_int32), ("thr_den", ctypes.c_int32), ("expand", ctypes.c_int32),
+                ("chunk_sweeps", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -353,11 +354,11 @@ class Batch:
                                                  _stream(stream)))
 
     def run_plan(self, anneal_beta, rounds, reanneal_beta, thr_num=9, thr_den=10, expand=True, targets=None,
-                 use_graph=True, stream=None):
+                 use_graph=True, chunk_sweeps=0, stream=None):
         a = np.ascontiguousarray(np.asarray(anneal_beta, np.float64).reshape(-1))
         r = np.ascontiguousarray(np.asarray(reanneal_beta, np.float64).reshape(2, -1))
         plan = Plan(a.ctypes.data, a.size, int(rounds), r.ctypes.data, r.shape[1], int(thr_num), int(thr_den),
-                    int(bool(expand)))
+                    int(bool(expand)), int(chunk_sweeps))
         t = self._targets(targets)
         _check(lib().nmc_batch_run_plan(self._h, ctypes.byref(plan), _ptr(t), int(bool(use_graph)), _stream(stream)))
 

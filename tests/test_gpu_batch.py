@@ -80,15 +80,15 @@ def test_batched_calls_equal_individual_calls():
         _compare(alone[i], batched[i])
 
 
-@pytest.mark.parametrize("use_graph", [True, False])
-def test_plan_equals_call_sequence(use_graph):
-    say(f"case: plan (graph={use_graph})")
+@pytest.mark.parametrize("use_graph,chunk", [(True, 0), (False, 0), (True, 7)])
+def test_plan_equals_call_sequence(use_graph, chunk):
+    say(f"case: plan (graph={use_graph}, chunk={chunk})")
     mix = [m for m in _mix(23) if m[0] == "ksat"]
     alone = _make(mix)
     planned = _make(mix)
     a_beta, r_beta = _sched()
     b = nmc.Batch(planned)
-    b.run_plan(a_beta, 2, r_beta, 9, 10, True, targets=5, use_graph=use_graph)
+    b.run_plan(a_beta, 2, r_beta, 9, 10, True, targets=5, use_graph=use_graph, chunk_sweeps=chunk)
     for s in alone:
         s.anneal(a_beta[None, :], target=5)
         for _ in range(2):
