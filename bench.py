@@ -133,6 +133,56 @@ def bench_batch(nmc, torch, seed):
     return out
 
 
+def qap_beta_scale(F, D, seed, samples=100000):
+    """1 / median positive swap cost change over random (assignment, pair)
+    samples: the schedule's inverse temperatures are given in these units."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = F.shape[0]
+    F = F.astype(np.int64)
+    D = D.astype(np.int64)
+    p = np.argsort(rng.random((samples, n)), axis=1)
+    a = rng.integers(0, n, samples)
+    b = (a + 1 + rng.integers(0, n - 1, samples)) % n
+    rows = np.arange(samples)[:, None]
+    fa, fb = F[a], F[b]
+    pa, pb = p[np.arange(samples), a], p[np.arange(samples), b]
+    d = 2 * ((fa - fb) * (D[pb[:, None], p] - D[pa[:, None], p])).sum(1)
+    d = d[d > 0]
+    return 1.0 / float(np.median(d))
+
+
+def bench_qap(nmc, torch, seed, sweeps_only=0):
+    """QAP NMC: n = 100, 4096 replicas, anneal 5000 sweeps of 4950 proposed
+    swaps, then 2 x (frequency backbone -> reanneal 1000)."""
+    n, Rq, S_A, RND, S_R = 100, 4096, 5000, 2, 1000
+    F, D = instances.gen_qap(n, seed)
+    sc = qap_beta_scale(F, D, seed + 1)
+    inst = nmc.Instance.qap(F, D).bind()
+    a_beta = instances.linear_schedule(BETA0 * sc, BETA1 * sc, S_A)
+    r_beta = instances.profile_schedule(np.full(S_R, BETA1 * sc), instances.linear_schedule(BETA_HOT * sc, BETA1 * sc, S_R))
+    rep = nmc.Replicas(inst, Rq, seed)
+    rep.set_profiling(True)
+    pairs = n * (n - 1) // 2
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if sweeps_only:
+        rep.anneal(a_beta[None, :sweeps_only])
+        S_tot = sweeps_only
+    else:
+        rep.anneal(a_beta[None, :])
+        for _ in range(RND):
+            rep.estimate_backbone_device(9, 10, False)
+            rep.reanneal(r_beta, "backbone")
+        S_tot = S_A + RND * S_R
+    be = rep.best_energy()
+    wall = time.perf_counter() - t0
+    kt = rep.kernel_time()
+    props = float(Rq) * pairs * S_tot
+    return {"proposals": props, "wall_s": wall, "proposals_per_s": props / wall,
+            "kernel_ms": kt["ms"], "kernel_proposals_per_s": kt["attempts"] / (kt["ms"] / 1000.0),
+            "beta_unit": sc, "best_cost": be["best"], "sweeps": S_tot}
+
+
 def summarize(wall, attempts, ttt):
     hit = [t for t in ttt if t is not None]
     return {"wall_s": wall, "attempts_per_s": attempts / wall, "instances_hit": len(hit),
@@ -168,7 +218,7 @@ def main():
     ap.add_argument("--no-ttt", action="store_true")
     ap.add_argument("--block-threads", type=int, default=0)
     ap.add_argument("--class-cap", type=int, default=CLASS_CAP)
-    ap.add_argument("--workload", choices=["nmc", "batch"], default="nmc",
+    ap.add_argument("--workload", choices=["nmc", "batch", "qap"], default="nmc",
                     help="nmc: the N=50000 NMC path (default); batch: 256 mixed instances, batched vs per-instance")
     ap.add_argument("--sweeps-only", type=int, default=0,
                     help="only time one homogeneous anneal of this many sweeps (for counter profiles) and exit")
@@ -198,6 +248,14 @@ def main():
         return
     stream = torch.cuda.current_stream()
     seed = instances.DEFAULT_SEED
+    if args.workload == "qap":
+        res = bench_qap(nmc, torch, seed, args.sweeps_only)
+        print(json.dumps({"metric": "QAP swap proposals/s (whole NMC path)", "value": res["proposals_per_s"],
+                          "unit": "proposals/s", "n_gpus": 1, "higher_is_better": True, "dtype": "int32",
+                          "data": "synthetic",
+                          "config": {"workload": "QAP n=100, 4096 replicas, anneal 5000 + 2x(backbone + reanneal 1000)"},
+                          "qap": res}), flush=True)
+        return
     if args.workload == "batch":
         res = bench_batch(nmc, torch, seed)
         print(json.dumps({"metric": "batched NMC vs one-launch-per-instance plain SA: attempts/s and time-to-target",

@@ -11,6 +11,7 @@
 // The 4 replicas of a wave form one Philox group, so one wave-uniform
 // generator call serves all of them.
 #include <climits>
+#include <type_traits>
 
 #include "nmc_internal.h"
 #include "nmc_philox.h"
@@ -20,6 +21,25 @@ namespace nmc {
 namespace {
 
 constexpr int kRepPerBlock = kQapRepPerWave * 4;  // 4 waves
+
+// Sum over the 16 lanes of each DPP row (= one replica's segment), returned
+// to every lane of the row: rotations by 8, 4, 2, 1 within the row.
+__device__ __forceinline__ int row_allreduce16(int x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false);  // row_ror:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x124, 0xF, 0xF, false);  // row_ror:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x122, 0xF, 0xF, false);  // row_ror:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x121, 0xF, 0xF, false);  // row_ror:1
+    return x;
+}
+
+// Value of lane c (wave-uniform, < 16) of the caller's own 16-lane row.
+__device__ __forceinline__ uint32_t row_lane16(uint32_t v, int c, int sub) {
+    const uint32_t w0 = (uint32_t)__builtin_amdgcn_readlane((int)v, c);
+    const uint32_t w1 = (uint32_t)__builtin_amdgcn_readlane((int)v, 16 + c);
+    const uint32_t w2 = (uint32_t)__builtin_amdgcn_readlane((int)v, 32 + c);
+    const uint32_t w3 = (uint32_t)__builtin_amdgcn_readlane((int)v, 48 + c);
+    return sub == 0 ? w0 : sub == 1 ? w1 : sub == 2 ? w2 : w3;
+}
 
 __global__ void qap_init_kernel(QapDev I, QapRepDev R, uint32_t key0, uint32_t key1) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -78,25 +98,37 @@ __global__ void qap_reset_tallies_kernel(QapRepDev R) {
 
 // n_sweeps sweeps for the 16 replicas of block `blk`, by the whole
 // 256-thread workgroup, with smem = the workgroup's dynamic LDS block.
+// KPL = facilities handled per lane (k = q, q + 16, ...), KPL * 16 >= n; the
+// flow matrix sits in LDS with rows padded with zeros to 16 * KPL entries, so
+// padding k contribute (0 - 0) * (...) = 0 and no lane needs a bound check.
+// Each lane keeps, for its k: the location p_k, F[a][k] and D[p_a][p_k] in
+// registers, refreshed when a changes or a swap is accepted; a proposal (a, b)
+// then needs F[b][k] and D[p_b][p_k] from LDS.  The sum runs over every k and
+// is corrected by + 2 F_ab D_{p_a p_b}: with symmetric zero-diagonal matrices
+// the k = a and k = b terms are -F_ab D_{p_b p_a} and -F_ab D_{p_a p_b}.
+template <int KPL>
 __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev &R, const QapCall &C, const int blk,
                                                 uint8_t *smem) {
+    constexpr int FS = 16 * KPL;  // padded flow row
     const int n = I.n, nn = n * n;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int sub = lane >> 4, q = lane & 15;
     const int npad = (int)align_up(n, 4);
 
-    uint8_t *F = smem;
-    uint8_t *D = F + align_up(nn, 16);
+    uint8_t *F = smem;                      // [n][FS]
+    uint8_t *D = F + align_up((size_t)n * FS, 16);
     uint8_t *P = D + align_up(nn, 16);
     uint8_t *cls = P + kRepPerBlock * npad;
     uint32_t *tl = (uint32_t *)(cls + align_up(n, 16));
     const int tab_words = C.n_classes * C.stride;
 
-    for (int i = tid; i < nn; i += blockDim.x) {
-        F[i] = I.F[i];
-        D[i] = I.D[i];
+    for (int i = tid; i < n * FS; i += blockDim.x) {
+        const int r = i / FS, k = i % FS;
+        F[i] = k < n ? I.F[r * n + k] : 0;
     }
+    for (int i = tid; i < nn; i += blockDim.x)
+        D[i] = I.D[i];
     for (int i = tid; i < n; i += blockDim.x)
         cls[i] = C.fac_cls ? C.fac_cls[i] : 0;
     const int rbase = blk * kRepPerBlock;
@@ -123,6 +155,7 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
     }
     __syncthreads();
 
+    int pk[KPL], fa[KPL], da[KPL];
     for (int s = 0; s < C.n_sweeps; ++s) {
         const uint32_t t = C.t0 + (uint32_t)s;
         const uint32_t *tg = C.tab + (size_t)s * tab_words;
@@ -130,43 +163,72 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
             tl[i] = tg[i];
         __syncthreads();
 
+#pragma unroll
+        for (int i = 0; i < KPL; ++i) {
+            const int k = q + 16 * i;
+            pk[i] = k < n ? pr[k] : 0;
+        }
         uint32_t qidx = 0;
+        uint32_t uword = 0;  // this lane's Philox word for pair (qidx & ~15) + q
         for (int a = 0; a < n - 1; ++a) {
             const int ca = cls[a];
+            int pa = pr[a];
+            const uint8_t *frow_a = F + a * FS + q;
+#pragma unroll
+            for (int i = 0; i < KPL; ++i) {
+                fa[i] = frow_a[16 * i];
+                da[i] = D[pa * n + pk[i]];
+            }
+            int pb_next = pr[a + 1];
             for (int b = a + 1; b < n; ++b, ++qidx) {
-                const int pa = pr[a], pb = pr[b];
-                int part = 0;
-                for (int k = q; k < n; k += kQapLanesPerRep) {
-                    if (k == a || k == b)
-                        continue;
-                    const int pk = pr[k];
-                    part += ((int)F[a * n + k] - (int)F[b * n + k]) * ((int)D[pb * n + pk] - (int)D[pa * n + pk]);
+                if ((qidx & 15u) == 0) {
+                    const uint4 u4 = philox4x32_10(qidx + (uint32_t)q, t, group, kStreamQapSweep, C.key0, C.key1);
+                    uword = sub == 0 ? u4.x : sub == 1 ? u4.y : sub == 2 ? u4.z : u4.w;
                 }
-                part += __shfl_xor(part, 8, 16);
-                part += __shfl_xor(part, 4, 16);
-                part += __shfl_xor(part, 2, 16);
-                part += __shfl_xor(part, 1, 16);
+                // a swap at (a, b) changes p_a and p_b only, so p_{b+1} read
+                // now stays valid for the next proposal
+                const int pb = pb_next;
+                if (b + 1 < n)
+                    pb_next = pr[b + 1];
+                const uint8_t *frow_b = F + b * FS + q;
+                const uint8_t *drow_b = D + pb * n;
+                int part = 0;
+#pragma unroll
+                for (int i = 0; i < KPL; ++i)
+                    part += (fa[i] - (int)frow_b[16 * i]) * ((int)drow_b[pk[i]] - da[i]);
+                if (q == 0)
+                    part += 2 * (int)F[a * FS + b] * (int)D[pa * n + pb];
+                part = row_allreduce16(part);
                 const int dc = 2 * part;
+                const uint32_t u = row_lane16(uword, (int)(qidx & 15u), sub);
                 bool accept = dc <= 0;
-                const bool need = active && !accept;
-                if (__any(need)) {
-                    const uint4 u4 = philox4x32_10(qidx, t, group, kStreamQapSweep, C.key0, C.key1);
-                    const uint32_t u = sub == 0 ? u4.x : sub == 1 ? u4.y : sub == 2 ? u4.z : u4.w;
+                if (!accept) {
                     const int cl = max(ca, (int)cls[b]);
                     const uint32_t *T = tl + cl * C.stride;
                     const int h = dc >> kQapLowBits, l = dc & ((1 << kQapLowBits) - 1);
-                    uint32_t thr = 0;
-                    if (need && h < I.ha)
-                        thr = (uint32_t)(((uint64_t)T[h] * (uint64_t)T[I.ha + l]) >> 32);
-                    if (need)
-                        accept = u < thr;
+                    const uint32_t thr =
+                        h < I.ha ? (uint32_t)(((uint64_t)T[h] * (uint64_t)T[I.ha + l]) >> 32) : 0u;
+                    accept = u < thr;
                 }
-                if (active && accept) {
+                accept = accept && active;
+                if (accept) {
+                    const int pa_old = pa;
                     if (q == 0) {
                         pr[a] = (uint8_t)pb;
-                        pr[b] = (uint8_t)pa;
+                        pr[b] = (uint8_t)pa_old;
                     }
                     cost += dc;
+                    pa = pb;
+                    // only the lanes holding k = a and k = b see new locations
+                    // (register index a / 16 and b / 16 are wave-uniform)
+#pragma unroll
+                    for (int i = 0; i < KPL; ++i) {
+                        if (i == (a >> 4) && q == (a & 15))
+                            pk[i] = pb;
+                        if (i == (b >> 4) && q == (b & 15))
+                            pk[i] = pa_old;
+                        da[i] = D[pa * n + pk[i]];
+                    }
                 }
             }
         }
@@ -198,9 +260,23 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
     }
 }
 
+template <typename Fn>
+__device__ __forceinline__ void qap_dispatch_kpl(int n, Fn &&fn) {
+    if (n <= 32)
+        fn(std::integral_constant<int, 2>{});
+    else if (n <= 64)
+        fn(std::integral_constant<int, 4>{});
+    else if (n <= 112)
+        fn(std::integral_constant<int, 7>{});
+    else if (n <= 160)
+        fn(std::integral_constant<int, 10>{});
+    else
+        fn(std::integral_constant<int, 16>{});
+}
+
 __global__ void __launch_bounds__(256) qap_sweep_kernel(QapDev I, QapRepDev R, QapCall C) {
     extern __shared__ __align__(16) uint8_t smem[];
-    qap_sweep_block(I, R, C, blockIdx.x, smem);
+    qap_dispatch_kpl(I.n, [&](auto kpl) { qap_sweep_block<decltype(kpl)::value>(I, R, C, blockIdx.x, smem); });
 }
 
 // Batched launch over (job, block of 16 replicas) items in decreasing cost.
@@ -209,7 +285,7 @@ __global__ void __launch_bounds__(256) qap_sweep_batch_kernel(const QapJob *jobs
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int2 w = items[it];
         const QapJob &J = jobs[w.x];
-        qap_sweep_block(J.I, J.R, J.C, w.y, smem);
+        qap_dispatch_kpl(J.I.n, [&](auto kpl) { qap_sweep_block<decltype(kpl)::value>(J.I, J.R, J.C, w.y, smem); });
         __syncthreads();
     }
 }
@@ -280,10 +356,12 @@ __global__ void qap_tally_kernel(QapRepDev R) {
 
 }  // namespace
 
+int qap_kpl(int n) { return n <= 32 ? 2 : n <= 64 ? 4 : n <= 112 ? 7 : n <= 160 ? 10 : 16; }
+
 size_t qap_sweep_lds_bytes(int n, int n_classes, int stride) {
     const size_t nn = (size_t)n * n;
-    return 2 * align_up(nn, 16) + kRepPerBlock * align_up(n, 4) + align_up(n, 16) +
-           (size_t)n_classes * stride * sizeof(uint32_t);
+    return align_up((size_t)n * 16 * qap_kpl(n), 16) + align_up(nn, 16) + kRepPerBlock * align_up(n, 4) +
+           align_up(n, 16) + (size_t)n_classes * stride * sizeof(uint32_t);
 }
 
 hipError_t qap_launch_init(const QapDev &I, const QapRepDev &R, uint32_t key0, uint32_t key1, hipStream_t s) {
