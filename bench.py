@@ -36,7 +36,8 @@ BETA0, BETA1, BETA_HOT = 0.1, 4.0, 0.5
 CLASS_CAP = 1024
 BLOCK_THREADS = 0
 # VALU lane-operations the sweep kernel issues per (variable, clause slot) for
-# its 4 replicas, and per variable for the acceptance step; see the design doc.
+# its 4 replicas, and per variable for the acceptance step, counted in the
+# kernel's instruction stream.
 OPS_PER_SLOT = 9.0
 OPS_PER_VAR = 62.0
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock
@@ -183,6 +184,126 @@ def bench_qap(nmc, torch, seed, sweeps_only=0):
             "beta_unit": sc, "best_cost": be["best"], "sweeps": S_tot}
 
 
+SERVE_RATE, SERVE_SECONDS, SERVE_BUDGET_S = 50.0, 60.0, 2.0
+SERVE_SCHED = (150, 2, 50)  # anneal sweeps, rounds, reanneal sweeps per request
+SERVE_CHUNK = 25
+SERVE_KSAT_GRID = (2000, 4500, 10000, 22400, 50000)
+SERVE_QAP_GRID = (30, 60, 90, 120, 150)
+
+
+def _serve_gen(m):
+    if m["kind"] == "ksat":
+        return instances.gen_ksat(m["n"], m["alpha"], m["k"], m["seed"])
+    return instances.gen_qap(m["n"], m["seed"])
+
+
+def _qap_random_cost(F, D):
+    """Mean cost over uniformly random assignments."""
+    n = F.shape[0]
+    return float(F.astype(np.float64).sum()) * float(D.astype(np.float64).sum()) / (n * (n - 1))
+
+
+def serve_calibration(nmc, seed):
+    """Targets by request size: plain SA over the request's sweep total on one
+    calibration instance per grid size; k-SAT keeps the 10th-percentile final
+    energy per variable, QAP the 10th-percentile final cost relative to the
+    random-assignment mean, and its inverse-temperature scale."""
+    S = sum((SERVE_SCHED[0], SERVE_SCHED[1] * SERVE_SCHED[2]))
+    sa = instances.linear_schedule(BETA0, BETA1, S)
+    sets, kinfo, qinfo = [], [], []
+    for i, n in enumerate(SERVE_KSAT_GRID):
+        cp, lits = instances.gen_ksat(n, "9.7", 4, seed + 500 + i)
+        inst = nmc.Instance.ksat(n, cp, lits).bind()
+        sets.append(nmc.Replicas(inst, instances.serve_ksat_replicas(n), seed + 600 + i))
+    kb = nmc.Batch(sets)
+    kb.anneal(sa[None, :])
+    for n, rep in zip(SERVE_KSAT_GRID, sets):
+        kinfo.append(float(np.percentile(rep.best_energy()["energy"], 10)) / n)
+    kb.free()
+    for i, n in enumerate(SERVE_QAP_GRID):
+        F, D = instances.gen_qap(n, seed + 700 + i)
+        sc = qap_beta_scale(F, D, seed + 800 + i, samples=20000)
+        rep = nmc.Replicas(nmc.Instance.qap(F, D).bind(), 256, seed + 900 + i)
+        rep.anneal(sa[None, :] * sc)
+        qinfo.append((float(np.percentile(rep.best_energy()["energy"], 10)) / _qap_random_cost(F, D), sc))
+    return {"ksat_density": kinfo, "qap_ratio": [q[0] for q in qinfo], "qap_beta_scale": [q[1] for q in qinfo]}
+
+
+def bench_serve(nmc, torch, seed, seconds):
+    """Served NMC: a Poisson stream of k-SAT and QAP requests into the
+    continuous-batching server; latency from submission to the round end
+    where the request reached its target."""
+    from multiprocessing import Pool
+
+    cal = serve_calibration(nmc, seed)
+    mix = instances.serve_mix(SERVE_RATE, seconds, seed)
+    with Pool(max(1, min(16, os.cpu_count() or 1))) as pool:
+        data = pool.map(_serve_gen, mix, chunksize=8)
+    lk = np.log(np.asarray(SERVE_KSAT_GRID, np.float64))
+    reqs = []
+    for m, d in zip(mix, data):
+        if m["kind"] == "ksat":
+            dens = float(np.interp(np.log(m["n"]), lk, cal["ksat_density"]))
+            reqs.append((m, d, int(np.floor(dens * m["n"])), 1.0))
+        else:
+            F, D = d
+            ratio = float(np.interp(m["n"], SERVE_QAP_GRID, cal["qap_ratio"]))
+            sc = float(np.interp(m["n"], SERVE_QAP_GRID, cal["qap_beta_scale"]))
+            reqs.append((m, d, int(np.floor((1.0 + 1e-2) * ratio * _qap_random_cost(F, D))), sc))
+    del data
+    a, rounds, re = SERVE_SCHED
+    srv = nmc.Server(chunk_sweeps=SERVE_CHUNK, loader_threads=max(2, min(12, (os.cpu_count() or 8) - 4)))
+    ids = []
+    t_start = time.perf_counter()
+    for m, d, target, sc in reqs:
+        delay = m["arrival"] - (time.perf_counter() - t_start)
+        if delay > 0:
+            time.sleep(delay)
+        if m["kind"] == "ksat":
+            cp, lits = d
+            rid = srv.submit_ksat(m["n"], cp, lits, m["replicas"], m["seed"], BETA0, BETA1, BETA_HOT, a, rounds, re,
+                                  target=target, budget_s=SERVE_BUDGET_S)
+        else:
+            F, D = d
+            rid = srv.submit_qap(F, D, m["replicas"], m["seed"], BETA0 * sc, BETA1 * sc, BETA_HOT * sc, a, rounds,
+                                 re, target=target, budget_s=SERVE_BUDGET_S)
+        ids.append(rid)
+        if len(ids) % 500 == 0:
+            print(f"# serve: {len(ids)} submitted, {srv.stats()['completed']} completed", file=sys.stderr, flush=True)
+    drained = srv.wait_idle(300.0)
+    res = [srv.poll(i) for i in ids]
+    stats = srv.stats()
+    srv.free()
+    t0 = min(r["t_submit"] for r in res)
+    wall = max(r["t_done"] for r in res) - t0
+
+    def pct(xs):
+        return {"p50": float(np.percentile(xs, 50)), "p99": float(np.percentile(xs, 99))} if xs else None
+
+    out = {"requests": len(res), "offered_rate_per_s": SERVE_RATE, "seconds": seconds, "drained": drained,
+           "schedule": {"anneal": a, "rounds": rounds, "reanneal": re, "chunk_sweeps": SERVE_CHUNK,
+                        "budget_s": SERVE_BUDGET_S},
+           "wall_s": wall, "gpu_busy_s_summed_over_workers": stats["gpu_busy_s"], "rounds": stats["rounds"],
+           "calibration": cal}
+    attempts = 0.0
+    for kind in ("ksat", "qap", "all"):
+        sel = [(m, r) for (m, _, _, _), r in zip(reqs, res) if kind == "all" or m["kind"] == kind]
+        solved = [r for _, r in sel if r["status"] == "solved"]
+        counts = {}
+        for _, r in sel:
+            counts[r["status"]] = counts.get(r["status"], 0) + 1
+        out[kind] = {"requests": len(sel), "status": counts, "solves_per_s": len(solved) / wall,
+                     "time_to_target_s": pct([r["t_done"] - r["t_submit"] for r in solved]),
+                     "latency_s": pct([r["t_done"] - r["t_submit"] for _, r in sel]),
+                     "queueing_s": pct([r["t_admit"] - r["t_submit"] for _, r in sel if r["t_admit"] > 0])}
+        if kind != "all":
+            for m, r in sel:
+                per = m["n"] if kind == "ksat" else m["n"] * (m["n"] - 1) / 2
+                attempts += float(m["replicas"]) * per * r["sweeps_done"]
+    out["moves_per_s"] = attempts / wall
+    return out
+
+
 def summarize(wall, attempts, ttt):
     hit = [t for t in ttt if t is not None]
     return {"wall_s": wall, "attempts_per_s": attempts / wall, "instances_hit": len(hit),
@@ -218,8 +339,10 @@ def main():
     ap.add_argument("--no-ttt", action="store_true")
     ap.add_argument("--block-threads", type=int, default=0)
     ap.add_argument("--class-cap", type=int, default=CLASS_CAP)
-    ap.add_argument("--workload", choices=["nmc", "batch", "qap"], default="nmc",
-                    help="nmc: the N=50000 NMC path (default); batch: 256 mixed instances, batched vs per-instance")
+    ap.add_argument("--workload", choices=["nmc", "batch", "qap", "serve"], default="nmc",
+                    help="nmc: the N=50000 NMC path (default); batch: 256 mixed instances, batched vs "
+                         "per-instance; qap: the n=100 QAP path; serve: Poisson stream into the server")
+    ap.add_argument("--serve-seconds", type=float, default=SERVE_SECONDS)
     ap.add_argument("--sweeps-only", type=int, default=0,
                     help="only time one homogeneous anneal of this many sweeps (for counter profiles) and exit")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -227,7 +350,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the replica-parallel path "
-              f"shards by replicas, see DESIGN.md", file=sys.stderr)
+              f"would shard by replicas, one slice per GPU", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -255,6 +378,15 @@ def main():
                           "data": "synthetic",
                           "config": {"workload": "QAP n=100, 4096 replicas, anneal 5000 + 2x(backbone + reanneal 1000)"},
                           "qap": res}), flush=True)
+        return
+    if args.workload == "serve":
+        res = bench_serve(nmc, torch, seed, args.serve_seconds)
+        print(json.dumps({"metric": "served NMC: solves/s and p50/p99 time-to-target", "value": res["all"]["solves_per_s"],
+                          "unit": "solves/s", "n_gpus": 1, "higher_is_better": True, "dtype": "int32",
+                          "data": "synthetic",
+                          "config": {"workload": f"Poisson {SERVE_RATE:g} req/s for {args.serve_seconds:g} s: 70% 4-SAT "
+                                                 "N log-uniform [2000, 50000] alpha 9.7, 30% QAP n in [30, 150]"},
+                          "serve": res}), flush=True)
         return
     if args.workload == "batch":
         res = bench_batch(nmc, torch, seed)

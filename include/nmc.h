@@ -280,6 +280,10 @@ typedef struct nmc_plan {
 int nmc_batch_create(nmc_replicas *const *sets, int32_t n_sets, nmc_batch **out);
 void nmc_batch_free(nmc_batch *batch);
 
+/* Replace the batch's member sets (n_sets >= 0, distinct); keeps the handle's
+ * device buffers, tuning and profiling state.  For continuous batching. */
+int nmc_batch_set_members(nmc_batch *batch, nmc_replicas *const *sets, int32_t n_sets);
+
 /* k-SAT sweep workgroup size for this batch's launches (64..1024, multiple of
  * 64; 0 = choose from the instances' colour-class sizes).  Results never
  * depend on it. */
@@ -308,9 +312,123 @@ int nmc_batch_estimate_backbone(nmc_batch *batch, int32_t thr_num, int32_t thr_d
 int nmc_batch_run_plan(nmc_batch *batch, const nmc_plan *plan, const int64_t *targets, int32_t use_graph,
                        void *stream);
 
+/* One step of n_sweeps for every set, each running its own segment of its
+ * own schedule (continuous batching: sets may be at different points of their
+ * plans).  segs[i] for set i:
+ *   beta[0], beta[1]   constant inverse temperatures of the cold / hot class
+ *                      over this step (class 1 only with the backbone profile)
+ *   profile            NMC_PROFILE_HOMOGENEOUS, NMC_PROFILE_BACKBONE, or < 0
+ *                      to leave the set idle in this step
+ *   backbone_before    != 0: estimate the set's backbone (thr_num / thr_den,
+ *                      expand) before the step
+ *   target             first-hit target, as nmc_anneal
+ * status_out (optional, n_sets entries) receives every set's best energy,
+ * replicas with best energy 0 and earliest first-hit sweep (-1 if none).
+ * One launch per kernel kind.  Synchronizes the stream before returning. */
+typedef struct nmc_segment {
+    double beta[2];
+    int32_t profile;
+    int32_t backbone_before;
+    int64_t target;
+} nmc_segment;
+
+typedef struct nmc_set_status {
+    int64_t best;
+    int32_t n_at_zero;
+    int32_t first_hit;
+} nmc_set_status;
+
+int nmc_batch_step(nmc_batch *batch, const nmc_segment *segs, int32_t n_sweeps, int32_t thr_num, int32_t thr_den,
+                   int32_t expand, nmc_set_status *status_out, void *stream);
+
 /* Kernel timing of batched sweeps, as nmc_set_profiling / nmc_kernel_time. */
 int nmc_batch_set_profiling(nmc_batch *batch, int32_t enable);
 int nmc_batch_kernel_time(nmc_batch *batch, double *ms, int64_t *launches, double *attempts, int32_t reset);
+
+/* ---------------------------------------------------------------------------
+ * serving: continuous batching of solve requests
+ * ------------------------------------------------------------------------- */
+
+typedef struct nmc_server nmc_server;
+
+typedef struct nmc_server_config {
+    size_t hbm_cap_bytes;    /* admit while the admitted requests' device bytes fit (0 = 64 GiB) */
+    int32_t chunk_sweeps;    /* sweeps per round; targets are checked at round ends (0 = 50) */
+    int32_t max_active;      /* most requests on the GPU at once (0 = 512) */
+    int32_t loader_threads;  /* host threads building instance layouts (0 = 4) */
+    int32_t block_threads;   /* k-SAT sweep workgroup size (0 = chosen per round) */
+    int32_t thr_num, thr_den, expand;  /* backbone rule for every request (0, 0 = 9/10, expand) */
+} nmc_server_config;
+
+/* A solve request.  The server copies every array during nmc_server_submit.
+ * Schedule (piecewise constant over rounds of chunk_sweeps sweeps): anneal
+ * rounds take beta0 .. beta1 linearly (both ends) on one class; then `rounds`
+ * times: backbone estimate (the server's rule), reanneal rounds with the cold
+ * class at beta1 and the hot class ramped beta_hot .. beta1.
+ * anneal_sweeps and reanneal_sweeps must be multiples of chunk_sweeps.
+ * QAP betas are in inverse cost units (already scaled by the caller). */
+typedef struct nmc_request {
+    int32_t kind;                                  /* NMC_KIND_KSAT or NMC_KIND_QAP */
+    int32_t n_vars, n_clauses, class_cap;          /* k-SAT (as nmc_ksat_load) */
+    const int32_t *clause_ptr, *lits;
+    int32_t n;                                     /* QAP (as nmc_qap_load) */
+    const int32_t *flow, *dist;
+    int32_t n_replicas;
+    uint64_t seed;
+    double beta0, beta1, beta_hot;
+    int32_t anneal_sweeps, rounds, reanneal_sweeps;
+    int64_t target;                                /* stop at the first round end with a replica <= target */
+    int32_t has_target;
+    double budget_s;                               /* stop after this long since admission (0 = none) */
+} nmc_request;
+
+enum nmc_request_status {
+    NMC_REQ_QUEUED = 0, NMC_REQ_LOADED = 1, NMC_REQ_RUNNING = 2,
+    NMC_REQ_SOLVED = 3,     /* reached its target */
+    NMC_REQ_EXHAUSTED = 4,  /* finished its schedule without reaching the target */
+    NMC_REQ_TIMEOUT = 5,    /* budget spent */
+    NMC_REQ_FAILED = 6      /* see message */
+};
+
+typedef struct nmc_result {
+    int32_t status;          /* nmc_request_status */
+    int32_t n_at_zero;
+    int64_t best;            /* lowest energy any replica reached at a sweep end */
+    int32_t first_hit_sweep; /* first sweep boundary at or below the target, -1 if none */
+    uint32_t sweeps_done;
+    double t_submit, t_admit, t_done;  /* seconds on the server clock */
+    size_t device_bytes;
+    char message[128];
+} nmc_result;
+
+typedef struct nmc_server_stats {
+    int64_t rounds, submitted, completed;
+    int32_t active, waiting;
+    size_t device_bytes_in_use;
+    double gpu_busy_s;       /* summed wall time of the rounds */
+} nmc_server_stats;
+
+/* Start a server: a worker thread that owns the GPU work on its own stream and
+ * loader threads that build instance layouts.  Every round advances all
+ * admitted requests by chunk_sweeps sweeps in one batched launch per kernel
+ * kind; loaded requests are admitted in arrival order as device memory and
+ * slots free up (a request larger than the cap runs alone), and retire at the
+ * round end where they reach their target, spend their budget or finish their
+ * schedule.  A request's results do not depend on what
+ * else is on the GPU (its own seed, schedule and sweep counter). */
+int nmc_server_create(const nmc_server_config *config, nmc_server **out);
+/* Thread-safe; copies the request.  *id identifies it in nmc_server_poll. */
+int nmc_server_submit(nmc_server *server, const nmc_request *req, uint64_t *id);
+/* Thread-safe snapshot of a request's state and result. */
+int nmc_server_poll(nmc_server *server, uint64_t id, nmc_result *out);
+/* Block until every submitted request has completed or timeout_s passes
+ * (returns NMC_ERR_STATE on timeout). */
+int nmc_server_wait_idle(nmc_server *server, double timeout_s);
+int nmc_server_get_stats(nmc_server *server, nmc_server_stats *out);
+/* Seconds on the server clock (steady, since creation). */
+double nmc_server_now(const nmc_server *server);
+/* Stop the threads (requests still running are marked FAILED) and free. */
+void nmc_server_free(nmc_server *server);
 
 #ifdef __cplusplus
 }

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnmc.so")
-SOURCES = ["nmc_api.cpp", "nmc_ksat.hip", "nmc_qap.hip"]
+SOURCES = ["nmc_api.cpp", "nmc_server.cpp", "nmc_ksat.hip", "nmc_qap.hip"]
 ARCH = os.environ.get("NMC_OFFLOAD_ARCH", "gfx950")
 
 
@@ -35,7 +35,7 @@ def build(verbose: bool = False) -> str:
         subprocess.check_call(cmd)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -39,6 +39,15 @@ int ok() {
     return NMC_OK;
 }
 
+}  // namespace
+
+int nmc::set_last_error(int code, const char *msg) {
+    g_err = msg ? msg : "";
+    return code;
+}
+
+namespace {
+
 #define HIP_OR_FAIL(expr)                                                                                  \
     do {                                                                                                   \
         hipError_t e_ = (expr);                                                                            \
@@ -786,6 +795,7 @@ static int anneal_impl(nmc_replicas *P, const double *beta, int32_t n_classes, i
         C.n_classes = n_classes;
         C.stride = stride;
         C.n_sweeps = n_sweeps;
+        C.sweep_words = n_classes * stride;
         C.t0 = P->sweeps_done;
         C.target = (int32_t)std::max<int64_t>(std::min<int64_t>(target, INT32_MAX), INT32_MIN);
         C.check_start = 1;
@@ -799,6 +809,7 @@ static int anneal_impl(nmc_replicas *P, const double *beta, int32_t n_classes, i
         C.n_classes = n_classes;
         C.stride = stride;
         C.n_sweeps = n_sweeps;
+        C.sweep_words = n_classes * stride;
         C.t0 = P->sweeps_done;
         C.target = target;
         C.check_start = 1;
@@ -1211,6 +1222,7 @@ int build_batch(nmc_batch *B, const std::vector<PhaseSpec> &phases, bool with_ba
                 J.C.n_classes = ph.n_classes;
                 J.C.stride = stride_k;
                 J.C.n_sweeps = ph.n_sweeps;
+                J.C.sweep_words = ph.n_classes * stride_k;
                 J.C.t0 = P->sweeps_done + offset_sweeps;
                 const int64_t tg = targets ? targets[kidx[j]] : -1;
                 J.C.target = (int32_t)std::max<int64_t>(std::min<int64_t>(tg, INT32_MAX), INT32_MIN);
@@ -1248,6 +1260,7 @@ int build_batch(nmc_batch *B, const std::vector<PhaseSpec> &phases, bool with_ba
                 J.C.n_classes = ph.n_classes;
                 J.C.stride = stride_q;
                 J.C.n_sweeps = ph.n_sweeps;
+                J.C.sweep_words = ph.n_classes * stride_q;
                 J.C.t0 = P->sweeps_done + offset_sweeps;
                 J.C.target = targets ? targets[qidx[j]] : -1;
                 J.C.check_start = 1;
@@ -1525,6 +1538,26 @@ int nmc_batch_create(nmc_replicas *const *sets, int32_t n_sets, nmc_batch **out)
     }
 }
 
+int nmc_batch_set_members(nmc_batch *B, nmc_replicas *const *sets, int32_t n_sets) {
+    if (!B || (!sets && n_sets > 0) || n_sets < 0)
+        return fail(NMC_ERR_INVALID, "bad argument");
+    try {
+        std::vector<nmc_replicas *> v;
+        for (int32_t i = 0; i < n_sets; ++i) {
+            if (!sets[i])
+                return fail(NMC_ERR_INVALID, "sets[%d] is NULL", i);
+            for (int32_t j = 0; j < i; ++j)
+                if (sets[j] == sets[i])
+                    return fail(NMC_ERR_INVALID, "replica set %d appears twice", i);
+            v.push_back(sets[i]);
+        }
+        B->sets.swap(v);
+        return ok();
+    } catch (const std::bad_alloc &) {
+        return fail(NMC_ERR_CAPACITY, "host allocation failed");
+    }
+}
+
 void nmc_batch_free(nmc_batch *B) {
     if (!B)
         return;
@@ -1779,6 +1812,238 @@ extern "C" int nmc_batch_tune(nmc_batch *B, int32_t probe_sweeps, int32_t *chose
         B->block_threads = best_b;
         if (chosen)
             *chosen = best_b;
+        return ok();
+    } catch (const std::bad_alloc &) {
+        return fail(NMC_ERR_CAPACITY, "host allocation failed");
+    }
+}
+
+// ---------------------------------------------------------------------------
+// one batched step where every set runs its own segment (serving)
+// ---------------------------------------------------------------------------
+
+extern "C" int nmc_batch_step(nmc_batch *B, const nmc_segment *segs, int32_t n_sweeps, int32_t thr_num,
+                              int32_t thr_den, int32_t expand, nmc_set_status *status_out, void *stream) {
+    if (!B || !segs)
+        return fail(NMC_ERR_INVALID, "NULL argument");
+    if (n_sweeps < 0)
+        return fail(NMC_ERR_INVALID, "n_sweeps must be >= 0");
+    try {
+        const size_t ns = B->sets.size();
+        bool any_bb = false;
+        for (size_t i = 0; i < ns; ++i) {
+            const nmc_segment &g = segs[i];
+            if (g.profile < 0)
+                continue;
+            if (g.profile != NMC_PROFILE_HOMOGENEOUS && g.profile != NMC_PROFILE_BACKBONE)
+                return fail(NMC_ERR_UNSUPPORTED, "segment %zu: profile must be homogeneous or backbone", i);
+            for (int c = 0; c < 2; ++c)
+                if (!std::isfinite(g.beta[c]) || g.beta[c] < 0)
+                    return fail(NMC_ERR_INVALID, "segment %zu: beta not finite and >= 0", i);
+            if (g.profile == NMC_PROFILE_BACKBONE && !g.backbone_before && !B->sets[i]->has_backbone)
+                return fail(NMC_ERR_STATE, "segment %zu: no backbone estimate yet", i);
+            if ((uint64_t)B->sets[i]->sweeps_done + (uint64_t)n_sweeps > 0xFFFFFFFFull)
+                return fail(NMC_ERR_INVALID, "segment %zu: sweep counter would pass 2^32 - 1", i);
+            any_bb = any_bb || g.backbone_before;
+        }
+        if (any_bb && (thr_den <= 0 || thr_num <= 0 || thr_num > thr_den))
+            return fail(NMC_ERR_INVALID, "need 0 < thr_num <= thr_den");
+        hipStream_t s = as_stream(stream);
+        int32_t stride_k = 1, ha = 1;
+        for (size_t i = 0; i < ns; ++i) {
+            if (segs[i].profile < 0)
+                continue;
+            const nmc_instance *I = B->sets[i]->inst;
+            if (I->kind == NMC_KIND_KSAT)
+                stride_k = std::max(stride_k, I->dmax + 1);
+            else
+                ha = std::max(ha, I->qap_ha);
+        }
+        const int32_t stride_q = ha + (1 << kQapLowBits);
+        std::vector<nmc_replicas *> ks;
+        for (size_t i = 0; i < ns; ++i)
+            if (segs[i].profile >= 0 && B->sets[i]->inst->kind == NMC_KIND_KSAT)
+                ks.push_back(B->sets[i]);
+        const int block_k = B->block_threads > 0 ? B->block_threads : heuristic_block(ks);
+        const int cus = device_cus();
+
+        // two passes over the layout: sizes, then contents with device addresses
+        Blob blob;
+        size_t off_kjobs = 0, off_kitems = 0, off_qjobs = 0, off_qitems = 0, off_bbk = 0, off_bbki = 0, off_bbq = 0,
+               off_bbqi = 0, off_src = 0, off_out = 0;
+        int nk = 0, nq = 0, nbk = 0, nbq = 0;
+        size_t lds_k = 0, lds_q = 0;
+        for (int pass = 0; pass < 2; ++pass) {
+            uint8_t *base = pass ? B->dev : nullptr;
+            blob.host.clear();
+            std::vector<KsatJob> kj;
+            std::vector<QapJob> qj;
+            std::vector<std::pair<double, int2>> kit, qit;
+            std::vector<int2> bbk, bbq;
+            std::vector<KsatJob> bbkj;
+            std::vector<QapJob> bbqj;
+            for (size_t i = 0; i < ns; ++i) {
+                const nmc_segment &g = segs[i];
+                if (g.profile < 0)
+                    continue;
+                nmc_replicas *P = B->sets[i];
+                const int32_t nc = g.profile == NMC_PROFILE_BACKBONE ? 2 : 1;
+                if (P->inst->kind == NMC_KIND_KSAT) {
+                    const size_t off = blob.take((size_t)nc * stride_k * 4);
+                    uint32_t *t = reinterpret_cast<uint32_t *>(blob.host.data() + off);
+                    for (int32_t c = 0; c < nc; ++c) {
+                        t[(size_t)c * stride_k] = 0xFFFFFFFFu;
+                        for (int32_t d = 1; d < stride_k; ++d)
+                            t[(size_t)c * stride_k + d] = threshold(g.beta[c], d);
+                    }
+                    KsatJob J{};
+                    J.I = P->inst->ksat_dev();
+                    J.R = P->k;
+                    J.C.tab = reinterpret_cast<const uint32_t *>(base + off);
+                    J.C.var_cls = nc == 2 ? P->k.cls : nullptr;
+                    J.C.n_classes = nc;
+                    J.C.stride = stride_k;
+                    J.C.n_sweeps = n_sweeps;
+                    J.C.sweep_words = 0;
+                    J.C.t0 = P->sweeps_done;
+                    J.C.target = (int32_t)std::max<int64_t>(std::min<int64_t>(g.target, INT32_MAX), INT32_MIN);
+                    J.C.check_start = 1;
+                    J.C.key0 = (uint32_t)P->seed;
+                    J.C.key1 = (uint32_t)(P->seed >> 32);
+                    const double cost = (double)P->inst->n * (P->inst->dmax + 1);
+                    for (int gi = 0; gi < P->G; ++gi)
+                        kit.push_back({cost, make_int2((int)kj.size(), gi)});
+                    lds_k = std::max(lds_k, ksat_sweep_lds_bytes(P->inst->n, nc, stride_k));
+                    kj.push_back(J);
+                    if (g.backbone_before) {
+                        for (int v0 = 0; v0 < P->inst->n; v0 += 256)
+                            bbk.push_back(make_int2((int)bbkj.size(), v0));
+                        bbkj.push_back(J);
+                    }
+                } else {
+                    const size_t off = blob.take((size_t)nc * stride_q * 4);
+                    uint32_t *t = reinterpret_cast<uint32_t *>(blob.host.data() + off);
+                    for (int32_t c = 0; c < nc; ++c) {
+                        uint32_t *row = t + (size_t)c * stride_q;
+                        row[0] = 0xFFFFFFFFu;
+                        for (int32_t h = 1; h < ha; ++h)
+                            row[h] = threshold(g.beta[c], (int64_t)h << kQapLowBits);
+                        row[ha] = 0xFFFFFFFFu;
+                        for (int32_t l = 1; l < (1 << kQapLowBits); ++l)
+                            row[ha + l] = threshold(g.beta[c], l);
+                    }
+                    QapJob J{};
+                    J.I = P->inst->qap_dev();
+                    J.I.ha = ha;
+                    J.R = P->q;
+                    J.C.tab = reinterpret_cast<const uint32_t *>(base + off);
+                    J.C.fac_cls = nc == 2 ? P->q.cls : nullptr;
+                    J.C.n_classes = nc;
+                    J.C.stride = stride_q;
+                    J.C.n_sweeps = n_sweeps;
+                    J.C.sweep_words = 0;
+                    J.C.t0 = P->sweeps_done;
+                    J.C.target = g.target;
+                    J.C.check_start = 1;
+                    J.C.key0 = (uint32_t)P->seed;
+                    J.C.key1 = (uint32_t)(P->seed >> 32);
+                    const double nd = P->inst->n;
+                    const int blocks = (P->R + kQapRepPerBlock - 1) / kQapRepPerBlock;
+                    for (int b = 0; b < blocks; ++b)
+                        qit.push_back({nd * nd * nd, make_int2((int)qj.size(), b)});
+                    lds_q = std::max(lds_q, qap_sweep_lds_bytes(P->inst->n, nc, stride_q));
+                    qj.push_back(J);
+                    if (g.backbone_before) {
+                        for (int f = 0; f < P->inst->n; ++f)
+                            bbq.push_back(make_int2((int)bbqj.size(), f));
+                        bbqj.push_back(J);
+                    }
+                }
+            }
+            auto by_cost = [](const std::pair<double, int2> &x, const std::pair<double, int2> &y) {
+                return x.first > y.first;
+            };
+            std::stable_sort(kit.begin(), kit.end(), by_cost);
+            std::stable_sort(qit.begin(), qit.end(), by_cost);
+            auto put = [&](size_t &off, const void *src, size_t bytes) {
+                off = blob.take(std::max<size_t>(bytes, 16));
+                if (bytes)
+                    std::memcpy(blob.host.data() + off, src, bytes);
+            };
+            std::vector<int2> kitems, qitems;
+            for (auto &p : kit)
+                kitems.push_back(p.second);
+            for (auto &p : qit)
+                qitems.push_back(p.second);
+            put(off_kjobs, kj.data(), kj.size() * sizeof(KsatJob));
+            put(off_kitems, kitems.data(), kitems.size() * sizeof(int2));
+            put(off_qjobs, qj.data(), qj.size() * sizeof(QapJob));
+            put(off_qitems, qitems.data(), qitems.size() * sizeof(int2));
+            put(off_bbk, bbkj.data(), bbkj.size() * sizeof(KsatJob));
+            put(off_bbki, bbk.data(), bbk.size() * sizeof(int2));
+            put(off_bbq, bbqj.data(), bbqj.size() * sizeof(QapJob));
+            put(off_bbqi, bbq.data(), bbq.size() * sizeof(int2));
+            std::vector<SetStatusSrc> src(ns);
+            for (size_t i = 0; i < ns; ++i) {
+                nmc_replicas *P = B->sets[i];
+                const bool k = P->inst->kind == NMC_KIND_KSAT;
+                src[i].best = k ? (const void *)P->k.best : (const void *)P->q.best;
+                src[i].first_hit = k ? P->k.first_hit : P->q.first_hit;
+                src[i].n_rep = P->R;
+                src[i].best_is_64 = k ? 0 : 1;
+            }
+            put(off_src, src.data(), src.size() * sizeof(SetStatusSrc));
+            off_out = blob.take(ns * sizeof(SetStatus));
+            nk = (int)kitems.size();
+            nq = (int)qitems.size();
+            nbk = (int)bbk.size();
+            nbq = (int)bbq.size();
+            if (pass == 0) {
+                if (lds_k > kLdsBytes || lds_q > kLdsBytes)
+                    return fail(NMC_ERR_CAPACITY, "batched step needs more LDS than a workgroup has");
+                const int rc = ensure_batch_mem(B, blob.host.size());
+                if (rc)
+                    return rc;
+            }
+        }
+        HIP_OR_FAIL(hipMemcpyAsync(B->dev, blob.host.data(), blob.host.size(), hipMemcpyHostToDevice, s));
+        if (nbk)
+            HIP_OR_FAIL(ksat_launch_backbone_batch(reinterpret_cast<const KsatJob *>(B->dev + off_bbk),
+                                                   reinterpret_cast<const int2 *>(B->dev + off_bbki), nbk, thr_num,
+                                                   thr_den, expand ? 1 : 0, s));
+        if (nbq)
+            HIP_OR_FAIL(qap_launch_backbone_batch(reinterpret_cast<const QapJob *>(B->dev + off_bbq),
+                                                  reinterpret_cast<const int2 *>(B->dev + off_bbqi), nbq, thr_num,
+                                                  thr_den, s));
+        if (nk) {
+            const int grid = std::min(nk, ksat_batch_occupancy(block_k, lds_k) * cus);
+            HIP_OR_FAIL(ksat_launch_sweep_batch(reinterpret_cast<const KsatJob *>(B->dev + off_kjobs),
+                                                reinterpret_cast<const int2 *>(B->dev + off_kitems), nk, lds_k,
+                                                block_k, grid, s));
+        }
+        if (nq) {
+            const int grid = std::min(nq, qap_batch_occupancy(lds_q) * cus);
+            HIP_OR_FAIL(qap_launch_sweep_batch(reinterpret_cast<const QapJob *>(B->dev + off_qjobs),
+                                               reinterpret_cast<const int2 *>(B->dev + off_qitems), nq, lds_q, grid,
+                                               s));
+        }
+        HIP_OR_FAIL(launch_set_status(reinterpret_cast<const SetStatusSrc *>(B->dev + off_src),
+                                      reinterpret_cast<SetStatus *>(B->dev + off_out), (int)ns, s));
+        std::vector<SetStatus> st(ns);
+        HIP_OR_FAIL(hipMemcpyAsync(st.data(), B->dev + off_out, ns * sizeof(SetStatus), hipMemcpyDeviceToHost, s));
+        HIP_OR_FAIL(hipStreamSynchronize(s));
+        for (size_t i = 0; i < ns; ++i) {
+            if (segs[i].profile >= 0) {
+                B->sets[i]->sweeps_done += (uint32_t)n_sweeps;
+                if (segs[i].backbone_before)
+                    B->sets[i]->has_backbone = true;
+            }
+            if (status_out) {
+                status_out[i].best = st[i].best;
+                status_out[i].n_at_zero = st[i].n_zero;
+                status_out[i].first_hit = st[i].first_hit;
+            }
+        }
         return ok();
     } catch (const std::bad_alloc &) {
         return fail(NMC_ERR_CAPACITY, "host allocation failed");

@@ -61,6 +61,7 @@ struct SweepCall {
     const uint32_t *tab;    // [n_sweeps][n_classes][stride] thresholds
     const uint8_t *var_cls; // per-variable class or nullptr
     int32_t n_classes, stride, n_sweeps;
+    int32_t sweep_words;    // words between consecutive sweeps' tables (0: one table for all)
     uint32_t t0;
     int32_t target;
     int32_t check_start;
@@ -96,6 +97,7 @@ struct QapCall {
     const uint32_t *tab;   // [n_sweeps][n_classes][ha + 1024]
     const uint8_t *fac_cls;// per-facility class or nullptr
     int32_t n_classes, stride, n_sweeps;
+    int32_t sweep_words;   // words between consecutive sweeps' tables (0: one table for all)
     uint32_t t0;
     int64_t target;
     int32_t check_start;
@@ -114,6 +116,21 @@ struct QapJob {
     QapRepDev R;
     QapCall C;
 };
+
+// Per-set status after a batched step: lowest best energy, replicas whose
+// best is 0, earliest first-hit sweep (-1 if none).
+struct SetStatusSrc {
+    const void *best;       // int32 (k-SAT) or int64 (QAP) per replica
+    const int32_t *first_hit;
+    int32_t n_rep;
+    int32_t best_is_64;
+};
+struct SetStatus {
+    long long best;
+    int32_t n_zero;
+    int32_t first_hit;
+};
+hipError_t launch_set_status(const SetStatusSrc *src, SetStatus *out, int n_sets, hipStream_t s);
 
 // ---- launchers (nmc_ksat.hip) ----
 size_t ksat_sweep_lds_bytes(int n, int n_classes, int stride);
@@ -148,5 +165,8 @@ int qap_batch_occupancy(size_t lds);
 hipError_t qap_launch_backbone_batch(const QapJob *jobs, const int2 *items, int n_items, int thr_num, int thr_den,
                                      hipStream_t s);
 constexpr int kQapRepPerBlock = 16;
+
+// records msg as the calling thread's nmc_last_error text; returns code
+int set_last_error(int code, const char *msg);
 
 }  // namespace nmc

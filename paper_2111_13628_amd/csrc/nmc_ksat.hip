@@ -175,7 +175,7 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
 
     for (int s = 0; s < C.n_sweeps; ++s) {
         const uint32_t t = C.t0 + (uint32_t)s;
-        const uint32_t *tg = C.tab + (size_t)s * tab_words;
+        const uint32_t *tg = C.tab + (size_t)s * C.sweep_words;
         for (int i = tid; i < tab_words; i += nthr)
             tl[i] = tg[i];
         __syncthreads();
@@ -465,6 +465,47 @@ __global__ void ksat_pack_kernel(const uint8_t *rows, int n, int n_groups, int n
     }
 }
 
+__global__ void set_status_kernel(const SetStatusSrc *src, SetStatus *out) {
+    __shared__ long long smin[4];
+    __shared__ int scnt[4], sfh[4];
+    const SetStatusSrc S = src[blockIdx.x];
+    long long mn = LLONG_MAX;
+    int cnt = 0, fh = INT_MAX;
+    for (int r = threadIdx.x; r < S.n_rep; r += blockDim.x) {
+        const long long b = S.best_is_64 ? reinterpret_cast<const long long *>(S.best)[r]
+                                         : (long long)reinterpret_cast<const int32_t *>(S.best)[r];
+        mn = b < mn ? b : mn;
+        cnt += b == 0;
+        const int f = S.first_hit[r];
+        if (f >= 0 && f < fh)
+            fh = f;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const long long o = __shfl_xor(mn, off, 64);
+        mn = o < mn ? o : mn;
+        cnt += __shfl_xor(cnt, off, 64);
+        fh = min(fh, __shfl_xor(fh, off, 64));
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        smin[w] = mn;
+        scnt[w] = cnt;
+        sfh[w] = fh;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
+            mn = smin[i] < mn ? smin[i] : mn;
+            cnt += scnt[i];
+            fh = min(fh, sfh[i]);
+        }
+        out[blockIdx.x].best = mn;
+        out[blockIdx.x].n_zero = cnt;
+        out[blockIdx.x].first_hit = fh == INT_MAX ? -1 : fh;
+    }
+}
+
 int grid_for(size_t total, int block) {
     size_t g = (total + block - 1) / block;
     if (g > 65536)
@@ -476,6 +517,11 @@ int grid_for(size_t total, int block) {
 
 size_t ksat_sweep_lds_bytes(int n, int n_classes, int stride) {
     return align_up(2 * (size_t)n + 2, 16) + align_up((size_t)n_classes * stride, 4) * 4 + 8 * sizeof(int);
+}
+
+hipError_t launch_set_status(const SetStatusSrc *src, SetStatus *out, int n_sets, hipStream_t s) {
+    hipLaunchKernelGGL(set_status_kernel, dim3(n_sets), dim3(256), 0, s, src, out);
+    return hipGetLastError();
 }
 
 hipError_t ksat_launch_init(const KsatDev &I, const KsatRepDev &R, uint32_t key0, uint32_t key1, hipStream_t s) {

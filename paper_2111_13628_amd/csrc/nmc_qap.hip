@@ -158,7 +158,7 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
     int pk[KPL], fa[KPL], da[KPL];
     for (int s = 0; s < C.n_sweeps; ++s) {
         const uint32_t t = C.t0 + (uint32_t)s;
-        const uint32_t *tg = C.tab + (size_t)s * tab_words;
+        const uint32_t *tg = C.tab + (size_t)s * C.sweep_words;
         for (int i = tid; i < tab_words; i += blockDim.x)
             tl[i] = tg[i];
         __syncthreads();

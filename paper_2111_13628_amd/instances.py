@@ -105,6 +105,13 @@ def batch_mix(n_instances: int, seed: int):
     return out
 
 
+def serve_ksat_replicas(n: int) -> int:
+    """Replicas of a served 4-SAT request: 64, 128 or 256 as N grows over
+    [2000, 50000] in thirds of its log range."""
+    step = min(2, int(np.floor(3.0 * np.log(n / 2000.0) / np.log(25.0))))
+    return 64 * (2 ** max(0, step))
+
+
 def serve_mix(rate_per_s: float, duration_s: float, seed: int):
     """Poisson request stream: 70 % random 4-SAT (N log-uniform in [2000, 50000],
     alpha 9.7), 30 % QAP (n uniform in [30, 150], entries in [0, 99])."""
@@ -118,9 +125,8 @@ def serve_mix(rate_per_s: float, duration_s: float, seed: int):
             break
         if rng.uniform() < 0.7:
             n = int(round(float(np.exp(rng.uniform(np.log(2000.0), np.log(50000.0))))))
-            step = min(2, int(np.floor(3.0 * np.log(n / 2000.0) / np.log(25.0))))
             reqs.append(dict(kind="ksat", arrival=t, n=n, k=4, alpha="9.7",
-                             replicas=64 * (2 ** max(0, step)), seed=seed + 1 + i))
+                             replicas=serve_ksat_replicas(n), seed=seed + 1 + i))
         else:
             n = int(rng.integers(30, 151))
             reqs.append(dict(kind="qap", arrival=t, n=n, replicas=256, seed=seed + 1 + i))

@@ -44,6 +44,47 @@ class Plan(ctypes.Structure):
                 ("chunk_sweeps", ctypes.c_int32)]
 
 
+class Segment(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double * 2), ("profile", ctypes.c_int32), ("backbone_before", ctypes.c_int32),
+                ("target", ctypes.c_int64)]
+
+
+class SetStatus(ctypes.Structure):
+    _fields_ = [("best", ctypes.c_int64), ("n_at_zero", ctypes.c_int32), ("first_hit", ctypes.c_int32)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_cap_bytes", ctypes.c_size_t), ("chunk_sweeps", ctypes.c_int32),
+                ("max_active", ctypes.c_int32), ("loader_threads", ctypes.c_int32),
+                ("block_threads", ctypes.c_int32), ("thr_num", ctypes.c_int32), ("thr_den", ctypes.c_int32),
+                ("expand", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n_vars", ctypes.c_int32), ("n_clauses", ctypes.c_int32),
+                ("class_cap", ctypes.c_int32), ("clause_ptr", ctypes.c_void_p), ("lits", ctypes.c_void_p),
+                ("n", ctypes.c_int32), ("flow", ctypes.c_void_p), ("dist", ctypes.c_void_p),
+                ("n_replicas", ctypes.c_int32), ("seed", ctypes.c_uint64), ("beta0", ctypes.c_double),
+                ("beta1", ctypes.c_double), ("beta_hot", ctypes.c_double), ("anneal_sweeps", ctypes.c_int32),
+                ("rounds", ctypes.c_int32), ("reanneal_sweeps", ctypes.c_int32), ("target", ctypes.c_int64),
+                ("has_target", ctypes.c_int32), ("budget_s", ctypes.c_double)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("n_at_zero", ctypes.c_int32), ("best", ctypes.c_int64),
+                ("first_hit_sweep", ctypes.c_int32), ("sweeps_done", ctypes.c_uint32), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double), ("device_bytes", ctypes.c_size_t),
+                ("message", ctypes.c_char * 128)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int64), ("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("active", ctypes.c_int32), ("waiting", ctypes.c_int32), ("device_bytes_in_use", ctypes.c_size_t),
+                ("gpu_busy_s", ctypes.c_double)]
+
+
+REQ_STATUS = {0: "queued", 1: "loaded", 2: "running", 3: "solved", 4: "exhausted", 5: "timeout", 6: "failed"}
+
 _P = ctypes.c_void_p
 _I32 = ctypes.c_int32
 _U32 = ctypes.c_uint32
@@ -82,8 +123,17 @@ _SIGS = {
     "nmc_batch_anneal": ([_P, _P, _I32, _I32, _I32, _P, _P], ctypes.c_int),
     "nmc_batch_estimate_backbone": ([_P, _I32, _I32, _I32, _P], ctypes.c_int),
     "nmc_batch_run_plan": ([_P, ctypes.POINTER(Plan), _P, _I32, _P], ctypes.c_int),
+    "nmc_batch_set_members": ([_P, _P, _I32], ctypes.c_int),
+    "nmc_batch_step": ([_P, _P, _I32, _I32, _I32, _I32, _P, _P], ctypes.c_int),
     "nmc_batch_set_profiling": ([_P, _I32], ctypes.c_int),
     "nmc_batch_kernel_time": ([_P, _P, _P, _P, _I32], ctypes.c_int),
+    "nmc_server_create": ([ctypes.POINTER(ServerConfig), _PP], ctypes.c_int),
+    "nmc_server_submit": ([_P, ctypes.POINTER(Request), ctypes.POINTER(_U64)], ctypes.c_int),
+    "nmc_server_poll": ([_P, _U64, ctypes.POINTER(Result)], ctypes.c_int),
+    "nmc_server_wait_idle": ([_P, ctypes.c_double], ctypes.c_int),
+    "nmc_server_get_stats": ([_P, ctypes.POINTER(ServerStats)], ctypes.c_int),
+    "nmc_server_now": ([_P], ctypes.c_double),
+    "nmc_server_free": ([_P], None),
 }
 
 _lib = None
@@ -362,6 +412,29 @@ class Batch:
         t = self._targets(targets)
         _check(lib().nmc_batch_run_plan(self._h, ctypes.byref(plan), _ptr(t), int(bool(use_graph)), _stream(stream)))
 
+    def set_members(self, sets):
+        """Replace the member sets (same rules as the constructor)."""
+        sets = list(sets)
+        arr = (ctypes.c_void_p * len(sets))(*[x._h for x in sets])
+        _check(lib().nmc_batch_set_members(self._h, arr, len(sets)))
+        self.sets = sets
+
+    def step(self, segments, n_sweeps, thr_num=9, thr_den=10, expand=True, stream=None):
+        """One batched step of n_sweeps sweeps; every set at its own constant
+        beta pair.  segments: per set (beta_cold, beta_hot, profile,
+        backbone_before, target) with profile a name or None (idle).
+        Returns [(best, n_at_zero, first_hit)] per set."""
+        segs = (Segment * len(self.sets))()
+        for g, (b0, b1, prof, bb, tgt) in zip(segs, segments):
+            g.beta[0], g.beta[1] = float(b0), float(b1)
+            g.profile = -1 if prof is None else (PROFILE[prof] if isinstance(prof, str) else int(prof))
+            g.backbone_before = int(bool(bb))
+            g.target = int(tgt)
+        st = (SetStatus * len(self.sets))()
+        _check(lib().nmc_batch_step(self._h, segs, int(n_sweeps), int(thr_num), int(thr_den), int(bool(expand)), st,
+                                    _stream(stream)))
+        return [(x.best, x.n_at_zero, x.first_hit) for x in st]
+
     def set_profiling(self, enable=True):
         _check(lib().nmc_batch_set_profiling(self._h, int(bool(enable))))
 
@@ -376,6 +449,88 @@ class Batch:
     def free(self):
         if getattr(self, "_h", None):
             lib().nmc_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching solve server (nmc_server_*): a native worker thread
+    advances every admitted request by chunk_sweeps sweeps per round in one
+    batched launch per kernel kind."""
+
+    def __init__(self, hbm_cap_bytes=0, chunk_sweeps=0, max_active=0, loader_threads=0, block_threads=0,
+                 thr_num=0, thr_den=0, expand=True):
+        import torch
+        if not torch.cuda.is_available():
+            raise NmcError(-3, "no GPU visible to torch")
+        torch.cuda.init()
+        cfg = ServerConfig(int(hbm_cap_bytes), int(chunk_sweeps), int(max_active), int(loader_threads),
+                           int(block_threads), int(thr_num), int(thr_den), int(bool(expand)))
+        h = ctypes.c_void_p()
+        _check(lib().nmc_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+
+    def submit_ksat(self, n_vars, clause_ptr, lits, n_replicas, seed, beta0, beta1, beta_hot, anneal_sweeps,
+                    rounds, reanneal_sweeps, target=None, budget_s=0.0, class_cap=0):
+        cp = np.ascontiguousarray(clause_ptr, np.int32)
+        li = np.ascontiguousarray(lits, np.int32)
+        r = Request(kind=KIND_KSAT, n_vars=int(n_vars), n_clauses=cp.size - 1, class_cap=int(class_cap),
+                    clause_ptr=cp.ctypes.data, lits=li.ctypes.data)
+        return self._submit(r, n_replicas, seed, beta0, beta1, beta_hot, anneal_sweeps, rounds, reanneal_sweeps,
+                            target, budget_s)
+
+    def submit_qap(self, flow, dist, n_replicas, seed, beta0, beta1, beta_hot, anneal_sweeps, rounds,
+                   reanneal_sweeps, target=None, budget_s=0.0):
+        F = np.ascontiguousarray(flow, np.int32)
+        D = np.ascontiguousarray(dist, np.int32)
+        r = Request(kind=KIND_QAP, n=F.shape[0], flow=F.ctypes.data, dist=D.ctypes.data)
+        return self._submit(r, n_replicas, seed, beta0, beta1, beta_hot, anneal_sweeps, rounds, reanneal_sweeps,
+                            target, budget_s)
+
+    def _submit(self, r, n_replicas, seed, beta0, beta1, beta_hot, anneal_sweeps, rounds, reanneal_sweeps, target,
+                budget_s):
+        r.n_replicas, r.seed = int(n_replicas), int(seed)
+        r.beta0, r.beta1, r.beta_hot = float(beta0), float(beta1), float(beta_hot)
+        r.anneal_sweeps, r.rounds, r.reanneal_sweeps = int(anneal_sweeps), int(rounds), int(reanneal_sweeps)
+        r.has_target = int(target is not None)
+        r.target = int(target) if target is not None else 0
+        r.budget_s = float(budget_s)
+        rid = ctypes.c_uint64()
+        _check(lib().nmc_server_submit(self._h, ctypes.byref(r), ctypes.byref(rid)))
+        return rid.value
+
+    def poll(self, rid):
+        res = Result()
+        _check(lib().nmc_server_poll(self._h, int(rid), ctypes.byref(res)))
+        return dict(status=REQ_STATUS[res.status], n_at_zero=res.n_at_zero, best=res.best,
+                    first_hit=res.first_hit_sweep, sweeps_done=res.sweeps_done, t_submit=res.t_submit,
+                    t_admit=res.t_admit, t_done=res.t_done, device_bytes=res.device_bytes,
+                    message=res.message.decode(errors="replace"))
+
+    def wait_idle(self, timeout_s=600.0):
+        """True when every submitted request completed within timeout_s."""
+        rc = lib().nmc_server_wait_idle(self._h, float(timeout_s))
+        if rc == -4:
+            return False
+        _check(rc)
+        return True
+
+    def stats(self):
+        st = ServerStats()
+        _check(lib().nmc_server_get_stats(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def now(self):
+        return lib().nmc_server_now(self._h)
+
+    def free(self):
+        if getattr(self, "_h", None):
+            lib().nmc_server_free(self._h)
             self._h = None
 
     def __del__(self):

@@ -103,3 +103,41 @@ def test_unbound_instance_rejects_replicas():
     h = ctypes.c_void_p()
     rc = nmc.lib().nmc_replicas_create(inst._h, 4, 1, ctypes.c_void_p(256), 1 << 20, None, ctypes.byref(h))
     assert rc == -4
+
+
+def test_server_validation_without_gpu():
+    """Config and request checks happen on the calling thread, before any GPU
+    work; a server whose worker finds no GPU reports it on submit or wait."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("the no-GPU error path needs a machine without a GPU")
+    L = nmc.lib()
+    h = ctypes.c_void_p()
+    bad = nmc.ServerConfig(0, 10, 0, 1, 0, 11, 10, 1)
+    assert L.nmc_server_create(ctypes.byref(bad), ctypes.byref(h)) == -1
+    bad = nmc.ServerConfig(0, 10, 0, 1, 100, 0, 0, 1)
+    assert L.nmc_server_create(ctypes.byref(bad), ctypes.byref(h)) == -1
+    cfg = nmc.ServerConfig(0, 10, 0, 1, 0, 0, 0, 1)
+    assert L.nmc_server_create(ctypes.byref(cfg), ctypes.byref(h)) == 0
+    try:
+        cp, lits = instances.gen_ksat(100, "4.2", 3, 1)
+        r = nmc.Request(kind=nmc.KIND_KSAT, n_vars=100, n_clauses=cp.size - 1, clause_ptr=cp.ctypes.data,
+                        lits=lits.ctypes.data, n_replicas=8, seed=1, beta0=0.1, beta1=3.0, beta_hot=1.0,
+                        anneal_sweeps=15, rounds=0, reanneal_sweeps=0)
+        rid = ctypes.c_uint64()
+        assert L.nmc_server_submit(h, ctypes.byref(r), ctypes.byref(rid)) == -1  # not a multiple of 10
+        r.anneal_sweeps, r.kind = 20, 7
+        assert L.nmc_server_submit(h, ctypes.byref(r), ctypes.byref(rid)) == -1
+        r.kind, r.n_replicas = nmc.KIND_KSAT, 0
+        assert L.nmc_server_submit(h, ctypes.byref(r), ctypes.byref(rid)) == -1
+        q = nmc.Request(kind=nmc.KIND_QAP, n=300, n_replicas=8, anneal_sweeps=10)
+        assert L.nmc_server_submit(h, ctypes.byref(q), ctypes.byref(rid)) == -1
+        r.n_replicas = 8
+        rc = L.nmc_server_submit(h, ctypes.byref(r), ctypes.byref(rid))
+        assert rc in (0, -3)
+        assert L.nmc_server_wait_idle(h, 5.0) == -3
+        assert b"GPU" in L.nmc_last_error()
+        res = nmc.Result()
+        assert L.nmc_server_poll(h, 12345, ctypes.byref(res)) == -1
+    finally:
+        L.nmc_server_free(h)
