@@ -20,6 +20,7 @@ import argparse
 import json
 import os
 import platform
+import re
 import sys
 import time
 
@@ -45,6 +46,31 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock
 
 def reanneal_profile(S):
     return instances.profile_schedule(np.full(S, BETA1), instances.linear_schedule(BETA_HOT, BETA1, S))
+
+
+KSAT_PROFILE = os.path.join(ROOT, "profiles", "ksat_sweep_n50000_r1024.md")
+
+
+def counter_bytes_per_sweep():
+    """HBM bytes per sweep of the k-SAT sweep kernel from the committed
+    counter passes, or None when the kernel sources changed since then."""
+    import hashlib
+    try:
+        text = open(KSAT_PROFILE).read()
+    except OSError:
+        return None
+    fields = dict(re.findall(r"^(\w+): (.+)$", text, flags=re.M))
+    if "counter_bytes_per_sweep" not in fields or "kernel_sources" not in fields:
+        return None
+    h = hashlib.sha256()
+    for f in fields["kernel_sources"].split():
+        try:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        except OSError:
+            return None
+    if h.hexdigest() != fields.get("kernel_sources_sha256", "").strip():
+        return None
+    return float(fields["counter_bytes_per_sweep"])
 
 
 def run_path(inst, seed, target, nmc, stream=None, profile=False):
@@ -319,7 +345,7 @@ def cpu_baseline(cp, lits, seed):
     _, order, _ = ok.color(CLASS_CAP)
     Rs = 4 * threads
     rep = oracle.KSatReplicas(ok, Rs, seed, order, threads=threads, snapshot=True)
-    sweeps = 2
+    sweeps = 32  # about 10-30 s of host work
     t0 = time.perf_counter()
     rep.anneal(instances.linear_schedule(BETA0, BETA1, S_ANNEAL)[None, :sweeps])
     dt = time.perf_counter() - t0
@@ -435,8 +461,12 @@ def main():
     deg_mean = K * M / N
     ops_per_attempt = (OPS_PER_SLOT * deg_mean + OPS_PER_VAR) / 4.0
     achieved = att_per_launch * ops_per_attempt / (kern_ms / 1000.0)
+    bps = counter_bytes_per_sweep()
+    sweeps_per_launch = (S_ANNEAL + ROUNDS * S_RE) / (1 + ROUNDS)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                "unit": "T lane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                "unit": "T lane-op/s", "frac": achieved / PEAK_LANE_OPS,
+                "traffic": None if bps is None else bps * sweeps_per_launch,
+                "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "kernel": "ksat_sweep_kernel", "kernel_ms_per_launch": kern_ms,
                 "kernel_attempts_per_s": kt["attempts"] / (kt["ms"] / 1000.0),
                 "launches": kt["launches"]}

@@ -70,8 +70,7 @@ struct SweepCall {
 
 // QAP: permutations as bytes, pair ranks in lexicographic order.
 constexpr int kQapMaxN = 255;
-constexpr int kQapLanesPerRep = 16;   // k-parts per replica inside a wave
-constexpr int kQapRepPerWave = 4;
+constexpr int kQapRepPerBlock = 16;   // one replica per wave, 16 waves per workgroup
 constexpr int kQapLowBits = 10;       // low digit of the two-level threshold
 
 struct QapDev {
@@ -164,7 +163,6 @@ hipError_t qap_launch_sweep_batch(const QapJob *jobs, const int2 *items, int n_i
 int qap_batch_occupancy(size_t lds);
 hipError_t qap_launch_backbone_batch(const QapJob *jobs, const int2 *items, int n_items, int thr_num, int thr_den,
                                      hipStream_t s);
-constexpr int kQapRepPerBlock = 16;
 
 // records msg as the calling thread's nmc_last_error text; returns code
 int set_last_error(int code, const char *msg);

@@ -1,15 +1,17 @@
 // QAP kernels for gfx950.
 //
-// A workgroup of 4 waves owns 16 replicas; each wave runs 4 replicas in
-// lockstep through the lexicographic pair sequence, 16 lanes per replica
-// splitting the sum over facilities k.  Flow F, distance D (bytes), the 16
-// permutations and the current sweep's threshold tables sit in LDS.
-// For symmetric, zero-diagonal F and D (subsection "Quadratic Assignment
-// Problems"; cost sum_ij F_ij D_{p_i p_j}) exchanging the locations of
-// facilities a and b changes the cost by
+// A workgroup of 16 waves owns 16 replicas, one per wave.  A wave evaluates
+// four consecutive proposals of the lexicographic pair sequence at once, one
+// per 16-lane row, each row splitting the sum over facilities k among its
+// lanes; the decisions are then taken in sequence order: the first accepted
+// proposal is applied and the ones after it (computed against the old
+// assignment) are dropped and evaluated again in the next step.  A step thus
+// commits 1 to 4 proposals with exactly the sequential result.  Flow F and
+// distance D (bytes), the 16 permutations and the sweep's threshold tables sit
+// in LDS.  For symmetric, zero-diagonal F and D (subsection "Quadratic
+// Assignment Problems"; cost sum_ij F_ij D_{p_i p_j}) exchanging the locations
+// of facilities a and b changes the cost by
 //   dC = 2 * sum_{k != a,b} (F_ak - F_bk) * (D_{p_b p_k} - D_{p_a p_k}).
-// The 4 replicas of a wave form one Philox group, so one wave-uniform
-// generator call serves all of them.
 #include <climits>
 #include <type_traits>
 
@@ -20,10 +22,11 @@ namespace nmc {
 
 namespace {
 
-constexpr int kRepPerBlock = kQapRepPerWave * 4;  // 4 waves
+constexpr int kRepPerBlock = kQapRepPerBlock;  // one replica per wave
+constexpr int kBlockThreads = 64 * kRepPerBlock;
 
-// Sum over the 16 lanes of each DPP row (= one replica's segment), returned
-// to every lane of the row: rotations by 8, 4, 2, 1 within the row.
+// Sum over the 16 lanes of each DPP row, returned to every lane of the row:
+// rotations by 8, 4, 2, 1 within the row.
 __device__ __forceinline__ int row_allreduce16(int x) {
     x += __builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false);  // row_ror:8
     x += __builtin_amdgcn_update_dpp(0, x, 0x124, 0xF, 0xF, false);  // row_ror:4
@@ -32,13 +35,25 @@ __device__ __forceinline__ int row_allreduce16(int x) {
     return x;
 }
 
-// Value of lane c (wave-uniform, < 16) of the caller's own 16-lane row.
-__device__ __forceinline__ uint32_t row_lane16(uint32_t v, int c, int sub) {
-    const uint32_t w0 = (uint32_t)__builtin_amdgcn_readlane((int)v, c);
-    const uint32_t w1 = (uint32_t)__builtin_amdgcn_readlane((int)v, 16 + c);
-    const uint32_t w2 = (uint32_t)__builtin_amdgcn_readlane((int)v, 32 + c);
-    const uint32_t w3 = (uint32_t)__builtin_amdgcn_readlane((int)v, 48 + c);
-    return sub == 0 ? w0 : sub == 1 ? w1 : sub == 2 ? w2 : w3;
+// Moves (a, b) `steps` places forward in the lexicographic pair order; past
+// the last pair it parks on (n - 2, n - 1) so that every index stays in range.
+__device__ __forceinline__ void pair_advance(int &a, int &b, int n, int steps) {
+    for (int r = 0; r < steps; ++r) {
+        if (++b == n) {
+            ++a;
+            b = a + 1;
+        }
+    }
+    if (a >= n - 1) {
+        a = n - 2;
+        b = n - 1;
+    }
+}
+
+__device__ __forceinline__ uint32_t sweep_word(uint32_t pair, uint32_t t, uint32_t group, int word, uint32_t key0,
+                                               uint32_t key1) {
+    const uint4 u4 = philox4x32_10(pair, t, group, kStreamQapSweep, key0, key1);
+    return word == 0 ? u4.x : word == 1 ? u4.y : word == 2 ? u4.z : u4.w;
 }
 
 __global__ void qap_init_kernel(QapDev I, QapRepDev R, uint32_t key0, uint32_t key1) {
@@ -97,15 +112,19 @@ __global__ void qap_reset_tallies_kernel(QapRepDev R) {
 }
 
 // n_sweeps sweeps for the 16 replicas of block `blk`, by the whole
-// 256-thread workgroup, with smem = the workgroup's dynamic LDS block.
+// 1024-thread workgroup, with smem = the workgroup's dynamic LDS block.
 // KPL = facilities handled per lane (k = q, q + 16, ...), KPL * 16 >= n; the
 // flow matrix sits in LDS with rows padded with zeros to 16 * KPL entries, so
 // padding k contribute (0 - 0) * (...) = 0 and no lane needs a bound check.
-// Each lane keeps, for its k: the location p_k, F[a][k] and D[p_a][p_k] in
-// registers, refreshed when a changes or a swap is accepted; a proposal (a, b)
-// then needs F[b][k] and D[p_b][p_k] from LDS.  The sum runs over every k and
-// is corrected by + 2 F_ab D_{p_a p_b}: with symmetric zero-diagonal matrices
-// the k = a and k = b terms are -F_ab D_{p_b p_a} and -F_ab D_{p_a p_b}.
+// Each lane keeps, for its k: the location p_k, and for its row's proposal
+// (a, b): F[a][k] and D[p_a][p_k] in registers, refreshed when the row's a
+// changes or a swap is accepted; a proposal then needs F[b][k] and
+// D[p_b][p_k] from LDS.  The sum runs over every k and is corrected by
+// + 2 F_ab D_{p_a p_b}: with symmetric zero-diagonal matrices the k = a and
+// k = b terms are -F_ab D_{p_b p_a} and -F_ab D_{p_a p_b}.
+// Random words: lane l of a batch holds the word of pair base + l (64 pairs
+// per generator call per lane); counter (pair, sweep, replica / 4, stream),
+// word replica % 4.
 template <int KPL>
 __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev &R, const QapCall &C, const int blk,
                                                 uint8_t *smem) {
@@ -113,8 +132,9 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
     const int n = I.n, nn = n * n;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
-    const int sub = lane >> 4, q = lane & 15;
+    const int row = lane >> 4, q = lane & 15;
     const int npad = (int)align_up(n, 4);
+    const int npairs = n * (n - 1) / 2;
 
     uint8_t *F = smem;                      // [n][FS]
     uint8_t *D = F + align_up((size_t)n * FS, 16);
@@ -137,12 +157,11 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
         const int rep = rbase + rl;
         P[rl * npad + f] = rep < R.n_rep ? R.perm[(size_t)rep * n + f] : (uint8_t)f;
     }
-
-    const int rl = wave * kQapRepPerWave + sub;
-    const int rep = rbase + rl;
-    const bool active = rep < R.n_rep;
-    uint8_t *pr = P + rl * npad;
-    const uint32_t group = (uint32_t)((rbase + wave * kQapRepPerWave) >> 2);
+    const int rep = rbase + wave;
+    const bool active = rep < R.n_rep;  // wave-uniform
+    uint8_t *pr = P + wave * npad;
+    const uint32_t group = (uint32_t)rep >> 2;
+    const int word = rep & 3;
 
     long long cost = 0, best = 0;
     int fh = -1;
@@ -163,96 +182,121 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
             tl[i] = tg[i];
         __syncthreads();
 
-#pragma unroll
-        for (int i = 0; i < KPL; ++i) {
-            const int k = q + 16 * i;
-            pk[i] = k < n ? pr[k] : 0;
-        }
-        uint32_t qidx = 0;
-        uint32_t uword = 0;  // this lane's Philox word for pair (qidx & ~15) + q
-        for (int a = 0; a < n - 1; ++a) {
-            const int ca = cls[a];
-            int pa = pr[a];
-            const uint8_t *frow_a = F + a * FS + q;
+        if (active) {
 #pragma unroll
             for (int i = 0; i < KPL; ++i) {
-                fa[i] = frow_a[16 * i];
-                da[i] = D[pa * n + pk[i]];
+                const int k = q + 16 * i;
+                pk[i] = k < n ? pr[k] : 0;
             }
-            int pb_next = pr[a + 1];
-            for (int b = a + 1; b < n; ++b, ++qidx) {
-                if ((qidx & 15u) == 0) {
-                    const uint4 u4 = philox4x32_10(qidx + (uint32_t)q, t, group, kStreamQapSweep, C.key0, C.key1);
-                    uword = sub == 0 ? u4.x : sub == 1 ? u4.y : sub == 2 ? u4.z : u4.w;
+            // this row's proposal is pair p0 + row
+            int p0 = 0, ar = 0, br = 1;
+            pair_advance(ar, br, n, row);
+            int cur_a = -1, pa = 0;
+            bool refresh = false;  // a swap was applied: D[p_a][p_k] is stale
+            uint32_t pbase = 0;
+            uint32_t uw = sweep_word((uint32_t)lane, t, group, word, C.key0, C.key1);
+            uint32_t uw2 = sweep_word(64u + (uint32_t)lane, t, group, word, C.key0, C.key1);
+            while (p0 < npairs) {
+                if (ar != cur_a) {
+                    cur_a = ar;
+                    pa = pr[ar];
+                    const uint8_t *frow_a = F + ar * FS + q;
+#pragma unroll
+                    for (int i = 0; i < KPL; ++i)
+                        fa[i] = frow_a[16 * i];
+                    refresh = true;
                 }
-                // a swap at (a, b) changes p_a and p_b only, so p_{b+1} read
-                // now stays valid for the next proposal
-                const int pb = pb_next;
-                if (b + 1 < n)
-                    pb_next = pr[b + 1];
-                const uint8_t *frow_b = F + b * FS + q;
+                if (refresh) {
+#pragma unroll
+                    for (int i = 0; i < KPL; ++i)
+                        da[i] = D[pa * n + pk[i]];
+                    refresh = false;
+                }
+                const int pb = pr[br];
+                const uint8_t *frow_b = F + br * FS + q;
                 const uint8_t *drow_b = D + pb * n;
                 int part = 0;
 #pragma unroll
                 for (int i = 0; i < KPL; ++i)
                     part += (fa[i] - (int)frow_b[16 * i]) * ((int)drow_b[pk[i]] - da[i]);
                 if (q == 0)
-                    part += 2 * (int)F[a * FS + b] * (int)D[pa * n + pb];
-                part = row_allreduce16(part);
-                const int dc = 2 * part;
-                const uint32_t u = row_lane16(uword, (int)(qidx & 15u), sub);
-                bool accept = dc <= 0;
-                if (!accept) {
-                    const int cl = max(ca, (int)cls[b]);
+                    part += 2 * (int)F[ar * FS + br] * (int)D[pa * n + pb];
+                const int dc = 2 * row_allreduce16(part);
+
+                const int pi = p0 + row;
+                const int src = pi - (int)pbase;  // 0 .. 66
+                const int sl = (src & 63) << 2;
+                const uint32_t ua = (uint32_t)__builtin_amdgcn_ds_bpermute(sl, (int)uw);
+                const uint32_t ub = (uint32_t)__builtin_amdgcn_ds_bpermute(sl, (int)uw2);
+                const uint32_t u = src < 64 ? ua : ub;
+                bool acc = dc <= 0;
+                if (!acc) {
+                    const int cl = max((int)cls[ar], (int)cls[br]);
                     const uint32_t *T = tl + cl * C.stride;
                     const int h = dc >> kQapLowBits, l = dc & ((1 << kQapLowBits) - 1);
-                    const uint32_t thr =
-                        h < I.ha ? (uint32_t)(((uint64_t)T[h] * (uint64_t)T[I.ha + l]) >> 32) : 0u;
-                    accept = u < thr;
+                    const uint32_t thr = h < I.ha ? (uint32_t)(((uint64_t)T[h] * (uint64_t)T[I.ha + l]) >> 32) : 0u;
+                    acc = u < thr;
                 }
-                accept = accept && active;
-                if (accept) {
-                    const int pa_old = pa;
-                    if (q == 0) {
-                        pr[a] = (uint8_t)pb;
-                        pr[b] = (uint8_t)pa_old;
+                acc = acc && pi < npairs;
+                const uint64_t m = __ballot(acc);
+                const uint32_t rows = (uint32_t)((m & 1u) | ((m >> 15) & 2u) | ((m >> 30) & 4u) | ((m >> 45) & 8u));
+                int adv = 4;
+                if (rows) {
+                    const int j = __builtin_ctz(rows);
+                    adv = j + 1;
+                    const int jl = 16 * j;
+                    const int aj = __builtin_amdgcn_readlane(ar, jl);
+                    const int bj = __builtin_amdgcn_readlane(br, jl);
+                    const int paj = __builtin_amdgcn_readlane(pa, jl);
+                    const int pbj = __builtin_amdgcn_readlane(pb, jl);
+                    cost += __builtin_amdgcn_readlane(dc, jl);
+                    if (lane == 0) {
+                        pr[aj] = (uint8_t)pbj;
+                        pr[bj] = (uint8_t)paj;
                     }
-                    cost += dc;
-                    pa = pb;
-                    // only the lanes holding k = a and k = b see new locations
-                    // (register index a / 16 and b / 16 are wave-uniform)
+                    // only the lanes holding k = aj and k = bj see new
+                    // locations (register index k / 16 is wave-uniform)
 #pragma unroll
                     for (int i = 0; i < KPL; ++i) {
-                        if (i == (a >> 4) && q == (a & 15))
-                            pk[i] = pb;
-                        if (i == (b >> 4) && q == (b & 15))
-                            pk[i] = pa_old;
-                        da[i] = D[pa * n + pk[i]];
+                        if (i == (aj >> 4) && q == (aj & 15))
+                            pk[i] = pbj;
+                        if (i == (bj >> 4) && q == (bj & 15))
+                            pk[i] = paj;
                     }
+                    if (ar == aj)
+                        pa = pbj;
+                    else if (ar == bj)
+                        pa = paj;
+                    refresh = true;
+                }
+                p0 += adv;
+                pair_advance(ar, br, n, adv);
+                if (p0 >= (int)pbase + 64) {
+                    pbase += 64;
+                    uw = uw2;
+                    uw2 = sweep_word(pbase + 64u + (uint32_t)lane, t, group, word, C.key0, C.key1);
                 }
             }
-        }
-        // sweep end
-        bool imp = false;
-        if (active) {
+            // sweep end
+            bool imp = false;
             if (cost < best) {
                 best = cost;
                 imp = true;
             }
             if (fh < 0 && cost <= C.target)
                 fh = (int)(t + 1);
-        }
-        if (imp) {
-            for (int f = q; f < n; f += kQapLanesPerRep)
-                R.best_perm[(size_t)rep * n + f] = pr[f];
+            if (imp) {
+                for (int f = lane; f < n; f += 64)
+                    R.best_perm[(size_t)rep * n + f] = pr[f];
+            }
         }
         __syncthreads();
     }
 
     if (active) {
-        for (int f = q; f < n; f += kQapLanesPerRep)
+        for (int f = lane; f < n; f += 64)
             R.perm[(size_t)rep * n + f] = pr[f];
-        if (q == 0) {
+        if (lane == 0) {
             R.cost[rep] = cost;
             R.best[rep] = best;
             R.first_hit[rep] = fh;
@@ -274,13 +318,13 @@ __device__ __forceinline__ void qap_dispatch_kpl(int n, Fn &&fn) {
         fn(std::integral_constant<int, 16>{});
 }
 
-__global__ void __launch_bounds__(256) qap_sweep_kernel(QapDev I, QapRepDev R, QapCall C) {
+__global__ void __launch_bounds__(1024) qap_sweep_kernel(QapDev I, QapRepDev R, QapCall C) {
     extern __shared__ __align__(16) uint8_t smem[];
     qap_dispatch_kpl(I.n, [&](auto kpl) { qap_sweep_block<decltype(kpl)::value>(I, R, C, blockIdx.x, smem); });
 }
 
 // Batched launch over (job, block of 16 replicas) items in decreasing cost.
-__global__ void __launch_bounds__(256) qap_sweep_batch_kernel(const QapJob *jobs, const int2 *items, int n_items) {
+__global__ void __launch_bounds__(1024) qap_sweep_batch_kernel(const QapJob *jobs, const int2 *items, int n_items) {
     extern __shared__ __align__(16) uint8_t smem[];
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int2 w = items[it];
@@ -394,7 +438,7 @@ hipError_t qap_launch_sweep(const QapDev &I, const QapRepDev &R, const QapCall &
         attr = true;
     }
     const int blocks = (R.n_rep + kRepPerBlock - 1) / kRepPerBlock;
-    hipLaunchKernelGGL(qap_sweep_kernel, dim3(blocks), dim3(256), lds, s, I, R, C);
+    hipLaunchKernelGGL(qap_sweep_kernel, dim3(blocks), dim3(kBlockThreads), lds, s, I, R, C);
     return hipGetLastError();
 }
 
@@ -408,13 +452,14 @@ hipError_t qap_launch_sweep_batch(const QapJob *jobs, const int2 *items, int n_i
             return ea;
         attr = true;
     }
-    hipLaunchKernelGGL(qap_sweep_batch_kernel, dim3(grid), dim3(256), lds, s, jobs, items, n_items);
+    hipLaunchKernelGGL(qap_sweep_batch_kernel, dim3(grid), dim3(kBlockThreads), lds, s, jobs, items, n_items);
     return hipGetLastError();
 }
 
 int qap_batch_occupancy(size_t lds) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)qap_sweep_batch_kernel, 256, lds) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)qap_sweep_batch_kernel, kBlockThreads, lds) !=
+        hipSuccess)
         return 1;
     return nb < 1 ? 1 : nb;
 }
