@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -13,6 +14,7 @@
 #include <new>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/nmc.h"
@@ -40,6 +42,17 @@ int ok() {
 }
 
 }  // namespace
+
+// Proposals per step of the QAP sweep: 0 = chosen per sweep by the kernel;
+// NMC_QAP_ROWS=1, 4 or 8 pins it (for measurements; results do not change).
+static int32_t qap_rows_setting() {
+    static const int32_t rows = [] {
+        const char *e = std::getenv("NMC_QAP_ROWS");
+        const int v = e ? std::atoi(e) : 0;
+        return (int32_t)(v == 1 || v == 4 || v == 8 ? v : 0);
+    }();
+    return rows;
+}
 
 int nmc::set_last_error(int code, const char *msg) {
     g_err = msg ? msg : "";
@@ -169,6 +182,44 @@ struct ChunkRec {
     uint32_t neg;
 };
 
+// Bank model of one byte gather on gfx950 LDS: 32 banks of 4 bytes, a wave's
+// 64 addresses served in two half-waves of 32; lanes reading the same dword
+// share one access, different dwords on one bank serialize.  Cost of a
+// half-wave = the largest number of distinct dwords on one bank.
+struct BankLoad {
+    int32_t dw[32][8];
+    int8_t cnt[32];
+    int8_t mx;
+    void clear() {
+        std::memset(cnt, 0, sizeof cnt);
+        mx = 0;
+    }
+    // distinct-dword count of the bank after adding dword d (no change)
+    int after(int32_t d) const {
+        const int b = d & 31;
+        for (int i = 0; i < cnt[b] && i < 8; ++i)
+            if (dw[b][i] == d)
+                return cnt[b];
+        return cnt[b] + 1;
+    }
+    void add(int32_t d) {
+        const int b = d & 31;
+        for (int i = 0; i < cnt[b] && i < 8; ++i)
+            if (dw[b][i] == d)
+                return;
+        if (cnt[b] < 8)
+            dw[b][(int)cnt[b]] = d;
+        cnt[b]++;
+        mx = std::max<int8_t>(mx, cnt[b]);
+    }
+};
+
+// Places every lane's records into slots (and orders each record's three
+// addresses) so that each slot's three gathers touch few distinct dwords per
+// bank in each half-wave.  Greedy per slot: lanes take, in turn, the record
+// and address order that raises the half-wave's worst bank least, then loads
+// the fewest-used banks; the most loaded lanes go first.  Any placement gives
+// the same results; only the gathers' bank conflicts change.
 void schedule_chunk(std::vector<std::vector<ChunkRec>> &lanes, int32_t nslot, bool optimize,
                     std::vector<ChunkRec> &out /* [nslot][64] */, const ChunkRec &dummy) {
     static const int perms[6][3] = {{0, 1, 2}, {1, 2, 0}, {2, 0, 1}, {0, 2, 1}, {1, 0, 2}, {2, 1, 0}};
@@ -180,12 +231,16 @@ void schedule_chunk(std::vector<std::vector<ChunkRec>> &lanes, int32_t nslot, bo
         return;
     }
     std::vector<int> order(kChunk);
+    BankLoad load[3][2];
     for (int32_t s = 0; s < nslot; ++s) {
-        int32_t owner[3][2][32];
         for (int j = 0; j < 3; ++j)
             for (int h = 0; h < 2; ++h)
-                for (int b = 0; b < 32; ++b)
-                    owner[j][h][b] = -1;
+                load[j][h].clear();
+        // lanes without records read the inert dummy in this slot
+        for (int l = 0; l < kChunk; ++l)
+            if (lanes[l].empty())
+                for (int j = 0; j < 3; ++j)
+                    load[j][l / 32].add((int32_t)(dummy.a[j] >> 2));
         std::iota(order.begin(), order.end(), 0);
         std::stable_sort(order.begin(), order.end(),
                          [&](int x, int y) { return lanes[x].size() > lanes[y].size(); });
@@ -194,14 +249,15 @@ void schedule_chunk(std::vector<std::vector<ChunkRec>> &lanes, int32_t nslot, bo
             if (rem.empty())
                 continue;
             const int h = l / 32;
+            // cost: 64 per gather whose worst bank grows, plus the distinct
+            // dwords already on the banks this record's addresses join
             int best_i = 0, best_p = 0, best_c = 1 << 30;
             for (size_t i = 0; i < rem.size() && best_c > 0; ++i)
                 for (int p = 0; p < 6 && best_c > 0; ++p) {
                     int c = 0;
                     for (int j = 0; j < 3; ++j) {
-                        const int32_t d = (int32_t)(rem[i].a[perms[p][j]] >> 2);
-                        const int32_t o = owner[j][h][d & 31];
-                        c += (o >= 0 && o != d);
+                        const int a = load[j][h].after((int32_t)(rem[i].a[perms[p][j]] >> 2));
+                        c += (a > load[j][h].mx ? 64 : 0) + (a - 1);
                     }
                     if (c < best_c) {
                         best_c = c;
@@ -213,15 +269,29 @@ void schedule_chunk(std::vector<std::vector<ChunkRec>> &lanes, int32_t nslot, bo
             ChunkRec placed = r;
             for (int j = 0; j < 3; ++j) {
                 placed.a[j] = r.a[perms[best_p][j]];
-                const int32_t d = (int32_t)(placed.a[j] >> 2);
-                if (owner[j][h][d & 31] < 0)
-                    owner[j][h][d & 31] = d;
+                load[j][h].add((int32_t)(placed.a[j] >> 2));
             }
             out[(size_t)s * kChunk + l] = placed;
             rem[best_i] = rem.back();
             rem.pop_back();
         }
     }
+}
+
+// Modeled LDS cycles of a chunk's gathers (sum over slots, positions and
+// half-waves of the worst bank's distinct dwords).
+int64_t chunk_gather_cycles(const std::vector<ChunkRec> &placed, int32_t nslot) {
+    int64_t cyc = 0;
+    BankLoad bl;
+    for (int32_t s = 0; s < nslot; ++s)
+        for (int j = 0; j < 3; ++j)
+            for (int h = 0; h < 2; ++h) {
+                bl.clear();
+                for (int l = h * 32; l < h * 32 + 32; ++l)
+                    bl.add((int32_t)(placed[(size_t)s * kChunk + l].a[j] >> 2));
+                cyc += bl.mx;
+            }
+    return cyc;
 }
 
 }  // namespace
@@ -322,10 +392,21 @@ int nmc_ksat_load(int32_t n_vars, int32_t n_clauses, const int32_t *clause_ptr, 
         };
         const char *sched_env = std::getenv("NMC_KSAT_BANK_SCHEDULE");
         const bool bank_schedule = !(sched_env && sched_env[0] == '0');
+        const bool debug_banks = std::getenv("NMC_DEBUG_BANKS") != nullptr;
+        int64_t model_cycles = 0, model_gathers = 0;
         std::vector<int32_t> chunk_var, color_chunk(ncol + 1, 0);
         std::vector<int2> chunk_info;
         std::vector<uint64_t> rec;
         int32_t slot_rows = 0;
+        // (1) every chunk's lanes and records, (2) placement (chunks are
+        // independent: spread over host threads for large instances), (3) the
+        // packed record image in chunk order
+        struct ChunkWork {
+            std::vector<std::vector<ChunkRec>> lanes;
+            int32_t nslot = 0;
+            std::vector<ChunkRec> placed;
+        };
+        std::vector<ChunkWork> work;
         for (int32_t c = 0; c < ncol; ++c) {
             std::vector<int32_t> vs(I->order.begin() + I->color_ptr[c], I->order.begin() + I->color_ptr[c + 1]);
             std::stable_sort(vs.begin(), vs.end(), [&](int32_t x, int32_t y) {
@@ -338,7 +419,10 @@ int nmc_ksat_load(int32_t n_vars, int32_t n_clauses, const int32_t *clause_ptr, 
                     nslot = std::max(nslot, vptr[vs[i] + 1] - vptr[vs[i]]);
                 nslot = std::max<int32_t>(kSlotUnroll, (int32_t)align_up(nslot, kSlotUnroll));  // padding slots are inert
                 chunk_info.push_back(make_int2(slot_rows, nslot));
-                std::vector<std::vector<ChunkRec>> lanes(kChunk);
+                slot_rows += nslot;
+                ChunkWork w;
+                w.lanes.resize(kChunk);
+                w.nslot = nslot;
                 int32_t n1[kChunk] = {0};
                 for (size_t i = b; i < e; ++i) {
                     const int lane = (int)(i - b);
@@ -351,23 +435,10 @@ int nmc_ksat_load(int32_t n_vars, int32_t n_clauses, const int32_t *clause_ptr, 
                             if (p != own)
                                 r.a[k++] = lit_addr(lits[p]);
                         n1[lane] += (int32_t)r.neg;
-                        lanes[lane].push_back(r);
+                        w.lanes[lane].push_back(r);
                     }
                 }
-                std::vector<ChunkRec> placed;
-                schedule_chunk(lanes, nslot, bank_schedule, placed, ChunkRec{{ONES, ZERO, ZERO}, 0u});
-                const size_t base = rec.size();
-                rec.resize(base + (size_t)nslot * kChunk);
-                // slots are stored in pairs: [slot / 2][lane][slot % 2], so one
-                // 16-byte load gives a lane two consecutive slots
-                for (int32_t sl = 0; sl < nslot; ++sl)
-                    for (int lane = 0; lane < kChunk; ++lane) {
-                        const ChunkRec &r = placed[(size_t)sl * kChunk + lane];
-                        rec[base + (size_t)(sl / 2) * 2 * kChunk + (size_t)lane * 2 + (sl & 1)] =
-                            (uint64_t)r.a[0] | ((uint64_t)r.a[1] << kAddrBits) |
-                            ((uint64_t)r.a[2] << (2 * kAddrBits)) | ((uint64_t)r.neg << (3 * kAddrBits));
-                    }
-                slot_rows += nslot;
+                work.push_back(std::move(w));
                 // lane word: variable in bits 0..19 and its count of clauses
                 // holding it negated in bits 20..27; -1 = empty lane
                 for (int lane = 0; lane < kChunk; ++lane)
@@ -375,7 +446,46 @@ int nmc_ksat_load(int32_t n_vars, int32_t n_clauses, const int32_t *clause_ptr, 
             }
             color_chunk[c + 1] = (int32_t)chunk_info.size();
         }
+        {
+            const ChunkRec dummy{{ONES, ZERO, ZERO}, 0u};
+            std::atomic<size_t> next{0};
+            auto worker = [&] {
+                for (size_t i; (i = next.fetch_add(1)) < work.size();)
+                    schedule_chunk(work[i].lanes, work[i].nslot, bank_schedule, work[i].placed, dummy);
+            };
+            const size_t n_rec = vcl.size();
+            const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+            const unsigned nt = bank_schedule && n_rec >= 200000 ? std::min(8u, hw) : 1u;
+            std::vector<std::thread> pool;
+            for (unsigned t = 1; t < nt; ++t)
+                pool.emplace_back(worker);
+            worker();
+            for (auto &t : pool)
+                t.join();
+        }
+        rec.resize((size_t)slot_rows * kChunk);
+        for (size_t i = 0; i < work.size(); ++i) {
+            const int32_t nslot = work[i].nslot;
+            const std::vector<ChunkRec> &placed = work[i].placed;
+            if (debug_banks) {
+                model_cycles += chunk_gather_cycles(placed, nslot);
+                model_gathers += 3 * (int64_t)nslot;
+            }
+            const size_t base = (size_t)chunk_info[i].x * kChunk;
+            // slots are stored in pairs: [slot / 2][lane][slot % 2], so one
+            // 16-byte load gives a lane two consecutive slots
+            for (int32_t sl = 0; sl < nslot; ++sl)
+                for (int lane = 0; lane < kChunk; ++lane) {
+                    const ChunkRec &r = placed[(size_t)sl * kChunk + lane];
+                    rec[base + (size_t)(sl / 2) * 2 * kChunk + (size_t)lane * 2 + (sl & 1)] =
+                        (uint64_t)r.a[0] | ((uint64_t)r.a[1] << kAddrBits) | ((uint64_t)r.a[2] << (2 * kAddrBits)) |
+                        ((uint64_t)r.neg << (3 * kAddrBits));
+                }
+        }
         I->n_chunks = (int32_t)chunk_info.size();
+        if (debug_banks && model_gathers)
+            std::fprintf(stderr, "nmc: %d chunks, %lld slot gathers, modeled %.3f LDS cycles per gather\n",
+                         I->n_chunks, (long long)model_gathers, (double)model_cycles / (double)model_gathers);
 
         std::vector<uint32_t> clause_addr((size_t)m * 4, ZERO);
         for (int32_t a = 0; a < m; ++a) {
@@ -813,6 +923,7 @@ static int anneal_impl(nmc_replicas *P, const double *beta, int32_t n_classes, i
         C.t0 = P->sweeps_done;
         C.target = target;
         C.check_start = 1;
+        C.rows = qap_rows_setting();
         C.key0 = (uint32_t)P->seed;
         C.key1 = (uint32_t)(P->seed >> 32);
         HIP_OR_FAIL(qap_launch_sweep(I->qap_dev(), P->q, C, 256, s));
@@ -1264,6 +1375,7 @@ int build_batch(nmc_batch *B, const std::vector<PhaseSpec> &phases, bool with_ba
                 J.C.t0 = P->sweeps_done + offset_sweeps;
                 J.C.target = targets ? targets[qidx[j]] : -1;
                 J.C.check_start = 1;
+                J.C.rows = qap_rows_setting();
                 J.C.key0 = (uint32_t)P->seed;
                 J.C.key1 = (uint32_t)(P->seed >> 32);
                 std::memcpy(blob.host.data() + bp.off_qjobs + j * sizeof(QapJob), &J, sizeof J);
@@ -1945,6 +2057,7 @@ extern "C" int nmc_batch_step(nmc_batch *B, const nmc_segment *segs, int32_t n_s
                     J.C.t0 = P->sweeps_done;
                     J.C.target = g.target;
                     J.C.check_start = 1;
+                    J.C.rows = qap_rows_setting();
                     J.C.key0 = (uint32_t)P->seed;
                     J.C.key1 = (uint32_t)(P->seed >> 32);
                     const double nd = P->inst->n;

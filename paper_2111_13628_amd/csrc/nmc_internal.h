@@ -101,6 +101,7 @@ struct QapCall {
     int64_t target;
     int32_t check_start;
     uint32_t key0, key1;
+    int32_t rows;          // proposals evaluated per step: 0 = chosen per sweep, else 1, 4 or 8
 };
 
 // One replica set of a batched launch.

@@ -35,6 +35,15 @@ __device__ __forceinline__ int row_allreduce16(int x) {
     return x;
 }
 
+// Sum over each group of 8 lanes, returned to every lane of the group:
+// swaps within quads (xor 1, xor 2), then the mirror within each half-row.
+__device__ __forceinline__ int group_allreduce8(int x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    x += __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    x += __builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    return x;
+}
+
 // Moves (a, b) `steps` places forward in the lexicographic pair order; past
 // the last pair it parks on (n - 2, n - 1) so that every index stays in range.
 __device__ __forceinline__ void pair_advance(int &a, int &b, int n, int steps) {
@@ -111,32 +120,194 @@ __global__ void qap_reset_tallies_kernel(QapRepDev R) {
     }
 }
 
-// n_sweeps sweeps for the 16 replicas of block `blk`, by the whole
-// 1024-thread workgroup, with smem = the workgroup's dynamic LDS block.
-// KPL = facilities handled per lane (k = q, q + 16, ...), KPL * 16 >= n; the
-// flow matrix sits in LDS with rows padded with zeros to 16 * KPL entries, so
-// padding k contribute (0 - 0) * (...) = 0 and no lane needs a bound check.
-// Each lane keeps, for its k: the location p_k, and for its row's proposal
-// (a, b): F[a][k] and D[p_a][p_k] in registers, refreshed when the row's a
-// changes or a swap is accepted; a proposal then needs F[b][k] and
-// D[p_b][p_k] from LDS.  The sum runs over every k and is corrected by
-// + 2 F_ab D_{p_a p_b}: with symmetric zero-diagonal matrices the k = a and
-// k = b terms are -F_ab D_{p_b p_a} and -F_ab D_{p_a p_b}.
+// Flow matrix layout in LDS: row b holds F[b][k] at byte (k % 16) * KP + k / 16
+// (zero for k >= n), so the KP bytes a lane of a 16-lane row needs
+// (k = q, q + 16, ...) are contiguous and come in one wide read.  Fills
+// f[i] = F[row][k_i] for the lane's k_i = q + (64 / ROWS) * i.
+template <int ROWS, int KPL, int KP>
+__device__ __forceinline__ void flow_row(const uint8_t *row, int q, int (&f)[KPL]) {
+    if constexpr (ROWS == 4) {
+        uint32_t w[KP / 4];
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(row + q * KP);
+#pragma unroll
+        for (int j = 0; j < KP / 4; ++j)
+            w[j] = src[j];
+#pragma unroll
+        for (int i = 0; i < KPL; ++i)
+            f[i] = (int)((w[i >> 2] >> (8 * (i & 3))) & 0xFFu);
+    } else {
+#pragma unroll
+        for (int i = 0; i < KPL; ++i) {
+            const int k = q + (64 / ROWS) * i;
+            f[i] = row[(k & 15) * KP + (k >> 4)];
+        }
+    }
+}
+
+// One sweep of one replica by one wave.  ROWS proposals are evaluated per
+// step, one per row of LANES = 64 / ROWS lanes; KPL = facilities per lane
+// (k = q, q + LANES, ...), LANES * KPL <= 16 * KP, the flow row length (rows
+// of F padded with zeros, so padding k contribute (0 - 0) * (...) = 0 and no
+// lane needs a bound check).  Each lane keeps, for its k: the location p_k,
+// and for its row's proposal (a, b): F[a][k] and D[p_a][p_k] in registers,
+// refreshed when the row's a changes or a swap is applied; a proposal then
+// needs F[b][k] and D[p_b][p_k] from LDS.  The sum runs over every k and is
+// corrected by + 2 F_ab D_{p_a p_b}: with symmetric zero-diagonal matrices the
+// k = a and k = b terms are -F_ab D_{p_b p_a} and -F_ab D_{p_a p_b}.
+// The decisions are taken in pair order: the first accepted proposal is
+// applied and the ones after it are evaluated again in the next step.
 // Random words: lane l of a batch holds the word of pair base + l (64 pairs
 // per generator call per lane); counter (pair, sweep, replica / 4, stream),
-// word replica % 4.
-template <int KPL>
+// word replica % 4.  Returns the number of accepted swaps.
+template <int ROWS, int KPL, int KP>
+__device__ __forceinline__ int qap_wave_sweep(const QapDev &I, const QapCall &C, const uint8_t *F, const uint8_t *D,
+                                              const uint8_t *cls, const uint32_t *tl, uint8_t *pr, uint32_t t,
+                                              uint32_t group, int word, long long &cost) {
+    constexpr int LANES = 64 / ROWS;
+    constexpr int RB = 16 * KP;  // bytes per flow row
+    static_assert(ROWS == 1 || ROWS == 8 || (ROWS == 4 && KPL <= KP), "flow layout");
+    const int n = I.n;
+    const int npairs = n * (n - 1) / 2;
+    const int lane = threadIdx.x & 63;
+    const int row = lane / LANES, q = lane % LANES;
+    const bool one_class = C.n_classes == 1;
+    int pk[KPL], fa[KPL], da[KPL];
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) {
+        const int k = q + LANES * i;
+        pk[i] = k < n ? pr[k] : 0;
+    }
+    // this row's proposal is pair p0 + row
+    int p0 = 0, ar = 0, br = 1;
+    pair_advance(ar, br, n, row);
+    int cur_a = -1, pa = 0, n_acc = 0;
+    bool refresh = false;  // a swap was applied: D[p_a][p_k] is stale
+    uint32_t pbase = 0;
+    uint32_t uw = sweep_word((uint32_t)lane, t, group, word, C.key0, C.key1);
+    uint32_t uw2 = sweep_word(64u + (uint32_t)lane, t, group, word, C.key0, C.key1);
+    while (p0 < npairs) {
+        if (ar != cur_a) {
+            cur_a = ar;
+            pa = pr[ar];
+            flow_row<ROWS, KPL, KP>(F + ar * RB, q, fa);
+            refresh = true;
+        }
+        if (refresh) {
+#pragma unroll
+            for (int i = 0; i < KPL; ++i)
+                da[i] = D[pa * n + pk[i]];
+            refresh = false;
+        }
+        const int pb = pr[br];
+        int fb[KPL];
+        flow_row<ROWS, KPL, KP>(F + br * RB, q, fb);
+        const uint8_t *drow_b = D + pb * n;
+        int part = 0;
+#pragma unroll
+        for (int i = 0; i < KPL; ++i)
+            part += (fa[i] - fb[i]) * ((int)drow_b[pk[i]] - da[i]);
+        if (q == 0)
+            part += 2 * (int)F[ar * RB + (br & 15) * KP + (br >> 4)] * (int)D[pa * n + pb];
+        if constexpr (ROWS == 8)
+            part = group_allreduce8(part);
+        else
+            part = row_allreduce16(part);
+        int dc;
+        uint32_t u;
+        if constexpr (ROWS == 1) {
+            dc = 2 * (__builtin_amdgcn_readlane(part, 0) + __builtin_amdgcn_readlane(part, 16) +
+                      __builtin_amdgcn_readlane(part, 32) + __builtin_amdgcn_readlane(part, 48));
+            const int src = p0 - (int)pbase;  // 0 .. 63
+            u = (uint32_t)__builtin_amdgcn_readlane((int)uw, src);
+        } else {
+            dc = 2 * part;
+            const int src = p0 + row - (int)pbase;  // 0 .. 63 + ROWS - 1
+            const int sl = (src & 63) << 2;
+            const uint32_t ua = (uint32_t)__builtin_amdgcn_ds_bpermute(sl, (int)uw);
+            const uint32_t ub = (uint32_t)__builtin_amdgcn_ds_bpermute(sl, (int)uw2);
+            u = src < 64 ? ua : ub;
+        }
+        bool acc = dc <= 0;
+        if (!acc) {
+            const int cl = one_class ? 0 : max((int)cls[ar], (int)cls[br]);
+            const uint32_t *T = tl + cl * C.stride;
+            const int h = dc >> kQapLowBits, l = dc & ((1 << kQapLowBits) - 1);
+            const uint32_t thr = h < I.ha ? (uint32_t)(((uint64_t)T[h] * (uint64_t)T[I.ha + l]) >> 32) : 0u;
+            acc = u < thr;
+        }
+        int adv = ROWS, j = -1;
+        if constexpr (ROWS == 1) {
+            if (acc)
+                j = 0;
+        } else {
+            acc = acc && p0 + row < npairs;
+            const uint64_t m = __ballot(acc);
+            uint32_t rows = 0;
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r)
+                rows |= (uint32_t)((m >> (LANES * r)) & 1u) << r;
+            if (rows)
+                j = __builtin_ctz(rows);
+        }
+        if (j >= 0) {
+            adv = j + 1;
+            ++n_acc;
+            const int jl = LANES * j;
+            const int aj = __builtin_amdgcn_readlane(ar, jl);
+            const int bj = __builtin_amdgcn_readlane(br, jl);
+            const int paj = __builtin_amdgcn_readlane(pa, jl);
+            const int pbj = __builtin_amdgcn_readlane(pb, jl);
+            cost += __builtin_amdgcn_readlane(dc, jl);
+            if (lane == 0) {
+                pr[aj] = (uint8_t)pbj;
+                pr[bj] = (uint8_t)paj;
+            }
+            // only the lanes holding k = aj and k = bj see new locations
+            // (register index k / LANES is wave-uniform)
+#pragma unroll
+            for (int i = 0; i < KPL; ++i) {
+                if (i == aj / LANES && q == aj % LANES)
+                    pk[i] = pbj;
+                if (i == bj / LANES && q == bj % LANES)
+                    pk[i] = paj;
+            }
+            if (ar == aj)
+                pa = pbj;
+            else if (ar == bj)
+                pa = paj;
+            refresh = true;
+        }
+        p0 += adv;
+        pair_advance(ar, br, n, adv);
+        if (p0 >= (int)pbase + 64) {
+            pbase += 64;
+            uw = uw2;
+            uw2 = sweep_word(pbase + 64u + (uint32_t)lane, t, group, word, C.key0, C.key1);
+        }
+    }
+    return n_acc;
+}
+
+// n_sweeps sweeps for the 16 replicas of block `blk`, by the whole
+// 1024-thread workgroup, with smem = the workgroup's dynamic LDS block.  Each
+// wave picks, per sweep, four proposals per step (16 lanes each) when few
+// proposals were accepted in its previous sweep, else one (64 lanes): with
+// many acceptances most of the four would be dropped.  The choice changes
+// only the speed, never the result.
+template <int KPL4, int KPL1, int KPL8>
 __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev &R, const QapCall &C, const int blk,
                                                 uint8_t *smem) {
-    constexpr int FS = 16 * KPL;  // padded flow row
+    constexpr int KP = KPL4 <= 4 ? 4 : KPL4 <= 8 ? 8 : 16;  // flow bytes per lane of a 16-lane row
+    constexpr int FS = 16 * KP;                            // flow row bytes
+    static_assert(64 * KPL1 <= FS, "flow row too short for one proposal per step");
+    static_assert(8 * KPL8 <= FS, "flow row too short for eight proposals per step");
     const int n = I.n, nn = n * n;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
-    const int row = lane >> 4, q = lane & 15;
     const int npad = (int)align_up(n, 4);
     const int npairs = n * (n - 1) / 2;
 
-    uint8_t *F = smem;                      // [n][FS]
+    uint8_t *F = smem;  // [n][FS]
     uint8_t *D = F + align_up((size_t)n * FS, 16);
     uint8_t *P = D + align_up(nn, 16);
     uint8_t *cls = P + kRepPerBlock * npad;
@@ -144,7 +315,8 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
     const int tab_words = C.n_classes * C.stride;
 
     for (int i = tid; i < n * FS; i += blockDim.x) {
-        const int r = i / FS, k = i % FS;
+        const int r = i / FS, o = i % FS;
+        const int k = (o % KP) * 16 + o / KP;  // inverse of (k % 16) * KP + k / 16
         F[i] = k < n ? I.F[r * n + k] : 0;
     }
     for (int i = tid; i < nn; i += blockDim.x)
@@ -174,7 +346,10 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
     }
     __syncthreads();
 
-    int pk[KPL], fa[KPL], da[KPL];
+    // proposals per step: 8 (when the size allows), 4 or 1
+    int rows = C.rows != 0 ? C.rows : 4;
+    if (rows == 8 && KPL8 == 0)
+        rows = 4;
     for (int s = 0; s < C.n_sweeps; ++s) {
         const uint32_t t = C.t0 + (uint32_t)s;
         const uint32_t *tg = C.tab + (size_t)s * C.sweep_words;
@@ -183,99 +358,21 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
         __syncthreads();
 
         if (active) {
-#pragma unroll
-            for (int i = 0; i < KPL; ++i) {
-                const int k = q + 16 * i;
-                pk[i] = k < n ? pr[k] : 0;
+            int n_acc;
+            if constexpr (KPL8 > 0) {
+                if (rows == 8)
+                    n_acc = qap_wave_sweep<8, KPL8, KP>(I, C, F, D, cls, tl, pr, t, group, word, cost);
+                else
+                    n_acc = rows == 4 ? qap_wave_sweep<4, KPL4, KP>(I, C, F, D, cls, tl, pr, t, group, word, cost)
+                                      : qap_wave_sweep<1, KPL1, KP>(I, C, F, D, cls, tl, pr, t, group, word, cost);
+            } else {
+                n_acc = rows == 4 ? qap_wave_sweep<4, KPL4, KP>(I, C, F, D, cls, tl, pr, t, group, word, cost)
+                                  : qap_wave_sweep<1, KPL1, KP>(I, C, F, D, cls, tl, pr, t, group, word, cost);
             }
-            // this row's proposal is pair p0 + row
-            int p0 = 0, ar = 0, br = 1;
-            pair_advance(ar, br, n, row);
-            int cur_a = -1, pa = 0;
-            bool refresh = false;  // a swap was applied: D[p_a][p_k] is stale
-            uint32_t pbase = 0;
-            uint32_t uw = sweep_word((uint32_t)lane, t, group, word, C.key0, C.key1);
-            uint32_t uw2 = sweep_word(64u + (uint32_t)lane, t, group, word, C.key0, C.key1);
-            while (p0 < npairs) {
-                if (ar != cur_a) {
-                    cur_a = ar;
-                    pa = pr[ar];
-                    const uint8_t *frow_a = F + ar * FS + q;
-#pragma unroll
-                    for (int i = 0; i < KPL; ++i)
-                        fa[i] = frow_a[16 * i];
-                    refresh = true;
-                }
-                if (refresh) {
-#pragma unroll
-                    for (int i = 0; i < KPL; ++i)
-                        da[i] = D[pa * n + pk[i]];
-                    refresh = false;
-                }
-                const int pb = pr[br];
-                const uint8_t *frow_b = F + br * FS + q;
-                const uint8_t *drow_b = D + pb * n;
-                int part = 0;
-#pragma unroll
-                for (int i = 0; i < KPL; ++i)
-                    part += (fa[i] - (int)frow_b[16 * i]) * ((int)drow_b[pk[i]] - da[i]);
-                if (q == 0)
-                    part += 2 * (int)F[ar * FS + br] * (int)D[pa * n + pb];
-                const int dc = 2 * row_allreduce16(part);
-
-                const int pi = p0 + row;
-                const int src = pi - (int)pbase;  // 0 .. 66
-                const int sl = (src & 63) << 2;
-                const uint32_t ua = (uint32_t)__builtin_amdgcn_ds_bpermute(sl, (int)uw);
-                const uint32_t ub = (uint32_t)__builtin_amdgcn_ds_bpermute(sl, (int)uw2);
-                const uint32_t u = src < 64 ? ua : ub;
-                bool acc = dc <= 0;
-                if (!acc) {
-                    const int cl = max((int)cls[ar], (int)cls[br]);
-                    const uint32_t *T = tl + cl * C.stride;
-                    const int h = dc >> kQapLowBits, l = dc & ((1 << kQapLowBits) - 1);
-                    const uint32_t thr = h < I.ha ? (uint32_t)(((uint64_t)T[h] * (uint64_t)T[I.ha + l]) >> 32) : 0u;
-                    acc = u < thr;
-                }
-                acc = acc && pi < npairs;
-                const uint64_t m = __ballot(acc);
-                const uint32_t rows = (uint32_t)((m & 1u) | ((m >> 15) & 2u) | ((m >> 30) & 4u) | ((m >> 45) & 8u));
-                int adv = 4;
-                if (rows) {
-                    const int j = __builtin_ctz(rows);
-                    adv = j + 1;
-                    const int jl = 16 * j;
-                    const int aj = __builtin_amdgcn_readlane(ar, jl);
-                    const int bj = __builtin_amdgcn_readlane(br, jl);
-                    const int paj = __builtin_amdgcn_readlane(pa, jl);
-                    const int pbj = __builtin_amdgcn_readlane(pb, jl);
-                    cost += __builtin_amdgcn_readlane(dc, jl);
-                    if (lane == 0) {
-                        pr[aj] = (uint8_t)pbj;
-                        pr[bj] = (uint8_t)paj;
-                    }
-                    // only the lanes holding k = aj and k = bj see new
-                    // locations (register index k / 16 is wave-uniform)
-#pragma unroll
-                    for (int i = 0; i < KPL; ++i) {
-                        if (i == (aj >> 4) && q == (aj & 15))
-                            pk[i] = pbj;
-                        if (i == (bj >> 4) && q == (bj & 15))
-                            pk[i] = paj;
-                    }
-                    if (ar == aj)
-                        pa = pbj;
-                    else if (ar == bj)
-                        pa = paj;
-                    refresh = true;
-                }
-                p0 += adv;
-                pair_advance(ar, br, n, adv);
-                if (p0 >= (int)pbase + 64) {
-                    pbase += 64;
-                    uw = uw2;
-                    uw2 = sweep_word(pbase + 64u + (uint32_t)lane, t, group, word, C.key0, C.key1);
-                }
+            if (C.rows == 0) {
+                // acceptance of this sweep: above 1/2 one proposal per step,
+                // below 1/16 eight, else four
+                rows = 2 * n_acc > npairs ? 1 : (16 * n_acc < npairs && KPL8 > 0) ? 8 : 4;
             }
             // sweep end
             bool imp = false;
@@ -304,23 +401,27 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
     }
 }
 
+// facilities per lane with 16, 64 and 8 lanes per proposal (0: no 8-lane mode)
 template <typename Fn>
 __device__ __forceinline__ void qap_dispatch_kpl(int n, Fn &&fn) {
+    using std::integral_constant;
     if (n <= 32)
-        fn(std::integral_constant<int, 2>{});
+        fn(integral_constant<int, 2>{}, integral_constant<int, 1>{}, integral_constant<int, 4>{});
     else if (n <= 64)
-        fn(std::integral_constant<int, 4>{});
+        fn(integral_constant<int, 4>{}, integral_constant<int, 1>{}, integral_constant<int, 8>{});
     else if (n <= 112)
-        fn(std::integral_constant<int, 7>{});
+        fn(integral_constant<int, 7>{}, integral_constant<int, 2>{}, integral_constant<int, 14>{});
     else if (n <= 160)
-        fn(std::integral_constant<int, 10>{});
+        fn(integral_constant<int, 10>{}, integral_constant<int, 3>{}, integral_constant<int, 0>{});
     else
-        fn(std::integral_constant<int, 16>{});
+        fn(integral_constant<int, 16>{}, integral_constant<int, 4>{}, integral_constant<int, 0>{});
 }
 
 __global__ void __launch_bounds__(1024) qap_sweep_kernel(QapDev I, QapRepDev R, QapCall C) {
     extern __shared__ __align__(16) uint8_t smem[];
-    qap_dispatch_kpl(I.n, [&](auto kpl) { qap_sweep_block<decltype(kpl)::value>(I, R, C, blockIdx.x, smem); });
+    qap_dispatch_kpl(I.n, [&](auto k4, auto k1, auto k8) {
+        qap_sweep_block<decltype(k4)::value, decltype(k1)::value, decltype(k8)::value>(I, R, C, blockIdx.x, smem);
+    });
 }
 
 // Batched launch over (job, block of 16 replicas) items in decreasing cost.
@@ -329,7 +430,10 @@ __global__ void __launch_bounds__(1024) qap_sweep_batch_kernel(const QapJob *job
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int2 w = items[it];
         const QapJob &J = jobs[w.x];
-        qap_dispatch_kpl(J.I.n, [&](auto kpl) { qap_sweep_block<decltype(kpl)::value>(J.I, J.R, J.C, w.y, smem); });
+        qap_dispatch_kpl(J.I.n, [&](auto k4, auto k1, auto k8) {
+            qap_sweep_block<decltype(k4)::value, decltype(k1)::value, decltype(k8)::value>(J.I, J.R, J.C, w.y,
+                                                                                          smem);
+        });
         __syncthreads();
     }
 }
@@ -400,11 +504,12 @@ __global__ void qap_tally_kernel(QapRepDev R) {
 
 }  // namespace
 
-int qap_kpl(int n) { return n <= 32 ? 2 : n <= 64 ? 4 : n <= 112 ? 7 : n <= 160 ? 10 : 16; }
+// flow row bytes 16 * KP of qap_sweep_block for qap_dispatch_kpl's KPL4
+int qap_flow_row(int n) { return n <= 64 ? 64 : n <= 112 ? 128 : 256; }
 
 size_t qap_sweep_lds_bytes(int n, int n_classes, int stride) {
     const size_t nn = (size_t)n * n;
-    return align_up((size_t)n * 16 * qap_kpl(n), 16) + align_up(nn, 16) + kRepPerBlock * align_up(n, 4) +
+    return align_up((size_t)n * qap_flow_row(n), 16) + align_up(nn, 16) + kRepPerBlock * align_up(n, 4) +
            align_up(n, 16) + (size_t)n_classes * stride * sizeof(uint32_t);
 }
 
