@@ -46,12 +46,9 @@ int ok() {
 // Proposals per step of the QAP sweep: 0 = chosen per sweep by the kernel;
 // NMC_QAP_ROWS=1, 4 or 8 pins it (for measurements; results do not change).
 static int32_t qap_rows_setting() {
-    static const int32_t rows = [] {
-        const char *e = std::getenv("NMC_QAP_ROWS");
-        const int v = e ? std::atoi(e) : 0;
-        return (int32_t)(v == 1 || v == 4 || v == 8 ? v : 0);
-    }();
-    return rows;
+    const char *e = std::getenv("NMC_QAP_ROWS");
+    const int v = e ? std::atoi(e) : 0;
+    return (int32_t)(v == 1 || v == 4 || v == 8 ? v : 0);
 }
 
 int nmc::set_last_error(int code, const char *msg) {

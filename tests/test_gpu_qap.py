@@ -80,3 +80,22 @@ def test_qap_full_size_n100_r4096_short_schedule():
     cls = p.backbone(9, 10)
     p.anneal(reanneal_profile(1000, sc)[:, :1], profile="backbone", class_of=cls)
     p.compare()
+
+
+@pytest.mark.parametrize("rows", ["1", "4", "8", "0"])
+def test_qap_every_step_width_matches_oracle(rows, monkeypatch):
+    """The number of proposals a wave evaluates per step (pinned to 1, 4 or 8,
+    or chosen per sweep from the acceptance rate) never changes the result:
+    sizes on each side of the width limits, and a schedule that crosses from
+    mostly-accepted to mostly-rejected sweeps inside one call."""
+    monkeypatch.setenv("NMC_QAP_ROWS", rows)
+    for n, R in ((45, 9), (100, 6), (130, 5)):
+        say(f"case: qap width={rows} n={n} R={R}")
+        F, D = instances.gen_qap(n, SEED + 3 * n)
+        sc = beta_scale(F, D)
+        p = QapPair(F, D, R, SEED + n)
+        p.anneal(np.geomspace(0.05 * sc, 8.0 * sc, 10)[None, :], target=0)
+        p.compare()
+        cls = p.backbone(2, 3)
+        p.anneal(reanneal_profile(4, sc), profile="backbone", class_of=cls)
+        p.compare()
