@@ -288,6 +288,121 @@ __device__ __forceinline__ int qap_wave_sweep(const QapDev &I, const QapCall &C,
     return n_acc;
 }
 
+// One sweep of one replica by one wave, one proposal per step on all 64
+// lanes (KPL facilities per lane, k = lane, lane + 64, ...), for sweeps where
+// most proposals are accepted.  The step's chain is kept short: the next
+// pair's location (and, when a changes, its flow row and location) is read
+// while the current pair is evaluated, and an accepted swap (a, b) updates
+// D[p_a][p_k] from registers: with zero diagonal and symmetric D the new row
+// is D[p_b][p_k] (just gathered) except D[p_b][p_b] = 0 at k = a and
+// D[p_b][p_a] = D[p_a][p_b] (the old value) at k = b.  Same decisions, words
+// and counters as qap_wave_sweep.  Returns the number of accepted swaps.
+template <int KPL, int KP>
+__device__ __forceinline__ int qap_wave_sweep1(const QapDev &I, const QapCall &C, const uint8_t *F, const uint8_t *D,
+                                               const uint8_t *cls, const uint32_t *tl, uint8_t *pr, uint32_t t,
+                                               uint32_t group, int word, long long &cost) {
+    constexpr int RB = 16 * KP;
+    const int n = I.n;
+    const int npairs = n * (n - 1) / 2;
+    const int lane = threadIdx.x & 63;
+    const bool one_class = C.n_classes == 1;
+    int pk[KPL], fa[KPL], da[KPL];
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) {
+        const int k = lane + 64 * i;
+        pk[i] = k < n ? pr[k] : 0;
+    }
+    int ar = 0, br = 1;
+    int pa = pr[0], pb = pr[1];
+    flow_row<1, KPL, KP>(F, lane, fa);
+#pragma unroll
+    for (int i = 0; i < KPL; ++i)
+        da[i] = D[pa * n + pk[i]];
+    int n_acc = 0;
+    uint32_t pbase = 0;
+    uint32_t uw = sweep_word((uint32_t)lane, t, group, word, C.key0, C.key1);
+    for (int p0 = 0; p0 < npairs; ++p0) {
+        // next pair and its reads (the current swap can change them only
+        // through a or b, fixed below)
+        int an = ar, bn = br;
+        pair_advance(an, bn, n, 1);
+        int pbn = pr[bn], pan = pa;
+        int fan[KPL];
+        const bool new_a = an != ar;
+        if (new_a) {
+            pan = pr[an];
+            flow_row<1, KPL, KP>(F + an * RB, lane, fan);
+        }
+        // the current proposal
+        int fb[KPL], db[KPL];
+        flow_row<1, KPL, KP>(F + br * RB, lane, fb);
+        int part = 0;
+#pragma unroll
+        for (int i = 0; i < KPL; ++i) {
+            db[i] = D[pb * n + pk[i]];
+            part += (fa[i] - fb[i]) * (db[i] - da[i]);
+        }
+        if (lane == 0)
+            part += 2 * (int)F[ar * RB + (br & 15) * KP + (br >> 4)] * (int)D[pa * n + pb];
+        part = row_allreduce16(part);
+        const int dc = 2 * (__builtin_amdgcn_readlane(part, 0) + __builtin_amdgcn_readlane(part, 16) +
+                            __builtin_amdgcn_readlane(part, 32) + __builtin_amdgcn_readlane(part, 48));
+        const uint32_t u = (uint32_t)__builtin_amdgcn_readlane((int)uw, p0 - (int)pbase);
+        bool acc = dc <= 0;
+        if (!acc) {
+            const int cl = one_class ? 0 : max((int)cls[ar], (int)cls[br]);
+            const uint32_t *T = tl + cl * C.stride;
+            const int h = dc >> kQapLowBits, l = dc & ((1 << kQapLowBits) - 1);
+            const uint32_t thr = h < I.ha ? (uint32_t)(((uint64_t)T[h] * (uint64_t)T[I.ha + l]) >> 32) : 0u;
+            acc = u < thr;
+        }
+        if (acc) {
+            ++n_acc;
+            cost += dc;
+            if (lane == 0) {
+                pr[ar] = (uint8_t)pb;
+                pr[br] = (uint8_t)pa;
+            }
+#pragma unroll
+            for (int i = 0; i < KPL; ++i) {
+                const int k = lane + 64 * i;
+                const int nd = k == ar ? 0 : k == br ? da[i] : db[i];
+                if (k == ar)
+                    pk[i] = pb;
+                if (k == br)
+                    pk[i] = pa;
+                da[i] = nd;
+            }
+            // locations read ahead that this swap changed
+            if (bn == ar)
+                pbn = pb;
+            else if (bn == br)
+                pbn = pa;
+            if (an == br)
+                pan = pa;
+            const int pa_old = pa;
+            pa = pb;
+            pb = pa_old;
+        }
+        if (new_a) {
+            ar = an;
+            pa = pan;
+#pragma unroll
+            for (int i = 0; i < KPL; ++i) {
+                fa[i] = fan[i];
+                da[i] = D[pa * n + pk[i]];
+            }
+        }
+        br = bn;
+        pb = pbn;
+        if (p0 + 1 == (int)pbase + 64) {
+            pbase += 64;
+            uw = sweep_word(pbase + (uint32_t)lane, t, group, word, C.key0, C.key1);
+        }
+    }
+    return n_acc;
+}
+
 // n_sweeps sweeps for the 16 replicas of block `blk`, by the whole
 // 1024-thread workgroup, with smem = the workgroup's dynamic LDS block.  Each
 // wave picks, per sweep, four proposals per step (16 lanes each) when few
@@ -364,15 +479,15 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
                     n_acc = qap_wave_sweep<8, KPL8, KP>(I, C, F, D, cls, tl, pr, t, group, word, cost);
                 else
                     n_acc = rows == 4 ? qap_wave_sweep<4, KPL4, KP>(I, C, F, D, cls, tl, pr, t, group, word, cost)
-                                      : qap_wave_sweep<1, KPL1, KP>(I, C, F, D, cls, tl, pr, t, group, word, cost);
+                                      : qap_wave_sweep1<KPL1, KP>(I, C, F, D, cls, tl, pr, t, group, word, cost);
             } else {
                 n_acc = rows == 4 ? qap_wave_sweep<4, KPL4, KP>(I, C, F, D, cls, tl, pr, t, group, word, cost)
-                                  : qap_wave_sweep<1, KPL1, KP>(I, C, F, D, cls, tl, pr, t, group, word, cost);
+                                  : qap_wave_sweep1<KPL1, KP>(I, C, F, D, cls, tl, pr, t, group, word, cost);
             }
             if (C.rows == 0) {
-                // acceptance of this sweep: above 1/2 one proposal per step,
+                // acceptance of this sweep: above 3/10 one proposal per step,
                 // below 1/16 eight, else four
-                rows = 2 * n_acc > npairs ? 1 : (16 * n_acc < npairs && KPL8 > 0) ? 8 : 4;
+                rows = 10 * n_acc > 3 * npairs ? 1 : (16 * n_acc < npairs && KPL8 > 0) ? 8 : 4;
             }
             // sweep end
             bool imp = false;
