@@ -185,10 +185,13 @@ __device__ __forceinline__ int qap_wave_sweep(const QapDev &I, const QapCall &C,
     uint32_t pbase = 0;
     uint32_t uw = sweep_word((uint32_t)lane, t, group, word, C.key0, C.key1);
     uint32_t uw2 = sweep_word(64u + (uint32_t)lane, t, group, word, C.key0, C.key1);
+    // locations of this step's b and a, read during the previous step
+    // (valid because no swap happened since; re-read after a swap)
+    int pb = pr[br], pa_ahead = pr[ar];
     while (p0 < npairs) {
         if (ar != cur_a) {
             cur_a = ar;
-            pa = pr[ar];
+            pa = pa_ahead;
             flow_row<ROWS, KPL, KP>(F + ar * RB, q, fa);
             refresh = true;
         }
@@ -198,7 +201,10 @@ __device__ __forceinline__ int qap_wave_sweep(const QapDev &I, const QapCall &C,
                 da[i] = D[pa * n + pk[i]];
             refresh = false;
         }
-        const int pb = pr[br];
+        // the next step's pairs if no proposal of this step is accepted
+        int an = ar, bn = br;
+        pair_advance(an, bn, n, ROWS);
+        const int pbn = pr[bn], pan = pr[an];
         int fb[KPL];
         flow_row<ROWS, KPL, KP>(F + br * RB, q, fb);
         const uint8_t *drow_b = D + pb * n;
@@ -278,7 +284,16 @@ __device__ __forceinline__ int qap_wave_sweep(const QapDev &I, const QapCall &C,
             refresh = true;
         }
         p0 += adv;
-        pair_advance(ar, br, n, adv);
+        if (j >= 0) {
+            pair_advance(ar, br, n, adv);
+            pb = pr[br];
+            pa_ahead = pr[ar];
+        } else {
+            ar = an;
+            br = bn;
+            pb = pbn;
+            pa_ahead = pan;
+        }
         if (p0 >= (int)pbase + 64) {
             pbase += 64;
             uw = uw2;
