@@ -22,8 +22,11 @@
  *  - Device memory for instances and replica sets is owned by the caller:
  *    nmc_footprint() gives the byte sizes, the caller allocates (e.g. torch
  *    tensors on cuda:0) and passes raw device pointers.  The library never
- *    frees caller memory.  The library owns only a small per-replica-set
- *    table buffer (acceptance thresholds), released by nmc_replicas_free().
+ *    frees caller memory.  The library owns only working buffers it sizes
+ *    itself: a per-replica-set threshold table (released by
+ *    nmc_replicas_free), a per-batch descriptor and table buffer (released by
+ *    nmc_batch_free), and, for a server, the device memory of the requests it
+ *    admits (released when a request retires or by nmc_server_free).
  *  - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on
  *    it in call order; calls on one replica set must not overlap in time.
  *  - Energies are exact integers: the k-SAT energy is the number of violated

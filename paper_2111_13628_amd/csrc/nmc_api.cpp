@@ -1209,13 +1209,13 @@ struct nmc_batch {
 namespace {
 
 int device_cus() {
-    static int cus = 0;
-    if (!cus) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
-                                                    hipSuccess || cus <= 0)
-            cus = 256;
-    }
+    static const int cus = [] {
+        int dev = 0, c = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                    hipSuccess || c <= 0)
+            c = 256;
+        return c;
+    }();
     return cus;
 }
 
@@ -1692,6 +1692,8 @@ int nmc_batch_anneal(nmc_batch *B, const double *beta, int32_t n_classes, int32_
                      const int64_t *targets, void *stream) {
     if (!B)
         return fail(NMC_ERR_INVALID, "NULL batch");
+    if (B->sets.empty())
+        return ok();
     try {
         return run_batch(B, {PhaseSpec{beta, n_classes, n_sweeps, profile}}, {0}, 0, 0, 0, targets, false,
                          as_stream(stream));
@@ -1705,6 +1707,8 @@ int nmc_batch_estimate_backbone(nmc_batch *B, int32_t thr_num, int32_t thr_den, 
         return fail(NMC_ERR_INVALID, "NULL batch");
     if (thr_den <= 0 || thr_num <= 0 || thr_num > thr_den)
         return fail(NMC_ERR_INVALID, "need 0 < thr_num <= thr_den");
+    if (B->sets.empty())
+        return ok();
     try {
         Blob blob;
         std::vector<BuiltPhase> built;
@@ -1741,6 +1745,8 @@ int nmc_batch_run_plan(nmc_batch *B, const nmc_plan *plan, const int64_t *target
         return fail(NMC_ERR_INVALID, "negative plan field");
     if (plan->rounds > 0 && (plan->thr_den <= 0 || plan->thr_num <= 0 || plan->thr_num > plan->thr_den))
         return fail(NMC_ERR_INVALID, "need 0 < thr_num <= thr_den");
+    if (B->sets.empty())
+        return ok();
     try {
         if (plan->chunk_sweeps < 0)
             return fail(NMC_ERR_INVALID, "chunk_sweeps must be >= 0");
@@ -1861,8 +1867,29 @@ extern "C" int nmc_batch_tune(nmc_batch *B, int32_t probe_sweeps, int32_t *chose
             offs.push_back(total);
             total += align_up(P->bytes, 256);
         }
-        uint8_t *scratch = nullptr;
-        HIP_OR_FAIL(hipMalloc(&scratch, total));
+        // releases the probe's resources and restores the setting on every exit
+        struct Guard {
+            nmc_batch *B;
+            hipStream_t s;
+            int saved;
+            bool keep = false;
+            uint8_t *scratch = nullptr;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            ~Guard() {
+                if (e0)
+                    (void)hipEventDestroy(e0);
+                if (e1)
+                    (void)hipEventDestroy(e1);
+                if (scratch) {
+                    (void)hipStreamSynchronize(s);
+                    (void)hipFree(scratch);
+                }
+                if (!keep)
+                    B->block_threads = saved;
+            }
+        } guard{B, s, B->block_threads};
+        HIP_OR_FAIL(hipMalloc(&guard.scratch, total));
+        uint8_t *scratch = guard.scratch;
         std::vector<nmc_replicas> clones;
         clones.reserve(ks.size());
         for (size_t i = 0; i < ks.size(); ++i) {
@@ -1873,13 +1900,12 @@ extern "C" int nmc_batch_tune(nmc_batch *B, int32_t probe_sweeps, int32_t *chose
         for (auto &c : clones)
             cptr.push_back(&c);
         std::vector<double> beta((size_t)probe_sweeps, 1.0);
-        const int saved = B->block_threads;
         int best_b = 0;
         float best_ms = 0;
         int rc = NMC_OK;
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        HIP_OR_FAIL(hipEventCreate(&e0));
-        HIP_OR_FAIL(hipEventCreate(&e1));
+        HIP_OR_FAIL(hipEventCreate(&guard.e0));
+        HIP_OR_FAIL(hipEventCreate(&guard.e1));
+        hipEvent_t e0 = guard.e0, e1 = guard.e1;
         for (int cand : {64, 128, 256, 512, 1024}) {
             B->block_threads = cand;
             Blob blob;
@@ -1910,14 +1936,9 @@ extern "C" int nmc_batch_tune(nmc_batch *B, int32_t probe_sweeps, int32_t *chose
                 best_ms = ms;
             }
         }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        (void)hipStreamSynchronize(s);
-        (void)hipFree(scratch);
-        if (rc) {
-            B->block_threads = saved;
+        if (rc)
             return rc;
-        }
+        guard.keep = true;
         B->block_threads = best_b;
         if (chosen)
             *chosen = best_b;
@@ -1937,6 +1958,8 @@ extern "C" int nmc_batch_step(nmc_batch *B, const nmc_segment *segs, int32_t n_s
         return fail(NMC_ERR_INVALID, "NULL argument");
     if (n_sweeps < 0)
         return fail(NMC_ERR_INVALID, "n_sweeps must be >= 0");
+    if (B->sets.empty())
+        return ok();
     try {
         const size_t ns = B->sets.size();
         bool any_bb = false;

@@ -533,14 +533,11 @@ hipError_t ksat_launch_init(const KsatDev &I, const KsatRepDev &R, uint32_t key0
 hipError_t ksat_launch_recount(const KsatDev &I, const uint8_t *xs, int n_groups, int n_rep, int32_t *energy_out,
                                hipStream_t s) {
     const size_t lds = align_up(2 * (size_t)I.n + 2, 16) + 16 * sizeof(int);
-    static bool attr = false;
-    if (!attr) {
-        const hipError_t ea = hipFuncSetAttribute((const void *)ksat_recount_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                  (int)kLdsBytes);
-        if (ea != hipSuccess)
-            return ea;
-        attr = true;
-    }
+    // once per process (thread-safe initialization)
+    static const hipError_t attr = hipFuncSetAttribute((const void *)ksat_recount_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       (int)kLdsBytes);
+    if (attr != hipSuccess)
+        return attr;
     hipLaunchKernelGGL(ksat_recount_kernel, dim3(n_groups), dim3(1024), lds, s, I, xs, n_rep, energy_out);
     return hipGetLastError();
 }
@@ -557,28 +554,22 @@ hipError_t ksat_launch_reset_tallies(const KsatRepDev &R, int n, hipStream_t s) 
 hipError_t ksat_launch_sweep(const KsatDev &I, const KsatRepDev &R, const SweepCall &C, int block_threads,
                              hipStream_t s) {
     const size_t lds = ksat_sweep_lds_bytes(I.n, C.n_classes, C.stride);
-    static bool attr = false;
-    if (!attr) {
-        const hipError_t ea = hipFuncSetAttribute((const void *)ksat_sweep_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                  (int)kLdsBytes);
-        if (ea != hipSuccess)
-            return ea;
-        attr = true;
-    }
+    // once per process (thread-safe initialization)
+    static const hipError_t attr = hipFuncSetAttribute((const void *)ksat_sweep_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       (int)kLdsBytes);
+    if (attr != hipSuccess)
+        return attr;
     hipLaunchKernelGGL(ksat_sweep_kernel, dim3(R.n_groups), dim3(block_threads), lds, s, I, R, C);
     return hipGetLastError();
 }
 
 hipError_t ksat_launch_sweep_batch(const KsatJob *jobs, const int2 *items, int n_items, size_t lds, int block_threads,
                                    int grid, hipStream_t s) {
-    static bool attr = false;
-    if (!attr) {
-        const hipError_t ea = hipFuncSetAttribute((const void *)ksat_sweep_batch_kernel,
-                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
-        if (ea != hipSuccess)
-            return ea;
-        attr = true;
-    }
+    // once per process (thread-safe initialization)
+    static const hipError_t attr = hipFuncSetAttribute((const void *)ksat_sweep_batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       (int)kLdsBytes);
+    if (attr != hipSuccess)
+        return attr;
     hipLaunchKernelGGL(ksat_sweep_batch_kernel, dim3(grid), dim3(block_threads), lds, s, jobs, items, n_items);
     return hipGetLastError();
 }

@@ -664,14 +664,11 @@ hipError_t qap_launch_reset_tallies(const QapRepDev &R, int n, hipStream_t s) {
 hipError_t qap_launch_sweep(const QapDev &I, const QapRepDev &R, const QapCall &C, int block_threads, hipStream_t s) {
     (void)block_threads;
     const size_t lds = qap_sweep_lds_bytes(I.n, C.n_classes, C.stride);
-    static bool attr = false;
-    if (!attr) {
-        const hipError_t ea = hipFuncSetAttribute((const void *)qap_sweep_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                  (int)kLdsBytes);
-        if (ea != hipSuccess)
-            return ea;
-        attr = true;
-    }
+    // once per process (thread-safe initialization)
+    static const hipError_t attr = hipFuncSetAttribute((const void *)qap_sweep_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       (int)kLdsBytes);
+    if (attr != hipSuccess)
+        return attr;
     const int blocks = (R.n_rep + kRepPerBlock - 1) / kRepPerBlock;
     hipLaunchKernelGGL(qap_sweep_kernel, dim3(blocks), dim3(kBlockThreads), lds, s, I, R, C);
     return hipGetLastError();
@@ -679,14 +676,11 @@ hipError_t qap_launch_sweep(const QapDev &I, const QapRepDev &R, const QapCall &
 
 hipError_t qap_launch_sweep_batch(const QapJob *jobs, const int2 *items, int n_items, size_t lds, int grid,
                                   hipStream_t s) {
-    static bool attr = false;
-    if (!attr) {
-        const hipError_t ea = hipFuncSetAttribute((const void *)qap_sweep_batch_kernel,
-                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
-        if (ea != hipSuccess)
-            return ea;
-        attr = true;
-    }
+    // once per process (thread-safe initialization)
+    static const hipError_t attr = hipFuncSetAttribute((const void *)qap_sweep_batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       (int)kLdsBytes);
+    if (attr != hipSuccess)
+        return attr;
     hipLaunchKernelGGL(qap_sweep_batch_kernel, dim3(grid), dim3(kBlockThreads), lds, s, jobs, items, n_items);
     return hipGetLastError();
 }
