@@ -345,7 +345,7 @@ def cpu_baseline(cp, lits, seed):
     _, order, _ = ok.color(CLASS_CAP)
     Rs = 4 * threads
     rep = oracle.KSatReplicas(ok, Rs, seed, order, threads=threads, snapshot=True)
-    sweeps = 32  # about 10-30 s of host work
+    sweeps = 48  # about 10-30 s of host work
     t0 = time.perf_counter()
     rep.anneal(instances.linear_schedule(BETA0, BETA1, S_ANNEAL)[None, :sweeps])
     dt = time.perf_counter() - t0
