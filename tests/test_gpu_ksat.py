@@ -29,10 +29,11 @@ def test_plain_sa_n200_r64_1000_sweeps():
 
 
 @pytest.mark.parametrize("n,alpha,k,R,cap", [(300, "9.6", 4, 38, 0), (700, "4.15", 3, 21, 64),
-                                             (2100, "9.9", 4, 12, 128)])
+                                             (2100, "9.9", 4, 12, 128), (120, "9.6", 4, 9, 1)])
 def test_nmc_rounds_ragged(n, alpha, k, R, cap):
     """anneal -> backbone -> reanneal -> backbone -> reanneal, with replica
-    counts that leave a partial group and several tiles per colour class."""
+    counts that leave a partial group and several tiles per colour class;
+    cap = 1 gives one variable per class (the plain index order)."""
     say(f"case: nmc rounds n={n} k={k} R={R} cap={cap}")
     cp, lits = instances.gen_ksat(n, alpha, k, SEED + n)
     p = KsatPair(n, cp, lits, R, SEED + 1, cap=cap)

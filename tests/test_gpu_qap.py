@@ -89,7 +89,7 @@ def test_qap_every_step_width_matches_oracle(rows, monkeypatch):
     sizes on each side of the width limits, and a schedule that crosses from
     mostly-accepted to mostly-rejected sweeps inside one call."""
     monkeypatch.setenv("NMC_QAP_ROWS", rows)
-    for n, R in ((45, 9), (100, 6), (130, 5)):
+    for n, R in ((45, 9), (100, 6), (130, 5), (7, 4), (10, 3)):
         say(f"case: qap width={rows} n={n} R={R}")
         F, D = instances.gen_qap(n, SEED + 3 * n)
         sc = beta_scale(F, D)
