@@ -5,7 +5,8 @@ workgroup size the tuner picks."""
 import numpy as np
 import pytest
 
-from gpu_util import say
+import oracle
+from gpu_util import say, threads
 from paper_2111_13628_amd import instances, nmc
 
 pytestmark = pytest.mark.gpu
@@ -133,3 +134,41 @@ def test_tuner_choice_does_not_change_results():
         else:
             for (x0, b0), (x1, b1) in zip(ref, got):
                 assert (x0 == x1).all() and (b0 == b1).all()
+
+
+def test_full_batch_of_256_sampled_against_oracle():
+    """The batched benchmark's configuration (256 mixed k-SAT instances, the
+    tuner's block size, one HIP graph, lockstep chunks) on a short plan;
+    sampled instances, from the smallest to the largest, checked against the
+    oracle running them alone."""
+    say("case: 256-instance batch, sampled parity")
+    mix = instances.batch_mix(256, instances.DEFAULT_SEED)
+    data = [instances.gen_ksat(m["n"], m["alpha"], m["k"], m["seed"]) for m in mix]
+    sets = []
+    for m, (cp, lits) in zip(mix, data):
+        inst = nmc.Instance.ksat(m["n"], cp, lits, 0).bind()
+        sets.append(nmc.Replicas(inst, m["replicas"], m["seed"]))
+    b = nmc.Batch(sets)
+    b.tune(2)
+    a_beta = instances.linear_schedule(0.1, 4.0, 1000)[:4]
+    r_beta = instances.profile_schedule(np.full(500, 4.0), instances.linear_schedule(0.5, 4.0, 500))[:, :3]
+    targets = [len(cp) if i % 2 else 0 for i, (cp, _) in enumerate(data)]
+    b.run_plan(a_beta, 1, r_beta, 9, 10, True, targets=targets, use_graph=True, chunk_sweeps=2)
+    by_size = sorted(range(256), key=lambda i: mix[i]["n"] * mix[i]["replicas"])
+    for i in by_size[:3] + by_size[127:129] + by_size[-1:]:
+        m, (cp, lits) = mix[i], data[i]
+        say(f"  instance {i}: N={m['n']} k={m['k']} R={m['replicas']}")
+        ok = oracle.KSat(m["n"], cp, lits)
+        _, order, _ = ok.color(0)
+        orep = oracle.KSatReplicas(ok, m["replicas"], m["seed"], order, threads=threads())
+        orep.anneal(a_beta[None, :], target=targets[i])
+        cls, _ = orep.backbone(9, 10, True)
+        orep.anneal(r_beta, class_of=cls, target=targets[i])
+        s_ = sets[i]
+        assert (s_.get_state() == orep.x).all()
+        assert (s_.get_state("best") == orep.best_x).all()
+        be = s_.best_energy()
+        assert (be["energy"] == orep.energy).all()
+        assert (be["best_per_replica"] == orep.best).all()
+        assert (be["first_hit"] == orep.first_hit).all()
+        assert s_.sweeps_done() == orep.sweeps_done

@@ -114,6 +114,25 @@ def test_edge_cases():
     p.compare()
 
 
+def test_largest_instance_and_no_clauses():
+    """N = 65534, the largest spin table the LDS holds (2N + 2 bytes of 160 KB),
+    and an instance without clauses (every move has dE = 0)."""
+    say("case: N = 65534, 5 replicas")
+    n = 65534
+    cp, lits = instances.gen_ksat(n, "9.9", 4, SEED + 7)
+    p = KsatPair(n, cp, lits, 5, SEED + 8, cap=1024)
+    p.anneal(instances.linear_schedule(0.1, 4.0, 100)[None, :2], target=0)
+    p.compare()
+    cls = p.backbone(9, 10, True)
+    p.anneal(reanneal_profile(2), profile="backbone", class_of=cls)
+    p.compare()
+    say("case: 300 variables, no clauses")
+    p = KsatPair(300, np.zeros(1, np.int32), np.zeros(0, np.int32), 11, 5)
+    p.anneal(np.full((1, 3), 2.0), target=0)
+    p.compare()
+    assert (p.orep.energy == 0).all() and (p.orep.first_hit == 0).all()
+
+
 def test_set_state_resume_matches_continuation():
     n = 800
     cp, lits = instances.gen_ksat(n, "9.9", 4, 4)

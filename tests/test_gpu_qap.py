@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 from gpu_util import QapPair, say
-from paper_2111_13628_amd import instances
+from paper_2111_13628_amd import instances, nmc
 
 pytestmark = pytest.mark.gpu
 
@@ -99,3 +99,23 @@ def test_qap_every_step_width_matches_oracle(rows, monkeypatch):
         cls = p.backbone(2, 3)
         p.anneal(reanneal_profile(4, sc), profile="backbone", class_of=cls)
         p.compare()
+
+
+def test_qap_largest_n255():
+    """n = 255, the largest permutation a byte holds.  With entries up to 99
+    one threshold table fits next to F and D in LDS but two do not: the
+    backbone profile must then fail cleanly with NMC_ERR_CAPACITY."""
+    say("case: qap n=255")
+    F, D = instances.gen_qap(255, SEED + 255)
+    sc = beta_scale(F, D, samples=300)
+    p = QapPair(F, D, 3, SEED)
+    p.anneal(np.full((1, 2), 2.0 * sc), target=0)
+    p.compare()
+    cls = p.backbone(1, 3)
+    try:
+        p.rep.reanneal(reanneal_profile(1, sc), "backbone")
+    except nmc.NmcError as e:
+        assert e.code == -5, e
+        return
+    p.orep.anneal(reanneal_profile(1, sc), class_of=cls)
+    p.compare()
