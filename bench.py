@@ -278,22 +278,36 @@ def bench_serve(nmc, torch, seed, seconds):
             reqs.append((m, d, int(np.floor((1.0 + 1e-2) * ratio * _qap_random_cost(F, D))), sc))
     del data
     a, rounds, re = SERVE_SCHED
-    srv = nmc.Server(chunk_sweeps=SERVE_CHUNK, loader_threads=max(2, min(12, (os.cpu_count() or 8) - 4)))
-    ids = []
-    t_start = time.perf_counter()
-    for m, d, target, sc in reqs:
-        delay = m["arrival"] - (time.perf_counter() - t_start)
-        if delay > 0:
-            time.sleep(delay)
+    loaders = max(2, min(12, (os.cpu_count() or 8) - 4))
+
+    def submit(srv, m, d, target, sc):
         if m["kind"] == "ksat":
             cp, lits = d
-            rid = srv.submit_ksat(m["n"], cp, lits, m["replicas"], m["seed"], BETA0, BETA1, BETA_HOT, a, rounds, re,
-                                  target=target, budget_s=SERVE_BUDGET_S)
-        else:
-            F, D = d
-            rid = srv.submit_qap(F, D, m["replicas"], m["seed"], BETA0 * sc, BETA1 * sc, BETA_HOT * sc, a, rounds,
-                                 re, target=target, budget_s=SERVE_BUDGET_S)
-        ids.append(rid)
+            return srv.submit_ksat(m["n"], cp, lits, m["replicas"], m["seed"], BETA0, BETA1, BETA_HOT, a, rounds,
+                                   re, target=target, budget_s=SERVE_BUDGET_S)
+        F, D = d
+        return srv.submit_qap(F, D, m["replicas"], m["seed"], BETA0 * sc, BETA1 * sc, BETA_HOT * sc, a, rounds, re,
+                              target=target, budget_s=SERVE_BUDGET_S)
+
+    # capacity: the first requests of the stream submitted at once (closed loop)
+    n_cap = min(len(reqs), 400)
+    srv = nmc.Server(chunk_sweeps=SERVE_CHUNK, loader_threads=loaders)
+    cap_ids = [submit(srv, *q) for q in reqs[:n_cap]]
+    srv.wait_idle(300.0)
+    cap_res = [srv.poll(i) for i in cap_ids]
+    srv.free()
+    cap_wall = max(r["t_done"] for r in cap_res) - min(r["t_submit"] for r in cap_res)
+    capacity = n_cap / cap_wall
+    print(f"# serve: capacity {capacity:.1f} requests/s ({n_cap} at once)", file=sys.stderr, flush=True)
+
+    srv = nmc.Server(chunk_sweeps=SERVE_CHUNK, loader_threads=loaders)
+    ids = []
+    t_start = time.perf_counter()
+    for q in reqs:
+        delay = q[0]["arrival"] - (time.perf_counter() - t_start)
+        if delay > 0:
+            time.sleep(delay)
+        ids.append(submit(srv, *q))
         if len(ids) % 500 == 0:
             print(f"# serve: {len(ids)} submitted, {srv.stats()['completed']} completed", file=sys.stderr, flush=True)
     drained = srv.wait_idle(300.0)
@@ -307,6 +321,7 @@ def bench_serve(nmc, torch, seed, seconds):
         return {"p50": float(np.percentile(xs, 50)), "p99": float(np.percentile(xs, 99))} if xs else None
 
     out = {"requests": len(res), "offered_rate_per_s": SERVE_RATE, "seconds": seconds, "drained": drained,
+           "capacity_requests_per_s": capacity, "offered_load": len(res) / seconds / capacity,
            "schedule": {"anneal": a, "rounds": rounds, "reanneal": re, "chunk_sweeps": SERVE_CHUNK,
                         "budget_s": SERVE_BUDGET_S},
            "wall_s": wall, "gpu_busy_s_summed_over_workers": stats["gpu_busy_s"], "rounds": stats["rounds"],
