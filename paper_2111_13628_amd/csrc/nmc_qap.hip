@@ -144,6 +144,18 @@ __device__ __forceinline__ void flow_row(const uint8_t *row, int q, int (&f)[KPL
     }
 }
 
+// Second flow layout, for eight 8-lane rows: row b holds F[b][q + 8i] at byte
+// q * 16 + i (zero past n), so a lane's 16 bytes come in one 16-byte read.
+template <int KPL>
+__device__ __forceinline__ void flow_row8(const uint8_t *row, int q, int (&f)[KPL]) {
+    static_assert(KPL <= 16, "flow layout");
+    const uint4 v = *reinterpret_cast<const uint4 *>(row + q * 16);
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int i = 0; i < KPL; ++i)
+        f[i] = (int)((w[i >> 2] >> (8 * (i & 3))) & 0xFFu);
+}
+
 // One sweep of one replica by one wave.  ROWS proposals are evaluated per
 // step, one per row of LANES = 64 / ROWS lanes; KPL = facilities per lane
 // (k = q, q + LANES, ...), LANES * KPL <= 16 * KP, the flow row length (rows
@@ -160,9 +172,9 @@ __device__ __forceinline__ void flow_row(const uint8_t *row, int q, int (&f)[KPL
 // per generator call per lane); counter (pair, sweep, replica / 4, stream),
 // word replica % 4.  Returns the number of accepted swaps.
 template <int ROWS, int KPL, int KP>
-__device__ __forceinline__ int qap_wave_sweep(const QapDev &I, const QapCall &C, const uint8_t *F, const uint8_t *D,
-                                              const uint8_t *cls, const uint32_t *tl, uint8_t *pr, uint32_t t,
-                                              uint32_t group, int word, long long &cost) {
+__device__ __forceinline__ int qap_wave_sweep(const QapDev &I, const QapCall &C, const uint8_t *F, const uint8_t *F8,
+                                              const uint8_t *D, const uint8_t *cls, const uint32_t *tl, uint8_t *pr,
+                                              uint32_t t, uint32_t group, int word, long long &cost) {
     constexpr int LANES = 64 / ROWS;
     constexpr int RB = 16 * KP;  // bytes per flow row
     static_assert(ROWS == 1 || ROWS == 8 || (ROWS == 4 && KPL <= KP), "flow layout");
@@ -192,7 +204,10 @@ __device__ __forceinline__ int qap_wave_sweep(const QapDev &I, const QapCall &C,
         if (ar != cur_a) {
             cur_a = ar;
             pa = pa_ahead;
-            flow_row<ROWS, KPL, KP>(F + ar * RB, q, fa);
+            if constexpr (ROWS == 8)
+                flow_row8<KPL>(F8 + ar * 128, q, fa);
+            else
+                flow_row<ROWS, KPL, KP>(F + ar * RB, q, fa);
             refresh = true;
         }
         if (refresh) {
@@ -206,7 +221,10 @@ __device__ __forceinline__ int qap_wave_sweep(const QapDev &I, const QapCall &C,
         pair_advance(an, bn, n, ROWS);
         const int pbn = pr[bn], pan = pr[an];
         int fb[KPL];
-        flow_row<ROWS, KPL, KP>(F + br * RB, q, fb);
+        if constexpr (ROWS == 8)
+            flow_row8<KPL>(F8 + br * 128, q, fb);
+        else
+            flow_row<ROWS, KPL, KP>(F + br * RB, q, fb);
         const uint8_t *drow_b = D + pb * n;
         int part = 0;
 #pragma unroll
@@ -438,7 +456,8 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
     const int npairs = n * (n - 1) / 2;
 
     uint8_t *F = smem;  // [n][FS]
-    uint8_t *D = F + align_up((size_t)n * FS, 16);
+    uint8_t *F8 = F + align_up((size_t)n * FS, 16);  // [n][128], only with the 8-row scheme
+    uint8_t *D = F8 + (KPL8 > 0 ? align_up((size_t)n * 128, 16) : 0);
     uint8_t *P = D + align_up(nn, 16);
     uint8_t *cls = P + kRepPerBlock * npad;
     uint32_t *tl = (uint32_t *)(cls + align_up(n, 16));
@@ -448,6 +467,12 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
         const int r = i / FS, o = i % FS;
         const int k = (o % KP) * 16 + o / KP;  // inverse of (k % 16) * KP + k / 16
         F[i] = k < n ? I.F[r * n + k] : 0;
+    }
+    if constexpr (KPL8 > 0) {
+        for (int i = tid; i < n * 128; i += blockDim.x) {
+            const int r = i >> 7, k = ((i >> 4) & 7) + 8 * (i & 15);  // byte q * 16 + j holds k = q + 8j
+            F8[i] = k < n ? I.F[r * n + k] : 0;
+        }
     }
     for (int i = tid; i < nn; i += blockDim.x)
         D[i] = I.D[i];
@@ -491,12 +516,12 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
             int n_acc;
             if constexpr (KPL8 > 0) {
                 if (rows == 8)
-                    n_acc = qap_wave_sweep<8, KPL8, KP>(I, C, F, D, cls, tl, pr, t, group, word, cost);
+                    n_acc = qap_wave_sweep<8, KPL8, KP>(I, C, F, F8, D, cls, tl, pr, t, group, word, cost);
                 else
-                    n_acc = rows == 4 ? qap_wave_sweep<4, KPL4, KP>(I, C, F, D, cls, tl, pr, t, group, word, cost)
+                    n_acc = rows == 4 ? qap_wave_sweep<4, KPL4, KP>(I, C, F, F8, D, cls, tl, pr, t, group, word, cost)
                                       : qap_wave_sweep1<KPL1, KP>(I, C, F, D, cls, tl, pr, t, group, word, cost);
             } else {
-                n_acc = rows == 4 ? qap_wave_sweep<4, KPL4, KP>(I, C, F, D, cls, tl, pr, t, group, word, cost)
+                n_acc = rows == 4 ? qap_wave_sweep<4, KPL4, KP>(I, C, F, F8, D, cls, tl, pr, t, group, word, cost)
                                   : qap_wave_sweep1<KPL1, KP>(I, C, F, D, cls, tl, pr, t, group, word, cost);
             }
             if (C.rows == 0) {
@@ -639,7 +664,8 @@ int qap_flow_row(int n) { return n <= 64 ? 64 : n <= 112 ? 128 : 256; }
 
 size_t qap_sweep_lds_bytes(int n, int n_classes, int stride) {
     const size_t nn = (size_t)n * n;
-    return align_up((size_t)n * qap_flow_row(n), 16) + align_up(nn, 16) + kRepPerBlock * align_up(n, 4) +
+    return align_up((size_t)n * qap_flow_row(n), 16) + (n <= 112 ? align_up((size_t)n * 128, 16) : 0) +
+           align_up(nn, 16) + kRepPerBlock * align_up(n, 4) +
            align_up(n, 16) + (size_t)n_classes * stride * sizeof(uint32_t);
 }
 
