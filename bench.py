@@ -42,6 +42,7 @@ BLOCK_THREADS = 0
 OPS_PER_SLOT = 9.0
 OPS_PER_VAR = 62.0
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock
+LDS_LANE_READS = 256 * 32 * 2.4e9  # CUs x LDS banks x clock (one lane read per bank per clock)
 
 
 def reanneal_profile(S):
@@ -205,8 +206,17 @@ def bench_qap(nmc, torch, seed, sweeps_only=0):
     wall = time.perf_counter() - t0
     kt = rep.kernel_time()
     props = float(Rq) * pairs * S_tot
+    kps = kt["attempts"] / (kt["ms"] / 1000.0)
+    # LDS byte reads per proposal: F[b][k] and the gather D[p_b][p_k] for every k
+    # but a, b; peak: 32 banks per CU served per clock
+    reads = 2.0 * (n - 2)
+    achieved = kps * reads
+    roofline = {"bound": "lds", "achieved": achieved / 1e12, "peak": LDS_LANE_READS / 1e12,
+                "unit": "T lane-reads/s", "frac": achieved / LDS_LANE_READS, "traffic": None,
+                "kernel": "qap_sweep_kernel", "kernel_ms_per_launch": kt["ms"] / max(1, kt["launches"]),
+                "launches": kt["launches"]}
     return {"proposals": props, "wall_s": wall, "proposals_per_s": props / wall,
-            "kernel_ms": kt["ms"], "kernel_proposals_per_s": kt["attempts"] / (kt["ms"] / 1000.0),
+            "kernel_ms": kt["ms"], "kernel_proposals_per_s": kps, "roofline": roofline,
             "beta_unit": sc, "best_cost": be["best"], "sweeps": S_tot}
 
 
@@ -418,7 +428,7 @@ def main():
                           "unit": "proposals/s", "n_gpus": 1, "higher_is_better": True, "dtype": "int32",
                           "data": "synthetic",
                           "config": {"workload": "QAP n=100, 4096 replicas, anneal 5000 + 2x(backbone + reanneal 1000)"},
-                          "qap": res}), flush=True)
+                          "roofline": res["roofline"], "qap": res}), flush=True)
         return
     if args.workload == "serve":
         res = bench_serve(nmc, torch, seed, args.serve_seconds)
