@@ -239,8 +239,9 @@ int nmc_replicas_info(const nmc_replicas *rep, int32_t *n_replicas, uint64_t *se
  * tuning and timing (results never depend on these)
  * ------------------------------------------------------------------------- */
 
-/* block_threads: threads per workgroup of the sweep kernels (64..1024,
- * multiple of 64; 0 = default). */
+/* block_threads: threads per workgroup of the k-SAT sweep kernel (64..1024,
+ * multiple of 64; 0 = default 1024).  QAP sweeps always run one replica per
+ * wave, 16 per 1024-thread workgroup, and ignore it. */
 int nmc_set_tuning(nmc_replicas *rep, int32_t block_threads);
 
 /* When enabled, every sweep-kernel launch is bracketed by HIP events on the
