@@ -12,6 +12,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+from concurrent.futures import ThreadPoolExecutor
 import subprocess
 import threading
 
@@ -21,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "nmc_oracle.c")
 _LIB = os.path.join(_HERE, "libnmc_oracle.so")
 
-STREAM_SWEEP, STREAM_INIT, STREAM_QAP_SWEEP, STREAM_QAP_INIT = 0, 1, 2, 3
+STREAM_SWEEP, STREAM_INIT, STREAM_QAP_SWEEP, STREAM_QAP_INIT, STREAM_PT_SWAP = 0, 1, 2, 3, 4
 
 
 def build(force: bool = True) -> str:
@@ -78,6 +79,9 @@ def lib():
                                          _I64, _P, _P, _P, _P, _P]
             L.orc_qap_anneal.restype = ctypes.c_int
             L.orc_qap_backbone.argtypes = [_I32, _I32, _P, _I32, _I32, _P, _P]
+            L.orc_pt_exchange.argtypes = [_I32, _I32, _P, _U64, _U32, _I32, _I32, _P, _P, _P, _P]
+            L.orc_energy_sigma.argtypes = [_P, _I64]
+            L.orc_energy_sigma.restype = _D
             _lib = L
     return _lib
 
@@ -181,16 +185,23 @@ class KSatReplicas:
         beta = _c(beta, np.float64)
         cls = None if class_of is None else _c(class_of, np.uint8)
         r_end = self.R if r_end is None else r_end
-        inst = self.inst
-
-        def run(a, b):
-            lib().orc_ksat_anneal(inst.n, inst.m, _p(inst.cptr), _p(inst.lits), _p(self.order), a, b,
-                                  self.seed, self.sweeps_done, S, nc, _p(beta), _p(cls), int(target),
-                                  _p(self.x), _p(self.energy), _p(self.best), _p(self.first_hit),
-                                  _p(self.best_x))
-
-        _run_threads(run, _split(r_begin, r_end, self.threads))
+        _run_threads(lambda a, b: self._sweeps(beta, cls, target, a, b), _split(r_begin, r_end, self.threads))
         self.sweeps_done += S
+
+    def _sweeps(self, beta, cls, target, a, b):
+        """Sweeps of replicas a..b-1 from the current sweep counter (not advanced)."""
+        inst = self.inst
+        nc, S = beta.shape
+        lib().orc_ksat_anneal(inst.n, inst.m, _p(inst.cptr), _p(inst.lits), _p(self.order), a, b,
+                              self.seed, self.sweeps_done, S, nc, _p(beta), _p(cls), int(target),
+                              _p(self.x), _p(self.energy), _p(self.best), _p(self.first_hit),
+                              _p(self.best_x))
+
+    def pt_run(self, beta, n_rounds, sweeps_per_round, first_parity=0, target=-1):
+        return _pt_run(self, self.x, beta, n_rounds, sweeps_per_round, first_parity, target)
+
+    def apt_ladder(self, beta_first, alpha, sigma_min, equil, meas, max_temps):
+        return _apt_ladder(self, beta_first, alpha, sigma_min, equil, meas, max_temps)
 
     def backbone(self, thr_num=9, thr_den=10, expand=True):
         inst = self.inst
@@ -240,15 +251,25 @@ class QapReplicas:
         beta = _c(beta, np.float64)
         cls = None if class_of is None else _c(class_of, np.uint8)
         r_end = self.R if r_end is None else r_end
-        inst = self.inst
-
-        def run(a, b):
-            lib().orc_qap_anneal(inst.n, _p(inst.F), _p(inst.D), a, b, self.seed, self.sweeps_done, S, nc,
-                                 _p(beta), _p(cls), int(target), _p(self.perm), _p(self.cost),
-                                 _p(self.best), _p(self.first_hit), _p(self.best_perm))
-
-        _run_threads(run, _split(r_begin, r_end, self.threads))
+        _run_threads(lambda a, b: self._sweeps(beta, cls, target, a, b), _split(r_begin, r_end, self.threads))
         self.sweeps_done += S
+
+    def _sweeps(self, beta, cls, target, a, b):
+        inst = self.inst
+        nc, S = beta.shape
+        lib().orc_qap_anneal(inst.n, _p(inst.F), _p(inst.D), a, b, self.seed, self.sweeps_done, S, nc,
+                             _p(beta), _p(cls), int(target), _p(self.perm), _p(self.cost),
+                             _p(self.best), _p(self.first_hit), _p(self.best_perm))
+
+    @property
+    def energy(self):
+        return self.cost
+
+    def pt_run(self, beta, n_rounds, sweeps_per_round, first_parity=0, target=-1):
+        return _pt_run(self, self.perm, beta, n_rounds, sweeps_per_round, first_parity, target)
+
+    def apt_ladder(self, beta_first, alpha, sigma_min, equil, meas, max_temps):
+        return _apt_ladder(self, beta_first, alpha, sigma_min, equil, meas, max_temps)
 
     def backbone(self, thr_num=9, thr_den=10):
         inst = self.inst
@@ -256,3 +277,77 @@ class QapReplicas:
         cls = np.zeros(inst.n, np.uint8)
         lib().orc_qap_backbone(inst.n, self.R, _p(self.perm), thr_num, thr_den, _p(freq), _p(cls))
         return cls, freq
+
+
+# ---------------------------------------------------------------- parallel tempering
+
+def energy_sigma(samples):
+    """sigma = sqrt(<E^2> - <E>^2) over the samples (appendix A)."""
+    e = _c(samples, np.int64)
+    return float(lib().orc_energy_sigma(_p(e), e.size))
+
+
+def pt_exchange(beta, n_chains, seed, t, parity, rows, energy):
+    """One exchange step on rows [R][row_len] and energies [R] (both updated
+    in place); returns (accepted, attempted) per pair position."""
+    beta = _c(beta, np.float64)
+    M = beta.size
+    acc = np.zeros(max(M - 1, 1), np.int64)
+    att = np.zeros(max(M - 1, 1), np.int64)
+    e = _c(energy, np.int64)
+    lib().orc_pt_exchange(M, int(n_chains), _p(beta), int(seed), int(t), int(parity), rows.shape[1], _p(rows),
+                          _p(e), _p(acc), _p(att))
+    energy[:] = e
+    return acc[: M - 1], att[: M - 1]
+
+
+def _pt_run(rep, rows, beta, n_rounds, sweeps_per_round, first_parity, target):
+    """Parallel tempering rounds (appendix A).  Replica r = i * C + c runs at
+    beta[i]; every round is sweeps_per_round Metropolis sweeps of every
+    replica at its ladder temperature, then one exchange step with parity
+    (first_parity + round) mod 2.  Returns summed (accepted, attempted)."""
+    beta = _c(beta, np.float64)
+    M = beta.size
+    C = rep.R // M
+    assert C * M == rep.R
+    S = int(sweeps_per_round)
+    acc = np.zeros(max(M - 1, 0), np.int64)
+    att = np.zeros(max(M - 1, 0), np.int64)
+    tabs = [np.full((1, S), b) for b in beta]
+    parts = []
+    per = max(1, rep.threads // M) if M else 1
+    for i in range(M):
+        parts += [(i, a, b) for a, b in _split(i * C, (i + 1) * C, per)]
+    with ThreadPoolExecutor(max_workers=max(1, rep.threads)) as pool:
+        for k in range(n_rounds):
+            list(pool.map(lambda p: rep._sweeps(tabs[p[0]], None, target, p[1], p[2]), parts))
+            rep.sweeps_done += S
+            if M > 1:
+                a, t = pt_exchange(beta, C, rep.seed, rep.sweeps_done, (first_parity + k) & 1, rows, rep.energy)
+                acc += a
+                att += t
+    return acc, att
+
+
+def _apt_ladder(rep, beta_first, alpha, sigma_min, equil, meas, max_temps):
+    """Adaptive ladder (appendix A): at beta_i every replica runs `equil`
+    sweeps, then `meas` sweeps after each of which all replica energies are
+    sampled; sigma_i is their spread and beta_{i+1} = beta_i + alpha / sigma_i,
+    until sigma_i <= sigma_min or max_temps positions exist.  The replicas
+    carry their states from one temperature to the next."""
+    betas, sigmas = [], []
+    b = float(beta_first)
+    while True:
+        if equil:
+            rep.anneal(np.full((1, int(equil)), b))
+        samples = []
+        for _ in range(int(meas)):
+            rep.anneal(np.full((1, 1), b))
+            samples.append(np.array(rep.energy, np.int64))
+        s = energy_sigma(np.concatenate(samples))
+        betas.append(b)
+        sigmas.append(s)
+        if s <= sigma_min or len(betas) >= max_temps:
+            break
+        b = b + alpha / s
+    return np.array(betas), np.array(sigmas)

@@ -22,6 +22,9 @@
  *   - QAP cost (Koopmans-Beckmann form, subsection "Quadratic Assignment
  *     Problems") with pairwise-swap Metropolis moves and the per-facility
  *     assignment-frequency backbone.
+ *   - replica exchange between neighbouring temperatures and the energy
+ *     spread that sets the adaptive temperature ladder (appendix A,
+ *     "Adaptive Parallel Tempering"; the first step of algorithm 1).
  *
  * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random
  * numbers: as easy as 1, 2, 3", SC'11), written here from that paper's
@@ -40,6 +43,7 @@
 #define ORC_STREAM_INIT 1u
 #define ORC_STREAM_QAP_SWEEP 2u
 #define ORC_STREAM_QAP_INIT 3u
+#define ORC_STREAM_PT_SWAP 4u
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon et al. SC'11, section 3.3 "Philox")                 */
@@ -488,4 +492,74 @@ void orc_qap_backbone(int32_t n, int32_t R, const uint8_t *perm, int32_t thr_num
     }
     if (!freq)
         free(h);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Parallel tempering (appendix A, "Adaptive Parallel Tempering")            */
+/* ------------------------------------------------------------------------ */
+
+/* Replicas are laid out temperature-major: replica r = i * n_chains + c holds
+ * ladder position i (inverse temperature beta[i], ascending in i) of chain c.
+ * One exchange step offers, in every chain, the neighbour pairs (i, i + 1)
+ * for i = parity, parity + 2, ... (disjoint pairs; the caller alternates the
+ * parity).  The pair exchanges its two configurations with probability
+ * p = min{1, exp[(beta_i - beta_{i+1}) (E_i - E_{i+1})]} (appendix A, the
+ * replica-exchange rule), so p = 1 when E_i <= E_{i+1}.  Otherwise the pair
+ * draws word 0 of the Philox block at counter (c, t, i, PT_SWAP) and swaps iff
+ * u < orc_qap_threshold(beta_{i+1} - beta_i, E_i - E_{i+1}): the factored
+ * threshold of the QAP moves, since energy gaps between replicas span the
+ * whole energy range.  t is the number of sweeps done when the step is taken.
+ * rows is [R][row_len] (spins or assignments) and energy [R]; both move with
+ * the configuration.  accepted / attempted [n_temps - 1] count per pair
+ * position. */
+void orc_pt_exchange(int32_t n_temps, int32_t n_chains, const double *beta, uint64_t seed, uint32_t t,
+                     int32_t parity, int32_t row_len, uint8_t *rows, int64_t *energy, int64_t *accepted,
+                     int64_t *attempted)
+{
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    for (int32_t i = parity; i + 1 < n_temps; i += 2) {
+        double dbeta = beta[i + 1] - beta[i];
+        for (int32_t c = 0; c < n_chains; ++c) {
+            int64_t a = (int64_t)i * n_chains + c;
+            int64_t b = a + n_chains;
+            int64_t d = energy[a] - energy[b];
+            int accept = d <= 0;
+            if (!accept) {
+                uint32_t ctr[4] = { (uint32_t)c, t, (uint32_t)i, ORC_STREAM_PT_SWAP };
+                uint32_t out[4];
+                orc_philox4x32_10(ctr, key, out);
+                accept = out[0] < orc_qap_threshold(dbeta, d);
+            }
+            attempted[i]++;
+            if (accept) {
+                accepted[i]++;
+                for (int32_t k = 0; k < row_len; ++k) {
+                    uint8_t tmp = rows[(size_t)a * row_len + k];
+                    rows[(size_t)a * row_len + k] = rows[(size_t)b * row_len + k];
+                    rows[(size_t)b * row_len + k] = tmp;
+                }
+                int64_t te = energy[a];
+                energy[a] = energy[b];
+                energy[b] = te;
+            }
+        }
+    }
+}
+
+/* Energy spread at one inverse temperature (appendix A):
+ * sigma^2 = <E^2> - <E>^2 over the samples.  Energies are non-negative and
+ * below 2^32, so with S1 = sum E and S2 = sum E^2 the numerator
+ * count * S2 - S1^2 is an exact 128-bit integer; it is rounded to double once
+ * and divided by count^2 (exact in double for count < 2^26). */
+double orc_energy_sigma(const int64_t *e, int64_t count)
+{
+    unsigned __int128 s1 = 0, s2 = 0;
+    for (int64_t k = 0; k < count; ++k) {
+        unsigned __int128 v = (unsigned __int128)(uint64_t)e[k];
+        s1 += v;
+        s2 += v * v;
+    }
+    unsigned __int128 num = (unsigned __int128)(uint64_t)count * s2 - s1 * s1;
+    double var = (double)num / ((double)count * (double)count);
+    return sqrt(var);
 }

@@ -61,6 +61,20 @@ def gen_ksat(n_vars: int, alpha, k: int, seed: int):
     return clause_ptr, lits
 
 
+def gen_ksat_disjoint(n_clauses: int, k: int, seed: int):
+    """k-SAT formula whose clauses share no variable: clause a holds variables
+    k*a .. k*a+k-1 with fair-coin signs (N = k * n_clauses).  Its energy at
+    inverse temperature beta is a sum of independent clause indicators, so its
+    equilibrium statistics have closed forms.  Same return convention as
+    gen_ksat."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    v = np.arange(n_clauses * k, dtype=np.int64).reshape(n_clauses, k)
+    neg = rng.integers(0, 2, size=(n_clauses, k), dtype=np.int64)
+    lits = ((v + 1) * (1 - 2 * neg)).astype(np.int32).reshape(-1)
+    clause_ptr = (np.arange(n_clauses + 1, dtype=np.int64) * k).astype(np.int32)
+    return clause_ptr, lits
+
+
 def gen_qap(n: int, seed: int, lo: int = 0, hi: int = 99):
     """Symmetric flow and distance matrices with zero diagonal and integer
     entries uniform in [lo, hi].  Returns (F, D) as int32[n, n]."""
