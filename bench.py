@@ -220,6 +220,68 @@ def bench_qap(nmc, torch, seed, sweeps_only=0):
             "beta_unit": sc, "best_cost": be["best"], "sweeps": S_tot}
 
 
+APT_TEMPS, APT_CHAINS, APT_BETA_FIRST, APT_ALPHA = 64, 16, 1.5, 1.1
+APT_EQUIL, APT_MEAS, APT_ROUNDS = 20, 5, 2000
+
+
+def bench_apt(nmc, torch, seed, rounds, sweeps_per_round):
+    """Adaptive parallel tempering on the N = 50,000 4-SAT instance: the
+    adaptive ladder (64 positions from beta 1.5, alpha 1.1, 20 + 5 sweeps per
+    position) built on the 1024 replicas, then `rounds` rounds of
+    [sweeps_per_round sweeps at every position -> one exchange step] over 16
+    chains."""
+    cp, lits = instances.gen_ksat(N, ALPHA, K, seed)
+    inst = nmc.Instance.ksat(N, cp, lits, CLASS_CAP).bind()
+    M = inst.info.n_clauses
+    Rp = APT_TEMPS * APT_CHAINS
+
+    def step(profile):
+        rep = nmc.Replicas(inst, Rp, seed)
+        rep.set_profiling(profile)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        betas, sigmas = rep.apt_ladder(APT_BETA_FIRST, APT_ALPHA, 0.0, APT_EQUIL, APT_MEAS, APT_TEMPS)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        acc, att = rep.pt_run(betas, rounds, sweeps_per_round)
+        be = rep.best_energy()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return rep, betas, sigmas, acc, att, be, t1 - t0, t2 - t1
+
+    step(False)  # warm-up
+    rep, betas, sigmas, acc, att, be, t_ladder, t_pt = step(False)
+    ladder_sweeps = len(betas) * (APT_EQUIL + APT_MEAS)
+    pt_sweeps = rounds * sweeps_per_round
+    att_ladder = float(Rp) * N * ladder_sweeps
+    att_pt = float(Rp) * N * pt_sweeps
+    # sweep-kernel time of the tempering rounds from HIP events (separate pass)
+    prep = nmc.Replicas(inst, Rp, seed)
+    prep.anneal(np.full((1, 50), betas[0]))
+    prep.set_profiling(True)
+    prep.pt_run(betas, min(rounds, 500), sweeps_per_round)
+    kt = prep.kernel_time()
+    kern_ms = kt["ms"] / max(1, kt["launches"])
+    deg_mean = K * M / N
+    ops_per_attempt = (OPS_PER_SLOT * deg_mean + OPS_PER_VAR) / 4.0
+    achieved = kt["attempts"] / (kt["ms"] / 1000.0) * ops_per_attempt
+    rate = acc / np.maximum(att, 1)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                "unit": "T lane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                "kernel": "ksat_sweep_kernel", "kernel_ms_per_launch": kern_ms,
+                "kernel_attempts_per_s": kt["attempts"] / (kt["ms"] / 1000.0), "launches": kt["launches"]}
+    return {"attempts": att_ladder + att_pt, "wall_s": t_ladder + t_pt,
+            "attempts_per_s": (att_ladder + att_pt) / (t_ladder + t_pt),
+            "ladder_s": t_ladder, "ladder_attempts_per_s": att_ladder / t_ladder,
+            "pt_s": t_pt, "pt_attempts_per_s": att_pt / t_pt, "pt_rounds_per_s": rounds / t_pt,
+            "sweep_kernel_share_of_pt": kt["ms"] / 1000.0 * rounds / min(rounds, 500) / t_pt,
+            "ladder": {"positions": len(betas), "beta_first": float(betas[0]), "beta_last": float(betas[-1]),
+                       "sigma_first": float(sigmas[0]), "sigma_last": float(sigmas[-1])},
+            "exchange_rate": {"min": float(rate.min()), "mean": float(rate.mean()), "max": float(rate.max())},
+            "best_energy": be["best"], "roofline": roofline, "rounds": rounds,
+            "sweeps_per_round": sweeps_per_round, "replicas": Rp, "chains": APT_CHAINS}
+
+
 SERVE_RATE, SERVE_SECONDS, SERVE_BUDGET_S = 50.0, 60.0, 2.0
 SERVE_SCHED = (150, 2, 50)  # anneal sweeps, rounds, reanneal sweeps per request
 SERVE_CHUNK = 25
@@ -390,9 +452,12 @@ def main():
     ap.add_argument("--no-ttt", action="store_true")
     ap.add_argument("--block-threads", type=int, default=0)
     ap.add_argument("--class-cap", type=int, default=CLASS_CAP)
-    ap.add_argument("--workload", choices=["nmc", "batch", "qap", "serve"], default="nmc",
+    ap.add_argument("--workload", choices=["nmc", "batch", "qap", "serve", "apt"], default="nmc",
                     help="nmc: the N=50000 NMC path (default); batch: 256 mixed instances, batched vs "
-                         "per-instance; qap: the n=100 QAP path; serve: Poisson stream into the server")
+                         "per-instance; qap: the n=100 QAP path; serve: Poisson stream into the server; "
+                         "apt: adaptive parallel tempering on the N=50000 instance")
+    ap.add_argument("--pt-rounds", type=int, default=APT_ROUNDS)
+    ap.add_argument("--pt-sweeps-per-round", type=int, default=1)
     ap.add_argument("--serve-seconds", type=float, default=SERVE_SECONDS)
     ap.add_argument("--sweeps-only", type=int, default=0,
                     help="only time one homogeneous anneal of this many sweeps (for counter profiles) and exit")
@@ -429,6 +494,16 @@ def main():
                           "data": "synthetic",
                           "config": {"workload": "QAP n=100, 4096 replicas, anneal 5000 + 2x(backbone + reanneal 1000)"},
                           "roofline": res["roofline"], "qap": res}), flush=True)
+        return
+    if args.workload == "apt":
+        res = bench_apt(nmc, torch, seed, args.pt_rounds, args.pt_sweeps_per_round)
+        print(json.dumps({"metric": "spin-flip attempts/s (adaptive ladder + parallel tempering)",
+                          "value": res["attempts_per_s"], "unit": "attempts/s", "n_gpus": 1,
+                          "higher_is_better": True, "dtype": "int32", "data": "synthetic",
+                          "config": {"workload": f"APT random 4-SAT N=50000 alpha=9.9, {APT_TEMPS} temperatures x "
+                                                 f"{APT_CHAINS} chains, ladder + {args.pt_rounds} rounds of "
+                                                 f"{args.pt_sweeps_per_round} sweep(s) + exchange"},
+                          "roofline": res["roofline"], "apt": res}), flush=True)
         return
     if args.workload == "serve":
         res = bench_serve(nmc, torch, seed, args.serve_seconds)

@@ -211,6 +211,57 @@ int nmc_estimate_backbone(nmc_replicas *rep, int32_t thr_num, int32_t thr_den, i
                           int32_t *counts_out, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * parallel tempering (appendix A, "Adaptive Parallel Tempering"; the
+ * replica-exchange step that opens Algorithm 1)
+ * ------------------------------------------------------------------------- */
+
+/* n_rounds rounds of replica-exchange Monte Carlo.  The R replicas form
+ * C = R / n_temps independent chains, laid out temperature-major: replica
+ * r = i * C + c holds ladder position i of chain c and sweeps at beta[i].
+ * C must be a multiple of 4 (k-SAT) or 16 (QAP), so that the replicas one
+ * sweep workgroup owns share a temperature.
+ *   beta[n_temps]     host doubles, finite, >= 0, strictly increasing (position
+ *                     0 is the hottest)
+ *   sweeps_per_round  >= 1 Metropolis sweeps of every replica at its own
+ *                     temperature (the nmc_anneal rules, sweep counter
+ *                     continuing), then one exchange step
+ *   first_parity      the exchange step of round k offers the pairs
+ *                     (i, i + 1), i = p, p + 2, ... with p = (first_parity + k)
+ *                     mod 2, in every chain
+ *   target            as nmc_anneal (first_hit of each replica slot)
+ *   accepted, attempted  optional host arrays [n_temps - 1]: exchanges taken
+ *                     and offered per pair position during this call
+ * Exchange: the pair swaps its configurations (and their energies) with
+ * probability min{1, exp[(beta_i - beta_{i+1})(E_i - E_{i+1})]}: always when
+ * E_i <= E_{i+1}; otherwise iff u < T with u word 0 of the Philox block at
+ * counter (c, sweeps done, i, 4) and T the two-level threshold of nmc_anneal
+ * at beta_{i+1} - beta_i and gap E_i - E_{i+1}.  Best energies, best-state
+ * snapshots and first-hit sweeps belong to replica slots (ladder positions)
+ * and are updated at sweep boundaries only.  n_temps = 1 runs plain sweeps.
+ * The exchange tables and counters live in the library-owned upload buffer.
+ * Errors: INVALID (layout, ladder, counts), STATE (unbound), CAPACITY (LDS,
+ * or a ladder step too fine for the energy range), DEVICE. */
+int nmc_pt_run(nmc_replicas *rep, const double *beta, int32_t n_temps, int32_t n_rounds, int32_t sweeps_per_round,
+               int32_t first_parity, int64_t target, int64_t *accepted, int64_t *attempted, void *stream);
+
+/* Adaptive temperature ladder (appendix A).  Starting at beta_first, all
+ * replicas run equil_sweeps sweeps at the current beta_i, then meas_sweeps
+ * sweeps after each of which every replica's energy is sampled on the
+ * device; sigma_i = sqrt(<E^2> - <E>^2) over those R * meas_sweeps samples,
+ * evaluated as (n S2 - S1^2) / n^2 with exact integer sums and one rounding.
+ * The next position is beta_i + alpha / sigma_i; the ladder ends at the first
+ * sigma_i <= sigma_min, or after max_temps positions.  The replicas carry
+ * their states from one temperature to the next (the sweep counter advances
+ * by equil_sweeps + meas_sweeps per position).
+ *   beta_out, sigma_out  host arrays of max_temps doubles; *n_temps receives
+ *                        the positions written
+ * alpha > 0 (about 1.1 per appendix A), sigma_min >= 0, meas_sweeps >= 1,
+ * R * meas_sweeps <= 2^26.  Errors: INVALID, STATE, CAPACITY, DEVICE. */
+int nmc_apt_ladder(nmc_replicas *rep, double beta_first, double alpha, double sigma_min, int32_t equil_sweeps,
+                   int32_t meas_sweeps, int32_t max_temps, double *beta_out, double *sigma_out, int32_t *n_temps,
+                   void *stream);
+
+/* ---------------------------------------------------------------------------
  * best_energy and state access
  * ------------------------------------------------------------------------- */
 
@@ -247,7 +298,8 @@ int nmc_set_tuning(nmc_replicas *rep, int32_t block_threads);
 /* When enabled, every sweep-kernel launch is bracketed by HIP events on the
  * launch stream; nmc_kernel_time() then returns the summed kernel time (ms),
  * the number of sweep-kernel launches and the Metropolis attempts they made
- * since the last reset.  Enabling it adds a stream synchronization per call. */
+ * since the last reset (nmc_pt_run counts its sweep launches, not its
+ * exchange launches).  Enabling it adds a stream synchronization per call. */
 int nmc_set_profiling(nmc_replicas *rep, int32_t enable);
 int nmc_kernel_time(nmc_replicas *rep, double *ms, int64_t *launches, double *attempts, int32_t reset);
 

@@ -79,7 +79,7 @@ def lib():
                                          _I64, _P, _P, _P, _P, _P]
             L.orc_qap_anneal.restype = ctypes.c_int
             L.orc_qap_backbone.argtypes = [_I32, _I32, _P, _I32, _I32, _P, _P]
-            L.orc_pt_exchange.argtypes = [_I32, _I32, _P, _U64, _U32, _I32, _I32, _P, _P, _P, _P]
+            L.orc_pt_exchange.argtypes = [_I32, _I32, _I32, _I32, _P, _U64, _U32, _I32, _I32, _P, _P, _P, _P]
             L.orc_energy_sigma.argtypes = [_P, _I64]
             L.orc_energy_sigma.restype = _D
             _lib = L
@@ -197,8 +197,8 @@ class KSatReplicas:
                               _p(self.x), _p(self.energy), _p(self.best), _p(self.first_hit),
                               _p(self.best_x))
 
-    def pt_run(self, beta, n_rounds, sweeps_per_round, first_parity=0, target=-1):
-        return _pt_run(self, self.x, beta, n_rounds, sweeps_per_round, first_parity, target)
+    def pt_run(self, beta, n_rounds, sweeps_per_round, first_parity=0, target=-1, chains=None):
+        return _pt_run(self, self.x, beta, n_rounds, sweeps_per_round, first_parity, target, chains)
 
     def apt_ladder(self, beta_first, alpha, sigma_min, equil, meas, max_temps):
         return _apt_ladder(self, beta_first, alpha, sigma_min, equil, meas, max_temps)
@@ -265,8 +265,8 @@ class QapReplicas:
     def energy(self):
         return self.cost
 
-    def pt_run(self, beta, n_rounds, sweeps_per_round, first_parity=0, target=-1):
-        return _pt_run(self, self.perm, beta, n_rounds, sweeps_per_round, first_parity, target)
+    def pt_run(self, beta, n_rounds, sweeps_per_round, first_parity=0, target=-1, chains=None):
+        return _pt_run(self, self.perm, beta, n_rounds, sweeps_per_round, first_parity, target, chains)
 
     def apt_ladder(self, beta_first, alpha, sigma_min, equil, meas, max_temps):
         return _apt_ladder(self, beta_first, alpha, sigma_min, equil, meas, max_temps)
@@ -287,29 +287,34 @@ def energy_sigma(samples):
     return float(lib().orc_energy_sigma(_p(e), e.size))
 
 
-def pt_exchange(beta, n_chains, seed, t, parity, rows, energy):
+def pt_exchange(beta, n_chains, seed, t, parity, rows, energy, chains=None):
     """One exchange step on rows [R][row_len] and energies [R] (both updated
-    in place); returns (accepted, attempted) per pair position."""
+    in place) for chains[0]..chains[1]-1 (default all); returns (accepted,
+    attempted) per pair position."""
     beta = _c(beta, np.float64)
     M = beta.size
     acc = np.zeros(max(M - 1, 1), np.int64)
     att = np.zeros(max(M - 1, 1), np.int64)
     e = _c(energy, np.int64)
-    lib().orc_pt_exchange(M, int(n_chains), _p(beta), int(seed), int(t), int(parity), rows.shape[1], _p(rows),
-                          _p(e), _p(acc), _p(att))
+    c0, c1 = (0, int(n_chains)) if chains is None else chains
+    lib().orc_pt_exchange(M, int(n_chains), c0, c1, _p(beta), int(seed), int(t), int(parity), rows.shape[1],
+                          _p(rows), _p(e), _p(acc), _p(att))
     energy[:] = e
     return acc[: M - 1], att[: M - 1]
 
 
-def _pt_run(rep, rows, beta, n_rounds, sweeps_per_round, first_parity, target):
+def _pt_run(rep, rows, beta, n_rounds, sweeps_per_round, first_parity, target, chains=None):
     """Parallel tempering rounds (appendix A).  Replica r = i * C + c runs at
     beta[i]; every round is sweeps_per_round Metropolis sweeps of every
     replica at its ladder temperature, then one exchange step with parity
-    (first_parity + round) mod 2.  Returns summed (accepted, attempted)."""
+    (first_parity + round) mod 2.  chains = (c0, c1) follows only those
+    chains (the other replicas are left untouched).  Returns summed
+    (accepted, attempted) of the chains followed."""
     beta = _c(beta, np.float64)
     M = beta.size
     C = rep.R // M
     assert C * M == rep.R
+    c0, c1 = (0, C) if chains is None else chains
     S = int(sweeps_per_round)
     acc = np.zeros(max(M - 1, 0), np.int64)
     att = np.zeros(max(M - 1, 0), np.int64)
@@ -317,13 +322,14 @@ def _pt_run(rep, rows, beta, n_rounds, sweeps_per_round, first_parity, target):
     parts = []
     per = max(1, rep.threads // M) if M else 1
     for i in range(M):
-        parts += [(i, a, b) for a, b in _split(i * C, (i + 1) * C, per)]
+        parts += [(i, a, b) for a, b in _split(i * C + c0, i * C + c1, per)]
     with ThreadPoolExecutor(max_workers=max(1, rep.threads)) as pool:
         for k in range(n_rounds):
             list(pool.map(lambda p: rep._sweeps(tabs[p[0]], None, target, p[1], p[2]), parts))
             rep.sweeps_done += S
             if M > 1:
-                a, t = pt_exchange(beta, C, rep.seed, rep.sweeps_done, (first_parity + k) & 1, rows, rep.energy)
+                a, t = pt_exchange(beta, C, rep.seed, rep.sweeps_done, (first_parity + k) & 1, rows, rep.energy,
+                                   (c0, c1))
                 acc += a
                 att += t
     return acc, att

@@ -510,16 +510,17 @@ void orc_qap_backbone(int32_t n, int32_t R, const uint8_t *perm, int32_t thr_num
  * threshold of the QAP moves, since energy gaps between replicas span the
  * whole energy range.  t is the number of sweeps done when the step is taken.
  * rows is [R][row_len] (spins or assignments) and energy [R]; both move with
- * the configuration.  accepted / attempted [n_temps - 1] count per pair
- * position. */
-void orc_pt_exchange(int32_t n_temps, int32_t n_chains, const double *beta, uint64_t seed, uint32_t t,
-                     int32_t parity, int32_t row_len, uint8_t *rows, int64_t *energy, int64_t *accepted,
-                     int64_t *attempted)
+ * the configuration.  Only chains c_begin..c_end-1 are stepped (chains are
+ * independent, so a sample of them can be followed alone).  accepted /
+ * attempted [n_temps - 1] count per pair position. */
+void orc_pt_exchange(int32_t n_temps, int32_t n_chains, int32_t c_begin, int32_t c_end, const double *beta,
+                     uint64_t seed, uint32_t t, int32_t parity, int32_t row_len, uint8_t *rows, int64_t *energy,
+                     int64_t *accepted, int64_t *attempted)
 {
     uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
     for (int32_t i = parity; i + 1 < n_temps; i += 2) {
         double dbeta = beta[i + 1] - beta[i];
-        for (int32_t c = 0; c < n_chains; ++c) {
+        for (int32_t c = c_begin; c < c_end; ++c) {
             int64_t a = (int64_t)i * n_chains + c;
             int64_t b = a + n_chains;
             int64_t d = energy[a] - energy[b];

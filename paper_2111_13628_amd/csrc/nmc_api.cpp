@@ -101,6 +101,8 @@ struct nmc_instance {
     // QAP host data
     int64_t delta_bound = 0;
     int32_t qap_ha = 0;
+    // largest energy any state can have (k-SAT: M; QAP: sum F * max D)
+    int64_t energy_bound = 0;
     size_t off_F = 0, off_D = 0;
     // packed host image of the device arena
     std::vector<uint8_t> image;
@@ -338,6 +340,7 @@ int nmc_ksat_load(int32_t n_vars, int32_t n_clauses, const int32_t *clause_ptr, 
         I->kind = NMC_KIND_KSAT;
         I->n = n_vars;
         I->m = n_clauses;
+        I->energy_bound = n_clauses;
         I->kmax = kmax;
         const int32_t n = n_vars, m = n_clauses;
 
@@ -547,6 +550,10 @@ int nmc_qap_load(int32_t n, const int32_t *flow, const int32_t *dist, nmc_instan
         I->kind = NMC_KIND_QAP;
         I->n = n;
         I->delta_bound = 2ll * (n - 2) * fmax * dmax;
+        int64_t fsum = 0;
+        for (size_t i = 0; i < (size_t)n * n; ++i)
+            fsum += flow[i];
+        I->energy_bound = fsum * dmax;
         I->qap_ha = (int32_t)(I->delta_bound >> kQapLowBits) + 1;
         Arena ar;
         I->off_F = ar.take((size_t)n * n);
@@ -622,6 +629,8 @@ struct nmc_replicas {
     // library-owned threshold / class upload buffer
     uint8_t *tab_dev = nullptr;
     size_t tab_cap = 0;
+    // energy-moment accumulators of the tempering ladder (library-owned)
+    unsigned long long *pt_acc = nullptr;
     // profiling
     bool profiling = false;
     double prof_ms = 0;
@@ -803,10 +812,12 @@ int nmc_replicas_create(nmc_instance *I, int32_t n_replicas, uint64_t seed, void
 void nmc_replicas_free(nmc_replicas *P) {
     if (!P)
         return;
-    if (P->tab_dev) {
+    if (P->tab_dev || P->pt_acc)
         (void)hipDeviceSynchronize();
+    if (P->tab_dev)
         (void)hipFree(P->tab_dev);
-    }
+    if (P->pt_acc)
+        (void)hipFree(P->pt_acc);
     if (P->inst)
         P->inst->live_replicas--;
     delete P;
@@ -1169,6 +1180,271 @@ int nmc_set_profiling(nmc_replicas *P, int32_t enable) {
         return fail(NMC_ERR_INVALID, "NULL replicas");
     P->profiling = enable != 0;
     return ok();
+}
+
+// ---------------------------------------------------------------------------
+// parallel tempering (appendix A)
+// ---------------------------------------------------------------------------
+
+static int pt_run_impl(nmc_replicas *P, const double *beta, int32_t n_temps, int32_t n_rounds,
+                       int32_t sweeps_per_round, int32_t first_parity, int64_t target, int64_t *accepted,
+                       int64_t *attempted, void *stream) {
+    if (!P || !beta)
+        return fail(NMC_ERR_INVALID, "NULL argument");
+    nmc_instance *I = P->inst;
+    if (!I->dev)
+        return fail(NMC_ERR_STATE, "instance is not bound");
+    const bool ksat = I->kind == NMC_KIND_KSAT;
+    if (n_temps < 1 || P->R % n_temps)
+        return fail(NMC_ERR_INVALID, "n_temps = %d must be >= 1 and divide the %d replicas", n_temps, P->R);
+    const int32_t chains = P->R / n_temps;
+    const int32_t unit = ksat ? kGroup : kQapRepPerBlock;
+    if (chains % unit)
+        return fail(NMC_ERR_INVALID, "replicas / n_temps = %d chains must be a multiple of %d", chains, unit);
+    if (n_rounds < 0 || sweeps_per_round < 1)
+        return fail(NMC_ERR_INVALID, "need n_rounds >= 0 and sweeps_per_round >= 1");
+    if (first_parity != 0 && first_parity != 1)
+        return fail(NMC_ERR_INVALID, "first_parity must be 0 or 1");
+    if ((uint64_t)P->sweeps_done + (uint64_t)n_rounds * (uint64_t)sweeps_per_round > 0xFFFFFFFFull)
+        return fail(NMC_ERR_INVALID, "sweep counter would pass 2^32 - 1");
+    for (int32_t i = 0; i < n_temps; ++i) {
+        if (!std::isfinite(beta[i]) || beta[i] < 0)
+            return fail(NMC_ERR_INVALID, "beta[%d] = %g is not finite and >= 0", i, beta[i]);
+        if (i > 0 && !(beta[i] > beta[i - 1]))
+            return fail(NMC_ERR_INVALID, "the ladder must increase strictly (beta[%d] <= beta[%d])", i, i - 1);
+    }
+    hipStream_t s = as_stream(stream);
+    const int32_t stride = ksat ? I->dmax + 1 : I->qap_ha + (1 << kQapLowBits);
+    const size_t lds = ksat ? ksat_sweep_lds_bytes(I->n, 1, stride) : qap_sweep_lds_bytes(I->n, 1, stride);
+    if (lds > kLdsBytes)
+        return fail(NMC_ERR_CAPACITY, "sweep needs %zu bytes of LDS (limit %zu)", lds, kLdsBytes);
+    if (ksat && target > INT32_MAX)
+        target = INT32_MAX;
+
+    // sweep thresholds, one row per ladder position
+    std::vector<uint32_t> tab((size_t)n_temps * stride);
+    for (int32_t i = 0; i < n_temps; ++i) {
+        uint32_t *row = tab.data() + (size_t)i * stride;
+        row[0] = 0xFFFFFFFFu;
+        if (ksat) {
+            for (int32_t d = 1; d < stride; ++d)
+                row[d] = threshold(beta[i], d);
+        } else {
+            const int32_t ha = I->qap_ha;
+            for (int32_t h = 1; h < ha; ++h)
+                row[h] = threshold(beta[i], (int64_t)h << kQapLowBits);
+            row[ha] = 0xFFFFFFFFu;
+            for (int32_t l = 1; l < (1 << kQapLowBits); ++l)
+                row[ha + l] = threshold(beta[i], l);
+        }
+    }
+    // exchange thresholds of every neighbour pair: the high digit runs until
+    // it reaches zero (every larger gap then has threshold zero) or covers the
+    // largest possible energy gap; the 1024 low-digit words follow it
+    const int32_t npairs = n_temps - 1;
+    std::vector<int64_t> off(std::max(npairs, 1));
+    std::vector<int32_t> len(std::max(npairs, 1));
+    const size_t xtab_at = tab.size();
+    const int64_t hmax = I->energy_bound >> kQapLowBits;
+    for (int32_t i = 0; i < npairs; ++i) {
+        const double db = beta[i + 1] - beta[i];
+        off[i] = (int64_t)(tab.size() - xtab_at);
+        tab.push_back(0xFFFFFFFFu);
+        for (int64_t h = 1; h <= hmax; ++h) {
+            const uint32_t v = threshold(db, h << kQapLowBits);
+            if (!v)
+                break;
+            tab.push_back(v);
+            if (tab.size() - xtab_at > ((size_t)1 << 26))
+                return fail(NMC_ERR_CAPACITY, "ladder step %d (%g) is too fine for the energy range", i, db);
+        }
+        len[i] = (int32_t)(tab.size() - xtab_at - off[i]);
+        tab.push_back(0xFFFFFFFFu);
+        for (int32_t l = 1; l < (1 << kQapLowBits); ++l)
+            tab.push_back(threshold(db, l));
+    }
+    const size_t tab_bytes = align_up(tab.size() * 4, 256);
+    const size_t off_bytes = align_up(off.size() * 8, 256), len_bytes = align_up(len.size() * 4, 256);
+    const size_t cnt_bytes = align_up((size_t)std::max(npairs, 1) * 8, 256);
+    int rc = ensure_tab(P, tab_bytes + off_bytes + len_bytes + 2 * cnt_bytes);
+    if (rc)
+        return rc;
+    uint8_t *base = P->tab_dev;
+    HIP_OR_FAIL(hipMemcpyAsync(base, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, s));
+    HIP_OR_FAIL(hipMemcpyAsync(base + tab_bytes, off.data(), off.size() * 8, hipMemcpyHostToDevice, s));
+    HIP_OR_FAIL(hipMemcpyAsync(base + tab_bytes + off_bytes, len.data(), len.size() * 4, hipMemcpyHostToDevice, s));
+    unsigned long long *acc_dev = reinterpret_cast<unsigned long long *>(base + tab_bytes + off_bytes + len_bytes);
+    unsigned long long *att_dev = reinterpret_cast<unsigned long long *>(base + tab_bytes + off_bytes + len_bytes +
+                                                                         cnt_bytes);
+    HIP_OR_FAIL(hipMemsetAsync(acc_dev, 0, 2 * cnt_bytes, s));
+
+    PtCall X{};
+    X.tab = reinterpret_cast<const uint32_t *>(base) + xtab_at;
+    X.off = reinterpret_cast<const int64_t *>(base + tab_bytes);
+    X.len = reinterpret_cast<const int32_t *>(base + tab_bytes + off_bytes);
+    X.accepted = acc_dev;
+    X.attempted = att_dev;
+    X.n_temps = n_temps;
+    X.n_chains = chains;
+    X.key0 = (uint32_t)P->seed;
+    X.key1 = (uint32_t)(P->seed >> 32);
+
+    std::vector<hipEvent_t> ev;
+    for (int32_t k = 0; k < n_rounds; ++k) {
+        if (P->profiling) {
+            ev.resize(ev.size() + 2);
+            HIP_OR_FAIL(hipEventCreate(&ev[ev.size() - 2]));
+            HIP_OR_FAIL(hipEventCreate(&ev[ev.size() - 1]));
+            HIP_OR_FAIL(hipEventRecord(ev[ev.size() - 2], s));
+        }
+        if (ksat) {
+            SweepCall C{};
+            C.tab = reinterpret_cast<const uint32_t *>(base);
+            C.var_cls = nullptr;
+            C.n_classes = 1;
+            C.stride = stride;
+            C.n_sweeps = sweeps_per_round;
+            C.sweep_words = 0;
+            C.t0 = P->sweeps_done;
+            C.target = (int32_t)std::max<int64_t>(std::min<int64_t>(target, INT32_MAX), INT32_MIN);
+            C.check_start = 1;
+            C.key0 = X.key0;
+            C.key1 = X.key1;
+            C.reps_per_row = chains;
+            HIP_OR_FAIL(ksat_launch_sweep(I->ksat_dev(), P->k, C, P->block_threads, s));
+        } else {
+            QapCall C{};
+            C.tab = reinterpret_cast<const uint32_t *>(base);
+            C.fac_cls = nullptr;
+            C.n_classes = 1;
+            C.stride = stride;
+            C.n_sweeps = sweeps_per_round;
+            C.sweep_words = 0;
+            C.t0 = P->sweeps_done;
+            C.target = target;
+            C.check_start = 1;
+            C.rows = qap_rows_setting();
+            C.key0 = X.key0;
+            C.key1 = X.key1;
+            C.reps_per_row = chains;
+            HIP_OR_FAIL(qap_launch_sweep(I->qap_dev(), P->q, C, 256, s));
+        }
+        if (P->profiling)
+            HIP_OR_FAIL(hipEventRecord(ev.back(), s));
+        P->sweeps_done += (uint32_t)sweeps_per_round;
+        if (n_temps > 1) {
+            X.parity = (first_parity + k) & 1;
+            X.t = P->sweeps_done;
+            HIP_OR_FAIL(ksat ? pt_launch_exchange_ksat(I->ksat_dev(), P->k, X, s)
+                             : pt_launch_exchange_qap(I->qap_dev(), P->q, X, s));
+        }
+    }
+    if (!ev.empty()) {
+        HIP_OR_FAIL(hipEventSynchronize(ev.back()));
+        for (size_t e = 0; e < ev.size(); e += 2) {
+            float ms = 0;
+            HIP_OR_FAIL(hipEventElapsedTime(&ms, ev[e], ev[e + 1]));
+            P->prof_ms += ms;
+        }
+        for (hipEvent_t e : ev)
+            (void)hipEventDestroy(e);
+        P->prof_launches += n_rounds;
+        const double per_sweep = ksat ? (double)P->R * I->n : (double)P->R * I->n * (I->n - 1) / 2.0;
+        P->prof_attempts += per_sweep * sweeps_per_round * n_rounds;
+    }
+    if (npairs > 0 && (accepted || attempted)) {
+        std::vector<int64_t> a(npairs), t(npairs);
+        HIP_OR_FAIL(hipMemcpyAsync(a.data(), acc_dev, (size_t)npairs * 8, hipMemcpyDeviceToHost, s));
+        HIP_OR_FAIL(hipMemcpyAsync(t.data(), att_dev, (size_t)npairs * 8, hipMemcpyDeviceToHost, s));
+        HIP_OR_FAIL(hipStreamSynchronize(s));
+        for (int32_t i = 0; i < npairs; ++i) {
+            if (accepted)
+                accepted[i] = a[i];
+            if (attempted)
+                attempted[i] = t[i];
+        }
+    }
+    return ok();
+}
+
+int nmc_pt_run(nmc_replicas *P, const double *beta, int32_t n_temps, int32_t n_rounds, int32_t sweeps_per_round,
+               int32_t first_parity, int64_t target, int64_t *accepted, int64_t *attempted, void *stream) {
+    try {
+        return pt_run_impl(P, beta, n_temps, n_rounds, sweeps_per_round, first_parity, target, accepted, attempted,
+                           stream);
+    } catch (const std::bad_alloc &) {
+        return fail(NMC_ERR_CAPACITY, "host allocation failed");
+    }
+}
+
+static int apt_ladder_impl(nmc_replicas *P, double beta_first, double alpha, double sigma_min, int32_t equil_sweeps,
+                           int32_t meas_sweeps, int32_t max_temps, double *beta_out, double *sigma_out,
+                           int32_t *n_temps, void *stream) {
+    if (!P || !beta_out || !sigma_out || !n_temps)
+        return fail(NMC_ERR_INVALID, "NULL argument");
+    nmc_instance *I = P->inst;
+    if (!I->dev)
+        return fail(NMC_ERR_STATE, "instance is not bound");
+    if (!std::isfinite(beta_first) || beta_first < 0)
+        return fail(NMC_ERR_INVALID, "beta_first = %g is not finite and >= 0", beta_first);
+    if (!std::isfinite(alpha) || !(alpha > 0))
+        return fail(NMC_ERR_INVALID, "alpha = %g must be finite and > 0", alpha);
+    if (!std::isfinite(sigma_min) || sigma_min < 0)
+        return fail(NMC_ERR_INVALID, "sigma_min = %g must be finite and >= 0", sigma_min);
+    if (equil_sweeps < 0 || meas_sweeps < 1 || max_temps < 1)
+        return fail(NMC_ERR_INVALID, "need equil_sweeps >= 0, meas_sweeps >= 1 and max_temps >= 1");
+    if ((uint64_t)P->R * (uint64_t)meas_sweeps > ((uint64_t)1 << 26))
+        return fail(NMC_ERR_INVALID, "replicas x meas_sweeps = %lld samples exceeds 2^26",
+                    (long long)P->R * meas_sweeps);
+    if ((uint64_t)P->sweeps_done + (uint64_t)max_temps * (uint64_t)(equil_sweeps + meas_sweeps) > 0xFFFFFFFFull)
+        return fail(NMC_ERR_INVALID, "sweep counter could pass 2^32 - 1");
+    hipStream_t s = as_stream(stream);
+    if (!P->pt_acc)
+        HIP_OR_FAIL(hipMalloc(&P->pt_acc, 256));
+    const bool ksat = I->kind == NMC_KIND_KSAT;
+    const void *energy = ksat ? (const void *)P->k.energy : (const void *)P->q.cost;
+    std::vector<double> row(std::max(equil_sweeps, 1));
+    double b = beta_first;
+    for (int32_t k = 0;; ++k) {
+        if (equil_sweeps) {
+            std::fill(row.begin(), row.end(), b);
+            int rc = anneal_impl(P, row.data(), 1, equil_sweeps, NMC_PROFILE_HOMOGENEOUS, nullptr, -1, stream);
+            if (rc)
+                return rc;
+        }
+        HIP_OR_FAIL(hipMemsetAsync(P->pt_acc, 0, 32, s));
+        for (int32_t m = 0; m < meas_sweeps; ++m) {
+            int rc = anneal_impl(P, &b, 1, 1, NMC_PROFILE_HOMOGENEOUS, nullptr, -1, stream);
+            if (rc)
+                return rc;
+            HIP_OR_FAIL(pt_launch_moments(energy, ksat ? 0 : 1, P->R, P->pt_acc, s));
+        }
+        unsigned long long acc[4];
+        HIP_OR_FAIL(hipMemcpyAsync(acc, P->pt_acc, 32, hipMemcpyDeviceToHost, s));
+        HIP_OR_FAIL(hipStreamSynchronize(s));
+        // sigma^2 = (count S2 - S1^2) / count^2, the numerator exact in 128 bits
+        const unsigned __int128 s2 = ((unsigned __int128)acc[3] << 64) | acc[2];
+        const unsigned __int128 num = (unsigned __int128)acc[0] * s2 - (unsigned __int128)acc[1] * acc[1];
+        const double sigma = std::sqrt((double)num / ((double)acc[0] * (double)acc[0]));
+        beta_out[k] = b;
+        sigma_out[k] = sigma;
+        if (sigma <= sigma_min || k + 1 == max_temps) {
+            *n_temps = k + 1;
+            return ok();
+        }
+        b = b + alpha / sigma;
+    }
+}
+
+int nmc_apt_ladder(nmc_replicas *P, double beta_first, double alpha, double sigma_min, int32_t equil_sweeps,
+                   int32_t meas_sweeps, int32_t max_temps, double *beta_out, double *sigma_out, int32_t *n_temps,
+                   void *stream) {
+    try {
+        return apt_ladder_impl(P, beta_first, alpha, sigma_min, equil_sweeps, meas_sweeps, max_temps, beta_out,
+                               sigma_out, n_temps, stream);
+    } catch (const std::bad_alloc &) {
+        return fail(NMC_ERR_CAPACITY, "host allocation failed");
+    }
 }
 
 int nmc_kernel_time(nmc_replicas *P, double *ms, int64_t *launches, double *attempts, int32_t reset) {

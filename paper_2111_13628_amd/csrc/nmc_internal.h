@@ -13,6 +13,7 @@ constexpr uint32_t kStreamKsatSweep = 0;
 constexpr uint32_t kStreamKsatInit = 1;
 constexpr uint32_t kStreamQapSweep = 2;
 constexpr uint32_t kStreamQapInit = 3;
+constexpr uint32_t kStreamPtSwap = 4;
 
 // k-SAT: replicas are handled in groups of 4; group g holds replicas
 // 4g..4g+3 as bits 0..3 of one byte per variable.
@@ -66,6 +67,7 @@ struct SweepCall {
     int32_t target;
     int32_t check_start;
     uint32_t key0, key1;
+    int32_t reps_per_row;   // > 0: replica r reads table row r / reps_per_row (one [n_classes][stride] block per row)
 };
 
 // QAP: permutations as bytes, pair ranks in lexicographic order.
@@ -102,6 +104,7 @@ struct QapCall {
     int32_t check_start;
     uint32_t key0, key1;
     int32_t rows;          // proposals evaluated per step: 0 = chosen per sweep, else 1, 4 or 8
+    int32_t reps_per_row;  // > 0: replica r reads table row r / reps_per_row (one [n_classes][stride] block per row)
 };
 
 // One replica set of a batched launch.
@@ -164,6 +167,27 @@ hipError_t qap_launch_sweep_batch(const QapJob *jobs, const int2 *items, int n_i
 int qap_batch_occupancy(size_t lds);
 hipError_t qap_launch_backbone_batch(const QapJob *jobs, const int2 *items, int n_items, int thr_num, int thr_den,
                                      hipStream_t s);
+
+// ---- parallel tempering (nmc_pt.hip) ----
+// Replicas are temperature-major: replica r = i * n_chains + c is ladder
+// position i of chain c.  Exchange thresholds of neighbour pair i are the
+// factored form (A_i[d >> 10] * B_i[d & 1023]) >> 32 with A_i = tab + off[i]
+// holding len[i] high-digit entries (entries past len[i] are zero) and B_i
+// the 1024 words after them.
+struct PtCall {
+    const uint32_t *tab;
+    const int64_t *off;     // [n_temps - 1] word offsets of A_i
+    const int32_t *len;     // [n_temps - 1]
+    unsigned long long *accepted, *attempted;  // [n_temps - 1]
+    int32_t n_temps, n_chains, parity;
+    uint32_t t;             // sweeps done when the exchange is taken
+    uint32_t key0, key1;
+};
+hipError_t pt_launch_exchange_ksat(const KsatDev &I, const KsatRepDev &R, const PtCall &C, hipStream_t s);
+hipError_t pt_launch_exchange_qap(const QapDev &I, const QapRepDev &R, const PtCall &C, hipStream_t s);
+// acc[0..3] += (count, sum E, low and high words of sum E^2) over energies
+// [n] (non-negative, below 2^32), exactly
+hipError_t pt_launch_moments(const void *energy, int energy_is_64, int n, unsigned long long *acc, hipStream_t s);
 
 // records msg as the calling thread's nmc_last_error text; returns code
 int set_last_error(int code, const char *msg);

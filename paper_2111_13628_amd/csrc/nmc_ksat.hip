@@ -150,6 +150,8 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
     const int r0 = g * kGroup;
     const int nact = min(kGroup, R.n_rep - r0);
     const uint32_t amask = (1u << nact) - 1u;
+    // per-temperature tables (tempering): the group's replicas share one row
+    const uint32_t *tab = C.tab + (C.reps_per_row > 0 ? (size_t)(r0 / C.reps_per_row) * tab_words : 0);
 
     uint8_t *xg = R.xs + (size_t)g * n;
     for (int v = tid; v < n; v += nthr) {
@@ -175,7 +177,7 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
 
     for (int s = 0; s < C.n_sweeps; ++s) {
         const uint32_t t = C.t0 + (uint32_t)s;
-        const uint32_t *tg = C.tab + (size_t)s * C.sweep_words;
+        const uint32_t *tg = tab + (size_t)s * C.sweep_words;
         for (int i = tid; i < tab_words; i += nthr)
             tl[i] = tg[i];
         __syncthreads();

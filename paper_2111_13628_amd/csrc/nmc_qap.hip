@@ -479,6 +479,8 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
     for (int i = tid; i < n; i += blockDim.x)
         cls[i] = C.fac_cls ? C.fac_cls[i] : 0;
     const int rbase = blk * kRepPerBlock;
+    // per-temperature tables (tempering): the block's replicas share one row
+    const uint32_t *tab = C.tab + (C.reps_per_row > 0 ? (size_t)(rbase / C.reps_per_row) * tab_words : 0);
     for (int i = tid; i < kRepPerBlock * n; i += blockDim.x) {
         const int rl = i / n, f = i % n;
         const int rep = rbase + rl;
@@ -507,7 +509,7 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
         rows = 4;
     for (int s = 0; s < C.n_sweeps; ++s) {
         const uint32_t t = C.t0 + (uint32_t)s;
-        const uint32_t *tg = C.tab + (size_t)s * C.sweep_words;
+        const uint32_t *tg = tab + (size_t)s * C.sweep_words;
         for (int i = tid; i < tab_words; i += blockDim.x)
             tl[i] = tg[i];
         __syncthreads();

@@ -116,6 +116,9 @@ _SIGS = {
     "nmc_set_tuning": ([_P, _I32], ctypes.c_int),
     "nmc_set_profiling": ([_P, _I32], ctypes.c_int),
     "nmc_kernel_time": ([_P, _P, _P, _P, _I32], ctypes.c_int),
+    "nmc_pt_run": ([_P, _P, _I32, _I32, _I32, _I32, _I64, _P, _P, _P], ctypes.c_int),
+    "nmc_apt_ladder": ([_P, ctypes.c_double, ctypes.c_double, ctypes.c_double, _I32, _I32, _I32, _P, _P,
+                        ctypes.POINTER(_I32), _P], ctypes.c_int),
     "nmc_batch_create": ([_P, _I32, _PP], ctypes.c_int),
     "nmc_batch_free": ([_P], None),
     "nmc_batch_set_tuning": ([_P, _I32], ctypes.c_int),
@@ -295,6 +298,28 @@ class Replicas:
 
     def reanneal(self, beta, profile="backbone", class_of=None, target=-1, stream=None):
         self._run(lib().nmc_reanneal, beta, profile, class_of, target, stream)
+
+    def pt_run(self, beta, n_rounds, sweeps_per_round=1, first_parity=0, target=-1, stream=None):
+        """Replica-exchange rounds over the ladder beta (replica r = i * C + c
+        at beta[i]); returns (accepted, attempted) per pair position."""
+        b = np.ascontiguousarray(beta, np.float64)
+        M = b.size
+        acc = np.zeros(max(M - 1, 1), np.int64)
+        att = np.zeros(max(M - 1, 1), np.int64)
+        _check(lib().nmc_pt_run(self._h, _ptr(b), M, int(n_rounds), int(sweeps_per_round), int(first_parity),
+                                ctypes.c_int64(int(target)), _ptr(acc), _ptr(att), _stream(stream)))
+        return acc[: M - 1], att[: M - 1]
+
+    def apt_ladder(self, beta_first, alpha=1.1, sigma_min=1.0, equil_sweeps=50, meas_sweeps=10, max_temps=256,
+                   stream=None):
+        """Adaptive ladder: returns (betas, sigmas)."""
+        b = np.zeros(int(max_temps), np.float64)
+        sg = np.zeros(int(max_temps), np.float64)
+        k = _I32()
+        _check(lib().nmc_apt_ladder(self._h, float(beta_first), float(alpha), float(sigma_min), int(equil_sweeps),
+                                    int(meas_sweeps), int(max_temps), _ptr(b), _ptr(sg), ctypes.byref(k),
+                                    _stream(stream)))
+        return b[: k.value].copy(), sg[: k.value].copy()
 
     def estimate_backbone(self, thr_num=9, thr_den=10, expand=True, stream=None):
         n = self.inst.n

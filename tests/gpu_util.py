@@ -39,6 +39,20 @@ class KsatPair:
             self.rep.anneal(beta, target=target)
         self.orep.anneal(beta, class_of=class_of, target=target)
 
+    def pt_run(self, beta, n_rounds, sweeps_per_round, first_parity=0, target=-1):
+        acc, att = self.rep.pt_run(beta, n_rounds, sweeps_per_round, first_parity, target)
+        oacc, oatt = self.orep.pt_run(beta, n_rounds, sweeps_per_round, first_parity, target)
+        assert (att == oatt).all(), (att, oatt)
+        assert (acc == oacc).all(), (acc, oacc)
+        return acc, att
+
+    def apt_ladder(self, *args):
+        b, sg = self.rep.apt_ladder(*args)
+        ob, osg = self.orep.apt_ladder(*args)
+        assert b.tolist() == ob.tolist(), (b, ob)
+        assert sg.tolist() == osg.tolist(), (sg, osg)
+        return b, sg
+
     def backbone(self, num=9, den=10, expand=True):
         cls, counts = self.rep.estimate_backbone(num, den, expand)
         ocls, ocounts = self.orep.backbone(num, den, expand)
@@ -78,6 +92,9 @@ class QapPair:
         else:
             self.rep.anneal(beta, target=target)
         self.orep.anneal(beta, class_of=class_of, target=target)
+
+    pt_run = KsatPair.pt_run
+    apt_ladder = KsatPair.apt_ladder
 
     def backbone(self, num=9, den=10):
         cls, freq = self.rep.estimate_backbone(num, den)

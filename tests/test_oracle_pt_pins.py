@@ -186,16 +186,19 @@ def test_ladder_sigma_matches_binomial_closed_form():
     _, order, _ = ks.color(0)
     rep = oracle.KSatReplicas(ks, 512, 12, order, threads=8, snapshot=False)
     alpha, sigma_min = 1.1, 2.5
-    betas, sigmas = rep.apt_ladder(0.2, alpha, sigma_min, 30, 10, 12)
+    # at high temperature most moves have dE = 0 and flip every sweep, so
+    # sweep-order Metropolis keeps an even/odd memory of its start for tens of
+    # sweeps; pooled samples then overstate the spread until it has decayed
+    betas, sigmas = rep.apt_ladder(0.4, alpha, sigma_min, 60, 10, 12)
     assert len(betas) >= 3
     for b, s in zip(betas, sigmas):
         p = _p_violated(b, k)
-        assert s == pytest.approx(math.sqrt(M * p * (1 - p)), rel=0.08), b
+        assert s == pytest.approx(math.sqrt(M * p * (1 - p)), rel=0.05), b
     for i in range(len(betas) - 1):
         assert betas[i + 1] == betas[i] + alpha / sigmas[i]
         assert sigmas[i] > sigma_min
     assert sigmas[-1] <= sigma_min or len(betas) == 12
-    assert rep.sweeps_done == len(betas) * 40
+    assert rep.sweeps_done == len(betas) * 70
 
 
 def test_qap_exchange_moves_assignments_with_costs():
@@ -212,3 +215,24 @@ def test_qap_exchange_moves_assignments_with_costs():
         assert sorted(rep.perm[r]) == list(range(9))
         assert rep.cost[r] == q.cost(rep.perm[r])
     assert (rep.best <= rep.cost).all()
+
+
+def test_following_some_chains_equals_the_full_run():
+    """Chains are independent: following chains 1..2 alone reproduces those
+    chains' slots of a run over all chains (used to check full-size runs on a
+    sample of chains)."""
+    cp, lits = instances.gen_ksat(200, "9.6", 4, 8)
+    ks = oracle.KSat(200, cp, lits)
+    _, order, _ = ks.color(0)
+    beta = np.array([0.8, 1.1, 1.5, 2.0])
+    C = 4
+    full = oracle.KSatReplicas(ks, C * len(beta), 3, order, threads=4)
+    part = oracle.KSatReplicas(ks, C * len(beta), 3, order, threads=4)
+    full.pt_run(beta, 9, 1, 1, 30)
+    part.pt_run(beta, 9, 1, 1, 30, chains=(1, 3))
+    slots = [i * C + c for i in range(len(beta)) for c in (1, 2)]
+    others = [r for r in range(C * len(beta)) if r not in slots]
+    assert (full.x[slots] == part.x[slots]).all()
+    for a in ("energy", "best", "first_hit"):
+        assert (getattr(full, a)[slots] == getattr(part, a)[slots]).all(), a
+    assert (part.x[others] == ks.init(C * len(beta), 3)[others]).all()
