@@ -153,11 +153,27 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
     // per-temperature tables (tempering): the group's replicas share one row
     const uint32_t *tab = C.tab + (C.reps_per_row > 0 ? (size_t)(r0 / C.reps_per_row) * tab_words : 0);
 
+    // spin tables x and not-x from the group's row; rows and tables are
+    // 16-byte aligned when N is a multiple of 16, then moved 16 bytes a lane
     uint8_t *xg = R.xs + (size_t)g * n;
-    for (int v = tid; v < n; v += nthr) {
-        const uint32_t b = xg[v] & amask;
-        xt[v] = (uint8_t)b;
-        xt[n + v] = (uint8_t)(~b & amask);
+    const bool wide = (n & 15) == 0;
+    if (wide) {
+        const uint32_t m4 = amask * 0x01010101u;
+        for (int w = tid; w < n / 16; w += nthr) {
+            uint4 b = reinterpret_cast<const uint4 *>(xg)[w];
+            b.x &= m4;
+            b.y &= m4;
+            b.z &= m4;
+            b.w &= m4;
+            reinterpret_cast<uint4 *>(xt)[w] = b;
+            reinterpret_cast<uint4 *>(xt + n)[w] = make_uint4(~b.x & m4, ~b.y & m4, ~b.z & m4, ~b.w & m4);
+        }
+    } else {
+        for (int v = tid; v < n; v += nthr) {
+            const uint32_t b = xg[v] & amask;
+            xt[v] = (uint8_t)b;
+            xt[n + v] = (uint8_t)(~b & amask);
+        }
     }
     if (tid == 0) {
         xt[2 * n] = 0;
@@ -302,8 +318,21 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
         const uint32_t imp = (uint32_t)red[4];
         if (imp) {
             uint8_t *bg = R.best_xs + (size_t)g * n;
-            for (int v = tid; v < n; v += nthr)
-                bg[v] = (uint8_t)((bg[v] & ~imp) | (xt[v] & imp));
+            if (wide) {
+                const uint32_t i4 = imp * 0x01010101u;
+                for (int w = tid; w < n / 16; w += nthr) {
+                    uint4 o = reinterpret_cast<const uint4 *>(bg)[w];
+                    const uint4 c = reinterpret_cast<const uint4 *>(xt)[w];
+                    o.x = (o.x & ~i4) | (c.x & i4);
+                    o.y = (o.y & ~i4) | (c.y & i4);
+                    o.z = (o.z & ~i4) | (c.z & i4);
+                    o.w = (o.w & ~i4) | (c.w & i4);
+                    reinterpret_cast<uint4 *>(bg)[w] = o;
+                }
+            } else {
+                for (int v = tid; v < n; v += nthr)
+                    bg[v] = (uint8_t)((bg[v] & ~imp) | (xt[v] & imp));
+            }
         }
         __syncthreads();
         if (tid < 8)
@@ -311,8 +340,13 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
     }
 
     __syncthreads();
-    for (int v = tid; v < n; v += nthr)
-        xg[v] = xt[v];
+    if (wide) {
+        for (int w = tid; w < n / 16; w += nthr)
+            reinterpret_cast<uint4 *>(xg)[w] = reinterpret_cast<const uint4 *>(xt)[w];
+    } else {
+        for (int v = tid; v < n; v += nthr)
+            xg[v] = xt[v];
+    }
     if (tid < nact) {
         R.energy[r0 + tid] = E;
         R.best[r0 + tid] = best;
