@@ -82,6 +82,10 @@ def lib():
             L.orc_pt_exchange.argtypes = [_I32, _I32, _I32, _I32, _P, _U64, _U32, _I32, _I32, _P, _P, _P, _P]
             L.orc_energy_sigma.argtypes = [_P, _I64]
             L.orc_energy_sigma.restype = _D
+            L.orc_lbp_cnf.argtypes = [_I32, _I32, _P, _P, _P, _D, _D, _D, _D, _I32, _D, _D, _P, _P, _P, _P]
+            L.orc_lbp_cnf.restype = ctypes.c_int
+            L.orc_cnf_clusters.argtypes = [_I32, _I32, _P, _P, _P, _D, _D, _P, _P]
+            L.orc_cnf_clusters.restype = _I32
             _lib = L
     return _lib
 
@@ -162,6 +166,33 @@ class KSat:
         x = np.zeros((R, self.n), np.uint8)
         _run_threads(lambda a, b: lib().orc_ksat_init(self.n, a, b, seed, _p(x)), _split(0, R, threads))
         return x
+
+
+    def lbp(self, x_ref, beta, lambda0, ratio, lambda_min, max_iter, tol, p_min=-2.0):
+        """Adiabatic LBP on the surrogate Hamiltonian around the 0/1 state
+        x_ref; returns dict(u per literal position, mag, corr per clause,
+        lambda, steps, iterations, converged, delta, overlap, self_overlap)."""
+        s = (2 * _c(x_ref, np.int8) - 1).astype(np.int8)
+        u = np.zeros(max(len(self.lits), 1), np.float64)
+        mag = np.zeros(max(self.n, 1), np.float64)
+        corr = np.zeros(max(self.m, 1), np.float64)
+        st = np.zeros(7, np.float64)
+        rc = lib().orc_lbp_cnf(self.n, self.m, _p(self.cptr), _p(self.lits), _p(s), float(beta), float(lambda0),
+                               float(ratio), float(lambda_min), int(max_iter), float(tol), float(p_min), _p(u),
+                               _p(mag), _p(corr), _p(st))
+        assert rc == 0
+        return dict(u=u[: len(self.lits)], mag=mag[: self.n], corr=corr[: self.m], **{
+            k: (int(v) if k in ("steps", "iterations", "converged") else float(v))
+            for k, v in zip(("lambda", "steps", "iterations", "converged", "delta", "overlap", "self_overlap"), st)})
+
+    def clusters(self, corr, theta_seed, theta_cut):
+        """Connected backbone growth: (label, cls, n_clusters)."""
+        corr = _c(corr, np.float64)
+        label = np.zeros(max(self.n, 1), np.int32)
+        cls = np.zeros(max(self.n, 1), np.uint8)
+        k = lib().orc_cnf_clusters(self.n, self.m, _p(self.cptr), _p(self.lits), _p(corr), float(theta_seed),
+                                   float(theta_cut), _p(label), _p(cls))
+        return label[: self.n], cls[: self.n], int(k)
 
 
 class KSatReplicas:

@@ -564,3 +564,279 @@ double orc_energy_sigma(const int64_t *e, int64_t count)
     double var = (double)num / ((double)count * (double)count);
     return sqrt(var);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Localized surrogate Hamiltonian and LBP on the CNF factor graph           */
+/* (section "Constructing localized surrogate Hamiltonians", section         */
+/* "Efficient sampling of localized surrogate Hamiltonians via LBP",         */
+/* subsection "4-SAT Problems Near Computational Phase Transitions",         */
+/* appendix C "Loopy Belief propagation for k-local Hamiltonians over        */
+/* conjugate normal form")                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Spins r_i = +1 for x_i = 1, -1 for x_i = 0.  Edge p (a literal position of
+ * the CSR) joins clause a and variable i = var(p); sigma_p = +1 if the literal
+ * is positive (r_i = +1 satisfies it), -1 if negated.  A clause violated by
+ * r carries the weight exp(-2 beta), a satisfied one 1.  The reference
+ * configuration s* couples through the field H_i = lambda eps_i s*_i with
+ * eps_i = the number of clauses holding i.
+ *
+ * Messages (in the frame of the clause: positive = leaning to satisfy it):
+ *   h_{i->a} = sigma_{ia} H_i + sum_{b in di \ a} sigma_{ia} sigma_{ib} u_{b->i}
+ *   u_{a->i} = -1/2 ln[1 - (1 - e^{-2 beta}) prod_{j in da \ i} (1 - tanh h_{j->a}) / 2]
+ * Magnetization <r_i> = tanh(H_i + sum_{a in di} sigma_{ia} u_{a->i}).
+ * Clause moment under mu_a(r) ~ omega_a(r) prod_j (1 + sigma_{ja} r_j t_j) / 2,
+ * t_j = tanh h_{j->a}:
+ *   <prod_j r_j>_a = [prod_j sigma_{ja} t_j - (1 - e^{-2 beta}) prod_j (-sigma_{ja}) (1 - t_j) / 2] / z_a,
+ *   z_a = 1 - (1 - e^{-2 beta}) prod_j (1 - t_j) / 2. */
+
+static int32_t lit_var(int32_t l) { return (l > 0 ? l : -l) - 1; }
+static double lit_sign(int32_t l) { return l > 0 ? 1.0 : -1.0; }
+
+/* every edge of variable i: edge list built by counting, in CSR order */
+typedef struct {
+    int32_t *ptr; /* n+1 */
+    int32_t *edge; /* cptr[m] */
+} orc_vedges;
+
+static int vedges_build(int32_t n, int32_t m, const int32_t *cptr, const int32_t *lits, orc_vedges *g)
+{
+    int32_t ne = cptr[m];
+    g->ptr = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));
+    g->edge = (int32_t *)malloc(((size_t)ne + 1) * sizeof(int32_t));
+    int32_t *fill = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));
+    if (!g->ptr || !g->edge || !fill) {
+        free(g->ptr); free(g->edge); free(fill);
+        return -1;
+    }
+    for (int32_t p = 0; p < ne; ++p)
+        g->ptr[lit_var(lits[p]) + 1]++;
+    for (int32_t v = 0; v < n; ++v)
+        g->ptr[v + 1] += g->ptr[v];
+    for (int32_t p = 0; p < ne; ++p) {
+        int32_t v = lit_var(lits[p]);
+        g->edge[g->ptr[v] + fill[v]++] = p;
+    }
+    free(fill);
+    return 0;
+}
+
+/* one message iteration: every h from u, then every u from h (both
+ * computed as their definitions state); returns max |u_new - u_old| */
+static double lbp_iterate(int32_t n, int32_t m, const int32_t *cptr, const int32_t *lits, const orc_vedges *g,
+                          const double *H, double beta, double *h, double *u, double *u_new)
+{
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t e = g->ptr[i]; e < g->ptr[i + 1]; ++e) {
+            int32_t p = g->edge[e];
+            double sp = lit_sign(lits[p]);
+            double s = sp * H[i];
+            for (int32_t f = g->ptr[i]; f < g->ptr[i + 1]; ++f) {
+                int32_t q = g->edge[f];
+                if (q != p)
+                    s += sp * lit_sign(lits[q]) * u[q];
+            }
+            h[p] = s;
+        }
+    double w = 1.0 - exp(-2.0 * beta);
+    double delta = 0.0;
+    for (int32_t a = 0; a < m; ++a)
+        for (int32_t p = cptr[a]; p < cptr[a + 1]; ++p) {
+            double prod = 1.0;
+            for (int32_t q = cptr[a]; q < cptr[a + 1]; ++q)
+                if (q != p)
+                    prod *= (1.0 - tanh(h[q])) / 2.0;
+            u_new[p] = -0.5 * log(1.0 - w * prod);
+            double d = fabs(u_new[p] - u[p]);
+            if (d > delta)
+                delta = d;
+        }
+    memcpy(u, u_new, (size_t)cptr[m] * sizeof(double));
+    return delta;
+}
+
+/* Adiabatic LBP (section on LBP: start at a large lambda with messages
+ * h_{i->a} = sigma_{ia} H_i and u from them, then lower lambda step by step
+ * keeping the messages).  Step k uses lambda_k = lambda0 * ratio^k while
+ * lambda_k >= lambda_min; at each step the messages are iterated until
+ * max |du| < tol (at most max_iter iterations).  A step that does not
+ * converge, or whose overlap p = (1/N) sum s*_i <r_i> falls below p_min, is
+ * discarded and the previous step's messages are kept.
+ * Outputs from the kept messages: u (final), mag[n], corr[m] (signed clause
+ * moments) and stats = {lambda, steps tried, iterations, converged, delta, p,
+ * q1 = (1/N) sum <r_i>^2}.  s_star[i] in {-1, +1}.  Returns 0, or -1 on
+ * allocation failure. */
+int orc_lbp_cnf(int32_t n, int32_t m, const int32_t *cptr, const int32_t *lits, const int8_t *s_star, double beta,
+                double lambda0, double ratio, double lambda_min, int32_t max_iter, double tol, double p_min,
+                double *u, double *mag, double *corr, double *stats)
+{
+    orc_vedges g;
+    if (vedges_build(n, m, cptr, lits, &g))
+        return -1;
+    int32_t ne = cptr[m];
+    double *eps = (double *)malloc(((size_t)n + 1) * sizeof(double));
+    double *H = (double *)malloc(((size_t)n + 1) * sizeof(double));
+    double *h = (double *)malloc(((size_t)ne + 1) * sizeof(double));
+    double *un = (double *)malloc(((size_t)ne + 1) * sizeof(double));
+    double *keep = (double *)malloc(((size_t)ne + 1) * sizeof(double));
+    for (int32_t i = 0; i < n; ++i)
+        eps[i] = (double)(g.ptr[i + 1] - g.ptr[i]);
+    double w = 1.0 - exp(-2.0 * beta);
+
+    /* initial messages at lambda0 */
+    for (int32_t i = 0; i < n; ++i)
+        H[i] = lambda0 * eps[i] * s_star[i];
+    for (int32_t p = 0; p < ne; ++p)
+        h[p] = lit_sign(lits[p]) * H[lit_var(lits[p])];
+    for (int32_t a = 0; a < m; ++a)
+        for (int32_t p = cptr[a]; p < cptr[a + 1]; ++p) {
+            double prod = 1.0;
+            for (int32_t q = cptr[a]; q < cptr[a + 1]; ++q)
+                if (q != p)
+                    prod *= (1.0 - tanh(h[q])) / 2.0;
+            u[p] = -0.5 * log(1.0 - w * prod);
+        }
+
+    double lambda = lambda0, kept_lambda = lambda0, kept_delta = 0.0;
+    int32_t steps = 0, iters = 0, have = 0;
+    for (;;) {
+        for (int32_t i = 0; i < n; ++i)
+            H[i] = lambda * eps[i] * s_star[i];
+        memcpy(keep, u, (size_t)ne * sizeof(double));
+        double delta = 0.0;
+        int conv = 0;
+        for (int32_t it = 0; it < max_iter; ++it) {
+            delta = lbp_iterate(n, m, cptr, lits, &g, H, beta, h, u, un);
+            ++iters;
+            if (delta < tol) {
+                conv = 1;
+                break;
+            }
+        }
+        ++steps;
+        double pov = 0.0;
+        if (conv) {
+            for (int32_t i = 0; i < n; ++i) {
+                double f = H[i];
+                for (int32_t e = g.ptr[i]; e < g.ptr[i + 1]; ++e)
+                    f += lit_sign(lits[g.edge[e]]) * u[g.edge[e]];
+                pov += s_star[i] * tanh(f);
+            }
+            pov = n ? pov / n : 1.0;
+        }
+        if (!conv || (have && pov < p_min)) {
+            if (have)
+                memcpy(u, keep, (size_t)ne * sizeof(double));
+            else
+                kept_delta = delta;
+            break;
+        }
+        have = 1;
+        kept_lambda = lambda;
+        kept_delta = delta;
+        double next = lambda * ratio;
+        if (!(next >= lambda_min))
+            break;
+        lambda = next;
+    }
+
+    /* marginals and clause moments from the kept messages */
+    for (int32_t i = 0; i < n; ++i)
+        H[i] = kept_lambda * eps[i] * s_star[i];
+    double p_sum = 0.0, q_sum = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        double f = H[i];
+        for (int32_t e = g.ptr[i]; e < g.ptr[i + 1]; ++e)
+            f += lit_sign(lits[g.edge[e]]) * u[g.edge[e]];
+        mag[i] = tanh(f);
+        p_sum += s_star[i] * mag[i];
+        q_sum += mag[i] * mag[i];
+    }
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t e = g.ptr[i]; e < g.ptr[i + 1]; ++e) {
+            int32_t p = g.edge[e];
+            double sp = lit_sign(lits[p]);
+            double s = sp * H[i];
+            for (int32_t f = g.ptr[i]; f < g.ptr[i + 1]; ++f) {
+                int32_t q = g.edge[f];
+                if (q != p)
+                    s += sp * lit_sign(lits[q]) * u[q];
+            }
+            h[p] = s;
+        }
+    for (int32_t a = 0; a < m; ++a) {
+        double sat = 1.0, viol = 1.0, pv = 1.0;
+        for (int32_t q = cptr[a]; q < cptr[a + 1]; ++q) {
+            double t = tanh(h[q]), sg = lit_sign(lits[q]);
+            sat *= sg * t;
+            viol *= -sg * (1.0 - t) / 2.0;
+            pv *= (1.0 - t) / 2.0;
+        }
+        corr[a] = (sat - w * viol) / (1.0 - w * pv);
+    }
+    stats[0] = kept_lambda;
+    stats[1] = steps;
+    stats[2] = iters;
+    stats[3] = have;
+    stats[4] = kept_delta;
+    stats[5] = n ? p_sum / n : 1.0;
+    stats[6] = n ? q_sum / n : 1.0;
+    free(eps); free(H); free(h); free(un); free(keep);
+    free(g.ptr); free(g.edge);
+    return 0;
+}
+
+/* Connected backbone growth (section "Generating backbones of rigid
+ * variables"): a clause is rigid when |corr_a| >= theta_cut and a seed when
+ * |corr_a| >= theta_seed.  Rigid clauses join all their variables; a
+ * connected group of variables that holds at least one seed clause is a
+ * cluster of the backbone.  label[i] = smallest variable index of i's
+ * cluster, -1 outside the backbone; cls[i] = 1 inside, 0 outside.  Returns
+ * the number of clusters. */
+int32_t orc_cnf_clusters(int32_t n, int32_t m, const int32_t *cptr, const int32_t *lits, const double *corr,
+                         double theta_seed, double theta_cut, int32_t *label, uint8_t *cls)
+{
+    orc_adj g;
+    if (adj_build(n, m, cptr, lits, &g))
+        return -1;
+    int32_t *queue = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+    int32_t *comp = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+    for (int32_t i = 0; i < n; ++i)
+        comp[i] = -1;
+    int32_t clusters = 0;
+    for (int32_t s = 0; s < n; ++s) {
+        if (comp[s] >= 0)
+            continue;
+        /* breadth-first search from s over rigid clauses */
+        int32_t qh = 0, qt = 0, seeded = 0;
+        queue[qt++] = s;
+        comp[s] = s;
+        while (qh < qt) {
+            int32_t i = queue[qh++];
+            for (int32_t e = g.ptr[i]; e < g.ptr[i + 1]; ++e) {
+                int32_t a = g.cl[e];
+                double c = fabs(corr[a]);
+                if (!(c >= theta_cut))
+                    continue;
+                if (c >= theta_seed)
+                    seeded = 1;
+                for (int32_t p = cptr[a]; p < cptr[a + 1]; ++p) {
+                    int32_t j = lit_var(lits[p]);
+                    if (comp[j] < 0) {
+                        comp[j] = s;
+                        queue[qt++] = j;
+                    }
+                }
+            }
+        }
+        for (int32_t k = 0; k < qt; ++k) {
+            label[queue[k]] = seeded ? s : -1;
+            cls[queue[k]] = (uint8_t)seeded;
+        }
+        clusters += seeded;
+    }
+    free(queue);
+    free(comp);
+    adj_free(&g);
+    return clusters;
+}
