@@ -220,6 +220,69 @@ def bench_qap(nmc, torch, seed, sweeps_only=0):
             "beta_unit": sc, "best_cost": be["best"], "sweeps": S_tot}
 
 
+LBP_CFG = dict(beta=1.0, lambda0=4.0, lambda_ratio=0.8, lambda_min=1e-3, max_iter=100, tol=1e-8, p_min=-2.0)
+LBP_THRESHOLDS = ((0.8, 0.6), (0.9, 0.8), (0.95, 0.9))  # (seed, cutoff) per round, raised round by round
+# HBM bytes one message iteration must move per literal slot (edge): u read,
+# h written, h read, u read and written (8 B each), the variable's edge index
+# and the clause's literal address (4 B each); per variable: clause range,
+# reference spin
+LBP_BYTES_PER_EDGE, LBP_BYTES_PER_VAR = 48, 5
+
+
+def bench_lbp(nmc, torch, seed):
+    """NMC with the paper's backbone estimator on the N = 50,000 instance:
+    anneal 2000 sweeps (beta 0.1 -> 4.0), then 3 rounds of [LBP on the
+    surrogate Hamiltonian around the best state of the best replica ->
+    connected backbone (thresholds raised each round) -> reanneal 1000
+    sweeps, backbone hot]."""
+    cp, lits = instances.gen_ksat(N, ALPHA, K, seed)
+    inst = nmc.Instance.ksat(N, cp, lits, CLASS_CAP).bind()
+    M = inst.info.n_clauses
+
+    def path(profile):
+        rep = nmc.Replicas(inst, R, seed)
+        rep.set_profiling(profile)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep.anneal(instances.linear_schedule(BETA0, BETA1, S_ANNEAL)[None, :])
+        rounds, t_lbp = [], 0.0
+        for ts, tc in LBP_THRESHOLDS:
+            r0 = int(np.argmin(rep.best_energy()["best_per_replica"]))
+            t1 = time.perf_counter()
+            g = rep.lbp_backbone(r0, "best", **LBP_CFG, theta_seed=ts, theta_cut=tc)
+            t_lbp += time.perf_counter() - t1
+            rounds.append({k: g[k] for k in ("lambda", "steps", "iterations", "converged", "overlap", "self_overlap",
+                                             "backbone_size", "n_clusters", "largest_cluster")})
+            rep.reanneal(reanneal_profile(S_RE), "backbone")
+        be = rep.best_energy()
+        torch.cuda.synchronize()
+        return rep, rounds, be, time.perf_counter() - t0, t_lbp
+
+    path(False)  # warm-up
+    rep, rounds, be, wall, t_lbp = path(False)
+    prep, _, _, _, _ = path(True)
+    kt = prep.kernel_time()
+    lt = prep.lbp_kernel_time()
+    edges, nvar = 4 * M, N
+    bytes_it = LBP_BYTES_PER_EDGE * edges + LBP_BYTES_PER_VAR * nvar
+    ms_it = lt["ms"] / max(1, lt["iterations"])
+    att = float(R) * N * (S_ANNEAL + ROUNDS * S_RE)
+    deg_mean = K * M / N
+    ops_per_attempt = (OPS_PER_SLOT * deg_mean + OPS_PER_VAR) / 4.0
+    achieved = kt["attempts"] / (kt["ms"] / 1000.0) * ops_per_attempt
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                "unit": "T lane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                "kernel": "ksat_sweep_kernel", "kernel_ms_per_launch": kt["ms"] / max(1, kt["launches"]),
+                "kernel_attempts_per_s": kt["attempts"] / (kt["ms"] / 1000.0), "launches": kt["launches"]}
+    lbp_roofline = {"bound": "hbm", "achieved": bytes_it / (ms_it / 1000.0) / 1e9, "peak": 8000.0, "unit": "GB/s",
+                    "frac": bytes_it / (ms_it / 1000.0) / 8e12, "traffic": None,
+                    "kernel": "lbp_var_kernel + lbp_clause_kernel (one message iteration)",
+                    "ms_per_iteration": ms_it, "bytes_per_iteration": bytes_it, "iterations": lt["iterations"]}
+    return {"attempts": att, "wall_s": wall, "attempts_per_s": att / wall, "lbp_s": t_lbp,
+            "lbp_share": t_lbp / wall, "rounds": rounds, "best_energy": be["best"], "roofline": roofline,
+            "lbp_roofline": lbp_roofline}
+
+
 APT_TEMPS, APT_CHAINS, APT_BETA_FIRST, APT_ALPHA = 64, 16, 1.5, 1.1
 APT_EQUIL, APT_MEAS, APT_ROUNDS = 20, 5, 2000
 
@@ -452,10 +515,11 @@ def main():
     ap.add_argument("--no-ttt", action="store_true")
     ap.add_argument("--block-threads", type=int, default=0)
     ap.add_argument("--class-cap", type=int, default=CLASS_CAP)
-    ap.add_argument("--workload", choices=["nmc", "batch", "qap", "serve", "apt"], default="nmc",
+    ap.add_argument("--workload", choices=["nmc", "batch", "qap", "serve", "apt", "lbp"], default="nmc",
                     help="nmc: the N=50000 NMC path (default); batch: 256 mixed instances, batched vs "
                          "per-instance; qap: the n=100 QAP path; serve: Poisson stream into the server; "
-                         "apt: adaptive parallel tempering on the N=50000 instance")
+                         "apt: adaptive parallel tempering on the N=50000 instance; lbp: NMC with LBP "
+                         "surrogate backbones on the N=50000 instance")
     ap.add_argument("--pt-rounds", type=int, default=APT_ROUNDS)
     ap.add_argument("--pt-sweeps-per-round", type=int, default=1)
     ap.add_argument("--serve-seconds", type=float, default=SERVE_SECONDS)
@@ -494,6 +558,15 @@ def main():
                           "data": "synthetic",
                           "config": {"workload": "QAP n=100, 4096 replicas, anneal 5000 + 2x(backbone + reanneal 1000)"},
                           "roofline": res["roofline"], "qap": res}), flush=True)
+        return
+    if args.workload == "lbp":
+        res = bench_lbp(nmc, torch, seed)
+        print(json.dumps({"metric": "spin-flip attempts/s (NMC path with LBP surrogate backbones)",
+                          "value": res["attempts_per_s"], "unit": "attempts/s", "n_gpus": 1,
+                          "higher_is_better": True, "dtype": "int32", "data": "synthetic",
+                          "config": {"workload": "NMC random 4-SAT N=50000 alpha=9.9, 1024 replicas, anneal 2000 + "
+                                                 "3x(LBP backbone + reanneal 1000)"},
+                          "roofline": res["roofline"], "lbp": res}), flush=True)
         return
     if args.workload == "apt":
         res = bench_apt(nmc, torch, seed, args.pt_rounds, args.pt_sweeps_per_round)

@@ -138,7 +138,11 @@ int nmc_footprint(const nmc_instance *inst, int32_t n_replicas, size_t *instance
  * nmc_replicas_create.  Errors: SIZE, INVALID (misaligned), DEVICE. */
 int nmc_instance_bind(nmc_instance *inst, void *dev_buf, size_t bytes, void *stream);
 
-/* Frees host-side metadata.  Replica sets of the instance must be freed first. */
+/* Releases the caller's handle.  The host-side metadata is freed when the
+ * handle and every replica set created from the instance have been released,
+ * in any order (each replica set holds a reference; nmc_replicas_free drops
+ * it).  The instance's device buffer (caller memory) must stay valid while
+ * any of its replica sets runs work. */
 void nmc_instance_free(nmc_instance *inst);
 
 /* ---------------------------------------------------------------------------
@@ -262,6 +266,74 @@ int nmc_apt_ladder(nmc_replicas *rep, double beta_first, double alpha, double si
                    void *stream);
 
 /* ---------------------------------------------------------------------------
+ * surrogate-Hamiltonian backbone (section "Constructing localized surrogate
+ * Hamiltonians"; section "Efficient sampling of localized surrogate
+ * Hamiltonians via LBP" and its CNF form in subsection "4-SAT Problems Near
+ * Computational Phase Transitions" and appendix C; section "Generating
+ * backbones of rigid variables")
+ * ------------------------------------------------------------------------- */
+
+typedef struct nmc_lbp_config {
+    double beta;          /* a violated clause weighs exp(-2 beta), a satisfied one 1 */
+    double lambda0;       /* first (largest) localization strength, > 0 */
+    double lambda_ratio;  /* lambda_{k+1} = lambda_k * ratio, in (0, 1) */
+    double lambda_min;    /* no step below this lambda (the first step always runs) */
+    int32_t max_iter;     /* message iterations per step, >= 1 */
+    double tol;           /* a step has converged when max |du| of an iteration < tol */
+    double p_min;         /* a step whose overlap p falls below this is discarded */
+    double theta_seed;    /* seed clauses: |clause moment| >= theta_seed */
+    double theta_cut;     /* rigid clauses: |clause moment| >= theta_cut (<= theta_seed) */
+} nmc_lbp_config;
+
+typedef struct nmc_lbp_result {
+    double lambda;            /* lambda of the kept messages */
+    int32_t steps;            /* lambda steps tried (the discarded one included) */
+    int32_t iterations;       /* message iterations over all steps */
+    int32_t converged;        /* 1 when the kept messages converged */
+    double delta;             /* max |du| of the kept step's last iteration */
+    double overlap;           /* p  = (1/N) sum_i s*_i <r_i> */
+    double self_overlap;      /* q1 = (1/N) sum_i <r_i>^2 */
+    int32_t backbone_size;    /* variables in the backbone (hot class) */
+    int32_t n_clusters;
+    int32_t largest_cluster;
+    int32_t rigid_clauses;
+    int32_t seed_clauses;
+} nmc_lbp_result;
+
+/* Backbone of rigid variables around the state s* of one replica (k-SAT
+ * only): loopy belief propagation on the surrogate Hamiltonian
+ * H(r) - lambda sum_i eps_i s*_i r_i over the CNF factor graph, then
+ * connected clusters of strongly correlated clauses.
+ *   replica, which    s*_i = 2 x_i - 1 of replica `replica`'s current or best
+ *                     state (NMC_STATE_CURRENT / NMC_STATE_BEST)
+ * Spins r_i = 2 x_i - 1; eps_i = number of clauses holding i; sigma_{ia} = +1
+ * for a positive literal of i in clause a, -1 for a negated one.  Messages:
+ *   h_{i->a} = sigma_{ia} lambda eps_i s*_i + sum_{b in di \ a} sigma_{ia} sigma_{ib} u_{b->i}
+ *   u_{a->i} = -1/2 ln[1 - (1 - e^{-2 beta}) prod_{j in da \ i} (1 - tanh h_{j->a}) / 2]
+ * updated all h, then all u, per iteration.  Adiabatic schedule: messages
+ * start at h = sigma lambda0 eps s*, u from them; step k runs at
+ * lambda0 * ratio^k (while >= lambda_min) until converged or max_iter; a step
+ * that does not converge, or whose overlap p drops below p_min, is discarded
+ * and the previous step's messages are kept.  From the kept messages:
+ * <r_i> = tanh(lambda eps_i s*_i + sum_a sigma_{ia} u_{a->i}) and the clause
+ * moment <prod_{i in a} r_i> under the clause measure
+ * omega_a(r) prod_i (1 + sigma_{ia} r_i tanh h_{i->a}) / 2.  A clause is rigid
+ * when |moment| >= theta_cut, a seed when |moment| >= theta_seed; the
+ * backbone is every connected group of variables (joined by rigid clauses)
+ * that holds a seed clause.  The backbone becomes the device class array
+ * (1 = hot) used by NMC_PROFILE_BACKBONE, as after nmc_estimate_backbone.
+ * Outputs (each optional, host): class_out [N] bytes, mag_out [N] doubles,
+ * corr_out [M] doubles (signed clause moments), label_out [N] int32 (the
+ * smallest variable index of the cluster, -1 outside the backbone).
+ * Arithmetic is IEEE double.  The workspace (about 24 bytes per literal slot
+ * of the padded 4-per-clause layout plus 30 bytes per variable) is allocated
+ * on the first call and kept with the replica set.
+ * Errors: INVALID (arguments), STATE (unbound), UNSUPPORTED (QAP), DEVICE. */
+int nmc_lbp_backbone(nmc_replicas *rep, int32_t replica, int32_t which, const nmc_lbp_config *cfg,
+                     nmc_lbp_result *res, uint8_t *class_out, double *mag_out, double *corr_out, int32_t *label_out,
+                     void *stream);
+
+/* ---------------------------------------------------------------------------
  * best_energy and state access
  * ------------------------------------------------------------------------- */
 
@@ -302,6 +374,11 @@ int nmc_set_tuning(nmc_replicas *rep, int32_t block_threads);
  * exchange launches).  Enabling it adds a stream synchronization per call. */
 int nmc_set_profiling(nmc_replicas *rep, int32_t enable);
 int nmc_kernel_time(nmc_replicas *rep, double *ms, int64_t *launches, double *attempts, int32_t reset);
+
+/* With profiling enabled, nmc_lbp_backbone brackets the two kernels of every
+ * message iteration with HIP events; this returns their summed time (ms) and
+ * the iterations timed since the last reset. */
+int nmc_lbp_kernel_time(nmc_replicas *rep, double *ms, int64_t *iterations, int32_t reset);
 
 
 /* ---------------------------------------------------------------------------

@@ -103,12 +103,16 @@ struct nmc_instance {
     int32_t qap_ha = 0;
     // largest energy any state can have (k-SAT: M; QAP: sum F * max D)
     int64_t energy_bound = 0;
+    int64_t n_lits = 0;  // k-SAT: literal occurrences (sum of clause lengths)
     size_t off_F = 0, off_D = 0;
     // packed host image of the device arena
     std::vector<uint8_t> image;
     size_t arena_bytes = 0;
     uint8_t *dev = nullptr;
-    int live_replicas = 0;
+    std::atomic<int> live_replicas{0};
+    // references: the caller's handle plus one per live replica set; the
+    // host object goes when the last is released, whatever the order
+    std::atomic<int> refs{1};
 
     KsatDev ksat_dev() const {
         KsatDev d{};
@@ -341,6 +345,7 @@ int nmc_ksat_load(int32_t n_vars, int32_t n_clauses, const int32_t *clause_ptr, 
         I->n = n_vars;
         I->m = n_clauses;
         I->energy_bound = n_clauses;
+        I->n_lits = clause_ptr[n_clauses];
         I->kmax = kmax;
         const int32_t n = n_vars, m = n_clauses;
 
@@ -631,6 +636,11 @@ struct nmc_replicas {
     size_t tab_cap = 0;
     // energy-moment accumulators of the tempering ladder (library-owned)
     unsigned long long *pt_acc = nullptr;
+    // LBP workspace (library-owned, sized for the instance on first use)
+    uint8_t *lbp_dev = nullptr;
+    // LBP message-iteration kernel time (profiling)
+    double lbp_ms = 0;
+    int64_t lbp_iters = 0;
     // profiling
     bool profiling = false;
     double prof_ms = 0;
@@ -738,7 +748,10 @@ int nmc_instance_bind(nmc_instance *I, void *dev_buf, size_t bytes, void *stream
     return ok();
 }
 
-void nmc_instance_free(nmc_instance *I) { delete I; }
+void nmc_instance_free(nmc_instance *I) {
+    if (I && I->refs.fetch_sub(1) == 1)
+        delete I;
+}
 
 int nmc_replicas_create(nmc_instance *I, int32_t n_replicas, uint64_t seed, void *dev_buf, size_t bytes,
                         void *stream, nmc_replicas **out) {
@@ -802,6 +815,7 @@ int nmc_replicas_create(nmc_instance *I, int32_t n_replicas, uint64_t seed, void
             return rc;
         HIP_OR_FAIL(hipStreamSynchronize(s));
         I->live_replicas++;
+        I->refs++;
         *out = P.release();
         return ok();
     } catch (const std::bad_alloc &) {
@@ -812,15 +826,21 @@ int nmc_replicas_create(nmc_instance *I, int32_t n_replicas, uint64_t seed, void
 void nmc_replicas_free(nmc_replicas *P) {
     if (!P)
         return;
-    if (P->tab_dev || P->pt_acc)
+    if (P->tab_dev || P->pt_acc || P->lbp_dev)
         (void)hipDeviceSynchronize();
     if (P->tab_dev)
         (void)hipFree(P->tab_dev);
     if (P->pt_acc)
         (void)hipFree(P->pt_acc);
-    if (P->inst)
-        P->inst->live_replicas--;
+    if (P->lbp_dev)
+        (void)hipFree(P->lbp_dev);
+    nmc_instance *I = P->inst;
     delete P;
+    if (I) {
+        I->live_replicas--;
+        if (I->refs.fetch_sub(1) == 1)
+            delete I;
+    }
 }
 
 static int anneal_impl(nmc_replicas *P, const double *beta, int32_t n_classes, int32_t n_sweeps, int32_t profile,
@@ -1445,6 +1465,235 @@ int nmc_apt_ladder(nmc_replicas *P, double beta_first, double alpha, double sigm
     } catch (const std::bad_alloc &) {
         return fail(NMC_ERR_CAPACITY, "host allocation failed");
     }
+}
+
+// ---------------------------------------------------------------------------
+// surrogate-Hamiltonian LBP and connected backbone growth
+// ---------------------------------------------------------------------------
+
+static int lbp_impl(nmc_replicas *P, int32_t replica, int32_t which, const nmc_lbp_config *cfg, nmc_lbp_result *res,
+                    uint8_t *class_out, double *mag_out, double *corr_out, int32_t *label_out, void *stream) {
+    if (!P || !cfg)
+        return fail(NMC_ERR_INVALID, "NULL argument");
+    nmc_instance *I = P->inst;
+    if (!I->dev)
+        return fail(NMC_ERR_STATE, "instance is not bound");
+    if (I->kind != NMC_KIND_KSAT)
+        return fail(NMC_ERR_UNSUPPORTED, "LBP runs on k-SAT instances");
+    if (replica < 0 || replica >= P->R)
+        return fail(NMC_ERR_INVALID, "replica %d outside [0, %d)", replica, P->R);
+    if (which != NMC_STATE_CURRENT && which != NMC_STATE_BEST)
+        return fail(NMC_ERR_INVALID, "which must be NMC_STATE_CURRENT or NMC_STATE_BEST");
+    const nmc_lbp_config &c = *cfg;
+    if (!std::isfinite(c.beta) || c.beta < 0)
+        return fail(NMC_ERR_INVALID, "beta = %g must be finite and >= 0", c.beta);
+    if (!std::isfinite(c.lambda0) || !(c.lambda0 > 0))
+        return fail(NMC_ERR_INVALID, "lambda0 = %g must be finite and > 0", c.lambda0);
+    if (!(c.lambda_ratio > 0 && c.lambda_ratio < 1))
+        return fail(NMC_ERR_INVALID, "lambda_ratio = %g must lie in (0, 1)", c.lambda_ratio);
+    if (!std::isfinite(c.lambda_min) || c.lambda_min < 0)
+        return fail(NMC_ERR_INVALID, "lambda_min = %g must be finite and >= 0", c.lambda_min);
+    if (c.max_iter < 1 || !(c.tol > 0) || !std::isfinite(c.tol))
+        return fail(NMC_ERR_INVALID, "need max_iter >= 1 and a finite tol > 0");
+    if (std::isnan(c.p_min) || !std::isfinite(c.theta_seed) || !std::isfinite(c.theta_cut) ||
+        c.theta_cut < 0 || c.theta_seed < c.theta_cut)
+        return fail(NMC_ERR_INVALID, "need 0 <= theta_cut <= theta_seed (finite) and a p_min that is not NaN");
+    hipStream_t s = as_stream(stream);
+    const int32_t n = I->n, m = I->m;
+    // workspace
+    Arena ar;
+    const size_t o_u = ar.take((size_t)m * 4 * 8), o_keep = ar.take((size_t)m * 4 * 8), o_h = ar.take((size_t)m * 4 * 8);
+    const size_t o_mag = ar.take((size_t)n * 8), o_corr = ar.take((size_t)m * 8);
+    const size_t o_ve = ar.take((size_t)I->n_lits * 4), o_s = ar.take((size_t)n);
+    const size_t o_scal = ar.take(8), o_res = ar.take(16);
+    const size_t o_lab = ar.take((size_t)n * 4), o_olab = ar.take((size_t)n * 4), o_size = ar.take((size_t)n * 4);
+    const size_t o_seed = ar.take((size_t)n), o_flag = ar.take(4), o_cnt = ar.take(5 * 4);
+    const size_t total = align_up(ar.size, 256);
+    if (!P->lbp_dev) {
+        HIP_OR_FAIL(hipMalloc(&P->lbp_dev, total));
+        HIP_OR_FAIL(hipMemsetAsync(P->lbp_dev, 0, total, s));
+    }
+    uint8_t *b = P->lbp_dev;
+    LbpWork W{};
+    W.u = reinterpret_cast<double *>(b + o_u);
+    double *keep = reinterpret_cast<double *>(b + o_keep);
+    W.h = reinterpret_cast<double *>(b + o_h);
+    W.mag = reinterpret_cast<double *>(b + o_mag);
+    W.corr = reinterpret_cast<double *>(b + o_corr);
+    W.vedge = reinterpret_cast<int32_t *>(b + o_ve);
+    W.s = reinterpret_cast<int8_t *>(b + o_s);
+    W.scal = reinterpret_cast<unsigned long long *>(b + o_scal);
+    W.res = reinterpret_cast<double *>(b + o_res);
+    W.label = reinterpret_cast<int32_t *>(b + o_lab);
+    W.out_label = reinterpret_cast<int32_t *>(b + o_olab);
+    W.size = reinterpret_cast<int32_t *>(b + o_size);
+    W.seeded = b + o_seed;
+    W.flag = reinterpret_cast<int32_t *>(b + o_flag);
+    W.counts = reinterpret_cast<int32_t *>(b + o_cnt);
+    const KsatDev K = I->ksat_dev();
+    const uint8_t *row = (which == NMC_STATE_BEST ? P->k.best_xs : P->k.xs) + (size_t)(replica / kGroup) * n;
+    const double w = 1.0 - std::exp(-2.0 * c.beta);
+    const size_t ubytes = (size_t)m * 4 * 8;
+
+    hipEvent_t pe[2] = {nullptr, nullptr};
+    if (P->profiling) {
+        HIP_OR_FAIL(hipEventCreate(&pe[0]));
+        HIP_OR_FAIL(hipEventCreate(&pe[1]));
+    }
+    auto iterate = [&](double lambda, double *delta) -> int {
+        HIP_OR_FAIL(hipMemsetAsync(W.scal, 0, 8, s));
+        if (pe[0])
+            HIP_OR_FAIL(hipEventRecord(pe[0], s));
+        HIP_OR_FAIL(lbp_launch_var(K, W, lambda, 0, s));
+        HIP_OR_FAIL(lbp_launch_clause(K, W, w, 0, s));
+        if (pe[1])
+            HIP_OR_FAIL(hipEventRecord(pe[1], s));
+        unsigned long long bits = 0;
+        HIP_OR_FAIL(hipMemcpyAsync(&bits, W.scal, 8, hipMemcpyDeviceToHost, s));
+        HIP_OR_FAIL(hipStreamSynchronize(s));
+        std::memcpy(delta, &bits, 8);
+        if (pe[0]) {
+            float ms = 0;
+            HIP_OR_FAIL(hipEventElapsedTime(&ms, pe[0], pe[1]));
+            P->lbp_ms += ms;
+            P->lbp_iters += 1;
+        }
+        return NMC_OK;
+    };
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard() {
+            for (int k = 0; k < 2; ++k)
+                if (e[k])
+                    (void)hipEventDestroy(e[k]);
+        }
+    } ev_guard{pe};
+    auto overlap = [&](double lambda, double out[2]) -> int {
+        HIP_OR_FAIL(lbp_launch_var(K, W, lambda, 1, s));
+        HIP_OR_FAIL(lbp_launch_overlap(K, W, s));
+        HIP_OR_FAIL(hipMemcpyAsync(out, W.res, 16, hipMemcpyDeviceToHost, s));
+        HIP_OR_FAIL(hipStreamSynchronize(s));
+        return NMC_OK;
+    };
+
+    // initial messages at lambda0: h = sigma H, u from h
+    HIP_OR_FAIL(lbp_launch_setup(K, row, replica % kGroup, W, c.lambda0, s));
+    HIP_OR_FAIL(lbp_launch_clause(K, W, w, 0, s));
+    double lambda = c.lambda0, kept_lambda = c.lambda0, kept_delta = 0.0;
+    int32_t steps = 0, iters = 0;
+    bool have = false;
+    for (;;) {
+        if (ubytes)
+            HIP_OR_FAIL(hipMemcpyAsync(keep, W.u, ubytes, hipMemcpyDeviceToDevice, s));
+        double delta = 0.0;
+        bool conv = false;
+        for (int32_t it = 0; it < c.max_iter; ++it) {
+            int rc = iterate(lambda, &delta);
+            if (rc)
+                return rc;
+            ++iters;
+            if (delta < c.tol) {
+                conv = true;
+                break;
+            }
+        }
+        ++steps;
+        double ov[2] = {0, 0};
+        if (conv) {
+            int rc = overlap(lambda, ov);
+            if (rc)
+                return rc;
+        }
+        if (!conv || (have && ov[0] < c.p_min)) {
+            if (have) {
+                if (ubytes)
+                    HIP_OR_FAIL(hipMemcpyAsync(W.u, keep, ubytes, hipMemcpyDeviceToDevice, s));
+            } else {
+                kept_delta = delta;
+            }
+            break;
+        }
+        have = true;
+        kept_lambda = lambda;
+        kept_delta = delta;
+        const double next = lambda * c.lambda_ratio;
+        if (!(next >= c.lambda_min))
+            break;
+        lambda = next;
+    }
+    // marginals, clause moments, overlaps from the kept messages
+    double ov[2];
+    {
+        int rc = overlap(kept_lambda, ov);  // also recomputes h from the kept u
+        if (rc)
+            return rc;
+    }
+    HIP_OR_FAIL(lbp_launch_clause(K, W, w, 1, s));
+    // connected components of the rigid clauses
+    HIP_OR_FAIL(lbp_launch_label_init(K, W, s));
+    for (int32_t pass = 0;; ++pass) {
+        if (pass > 4 * n + 64)
+            return fail(NMC_ERR_DEVICE, "component labels did not settle");
+        HIP_OR_FAIL(hipMemsetAsync(W.flag, 0, 4, s));
+        HIP_OR_FAIL(lbp_launch_hook_jump(K, W, c.theta_cut, s));
+        int32_t changed = 0;
+        HIP_OR_FAIL(hipMemcpyAsync(&changed, W.flag, 4, hipMemcpyDeviceToHost, s));
+        HIP_OR_FAIL(hipStreamSynchronize(s));
+        if (!changed)
+            break;
+    }
+    HIP_OR_FAIL(lbp_launch_finish(K, W, c.theta_seed, c.theta_cut, P->k.cls, s));
+    int32_t cnt[5];
+    HIP_OR_FAIL(hipMemcpyAsync(cnt, W.counts, 20, hipMemcpyDeviceToHost, s));
+    if (class_out && n)
+        HIP_OR_FAIL(hipMemcpyAsync(class_out, P->k.cls, n, hipMemcpyDeviceToHost, s));
+    if (mag_out && n)
+        HIP_OR_FAIL(hipMemcpyAsync(mag_out, W.mag, (size_t)n * 8, hipMemcpyDeviceToHost, s));
+    if (corr_out && m)
+        HIP_OR_FAIL(hipMemcpyAsync(corr_out, W.corr, (size_t)m * 8, hipMemcpyDeviceToHost, s));
+    if (label_out && n)
+        HIP_OR_FAIL(hipMemcpyAsync(label_out, W.out_label, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(hipStreamSynchronize(s));
+    P->has_backbone = true;
+    if (res) {
+        res->lambda = kept_lambda;
+        res->steps = steps;
+        res->iterations = iters;
+        res->converged = have ? 1 : 0;
+        res->delta = kept_delta;
+        res->overlap = ov[0];
+        res->self_overlap = ov[1];
+        res->backbone_size = cnt[0];
+        res->n_clusters = cnt[1];
+        res->largest_cluster = cnt[2];
+        res->rigid_clauses = cnt[3];
+        res->seed_clauses = cnt[4];
+    }
+    return ok();
+}
+
+int nmc_lbp_backbone(nmc_replicas *P, int32_t replica, int32_t which, const nmc_lbp_config *cfg,
+                     nmc_lbp_result *res, uint8_t *class_out, double *mag_out, double *corr_out, int32_t *label_out,
+                     void *stream) {
+    try {
+        return lbp_impl(P, replica, which, cfg, res, class_out, mag_out, corr_out, label_out, stream);
+    } catch (const std::bad_alloc &) {
+        return fail(NMC_ERR_CAPACITY, "host allocation failed");
+    }
+}
+
+int nmc_lbp_kernel_time(nmc_replicas *P, double *ms, int64_t *iterations, int32_t reset) {
+    if (!P)
+        return fail(NMC_ERR_INVALID, "NULL replicas");
+    if (ms)
+        *ms = P->lbp_ms;
+    if (iterations)
+        *iterations = P->lbp_iters;
+    if (reset) {
+        P->lbp_ms = 0;
+        P->lbp_iters = 0;
+    }
+    return ok();
 }
 
 int nmc_kernel_time(nmc_replicas *P, double *ms, int64_t *launches, double *attempts, int32_t reset) {

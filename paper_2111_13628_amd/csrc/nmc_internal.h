@@ -189,6 +189,30 @@ hipError_t pt_launch_exchange_qap(const QapDev &I, const QapRepDev &R, const PtC
 // [n] (non-negative, below 2^32), exactly
 hipError_t pt_launch_moments(const void *energy, int energy_is_64, int n, unsigned long long *acc, hipStream_t s);
 
+// ---- surrogate-Hamiltonian LBP and backbone growth (nmc_lbp.hip) ----
+// Edges e = 4a + j (literal j of clause a); padded edges are never read.
+struct LbpWork {
+    double *u, *h;               // [4M] clause-to-variable and variable-to-clause messages
+    double *mag, *corr;          // [N] <r_i>, [M] clause moments
+    int32_t *vedge;              // [sum deg] edge of each variable incidence, bit 31 = negated literal
+    int8_t *s;                   // [N] reference spins (+1 / -1)
+    unsigned long long *scal;    // [0] bits of the largest |du| of an iteration
+    double *res;                 // [0] overlap p, [1] self-overlap q1
+    int32_t *label, *out_label, *size;  // [N]
+    uint8_t *seeded;             // [N]
+    int32_t *flag;               // [1] labels changed
+    int32_t *counts;             // [5] backbone size, clusters, largest, rigid clauses, seed clauses
+};
+hipError_t lbp_launch_setup(const KsatDev &I, const uint8_t *xs_row, int bit, const LbpWork &W, double lambda0,
+                            hipStream_t s);
+hipError_t lbp_launch_var(const KsatDev &I, const LbpWork &W, double lambda, int final_pass, hipStream_t s);
+hipError_t lbp_launch_clause(const KsatDev &I, const LbpWork &W, double w, int final_pass, hipStream_t s);
+hipError_t lbp_launch_overlap(const KsatDev &I, const LbpWork &W, hipStream_t s);
+hipError_t lbp_launch_label_init(const KsatDev &I, const LbpWork &W, hipStream_t s);
+hipError_t lbp_launch_hook_jump(const KsatDev &I, const LbpWork &W, double cut, hipStream_t s);
+hipError_t lbp_launch_finish(const KsatDev &I, const LbpWork &W, double seed_thr, double cut, uint8_t *cls,
+                             hipStream_t s);
+
 // records msg as the calling thread's nmc_last_error text; returns code
 int set_last_error(int code, const char *msg);
 

@@ -37,6 +37,20 @@ class InstanceInfo(ctypes.Structure):
                 ("n_colors", ctypes.c_int32), ("delta_bound", ctypes.c_int64)]
 
 
+class LbpConfig(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("lambda0", ctypes.c_double), ("lambda_ratio", ctypes.c_double),
+                ("lambda_min", ctypes.c_double), ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("p_min", ctypes.c_double), ("theta_seed", ctypes.c_double), ("theta_cut", ctypes.c_double)]
+
+
+class LbpResult(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("steps", ctypes.c_int32), ("iterations", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("delta", ctypes.c_double), ("overlap", ctypes.c_double),
+                ("self_overlap", ctypes.c_double), ("backbone_size", ctypes.c_int32),
+                ("n_clusters", ctypes.c_int32), ("largest_cluster", ctypes.c_int32),
+                ("rigid_clauses", ctypes.c_int32), ("seed_clauses", ctypes.c_int32)]
+
+
 class Plan(ctypes.Structure):
     _fields_ = [("anneal_beta", ctypes.c_void_p), ("anneal_sweeps", ctypes.c_int32), ("rounds", ctypes.c_int32),
                 ("reanneal_beta", ctypes.c_void_p), ("reanneal_sweeps", ctypes.c_int32),
@@ -117,6 +131,9 @@ _SIGS = {
     "nmc_set_profiling": ([_P, _I32], ctypes.c_int),
     "nmc_kernel_time": ([_P, _P, _P, _P, _I32], ctypes.c_int),
     "nmc_pt_run": ([_P, _P, _I32, _I32, _I32, _I32, _I64, _P, _P, _P], ctypes.c_int),
+    "nmc_lbp_kernel_time": ([_P, _P, _P, _I32], ctypes.c_int),
+    "nmc_lbp_backbone": ([_P, _I32, _I32, ctypes.POINTER(LbpConfig), ctypes.POINTER(LbpResult), _P, _P, _P, _P, _P],
+                         ctypes.c_int),
     "nmc_apt_ladder": ([_P, ctypes.c_double, ctypes.c_double, ctypes.c_double, _I32, _I32, _I32, _P, _P,
                         ctypes.POINTER(_I32), _P], ctypes.c_int),
     "nmc_batch_create": ([_P, _I32, _PP], ctypes.c_int),
@@ -271,6 +288,10 @@ class Replicas:
 
     def __init__(self, inst: Instance, n_replicas: int, seed: int, stream=None):
         self.inst = inst
+        # the instance's device arena must outlive these replicas even when
+        # the instance object is released first (explicitly, or by the cycle
+        # collector, which finalizes in no fixed order)
+        self._inst_buf = inst._buf
         self.R = int(n_replicas)
         self.seed = int(seed)
         _, rb = inst.footprint(self.R)
@@ -320,6 +341,28 @@ class Replicas:
                                     int(meas_sweeps), int(max_temps), _ptr(b), _ptr(sg), ctypes.byref(k),
                                     _stream(stream)))
         return b[: k.value].copy(), sg[: k.value].copy()
+
+    def lbp_backbone(self, replica, which="best", beta=1.0, lambda0=4.0, lambda_ratio=0.8, lambda_min=0.05,
+                     max_iter=200, tol=1e-10, p_min=-2.0, theta_seed=0.99, theta_cut=0.95, stream=None):
+        """Surrogate-Hamiltonian LBP around one replica's state and connected
+        backbone growth; the backbone becomes the device class array.
+        Returns dict(cls, mag, corr, label, lambda, steps, iterations,
+        converged, delta, overlap, self_overlap, backbone_size, n_clusters,
+        largest_cluster, rigid_clauses, seed_clauses)."""
+        n, m = self.inst.n, self.inst.info.n_clauses
+        cfg = LbpConfig(float(beta), float(lambda0), float(lambda_ratio), float(lambda_min), int(max_iter),
+                        float(tol), float(p_min), float(theta_seed), float(theta_cut))
+        res = LbpResult()
+        cls = np.zeros(max(n, 1), np.uint8)
+        mag = np.zeros(max(n, 1), np.float64)
+        corr = np.zeros(max(m, 1), np.float64)
+        label = np.zeros(max(n, 1), np.int32)
+        _check(lib().nmc_lbp_backbone(self._h, int(replica), STATE[which], ctypes.byref(cfg), ctypes.byref(res),
+                                      _ptr(cls), _ptr(mag), _ptr(corr), _ptr(label), _stream(stream)))
+        out = {f: getattr(res, f) for f, _ in LbpResult._fields_}
+        out["lambda"] = out.pop("lambda_")
+        out.update(cls=cls[:n], mag=mag[:n], corr=corr[:m], label=label[:n])
+        return out
 
     def estimate_backbone(self, thr_num=9, thr_den=10, expand=True, stream=None):
         n = self.inst.n
@@ -380,11 +423,18 @@ class Replicas:
                                      int(bool(reset))))
         return dict(ms=ms.value, launches=launches.value, attempts=att.value)
 
+    def lbp_kernel_time(self, reset=False):
+        ms = ctypes.c_double()
+        it = ctypes.c_int64()
+        _check(lib().nmc_lbp_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(it), int(bool(reset))))
+        return dict(ms=ms.value, iterations=it.value)
+
     def free(self):
         if getattr(self, "_h", None):
             lib().nmc_replicas_free(self._h)
             self._h = None
         self._buf = None
+        self._inst_buf = None
 
     def __del__(self):
         try:
