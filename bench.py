@@ -222,11 +222,12 @@ def bench_qap(nmc, torch, seed, sweeps_only=0):
 
 LBP_CFG = dict(beta=1.0, lambda0=4.0, lambda_ratio=0.8, lambda_min=1e-3, max_iter=100, tol=1e-8, p_min=-2.0)
 LBP_THRESHOLDS = ((0.8, 0.6), (0.9, 0.8), (0.95, 0.9))  # (seed, cutoff) per round, raised round by round
-# HBM bytes one message iteration must move per literal slot (edge): u read,
-# h written, h read, u read and written (8 B each), the variable's edge index
+# bytes one message iteration must move per literal slot (edge): u gathered
+# by the variable side, u read and written by the clause side, the field
+# total T gathered by the clause side (8 B each), the variable's edge index
 # and the clause's literal address (4 B each); per variable: clause range,
-# reference spin
-LBP_BYTES_PER_EDGE, LBP_BYTES_PER_VAR = 48, 5
+# reference spin, T written
+LBP_BYTES_PER_EDGE, LBP_BYTES_PER_VAR = 40, 13
 
 
 def bench_lbp(nmc, torch, seed):

@@ -325,9 +325,10 @@ typedef struct nmc_lbp_result {
  * Outputs (each optional, host): class_out [N] bytes, mag_out [N] doubles,
  * corr_out [M] doubles (signed clause moments), label_out [N] int32 (the
  * smallest variable index of the cluster, -1 outside the backbone).
- * Arithmetic is IEEE double.  The workspace (about 24 bytes per literal slot
- * of the padded 4-per-clause layout plus 30 bytes per variable) is allocated
- * on the first call and kept with the replica set.
+ * Arithmetic is IEEE double.  The workspace (16 bytes per literal slot of
+ * the padded 4-per-clause layout, 4 per literal, 8 per clause and about 35
+ * per variable) is allocated on the first call and kept with the replica
+ * set.
  * Errors: INVALID (arguments), STATE (unbound), UNSUPPORTED (QAP), DEVICE. */
 int nmc_lbp_backbone(nmc_replicas *rep, int32_t replica, int32_t which, const nmc_lbp_config *cfg,
                      nmc_lbp_result *res, uint8_t *class_out, double *mag_out, double *corr_out, int32_t *label_out,

@@ -1502,10 +1502,10 @@ static int lbp_impl(nmc_replicas *P, int32_t replica, int32_t which, const nmc_l
     const int32_t n = I->n, m = I->m;
     // workspace
     Arena ar;
-    const size_t o_u = ar.take((size_t)m * 4 * 8), o_keep = ar.take((size_t)m * 4 * 8), o_h = ar.take((size_t)m * 4 * 8);
+    const size_t o_u = ar.take((size_t)m * 4 * 8), o_keep = ar.take((size_t)m * 4 * 8), o_T = ar.take((size_t)n * 8);
     const size_t o_mag = ar.take((size_t)n * 8), o_corr = ar.take((size_t)m * 8);
     const size_t o_ve = ar.take((size_t)I->n_lits * 4), o_s = ar.take((size_t)n);
-    const size_t o_scal = ar.take(8), o_res = ar.take(16);
+    const size_t o_scal = ar.take(64 * 8), o_res = ar.take(24), o_ctl = ar.take(8);
     const size_t o_lab = ar.take((size_t)n * 4), o_olab = ar.take((size_t)n * 4), o_size = ar.take((size_t)n * 4);
     const size_t o_seed = ar.take((size_t)n), o_flag = ar.take(4), o_cnt = ar.take(5 * 4);
     const size_t total = align_up(ar.size, 256);
@@ -1517,13 +1517,14 @@ static int lbp_impl(nmc_replicas *P, int32_t replica, int32_t which, const nmc_l
     LbpWork W{};
     W.u = reinterpret_cast<double *>(b + o_u);
     double *keep = reinterpret_cast<double *>(b + o_keep);
-    W.h = reinterpret_cast<double *>(b + o_h);
+    W.T = reinterpret_cast<double *>(b + o_T);
     W.mag = reinterpret_cast<double *>(b + o_mag);
     W.corr = reinterpret_cast<double *>(b + o_corr);
     W.vedge = reinterpret_cast<int32_t *>(b + o_ve);
     W.s = reinterpret_cast<int8_t *>(b + o_s);
     W.scal = reinterpret_cast<unsigned long long *>(b + o_scal);
     W.res = reinterpret_cast<double *>(b + o_res);
+    W.ctl = reinterpret_cast<int32_t *>(b + o_ctl);
     W.label = reinterpret_cast<int32_t *>(b + o_lab);
     W.out_label = reinterpret_cast<int32_t *>(b + o_olab);
     W.size = reinterpret_cast<int32_t *>(b + o_size);
@@ -1540,24 +1541,36 @@ static int lbp_impl(nmc_replicas *P, int32_t replica, int32_t which, const nmc_l
         HIP_OR_FAIL(hipEventCreate(&pe[0]));
         HIP_OR_FAIL(hipEventCreate(&pe[1]));
     }
-    auto iterate = [&](double lambda, double *delta) -> int {
-        HIP_OR_FAIL(hipMemsetAsync(W.scal, 0, 8, s));
-        if (pe[0])
-            HIP_OR_FAIL(hipEventRecord(pe[0], s));
-        HIP_OR_FAIL(lbp_launch_var(K, W, lambda, 0, s));
-        HIP_OR_FAIL(lbp_launch_clause(K, W, w, 0, s));
-        if (pe[1])
-            HIP_OR_FAIL(hipEventRecord(pe[1], s));
-        unsigned long long bits = 0;
-        HIP_OR_FAIL(hipMemcpyAsync(&bits, W.scal, 8, hipMemcpyDeviceToHost, s));
-        HIP_OR_FAIL(hipStreamSynchronize(s));
-        std::memcpy(delta, &bits, 8);
-        if (pe[0]) {
-            float ms = 0;
-            HIP_OR_FAIL(hipEventElapsedTime(&ms, pe[0], pe[1]));
-            P->lbp_ms += ms;
-            P->lbp_iters += 1;
+    // one step's iterations: queued in batches, convergence decided on the
+    // device after each iteration, one host round trip per batch
+    constexpr int32_t kBatch = 8;
+    auto run_step = [&](double lambda, double *delta, int32_t *done_iters, bool *conv) -> int {
+        HIP_OR_FAIL(hipMemsetAsync(W.scal, 0, 64 * 8, s));
+        HIP_OR_FAIL(hipMemsetAsync(W.ctl, 0, 8, s));
+        int32_t queued = 0, ctl[2] = {0, 0};
+        while (queued < c.max_iter) {
+            const int32_t cnt = std::min(kBatch, c.max_iter - queued);
+            if (pe[0])
+                HIP_OR_FAIL(hipEventRecord(pe[0], s));
+            HIP_OR_FAIL(lbp_launch_iterations(K, W, lambda, w, c.tol, c.max_iter, cnt, s));
+            if (pe[1])
+                HIP_OR_FAIL(hipEventRecord(pe[1], s));
+            queued += cnt;
+            HIP_OR_FAIL(hipMemcpyAsync(ctl, W.ctl, 8, hipMemcpyDeviceToHost, s));
+            HIP_OR_FAIL(hipMemcpyAsync(delta, W.res + 2, 8, hipMemcpyDeviceToHost, s));
+            HIP_OR_FAIL(hipStreamSynchronize(s));
+            if (pe[0]) {
+                float ms = 0;
+                HIP_OR_FAIL(hipEventElapsedTime(&ms, pe[0], pe[1]));
+                P->lbp_ms += ms;
+            }
+            if (ctl[0])
+                break;
         }
+        if (pe[0])
+            P->lbp_iters += ctl[1];
+        *done_iters = ctl[1];
+        *conv = ctl[0] == 1;
         return NMC_OK;
     };
     struct EvGuard {
@@ -1576,7 +1589,9 @@ static int lbp_impl(nmc_replicas *P, int32_t replica, int32_t which, const nmc_l
         return NMC_OK;
     };
 
-    // initial messages at lambda0: h = sigma H, u from h
+    // initial messages at lambda0: u = 0 and T = H give h = sigma H, u from h
+    if (ubytes)
+        HIP_OR_FAIL(hipMemsetAsync(W.u, 0, ubytes, s));
     HIP_OR_FAIL(lbp_launch_setup(K, row, replica % kGroup, W, c.lambda0, s));
     HIP_OR_FAIL(lbp_launch_clause(K, W, w, 0, s));
     double lambda = c.lambda0, kept_lambda = c.lambda0, kept_delta = 0.0;
@@ -1587,16 +1602,13 @@ static int lbp_impl(nmc_replicas *P, int32_t replica, int32_t which, const nmc_l
             HIP_OR_FAIL(hipMemcpyAsync(keep, W.u, ubytes, hipMemcpyDeviceToDevice, s));
         double delta = 0.0;
         bool conv = false;
-        for (int32_t it = 0; it < c.max_iter; ++it) {
-            int rc = iterate(lambda, &delta);
+        int32_t done_iters = 0;
+        {
+            int rc = run_step(lambda, &delta, &done_iters, &conv);
             if (rc)
                 return rc;
-            ++iters;
-            if (delta < c.tol) {
-                conv = true;
-                break;
-            }
         }
+        iters += done_iters;
         ++steps;
         double ov[2] = {0, 0};
         if (conv) {
@@ -1624,7 +1636,7 @@ static int lbp_impl(nmc_replicas *P, int32_t replica, int32_t which, const nmc_l
     // marginals, clause moments, overlaps from the kept messages
     double ov[2];
     {
-        int rc = overlap(kept_lambda, ov);  // also recomputes h from the kept u
+        int rc = overlap(kept_lambda, ov);  // also recomputes T from the kept u
         if (rc)
             return rc;
     }

@@ -192,12 +192,14 @@ hipError_t pt_launch_moments(const void *energy, int energy_is_64, int n, unsign
 // ---- surrogate-Hamiltonian LBP and backbone growth (nmc_lbp.hip) ----
 // Edges e = 4a + j (literal j of clause a); padded edges are never read.
 struct LbpWork {
-    double *u, *h;               // [4M] clause-to-variable and variable-to-clause messages
+    double *u;                   // [4M] clause-to-variable messages
+    double *T;                   // [N] field totals H_i + sum_a sigma_ia u_{a->i}
     double *mag, *corr;          // [N] <r_i>, [M] clause moments
     int32_t *vedge;              // [sum deg] edge of each variable incidence, bit 31 = negated literal
     int8_t *s;                   // [N] reference spins (+1 / -1)
-    unsigned long long *scal;    // [0] bits of the largest |du| of an iteration
-    double *res;                 // [0] overlap p, [1] self-overlap q1
+    unsigned long long *scal;    // [64] bits of the largest |du| of an iteration, by slot
+    double *res;                 // [0] overlap p, [1] self-overlap q1, [2] last iteration's max |du|
+    int32_t *ctl;                // [0] 0 running / 1 converged / 2 out of iterations, [1] iterations
     int32_t *label, *out_label, *size;  // [N]
     uint8_t *seeded;             // [N]
     int32_t *flag;               // [1] labels changed
@@ -207,6 +209,9 @@ hipError_t lbp_launch_setup(const KsatDev &I, const uint8_t *xs_row, int bit, co
                             hipStream_t s);
 hipError_t lbp_launch_var(const KsatDev &I, const LbpWork &W, double lambda, int final_pass, hipStream_t s);
 hipError_t lbp_launch_clause(const KsatDev &I, const LbpWork &W, double w, int final_pass, hipStream_t s);
+// `count` gated iterations (variable side, clause side, control) of one step
+hipError_t lbp_launch_iterations(const KsatDev &I, const LbpWork &W, double lambda, double w, double tol,
+                                 int max_iter, int count, hipStream_t s);
 hipError_t lbp_launch_overlap(const KsatDev &I, const LbpWork &W, hipStream_t s);
 hipError_t lbp_launch_label_init(const KsatDev &I, const LbpWork &W, hipStream_t s);
 hipError_t lbp_launch_hook_jump(const KsatDev &I, const LbpWork &W, double cut, hipStream_t s);

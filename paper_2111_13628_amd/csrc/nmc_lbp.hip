@@ -10,12 +10,19 @@
 // clauses shorter than 4).  sigma_e = +1 for a positive literal.  With the
 // field H_i = lambda eps_i s*_i (eps_i = clauses holding i) and the clause
 // weight exp(-2 beta) for a violated clause, one message iteration is
-//   h_{i->a} = sigma_{ia} (H_i + sum_{b in di} sigma_{ib} u_{b->i}) - u_{a->i}
+//   T_i      = H_i + sum_{b in di} sigma_{ib} u_{b->i}           (per variable)
+//   h_{i->a} = sigma_{ia} T_i - u_{a->i}                         (the cavity field)
 //   u_{a->i} = -1/2 ln[1 - (1 - e^{-2 beta}) prod_{j in da \ i} (1 - tanh h_{j->a}) / 2]
-// (the cavity sum as the full sum minus the edge's own term).  One thread
-// per variable, then one per clause; the largest |du| of an iteration is an
-// atomic max over the bit patterns of non-negative doubles.  Everything is
-// fp64: the pass is memory- and latency-bound (8 bytes per edge and message).
+// The variable kernel (sixteen lanes per variable) writes only T, N doubles
+// that stay in L2; the clause kernel (one thread per clause) forms each h
+// from T and its own u, so no per-edge h is stored and the only scattered
+// access is the variable kernel's gather of u.  The largest |du| of an
+// iteration is a workgroup max, then an atomic max over the bit patterns of
+// non-negative doubles into one of 64 slots.  Iterations are queued in
+// batches without host round trips: a one-thread kernel after each iteration
+// decides convergence on the device, and the kernels of the rest of the batch
+// then return at once, so the result is that of checking after every
+// iteration.  Everything is fp64 (8 bytes per edge and message).
 //
 // Components: labels start as the variable's index; every rigid clause
 // (|moment| >= cutoff) lowers its variables' labels to their minimum
@@ -50,7 +57,8 @@ __device__ __forceinline__ void atomic_max_nonneg(unsigned long long *p, double 
 }
 
 // reference spins of one replica, edge list of every variable (edge | sign
-// bit 31, in the order of the variable's clause list), initial h = sigma H
+// bit 31, in the order of the variable's clause list) and T = H at lambda0
+// (with u = 0 the first clause pass then sees h = sigma H)
 __global__ void lbp_setup_kernel(KsatDev I, const uint8_t *xs_row, int bit, LbpWork W, double lambda0) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= I.n)
@@ -58,7 +66,7 @@ __global__ void lbp_setup_kernel(KsatDev I, const uint8_t *xs_row, int bit, LbpW
     const int s = ((xs_row[i] >> bit) & 1) ? 1 : -1;
     W.s[i] = (int8_t)s;
     const int q0 = I.var_ptr[i], q1 = I.var_ptr[i + 1];
-    const double H = lambda0 * (double)(q1 - q0) * (double)s;
+    W.T[i] = lambda0 * (double)(q1 - q0) * (double)s;
     for (int q = q0; q < q1; ++q) {
         const int a = I.var_cl[q];
         int j = 0;
@@ -68,36 +76,73 @@ __global__ void lbp_setup_kernel(KsatDev I, const uint8_t *xs_row, int bit, LbpW
                 break;
         }
         const uint32_t ad = I.clause_addr[(size_t)a * 4 + j];
-        const bool neg = ad >= (uint32_t)I.n;
-        W.vedge[q] = (4 * a + j) | (neg ? (int)0x80000000 : 0);
-        W.h[4 * a + j] = neg ? -H : H;
+        W.vedge[q] = (4 * a + j) | (ad >= (uint32_t)I.n ? (int)0x80000000 : 0);
     }
 }
 
-// variable side: h for every edge of i; with final != 0 also <r_i>
-__global__ void lbp_var_kernel(KsatDev I, LbpWork W, double lambda, int final_pass) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= I.n)
+// variable side: T_i; with final != 0 also <r_i> = tanh T_i.  kVarLanes
+// lanes share a variable: each takes every kVarLanes-th incidence
+// (consecutive lanes read consecutive edge words), the partial sums meet by
+// butterfly shuffles inside the lane group.  With gated != 0 the launch does
+// nothing once the iteration control has stopped.
+constexpr int kVarLanes = 16;
+
+__global__ void lbp_var_kernel(KsatDev I, LbpWork W, double lambda, int final_pass, int gated) {
+    if (gated && W.ctl[0])
         return;
-    const int q0 = I.var_ptr[i], q1 = I.var_ptr[i + 1];
-    double tot = lambda * (double)(q1 - q0) * (double)W.s[i];
-    for (int q = q0; q < q1; ++q) {
-        const int w = W.vedge[q];
-        const double u = W.u[w & 0x7FFFFFFF];
-        tot += w < 0 ? -u : u;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = t / kVarLanes, l = t % kVarLanes;
+    const bool live = i < I.n;
+    int q0 = 0, q1 = 0;
+    double part = 0.0;
+    if (live) {
+        q0 = I.var_ptr[i];
+        q1 = I.var_ptr[i + 1];
+        for (int q = q0 + l; q < q1; q += kVarLanes) {
+            const int w = W.vedge[q];
+            const double u = W.u[w & 0x7FFFFFFF];
+            part += w < 0 ? -u : u;
+        }
     }
-    for (int q = q0; q < q1; ++q) {
-        const int w = W.vedge[q];
-        const int e = w & 0x7FFFFFFF;
-        W.h[e] = (w < 0 ? -tot : tot) - W.u[e];
-    }
+    for (int off = kVarLanes / 2; off > 0; off >>= 1)
+        part += __shfl_xor(part, off, kVarLanes);
+    if (!live || l != 0)
+        return;
+    const double tot = lambda * (double)(q1 - q0) * (double)W.s[i] + part;
+    W.T[i] = tot;
     if (final_pass)
         W.mag[i] = tanh(tot);
 }
 
-// clause side: new u for every edge of a and the largest change; with
-// final != 0 the clause moment instead (u unchanged)
-__global__ void lbp_clause_kernel(KsatDev I, LbpWork W, double w, int final_pass) {
+constexpr int kDeltaSlots = 64;
+
+// iteration control, one thread after each iteration: take the iteration's
+// largest |du| (the 64 slots), clear them for the next, count the
+// iteration, stop on convergence (ctl[0] = 1) or at max_iter (ctl[0] = 2)
+__global__ void lbp_judge_kernel(LbpWork W, double tol, int max_iter) {
+    if (W.ctl[0])
+        return;
+    unsigned long long mx = 0;
+    for (int k = 0; k < kDeltaSlots; ++k) {
+        mx = W.scal[k] > mx ? W.scal[k] : mx;
+        W.scal[k] = 0ull;
+    }
+    const double d = __longlong_as_double((long long)mx);
+    W.res[2] = d;
+    const int it = ++W.ctl[1];
+    if (d < tol)
+        W.ctl[0] = 1;
+    else if (it >= max_iter)
+        W.ctl[0] = 2;
+}
+
+// clause side: h_{j->a} = sigma_j T_{v_j} - u_{a->j}, then the new u for
+// every edge of a and the largest change; with final != 0 the clause moment
+// instead (u unchanged)
+__global__ void __launch_bounds__(256) lbp_clause_kernel(KsatDev I, LbpWork W, double w, int final_pass, int gated) {
+    if (gated && W.ctl[0])
+        return;
+    __shared__ double wmax[256 / 64];
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     double dmax = 0.0;
     if (a < I.m) {
@@ -105,12 +150,12 @@ __global__ void lbp_clause_kernel(KsatDev I, LbpWork W, double w, int final_pass
         int k = 0;
         for (int j = 0; j < 4; ++j) {
             int v;
-            double s;
-            if (!decode(I.clause_addr[(size_t)a * 4 + j], I.n, v, s))
+            double sj;
+            if (!decode(I.clause_addr[(size_t)a * 4 + j], I.n, v, sj))
                 break;
-            t[j] = tanh(W.h[4 * a + j]);
+            t[j] = tanh(sj * W.T[v] - W.u[4 * a + j]);
             P[j] = (1.0 - t[j]) / 2.0;
-            sg[j] = s;
+            sg[j] = sj;
             k = j + 1;
         }
         if (!final_pass) {
@@ -135,11 +180,19 @@ __global__ void lbp_clause_kernel(KsatDev I, LbpWork W, double w, int final_pass
         }
     }
     if (!final_pass) {
-        // wave maximum, then one atomic per wave
+        // wave max, workgroup max, one atomic per workgroup into a slot
         for (int off = 32; off > 0; off >>= 1)
             dmax = fmax(dmax, __shfl_xor(dmax, off));
-        if ((threadIdx.x & 63) == 0 && dmax > 0.0)
-            atomic_max_nonneg(W.scal, dmax);
+        if ((threadIdx.x & 63) == 0)
+            wmax[threadIdx.x >> 6] = dmax;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double m = wmax[0];
+            for (int k = 1; k < (int)(blockDim.x >> 6); ++k)
+                m = fmax(m, wmax[k]);
+            if (m > 0.0)
+                atomic_max_nonneg(&W.scal[blockIdx.x % kDeltaSlots], m);
+        }
     }
 }
 
@@ -291,14 +344,28 @@ hipError_t lbp_launch_setup(const KsatDev &I, const uint8_t *xs_row, int bit, co
 hipError_t lbp_launch_var(const KsatDev &I, const LbpWork &W, double lambda, int final_pass, hipStream_t s) {
     if (I.n == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(lbp_var_kernel, dim3(blocks(I.n)), dim3(kLbpThreads), 0, s, I, W, lambda, final_pass);
+    hipLaunchKernelGGL(lbp_var_kernel, dim3(blocks(I.n * kVarLanes)), dim3(kLbpThreads), 0, s, I, W, lambda,
+                       final_pass, 0);
     return hipGetLastError();
 }
 
 hipError_t lbp_launch_clause(const KsatDev &I, const LbpWork &W, double w, int final_pass, hipStream_t s) {
     if (I.m == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(lbp_clause_kernel, dim3(blocks(I.m)), dim3(kLbpThreads), 0, s, I, W, w, final_pass);
+    hipLaunchKernelGGL(lbp_clause_kernel, dim3(blocks(I.m)), dim3(kLbpThreads), 0, s, I, W, w, final_pass, 0);
+    return hipGetLastError();
+}
+
+hipError_t lbp_launch_iterations(const KsatDev &I, const LbpWork &W, double lambda, double w, double tol,
+                                 int max_iter, int count, hipStream_t s) {
+    for (int k = 0; k < count; ++k) {
+        if (I.n > 0)
+            hipLaunchKernelGGL(lbp_var_kernel, dim3(blocks(I.n * kVarLanes)), dim3(kLbpThreads), 0, s, I, W, lambda,
+                               0, 1);
+        if (I.m > 0)
+            hipLaunchKernelGGL(lbp_clause_kernel, dim3(blocks(I.m)), dim3(kLbpThreads), 0, s, I, W, w, 0, 1);
+        hipLaunchKernelGGL(lbp_judge_kernel, dim3(1), dim3(1), 0, s, W, tol, max_iter);
+    }
     return hipGetLastError();
 }
 
