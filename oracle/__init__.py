@@ -86,6 +86,8 @@ def lib():
             L.orc_lbp_cnf.restype = ctypes.c_int
             L.orc_cnf_clusters.argtypes = [_I32, _I32, _P, _P, _P, _D, _D, _P, _P]
             L.orc_cnf_clusters.restype = _I32
+            L.orc_ksat_whiten.argtypes = [_I32, _I32, _P, _P, _P, _P, _P, _P]
+            L.orc_ksat_whiten.restype = _I32
             _lib = L
     return _lib
 
@@ -184,6 +186,16 @@ class KSat:
         return dict(u=u[: len(self.lits)], mag=mag[: self.n], corr=corr[: self.m], **{
             k: (int(v) if k in ("steps", "iterations", "converged") else float(v))
             for k, v in zip(("lambda", "steps", "iterations", "converged", "delta", "overlap", "self_overlap"), st)})
+
+    def whiten(self, x, order=None):
+        """Whitening of the 0/1 state x: (frozen count, star mask, passes)."""
+        x = _c(x, np.uint8)
+        star = np.zeros(max(self.n, 1), np.uint8)
+        passes = ctypes.c_int32()
+        o = None if order is None else _c(order, np.int32)
+        k = lib().orc_ksat_whiten(self.n, self.m, _p(self.cptr), _p(self.lits), _p(x), _p(o), _p(star),
+                                  ctypes.byref(passes))
+        return int(k), star[: self.n], passes.value
 
     def clusters(self, corr, theta_seed, theta_cut):
         """Connected backbone growth: (label, cls, n_clusters)."""

@@ -25,6 +25,11 @@
  *   - replica exchange between neighbouring temperatures and the energy
  *     spread that sets the adaptive temperature ladder (appendix A,
  *     "Adaptive Parallel Tempering"; the first step of algorithm 1).
+ *   - loopy belief propagation on the localized surrogate Hamiltonian of a
+ *     CNF and connected backbone growth (sections on surrogate Hamiltonians,
+ *     LBP and backbones; appendix C).
+ *   - whitening of low-energy states (section "Whitening procedure for low
+ *     energy states").
  *
  * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random
  * numbers: as easy as 1, 2, 3", SC'11), written here from that paper's
@@ -839,4 +844,66 @@ int32_t orc_cnf_clusters(int32_t n, int32_t m, const int32_t *cptr, const int32_
     free(comp);
     adj_free(&g);
     return clusters;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Whitening of a low-energy state (section "Whitening procedure for low    */
+/* energy states")                                                           */
+/* ------------------------------------------------------------------------ */
+
+/* A variable is labelled white ("star") when none of its clauses pins it.
+ * Clause a pins its variable i when i's literal is the only true literal of
+ * a and no other variable of a is white; a clause with no true literal (a
+ * violated clause of a low-energy state) pins nothing, which is the
+ * section's extension to states that are not solutions.  Variables are
+ * inspected one at a time in the given order (index order when order is
+ * NULL), pass after pass, until a pass labels nothing new; the others are
+ * frozen.  star[i] = 1 for white, 0 for frozen.  Returns the number of
+ * frozen variables; *passes receives the passes made (the last one labels
+ * nothing). */
+int32_t orc_ksat_whiten(int32_t n, int32_t m, const int32_t *cptr, const int32_t *lits, const uint8_t *x,
+                        const int32_t *order, uint8_t *star, int32_t *passes)
+{
+    orc_adj g;
+    if (adj_build(n, m, cptr, lits, &g))
+        return -1;
+    for (int32_t i = 0; i < n; ++i)
+        star[i] = 0;
+    int32_t npass = 0, changed = 1;
+    while (changed) {
+        changed = 0;
+        ++npass;
+        for (int32_t k = 0; k < n; ++k) {
+            int32_t i = order ? order[k] : k;
+            if (star[i])
+                continue;
+            int pinned = 0;
+            for (int32_t e = g.ptr[i]; e < g.ptr[i + 1] && !pinned; ++e) {
+                int32_t a = g.cl[e];
+                int own_true = 0, other_true = 0, other_star = 0;
+                for (int32_t p = cptr[a]; p < cptr[a + 1]; ++p) {
+                    int32_t v = lit_var(lits[p]);
+                    int t = lit_true(lits[p], x);
+                    if (v == i)
+                        own_true = t;
+                    else {
+                        other_true |= t;
+                        other_star |= star[v];
+                    }
+                }
+                pinned = own_true && !other_true && !other_star;
+            }
+            if (!pinned) {
+                star[i] = 1;
+                changed = 1;
+            }
+        }
+    }
+    int32_t frozen = 0;
+    for (int32_t i = 0; i < n; ++i)
+        frozen += !star[i];
+    if (passes)
+        *passes = npass;
+    adj_free(&g);
+    return frozen;
 }
