@@ -261,6 +261,24 @@ def bench_lbp(nmc, torch, seed):
 
     path(False)  # warm-up
     rep, rounds, be, wall, t_lbp = path(False)
+    # whitening of every replica's best state (section on whitening): frozen
+    # cores of the NMC-with-LBP states against plain SA over the same sweeps
+    def whiten(r):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fz, _, passes = r.whiten("best")
+        torch.cuda.synchronize()
+        bpr = r.best_energy()["best_per_replica"]
+        top = int(np.argmin(bpr))
+        return {"seconds": time.perf_counter() - t0, "passes": passes, "replicas_with_frozen": int((fz > 0).sum()),
+                "frozen_max": int(fz.max()), "frozen_mean": float(fz.mean()), "best_replica_energy": int(bpr[top]),
+                "best_replica_frozen": int(fz[top])}
+    white_nmc = whiten(rep)
+    sa = nmc.Replicas(inst, R, seed)
+    sa.anneal(instances.linear_schedule(BETA0, BETA1, S_ANNEAL + ROUNDS * S_RE)[None, :])
+    white_sa = whiten(sa)
+    white_sa["best_energy"] = sa.best_energy()["best"]
+    del sa
     prep, _, _, _, _ = path(True)
     kt = prep.kernel_time()
     lt = prep.lbp_kernel_time()
@@ -281,7 +299,7 @@ def bench_lbp(nmc, torch, seed):
                     "ms_per_iteration": ms_it, "bytes_per_iteration": bytes_it, "iterations": lt["iterations"]}
     return {"attempts": att, "wall_s": wall, "attempts_per_s": att / wall, "lbp_s": t_lbp,
             "lbp_share": t_lbp / wall, "rounds": rounds, "best_energy": be["best"], "roofline": roofline,
-            "lbp_roofline": lbp_roofline}
+            "lbp_roofline": lbp_roofline, "whitening_nmc_lbp": white_nmc, "whitening_plain_sa": white_sa}
 
 
 APT_TEMPS, APT_CHAINS, APT_BETA_FIRST, APT_ALPHA = 64, 16, 1.5, 1.1

@@ -335,6 +335,27 @@ int nmc_lbp_backbone(nmc_replicas *rep, int32_t replica, int32_t which, const nm
                      void *stream);
 
 /* ---------------------------------------------------------------------------
+ * whitening (section "Whitening procedure for low energy states")
+ * ------------------------------------------------------------------------- */
+
+/* Frozen variables of every replica's current or best state (k-SAT only).
+ * A variable turns white unless some clause has the variable's literal as its
+ * only true literal and no other white variable in it; a violated clause
+ * pins nothing (the section's extension to states that are not solutions).
+ * Repeated until nothing changes; the remaining variables are frozen (for a
+ * solution, a lower bound on the variables frozen across its cluster).
+ *   which       NMC_STATE_CURRENT or NMC_STATE_BEST
+ *   frozen_out  host int32 [R]: frozen variables per replica
+ *   white_out   optional host bytes [R][N]: 1 = white, 0 = frozen
+ *   passes      optional: passes over the variables of the slowest group of
+ *               4 replicas (the last pass changes nothing)
+ * The result does not depend on the inspection order.  The device workspace
+ * (N bytes per 4 replicas) is allocated on the first call and kept with the
+ * replica set.  Errors: INVALID, STATE, UNSUPPORTED (QAP), DEVICE. */
+int nmc_whiten(nmc_replicas *rep, int32_t which, int32_t *frozen_out, uint8_t *white_out, int32_t *passes,
+               void *stream);
+
+/* ---------------------------------------------------------------------------
  * best_energy and state access
  * ------------------------------------------------------------------------- */
 

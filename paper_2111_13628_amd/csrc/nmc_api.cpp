@@ -638,6 +638,8 @@ struct nmc_replicas {
     unsigned long long *pt_acc = nullptr;
     // LBP workspace (library-owned, sized for the instance on first use)
     uint8_t *lbp_dev = nullptr;
+    // whitening workspace (library-owned): white bits, counts, passes
+    uint8_t *wh_dev = nullptr;
     // LBP message-iteration kernel time (profiling)
     double lbp_ms = 0;
     int64_t lbp_iters = 0;
@@ -826,8 +828,10 @@ int nmc_replicas_create(nmc_instance *I, int32_t n_replicas, uint64_t seed, void
 void nmc_replicas_free(nmc_replicas *P) {
     if (!P)
         return;
-    if (P->tab_dev || P->pt_acc || P->lbp_dev)
+    if (P->tab_dev || P->pt_acc || P->lbp_dev || P->wh_dev)
         (void)hipDeviceSynchronize();
+    if (P->wh_dev)
+        (void)hipFree(P->wh_dev);
     if (P->tab_dev)
         (void)hipFree(P->tab_dev);
     if (P->pt_acc)
@@ -1689,6 +1693,53 @@ int nmc_lbp_backbone(nmc_replicas *P, int32_t replica, int32_t which, const nmc_
                      void *stream) {
     try {
         return lbp_impl(P, replica, which, cfg, res, class_out, mag_out, corr_out, label_out, stream);
+    } catch (const std::bad_alloc &) {
+        return fail(NMC_ERR_CAPACITY, "host allocation failed");
+    }
+}
+
+int nmc_whiten(nmc_replicas *P, int32_t which, int32_t *frozen_out, uint8_t *white_out, int32_t *passes,
+               void *stream) {
+    if (!P || !frozen_out)
+        return fail(NMC_ERR_INVALID, "NULL argument");
+    nmc_instance *I = P->inst;
+    if (!I->dev)
+        return fail(NMC_ERR_STATE, "instance is not bound");
+    if (I->kind != NMC_KIND_KSAT)
+        return fail(NMC_ERR_UNSUPPORTED, "whitening applies to k-SAT states");
+    if (which != NMC_STATE_CURRENT && which != NMC_STATE_BEST)
+        return fail(NMC_ERR_INVALID, "which must be NMC_STATE_CURRENT or NMC_STATE_BEST");
+    try {
+        hipStream_t s = as_stream(stream);
+        const int32_t n = I->n, G = P->G, R = P->R;
+        const size_t rows = align_up((size_t)G * n, 256), cnt = align_up((size_t)G * kGroup * 4, 256);
+        if (!P->wh_dev)
+            HIP_OR_FAIL(hipMalloc(&P->wh_dev, rows + cnt + 256));
+        uint8_t *white = P->wh_dev;
+        int32_t *frozen = reinterpret_cast<int32_t *>(P->wh_dev + rows);
+        int32_t *pass = reinterpret_cast<int32_t *>(P->wh_dev + rows + cnt);
+        HIP_OR_FAIL(hipMemsetAsync(pass, 0, 4, s));
+        const uint8_t *src = which == NMC_STATE_BEST ? P->k.best_xs : P->k.xs;
+        HIP_OR_FAIL(ksat_launch_whiten(I->ksat_dev(), src, G, R, white, frozen, pass, s));
+        HIP_OR_FAIL(hipMemcpyAsync(frozen_out, frozen, (size_t)R * 4, hipMemcpyDeviceToHost, s));
+        int32_t np = 0;
+        HIP_OR_FAIL(hipMemcpyAsync(&np, pass, 4, hipMemcpyDeviceToHost, s));
+        std::vector<uint8_t> packed;
+        if (white_out) {
+            packed.resize((size_t)G * n);
+            HIP_OR_FAIL(hipMemcpyAsync(packed.data(), white, packed.size(), hipMemcpyDeviceToHost, s));
+        }
+        HIP_OR_FAIL(hipStreamSynchronize(s));
+        if (white_out)
+            for (int32_t r = 0; r < R; ++r) {
+                const uint8_t *row = packed.data() + (size_t)(r / kGroup) * n;
+                uint8_t *dst = white_out + (size_t)r * n;
+                for (int32_t v = 0; v < n; ++v)
+                    dst[v] = (row[v] >> (r % kGroup)) & 1u;
+            }
+        if (passes)
+            *passes = np;
+        return ok();
     } catch (const std::bad_alloc &) {
         return fail(NMC_ERR_CAPACITY, "host allocation failed");
     }

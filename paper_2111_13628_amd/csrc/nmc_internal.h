@@ -218,6 +218,14 @@ hipError_t lbp_launch_hook_jump(const KsatDev &I, const LbpWork &W, double cut, 
 hipError_t lbp_launch_finish(const KsatDev &I, const LbpWork &W, double seed_thr, double cut, uint8_t *cls,
                              hipStream_t s);
 
+// ---- whitening (nmc_whiten.hip) ----
+size_t ksat_whiten_lds_bytes(int n);
+// white bits per (group, variable) into white_out [G][N], frozen count per
+// replica into frozen_out [R], passes of the slowest group (atomic max) into
+// *passes_out (zero it first)
+hipError_t ksat_launch_whiten(const KsatDev &I, const uint8_t *xs, int n_groups, int n_rep, uint8_t *white_out,
+                              int32_t *frozen_out, int32_t *passes_out, hipStream_t s);
+
 // records msg as the calling thread's nmc_last_error text; returns code
 int set_last_error(int code, const char *msg);
 

@@ -131,6 +131,7 @@ _SIGS = {
     "nmc_set_profiling": ([_P, _I32], ctypes.c_int),
     "nmc_kernel_time": ([_P, _P, _P, _P, _I32], ctypes.c_int),
     "nmc_pt_run": ([_P, _P, _I32, _I32, _I32, _I32, _I64, _P, _P, _P], ctypes.c_int),
+    "nmc_whiten": ([_P, _I32, _P, _P, _P, _P], ctypes.c_int),
     "nmc_lbp_kernel_time": ([_P, _P, _P, _I32], ctypes.c_int),
     "nmc_lbp_backbone": ([_P, _I32, _I32, ctypes.POINTER(LbpConfig), ctypes.POINTER(LbpResult), _P, _P, _P, _P, _P],
                          ctypes.c_int),
@@ -422,6 +423,15 @@ class Replicas:
         _check(lib().nmc_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(launches), ctypes.byref(att),
                                      int(bool(reset))))
         return dict(ms=ms.value, launches=launches.value, attempts=att.value)
+
+    def whiten(self, which="best", white=False, stream=None):
+        """Frozen variables per replica after whitening; with white=True also
+        the [R][N] white mask.  Returns (frozen, white_or_None, passes)."""
+        fz = np.zeros(self.R, np.int32)
+        wm = np.zeros((self.R, self.inst.n), np.uint8) if white else None
+        p = _I32()
+        _check(lib().nmc_whiten(self._h, STATE[which], _ptr(fz), _ptr(wm), ctypes.byref(p), _stream(stream)))
+        return fz, wm, p.value
 
     def lbp_kernel_time(self, reset=False):
         ms = ctypes.c_double()
