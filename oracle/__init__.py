@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "nmc_oracle.c")
 _LIB = os.path.join(_HERE, "libnmc_oracle.so")
 
-STREAM_SWEEP, STREAM_INIT, STREAM_QAP_SWEEP, STREAM_QAP_INIT, STREAM_PT_SWAP = 0, 1, 2, 3, 4
+STREAM_SWEEP, STREAM_INIT, STREAM_QAP_SWEEP, STREAM_QAP_INIT, STREAM_PT_SWAP, STREAM_CFLIP = 0, 1, 2, 3, 4, 5
 
 
 def build(force: bool = True) -> str:
@@ -88,6 +88,9 @@ def lib():
             L.orc_cnf_clusters.restype = _I32
             L.orc_ksat_whiten.argtypes = [_I32, _I32, _P, _P, _P, _P, _P, _P]
             L.orc_ksat_whiten.restype = _I32
+            L.orc_ksat_cluster_flip.argtypes = [_I32, _I32, _P, _P, _P, _I32, _I32, _U64, _U32, _D, _I64, _P, _P,
+                                                _P, _P, _P, _P]
+            L.orc_ksat_cluster_flip.restype = _I32
             _lib = L
     return _lib
 
@@ -242,6 +245,23 @@ class KSatReplicas:
 
     def pt_run(self, beta, n_rounds, sweeps_per_round, first_parity=0, target=-1, chains=None):
         return _pt_run(self, self.x, beta, n_rounds, sweeps_per_round, first_parity, target, chains)
+
+    def cluster_flip(self, label, beta, target=-1, r_begin=0, r_end=None):
+        """One collective-move sweep over the clusters of `label`; returns the
+        clusters flipped per replica."""
+        inst = self.inst
+        lab = _c(label, np.int32)
+        r_end = self.R if r_end is None else r_end
+        acc = np.zeros(self.R, np.int32)
+
+        def run(a, b):
+            lib().orc_ksat_cluster_flip(inst.n, inst.m, _p(inst.cptr), _p(inst.lits), _p(lab), a, b, self.seed,
+                                        self.sweeps_done, float(beta), int(target), _p(self.x), _p(self.energy),
+                                        _p(self.best), _p(self.first_hit), _p(self.best_x), _p(acc))
+
+        _run_threads(run, _split(r_begin, r_end, self.threads))
+        self.sweeps_done += 1
+        return acc
 
     def apt_ladder(self, beta_first, alpha, sigma_min, equil, meas, max_temps):
         return _apt_ladder(self, beta_first, alpha, sigma_min, equil, meas, max_temps)

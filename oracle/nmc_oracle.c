@@ -30,6 +30,8 @@
  *     LBP and backbones; appendix C).
  *   - whitening of low-energy states (section "Whitening procedure for low
  *     energy states").
+ *   - collective flips of backbone clusters (the NMC scheme's nonlocal
+ *     move: a whole cluster flipped at once under the Metropolis rule).
  *
  * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random
  * numbers: as easy as 1, 2, 3", SC'11), written here from that paper's
@@ -906,4 +908,69 @@ int32_t orc_ksat_whiten(int32_t n, int32_t m, const int32_t *cptr, const int32_t
         *passes = npass;
     adj_free(&g);
     return frozen;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Collective flips of backbone clusters (figure of the NMC scheme, panel   */
+/* (c): a nonlocal flip of a whole backbone cluster; the section on         */
+/* annealed thresholds lists it as the alternative to heating the backbone) */
+/* ------------------------------------------------------------------------ */
+
+/* One collective-move sweep: for every replica, the clusters (label[i] >= 0
+ * names variable i's cluster by its smallest variable; -1 = no cluster) are
+ * proposed in increasing label order; proposal k flips every variable of the
+ * k-th cluster at once and is taken when dE <= 0, else when the replica's
+ * CFLIP word u for (k, t, replica / 4) satisfies u < T(beta, dE) (the k-SAT
+ * threshold of orc_threshold).  dE is the exact energy difference (recounted
+ * here in full).  The sweep counts as sweep t of the schedule for best,
+ * first-hit and snapshot bookkeeping (as in orc_ksat_anneal).  accepted[r]
+ * receives the clusters flipped in replica r. */
+#define ORC_STREAM_CFLIP 5u
+int orc_ksat_cluster_flip(int32_t n, int32_t m, const int32_t *cptr, const int32_t *lits, const int32_t *label,
+                          int32_t r_begin, int32_t r_end, uint64_t seed, uint32_t t, double beta, int64_t target,
+                          uint8_t *x, int32_t *energy, int32_t *best, int32_t *first_hit, uint8_t *best_x,
+                          int32_t *accepted)
+{
+    /* the clusters in increasing label order */
+    int32_t *roots = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+    int32_t nc = 0;
+    for (int32_t i = 0; i < n; ++i)
+        if (label[i] == i)
+            roots[nc++] = i;
+    uint8_t *y = (uint8_t *)malloc((size_t)n + 1);
+    for (int32_t r = r_begin; r < r_end; ++r) {
+        uint8_t *xr = x + (size_t)r * n;
+        int32_t e = orc_ksat_energy(n, m, cptr, lits, xr);
+        int32_t acc = 0;
+        for (int32_t k = 0; k < nc; ++k) {
+            memcpy(y, xr, (size_t)n);
+            for (int32_t i = 0; i < n; ++i)
+                if (label[i] == roots[k])
+                    y[i] ^= 1;
+            int32_t d = orc_ksat_energy(n, m, cptr, lits, y) - e;
+            int take = d <= 0;
+            if (!take) {
+                uint32_t u = orc_uniform_u32(seed, ORC_STREAM_CFLIP, (uint32_t)k, t, (uint32_t)r);
+                take = u < orc_threshold(beta, d);
+            }
+            if (take) {
+                memcpy(xr, y, (size_t)n);
+                e += d;
+                ++acc;
+            }
+        }
+        energy[r] = e;
+        if (e < best[r]) {
+            best[r] = e;
+            if (best_x)
+                memcpy(best_x + (size_t)r * n, xr, (size_t)n);
+        }
+        if (first_hit[r] < 0 && e <= target)
+            first_hit[r] = (int32_t)(t + 1);
+        if (accepted)
+            accepted[r] = acc;
+    }
+    free(y);
+    free(roots);
+    return nc;
 }
