@@ -254,6 +254,7 @@ def bench_lbp(nmc, torch, seed):
             t_lbp += time.perf_counter() - t1
             rounds.append({k: g[k] for k in ("lambda", "steps", "iterations", "converged", "overlap", "self_overlap",
                                              "backbone_size", "n_clusters", "largest_cluster")})
+            rounds[-1]["label"] = g["label"]
             rep.reanneal(reanneal_profile(S_RE), "backbone")
         be = rep.best_energy()
         torch.cuda.synchronize()
@@ -274,6 +275,18 @@ def bench_lbp(nmc, torch, seed):
                 "frozen_max": int(fz.max()), "frozen_mean": float(fz.mean()), "best_replica_energy": int(bpr[top]),
                 "best_replica_frozen": int(fz[top])}
     white_nmc = whiten(rep)
+    # one collective-move sweep over the last round's clusters (the scheme's
+    # nonlocal move), timed on its own, at the cold beta and at beta_hot
+    cflip = {}
+    for b in (BETA1, BETA_HOT):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        acc = rep.cluster_flip(rounds[-1]["label"], b)
+        torch.cuda.synchronize()
+        cflip[f"beta_{b:g}"] = {"seconds": time.perf_counter() - t0, "clusters": rounds[-1]["n_clusters"],
+                                "flips_mean": float(acc.mean()), "replicas_with_flips": int((acc > 0).sum())}
+    for r in rounds:
+        r.pop("label")
     sa = nmc.Replicas(inst, R, seed)
     sa.anneal(instances.linear_schedule(BETA0, BETA1, S_ANNEAL + ROUNDS * S_RE)[None, :])
     white_sa = whiten(sa)
@@ -299,7 +312,8 @@ def bench_lbp(nmc, torch, seed):
                     "ms_per_iteration": ms_it, "bytes_per_iteration": bytes_it, "iterations": lt["iterations"]}
     return {"attempts": att, "wall_s": wall, "attempts_per_s": att / wall, "lbp_s": t_lbp,
             "lbp_share": t_lbp / wall, "rounds": rounds, "best_energy": be["best"], "roofline": roofline,
-            "lbp_roofline": lbp_roofline, "whitening_nmc_lbp": white_nmc, "whitening_plain_sa": white_sa}
+            "lbp_roofline": lbp_roofline, "whitening_nmc_lbp": white_nmc, "whitening_plain_sa": white_sa,
+            "cluster_flip": cflip}
 
 
 APT_TEMPS, APT_CHAINS, APT_BETA_FIRST, APT_ALPHA = 64, 16, 1.5, 1.1

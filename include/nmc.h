@@ -356,6 +356,31 @@ int nmc_whiten(nmc_replicas *rep, int32_t which, int32_t *frozen_out, uint8_t *w
                void *stream);
 
 /* ---------------------------------------------------------------------------
+ * collective cluster flips (the nonlocal move of the NMC scheme: a whole
+ * backbone cluster flipped at once; the section on annealed thresholds names
+ * it as the alternative to heating the backbone)
+ * ------------------------------------------------------------------------- */
+
+/* One collective-move sweep of every replica (k-SAT only).
+ *   label    host int32 [N]: -1, or the cluster of variable i named by a
+ *            variable that labels itself (label[label[i]] == label[i]); the
+ *            label_out of nmc_lbp_backbone has this form
+ *   beta     inverse temperature of the acceptance, finite, >= 0
+ * The clusters are proposed in increasing label order; proposal k flips every
+ * variable of the k-th cluster at once.  With dE the exact energy change, the
+ * flip is taken when dE <= 0, else when the replica's word of the Philox
+ * block at counter (k, sweeps done, replica / 4, 5) is below
+ * T = min(2^32-1, floor(2^32 exp(-beta dE))).  The call counts as one sweep:
+ * the sweep counter advances by 1, and best energies, best-state snapshots
+ * and first hits (against target) are updated at its end.  accepted_out
+ * (optional, host int32 [R]) receives the clusters flipped per replica.  The
+ * cluster lists are built on the host and uploaded to the library-owned
+ * buffer.  Errors: INVALID (labels, beta), STATE, UNSUPPORTED (QAP),
+ * CAPACITY, DEVICE. */
+int nmc_cluster_flip(nmc_replicas *rep, const int32_t *label, double beta, int64_t target, int32_t *accepted_out,
+                     void *stream);
+
+/* ---------------------------------------------------------------------------
  * best_energy and state access
  * ------------------------------------------------------------------------- */
 

@@ -1745,6 +1745,146 @@ int nmc_whiten(nmc_replicas *P, int32_t which, int32_t *frozen_out, uint8_t *whi
     }
 }
 
+static int cluster_flip_impl(nmc_replicas *P, const int32_t *label, double beta, int64_t target,
+                             int32_t *accepted_out, void *stream) {
+    if (!P || !label)
+        return fail(NMC_ERR_INVALID, "NULL argument");
+    nmc_instance *I = P->inst;
+    if (!I->dev)
+        return fail(NMC_ERR_STATE, "instance is not bound");
+    if (I->kind != NMC_KIND_KSAT)
+        return fail(NMC_ERR_UNSUPPORTED, "cluster flips apply to k-SAT states");
+    if (!std::isfinite(beta) || beta < 0)
+        return fail(NMC_ERR_INVALID, "beta = %g is not finite and >= 0", beta);
+    if ((uint64_t)P->sweeps_done + 1 > 0xFFFFFFFFull)
+        return fail(NMC_ERR_INVALID, "sweep counter would pass 2^32 - 1");
+    const int32_t n = I->n, m = I->m;
+    for (int32_t i = 0; i < n; ++i) {
+        const int32_t l = label[i];
+        if (l < -1 || l >= n || (l >= 0 && label[l] != l))
+            return fail(NMC_ERR_INVALID, "label[%d] = %d is not -1 or a variable that labels itself", i, l);
+    }
+    // clusters in increasing label order; their variables and clauses
+    std::vector<int32_t> ord(n, -1), v_ptr(1, 0), v_list, cl_ptr, cnt;
+    int32_t nc = 0;
+    for (int32_t i = 0; i < n; ++i)
+        if (label[i] == i)
+            ord[i] = nc++;
+    cnt.assign(nc + 1, 0);
+    for (int32_t i = 0; i < n; ++i)
+        if (label[i] >= 0)
+            cnt[ord[label[i]] + 1]++;
+    v_ptr.assign(nc + 1, 0);
+    for (int32_t k = 0; k < nc; ++k)
+        v_ptr[k + 1] = v_ptr[k] + cnt[k + 1];
+    v_list.resize(v_ptr[nc]);
+    {
+        std::vector<int32_t> fill(v_ptr.begin(), v_ptr.end() - 1);
+        for (int32_t i = 0; i < n; ++i)
+            if (label[i] >= 0)
+                v_list[fill[ord[label[i]]]++] = i;
+    }
+    // clause entries: one per (clause, cluster among its variables)
+    const std::vector<uint8_t> &img = I->image;
+    const uint32_t *caddr = reinterpret_cast<const uint32_t *>(img.data() + I->off_clause_addr);
+    std::vector<std::pair<int32_t, uint32_t>> ent;  // (cluster, clause | mask << 28)
+    for (int32_t a = 0; a < m; ++a) {
+        int32_t ks[4];
+        int nk = 0;
+        uint32_t masks[4] = {0, 0, 0, 0};
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t ad = caddr[(size_t)a * 4 + j];
+            if (ad >= 2u * (uint32_t)n)
+                continue;
+            const int32_t v = (int32_t)(ad >= (uint32_t)n ? ad - n : ad);
+            if (label[v] < 0)
+                continue;
+            const int32_t k = ord[label[v]];
+            int q = 0;
+            while (q < nk && ks[q] != k)
+                ++q;
+            if (q == nk)
+                ks[nk++] = k;
+            masks[q] |= 1u << j;
+        }
+        for (int q = 0; q < nk; ++q)
+            ent.emplace_back(ks[q], (uint32_t)a | (masks[q] << 28));
+    }
+    std::stable_sort(ent.begin(), ent.end(),
+                     [](const std::pair<int32_t, uint32_t> &x, const std::pair<int32_t, uint32_t> &y) {
+                         return x.first < y.first;
+                     });
+    cl_ptr.assign(nc + 1, 0);
+    int32_t longest = 0;
+    for (const auto &e : ent)
+        cl_ptr[e.first + 1]++;
+    for (int32_t k = 0; k < nc; ++k) {
+        longest = std::max(longest, cl_ptr[k + 1]);
+        cl_ptr[k + 1] += cl_ptr[k];
+    }
+    // thresholds up to the largest possible rise (the longest clause list),
+    // cut at the first zero (every larger rise then has threshold zero)
+    std::vector<uint32_t> thr(1, 0xFFFFFFFFu);
+    for (int32_t d = 1; d <= longest; ++d) {
+        const uint32_t v = threshold(beta, d);
+        if (!v)
+            break;
+        thr.push_back(v);
+    }
+    const size_t b_clp = align_up((nc + 1) * 4, 256), b_cl = align_up(std::max<size_t>(ent.size(), 1) * 4, 256);
+    const size_t b_vp = align_up((nc + 1) * 4, 256), b_vl = align_up(std::max<size_t>(v_list.size(), 1) * 4, 256);
+    const size_t b_thr = align_up(thr.size() * 4, 256), b_acc = align_up((size_t)P->G * kGroup * 4, 256);
+    int rc = ensure_tab(P, b_clp + b_cl + b_vp + b_vl + b_thr + b_acc);
+    if (rc)
+        return rc;
+    hipStream_t s = as_stream(stream);
+    uint8_t *base = P->tab_dev;
+    std::vector<uint32_t> cl_list(ent.size());
+    for (size_t i = 0; i < ent.size(); ++i)
+        cl_list[i] = ent[i].second;
+    HIP_OR_FAIL(hipMemcpyAsync(base, cl_ptr.data(), (nc + 1) * 4, hipMemcpyHostToDevice, s));
+    if (!cl_list.empty())
+        HIP_OR_FAIL(hipMemcpyAsync(base + b_clp, cl_list.data(), cl_list.size() * 4, hipMemcpyHostToDevice, s));
+    HIP_OR_FAIL(hipMemcpyAsync(base + b_clp + b_cl, v_ptr.data(), (nc + 1) * 4, hipMemcpyHostToDevice, s));
+    if (!v_list.empty())
+        HIP_OR_FAIL(hipMemcpyAsync(base + b_clp + b_cl + b_vp, v_list.data(), v_list.size() * 4,
+                                   hipMemcpyHostToDevice, s));
+    HIP_OR_FAIL(hipMemcpyAsync(base + b_clp + b_cl + b_vp + b_vl, thr.data(), thr.size() * 4, hipMemcpyHostToDevice,
+                               s));
+    CflipCall C{};
+    C.cl_ptr = reinterpret_cast<const int32_t *>(base);
+    C.cl_list = reinterpret_cast<const uint32_t *>(base + b_clp);
+    C.v_ptr = reinterpret_cast<const int32_t *>(base + b_clp + b_cl);
+    C.v_list = reinterpret_cast<const int32_t *>(base + b_clp + b_cl + b_vp);
+    C.thr = reinterpret_cast<const uint32_t *>(base + b_clp + b_cl + b_vp + b_vl);
+    C.accepted = reinterpret_cast<int32_t *>(base + b_clp + b_cl + b_vp + b_vl + b_thr);
+    C.n_clusters = nc;
+    C.thr_len = (int32_t)thr.size() - 1;
+    C.t = P->sweeps_done;
+    C.target = (int32_t)std::max<int64_t>(std::min<int64_t>(target, INT32_MAX), INT32_MIN);
+    C.key0 = (uint32_t)P->seed;
+    C.key1 = (uint32_t)(P->seed >> 32);
+    const size_t lds = ksat_cflip_lds_bytes(n);
+    if (lds > kLdsBytes - 64)
+        return fail(NMC_ERR_CAPACITY, "cluster flips need %zu bytes of LDS", lds);
+    HIP_OR_FAIL(ksat_launch_cflip(I->ksat_dev(), P->k, C, s));
+    P->sweeps_done += 1;
+    if (accepted_out) {
+        HIP_OR_FAIL(hipMemcpyAsync(accepted_out, C.accepted, (size_t)P->R * 4, hipMemcpyDeviceToHost, s));
+        HIP_OR_FAIL(hipStreamSynchronize(s));
+    }
+    return ok();
+}
+
+int nmc_cluster_flip(nmc_replicas *P, const int32_t *label, double beta, int64_t target, int32_t *accepted_out,
+                     void *stream) {
+    try {
+        return cluster_flip_impl(P, label, beta, target, accepted_out, stream);
+    } catch (const std::bad_alloc &) {
+        return fail(NMC_ERR_CAPACITY, "host allocation failed");
+    }
+}
+
 int nmc_lbp_kernel_time(nmc_replicas *P, double *ms, int64_t *iterations, int32_t reset) {
     if (!P)
         return fail(NMC_ERR_INVALID, "NULL replicas");

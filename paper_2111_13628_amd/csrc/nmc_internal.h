@@ -14,6 +14,7 @@ constexpr uint32_t kStreamKsatInit = 1;
 constexpr uint32_t kStreamQapSweep = 2;
 constexpr uint32_t kStreamQapInit = 3;
 constexpr uint32_t kStreamPtSwap = 4;
+constexpr uint32_t kStreamCflip = 5;
 
 // k-SAT: replicas are handled in groups of 4; group g holds replicas
 // 4g..4g+3 as bits 0..3 of one byte per variable.
@@ -225,6 +226,22 @@ size_t ksat_whiten_lds_bytes(int n);
 // *passes_out (zero it first)
 hipError_t ksat_launch_whiten(const KsatDev &I, const uint8_t *xs, int n_groups, int n_rep, uint8_t *white_out,
                               int32_t *frozen_out, int32_t *passes_out, hipStream_t s);
+
+// ---- collective cluster flips (nmc_cflip.hip) ----
+struct CflipCall {
+    const int32_t *cl_ptr;    // [n_clusters + 1] clause-list range of each cluster
+    const uint32_t *cl_list;  // clause | (mask of its literal positions inside the cluster) << 28
+    const int32_t *v_ptr;     // [n_clusters + 1] variable-list range of each cluster
+    const int32_t *v_list;    // the cluster's variables
+    const uint32_t *thr;      // [thr_len + 1] thresholds T(beta, d); zero for d > thr_len
+    int32_t *accepted;        // [R] clusters flipped per replica
+    int32_t n_clusters, thr_len;
+    uint32_t t;               // sweep counter of the move
+    int32_t target;
+    uint32_t key0, key1;
+};
+size_t ksat_cflip_lds_bytes(int n);
+hipError_t ksat_launch_cflip(const KsatDev &I, const KsatRepDev &R, const CflipCall &C, hipStream_t s);
 
 // records msg as the calling thread's nmc_last_error text; returns code
 int set_last_error(int code, const char *msg);

@@ -131,6 +131,7 @@ _SIGS = {
     "nmc_set_profiling": ([_P, _I32], ctypes.c_int),
     "nmc_kernel_time": ([_P, _P, _P, _P, _I32], ctypes.c_int),
     "nmc_pt_run": ([_P, _P, _I32, _I32, _I32, _I32, _I64, _P, _P, _P], ctypes.c_int),
+    "nmc_cluster_flip": ([_P, _P, ctypes.c_double, _I64, _P, _P], ctypes.c_int),
     "nmc_whiten": ([_P, _I32, _P, _P, _P, _P], ctypes.c_int),
     "nmc_lbp_kernel_time": ([_P, _P, _P, _I32], ctypes.c_int),
     "nmc_lbp_backbone": ([_P, _I32, _I32, ctypes.POINTER(LbpConfig), ctypes.POINTER(LbpResult), _P, _P, _P, _P, _P],
@@ -423,6 +424,15 @@ class Replicas:
         _check(lib().nmc_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(launches), ctypes.byref(att),
                                      int(bool(reset))))
         return dict(ms=ms.value, launches=launches.value, attempts=att.value)
+
+    def cluster_flip(self, label, beta, target=-1, stream=None):
+        """One collective-move sweep over the clusters of `label` (e.g. the
+        label of lbp_backbone); returns the clusters flipped per replica."""
+        lab = np.ascontiguousarray(label, np.int32)
+        acc = np.zeros(self.R, np.int32)
+        _check(lib().nmc_cluster_flip(self._h, _ptr(lab), float(beta), ctypes.c_int64(int(target)), _ptr(acc),
+                                      _stream(stream)))
+        return acc
 
     def whiten(self, which="best", white=False, stream=None):
         """Frozen variables per replica after whitening; with white=True also
