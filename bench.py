@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import json
+from concurrent.futures import ThreadPoolExecutor
 import os
 import platform
 import re
@@ -316,6 +317,88 @@ def bench_lbp(nmc, torch, seed):
             "cluster_flip": cflip}
 
 
+ALG1_BETA_FIRST, ALG1_PT_ROUNDS, ALG1_SEED_REPLICAS = 2.5, 1000, 64
+ALG1_THRESHOLDS = ((0.9, 0.8), (0.95, 0.9))
+ALG1_RE, ALG1_UNLEARN = 1000, 500
+
+
+def bench_alg1(nmc, torch, seed):
+    """Algorithm 1 end to end on the N = 50,000 instance: adaptive replica
+    exchange over the whole problem (64 temperatures x 16 chains: the ladder
+    from beta 2.5, then 1000 one-sweep rounds), the coldest replica of every
+    chain as a seed, and for each of the 16 seeds a set of 64 replicas
+    started at it; per round every set estimates the LBP backbone around its
+    best replica, then all sets run one batched launch of inhomogeneous MC
+    (backbone hot 0.5 -> 4.0, rest at 4.0) and one of homogeneous unlearning
+    at 4.0.  Plain SA over the same sweeps per replica is timed beside it."""
+    cp, lits = instances.gen_ksat(N, ALPHA, K, seed)
+    inst = nmc.Instance.ksat(N, cp, lits, CLASS_CAP).bind()
+    Rp = APT_TEMPS * APT_CHAINS
+
+    streams = [torch.cuda.Stream() for _ in range(APT_CHAINS)]
+
+    def run():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        apt = nmc.Replicas(inst, Rp, seed)
+        betas, _ = apt.apt_ladder(ALG1_BETA_FIRST, APT_ALPHA, 0.0, APT_EQUIL, APT_MEAS, APT_TEMPS)
+        acc, att = apt.pt_run(betas, ALG1_PT_ROUNDS, 1)
+        x = apt.get_state("current")
+        cold = slice((APT_TEMPS - 1) * APT_CHAINS, APT_TEMPS * APT_CHAINS)
+        seeds_e = apt.best_energy()["energy"][cold]
+        seeds = x[cold]
+        t_apt = time.perf_counter() - t0
+        sets = []
+        for k in range(APT_CHAINS):
+            rs = nmc.Replicas(inst, ALG1_SEED_REPLICAS, seed + 100 + k)
+            rs.set_state(np.repeat(seeds[k][None, :], ALG1_SEED_REPLICAS, 0), apt.sweeps_done())
+            sets.append(rs)
+        del apt
+        batch = nmc.Batch(sets)
+        rounds, t_lbp = [], 0.0
+        for ts, tc in ALG1_THRESHOLDS:
+            t1 = time.perf_counter()
+            torch.cuda.synchronize()
+
+            # the seeds' LBP runs are independent: one host thread and one
+            # stream each, so their latency-bound iterations overlap on the GPU
+            def lbp(k):
+                rs = sets[k]
+                with torch.cuda.stream(streams[k]):
+                    r0 = int(np.argmin(rs.best_energy(stream=streams[k])["best_per_replica"]))
+                    return rs.lbp_backbone(r0, "best", **LBP_CFG, theta_seed=ts, theta_cut=tc,
+                                           stream=streams[k])["backbone_size"]
+
+            with ThreadPoolExecutor(max_workers=len(sets)) as pool:
+                sizes = list(pool.map(lbp, range(len(sets))))
+            torch.cuda.synchronize()
+            t_lbp += time.perf_counter() - t1
+            batch.anneal(reanneal_profile(ALG1_RE), "backbone")
+            batch.anneal(np.full((1, ALG1_UNLEARN), BETA1))
+            rounds.append({"thresholds": [ts, tc], "backbone_min": int(min(sizes)), "backbone_max": int(max(sizes)),
+                           "best": int(min(rs.best_energy()["best"] for rs in sets))})
+        best = min(rs.best_energy()["best"] for rs in sets)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return {"wall_s": wall, "apt_s": t_apt, "lbp_s": t_lbp, "seed_energies": seeds_e.tolist(),
+                "exchange_rate_mean": float((acc / np.maximum(att, 1)).mean()), "ladder_last_beta": float(betas[-1]),
+                "rounds": rounds, "best_energy": int(best)}
+
+    run()  # warm-up
+    res = run()
+    sweeps = APT_TEMPS * (APT_EQUIL + APT_MEAS) + ALG1_PT_ROUNDS + len(ALG1_THRESHOLDS) * (ALG1_RE + ALG1_UNLEARN)
+    att = float(Rp) * N * sweeps
+    sa = nmc.Replicas(inst, Rp, seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sa.anneal(instances.linear_schedule(BETA0, BETA1, sweeps)[None, :])
+    sa_best = sa.best_energy()["best"]
+    torch.cuda.synchronize()
+    res.update({"sweeps_per_replica": sweeps, "attempts": att, "attempts_per_s": att / res["wall_s"],
+                "plain_sa": {"best_energy": int(sa_best), "wall_s": time.perf_counter() - t0}})
+    return res
+
+
 APT_TEMPS, APT_CHAINS, APT_BETA_FIRST, APT_ALPHA = 64, 16, 1.5, 1.1
 APT_EQUIL, APT_MEAS, APT_ROUNDS = 20, 5, 2000
 
@@ -548,11 +631,12 @@ def main():
     ap.add_argument("--no-ttt", action="store_true")
     ap.add_argument("--block-threads", type=int, default=0)
     ap.add_argument("--class-cap", type=int, default=CLASS_CAP)
-    ap.add_argument("--workload", choices=["nmc", "batch", "qap", "serve", "apt", "lbp"], default="nmc",
+    ap.add_argument("--workload", choices=["nmc", "batch", "qap", "serve", "apt", "lbp", "alg1"], default="nmc",
                     help="nmc: the N=50000 NMC path (default); batch: 256 mixed instances, batched vs "
                          "per-instance; qap: the n=100 QAP path; serve: Poisson stream into the server; "
                          "apt: adaptive parallel tempering on the N=50000 instance; lbp: NMC with LBP "
-                         "surrogate backbones on the N=50000 instance")
+                         "surrogate backbones on the N=50000 instance; alg1: tempering -> seeds -> per-seed "
+                         "LBP backbones -> batched inhomogeneous MC and unlearning")
     ap.add_argument("--pt-rounds", type=int, default=APT_ROUNDS)
     ap.add_argument("--pt-sweeps-per-round", type=int, default=1)
     ap.add_argument("--serve-seconds", type=float, default=SERVE_SECONDS)
@@ -591,6 +675,15 @@ def main():
                           "data": "synthetic",
                           "config": {"workload": "QAP n=100, 4096 replicas, anneal 5000 + 2x(backbone + reanneal 1000)"},
                           "roofline": res["roofline"], "qap": res}), flush=True)
+        return
+    if args.workload == "alg1":
+        res = bench_alg1(nmc, torch, seed)
+        print(json.dumps({"metric": "spin-flip attempts/s (Algorithm 1: tempering, seeds, LBP backbones, "
+                                    "inhomogeneous MC)", "value": res["attempts_per_s"], "unit": "attempts/s",
+                          "n_gpus": 1, "higher_is_better": True, "dtype": "int32", "data": "synthetic",
+                          "config": {"workload": "Algorithm 1 on random 4-SAT N=50000 alpha=9.9, 1024 replicas: "
+                                                 "APT 64x16 + 16 seeds x 64 replicas x 2 rounds"},
+                          "alg1": res}), flush=True)
         return
     if args.workload == "lbp":
         res = bench_lbp(nmc, torch, seed)

@@ -638,6 +638,7 @@ struct nmc_replicas {
     unsigned long long *pt_acc = nullptr;
     // LBP workspace (library-owned, sized for the instance on first use)
     uint8_t *lbp_dev = nullptr;
+    int64_t *lbp_pin = nullptr;  // pinned host words for the per-batch readback
     // whitening workspace (library-owned): white bits, counts, passes
     uint8_t *wh_dev = nullptr;
     // LBP message-iteration kernel time (profiling)
@@ -838,6 +839,8 @@ void nmc_replicas_free(nmc_replicas *P) {
         (void)hipFree(P->pt_acc);
     if (P->lbp_dev)
         (void)hipFree(P->lbp_dev);
+    if (P->lbp_pin)
+        (void)hipHostFree(P->lbp_pin);
     nmc_instance *I = P->inst;
     delete P;
     if (I) {
@@ -1517,6 +1520,8 @@ static int lbp_impl(nmc_replicas *P, int32_t replica, int32_t which, const nmc_l
         HIP_OR_FAIL(hipMalloc(&P->lbp_dev, total));
         HIP_OR_FAIL(hipMemsetAsync(P->lbp_dev, 0, total, s));
     }
+    if (!P->lbp_pin)
+        HIP_OR_FAIL(hipHostMalloc(reinterpret_cast<void **>(&P->lbp_pin), 64, hipHostMallocDefault));
     uint8_t *b = P->lbp_dev;
     LbpWork W{};
     W.u = reinterpret_cast<double *>(b + o_u);
@@ -1547,22 +1552,29 @@ static int lbp_impl(nmc_replicas *P, int32_t replica, int32_t which, const nmc_l
     }
     // one step's iterations: queued in batches, convergence decided on the
     // device after each iteration, one host round trip per batch
-    constexpr int32_t kBatch = 8;
+    // batches of 8, then 16 iterations; the control words come back through
+    // pinned host memory, so concurrent calls on other streams do not queue
+    // behind a staged copy
     auto run_step = [&](double lambda, double *delta, int32_t *done_iters, bool *conv) -> int {
         HIP_OR_FAIL(hipMemsetAsync(W.scal, 0, 64 * 8, s));
         HIP_OR_FAIL(hipMemsetAsync(W.ctl, 0, 8, s));
         int32_t queued = 0, ctl[2] = {0, 0};
+        int32_t *pin_ctl = reinterpret_cast<int32_t *>(P->lbp_pin);
+        double *pin_delta = reinterpret_cast<double *>(P->lbp_pin + 1);
         while (queued < c.max_iter) {
-            const int32_t cnt = std::min(kBatch, c.max_iter - queued);
+            const int32_t cnt = std::min(queued ? 16 : 8, c.max_iter - queued);
             if (pe[0])
                 HIP_OR_FAIL(hipEventRecord(pe[0], s));
             HIP_OR_FAIL(lbp_launch_iterations(K, W, lambda, w, c.tol, c.max_iter, cnt, s));
             if (pe[1])
                 HIP_OR_FAIL(hipEventRecord(pe[1], s));
             queued += cnt;
-            HIP_OR_FAIL(hipMemcpyAsync(ctl, W.ctl, 8, hipMemcpyDeviceToHost, s));
-            HIP_OR_FAIL(hipMemcpyAsync(delta, W.res + 2, 8, hipMemcpyDeviceToHost, s));
+            HIP_OR_FAIL(hipMemcpyAsync(pin_ctl, W.ctl, 8, hipMemcpyDeviceToHost, s));
+            HIP_OR_FAIL(hipMemcpyAsync(pin_delta, W.res + 2, 8, hipMemcpyDeviceToHost, s));
             HIP_OR_FAIL(hipStreamSynchronize(s));
+            ctl[0] = pin_ctl[0];
+            ctl[1] = pin_ctl[1];
+            *delta = *pin_delta;
             if (pe[0]) {
                 float ms = 0;
                 HIP_OR_FAIL(hipEventElapsedTime(&ms, pe[0], pe[1]));
@@ -1588,8 +1600,9 @@ static int lbp_impl(nmc_replicas *P, int32_t replica, int32_t which, const nmc_l
     auto overlap = [&](double lambda, double out[2]) -> int {
         HIP_OR_FAIL(lbp_launch_var(K, W, lambda, 1, s));
         HIP_OR_FAIL(lbp_launch_overlap(K, W, s));
-        HIP_OR_FAIL(hipMemcpyAsync(out, W.res, 16, hipMemcpyDeviceToHost, s));
+        HIP_OR_FAIL(hipMemcpyAsync(P->lbp_pin + 2, W.res, 16, hipMemcpyDeviceToHost, s));
         HIP_OR_FAIL(hipStreamSynchronize(s));
+        std::memcpy(out, P->lbp_pin + 2, 16);
         return NMC_OK;
     };
 
