@@ -9,7 +9,12 @@
  * across replicas; turns them into a two-class temperature profile; and
  * re-anneals from the current states (Algorithm 1 "Nonequilibrium Monte
  * Carlo", section "Nonequilibrium inhomogeneous sampling over subgraphs",
- * appendix B "Sampling localized replicas by Monte Carlo").
+ * appendix B "Sampling localized replicas by Monte Carlo").  The other steps
+ * of Algorithm 1 are here as well: adaptive parallel tempering (appendix A),
+ * the backbone estimate by loopy belief propagation on the localized
+ * surrogate Hamiltonian with connected cluster growth (the sections on
+ * surrogate Hamiltonians, LBP and backbones; appendix C), collective flips of
+ * backbone clusters, and the whitening diagnostic of low-energy states.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -23,10 +28,13 @@
  *    nmc_footprint() gives the byte sizes, the caller allocates (e.g. torch
  *    tensors on cuda:0) and passes raw device pointers.  The library never
  *    frees caller memory.  The library owns only working buffers it sizes
- *    itself: a per-replica-set threshold table (released by
- *    nmc_replicas_free), a per-batch descriptor and table buffer (released by
- *    nmc_batch_free), and, for a server, the device memory of the requests it
- *    admits (released when a request retires or by nmc_server_free).
+ *    itself: per replica set, an upload buffer for threshold tables and
+ *    tempering / cluster-flip lists, and (on first use) the tempering moment
+ *    accumulators, the LBP workspace with a small pinned host buffer, and the
+ *    whitening workspace, all released by nmc_replicas_free; a per-batch
+ *    descriptor and table buffer (released by nmc_batch_free); and, for a
+ *    server, the device memory of the requests it admits (released when a
+ *    request retires or by nmc_server_free).
  *  - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on
  *    it in call order; calls on one replica set must not overlap in time.
  *  - Energies are exact integers: the k-SAT energy is the number of violated
@@ -35,7 +43,9 @@
  *    replica set's 64-bit seed (low word first) and counter = (item, sweep,
  *    replica / 4, stream); replica r uses output word r mod 4.  Streams:
  *    0 k-SAT sweep (item = variable), 1 k-SAT init (item = variable, sweep 0),
- *    2 QAP sweep (item = pair rank), 3 QAP init (item = Fisher-Yates step).
+ *    2 QAP sweep (item = pair rank), 3 QAP init (item = Fisher-Yates step),
+ *    4 tempering exchange (counter (chain, sweep, ladder position, 4), word 0),
+ *    5 cluster flip (item = cluster ordinal).
  *    Results are a deterministic function of (instance, seed, schedule,
  *    profile, call sequence): no result depends on tuning, launch shape or on
  *    other work sharing the GPU.
