@@ -18,7 +18,6 @@ from __future__ import annotations
 
 import argparse
 import json
-from concurrent.futures import ThreadPoolExecutor
 import os
 import platform
 import re
@@ -328,14 +327,13 @@ def bench_alg1(nmc, torch, seed):
     from beta 2.5, then 1000 one-sweep rounds), the coldest replica of every
     chain as a seed, and for each of the 16 seeds a set of 64 replicas
     started at it; per round every set estimates the LBP backbone around its
-    best replica, then all sets run one batched launch of inhomogeneous MC
+    best replica (one batched LBP call for all sets), then all sets run one
+    batched launch of inhomogeneous MC
     (backbone hot 0.5 -> 4.0, rest at 4.0) and one of homogeneous unlearning
     at 4.0.  Plain SA over the same sweeps per replica is timed beside it."""
     cp, lits = instances.gen_ksat(N, ALPHA, K, seed)
     inst = nmc.Instance.ksat(N, cp, lits, CLASS_CAP).bind()
     Rp = APT_TEMPS * APT_CHAINS
-
-    streams = [torch.cuda.Stream() for _ in range(APT_CHAINS)]
 
     def run():
         torch.cuda.synchronize()
@@ -358,20 +356,10 @@ def bench_alg1(nmc, torch, seed):
         rounds, t_lbp = [], 0.0
         for ts, tc in ALG1_THRESHOLDS:
             t1 = time.perf_counter()
-            torch.cuda.synchronize()
-
-            # the seeds' LBP runs are independent: one host thread and one
-            # stream each, so their latency-bound iterations overlap on the GPU
-            def lbp(k):
-                rs = sets[k]
-                with torch.cuda.stream(streams[k]):
-                    r0 = int(np.argmin(rs.best_energy(stream=streams[k])["best_per_replica"]))
-                    return rs.lbp_backbone(r0, "best", **LBP_CFG, theta_seed=ts, theta_cut=tc,
-                                           stream=streams[k])["backbone_size"]
-
-            with ThreadPoolExecutor(max_workers=len(sets)) as pool:
-                sizes = list(pool.map(lbp, range(len(sets))))
-            torch.cuda.synchronize()
+            # the seeds' LBP runs advance together: one grid per kernel for all sets
+            seeds_r = [int(np.argmin(rs.best_energy()["best_per_replica"])) for rs in sets]
+            sizes = [g["backbone_size"] for g in batch.lbp_backbone(seeds_r, "best", **LBP_CFG, theta_seed=ts,
+                                                                     theta_cut=tc)]
             t_lbp += time.perf_counter() - t1
             batch.anneal(reanneal_profile(ALG1_RE), "backbone")
             batch.anneal(np.full((1, ALG1_UNLEARN), BETA1))

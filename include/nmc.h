@@ -492,6 +492,17 @@ int nmc_batch_tune(nmc_batch *batch, int32_t probe_sweeps, int32_t *chosen, void
 int nmc_batch_anneal(nmc_batch *batch, const double *beta, int32_t n_classes, int32_t n_sweeps, int32_t profile,
                      const int64_t *targets, void *stream);
 
+/* nmc_lbp_backbone for every set at once (k-SAT sets only): one run per set
+ * around replica replicas[i] of set i (current or best state), all runs
+ * sharing cfg and advancing through the lambda steps together (a run that
+ * stops keeps its messages while the others go on), one grid per kernel for
+ * all runs.  Each run's result equals the single-set call's; results
+ * (optional) receives n_sets entries; each set's backbone becomes its device
+ * class array.  The job descriptors (device) and a small pinned readback
+ * buffer belong to the batch.  Errors: INVALID, STATE, UNSUPPORTED, DEVICE. */
+int nmc_batch_lbp_backbone(nmc_batch *batch, const int32_t *replicas, int32_t which, const nmc_lbp_config *cfg,
+                           nmc_lbp_result *results, void *stream);
+
 /* nmc_estimate_backbone for every set (classes stay on the device). */
 int nmc_batch_estimate_backbone(nmc_batch *batch, int32_t thr_num, int32_t thr_den, int32_t expand, void *stream);
 

@@ -1478,20 +1478,7 @@ int nmc_apt_ladder(nmc_replicas *P, double beta_first, double alpha, double sigm
 // surrogate-Hamiltonian LBP and connected backbone growth
 // ---------------------------------------------------------------------------
 
-static int lbp_impl(nmc_replicas *P, int32_t replica, int32_t which, const nmc_lbp_config *cfg, nmc_lbp_result *res,
-                    uint8_t *class_out, double *mag_out, double *corr_out, int32_t *label_out, void *stream) {
-    if (!P || !cfg)
-        return fail(NMC_ERR_INVALID, "NULL argument");
-    nmc_instance *I = P->inst;
-    if (!I->dev)
-        return fail(NMC_ERR_STATE, "instance is not bound");
-    if (I->kind != NMC_KIND_KSAT)
-        return fail(NMC_ERR_UNSUPPORTED, "LBP runs on k-SAT instances");
-    if (replica < 0 || replica >= P->R)
-        return fail(NMC_ERR_INVALID, "replica %d outside [0, %d)", replica, P->R);
-    if (which != NMC_STATE_CURRENT && which != NMC_STATE_BEST)
-        return fail(NMC_ERR_INVALID, "which must be NMC_STATE_CURRENT or NMC_STATE_BEST");
-    const nmc_lbp_config &c = *cfg;
+static int lbp_check_config(const nmc_lbp_config &c) {
     if (!std::isfinite(c.beta) || c.beta < 0)
         return fail(NMC_ERR_INVALID, "beta = %g must be finite and >= 0", c.beta);
     if (!std::isfinite(c.lambda0) || !(c.lambda0 > 0))
@@ -1502,12 +1489,29 @@ static int lbp_impl(nmc_replicas *P, int32_t replica, int32_t which, const nmc_l
         return fail(NMC_ERR_INVALID, "lambda_min = %g must be finite and >= 0", c.lambda_min);
     if (c.max_iter < 1 || !(c.tol > 0) || !std::isfinite(c.tol))
         return fail(NMC_ERR_INVALID, "need max_iter >= 1 and a finite tol > 0");
-    if (std::isnan(c.p_min) || !std::isfinite(c.theta_seed) || !std::isfinite(c.theta_cut) ||
-        c.theta_cut < 0 || c.theta_seed < c.theta_cut)
+    if (std::isnan(c.p_min) || !std::isfinite(c.theta_seed) || !std::isfinite(c.theta_cut) || c.theta_cut < 0 ||
+        c.theta_seed < c.theta_cut)
         return fail(NMC_ERR_INVALID, "need 0 <= theta_cut <= theta_seed (finite) and a p_min that is not NaN");
-    hipStream_t s = as_stream(stream);
+    return NMC_OK;
+}
+
+// One LBP run of a batch: its replica set, seed and progress.
+struct LbpRun {
+    nmc_replicas *P = nullptr;
+    int32_t replica = 0;
+    LbpWork W{};
+    double *keep = nullptr;
+    size_t ubytes = 0;
+    double kept_lambda = 0, kept_delta = 0, ov[2] = {0, 0};
+    int32_t steps = 0, iters = 0, cnt[5] = {0, 0, 0, 0, 0};
+    bool have = false, done = false;
+};
+
+// the replica set's workspace (allocated on first use) laid out for its instance
+static int lbp_workspace(LbpRun &r, hipStream_t s) {
+    nmc_replicas *P = r.P;
+    nmc_instance *I = P->inst;
     const int32_t n = I->n, m = I->m;
-    // workspace
     Arena ar;
     const size_t o_u = ar.take((size_t)m * 4 * 8), o_keep = ar.take((size_t)m * 4 * 8), o_T = ar.take((size_t)n * 8);
     const size_t o_mag = ar.take((size_t)n * 8), o_corr = ar.take((size_t)m * 8);
@@ -1515,6 +1519,7 @@ static int lbp_impl(nmc_replicas *P, int32_t replica, int32_t which, const nmc_l
     const size_t o_scal = ar.take(64 * 8), o_res = ar.take(24), o_ctl = ar.take(8);
     const size_t o_lab = ar.take((size_t)n * 4), o_olab = ar.take((size_t)n * 4), o_size = ar.take((size_t)n * 4);
     const size_t o_seed = ar.take((size_t)n), o_flag = ar.take(4), o_cnt = ar.take(5 * 4);
+    const size_t o_job = ar.take(sizeof(LbpJob));
     const size_t total = align_up(ar.size, 256);
     if (!P->lbp_dev) {
         HIP_OR_FAIL(hipMalloc(&P->lbp_dev, total));
@@ -1523,9 +1528,9 @@ static int lbp_impl(nmc_replicas *P, int32_t replica, int32_t which, const nmc_l
     if (!P->lbp_pin)
         HIP_OR_FAIL(hipHostMalloc(reinterpret_cast<void **>(&P->lbp_pin), 64, hipHostMallocDefault));
     uint8_t *b = P->lbp_dev;
-    LbpWork W{};
+    LbpWork &W = r.W;
     W.u = reinterpret_cast<double *>(b + o_u);
-    double *keep = reinterpret_cast<double *>(b + o_keep);
+    r.keep = reinterpret_cast<double *>(b + o_keep);
     W.T = reinterpret_cast<double *>(b + o_T);
     W.mag = reinterpret_cast<double *>(b + o_mag);
     W.corr = reinterpret_cast<double *>(b + o_corr);
@@ -1540,55 +1545,32 @@ static int lbp_impl(nmc_replicas *P, int32_t replica, int32_t which, const nmc_l
     W.seeded = b + o_seed;
     W.flag = reinterpret_cast<int32_t *>(b + o_flag);
     W.counts = reinterpret_cast<int32_t *>(b + o_cnt);
-    const KsatDev K = I->ksat_dev();
-    const uint8_t *row = (which == NMC_STATE_BEST ? P->k.best_xs : P->k.xs) + (size_t)(replica / kGroup) * n;
-    const double w = 1.0 - std::exp(-2.0 * c.beta);
-    const size_t ubytes = (size_t)m * 4 * 8;
+    r.ubytes = (size_t)m * 4 * 8;
+    (void)o_job;
+    return NMC_OK;
+}
 
+static size_t lbp_job_offset(const nmc_instance *I) {
+    // the last region of the workspace laid out by lbp_workspace
+    Arena ar;
+    const int32_t n = I->n, m = I->m;
+    ar.take((size_t)m * 4 * 8), ar.take((size_t)m * 4 * 8), ar.take((size_t)n * 8);
+    ar.take((size_t)n * 8), ar.take((size_t)m * 8);
+    ar.take((size_t)I->n_lits * 4), ar.take((size_t)n);
+    ar.take(64 * 8), ar.take(24), ar.take(8);
+    ar.take((size_t)n * 4), ar.take((size_t)n * 4), ar.take((size_t)n * 4);
+    ar.take((size_t)n), ar.take(4), ar.take(5 * 4);
+    return ar.take(sizeof(LbpJob));
+}
+
+// Adiabatic LBP and cluster growth for every run, in lockstep over the
+// lambda steps (all runs share the configuration, so the runs still going
+// share lambda); jobs_dev holds the runs' job descriptors on the device.
+static int lbp_run_all(std::vector<LbpRun> &runs, const LbpJob *jobs_dev, const LbpDims &D, const nmc_lbp_config &c,
+                       int64_t *pin, hipStream_t s, bool profiling, double *prof_ms, int64_t *prof_iters) {
+    const double w = 1.0 - std::exp(-2.0 * c.beta);
+    const size_t nr = runs.size();
     hipEvent_t pe[2] = {nullptr, nullptr};
-    if (P->profiling) {
-        HIP_OR_FAIL(hipEventCreate(&pe[0]));
-        HIP_OR_FAIL(hipEventCreate(&pe[1]));
-    }
-    // one step's iterations: queued in batches, convergence decided on the
-    // device after each iteration, one host round trip per batch
-    // batches of 8, then 16 iterations; the control words come back through
-    // pinned host memory, so concurrent calls on other streams do not queue
-    // behind a staged copy
-    auto run_step = [&](double lambda, double *delta, int32_t *done_iters, bool *conv) -> int {
-        HIP_OR_FAIL(hipMemsetAsync(W.scal, 0, 64 * 8, s));
-        HIP_OR_FAIL(hipMemsetAsync(W.ctl, 0, 8, s));
-        int32_t queued = 0, ctl[2] = {0, 0};
-        int32_t *pin_ctl = reinterpret_cast<int32_t *>(P->lbp_pin);
-        double *pin_delta = reinterpret_cast<double *>(P->lbp_pin + 1);
-        while (queued < c.max_iter) {
-            const int32_t cnt = std::min(queued ? 16 : 8, c.max_iter - queued);
-            if (pe[0])
-                HIP_OR_FAIL(hipEventRecord(pe[0], s));
-            HIP_OR_FAIL(lbp_launch_iterations(K, W, lambda, w, c.tol, c.max_iter, cnt, s));
-            if (pe[1])
-                HIP_OR_FAIL(hipEventRecord(pe[1], s));
-            queued += cnt;
-            HIP_OR_FAIL(hipMemcpyAsync(pin_ctl, W.ctl, 8, hipMemcpyDeviceToHost, s));
-            HIP_OR_FAIL(hipMemcpyAsync(pin_delta, W.res + 2, 8, hipMemcpyDeviceToHost, s));
-            HIP_OR_FAIL(hipStreamSynchronize(s));
-            ctl[0] = pin_ctl[0];
-            ctl[1] = pin_ctl[1];
-            *delta = *pin_delta;
-            if (pe[0]) {
-                float ms = 0;
-                HIP_OR_FAIL(hipEventElapsedTime(&ms, pe[0], pe[1]));
-                P->lbp_ms += ms;
-            }
-            if (ctl[0])
-                break;
-        }
-        if (pe[0])
-            P->lbp_iters += ctl[1];
-        *done_iters = ctl[1];
-        *conv = ctl[0] == 1;
-        return NMC_OK;
-    };
     struct EvGuard {
         hipEvent_t *e;
         ~EvGuard() {
@@ -1597,107 +1579,197 @@ static int lbp_impl(nmc_replicas *P, int32_t replica, int32_t which, const nmc_l
                     (void)hipEventDestroy(e[k]);
         }
     } ev_guard{pe};
-    auto overlap = [&](double lambda, double out[2]) -> int {
-        HIP_OR_FAIL(lbp_launch_var(K, W, lambda, 1, s));
-        HIP_OR_FAIL(lbp_launch_overlap(K, W, s));
-        HIP_OR_FAIL(hipMemcpyAsync(P->lbp_pin + 2, W.res, 16, hipMemcpyDeviceToHost, s));
-        HIP_OR_FAIL(hipStreamSynchronize(s));
-        std::memcpy(out, P->lbp_pin + 2, 16);
-        return NMC_OK;
-    };
-
+    if (profiling) {
+        HIP_OR_FAIL(hipEventCreate(&pe[0]));
+        HIP_OR_FAIL(hipEventCreate(&pe[1]));
+    }
     // initial messages at lambda0: u = 0 and T = H give h = sigma H, u from h
-    if (ubytes)
-        HIP_OR_FAIL(hipMemsetAsync(W.u, 0, ubytes, s));
-    HIP_OR_FAIL(lbp_launch_setup(K, row, replica % kGroup, W, c.lambda0, s));
-    HIP_OR_FAIL(lbp_launch_clause(K, W, w, 0, s));
-    double lambda = c.lambda0, kept_lambda = c.lambda0, kept_delta = 0.0;
-    int32_t steps = 0, iters = 0;
-    bool have = false;
+    for (auto &r : runs)
+        if (r.ubytes)
+            HIP_OR_FAIL(hipMemsetAsync(r.W.u, 0, r.ubytes, s));
+    HIP_OR_FAIL(lbp_launch_setup(jobs_dev, D, c.lambda0, s));
+    HIP_OR_FAIL(lbp_launch_clause(jobs_dev, D, w, 0, s));
+    double lambda = c.lambda0;
     for (;;) {
-        if (ubytes)
-            HIP_OR_FAIL(hipMemcpyAsync(keep, W.u, ubytes, hipMemcpyDeviceToDevice, s));
-        double delta = 0.0;
-        bool conv = false;
-        int32_t done_iters = 0;
-        {
-            int rc = run_step(lambda, &delta, &done_iters, &conv);
-            if (rc)
-                return rc;
-        }
-        iters += done_iters;
-        ++steps;
-        double ov[2] = {0, 0};
-        if (conv) {
-            int rc = overlap(lambda, ov);
-            if (rc)
-                return rc;
-        }
-        if (!conv || (have && ov[0] < c.p_min)) {
-            if (have) {
-                if (ubytes)
-                    HIP_OR_FAIL(hipMemcpyAsync(W.u, keep, ubytes, hipMemcpyDeviceToDevice, s));
-            } else {
-                kept_delta = delta;
+        // one step for the runs still going: queued in batches of 8, then
+        // 16 iterations; convergence is decided on the device after every
+        // iteration and read back (pinned memory) once per batch
+        for (auto &r : runs)
+            if (!r.done) {
+                if (r.ubytes)
+                    HIP_OR_FAIL(hipMemcpyAsync(r.keep, r.W.u, r.ubytes, hipMemcpyDeviceToDevice, s));
+                HIP_OR_FAIL(hipMemsetAsync(r.W.scal, 0, 64 * 8, s));
+                HIP_OR_FAIL(hipMemsetAsync(r.W.ctl, 0, 8, s));
             }
-            break;
+        int32_t queued = 0;
+        for (;;) {
+            const int32_t cnt = std::min(queued ? 16 : 8, c.max_iter - queued);
+            if (pe[0])
+                HIP_OR_FAIL(hipEventRecord(pe[0], s));
+            HIP_OR_FAIL(lbp_launch_iterations(jobs_dev, D, lambda, w, c.tol, c.max_iter, cnt, s));
+            if (pe[1])
+                HIP_OR_FAIL(hipEventRecord(pe[1], s));
+            queued += cnt;
+            for (size_t k = 0; k < nr; ++k)
+                if (!runs[k].done) {
+                    HIP_OR_FAIL(hipMemcpyAsync(pin + 2 * k, runs[k].W.ctl, 8, hipMemcpyDeviceToHost, s));
+                    HIP_OR_FAIL(hipMemcpyAsync(pin + 2 * k + 1, runs[k].W.res + 2, 8, hipMemcpyDeviceToHost, s));
+                }
+            HIP_OR_FAIL(hipStreamSynchronize(s));
+            if (pe[0]) {
+                float ms = 0;
+                HIP_OR_FAIL(hipEventElapsedTime(&ms, pe[0], pe[1]));
+                *prof_ms += ms;
+            }
+            bool all_stopped = true;
+            for (size_t k = 0; k < nr; ++k)
+                if (!runs[k].done && reinterpret_cast<const int32_t *>(pin + 2 * k)[0] == 0)
+                    all_stopped = false;
+            if (all_stopped || queued >= c.max_iter)
+                break;
         }
-        have = true;
-        kept_lambda = lambda;
-        kept_delta = delta;
-        const double next = lambda * c.lambda_ratio;
-        if (!(next >= c.lambda_min))
-            break;
-        lambda = next;
-    }
-    // marginals, clause moments, overlaps from the kept messages
-    double ov[2];
-    {
-        int rc = overlap(kept_lambda, ov);  // also recomputes T from the kept u
-        if (rc)
-            return rc;
-    }
-    HIP_OR_FAIL(lbp_launch_clause(K, W, w, 1, s));
-    // connected components of the rigid clauses
-    HIP_OR_FAIL(lbp_launch_label_init(K, W, s));
-    for (int32_t pass = 0;; ++pass) {
-        if (pass > 4 * n + 64)
-            return fail(NMC_ERR_DEVICE, "component labels did not settle");
-        HIP_OR_FAIL(hipMemsetAsync(W.flag, 0, 4, s));
-        HIP_OR_FAIL(lbp_launch_hook_jump(K, W, c.theta_cut, s));
-        int32_t changed = 0;
-        HIP_OR_FAIL(hipMemcpyAsync(&changed, W.flag, 4, hipMemcpyDeviceToHost, s));
+        // overlaps at this lambda (every run; the ones that stopped earlier
+        // only overwrite scratch that the final pass recomputes)
+        HIP_OR_FAIL(lbp_launch_var(jobs_dev, D, lambda, 1, s));
+        HIP_OR_FAIL(lbp_launch_overlap(jobs_dev, D, s));
+        std::vector<double> pov(nr, 0.0);
+        std::vector<int32_t> ctl0(nr, 0), ctl1(nr, 0);
+        std::vector<double> delta(nr, 0.0);
+        for (size_t k = 0; k < nr; ++k)
+            if (!runs[k].done) {
+                const int32_t *cw = reinterpret_cast<const int32_t *>(pin + 2 * k);
+                ctl0[k] = cw[0];
+                ctl1[k] = cw[1];
+                std::memcpy(&delta[k], pin + 2 * k + 1, 8);
+            }
+        for (size_t k = 0; k < nr; ++k)
+            if (!runs[k].done)
+                HIP_OR_FAIL(hipMemcpyAsync(pin + 2 * k, runs[k].W.res, 8, hipMemcpyDeviceToHost, s));
         HIP_OR_FAIL(hipStreamSynchronize(s));
-        if (!changed)
+        for (size_t k = 0; k < nr; ++k)
+            if (!runs[k].done)
+                std::memcpy(&pov[k], pin + 2 * k, 8);
+        bool any = false;
+        for (size_t k = 0; k < nr; ++k) {
+            LbpRun &r = runs[k];
+            if (r.done)
+                continue;
+            r.iters += ctl1[k];
+            *prof_iters += profiling ? ctl1[k] : 0;
+            ++r.steps;
+            const bool conv = ctl0[k] == 1;
+            if (!conv || (r.have && pov[k] < c.p_min)) {
+                if (r.have) {
+                    if (r.ubytes)
+                        HIP_OR_FAIL(hipMemcpyAsync(r.W.u, r.keep, r.ubytes, hipMemcpyDeviceToDevice, s));
+                } else {
+                    r.kept_delta = delta[k];
+                }
+                r.done = true;
+                continue;
+            }
+            r.have = true;
+            r.kept_lambda = lambda;
+            r.kept_delta = delta[k];
+            if (!(lambda * c.lambda_ratio >= c.lambda_min))
+                r.done = true;
+            else
+                any = true;
+        }
+        if (!any)
+            break;
+        lambda *= c.lambda_ratio;
+    }
+    // marginals, moments and overlaps from each run's kept messages
+    for (size_t k = 0; k < nr; ++k) {
+        LbpDims one{1, runs[k].P->inst->n, runs[k].P->inst->m};
+        HIP_OR_FAIL(lbp_launch_var(jobs_dev + k, one, runs[k].have ? runs[k].kept_lambda : c.lambda0, 1, s));
+    }
+    HIP_OR_FAIL(lbp_launch_overlap(jobs_dev, D, s));
+    HIP_OR_FAIL(lbp_launch_clause(jobs_dev, D, w, 1, s));
+    // connected components of the rigid clauses (one shared change flag)
+    HIP_OR_FAIL(lbp_launch_label_init(jobs_dev, D, s));
+    int32_t *flag = runs[0].W.flag;
+    for (int32_t pass = 0;; ++pass) {
+        if (pass > 4 * D.max_n + 64)
+            return fail(NMC_ERR_DEVICE, "component labels did not settle");
+        HIP_OR_FAIL(hipMemsetAsync(flag, 0, 4, s));
+        HIP_OR_FAIL(lbp_launch_hook_jump(jobs_dev, D, c.theta_cut, s));
+        HIP_OR_FAIL(hipMemcpyAsync(pin, flag, 4, hipMemcpyDeviceToHost, s));
+        HIP_OR_FAIL(hipStreamSynchronize(s));
+        if (!reinterpret_cast<const int32_t *>(pin)[0])
             break;
     }
-    HIP_OR_FAIL(lbp_launch_finish(K, W, c.theta_seed, c.theta_cut, P->k.cls, s));
-    int32_t cnt[5];
-    HIP_OR_FAIL(hipMemcpyAsync(cnt, W.counts, 20, hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(lbp_launch_finish(jobs_dev, D, c.theta_seed, c.theta_cut, s));
+    for (size_t k = 0; k < nr; ++k) {
+        HIP_OR_FAIL(hipMemcpyAsync(runs[k].cnt, runs[k].W.counts, 20, hipMemcpyDeviceToHost, s));
+        HIP_OR_FAIL(hipMemcpyAsync(runs[k].ov, runs[k].W.res, 16, hipMemcpyDeviceToHost, s));
+    }
+    HIP_OR_FAIL(hipStreamSynchronize(s));
+    for (auto &r : runs)
+        r.P->has_backbone = true;
+    return NMC_OK;
+}
+
+static void lbp_fill_result(const LbpRun &r, const nmc_lbp_config &c, nmc_lbp_result *res) {
+    res->lambda = r.have ? r.kept_lambda : c.lambda0;
+    res->steps = r.steps;
+    res->iterations = r.iters;
+    res->converged = r.have ? 1 : 0;
+    res->delta = r.kept_delta;
+    res->overlap = r.ov[0];
+    res->self_overlap = r.ov[1];
+    res->backbone_size = r.cnt[0];
+    res->n_clusters = r.cnt[1];
+    res->largest_cluster = r.cnt[2];
+    res->rigid_clauses = r.cnt[3];
+    res->seed_clauses = r.cnt[4];
+}
+
+static int lbp_impl(nmc_replicas *P, int32_t replica, int32_t which, const nmc_lbp_config *cfg, nmc_lbp_result *res,
+                    uint8_t *class_out, double *mag_out, double *corr_out, int32_t *label_out, void *stream) {
+    if (!P || !cfg)
+        return fail(NMC_ERR_INVALID, "NULL argument");
+    nmc_instance *I = P->inst;
+    if (!I->dev)
+        return fail(NMC_ERR_STATE, "instance is not bound");
+    if (I->kind != NMC_KIND_KSAT)
+        return fail(NMC_ERR_UNSUPPORTED, "LBP runs on k-SAT instances");
+    if (replica < 0 || replica >= P->R)
+        return fail(NMC_ERR_INVALID, "replica %d outside [0, %d)", replica, P->R);
+    if (which != NMC_STATE_CURRENT && which != NMC_STATE_BEST)
+        return fail(NMC_ERR_INVALID, "which must be NMC_STATE_CURRENT or NMC_STATE_BEST");
+    if (int rc = lbp_check_config(*cfg))
+        return rc;
+    hipStream_t s = as_stream(stream);
+    std::vector<LbpRun> runs(1);
+    runs[0].P = P;
+    runs[0].replica = replica;
+    if (int rc = lbp_workspace(runs[0], s))
+        return rc;
+    LbpJob J{};
+    J.I = I->ksat_dev();
+    J.W = runs[0].W;
+    J.xs_row = (which == NMC_STATE_BEST ? P->k.best_xs : P->k.xs) + (size_t)(replica / kGroup) * I->n;
+    J.bit = replica % kGroup;
+    J.cls = P->k.cls;
+    LbpJob *jd = reinterpret_cast<LbpJob *>(P->lbp_dev + lbp_job_offset(I));
+    HIP_OR_FAIL(hipMemcpyAsync(jd, &J, sizeof J, hipMemcpyHostToDevice, s));
+    const LbpDims D{1, I->n, I->m};
+    if (int rc = lbp_run_all(runs, jd, D, *cfg, P->lbp_pin, s, P->profiling, &P->lbp_ms, &P->lbp_iters))
+        return rc;
+    const int32_t n = I->n, m = I->m;
     if (class_out && n)
         HIP_OR_FAIL(hipMemcpyAsync(class_out, P->k.cls, n, hipMemcpyDeviceToHost, s));
     if (mag_out && n)
-        HIP_OR_FAIL(hipMemcpyAsync(mag_out, W.mag, (size_t)n * 8, hipMemcpyDeviceToHost, s));
+        HIP_OR_FAIL(hipMemcpyAsync(mag_out, runs[0].W.mag, (size_t)n * 8, hipMemcpyDeviceToHost, s));
     if (corr_out && m)
-        HIP_OR_FAIL(hipMemcpyAsync(corr_out, W.corr, (size_t)m * 8, hipMemcpyDeviceToHost, s));
+        HIP_OR_FAIL(hipMemcpyAsync(corr_out, runs[0].W.corr, (size_t)m * 8, hipMemcpyDeviceToHost, s));
     if (label_out && n)
-        HIP_OR_FAIL(hipMemcpyAsync(label_out, W.out_label, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+        HIP_OR_FAIL(hipMemcpyAsync(label_out, runs[0].W.out_label, (size_t)n * 4, hipMemcpyDeviceToHost, s));
     HIP_OR_FAIL(hipStreamSynchronize(s));
-    P->has_backbone = true;
-    if (res) {
-        res->lambda = kept_lambda;
-        res->steps = steps;
-        res->iterations = iters;
-        res->converged = have ? 1 : 0;
-        res->delta = kept_delta;
-        res->overlap = ov[0];
-        res->self_overlap = ov[1];
-        res->backbone_size = cnt[0];
-        res->n_clusters = cnt[1];
-        res->largest_cluster = cnt[2];
-        res->rigid_clauses = cnt[3];
-        res->seed_clauses = cnt[4];
-    }
+    if (res)
+        lbp_fill_result(runs[0], *cfg, res);
     return ok();
 }
 
@@ -1945,6 +2017,12 @@ struct nmc_batch {
     double prof_ms = 0;
     int64_t prof_launches = 0;
     double prof_attempts = 0;
+    // batched LBP: job descriptors (device) and control readback (pinned)
+    LbpJob *lbp_jobs = nullptr;
+    int64_t *lbp_pin = nullptr;
+    size_t lbp_cap = 0;
+    double lbp_ms = 0;
+    int64_t lbp_iters = 0;
 };
 
 namespace {
@@ -2417,7 +2495,82 @@ void nmc_batch_free(nmc_batch *B) {
     }
     if (B->cap_stream)
         (void)hipStreamDestroy(B->cap_stream);
+    if (B->lbp_jobs) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(B->lbp_jobs);
+    }
+    if (B->lbp_pin)
+        (void)hipHostFree(B->lbp_pin);
     delete B;
+}
+
+int nmc_batch_lbp_backbone(nmc_batch *B, const int32_t *replicas, int32_t which, const nmc_lbp_config *cfg,
+                           nmc_lbp_result *results, void *stream) {
+    if (!B || !replicas || !cfg)
+        return fail(NMC_ERR_INVALID, "NULL argument");
+    if (which != NMC_STATE_CURRENT && which != NMC_STATE_BEST)
+        return fail(NMC_ERR_INVALID, "which must be NMC_STATE_CURRENT or NMC_STATE_BEST");
+    if (int rc = lbp_check_config(*cfg))
+        return rc;
+    const size_t ns = B->sets.size();
+    if (ns == 0)
+        return ok();
+    try {
+        for (size_t k = 0; k < ns; ++k) {
+            nmc_replicas *P = B->sets[k];
+            if (!P->inst->dev)
+                return fail(NMC_ERR_STATE, "set %zu: instance is not bound", k);
+            if (P->inst->kind != NMC_KIND_KSAT)
+                return fail(NMC_ERR_UNSUPPORTED, "set %zu: LBP runs on k-SAT instances", k);
+            if (replicas[k] < 0 || replicas[k] >= P->R)
+                return fail(NMC_ERR_INVALID, "set %zu: replica %d outside [0, %d)", k, replicas[k], P->R);
+        }
+        hipStream_t s = as_stream(stream);
+        if (B->lbp_cap < ns) {
+            if (B->lbp_jobs) {
+                HIP_OR_FAIL(hipDeviceSynchronize());
+                HIP_OR_FAIL(hipFree(B->lbp_jobs));
+                B->lbp_jobs = nullptr;
+            }
+            if (B->lbp_pin) {
+                HIP_OR_FAIL(hipHostFree(B->lbp_pin));
+                B->lbp_pin = nullptr;
+            }
+            B->lbp_cap = 0;
+            HIP_OR_FAIL(hipMalloc(reinterpret_cast<void **>(&B->lbp_jobs), ns * sizeof(LbpJob)));
+            HIP_OR_FAIL(hipHostMalloc(reinterpret_cast<void **>(&B->lbp_pin), std::max<size_t>(2 * ns, 8) * 8,
+                                      hipHostMallocDefault));
+            B->lbp_cap = ns;
+        }
+        std::vector<LbpRun> runs(ns);
+        std::vector<LbpJob> jobs(ns);
+        LbpDims D{(int)ns, 0, 0};
+        for (size_t k = 0; k < ns; ++k) {
+            nmc_replicas *P = B->sets[k];
+            runs[k].P = P;
+            runs[k].replica = replicas[k];
+            if (int rc = lbp_workspace(runs[k], s))
+                return rc;
+            LbpJob &J = jobs[k];
+            J.I = P->inst->ksat_dev();
+            J.W = runs[k].W;
+            J.W.flag = runs[0].W.flag;  // one change flag for the whole batch
+            J.xs_row = (which == NMC_STATE_BEST ? P->k.best_xs : P->k.xs) + (size_t)(replicas[k] / kGroup) * P->inst->n;
+            J.bit = replicas[k] % kGroup;
+            J.cls = P->k.cls;
+            D.max_n = std::max(D.max_n, P->inst->n);
+            D.max_m = std::max(D.max_m, P->inst->m);
+        }
+        HIP_OR_FAIL(hipMemcpyAsync(B->lbp_jobs, jobs.data(), ns * sizeof(LbpJob), hipMemcpyHostToDevice, s));
+        if (int rc = lbp_run_all(runs, B->lbp_jobs, D, *cfg, B->lbp_pin, s, B->profiling, &B->lbp_ms, &B->lbp_iters))
+            return rc;
+        if (results)
+            for (size_t k = 0; k < ns; ++k)
+                lbp_fill_result(runs[k], *cfg, &results[k]);
+        return ok();
+    } catch (const std::bad_alloc &) {
+        return fail(NMC_ERR_CAPACITY, "host allocation failed");
+    }
 }
 
 int nmc_batch_set_tuning(nmc_batch *B, int32_t block_threads) {

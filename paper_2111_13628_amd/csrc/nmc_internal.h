@@ -206,18 +206,27 @@ struct LbpWork {
     int32_t *flag;               // [1] labels changed
     int32_t *counts;             // [5] backbone size, clusters, largest, rigid clauses, seed clauses
 };
-hipError_t lbp_launch_setup(const KsatDev &I, const uint8_t *xs_row, int bit, const LbpWork &W, double lambda0,
-                            hipStream_t s);
-hipError_t lbp_launch_var(const KsatDev &I, const LbpWork &W, double lambda, int final_pass, hipStream_t s);
-hipError_t lbp_launch_clause(const KsatDev &I, const LbpWork &W, double w, int final_pass, hipStream_t s);
+// one LBP run: its instance, workspace, seed row and class output
+struct LbpJob {
+    KsatDev I;
+    LbpWork W;
+    const uint8_t *xs_row;  // the seed replica's group row of spins
+    int32_t bit;            // the seed replica's bit in it
+    uint8_t *cls;           // [N] class output (1 = backbone)
+};
+struct LbpDims {
+    int n_jobs, max_n, max_m;
+};
+hipError_t lbp_launch_setup(const LbpJob *jobs, const LbpDims &D, double lambda0, hipStream_t s);
+hipError_t lbp_launch_var(const LbpJob *jobs, const LbpDims &D, double lambda, int final_pass, hipStream_t s);
+hipError_t lbp_launch_clause(const LbpJob *jobs, const LbpDims &D, double w, int final_pass, hipStream_t s);
 // `count` gated iterations (variable side, clause side, control) of one step
-hipError_t lbp_launch_iterations(const KsatDev &I, const LbpWork &W, double lambda, double w, double tol,
+hipError_t lbp_launch_iterations(const LbpJob *jobs, const LbpDims &D, double lambda, double w, double tol,
                                  int max_iter, int count, hipStream_t s);
-hipError_t lbp_launch_overlap(const KsatDev &I, const LbpWork &W, hipStream_t s);
-hipError_t lbp_launch_label_init(const KsatDev &I, const LbpWork &W, hipStream_t s);
-hipError_t lbp_launch_hook_jump(const KsatDev &I, const LbpWork &W, double cut, hipStream_t s);
-hipError_t lbp_launch_finish(const KsatDev &I, const LbpWork &W, double seed_thr, double cut, uint8_t *cls,
-                             hipStream_t s);
+hipError_t lbp_launch_overlap(const LbpJob *jobs, const LbpDims &D, hipStream_t s);
+hipError_t lbp_launch_label_init(const LbpJob *jobs, const LbpDims &D, hipStream_t s);
+hipError_t lbp_launch_hook_jump(const LbpJob *jobs, const LbpDims &D, double cut, hipStream_t s);
+hipError_t lbp_launch_finish(const LbpJob *jobs, const LbpDims &D, double seed_thr, double cut, hipStream_t s);
 
 // ---- whitening (nmc_whiten.hip) ----
 size_t ksat_whiten_lds_bytes(int n);

@@ -59,7 +59,12 @@ __device__ __forceinline__ void atomic_max_nonneg(unsigned long long *p, double 
 // reference spins of one replica, edge list of every variable (edge | sign
 // bit 31, in the order of the variable's clause list) and T = H at lambda0
 // (with u = 0 the first clause pass then sees h = sigma H)
-__global__ void lbp_setup_kernel(KsatDev I, const uint8_t *xs_row, int bit, LbpWork W, double lambda0) {
+__global__ void lbp_setup_kernel(const LbpJob *jobs, double lambda0) {
+    const LbpJob &J = jobs[blockIdx.y];
+    const KsatDev &I = J.I;
+    const LbpWork &W = J.W;
+    const uint8_t *xs_row = J.xs_row;
+    const int bit = J.bit;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= I.n)
         return;
@@ -87,7 +92,10 @@ __global__ void lbp_setup_kernel(KsatDev I, const uint8_t *xs_row, int bit, LbpW
 // nothing once the iteration control has stopped.
 constexpr int kVarLanes = 16;
 
-__global__ void lbp_var_kernel(KsatDev I, LbpWork W, double lambda, int final_pass, int gated) {
+__global__ void lbp_var_kernel(const LbpJob *jobs, double lambda, int final_pass, int gated) {
+    const LbpJob &J = jobs[blockIdx.y];
+    const KsatDev &I = J.I;
+    const LbpWork &W = J.W;
     if (gated && W.ctl[0])
         return;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -119,7 +127,8 @@ constexpr int kDeltaSlots = 64;
 // iteration control, one thread after each iteration: take the iteration's
 // largest |du| (the 64 slots), clear them for the next, count the
 // iteration, stop on convergence (ctl[0] = 1) or at max_iter (ctl[0] = 2)
-__global__ void lbp_judge_kernel(LbpWork W, double tol, int max_iter) {
+__global__ void lbp_judge_kernel(const LbpJob *jobs, double tol, int max_iter) {
+    const LbpWork &W = jobs[blockIdx.y].W;
     if (W.ctl[0])
         return;
     unsigned long long mx = 0;
@@ -139,7 +148,10 @@ __global__ void lbp_judge_kernel(LbpWork W, double tol, int max_iter) {
 // clause side: h_{j->a} = sigma_j T_{v_j} - u_{a->j}, then the new u for
 // every edge of a and the largest change; with final != 0 the clause moment
 // instead (u unchanged)
-__global__ void __launch_bounds__(256) lbp_clause_kernel(KsatDev I, LbpWork W, double w, int final_pass, int gated) {
+__global__ void __launch_bounds__(256) lbp_clause_kernel(const LbpJob *jobs, double w, int final_pass, int gated) {
+    const LbpJob &J = jobs[blockIdx.y];
+    const KsatDev &I = J.I;
+    const LbpWork &W = J.W;
     if (gated && W.ctl[0])
         return;
     __shared__ double wmax[256 / 64];
@@ -198,7 +210,9 @@ __global__ void __launch_bounds__(256) lbp_clause_kernel(KsatDev I, LbpWork W, d
 
 // p = (1/N) sum s*_i <r_i> and q1 = (1/N) sum <r_i>^2 in a fixed order
 // (one workgroup: strided partial sums, then a tree)
-__global__ void __launch_bounds__(1024) lbp_overlap_kernel(KsatDev I, LbpWork W) {
+__global__ void __launch_bounds__(1024) lbp_overlap_kernel(const LbpJob *jobs) {
+    const KsatDev &I = jobs[blockIdx.y].I;
+    const LbpWork &W = jobs[blockIdx.y].W;
     __shared__ double sp[1024], sq[1024];
     const int tid = threadIdx.x;
     double p = 0.0, q = 0.0;
@@ -223,7 +237,9 @@ __global__ void __launch_bounds__(1024) lbp_overlap_kernel(KsatDev I, LbpWork W)
     }
 }
 
-__global__ void lbp_label_init_kernel(int n, LbpWork W) {
+__global__ void lbp_label_init_kernel(const LbpJob *jobs) {
+    const LbpWork &W = jobs[blockIdx.y].W;
+    const int n = jobs[blockIdx.y].I.n;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
         W.label[i] = i;
@@ -233,7 +249,9 @@ __global__ void lbp_label_init_kernel(int n, LbpWork W) {
 }
 
 // every rigid clause lowers its variables' labels to their minimum
-__global__ void lbp_hook_kernel(KsatDev I, LbpWork W, double cut) {
+__global__ void lbp_hook_kernel(const LbpJob *jobs, double cut) {
+    const KsatDev &I = jobs[blockIdx.y].I;
+    const LbpWork &W = jobs[blockIdx.y].W;
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= I.m || !(fabs(W.corr[a]) >= cut))
         return;
@@ -253,7 +271,9 @@ __global__ void lbp_hook_kernel(KsatDev I, LbpWork W, double cut) {
         W.flag[0] = 1;
 }
 
-__global__ void lbp_jump_kernel(int n, LbpWork W) {
+__global__ void lbp_jump_kernel(const LbpJob *jobs) {
+    const LbpWork &W = jobs[blockIdx.y].W;
+    const int n = jobs[blockIdx.y].I.n;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
@@ -265,7 +285,9 @@ __global__ void lbp_jump_kernel(int n, LbpWork W) {
 }
 
 // seed clauses mark their component
-__global__ void lbp_seed_kernel(KsatDev I, LbpWork W, double seed_thr) {
+__global__ void lbp_seed_kernel(const LbpJob *jobs, double seed_thr) {
+    const KsatDev &I = jobs[blockIdx.y].I;
+    const LbpWork &W = jobs[blockIdx.y].W;
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= I.m || !(fabs(W.corr[a]) >= seed_thr))
         return;
@@ -276,7 +298,10 @@ __global__ void lbp_seed_kernel(KsatDev I, LbpWork W, double seed_thr) {
 }
 
 // classes, output labels (-1 outside the backbone) and cluster sizes
-__global__ void lbp_classify_kernel(int n, LbpWork W, uint8_t *cls) {
+__global__ void lbp_classify_kernel(const LbpJob *jobs) {
+    const LbpWork &W = jobs[blockIdx.y].W;
+    const int n = jobs[blockIdx.y].I.n;
+    uint8_t *cls = jobs[blockIdx.y].cls;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
@@ -289,7 +314,9 @@ __global__ void lbp_classify_kernel(int n, LbpWork W, uint8_t *cls) {
 }
 
 // backbone size, cluster count, largest cluster, rigid and seed clauses
-__global__ void __launch_bounds__(1024) lbp_count_kernel(KsatDev I, LbpWork W, double seed_thr, double cut) {
+__global__ void __launch_bounds__(1024) lbp_count_kernel(const LbpJob *jobs, double seed_thr, double cut) {
+    const KsatDev &I = jobs[blockIdx.y].I;
+    const LbpWork &W = jobs[blockIdx.y].W;
     __shared__ int s_bb[1024], s_nc[1024], s_mx[1024], s_rg[1024], s_sd[1024];
     const int tid = threadIdx.x;
     int bb = 0, nc = 0, mx = 0, rg = 0, sd = 0;
@@ -333,69 +360,67 @@ int blocks(int n) { return (n + kLbpThreads - 1) / kLbpThreads; }
 
 }  // namespace
 
-hipError_t lbp_launch_setup(const KsatDev &I, const uint8_t *xs_row, int bit, const LbpWork &W, double lambda0,
-                            hipStream_t s) {
-    if (I.n == 0)
-        return hipSuccess;
-    hipLaunchKernelGGL(lbp_setup_kernel, dim3(blocks(I.n)), dim3(kLbpThreads), 0, s, I, xs_row, bit, W, lambda0);
+// Every launcher covers a batch of jobs (grid y = job); blocks past a job's
+// own size return (the clause kernel only after its barriers).
+hipError_t lbp_launch_setup(const LbpJob *jobs, const LbpDims &D, double lambda0, hipStream_t s) {
+    if (D.max_n > 0)
+        hipLaunchKernelGGL(lbp_setup_kernel, dim3(blocks(D.max_n), D.n_jobs), dim3(kLbpThreads), 0, s, jobs, lambda0);
     return hipGetLastError();
 }
 
-hipError_t lbp_launch_var(const KsatDev &I, const LbpWork &W, double lambda, int final_pass, hipStream_t s) {
-    if (I.n == 0)
-        return hipSuccess;
-    hipLaunchKernelGGL(lbp_var_kernel, dim3(blocks(I.n * kVarLanes)), dim3(kLbpThreads), 0, s, I, W, lambda,
-                       final_pass, 0);
+hipError_t lbp_launch_var(const LbpJob *jobs, const LbpDims &D, double lambda, int final_pass, hipStream_t s) {
+    if (D.max_n > 0)
+        hipLaunchKernelGGL(lbp_var_kernel, dim3(blocks(D.max_n * kVarLanes), D.n_jobs), dim3(kLbpThreads), 0, s, jobs,
+                           lambda, final_pass, 0);
     return hipGetLastError();
 }
 
-hipError_t lbp_launch_clause(const KsatDev &I, const LbpWork &W, double w, int final_pass, hipStream_t s) {
-    if (I.m == 0)
-        return hipSuccess;
-    hipLaunchKernelGGL(lbp_clause_kernel, dim3(blocks(I.m)), dim3(kLbpThreads), 0, s, I, W, w, final_pass, 0);
+hipError_t lbp_launch_clause(const LbpJob *jobs, const LbpDims &D, double w, int final_pass, hipStream_t s) {
+    if (D.max_m > 0)
+        hipLaunchKernelGGL(lbp_clause_kernel, dim3(blocks(D.max_m), D.n_jobs), dim3(kLbpThreads), 0, s, jobs, w,
+                           final_pass, 0);
     return hipGetLastError();
 }
 
-hipError_t lbp_launch_iterations(const KsatDev &I, const LbpWork &W, double lambda, double w, double tol,
+hipError_t lbp_launch_iterations(const LbpJob *jobs, const LbpDims &D, double lambda, double w, double tol,
                                  int max_iter, int count, hipStream_t s) {
     for (int k = 0; k < count; ++k) {
-        if (I.n > 0)
-            hipLaunchKernelGGL(lbp_var_kernel, dim3(blocks(I.n * kVarLanes)), dim3(kLbpThreads), 0, s, I, W, lambda,
-                               0, 1);
-        if (I.m > 0)
-            hipLaunchKernelGGL(lbp_clause_kernel, dim3(blocks(I.m)), dim3(kLbpThreads), 0, s, I, W, w, 0, 1);
-        hipLaunchKernelGGL(lbp_judge_kernel, dim3(1), dim3(1), 0, s, W, tol, max_iter);
+        if (D.max_n > 0)
+            hipLaunchKernelGGL(lbp_var_kernel, dim3(blocks(D.max_n * kVarLanes), D.n_jobs), dim3(kLbpThreads), 0, s,
+                               jobs, lambda, 0, 1);
+        if (D.max_m > 0)
+            hipLaunchKernelGGL(lbp_clause_kernel, dim3(blocks(D.max_m), D.n_jobs), dim3(kLbpThreads), 0, s, jobs, w, 0,
+                               1);
+        hipLaunchKernelGGL(lbp_judge_kernel, dim3(1, D.n_jobs), dim3(1), 0, s, jobs, tol, max_iter);
     }
     return hipGetLastError();
 }
 
-hipError_t lbp_launch_overlap(const KsatDev &I, const LbpWork &W, hipStream_t s) {
-    hipLaunchKernelGGL(lbp_overlap_kernel, dim3(1), dim3(1024), 0, s, I, W);
+hipError_t lbp_launch_overlap(const LbpJob *jobs, const LbpDims &D, hipStream_t s) {
+    hipLaunchKernelGGL(lbp_overlap_kernel, dim3(1, D.n_jobs), dim3(1024), 0, s, jobs);
     return hipGetLastError();
 }
 
-hipError_t lbp_launch_label_init(const KsatDev &I, const LbpWork &W, hipStream_t s) {
-    if (I.n == 0)
-        return hipSuccess;
-    hipLaunchKernelGGL(lbp_label_init_kernel, dim3(blocks(I.n)), dim3(kLbpThreads), 0, s, I.n, W);
+hipError_t lbp_launch_label_init(const LbpJob *jobs, const LbpDims &D, hipStream_t s) {
+    if (D.max_n > 0)
+        hipLaunchKernelGGL(lbp_label_init_kernel, dim3(blocks(D.max_n), D.n_jobs), dim3(kLbpThreads), 0, s, jobs);
     return hipGetLastError();
 }
 
-hipError_t lbp_launch_hook_jump(const KsatDev &I, const LbpWork &W, double cut, hipStream_t s) {
-    if (I.m > 0)
-        hipLaunchKernelGGL(lbp_hook_kernel, dim3(blocks(I.m)), dim3(kLbpThreads), 0, s, I, W, cut);
-    if (I.n > 0)
-        hipLaunchKernelGGL(lbp_jump_kernel, dim3(blocks(I.n)), dim3(kLbpThreads), 0, s, I.n, W);
+hipError_t lbp_launch_hook_jump(const LbpJob *jobs, const LbpDims &D, double cut, hipStream_t s) {
+    if (D.max_m > 0)
+        hipLaunchKernelGGL(lbp_hook_kernel, dim3(blocks(D.max_m), D.n_jobs), dim3(kLbpThreads), 0, s, jobs, cut);
+    if (D.max_n > 0)
+        hipLaunchKernelGGL(lbp_jump_kernel, dim3(blocks(D.max_n), D.n_jobs), dim3(kLbpThreads), 0, s, jobs);
     return hipGetLastError();
 }
 
-hipError_t lbp_launch_finish(const KsatDev &I, const LbpWork &W, double seed_thr, double cut, uint8_t *cls,
-                             hipStream_t s) {
-    if (I.m > 0)
-        hipLaunchKernelGGL(lbp_seed_kernel, dim3(blocks(I.m)), dim3(kLbpThreads), 0, s, I, W, seed_thr);
-    if (I.n > 0)
-        hipLaunchKernelGGL(lbp_classify_kernel, dim3(blocks(I.n)), dim3(kLbpThreads), 0, s, I.n, W, cls);
-    hipLaunchKernelGGL(lbp_count_kernel, dim3(1), dim3(1024), 0, s, I, W, seed_thr, cut);
+hipError_t lbp_launch_finish(const LbpJob *jobs, const LbpDims &D, double seed_thr, double cut, hipStream_t s) {
+    if (D.max_m > 0)
+        hipLaunchKernelGGL(lbp_seed_kernel, dim3(blocks(D.max_m), D.n_jobs), dim3(kLbpThreads), 0, s, jobs, seed_thr);
+    if (D.max_n > 0)
+        hipLaunchKernelGGL(lbp_classify_kernel, dim3(blocks(D.max_n), D.n_jobs), dim3(kLbpThreads), 0, s, jobs);
+    hipLaunchKernelGGL(lbp_count_kernel, dim3(1, D.n_jobs), dim3(1024), 0, s, jobs, seed_thr, cut);
     return hipGetLastError();
 }
 

@@ -143,6 +143,7 @@ _SIGS = {
     "nmc_batch_set_tuning": ([_P, _I32], ctypes.c_int),
     "nmc_batch_tune": ([_P, _I32, _P, _P], ctypes.c_int),
     "nmc_batch_anneal": ([_P, _P, _I32, _I32, _I32, _P, _P], ctypes.c_int),
+    "nmc_batch_lbp_backbone": ([_P, _P, _I32, ctypes.POINTER(LbpConfig), _P, _P], ctypes.c_int),
     "nmc_batch_estimate_backbone": ([_P, _I32, _I32, _I32, _P], ctypes.c_int),
     "nmc_batch_run_plan": ([_P, ctypes.POINTER(Plan), _P, _I32, _P], ctypes.c_int),
     "nmc_batch_set_members": ([_P, _P, _I32], ctypes.c_int),
@@ -493,6 +494,24 @@ class Batch:
         t = self._targets(targets)
         _check(lib().nmc_batch_anneal(self._h, _ptr(b), nc, S, PROFILE[profile] if isinstance(profile, str) else profile,
                                       _ptr(t), _stream(stream)))
+
+    def lbp_backbone(self, replicas, which="best", beta=1.0, lambda0=4.0, lambda_ratio=0.8, lambda_min=0.05,
+                     max_iter=200, tol=1e-10, p_min=-2.0, theta_seed=0.99, theta_cut=0.95, stream=None):
+        """LBP backbone of every set around replica replicas[i]; returns one
+        result dict per set (the fields of Replicas.lbp_backbone without the
+        arrays)."""
+        reps = np.ascontiguousarray(replicas, np.int32)
+        cfg = LbpConfig(float(beta), float(lambda0), float(lambda_ratio), float(lambda_min), int(max_iter),
+                        float(tol), float(p_min), float(theta_seed), float(theta_cut))
+        res = (LbpResult * max(len(reps), 1))()
+        _check(lib().nmc_batch_lbp_backbone(self._h, _ptr(reps), STATE[which], ctypes.byref(cfg),
+                                            ctypes.cast(res, ctypes.c_void_p), _stream(stream)))
+        out = []
+        for k in range(len(reps)):
+            d = {f: getattr(res[k], f) for f, _ in LbpResult._fields_}
+            d["lambda"] = d.pop("lambda_")
+            out.append(d)
+        return out
 
     def estimate_backbone(self, thr_num=9, thr_den=10, expand=True, stream=None):
         _check(lib().nmc_batch_estimate_backbone(self._h, int(thr_num), int(thr_den), int(bool(expand)),

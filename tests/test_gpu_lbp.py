@@ -182,3 +182,45 @@ def test_instance_released_before_its_replicas():
     for _ in range(5):
         assert cycle() == -1
         gc.collect()
+
+
+def test_batched_lbp_equals_single_runs_and_oracle():
+    """One batched call over three sets of different sizes gives every set
+    the result of its own single-set call (bit for bit) and of the oracle,
+    and leaves each set's own backbone on the device for its reanneal."""
+    say("case: batched LBP over 3 sets")
+    specs = [(300, "9.6", 4, 1, 5), (1000, "4.2", 3, 2, 0), (2000, "9.7", 4, 3, 14)]
+    pairs, singles, ocorr = [], [], []
+    sched = instances.linear_schedule(0.2, 3.0, 60)[None, :]
+    for n, alpha, k, seed, replica in specs:
+        cp, lits = instances.gen_ksat(n, alpha, k, seed)
+        pair = KsatPair(n, cp, lits, 16, 30 + seed)
+        pair.anneal(sched)
+        single = nmc.Replicas(nmc.Instance.ksat(n, cp, lits).bind(), 16, 30 + seed)
+        single.anneal(sched)
+        pairs.append(pair)
+        singles.append(single)
+        o = pair.oinst.lbp(pair.orep.best_x[replica], CFG["beta"], CFG["lambda0"], CFG["lambda_ratio"],
+                           CFG["lambda_min"], CFG["max_iter"], CFG["tol"], CFG["p_min"])
+        ocorr.append(o)
+    ts, tc = CFG["theta_seed"], CFG["theta_cut"]
+    for o in ocorr:
+        ts, tc = _safe_thresholds(o["corr"], ts, tc)
+    for o in ocorr:
+        assert _safe_thresholds(o["corr"], ts, tc) == (ts, tc)
+    cfg = dict(CFG, theta_seed=ts, theta_cut=tc)
+    batch = nmc.Batch([p.rep for p in pairs])
+    got = batch.lbp_backbone([sp[4] for sp in specs], "best", **cfg)
+    for (n, alpha, k, seed, replica), pair, single, o, g in zip(specs, pairs, singles, ocorr, got):
+        one = single.lbp_backbone(replica, "best", **cfg)
+        for key in ("lambda", "steps", "iterations", "converged", "delta", "overlap", "self_overlap",
+                    "backbone_size", "n_clusters", "largest_cluster", "rigid_clauses", "seed_clauses"):
+            assert g[key] == one[key], (n, key, g[key], one[key])
+        for key in ("steps", "iterations", "converged"):
+            assert g[key] == o[key], (n, key)
+        assert g["lambda"] == o["lambda"]
+        _, ocls, _ = pair.oinst.clusters(o["corr"], ts, tc)
+        assert g["backbone_size"] == int(ocls.sum())
+        beta = np.stack([np.full(20, 3.0), np.linspace(0.5, 3.0, 20)])
+        pair.anneal(beta, class_of=ocls, profile="backbone")
+        pair.compare()
