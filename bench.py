@@ -391,6 +391,37 @@ APT_TEMPS, APT_CHAINS, APT_BETA_FIRST, APT_ALPHA = 64, 16, 1.5, 1.1
 APT_EQUIL, APT_MEAS, APT_ROUNDS = 20, 5, 2000
 
 
+def bench_apt_qap(nmc, torch, seed, rounds=500):
+    """Tempering on the n = 100 QAP: 4096 replicas as 64 temperatures x 64
+    chains (a sweep workgroup's 16 replicas share a temperature), the
+    adaptive ladder from beta = 1.5 (in units of 1 / median |dC|), then
+    `rounds` rounds of one sweep and one exchange step."""
+    n = 100
+    F, D = instances.gen_qap(n, seed)
+    sc = qap_beta_scale(F, D, seed + 1)
+    inst = nmc.Instance.qap(F, D).bind()
+    chains = 4096 // APT_TEMPS
+    rep = nmc.Replicas(inst, APT_TEMPS * chains, seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    betas, sigmas = rep.apt_ladder(1.5 * sc, APT_ALPHA, 0.0, APT_EQUIL, APT_MEAS, APT_TEMPS)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    acc, att = rep.pt_run(betas, rounds, 1)
+    be = rep.best_energy()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    props = float(APT_TEMPS * chains) * n * (n - 1) / 2
+    rate = acc / np.maximum(att, 1)
+    return {"replicas": APT_TEMPS * chains, "chains": chains, "ladder_s": t1 - t0, "pt_s": t2 - t1,
+            "ladder_proposals_per_s": props * APT_TEMPS * (APT_EQUIL + APT_MEAS) / (t1 - t0),
+            "pt_proposals_per_s": props * rounds / (t2 - t1), "rounds": rounds,
+            "ladder": {"beta_first_units": 1.5, "beta_last_units": float(betas[-1] / sc),
+                       "sigma_first": float(sigmas[0]), "sigma_last": float(sigmas[-1])},
+            "exchange_rate": {"min": float(rate.min()), "mean": float(rate.mean()), "max": float(rate.max())},
+            "best_cost": int(be["best"])}
+
+
 def bench_apt(nmc, torch, seed, rounds, sweeps_per_round):
     """Adaptive parallel tempering on the N = 50,000 4-SAT instance: the
     adaptive ladder (64 positions from beta 1.5, alpha 1.1, 20 + 5 sweeps per
@@ -437,7 +468,8 @@ def bench_apt(nmc, torch, seed, rounds, sweeps_per_round):
                 "unit": "T lane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None,
                 "kernel": "ksat_sweep_kernel", "kernel_ms_per_launch": kern_ms,
                 "kernel_attempts_per_s": kt["attempts"] / (kt["ms"] / 1000.0), "launches": kt["launches"]}
-    return {"attempts": att_ladder + att_pt, "wall_s": t_ladder + t_pt,
+    qap = bench_apt_qap(nmc, torch, seed)
+    return {"attempts": att_ladder + att_pt, "wall_s": t_ladder + t_pt, "qap": qap,
             "attempts_per_s": (att_ladder + att_pt) / (t_ladder + t_pt),
             "ladder_s": t_ladder, "ladder_attempts_per_s": att_ladder / t_ladder,
             "pt_s": t_pt, "pt_attempts_per_s": att_pt / t_pt, "pt_rounds_per_s": rounds / t_pt,

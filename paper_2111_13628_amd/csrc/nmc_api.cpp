@@ -655,7 +655,7 @@ namespace {
 
 struct ReplicaLayout {
     size_t off_xs, off_best_xs, off_energy, off_best, off_first_hit, off_cls, off_counts, off_frozen, off_tally,
-        off_scratch, total;
+        off_scratch, off_hint, total;
 };
 
 ReplicaLayout replica_layout(const nmc_instance *I, int32_t R) {
@@ -685,6 +685,7 @@ ReplicaLayout replica_layout(const nmc_instance *I, int32_t R) {
         L.off_frozen = ar.take(16);
         L.off_tally = ar.take(64);
         L.off_scratch = ar.take((size_t)R * 8);
+        L.off_hint = ar.take((size_t)R);
     }
     L.total = align_up(ar.size, 256);
     return L;
@@ -809,8 +810,10 @@ int nmc_replicas_create(nmc_instance *I, int32_t n_replicas, uint64_t seed, void
             q.cls = b + L.off_cls;
             q.freq = reinterpret_cast<int32_t *>(b + L.off_counts);
             q.tally = reinterpret_cast<int32_t *>(b + L.off_tally);
+            q.rows_hint = b + L.off_hint;
             q.n_rep = n_replicas;
             P->scratch_energy = reinterpret_cast<int32_t *>(b + L.off_scratch);
+            HIP_OR_FAIL(hipMemsetAsync(q.rows_hint, 0, (size_t)n_replicas, s));
             HIP_OR_FAIL(qap_launch_init(I->qap_dev(), q, key0, key1, s));
         }
         int rc = reset_after_state(P.get(), s);
@@ -2732,6 +2735,7 @@ nmc_replicas rebased(const nmc_replicas *P, uint8_t *base) {
         C.q.cls = mv(P->q.cls);
         C.q.freq = mv(P->q.freq);
         C.q.tally = mv(P->q.tally);
+        C.q.rows_hint = mv(P->q.rows_hint);
     }
     C.scratch_energy = mv(P->scratch_energy);
     return C;

@@ -92,6 +92,7 @@ struct QapRepDev {
     uint8_t *cls;       // [n]
     int32_t *freq;      // [n][n]
     int32_t *tally;     // scratch
+    uint8_t *rows_hint; // [R] proposals per step the replica's last sweep chose (0: none yet)
     int32_t n_rep;
 };
 

@@ -8,7 +8,13 @@
 // assignment) are dropped and evaluated again in the next step.  A step thus
 // commits 1 to 4 proposals with exactly the sequential result.  Flow F and
 // distance D (bytes), the 16 permutations and the sweep's threshold tables sit
-// in LDS.  For symmetric, zero-diagonal F and D (subsection "Quadratic
+// in LDS.  Tempering launches (one table row per temperature) take the
+// replicas in quads: a workgroup holds the quads blk, blk + B, blk + 2B and
+// blk + 3B of its B-block grid, so under the temperature-major layout its four
+// quads sit at four temperatures spread along the ladder and one workgroup's
+// time no longer follows the hottest rows alone; every replica keeps its own
+// counter block, so the mapping changes the speed, never the result.  For
+// symmetric, zero-diagonal F and D (subsection "Quadratic
 // Assignment Problems"; cost sum_ij F_ij D_{p_i p_j}) exchanging the locations
 // of facilities a and b changes the cost by
 //   dC = 2 * sum_{k != a,b} (F_ak - F_bk) * (D_{p_b p_k} - D_{p_a p_k}).
@@ -438,13 +444,19 @@ __device__ __forceinline__ int qap_wave_sweep1(const QapDev &I, const QapCall &C
 
 // n_sweeps sweeps for the 16 replicas of block `blk`, by the whole
 // 1024-thread workgroup, with smem = the workgroup's dynamic LDS block.  Each
-// wave picks, per sweep, four proposals per step (16 lanes each) when few
-// proposals were accepted in its previous sweep, else one (64 lanes): with
-// many acceptances most of the four would be dropped.  The choice changes
-// only the speed, never the result.
+// wave picks, per sweep, eight proposals per step (8 lanes each) when very few
+// proposals were accepted in its previous sweep, four (16 lanes each) when
+// few, else one (64 lanes): with
+// many acceptances most of the four would be dropped.  The previous sweep may
+// be the replica's last one in an earlier launch (a per-replica hint byte), so
+// launches of one sweep each, as in tempering, still get the width that
+// suits the replica.  The choice changes only the speed, never the result.  With `mix` (tempering, n_rep a multiple
+// of 16) wave w runs replica 4 (blk + (w / 4) B) + w % 4 for B = n_rep / 16
+// and reads the table row of its quad; otherwise replica 16 blk + w and the
+// block's one row.
 template <int KPL4, int KPL1, int KPL8>
 __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev &R, const QapCall &C, const int blk,
-                                                uint8_t *smem) {
+                                                const bool mix, uint8_t *smem) {
     constexpr int KP = KPL4 <= 4 ? 4 : KPL4 <= 8 ? 8 : 16;  // flow bytes per lane of a 16-lane row
     constexpr int FS = 16 * KP;                            // flow row bytes
     static_assert(64 * KPL1 <= FS, "flow row too short for one proposal per step");
@@ -462,6 +474,10 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
     uint8_t *cls = P + kRepPerBlock * npad;
     uint32_t *tl = (uint32_t *)(cls + align_up(n, 16));
     const int tab_words = C.n_classes * C.stride;
+    const int nslots = mix ? kRepPerBlock / 4 : 1;  // table rows held in LDS
+    const int quad_stride = R.n_rep / 4 / 4;        // B quads between a block's slots (mix only)
+    // replica of wave (or P row) w
+    auto rep_of = [&](int w) { return mix ? 4 * (blk + (w >> 2) * quad_stride) + (w & 3) : blk * kRepPerBlock + w; };
 
     for (int i = tid; i < n * FS; i += blockDim.x) {
         const int r = i / FS, o = i % FS;
@@ -478,23 +494,27 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
         D[i] = I.D[i];
     for (int i = tid; i < n; i += blockDim.x)
         cls[i] = C.fac_cls ? C.fac_cls[i] : 0;
-    const int rbase = blk * kRepPerBlock;
-    // per-temperature tables (tempering): the block's replicas share one row
-    const uint32_t *tab = C.tab + (C.reps_per_row > 0 ? (size_t)(rbase / C.reps_per_row) * tab_words : 0);
+    // per-temperature tables (tempering): the replicas of a quad (mix) or of
+    // the block share one row
+    auto row_of = [&](int slot) {
+        return C.tab + (C.reps_per_row > 0 ? (size_t)(rep_of(4 * slot) / C.reps_per_row) * tab_words : 0);
+    };
     for (int i = tid; i < kRepPerBlock * n; i += blockDim.x) {
         const int rl = i / n, f = i % n;
-        const int rep = rbase + rl;
+        const int rep = rep_of(rl);
         P[rl * npad + f] = rep < R.n_rep ? R.perm[(size_t)rep * n + f] : (uint8_t)f;
     }
-    const int rep = rbase + wave;
+    const int rep = rep_of(wave);
     const bool active = rep < R.n_rep;  // wave-uniform
     uint8_t *pr = P + wave * npad;
+    const uint32_t *tw = tl + (mix ? (wave >> 2) * tab_words : 0);  // this wave's table
     const uint32_t group = (uint32_t)rep >> 2;
     const int word = rep & 3;
 
     long long cost = 0, best = 0;
-    int fh = -1;
+    int fh = -1, hint = 0;
     if (active) {
+        hint = R.rows_hint[rep];
         cost = R.cost[rep];
         best = R.best[rep];
         fh = R.first_hit[rep];
@@ -503,28 +523,31 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
     }
     __syncthreads();
 
-    // proposals per step: 8 (when the size allows), 4 or 1
-    int rows = C.rows != 0 ? C.rows : 4;
+    // proposals per step: 8 (when the size allows), 4 or 1; the first sweep
+    // of a launch takes what the replica's last sweep chose
+    int rows = C.rows != 0 ? C.rows : (hint == 1 || hint == 8) ? hint : 4;
     if (rows == 8 && KPL8 == 0)
         rows = 4;
     for (int s = 0; s < C.n_sweeps; ++s) {
         const uint32_t t = C.t0 + (uint32_t)s;
-        const uint32_t *tg = tab + (size_t)s * C.sweep_words;
-        for (int i = tid; i < tab_words; i += blockDim.x)
-            tl[i] = tg[i];
+        for (int q = 0; q < nslots; ++q) {
+            const uint32_t *tg = row_of(q) + (size_t)s * C.sweep_words;
+            for (int i = tid; i < tab_words; i += blockDim.x)
+                tl[q * tab_words + i] = tg[i];
+        }
         __syncthreads();
 
         if (active) {
             int n_acc;
             if constexpr (KPL8 > 0) {
                 if (rows == 8)
-                    n_acc = qap_wave_sweep<8, KPL8, KP>(I, C, F, F8, D, cls, tl, pr, t, group, word, cost);
+                    n_acc = qap_wave_sweep<8, KPL8, KP>(I, C, F, F8, D, cls, tw, pr, t, group, word, cost);
                 else
-                    n_acc = rows == 4 ? qap_wave_sweep<4, KPL4, KP>(I, C, F, F8, D, cls, tl, pr, t, group, word, cost)
-                                      : qap_wave_sweep1<KPL1, KP>(I, C, F, D, cls, tl, pr, t, group, word, cost);
+                    n_acc = rows == 4 ? qap_wave_sweep<4, KPL4, KP>(I, C, F, F8, D, cls, tw, pr, t, group, word, cost)
+                                      : qap_wave_sweep1<KPL1, KP>(I, C, F, D, cls, tw, pr, t, group, word, cost);
             } else {
-                n_acc = rows == 4 ? qap_wave_sweep<4, KPL4, KP>(I, C, F, F8, D, cls, tl, pr, t, group, word, cost)
-                                  : qap_wave_sweep1<KPL1, KP>(I, C, F, D, cls, tl, pr, t, group, word, cost);
+                n_acc = rows == 4 ? qap_wave_sweep<4, KPL4, KP>(I, C, F, F8, D, cls, tw, pr, t, group, word, cost)
+                                  : qap_wave_sweep1<KPL1, KP>(I, C, F, D, cls, tw, pr, t, group, word, cost);
             }
             if (C.rows == 0) {
                 // acceptance of this sweep: above 3/10 one proposal per step,
@@ -554,6 +577,8 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
             R.cost[rep] = cost;
             R.best[rep] = best;
             R.first_hit[rep] = fh;
+            if (C.rows == 0)
+                R.rows_hint[rep] = (uint8_t)rows;
         }
     }
 }
@@ -574,10 +599,11 @@ __device__ __forceinline__ void qap_dispatch_kpl(int n, Fn &&fn) {
         fn(integral_constant<int, 16>{}, integral_constant<int, 4>{}, integral_constant<int, 0>{});
 }
 
-__global__ void __launch_bounds__(1024) qap_sweep_kernel(QapDev I, QapRepDev R, QapCall C) {
+__global__ void __launch_bounds__(1024) qap_sweep_kernel(QapDev I, QapRepDev R, QapCall C, bool mix) {
     extern __shared__ __align__(16) uint8_t smem[];
     qap_dispatch_kpl(I.n, [&](auto k4, auto k1, auto k8) {
-        qap_sweep_block<decltype(k4)::value, decltype(k1)::value, decltype(k8)::value>(I, R, C, blockIdx.x, smem);
+        qap_sweep_block<decltype(k4)::value, decltype(k1)::value, decltype(k8)::value>(I, R, C, blockIdx.x, mix,
+                                                                                      smem);
     });
 }
 
@@ -589,7 +615,7 @@ __global__ void __launch_bounds__(1024) qap_sweep_batch_kernel(const QapJob *job
         const QapJob &J = jobs[w.x];
         qap_dispatch_kpl(J.I.n, [&](auto k4, auto k1, auto k8) {
             qap_sweep_block<decltype(k4)::value, decltype(k1)::value, decltype(k8)::value>(J.I, J.R, J.C, w.y,
-                                                                                          smem);
+                                                                                          false, smem);
         });
         __syncthreads();
     }
@@ -691,14 +717,18 @@ hipError_t qap_launch_reset_tallies(const QapRepDev &R, int n, hipStream_t s) {
 
 hipError_t qap_launch_sweep(const QapDev &I, const QapRepDev &R, const QapCall &C, int block_threads, hipStream_t s) {
     (void)block_threads;
-    const size_t lds = qap_sweep_lds_bytes(I.n, C.n_classes, C.stride);
+    // quads of four temperatures per workgroup when their four table rows fit
+    const size_t lds_mix = qap_sweep_lds_bytes(I.n, 4 * C.n_classes, C.stride);
+    const bool mix = C.reps_per_row > 0 && C.reps_per_row % 4 == 0 && R.n_rep % kRepPerBlock == 0 &&
+                     lds_mix <= kLdsBytes;
+    const size_t lds = mix ? lds_mix : qap_sweep_lds_bytes(I.n, C.n_classes, C.stride);
     // once per process (thread-safe initialization)
     static const hipError_t attr = hipFuncSetAttribute((const void *)qap_sweep_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                        (int)kLdsBytes);
     if (attr != hipSuccess)
         return attr;
     const int blocks = (R.n_rep + kRepPerBlock - 1) / kRepPerBlock;
-    hipLaunchKernelGGL(qap_sweep_kernel, dim3(blocks), dim3(kBlockThreads), lds, s, I, R, C);
+    hipLaunchKernelGGL(qap_sweep_kernel, dim3(blocks), dim3(kBlockThreads), lds, s, I, R, C, mix);
     return hipGetLastError();
 }
 

@@ -57,6 +57,23 @@ def test_qap_tempering_matches_oracle(n, M, C, seed, rows, monkeypatch):
     pair.compare()
 
 
+def test_qap_tempering_wide_tables_match_oracle():
+    """n = 160 with entries up to 255: one threshold row is 84 KB, so four
+    temperatures' rows do not fit one workgroup's LDS and the sweep keeps
+    the block-per-temperature mapping; the result is the same."""
+    say("case: QAP tempering n=160, entries to 255")
+    n = 160
+    rng = np.random.default_rng(21)
+    F = rng.integers(0, 256, (n, n), dtype=np.int32)
+    D = rng.integers(0, 256, (n, n), dtype=np.int32)
+    F = np.triu(F, 1) + np.triu(F, 1).T
+    D = np.triu(D, 1) + np.triu(D, 1).T
+    pair = QapPair(F, D, 32, 22)
+    beta = np.array([2e-6, 5e-6])
+    pair.pt_run(beta, 3, 1, 0)
+    pair.compare()
+
+
 def test_ksat_adaptive_ladder_matches_oracle():
     say("case: k-SAT adaptive ladder")
     cp, lits = instances.gen_ksat(600, "9.6", 4, 12)
