@@ -67,7 +67,7 @@ enum nmc_status {
     NMC_ERR_DEVICE = -3,      /* a HIP runtime call failed */
     NMC_ERR_STATE = -4,       /* call not valid in the object's current state */
     NMC_ERR_CAPACITY = -5,    /* does not fit (LDS or configured memory cap) */
-    NMC_ERR_UNSUPPORTED = -6  /* valid input outside what this build supports */
+    NMC_ERR_UNSUPPORTED = -6  /* valid input outside what the library supports */
 };
 
 enum nmc_kind { NMC_KIND_KSAT = 1, NMC_KIND_QAP = 2 };
