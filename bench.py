@@ -41,8 +41,30 @@ BLOCK_THREADS = 0
 # kernel's instruction stream.
 OPS_PER_SLOT = 9.0
 OPS_PER_VAR = 62.0
-PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock
+# VALU lane rate behind the published 157.3 TFLOP/s fp32 vector figure (two
+# flops per fused multiply-add): 256 CUs x 128 lane-operations x 2.4 GHz
+PEAK_LANE_OPS = 157.3e12 / 2
 LDS_LANE_READS = 256 * 32 * 2.4e9  # CUs x LDS banks x clock (one lane read per bank per clock)
+# LDS byte reads the sweep kernel does per (variable, clause slot) for its 4
+# replicas (the clause's three other literals) and per variable (its own spin)
+READS_PER_SLOT = 3.0
+READS_PER_VAR = 1.0
+
+
+def ksat_roofline(kt, traffic=None):
+    """Roofline of ksat_sweep_kernel from its HIP-event time `kt`: bound by
+    LDS byte gathers (algorithmic reads per attempt = (3 deg + 1) / 4 against
+    one lane read per bank per clock), with the VALU side beside it."""
+    deg_mean = K * M / N
+    att_s = kt["attempts"] / (kt["ms"] / 1000.0)
+    reads = att_s * (READS_PER_SLOT * deg_mean + READS_PER_VAR) / 4.0
+    ops = att_s * (OPS_PER_SLOT * deg_mean + OPS_PER_VAR) / 4.0
+    return {"bound": "lds", "achieved": reads / 1e12, "peak": LDS_LANE_READS / 1e12,
+            "unit": "T lane-reads/s", "frac": reads / LDS_LANE_READS, "traffic": traffic,
+            "kernel": "ksat_sweep_kernel", "kernel_ms_per_launch": kt["ms"] / max(1, kt["launches"]),
+            "kernel_attempts_per_s": att_s, "launches": kt["launches"],
+            "valu": {"achieved": ops / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "T lane-op/s",
+                     "frac": ops / PEAK_LANE_OPS}}
 
 
 def reanneal_profile(S):
@@ -299,13 +321,7 @@ def bench_lbp(nmc, torch, seed):
     bytes_it = LBP_BYTES_PER_EDGE * edges + LBP_BYTES_PER_VAR * nvar
     ms_it = lt["ms"] / max(1, lt["iterations"])
     att = float(R) * N * (S_ANNEAL + ROUNDS * S_RE)
-    deg_mean = K * M / N
-    ops_per_attempt = (OPS_PER_SLOT * deg_mean + OPS_PER_VAR) / 4.0
-    achieved = kt["attempts"] / (kt["ms"] / 1000.0) * ops_per_attempt
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                "unit": "T lane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None,
-                "kernel": "ksat_sweep_kernel", "kernel_ms_per_launch": kt["ms"] / max(1, kt["launches"]),
-                "kernel_attempts_per_s": kt["attempts"] / (kt["ms"] / 1000.0), "launches": kt["launches"]}
+    roofline = ksat_roofline(kt)
     lbp_roofline = {"bound": "hbm", "achieved": bytes_it / (ms_it / 1000.0) / 1e9, "peak": 8000.0, "unit": "GB/s",
                     "frac": bytes_it / (ms_it / 1000.0) / 8e12, "traffic": None,
                     "kernel": "lbp_var_kernel + lbp_clause_kernel (one message iteration)",
@@ -459,15 +475,8 @@ def bench_apt(nmc, torch, seed, rounds, sweeps_per_round):
     prep.set_profiling(True)
     prep.pt_run(betas, min(rounds, 500), sweeps_per_round)
     kt = prep.kernel_time()
-    kern_ms = kt["ms"] / max(1, kt["launches"])
-    deg_mean = K * M / N
-    ops_per_attempt = (OPS_PER_SLOT * deg_mean + OPS_PER_VAR) / 4.0
-    achieved = kt["attempts"] / (kt["ms"] / 1000.0) * ops_per_attempt
     rate = acc / np.maximum(att, 1)
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                "unit": "T lane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None,
-                "kernel": "ksat_sweep_kernel", "kernel_ms_per_launch": kern_ms,
-                "kernel_attempts_per_s": kt["attempts"] / (kt["ms"] / 1000.0), "launches": kt["launches"]}
+    roofline = ksat_roofline(kt)
     qap = bench_apt_qap(nmc, torch, seed)
     return {"attempts": att_ladder + att_pt, "wall_s": t_ladder + t_pt, "qap": qap,
             "attempts_per_s": (att_ladder + att_pt) / (t_ladder + t_pt),
@@ -616,6 +625,31 @@ def bench_serve(nmc, torch, seed, seconds):
     return out
 
 
+def measured_peaks(nmc, torch):
+    """Rates that simple, fully occupied kernels reach on this GPU, beside the
+    published peaks: LDS byte reads (lanes on distinct banks, and random
+    addresses in 100 KB), 32-bit integer adds, and a 1 GiB
+    device-to-device copy (bytes read + written)."""
+    out = {}
+    for which, iters, blocks in (("lds_distinct", 16384, 1024), ("lds_random", 4096, 1024),
+                                 ("valu_int", 16384, 2048)):
+        nmc.probe_peak(which, 64, blocks)  # warm-up
+        ms, ops = nmc.probe_peak(which, iters, blocks)
+        out[which + "_T_per_s"] = ops / (ms / 1e3) / 1e12
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    out["hbm_copy_TB_per_s"] = 5 * 2 * a.numel() * 4 / (e0.elapsed_time(e1) / 1e3) / 1e12
+    del a, b
+    return out
+
+
 def summarize(wall, attempts, ttt):
     hit = [t for t in ttt if t is not None]
     return {"wall_s": wall, "attempts_per_s": attempts / wall, "instances_hit": len(hit),
@@ -636,9 +670,25 @@ def cpu_baseline(cp, lits, seed):
     rep.anneal(instances.linear_schedule(BETA0, BETA1, S_ANNEAL)[None, :sweeps])
     dt = time.perf_counter() - t0
     att = Rs * N * sweeps
+    # the same oracle on one thread: 4 replicas (one group), 8 sweeps
+    one = oracle.KSatReplicas(ok, 4, seed, order, threads=1, snapshot=True)
+    t0 = time.perf_counter()
+    one.anneal(instances.linear_schedule(BETA0, BETA1, S_ANNEAL)[None, :8])
+    dt1 = time.perf_counter() - t0
+    model = platform.processor() or platform.machine()
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": att / dt, "unit": "attempts/s", "cores": threads, "kind": "oracle",
+            "single_thread_value": 4 * N * 8 / dt1, "nproc": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0)), "cpu_model": model,
             "sample": f"{Rs} replicas x {sweeps} anneal sweeps of the N=50000 instance ({att:.3g} attempts, "
-                      f"{dt:.1f} s wall on {threads} threads, {platform.processor() or platform.machine()})"}
+                      f"{dt:.1f} s wall on {threads} threads); single thread: 4 replicas x 8 sweeps "
+                      f"({dt1:.1f} s)"}
 
 
 def main():
@@ -775,21 +825,16 @@ def main():
     # sweep-kernel time from HIP events on the launch stream (separate pass)
     prep, _ = run_path(inst, seed, -1, nmc, profile=True)
     kt = prep.kernel_time()
-    kern_ms = kt["ms"] / max(1, kt["launches"])
-    att_per_launch = kt["attempts"] / max(1, kt["launches"])
-    deg_mean = K * M / N
-    ops_per_attempt = (OPS_PER_SLOT * deg_mean + OPS_PER_VAR) / 4.0
-    achieved = att_per_launch * ops_per_attempt / (kern_ms / 1000.0)
     bps = counter_bytes_per_sweep()
     sweeps_per_launch = (S_ANNEAL + ROUNDS * S_RE) / (1 + ROUNDS)
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                "unit": "T lane-op/s", "frac": achieved / PEAK_LANE_OPS,
-                "traffic": None if bps is None else bps * sweeps_per_launch,
-                "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "kernel": "ksat_sweep_kernel", "kernel_ms_per_launch": kern_ms,
-                "kernel_attempts_per_s": kt["attempts"] / (kt["ms"] / 1000.0),
-                "launches": kt["launches"]}
+    roofline = ksat_roofline(kt, None if bps is None else bps * sweeps_per_launch)
+    roofline["traffic_unit"] = "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     del prep
+    # the same rates against what the probe kernels reach on this GPU
+    peaks = measured_peaks(nmc, torch)
+    roofline["frac_of_measured_lds_random"] = roofline["achieved"] / peaks["lds_random_T_per_s"]
+    roofline["frac_of_measured_lds_distinct"] = roofline["achieved"] / peaks["lds_distinct_T_per_s"]
+    roofline["valu"]["frac_of_measured"] = roofline["valu"]["achieved"] / peaks["valu_int_T_per_s"]
 
     out = {
         "metric": "spin-flip attempts/s (whole NMC path) + time-to-target vs plain SA on 1 GPU",
@@ -805,6 +850,7 @@ def main():
                    "colors": inst.info.n_colors, "parallelism": "replicas"},
         "best_energy": last[1]["best"], "replicas_at_zero": last[1]["n_at_zero"],
         "roofline": roofline,
+        "measured_peaks": peaks,
     }
 
     if not args.no_ttt:

@@ -439,6 +439,29 @@ int nmc_lbp_kernel_time(nmc_replicas *rep, double *ms, int64_t *iterations, int3
 
 
 /* ---------------------------------------------------------------------------
+ * measurement helper (not part of the method)
+ * ------------------------------------------------------------------------- */
+
+enum {
+    NMC_PROBE_LDS_DISTINCT = 0, /* LDS byte reads, every lane of a wave on its own bank */
+    NMC_PROBE_LDS_RANDOM = 1,   /* LDS byte reads at uniformly random addresses in 100 KB */
+    NMC_PROBE_VALU_INT = 2      /* 32-bit integer adds, 8 chains per lane */
+};
+
+/* Times one launch of a peak-rate probe kernel on `stream` with HIP events:
+ * `blocks` workgroups of 1024 threads (one per CU at a time for the LDS
+ * probes, which take 100 KB of LDS each), every lane doing `iters`
+ * iterations of 16 reads (LDS probes) or 8 adds (VALU probe).  Writes the
+ * kernel time (ms) and the lane operations done (blocks x 1024 x iters x 16
+ * reads or x 8 adds), so the ratio is the measured rate to set
+ * beside a published peak.  The library allocates one 256-byte device word
+ * for the probes on first use (kept until the process ends).  Synchronizes
+ * the stream.  Errors: INVALID (unknown probe, iters not a multiple of 8 in
+ * [8, 2^24], blocks outside [1, 2^16]), DEVICE. */
+int nmc_probe_peak(int32_t which, int32_t iters, int32_t blocks, double *ms, double *lane_ops, void *stream);
+
+
+/* ---------------------------------------------------------------------------
  * batched launches (many replica sets of different instances at once)
  * ------------------------------------------------------------------------- */
 

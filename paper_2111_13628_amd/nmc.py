@@ -134,6 +134,7 @@ _SIGS = {
     "nmc_cluster_flip": ([_P, _P, ctypes.c_double, _I64, _P, _P], ctypes.c_int),
     "nmc_whiten": ([_P, _I32, _P, _P, _P, _P], ctypes.c_int),
     "nmc_lbp_kernel_time": ([_P, _P, _P, _I32], ctypes.c_int),
+    "nmc_probe_peak": ([_I32, _I32, _I32, _P, _P, _P], ctypes.c_int),
     "nmc_lbp_backbone": ([_P, _I32, _I32, ctypes.POINTER(LbpConfig), ctypes.POINTER(LbpResult), _P, _P, _P, _P, _P],
                          ctypes.c_int),
     "nmc_apt_ladder": ([_P, ctypes.c_double, ctypes.c_double, ctypes.c_double, _I32, _I32, _I32, _P, _P,
@@ -213,6 +214,19 @@ def _stream(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+PROBE = {"lds_distinct": 0, "lds_random": 1, "valu_int": 2}
+
+
+def probe_peak(which, iters, blocks, stream=None):
+    """One timed launch of a peak-rate probe kernel (measurement helper):
+    returns (kernel ms, lane operations done)."""
+    ms = ctypes.c_double()
+    ops = ctypes.c_double()
+    w = PROBE[which] if isinstance(which, str) else int(which)
+    _check(lib().nmc_probe_peak(w, int(iters), int(blocks), ctypes.byref(ms), ctypes.byref(ops), _stream(stream)))
+    return ms.value, ops.value
 
 
 def _device_buffer(nbytes: int):
