@@ -51,11 +51,12 @@ READS_PER_SLOT = 3.0
 READS_PER_VAR = 1.0
 
 
-def ksat_roofline(kt, traffic=None):
-    """Roofline of ksat_sweep_kernel from its HIP-event time `kt`: bound by
+def ksat_roofline(kt, n_clauses, traffic=None):
+    """Roofline of ksat_sweep_kernel from its HIP-event time `kt` on the
+    N-variable, n_clauses-clause k-SAT instance: bound by
     LDS byte gathers (algorithmic reads per attempt = (3 deg + 1) / 4 against
     one lane read per bank per clock), with the VALU side beside it."""
-    deg_mean = K * M / N
+    deg_mean = K * n_clauses / N
     att_s = kt["attempts"] / (kt["ms"] / 1000.0)
     reads = att_s * (READS_PER_SLOT * deg_mean + READS_PER_VAR) / 4.0
     ops = att_s * (OPS_PER_SLOT * deg_mean + OPS_PER_VAR) / 4.0
@@ -321,7 +322,7 @@ def bench_lbp(nmc, torch, seed):
     bytes_it = LBP_BYTES_PER_EDGE * edges + LBP_BYTES_PER_VAR * nvar
     ms_it = lt["ms"] / max(1, lt["iterations"])
     att = float(R) * N * (S_ANNEAL + ROUNDS * S_RE)
-    roofline = ksat_roofline(kt)
+    roofline = ksat_roofline(kt, M)
     lbp_roofline = {"bound": "hbm", "achieved": bytes_it / (ms_it / 1000.0) / 1e9, "peak": 8000.0, "unit": "GB/s",
                     "frac": bytes_it / (ms_it / 1000.0) / 8e12, "traffic": None,
                     "kernel": "lbp_var_kernel + lbp_clause_kernel (one message iteration)",
@@ -476,7 +477,7 @@ def bench_apt(nmc, torch, seed, rounds, sweeps_per_round):
     prep.pt_run(betas, min(rounds, 500), sweeps_per_round)
     kt = prep.kernel_time()
     rate = acc / np.maximum(att, 1)
-    roofline = ksat_roofline(kt)
+    roofline = ksat_roofline(kt, M)
     qap = bench_apt_qap(nmc, torch, seed)
     return {"attempts": att_ladder + att_pt, "wall_s": t_ladder + t_pt, "qap": qap,
             "attempts_per_s": (att_ladder + att_pt) / (t_ladder + t_pt),
@@ -827,7 +828,7 @@ def main():
     kt = prep.kernel_time()
     bps = counter_bytes_per_sweep()
     sweeps_per_launch = (S_ANNEAL + ROUNDS * S_RE) / (1 + ROUNDS)
-    roofline = ksat_roofline(kt, None if bps is None else bps * sweeps_per_launch)
+    roofline = ksat_roofline(kt, M, None if bps is None else bps * sweeps_per_launch)
     roofline["traffic_unit"] = "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     del prep
     # the same rates against what the probe kernels reach on this GPU
