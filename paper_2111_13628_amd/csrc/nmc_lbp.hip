@@ -158,40 +158,29 @@ __global__ void __launch_bounds__(256) lbp_clause_kernel(const LbpJob *jobs, dou
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     double dmax = 0.0;
     if (a < I.m) {
-        // the clause's 4 addresses and 4 messages in one 16-byte and two
-        // 16-byte loads (both arrays are 256-byte aligned, 16 and 32 bytes per
-        // clause)
-        const uint4 ad4 = reinterpret_cast<const uint4 *>(I.clause_addr)[a];
-        double2 *up = reinterpret_cast<double2 *>(W.u + 4 * (size_t)a);
-        const double2 u01 = up[0], u23 = up[1];
-        const uint32_t ad[4] = {ad4.x, ad4.y, ad4.z, ad4.w};
-        const double uo[4] = {u01.x, u01.y, u23.x, u23.y};
         double P[4], t[4], sg[4];
         int k = 0;
         for (int j = 0; j < 4; ++j) {
             int v;
             double sj;
-            if (!decode(ad[j], I.n, v, sj))
+            if (!decode(I.clause_addr[(size_t)a * 4 + j], I.n, v, sj))
                 break;
-            t[j] = tanh(sj * W.T[v] - uo[j]);
+            t[j] = tanh(sj * W.T[v] - W.u[4 * a + j]);
             P[j] = (1.0 - t[j]) / 2.0;
             sg[j] = sj;
             k = j + 1;
         }
         if (!final_pass) {
-            double un4[4] = {uo[0], uo[1], uo[2], uo[3]};  // padding slots keep theirs
             for (int j = 0; j < k; ++j) {
                 double prod = 1.0;
                 for (int l = 0; l < k; ++l)
                     if (l != j)
                         prod *= P[l];
                 const double un = -0.5 * log(1.0 - w * prod);
-                const double d = fabs(un - uo[j]);
+                const double d = fabs(un - W.u[4 * a + j]);
                 dmax = d > dmax ? d : dmax;
-                un4[j] = un;
+                W.u[4 * a + j] = un;
             }
-            up[0] = make_double2(un4[0], un4[1]);
-            up[1] = make_double2(un4[2], un4[3]);
         } else {
             double sat = 1.0, viol = 1.0, pv = 1.0;
             for (int j = 0; j < k; ++j) {
