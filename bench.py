@@ -238,6 +238,11 @@ def bench_qap(nmc, torch, seed, sweeps_only=0):
                 "unit": "T lane-reads/s", "frac": achieved / LDS_LANE_READS, "traffic": None,
                 "kernel": "qap_sweep_kernel", "kernel_ms_per_launch": kt["ms"] / max(1, kt["launches"]),
                 "launches": kt["launches"]}
+    if not sweeps_only:
+        peaks = measured_peaks(nmc, torch)
+        roofline["frac_of_measured_lds_distinct"] = roofline["achieved"] / peaks["lds_distinct_T_per_s"]
+        roofline["frac_of_measured_lds_random"] = roofline["achieved"] / peaks["lds_random_T_per_s"]
+        roofline["measured_peaks"] = peaks
     return {"proposals": props, "wall_s": wall, "proposals_per_s": props / wall,
             "kernel_ms": kt["ms"], "kernel_proposals_per_s": kps, "roofline": roofline,
             "beta_unit": sc, "best_cost": be["best"], "sweeps": S_tot}
