@@ -453,11 +453,11 @@ enum {
  * probes, which take 100 KB of LDS each), every lane doing `iters`
  * iterations of 16 reads (LDS probes) or 8 adds (VALU probe).  Writes the
  * kernel time (ms) and the lane operations done (blocks x 1024 x iters x 16
- * reads or x 8 adds), so the ratio is the measured rate to set
- * beside a published peak.  The library allocates one 256-byte device word
- * for the probes on first use (kept until the process ends).  Synchronizes
- * the stream.  Errors: INVALID (unknown probe, iters not a multiple of 8 in
- * [8, 2^24], blocks outside [1, 2^16]), DEVICE. */
+ * reads or x 8 adds), so the ratio is the measured rate to set beside a
+ * published peak.  The library allocates one 256-byte word on the current
+ * device at its first probe there (kept until the process ends).
+ * Synchronizes the stream.  Errors: INVALID (unknown probe, iters not a
+ * multiple of 8 in [8, 2^24], blocks outside [1, 2^16]), DEVICE. */
 int nmc_probe_peak(int32_t which, int32_t iters, int32_t blocks, double *ms, double *lane_ops, void *stream);
 
 

@@ -18,6 +18,7 @@
 // the host passes in (one no lane produces), so the compiler cannot drop the
 // work as dead.
 #include <cstdio>
+#include <mutex>
 
 #include "nmc.h"
 #include "nmc_internal.h"
@@ -97,10 +98,20 @@ __global__ void __launch_bounds__(kProbeThreads) probe_valu_kernel(int iters, ui
         sink[0] = r;
 }
 
+// one 256-byte word per device, allocated on the device's first probe and
+// kept until the process ends
+constexpr int kProbeMaxDevices = 64;
+
 uint32_t *probe_sink() {
-    static uint32_t *p = nullptr;
-    static const hipError_t e = hipMalloc((void **)&p, 256);
-    return e == hipSuccess ? p : nullptr;
+    static std::mutex mu;
+    static uint32_t *sinks[kProbeMaxDevices] = {};
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kProbeMaxDevices)
+        return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!sinks[dev] && hipMalloc((void **)&sinks[dev], 256) != hipSuccess)
+        sinks[dev] = nullptr;
+    return sinks[dev];
 }
 
 }  // namespace
