@@ -65,6 +65,32 @@ namespace {
             return fail(NMC_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));                  \
     } while (0)
 
+namespace {
+
+// HIP events owned by a scope: destroyed when it ends, early error returns
+// included
+struct ScopedEvents {
+    std::vector<hipEvent_t> ev;
+    ScopedEvents() = default;
+    ScopedEvents(const ScopedEvents &) = delete;
+    ScopedEvents &operator=(const ScopedEvents &) = delete;
+    ~ScopedEvents() {
+        for (hipEvent_t e : ev)
+            (void)hipEventDestroy(e);
+    }
+    hipError_t create(hipEvent_t *out) {
+        hipEvent_t e = nullptr;
+        const hipError_t r = hipEventCreate(&e);
+        if (r == hipSuccess) {
+            ev.push_back(e);
+            *out = e;
+        }
+        return r;
+    }
+};
+
+}  // namespace
+
 // Acceptance threshold for an energy rise d > 0 at inverse temperature beta:
 // min(2^32 - 1, floor(2^32 exp(-beta d))) evaluated in IEEE double.
 uint32_t threshold(double beta, int64_t d) {
@@ -930,10 +956,11 @@ static int anneal_impl(nmc_replicas *P, const double *beta, int32_t n_classes, i
         cls_dev = ksat ? P->k.cls : P->q.cls;
     }
 
+    ScopedEvents evs;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (P->profiling) {
-        HIP_OR_FAIL(hipEventCreate(&e0));
-        HIP_OR_FAIL(hipEventCreate(&e1));
+        HIP_OR_FAIL(evs.create(&e0));
+        HIP_OR_FAIL(evs.create(&e1));
         HIP_OR_FAIL(hipEventRecord(e0, s));
     }
     if (ksat) {
@@ -971,8 +998,6 @@ static int anneal_impl(nmc_replicas *P, const double *beta, int32_t n_classes, i
         HIP_OR_FAIL(hipEventSynchronize(e1));
         float ms = 0;
         HIP_OR_FAIL(hipEventElapsedTime(&ms, e0, e1));
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
         P->prof_ms += ms;
         P->prof_launches += 1;
         const double per_sweep = ksat ? (double)P->R * I->n : (double)P->R * I->n * (I->n - 1) / 2.0;
@@ -1319,13 +1344,14 @@ static int pt_run_impl(nmc_replicas *P, const double *beta, int32_t n_temps, int
     X.key0 = (uint32_t)P->seed;
     X.key1 = (uint32_t)(P->seed >> 32);
 
-    std::vector<hipEvent_t> ev;
+    ScopedEvents evs;  // (start, end) of every round's sweep launch when profiling
+    std::vector<hipEvent_t> &ev = evs.ev;
     for (int32_t k = 0; k < n_rounds; ++k) {
         if (P->profiling) {
-            ev.resize(ev.size() + 2);
-            HIP_OR_FAIL(hipEventCreate(&ev[ev.size() - 2]));
-            HIP_OR_FAIL(hipEventCreate(&ev[ev.size() - 1]));
-            HIP_OR_FAIL(hipEventRecord(ev[ev.size() - 2], s));
+            hipEvent_t a = nullptr, b = nullptr;
+            HIP_OR_FAIL(evs.create(&a));
+            HIP_OR_FAIL(evs.create(&b));
+            HIP_OR_FAIL(hipEventRecord(a, s));
         }
         if (ksat) {
             SweepCall C{};
@@ -1376,8 +1402,6 @@ static int pt_run_impl(nmc_replicas *P, const double *beta, int32_t n_temps, int
             HIP_OR_FAIL(hipEventElapsedTime(&ms, ev[e], ev[e + 1]));
             P->prof_ms += ms;
         }
-        for (hipEvent_t e : ev)
-            (void)hipEventDestroy(e);
         P->prof_launches += n_rounds;
         const double per_sweep = ksat ? (double)P->R * I->n : (double)P->R * I->n * (I->n - 1) / 2.0;
         P->prof_attempts += per_sweep * sweeps_per_round * n_rounds;
@@ -2356,6 +2380,12 @@ int run_batch(nmc_batch *B, const std::vector<PhaseSpec> &phases, const std::vec
     HIP_OR_FAIL(hipStreamSynchronize(s));
 
     if (use_graph) {
+        ScopedEvents evs;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (B->profiling) {
+            HIP_OR_FAIL(evs.create(&e0));
+            HIP_OR_FAIL(evs.create(&e1));
+        }
         if (!B->cap_stream)
             HIP_OR_FAIL(hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking));
         HIP_OR_FAIL(hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -2380,24 +2410,26 @@ int run_batch(nmc_batch *B, const std::vector<PhaseSpec> &phases, const std::vec
         (void)hipGraphDestroy(graph);
         if (ei != hipSuccess)
             return fail(NMC_ERR_DEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(ei));
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (B->profiling) {
-            HIP_OR_FAIL(hipEventCreate(&e0));
-            HIP_OR_FAIL(hipEventCreate(&e1));
-            HIP_OR_FAIL(hipEventRecord(e0, s));
-        }
-        const hipError_t el = hipGraphLaunch(exec, s);
+        // the executable graph goes on every exit, once the stream has drained
+        struct ExecGuard {
+            hipGraphExec_t x;
+            hipStream_t s;
+            ~ExecGuard() {
+                (void)hipStreamSynchronize(s);
+                (void)hipGraphExecDestroy(x);
+            }
+        } exec_guard{exec, s};
         if (B->profiling)
+            HIP_OR_FAIL(hipEventRecord(e0, s));
+        const hipError_t el = hipGraphLaunch(exec, s);
+        if (B->profiling && el == hipSuccess)
             HIP_OR_FAIL(hipEventRecord(e1, s));
         const hipError_t es = hipStreamSynchronize(s);
-        (void)hipGraphExecDestroy(exec);
         if (el != hipSuccess || es != hipSuccess)
             return fail(NMC_ERR_DEVICE, "graph launch failed: %s", hipGetErrorString(el != hipSuccess ? el : es));
         if (B->profiling) {
             float ms = 0;
             HIP_OR_FAIL(hipEventElapsedTime(&ms, e0, e1));
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
             B->prof_ms += ms;
             B->prof_launches += 1;
             for (const auto &bp : built)
@@ -2410,10 +2442,11 @@ int run_batch(nmc_batch *B, const std::vector<PhaseSpec> &phases, const std::vec
                 if (rc)
                     return rc;
             }
+            ScopedEvents evs;
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (B->profiling) {
-                HIP_OR_FAIL(hipEventCreate(&e0));
-                HIP_OR_FAIL(hipEventCreate(&e1));
+                HIP_OR_FAIL(evs.create(&e0));
+                HIP_OR_FAIL(evs.create(&e1));
                 HIP_OR_FAIL(hipEventRecord(e0, s));
             }
             rc = enqueue_phase(B, built[p], s);
@@ -2424,8 +2457,6 @@ int run_batch(nmc_batch *B, const std::vector<PhaseSpec> &phases, const std::vec
                 HIP_OR_FAIL(hipEventSynchronize(e1));
                 float ms = 0;
                 HIP_OR_FAIL(hipEventElapsedTime(&ms, e0, e1));
-                (void)hipEventDestroy(e0);
-                (void)hipEventDestroy(e1);
                 B->prof_ms += ms;
                 B->prof_launches += 1;
                 B->prof_attempts += built[p].attempts;
