@@ -66,6 +66,7 @@ struct nmc_server {
     uint64_t next_id = 1;
     int64_t rounds = 0, submitted = 0, completed = 0;
     size_t bytes_in_use = 0;
+    uint64_t release_gen = 0;  // bumped whenever device bytes or active slots are given back
     double busy_s = 0;
     int init_rc = NMC_OK;
     char init_msg[128] = {0};
@@ -236,14 +237,22 @@ void worker_main(nmc_server *S, int w) {
     std::vector<nmc_replicas *> sets;
     std::vector<nmc_segment> segs;
     std::vector<nmc_set_status> st;
+    // loaded requests left waiting by the last admission pass (for memory or
+    // a slot): with nothing active, wait for a release rather than retry
+    bool blocked = false;
+    uint64_t seen_gen = 0;
     for (;;) {
         // admission, in arrival order, while device bytes and slots allow
         std::vector<Req *> to_admit;
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            S->cv.wait(lk, [&] { return S->stop || has_loaded(S, kind) || !active.empty(); });
+            S->cv.wait(lk, [&] {
+                return S->stop || !active.empty() ||
+                       (has_loaded(S, kind) && (!blocked || S->release_gen != seen_gen));
+            });
             if (S->stop)
                 break;
+            seen_gen = S->release_gen;
             size_t bytes = S->bytes_in_use;
             size_t slots = n_active(S);
             for (auto it = S->loaded.begin(); it != S->loaded.end() && slots < (size_t)S->cfg.max_active;) {
@@ -263,6 +272,7 @@ void worker_main(nmc_server *S, int w) {
             // reserve the bytes now so that the other worker sees them
             for (Req *q : to_admit)
                 S->bytes_in_use += q->inst_bytes + q->rep_bytes;
+            blocked = has_loaded(S, kind);
         }
         for (Req *q : to_admit) {
             const bool okq = admit(q, mem);
@@ -274,6 +284,7 @@ void worker_main(nmc_server *S, int w) {
             } else {
                 release(q, mem);
                 S->bytes_in_use -= std::min(S->bytes_in_use, q->inst_bytes + q->rep_bytes);
+                S->release_gen++;
                 q->res.status = NMC_REQ_FAILED;
                 q->res.t_done = seconds_since(S->t0);
                 S->completed++;
@@ -344,6 +355,8 @@ void worker_main(nmc_server *S, int w) {
             S->completed++;
         }
         S->bytes_in_use -= std::min(S->bytes_in_use, freed);
+        if (!done.empty())
+            S->release_gen++;
         active.swap(keep);
         S->cv.notify_all();
     }
