@@ -392,7 +392,12 @@ __device__ __forceinline__ int qap_wave_sweep1(const QapDev &I, const QapCall &C
             const int cl = one_class ? 0 : max((int)cls[ar], (int)cls[br]);
             const uint32_t *T = tl + cl * C.stride;
             const int h = dc >> kQapLowBits, l = dc & ((1 << kQapLowBits) - 1);
-            const uint32_t thr = h < I.ha ? (uint32_t)(((uint64_t)T[h] * (uint64_t)T[I.ha + l]) >> 32) : 0u;
+            // the table words are the same for every lane: taking them as
+            // scalars keeps the accept branch a scalar branch
+            const uint32_t thr =
+                h < I.ha ? (uint32_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)T[h]) *
+                                       (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)T[I.ha + l])) >> 32)
+                         : 0u;
             acc = u < thr;
         }
         if (acc) {
@@ -425,7 +430,7 @@ __device__ __forceinline__ int qap_wave_sweep1(const QapDev &I, const QapCall &C
         }
         if (new_a) {
             ar = an;
-            pa = pan;
+            pa = __builtin_amdgcn_readfirstlane(pan);
 #pragma unroll
             for (int i = 0; i < KPL; ++i) {
                 fa[i] = fan[i];
@@ -433,7 +438,7 @@ __device__ __forceinline__ int qap_wave_sweep1(const QapDev &I, const QapCall &C
             }
         }
         br = bn;
-        pb = pbn;
+        pb = __builtin_amdgcn_readfirstlane(pbn);  // locations are wave-uniform
         if (p0 + 1 == (int)pbase + 64) {
             pbase += 64;
             uw = sweep_word(pbase + (uint32_t)lane, t, group, word, C.key0, C.key1);
