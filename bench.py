@@ -631,6 +631,37 @@ def bench_serve(nmc, torch, seed, seconds):
     return out
 
 
+def bench_c1(nmc, torch, seed):
+    """Plain SA on random 4-SAT N = 200, M = 1920, 64 replicas, 1000 sweeps
+    (beta 0.1 -> 4.0): the latency of the whole anneal, and the rate per
+    busy CU (16 workgroups of 4 replicas) against one CU's LDS read bound
+    ((3 deg + 1) / 4 byte reads per attempt, 32 lane reads per clock)."""
+    n, alpha, R, S = 200, "9.6", 64, 1000
+    cp, lits = instances.gen_ksat(n, alpha, K, seed)
+    inst = nmc.Instance.ksat(n, cp, lits).bind()
+    m = len(cp) - 1
+    sched = instances.linear_schedule(BETA0, BETA1, S)[None, :]
+    warm = nmc.Replicas(inst, R, seed + 1)
+    warm.anneal(sched[:, :20])
+    rep = nmc.Replicas(inst, R, seed)
+    rep.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rep.anneal(sched)
+    be = rep.best_energy()
+    wall = time.perf_counter() - t0
+    kt = rep.kernel_time()
+    att = float(R) * n * S
+    groups = (R + 3) // 4
+    deg = K * m / n
+    per_cu = att / (kt["ms"] / 1e3) / groups
+    cu_bound = 32 * 2.4e9 / ((3 * deg + 1) / 4)
+    return {"n_vars": n, "n_clauses": m, "replicas": R, "sweeps": S, "colors": inst.info.n_colors,
+            "latency_ms": kt["ms"], "wall_ms": wall * 1e3, "attempts_per_s": att / (kt["ms"] / 1e3),
+            "busy_cus": groups, "per_cu_attempts_per_s": per_cu, "cu_lds_bound_attempts_per_s": cu_bound,
+            "frac_of_one_cu": per_cu / cu_bound, "best_energy": int(be["best"])}
+
+
 def measured_peaks(nmc, torch):
     """Rates that simple, fully occupied kernels reach on this GPU, beside the
     published peaks: LDS byte reads (lanes on distinct banks, and random
@@ -707,7 +738,7 @@ def main():
     ap.add_argument("--no-ttt", action="store_true")
     ap.add_argument("--block-threads", type=int, default=0)
     ap.add_argument("--class-cap", type=int, default=CLASS_CAP)
-    ap.add_argument("--workload", choices=["nmc", "batch", "qap", "serve", "apt", "lbp", "alg1"], default="nmc",
+    ap.add_argument("--workload", choices=["nmc", "batch", "qap", "serve", "apt", "lbp", "alg1", "c1"], default="nmc",
                     help="nmc: the N=50000 NMC path (default); batch: 256 mixed instances, batched vs "
                          "per-instance; qap: the n=100 QAP path; serve: Poisson stream into the server; "
                          "apt: adaptive parallel tempering on the N=50000 instance; lbp: NMC with LBP "
@@ -751,6 +782,14 @@ def main():
                           "data": "synthetic",
                           "config": {"workload": "QAP n=100, 4096 replicas, anneal 5000 + 2x(backbone + reanneal 1000)"},
                           "roofline": res["roofline"], "qap": res}), flush=True)
+        return
+    if args.workload == "c1":
+        res = bench_c1(nmc, torch, seed)
+        print(json.dumps({"metric": "latency of plain SA, random 4-SAT N=200 M=1920, 64 replicas, 1000 sweeps",
+                          "value": res["latency_ms"], "unit": "ms", "n_gpus": 1, "higher_is_better": False,
+                          "dtype": "int32", "data": "synthetic",
+                          "config": {"workload": "plain SA, random 4-SAT N=200 alpha=9.6, 64 replicas, 1000 sweeps"},
+                          "c1": res}), flush=True)
         return
     if args.workload == "alg1":
         res = bench_alg1(nmc, torch, seed)
