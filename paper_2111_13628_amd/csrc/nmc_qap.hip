@@ -334,8 +334,12 @@ __device__ __forceinline__ int qap_wave_sweep(const QapDev &I, const QapCall &C,
 // while the current pair is evaluated, and an accepted swap (a, b) updates
 // D[p_a][p_k] from registers: with zero diagonal and symmetric D the new row
 // is D[p_b][p_k] (just gathered) except D[p_b][p_b] = 0 at k = a and
-// D[p_b][p_a] = D[p_a][p_b] (the old value) at k = b.  Same decisions, words
-// and counters as qap_wave_sweep.  Returns the number of accepted swaps.
+// D[p_b][p_a] = D[p_a][p_b] (the old value) at k = b.  The lanes holding
+// k = a and k = b add nothing to the sum, which is then the definition's sum
+// over the other k with no correction term (with two facilities per lane the
+// select is cheaper than the one-lane correction and its LDS round trip;
+// with the multi-proposal paths' 7 to 14 per lane it is not).  Same
+// decisions, words and counters as qap_wave_sweep.  Returns the number of accepted swaps.
 template <int KPL, int KP>
 __device__ __forceinline__ int qap_wave_sweep1(const QapDev &I, const QapCall &C, const uint8_t *F, const uint8_t *D,
                                                const uint8_t *cls, const uint32_t *tl, uint8_t *pr, uint32_t t,
@@ -379,10 +383,11 @@ __device__ __forceinline__ int qap_wave_sweep1(const QapDev &I, const QapCall &C
 #pragma unroll
         for (int i = 0; i < KPL; ++i) {
             db[i] = D[pb * n + pk[i]];
-            part += (fa[i] - fb[i]) * (db[i] - da[i]);
+            // the sum runs over k other than a and b
+            const int k = lane + 64 * i;
+            const int term = (fa[i] - fb[i]) * (db[i] - da[i]);
+            part += (k == ar || k == br) ? 0 : term;
         }
-        if (lane == 0)
-            part += 2 * (int)F[ar * RB + (br & 15) * KP + (br >> 4)] * (int)D[pa * n + pb];
         part = row_allreduce16(part);
         const int dc = 2 * (__builtin_amdgcn_readlane(part, 0) + __builtin_amdgcn_readlane(part, 16) +
                             __builtin_amdgcn_readlane(part, 32) + __builtin_amdgcn_readlane(part, 48));
