@@ -202,7 +202,7 @@ def qap_beta_scale(F, D, seed, samples=100000):
     return 1.0 / float(np.median(d))
 
 
-def bench_qap(nmc, torch, seed, sweeps_only=0):
+def bench_qap(nmc, torch, seed, sweeps_only=0, sweeps_offset=0):
     """QAP NMC: n = 100, 4096 replicas, anneal 5000 sweeps of 4950 proposed
     swaps, then 2 x (frequency backbone -> reanneal 1000)."""
     n, Rq, S_A, RND, S_R = 100, 4096, 5000, 2, 1000
@@ -217,8 +217,8 @@ def bench_qap(nmc, torch, seed, sweeps_only=0):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     if sweeps_only:
-        rep.anneal(a_beta[None, :sweeps_only])
-        S_tot = sweeps_only
+        rep.anneal(a_beta[None, sweeps_offset:sweeps_offset + sweeps_only])
+        S_tot = min(sweeps_only, max(0, S_A - sweeps_offset))
     else:
         rep.anneal(a_beta[None, :])
         for _ in range(RND):
@@ -749,6 +749,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=SERVE_SECONDS)
     ap.add_argument("--sweeps-only", type=int, default=0,
                     help="only time one homogeneous anneal of this many sweeps (for counter profiles) and exit")
+    ap.add_argument("--sweeps-offset", type=int, default=0,
+                    help="with --workload qap --sweeps-only: start that many sweeps into the anneal schedule")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain elementwise copy of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -776,7 +778,7 @@ def main():
     stream = torch.cuda.current_stream()
     seed = instances.DEFAULT_SEED
     if args.workload == "qap":
-        res = bench_qap(nmc, torch, seed, args.sweeps_only)
+        res = bench_qap(nmc, torch, seed, args.sweeps_only, args.sweeps_offset)
         print(json.dumps({"metric": "QAP swap proposals/s (whole NMC path)", "value": res["proposals_per_s"],
                           "unit": "proposals/s", "n_gpus": 1, "higher_is_better": True, "dtype": "int32",
                           "data": "synthetic",

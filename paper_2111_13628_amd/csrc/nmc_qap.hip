@@ -52,14 +52,16 @@ __device__ __forceinline__ int group_allreduce8(int x) {
 
 // Moves (a, b) `steps` places forward in the lexicographic pair order; past
 // the last pair it parks on (n - 2, n - 1) so that every index stays in range.
+// Row a holds the pairs (a, a + 1) .. (a, n - 1): steps that run past its end
+// carry over to row a + 1, starting at (a + 1, a + 2).
 __device__ __forceinline__ void pair_advance(int &a, int &b, int n, int steps) {
-    for (int r = 0; r < steps; ++r) {
-        if (++b == n) {
-            ++a;
-            b = a + 1;
-        }
+    b += steps;
+    while (b >= n && a < n - 2) {
+        const int over = b - n;  // steps left after reaching (a + 1, a + 2)
+        ++a;
+        b = a + 1 + over;
     }
-    if (a >= n - 1) {
+    if (a >= n - 1 || b >= n) {
         a = n - 2;
         b = n - 1;
     }
