@@ -349,14 +349,18 @@ int nmc_ksat_load(int32_t n_vars, int32_t n_clauses, const int32_t *clause_ptr, 
             return fail(NMC_ERR_INVALID, "class_cap must be >= 0");
         if (clause_ptr[0] != 0)
             return fail(NMC_ERR_INVALID, "clause_ptr[0] must be 0");
+        // every offset first, so that no literal is read through a bad offset
         int32_t kmax = 0;
         for (int32_t a = 0; a < n_clauses; ++a) {
-            const int32_t len = clause_ptr[a + 1] - clause_ptr[a];
+            const int64_t len = (int64_t)clause_ptr[a + 1] - clause_ptr[a];
             if (len < 1)
                 return fail(NMC_ERR_INVALID, "clause %d is empty or offsets decrease", a);
             if (len > 4)
-                return fail(NMC_ERR_UNSUPPORTED, "clause %d has %d literals (at most 4 supported)", a, len);
-            kmax = std::max(kmax, len);
+                return fail(NMC_ERR_UNSUPPORTED, "clause %d has %lld literals (at most 4 supported)", a,
+                            (long long)len);
+            kmax = std::max(kmax, (int32_t)len);
+        }
+        for (int32_t a = 0; a < n_clauses; ++a) {
             for (int32_t p = clause_ptr[a]; p < clause_ptr[a + 1]; ++p) {
                 const int32_t l = lits[p];
                 if (l == 0 || l > n_vars || l < -n_vars)

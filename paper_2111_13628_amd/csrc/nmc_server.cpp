@@ -143,13 +143,14 @@ void release(Req *q, const DevMem &m) {
     q->dev_rep = q->dev_inst = nullptr;
 }
 
-bool admit(Req *q, const DevMem &m) {
+// On failure the reason goes to msg (the caller publishes it under the lock).
+bool admit(Req *q, const DevMem &m, char (&msg)[sizeof(nmc_result::message)]) {
     const char *what = "device allocation";
     hipStream_t s = m.s;
     if (hipMallocFromPoolAsync(&q->dev_inst, std::max<size_t>(q->inst_bytes, 256), m.pool, s) != hipSuccess ||
         hipMallocFromPoolAsync(&q->dev_rep, std::max<size_t>(q->rep_bytes, 256), m.pool, s) != hipSuccess) {
         (void)hipGetLastError();
-        std::snprintf(q->res.message, sizeof q->res.message, "device allocation failed");
+        std::snprintf(msg, sizeof msg, "device allocation failed");
         return false;
     }
     what = "bind";
@@ -159,7 +160,7 @@ bool admit(Req *q, const DevMem &m) {
             NMC_OK)
             return true;
     }
-    set_msg(q->res, what);
+    std::snprintf(msg, sizeof msg, "%s: %s", what, nmc_last_error());
     return false;
 }
 
@@ -275,18 +276,21 @@ void worker_main(nmc_server *S, int w) {
             blocked = has_loaded(S, kind);
         }
         for (Req *q : to_admit) {
-            const bool okq = admit(q, mem);
+            char msg[sizeof(nmc_result::message)] = {0};
+            const bool okq = admit(q, mem, msg);
+            if (!okq)
+                release(q, mem);
             std::lock_guard<std::mutex> lk(S->mu);
             if (okq) {
                 q->res.t_admit = seconds_since(S->t0);
                 q->res.status = NMC_REQ_RUNNING;
                 active.push_back(q);
             } else {
-                release(q, mem);
                 S->bytes_in_use -= std::min(S->bytes_in_use, q->inst_bytes + q->rep_bytes);
                 S->release_gen++;
-                q->res.status = NMC_REQ_FAILED;
+                std::memcpy(q->res.message, msg, sizeof msg);
                 q->res.t_done = seconds_since(S->t0);
+                q->res.status = NMC_REQ_FAILED;
                 S->completed++;
                 S->cv.notify_all();
             }
@@ -316,28 +320,35 @@ void worker_main(nmc_server *S, int w) {
         }
         const double round_s = seconds_since(t_round);
         const double now = seconds_since(S->t0);
+        // new results are formed in copies (only this worker writes an active
+        // request's result, so reading it here races with nothing) and
+        // published under the lock, together with status and t_done, so that a
+        // poll never sees a terminal status without its completion time
         std::vector<Req *> done;
         std::vector<Req *> keep;
+        std::vector<nmc_result> fresh(act.size());
         for (size_t i = 0; i < act.size(); ++i) {
             Req *q = act[i];
+            nmc_result &nr = fresh[i];
+            nr = q->res;
             if (rc != NMC_OK) {
-                set_msg(q->res, "step");
-                q->res.status = NMC_REQ_FAILED;
+                set_msg(nr, "step");
+                nr.status = NMC_REQ_FAILED;
                 done.push_back(q);
                 continue;
             }
-            q->res.best = st[i].best;
-            q->res.n_at_zero = st[i].n_at_zero;
-            q->res.first_hit_sweep = st[i].first_hit;
-            q->res.sweeps_done += (uint32_t)K;
+            nr.best = st[i].best;
+            nr.n_at_zero = st[i].n_at_zero;
+            nr.first_hit_sweep = st[i].first_hit;
+            nr.sweeps_done += (uint32_t)K;
             const bool finished = advance(q, K);
             if (q->r.has_target && st[i].first_hit >= 0)
-                q->res.status = NMC_REQ_SOLVED;
+                nr.status = NMC_REQ_SOLVED;
             else if (finished)
-                q->res.status = NMC_REQ_EXHAUSTED;
-            else if (q->r.budget_s > 0 && now - q->res.t_admit >= q->r.budget_s)
-                q->res.status = NMC_REQ_TIMEOUT;
-            if (q->res.status == NMC_REQ_RUNNING)
+                nr.status = NMC_REQ_EXHAUSTED;
+            else if (q->r.budget_s > 0 && now - nr.t_admit >= q->r.budget_s)
+                nr.status = NMC_REQ_TIMEOUT;
+            if (nr.status == NMC_REQ_RUNNING)
                 keep.push_back(q);
             else
                 done.push_back(q);
@@ -350,10 +361,13 @@ void worker_main(nmc_server *S, int w) {
         std::lock_guard<std::mutex> lk(S->mu);
         S->rounds++;
         S->busy_s += round_s;
-        for (Req *q : done) {
-            q->res.t_done = now;
-            S->completed++;
+        for (size_t i = 0; i < act.size(); ++i) {
+            if (fresh[i].status != NMC_REQ_RUNNING)
+                fresh[i].t_done = now;
+            act[i]->res = fresh[i];
         }
+        for (size_t i = 0; i < done.size(); ++i)
+            S->completed++;
         S->bytes_in_use -= std::min(S->bytes_in_use, freed);
         if (!done.empty())
             S->release_gen++;

@@ -37,6 +37,19 @@ def test_ksat_validation_errors(cp, lits, code):
     assert e.value.code == code
 
 
+def test_ksat_offsets_checked_before_literals():
+    # clause 0 claims four literals but only three exist: the offsets are
+    # rejected (clause 1 decreases) before any literal is read through them
+    lits = np.array([1, 2, 3], dtype=np.int32)
+    with pytest.raises(nmc.NmcError) as e:
+        _load(3, np.array([0, 4, 3]), lits)
+    assert e.value.code == -1
+    assert "clause 1 is empty or offsets decrease" in str(e.value)
+    with pytest.raises(nmc.NmcError) as e:
+        _load(6, np.array([0, 5, 3]), lits)
+    assert e.value.code == -6 and "clause 0 has 5 literals" in str(e.value)
+
+
 def test_ksat_unsupported():
     with pytest.raises(nmc.NmcError) as e:
         _load(6, np.array([0, 5]), np.array([1, 2, 3, 4, 5]))

@@ -3,6 +3,8 @@ equals the same calls made set by set; the server's piecewise-constant
 schedule equals that schedule run directly, and the CPU oracle; a request's
 result does not depend on what else is served beside it; admission keeps the
 admitted device bytes under the cap; budgets and bad requests retire cleanly."""
+import time
+
 import numpy as np
 import pytest
 
@@ -244,3 +246,34 @@ def test_budget_and_failed_requests():
     assert ra["status"] == "timeout" and 10 <= ra["sweeps_done"] < 100000
     assert rb["status"] == "failed" and "load" in rb["message"]
     assert rc["status"] == "exhausted" and rc["sweeps_done"] == 100
+
+
+def test_poll_snapshots_are_consistent():
+    """Polls taken in a tight loop while requests run: whenever a snapshot
+    shows a terminal status it also holds the completion time (published
+    together under the server's lock), and a running request has an admission
+    time at or after its submission."""
+    say("case: polls while requests run")
+    reqs = _mix_requests()
+    srv = nmc.Server(chunk_sweeps=10, max_active=3)
+    seen_terminal = 0
+    try:
+        ids = [_submit(srv, q) for q in reqs]
+        deadline = time.monotonic() + 300
+        while True:
+            assert time.monotonic() < deadline, "requests did not finish"
+            snaps = [srv.poll(i) for i in ids]
+            for r in snaps:
+                if r["status"] in ("solved", "exhausted", "timeout", "failed"):
+                    seen_terminal += 1
+                    assert r["t_done"] > 0 and r["t_done"] >= r["t_submit"], r
+                    if r["status"] != "failed":
+                        assert r["t_done"] >= r["t_admit"] >= r["t_submit"], r
+                elif r["status"] == "running":
+                    assert r["t_admit"] >= r["t_submit"], r
+            if all(r["status"] in ("solved", "exhausted", "timeout", "failed") for r in snaps):
+                break
+        assert srv.wait_idle(300)
+    finally:
+        srv.free()
+    assert seen_terminal >= len(reqs)
