@@ -34,7 +34,8 @@
  *    whitening workspace, all released by nmc_replicas_free; a per-batch
  *    descriptor and table buffer (released by nmc_batch_free); and, for a
  *    server, the device memory of the requests it admits (released when a
- *    request retires or by nmc_server_free).
+ *    request retires or by nmc_server_free).  nmc_anneal_noalloc uses a fixed
+ *    device array of the library instead (one per device, never freed).
  *  - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on
  *    it in call order; calls on one replica set must not overlap in time.
  *  - Energies are exact integers: the k-SAT energy is the number of violated
@@ -204,6 +205,30 @@ int nmc_anneal(nmc_replicas *rep, const double *beta, int32_t n_classes, int32_t
  * current states and sweep counter; kept as its own name for the API. */
 int nmc_reanneal(nmc_replicas *rep, const double *beta, int32_t n_classes, int32_t n_sweeps, int32_t profile,
                  const uint8_t *class_of, int64_t target, void *stream);
+
+/* Allocation-free nmc_anneal, for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops that must not call the
+ * allocator).  Arguments, results and errors are those of nmc_anneal, with
+ * the same bits: the same kernels run, and only the place of the call's
+ * threshold tables differs.  The tables (4 bytes per table word: sweeps x
+ * classes x (max degree + 1) for k-SAT, x (high-digit entries + 1024) for
+ * QAP, rounded up to 256 bytes, plus N or n bytes of class_of for
+ * NMC_PROFILE_HOST, rounded up to 256) are uploaded into a fixed device array
+ * of the library (nmc_anneal_noalloc_capacity() bytes, one per device, held
+ * until the process ends) instead of the replica set's upload buffer; a call
+ * that needs more fails with NMC_ERR_CAPACITY before anything runs (split the
+ * schedule into shorter calls: the sweep counter continues).  The call makes
+ * no hipMalloc or hipFree and creates no events (nmc_set_profiling does not
+ * apply to it).  Every call on one GPU shares that GPU's array: calls that
+ * overlap in time on one GPU (other streams, other threads) race on it and
+ * must be serialized by the caller; calls in order on one stream are safe.
+ * Each call writes every byte of the array it reads, so no contents carry
+ * over between calls.  The calling thread's current device must be the one
+ * the replica set lives on. */
+int nmc_anneal_noalloc(nmc_replicas *rep, const double *beta, int32_t n_classes, int32_t n_sweeps, int32_t profile,
+                       const uint8_t *class_of, int64_t target, void *stream);
+/* Bytes of the fixed device array nmc_anneal_noalloc uploads into. */
+size_t nmc_anneal_noalloc_capacity(void);
 
 /* ---------------------------------------------------------------------------
  * estimate_backbone

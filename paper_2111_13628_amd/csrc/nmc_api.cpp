@@ -883,8 +883,13 @@ void nmc_replicas_free(nmc_replicas *P) {
     }
 }
 
+// ext_buf != nullptr: the thresholds (and a host class array) go to ext_buf
+// (device, ext_cap bytes) and nothing is allocated; a call that needs more
+// fails with NMC_ERR_CAPACITY before any work is queued.  Otherwise they go to
+// the replica set's own upload buffer, allocated or grown as needed.
 static int anneal_impl(nmc_replicas *P, const double *beta, int32_t n_classes, int32_t n_sweeps, int32_t profile,
-                       const uint8_t *class_of, int64_t target, void *stream) {
+                       const uint8_t *class_of, int64_t target, void *stream, uint8_t *ext_buf = nullptr,
+                       size_t ext_cap = 0) {
     if (!P || !beta)
         return fail(NMC_ERR_INVALID, "NULL argument");
     nmc_instance *I = P->inst;
@@ -927,9 +932,20 @@ static int anneal_impl(nmc_replicas *P, const double *beta, int32_t n_classes, i
     const size_t words = (size_t)n_sweeps * n_classes * stride;
     const size_t tab_bytes = align_up(std::max<size_t>(words * 4, 4), 256);
     const size_t cls_bytes = profile == NMC_PROFILE_HOST ? align_up(nitems, 256) : 0;
-    int rc = ensure_tab(P, tab_bytes + cls_bytes);
-    if (rc)
-        return rc;
+    uint8_t *up = ext_buf;
+    if (ext_buf) {
+        if (tab_bytes + cls_bytes > ext_cap)
+            return fail(NMC_ERR_CAPACITY,
+                        "this call's thresholds need %zu bytes (%d sweeps x %d classes x %d words%s), the "
+                        "allocation-free buffer holds %zu: split the schedule into shorter calls",
+                        tab_bytes + cls_bytes, n_sweeps, n_classes, stride,
+                        cls_bytes ? " + the class array" : "", ext_cap);
+    } else {
+        int rc = ensure_tab(P, tab_bytes + cls_bytes);
+        if (rc)
+            return rc;
+        up = P->tab_dev;
+    }
     std::vector<uint32_t> tab(std::max<size_t>(words, 1));
     for (int32_t sw = 0; sw < n_sweeps; ++sw)
         for (int32_t c = 0; c < n_classes; ++c) {
@@ -951,25 +967,27 @@ static int anneal_impl(nmc_replicas *P, const double *beta, int32_t n_classes, i
         }
     // the upload waits for earlier work on the stream that still reads the
     // buffer: pageable host-to-device copies are ordered in the stream
-    HIP_OR_FAIL(hipMemcpyAsync(P->tab_dev, tab.data(), words * 4, hipMemcpyHostToDevice, s));
+    HIP_OR_FAIL(hipMemcpyAsync(up, tab.data(), words * 4, hipMemcpyHostToDevice, s));
     const uint8_t *cls_dev = nullptr;
     if (profile == NMC_PROFILE_HOST) {
-        HIP_OR_FAIL(hipMemcpyAsync(P->tab_dev + tab_bytes, class_of, nitems, hipMemcpyHostToDevice, s));
-        cls_dev = P->tab_dev + tab_bytes;
+        HIP_OR_FAIL(hipMemcpyAsync(up + tab_bytes, class_of, nitems, hipMemcpyHostToDevice, s));
+        cls_dev = up + tab_bytes;
     } else if (profile == NMC_PROFILE_BACKBONE) {
         cls_dev = ksat ? P->k.cls : P->q.cls;
     }
 
+    // the allocation-free variant creates no timing events
+    const bool timed = P->profiling && !ext_buf;
     ScopedEvents evs;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (P->profiling) {
+    if (timed) {
         HIP_OR_FAIL(evs.create(&e0));
         HIP_OR_FAIL(evs.create(&e1));
         HIP_OR_FAIL(hipEventRecord(e0, s));
     }
     if (ksat) {
         SweepCall C{};
-        C.tab = reinterpret_cast<const uint32_t *>(P->tab_dev);
+        C.tab = reinterpret_cast<const uint32_t *>(up);
         C.var_cls = cls_dev;
         C.n_classes = n_classes;
         C.stride = stride;
@@ -983,7 +1001,7 @@ static int anneal_impl(nmc_replicas *P, const double *beta, int32_t n_classes, i
         HIP_OR_FAIL(ksat_launch_sweep(I->ksat_dev(), P->k, C, P->block_threads, s));
     } else {
         QapCall C{};
-        C.tab = reinterpret_cast<const uint32_t *>(P->tab_dev);
+        C.tab = reinterpret_cast<const uint32_t *>(up);
         C.fac_cls = cls_dev;
         C.n_classes = n_classes;
         C.stride = stride;
@@ -997,7 +1015,7 @@ static int anneal_impl(nmc_replicas *P, const double *beta, int32_t n_classes, i
         C.key1 = (uint32_t)(P->seed >> 32);
         HIP_OR_FAIL(qap_launch_sweep(I->qap_dev(), P->q, C, 256, s));
     }
-    if (P->profiling) {
+    if (timed) {
         HIP_OR_FAIL(hipEventRecord(e1, s));
         HIP_OR_FAIL(hipEventSynchronize(e1));
         float ms = 0;
@@ -1024,6 +1042,21 @@ int nmc_reanneal(nmc_replicas *P, const double *beta, int32_t n_classes, int32_t
                  const uint8_t *class_of, int64_t target, void *stream) {
     return nmc_anneal(P, beta, n_classes, n_sweeps, profile, class_of, target, stream);
 }
+
+}  // extern "C"
+
+int nmc::anneal_into(nmc_replicas *P, const double *beta, int32_t n_classes, int32_t n_sweeps, int32_t profile,
+                     const uint8_t *class_of, int64_t target, void *stream, uint8_t *buf, size_t cap) {
+    if (!buf)
+        return fail(NMC_ERR_INVALID, "NULL upload buffer");
+    try {
+        return anneal_impl(P, beta, n_classes, n_sweeps, profile, class_of, target, stream, buf, cap);
+    } catch (const std::bad_alloc &) {
+        return fail(NMC_ERR_CAPACITY, "host allocation failed");
+    }
+}
+
+extern "C" {
 
 int nmc_estimate_backbone(nmc_replicas *P, int32_t thr_num, int32_t thr_den, int32_t expand, uint8_t *class_out,
                           int32_t *counts_out, void *stream) {

@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+struct nmc_replicas;
+
 namespace nmc {
 
 // Philox stream identifiers (fourth counter word).
@@ -255,5 +257,12 @@ hipError_t ksat_launch_cflip(const KsatDev &I, const KsatRepDev &R, const CflipC
 
 // records msg as the calling thread's nmc_last_error text; returns code
 int set_last_error(int code, const char *msg);
+
+// nmc_anneal with the call's threshold tables (and host class array) uploaded
+// to buf (device memory, cap bytes) instead of the replica set's own upload
+// buffer: allocates nothing; NMC_ERR_CAPACITY when the call needs more than
+// cap bytes (checked before any work is queued).  No timing events.
+int anneal_into(nmc_replicas *P, const double *beta, int32_t n_classes, int32_t n_sweeps, int32_t profile,
+                const uint8_t *class_of, int64_t target, void *stream, uint8_t *buf, size_t cap);
 
 }  // namespace nmc

@@ -121,6 +121,8 @@ _SIGS = {
     "nmc_replicas_free": ([_P], None),
     "nmc_anneal": ([_P, _P, _I32, _I32, _I32, _P, _I64, _P], ctypes.c_int),
     "nmc_reanneal": ([_P, _P, _I32, _I32, _I32, _P, _I64, _P], ctypes.c_int),
+    "nmc_anneal_noalloc": ([_P, _P, _I32, _I32, _I32, _P, _I64, _P], ctypes.c_int),
+    "nmc_anneal_noalloc_capacity": ([], _SZ),
     "nmc_estimate_backbone": ([_P, _I32, _I32, _I32, _P, _P, _P], ctypes.c_int),
     "nmc_best_energy": ([_P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
     "nmc_recount": ([_P, _P, _P], ctypes.c_int),
@@ -336,6 +338,11 @@ class Replicas:
 
     def reanneal(self, beta, profile="backbone", class_of=None, target=-1, stream=None):
         self._run(lib().nmc_reanneal, beta, profile, class_of, target, stream)
+
+    def anneal_noalloc(self, beta, profile="homogeneous", class_of=None, target=-1, stream=None):
+        """nmc_anneal_noalloc: nmc_anneal with the thresholds in the library's
+        fixed device array (no device allocation)."""
+        self._run(lib().nmc_anneal_noalloc, beta, profile, class_of, target, stream)
 
     def pt_run(self, beta, n_rounds, sweeps_per_round=1, first_parity=0, target=-1, stream=None):
         """Replica-exchange rounds over the ladder beta (replica r = i * C + c
