@@ -554,12 +554,36 @@ int nmc_batch_lbp_backbone(nmc_batch *batch, const int32_t *replicas, int32_t wh
 /* nmc_estimate_backbone for every set (classes stay on the device). */
 int nmc_batch_estimate_backbone(nmc_batch *batch, int32_t thr_num, int32_t thr_den, int32_t expand, void *stream);
 
-/* The whole plan for every set.  With use_graph != 0 the plan's kernels
- * (anneal, then per round the backbone kernels and the reanneal) are captured
- * into one HIP graph and launched on `stream` as a unit.  Identical results
- * either way.  Synchronizes the stream before returning. */
+/* The same plan for every set: nmc_batch_run with plans[i] = *plan. */
 int nmc_batch_run_plan(nmc_batch *batch, const nmc_plan *plan, const int64_t *targets, int32_t use_graph,
                        void *stream);
+
+/* Algorithm 1's loop for every set of the batch, each with its own plan
+ * (plans[n_sets]: its own schedule, beta units, sweep counts, rounds,
+ * backbone rule and chunk size), so k-SAT and QAP sets with different
+ * schedules run together.  Set i runs exactly
+ *   nmc_anneal(plans[i].anneal_beta, 1 class, anneal_sweeps, homogeneous,
+ *              targets[i]);
+ *   rounds x { nmc_estimate_backbone(thr_num, thr_den, expand);
+ *              nmc_reanneal(reanneal_beta, 2 classes, reanneal_sweeps,
+ *                           backbone, targets[i]) }
+ * with identical results (targets NULL = no target).  The call's timeline
+ * is cut at every phase and chunk boundary of every set; each cut is one
+ * batched launch per kernel kind over the sets that have sweeps there (a set
+ * whose plan is shorter is left out once it is done), with each set's
+ * backbone estimates launched before its rounds.  With use_graph != 0 the
+ * whole launch sequence is captured into one HIP graph; the executable graph
+ * is kept with the batch and replayed by later calls whose launch sequence
+ * has the same shape (same sets' sizes, plan lengths, chunks and rules; the
+ * schedules' betas, targets and sweep counters are data uploaded before each
+ * launch).  Synchronizes the stream before returning.
+ * Errors: INVALID (a plan's fields, betas, thresholds; sweep counter
+ * overflow), CAPACITY (LDS), DEVICE. */
+int nmc_batch_run(nmc_batch *batch, const nmc_plan *plans, const int64_t *targets, int32_t use_graph, void *stream);
+
+/* Graph bookkeeping of nmc_batch_run / nmc_batch_run_plan: graphs captured
+ * and instantiated, and calls that replayed the kept graph. */
+int nmc_batch_graph_info(const nmc_batch *batch, int64_t *captures, int64_t *replays);
 
 /* One step of n_sweeps for every set, each running its own segment of its
  * own schedule (continuous batching: sets may be at different points of their

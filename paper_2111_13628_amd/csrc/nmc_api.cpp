@@ -10,11 +10,13 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <new>
 #include <numeric>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "../../include/nmc.h"
@@ -2071,6 +2073,23 @@ int nmc_kernel_time(nmc_replicas *P, double *ms, int64_t *launches, double *atte
 // batched launches (many replica sets, one grid per kernel kind)
 // ---------------------------------------------------------------------------
 
+// One launch of the plan's sequence, in the order it is enqueued.  Everything
+// a launch takes besides the uploaded descriptor blob is here, so two calls
+// whose launch lists (and blob address) are equal can replay one graph.
+struct BatchLaunch {
+    int32_t what = 0;  // 0 k-SAT sweep, 1 QAP sweep, 2 k-SAT backbone, 3 QAP backbone
+    size_t off_jobs = 0, off_items = 0;
+    int32_t n_items = 0, grid = 0, block = 0;
+    size_t lds = 0;
+    int32_t thr_num = 0, thr_den = 0, expand = 0;
+    double attempts = 0;
+    bool operator==(const BatchLaunch &o) const {
+        return what == o.what && off_jobs == o.off_jobs && off_items == o.off_items && n_items == o.n_items &&
+               grid == o.grid && block == o.block && lds == o.lds && thr_num == o.thr_num && thr_den == o.thr_den &&
+               expand == o.expand;
+    }
+};
+
 struct nmc_batch {
     std::vector<nmc_replicas *> sets;
     int32_t block_threads = 0;  // k-SAT sweep workgroup size; 0 = heuristic
@@ -2087,6 +2106,12 @@ struct nmc_batch {
     size_t lbp_cap = 0;
     double lbp_ms = 0;
     int64_t lbp_iters = 0;
+    // executable graph of the last per-set plan call, replayed while the
+    // launch list and the descriptor buffer stay the same
+    hipGraphExec_t exec = nullptr;
+    uint8_t *exec_dev = nullptr;
+    std::vector<BatchLaunch> exec_launches;
+    int64_t graph_captures = 0, graph_replays = 0;
 };
 
 namespace {
@@ -2380,7 +2405,7 @@ int validate_phase(nmc_batch *B, const PhaseSpec &ph, bool backbone_available) {
 }
 
 int run_batch(nmc_batch *B, const std::vector<PhaseSpec> &phases, const std::vector<char> &bb_before, int thr_num,
-              int thr_den, int expand, const int64_t *targets, bool use_graph, hipStream_t s) {
+              int thr_den, int expand, const int64_t *targets, hipStream_t s) {
     // phases run in order; bb_before[p] != 0 puts a backbone estimate before phase p
     bool any_bb = false, seen_bb = false;
     for (size_t p = 0; p < phases.size(); ++p) {
@@ -2416,95 +2441,455 @@ int run_batch(nmc_batch *B, const std::vector<PhaseSpec> &phases, const std::vec
     HIP_OR_FAIL(hipMemcpyAsync(B->dev, blob.host.data(), blob.host.size(), hipMemcpyHostToDevice, s));
     HIP_OR_FAIL(hipStreamSynchronize(s));
 
-    if (use_graph) {
+    for (size_t p = 0; p < built.size(); ++p) {
+        if (bb_before[p]) {
+            rc = enqueue_backbone(B, bb, thr_num, thr_den, expand, s);
+            if (rc)
+                return rc;
+        }
         ScopedEvents evs;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (B->profiling) {
             HIP_OR_FAIL(evs.create(&e0));
             HIP_OR_FAIL(evs.create(&e1));
-        }
-        if (!B->cap_stream)
-            HIP_OR_FAIL(hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking));
-        HIP_OR_FAIL(hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal));
-        int erc = NMC_OK;
-        for (size_t p = 0; p < built.size() && !erc; ++p) {
-            if (bb_before[p])
-                erc = enqueue_backbone(B, bb, thr_num, thr_den, expand, B->cap_stream);
-            if (!erc)
-                erc = enqueue_phase(B, built[p], B->cap_stream);
-        }
-        hipGraph_t graph = nullptr;
-        const hipError_t ee = hipStreamEndCapture(B->cap_stream, &graph);
-        if (erc) {
-            if (graph)
-                (void)hipGraphDestroy(graph);
-            return erc;
-        }
-        if (ee != hipSuccess)
-            return fail(NMC_ERR_DEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(ee));
-        hipGraphExec_t exec = nullptr;
-        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (ei != hipSuccess)
-            return fail(NMC_ERR_DEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(ei));
-        // the executable graph goes on every exit, once the stream has drained
-        struct ExecGuard {
-            hipGraphExec_t x;
-            hipStream_t s;
-            ~ExecGuard() {
-                (void)hipStreamSynchronize(s);
-                (void)hipGraphExecDestroy(x);
-            }
-        } exec_guard{exec, s};
-        if (B->profiling)
             HIP_OR_FAIL(hipEventRecord(e0, s));
-        const hipError_t el = hipGraphLaunch(exec, s);
-        if (B->profiling && el == hipSuccess)
-            HIP_OR_FAIL(hipEventRecord(e1, s));
-        const hipError_t es = hipStreamSynchronize(s);
-        if (el != hipSuccess || es != hipSuccess)
-            return fail(NMC_ERR_DEVICE, "graph launch failed: %s", hipGetErrorString(el != hipSuccess ? el : es));
+        }
+        rc = enqueue_phase(B, built[p], s);
+        if (rc)
+            return rc;
         if (B->profiling) {
+            HIP_OR_FAIL(hipEventRecord(e1, s));
+            HIP_OR_FAIL(hipEventSynchronize(e1));
             float ms = 0;
             HIP_OR_FAIL(hipEventElapsedTime(&ms, e0, e1));
             B->prof_ms += ms;
             B->prof_launches += 1;
-            for (const auto &bp : built)
-                B->prof_attempts += bp.attempts;
+            B->prof_attempts += built[p].attempts;
         }
-    } else {
-        for (size_t p = 0; p < built.size(); ++p) {
-            if (bb_before[p]) {
-                rc = enqueue_backbone(B, bb, thr_num, thr_den, expand, s);
-                if (rc)
-                    return rc;
-            }
-            ScopedEvents evs;
-            hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (B->profiling) {
-                HIP_OR_FAIL(evs.create(&e0));
-                HIP_OR_FAIL(evs.create(&e1));
-                HIP_OR_FAIL(hipEventRecord(e0, s));
-            }
-            rc = enqueue_phase(B, built[p], s);
-            if (rc)
-                return rc;
-            if (B->profiling) {
-                HIP_OR_FAIL(hipEventRecord(e1, s));
-                HIP_OR_FAIL(hipEventSynchronize(e1));
-                float ms = 0;
-                HIP_OR_FAIL(hipEventElapsedTime(&ms, e0, e1));
-                B->prof_ms += ms;
-                B->prof_launches += 1;
-                B->prof_attempts += built[p].attempts;
-            }
-        }
-        // the descriptor blob must outlive the kernels that read it
-        HIP_OR_FAIL(hipStreamSynchronize(s));
     }
+    // the descriptor blob must outlive the kernels that read it
+    HIP_OR_FAIL(hipStreamSynchronize(s));
     for (auto *P : B->sets) {
         P->sweeps_done += (uint32_t)total;
         if (any_bb)
+            P->has_backbone = true;
+    }
+    return ok();
+}
+
+// ---- per-set plans (nmc_batch_run) -----------------------------------------
+
+// One phase of one set's plan, on the call's sweep timeline.
+struct SetPhase {
+    int64_t start = 0;      // sweeps from the call's start
+    int32_t len = 0;        // sweeps
+    int32_t nc = 1;         // classes: 1 (anneal) or 2 (reanneal)
+    int32_t profile = NMC_PROFILE_HOMOGENEOUS;
+    const double *beta = nullptr;  // [nc][len]
+    int32_t chunk = 0;      // > 0: launches of at most this many sweeps
+    bool backbone_before = false;
+};
+
+int validate_plan(const nmc_plan &p, size_t i) {
+    if (p.rounds < 0 || p.anneal_sweeps < 0 || p.reanneal_sweeps < 0 || p.chunk_sweeps < 0)
+        return fail(NMC_ERR_INVALID, "plan %zu: negative field", i);
+    if (p.anneal_sweeps > 0 && !p.anneal_beta)
+        return fail(NMC_ERR_INVALID, "plan %zu: anneal_beta is NULL", i);
+    if (p.rounds > 0 && p.reanneal_sweeps > 0 && !p.reanneal_beta)
+        return fail(NMC_ERR_INVALID, "plan %zu: reanneal_beta is NULL", i);
+    if (p.rounds > 0 && (p.thr_den <= 0 || p.thr_num <= 0 || p.thr_num > p.thr_den))
+        return fail(NMC_ERR_INVALID, "plan %zu: need 0 < thr_num <= thr_den", i);
+    for (int64_t t = 0; t < p.anneal_sweeps; ++t)
+        if (!std::isfinite(p.anneal_beta[t]) || p.anneal_beta[t] < 0)
+            return fail(NMC_ERR_INVALID, "plan %zu: anneal_beta[%lld] is not finite and >= 0", i, (long long)t);
+    if (p.rounds > 0)
+        for (int64_t t = 0; t < 2 * (int64_t)p.reanneal_sweeps; ++t)
+            if (!std::isfinite(p.reanneal_beta[t]) || p.reanneal_beta[t] < 0)
+                return fail(NMC_ERR_INVALID, "plan %zu: reanneal_beta[%lld] is not finite and >= 0", i,
+                            (long long)t);
+    return NMC_OK;
+}
+
+std::vector<SetPhase> plan_phases(const nmc_plan &p) {
+    std::vector<SetPhase> v;
+    SetPhase a;
+    a.len = p.anneal_sweeps;
+    a.beta = p.anneal_beta;
+    a.chunk = p.chunk_sweeps;
+    v.push_back(a);
+    int64_t t = a.len;
+    for (int32_t r = 0; r < p.rounds; ++r) {
+        SetPhase ph;
+        ph.start = t;
+        ph.len = p.reanneal_sweeps;
+        ph.nc = 2;
+        ph.profile = NMC_PROFILE_BACKBONE;
+        ph.beta = p.reanneal_beta;
+        ph.chunk = p.chunk_sweeps;
+        ph.backbone_before = true;
+        v.push_back(ph);
+        t += ph.len;
+    }
+    return v;
+}
+
+// Lay out every launch of the per-set plans: the call's timeline is cut at
+// every phase and chunk boundary of every set, so that in each stage a set
+// runs sweeps of one phase only (or none: its plan is done); a set's backbone
+// estimates run at the start of its reanneal rounds.  Thresholds are built per
+// (kind, classes, sweeps, betas) and shared by the sets whose slices agree.
+int build_plans(nmc_batch *B, const std::vector<std::vector<SetPhase>> &ph, const std::vector<nmc_plan> &plans,
+                const int64_t *targets, uint8_t *dev_base, Blob &blob, std::vector<BatchLaunch> &launches) {
+    const std::vector<nmc_replicas *> &sets = B->sets;
+    const size_t ns = sets.size();
+    int32_t stride_k = 1, ha = 1;
+    std::vector<nmc_replicas *> ks;
+    for (auto *P : sets) {
+        if (P->inst->kind == NMC_KIND_KSAT) {
+            stride_k = std::max(stride_k, P->inst->dmax + 1);
+            ks.push_back(P);
+        } else {
+            ha = std::max(ha, P->inst->qap_ha);
+        }
+    }
+    const int32_t stride_q = ha + (1 << kQapLowBits);
+    const int block_k = B->block_threads > 0 ? B->block_threads : heuristic_block(ks);
+    const int cus = device_cus();
+    // stage boundaries
+    std::vector<int64_t> cut;
+    for (size_t i = 0; i < ns; ++i)
+        for (const SetPhase &p : ph[i]) {
+            const int64_t K = p.chunk > 0 ? p.chunk : std::max<int64_t>(p.len, 1);
+            for (int64_t s0 = 0; s0 < p.len; s0 += K)
+                cut.push_back(p.start + s0);
+            cut.push_back(p.start + p.len);
+            cut.push_back(p.start);
+        }
+    std::sort(cut.begin(), cut.end());
+    cut.erase(std::unique(cut.begin(), cut.end()), cut.end());
+    std::map<std::string, size_t> tab_at;
+    auto table = [&](bool ksat, const SetPhase &p, int64_t off, int32_t len) -> size_t {
+        std::string key(1, ksat ? 'k' : 'q');
+        key.push_back((char)p.nc);
+        for (int32_t c = 0; c < p.nc; ++c)
+            key.append(reinterpret_cast<const char *>(p.beta + (size_t)c * p.len + off), (size_t)len * sizeof(double));
+        auto it = tab_at.find(key);
+        if (it != tab_at.end())
+            return it->second;
+        const int32_t stride = ksat ? stride_k : stride_q;
+        const size_t at = blob.take(std::max<size_t>((size_t)len * p.nc * stride * 4, 4));
+        for (int32_t sw = 0; sw < len; ++sw)
+            for (int32_t c = 0; c < p.nc; ++c) {
+                uint32_t *row = reinterpret_cast<uint32_t *>(blob.host.data() + at) + ((size_t)sw * p.nc + c) * stride;
+                const double b = p.beta[(size_t)c * p.len + off + sw];
+                row[0] = 0xFFFFFFFFu;
+                if (ksat) {
+                    for (int32_t d = 1; d < stride_k; ++d)
+                        row[d] = threshold(b, d);
+                } else {
+                    for (int32_t h = 1; h < ha; ++h)
+                        row[h] = threshold(b, (int64_t)h << kQapLowBits);
+                    row[ha] = 0xFFFFFFFFu;
+                    for (int32_t l = 1; l < (1 << kQapLowBits); ++l)
+                        row[ha + l] = threshold(b, l);
+                }
+            }
+        tab_at.emplace(std::move(key), at);
+        return at;
+    };
+    auto by_cost = [](const std::pair<double, int2> &x, const std::pair<double, int2> &y) { return x.first > y.first; };
+    for (size_t k = 0; k < cut.size(); ++k) {
+        const int64_t T = cut[k];
+        // backbone estimates due at T, one launch per kind and rule
+        std::map<std::tuple<int, int, int, int>, std::vector<size_t>> bb_groups;
+        for (size_t i = 0; i < ns; ++i)
+            for (const SetPhase &p : ph[i])
+                if (p.backbone_before && p.start == T) {
+                    const bool kq = sets[i]->inst->kind == NMC_KIND_KSAT;
+                    bb_groups[{kq ? 2 : 3, plans[i].thr_num, plans[i].thr_den, kq ? (plans[i].expand ? 1 : 0) : 0}]
+                        .push_back(i);
+                    break;  // several zero-length rounds at T estimate the same states
+                }
+        for (auto &g : bb_groups) {
+            BatchLaunch L;
+            L.what = std::get<0>(g.first);
+            L.thr_num = std::get<1>(g.first);
+            L.thr_den = std::get<2>(g.first);
+            L.expand = std::get<3>(g.first);
+            const bool kq = L.what == 2;
+            std::vector<int2> items;
+            L.off_jobs = blob.take(g.second.size() * (kq ? sizeof(KsatJob) : sizeof(QapJob)));
+            for (size_t j = 0; j < g.second.size(); ++j) {
+                nmc_replicas *P = sets[g.second[j]];
+                if (kq) {
+                    KsatJob J{};
+                    J.I = P->inst->ksat_dev();
+                    J.R = P->k;
+                    std::memcpy(blob.host.data() + L.off_jobs + j * sizeof(KsatJob), &J, sizeof J);
+                    for (int v0 = 0; v0 < P->inst->n; v0 += 256)
+                        items.push_back(make_int2((int)j, v0));
+                } else {
+                    QapJob J{};
+                    J.I = P->inst->qap_dev();
+                    J.R = P->q;
+                    std::memcpy(blob.host.data() + L.off_jobs + j * sizeof(QapJob), &J, sizeof J);
+                    for (int f = 0; f < P->inst->n; ++f)
+                        items.push_back(make_int2((int)j, f));
+                }
+            }
+            L.n_items = (int32_t)items.size();
+            L.off_items = blob.take(items.size() * sizeof(int2));
+            std::memcpy(blob.host.data() + L.off_items, items.data(), items.size() * sizeof(int2));
+            if (L.n_items)
+                launches.push_back(L);
+        }
+        if (k + 1 == cut.size())
+            break;
+        const int64_t T1 = cut[k + 1];
+        const int32_t len = (int32_t)(T1 - T);
+        std::vector<KsatJob> kj;
+        std::vector<QapJob> qj;
+        std::vector<std::pair<double, int2>> kit, qit;
+        size_t lds_k = 0, lds_q = 0;
+        double att_k = 0, att_q = 0;
+        for (size_t i = 0; i < ns; ++i) {
+            const SetPhase *cur = nullptr;
+            for (const SetPhase &p : ph[i])
+                if (p.len > 0 && p.start <= T && T < p.start + p.len)
+                    cur = &p;
+            if (!cur)
+                continue;  // this set's plan is done (or between zero-length phases)
+            nmc_replicas *P = sets[i];
+            const int64_t off = T - cur->start;
+            const bool kq = P->inst->kind == NMC_KIND_KSAT;
+            const size_t tab = table(kq, *cur, off, len);
+            const int64_t tg = targets ? targets[i] : -1;
+            if (kq) {
+                KsatJob J{};
+                J.I = P->inst->ksat_dev();
+                J.R = P->k;
+                J.C.tab = reinterpret_cast<const uint32_t *>(dev_base + tab);
+                J.C.var_cls = cur->profile == NMC_PROFILE_BACKBONE ? P->k.cls : nullptr;
+                J.C.n_classes = cur->nc;
+                J.C.stride = stride_k;
+                J.C.n_sweeps = len;
+                J.C.sweep_words = cur->nc * stride_k;
+                J.C.t0 = P->sweeps_done + (uint32_t)T;
+                J.C.target = (int32_t)std::max<int64_t>(std::min<int64_t>(tg, INT32_MAX), INT32_MIN);
+                J.C.check_start = 1;
+                J.C.key0 = (uint32_t)P->seed;
+                J.C.key1 = (uint32_t)(P->seed >> 32);
+                const double cost = (double)P->inst->n * (P->inst->dmax + 1);
+                for (int gi = 0; gi < P->G; ++gi)
+                    kit.push_back({cost, make_int2((int)kj.size(), gi)});
+                lds_k = std::max(lds_k, ksat_sweep_lds_bytes(P->inst->n, cur->nc, stride_k));
+                att_k += (double)P->R * P->inst->n * len;
+                kj.push_back(J);
+            } else {
+                QapJob J{};
+                J.I = P->inst->qap_dev();
+                J.I.ha = ha;
+                J.R = P->q;
+                J.C.tab = reinterpret_cast<const uint32_t *>(dev_base + tab);
+                J.C.fac_cls = cur->profile == NMC_PROFILE_BACKBONE ? P->q.cls : nullptr;
+                J.C.n_classes = cur->nc;
+                J.C.stride = stride_q;
+                J.C.n_sweeps = len;
+                J.C.sweep_words = cur->nc * stride_q;
+                J.C.t0 = P->sweeps_done + (uint32_t)T;
+                J.C.target = tg;
+                J.C.check_start = 1;
+                J.C.rows = qap_rows_setting();
+                J.C.key0 = (uint32_t)P->seed;
+                J.C.key1 = (uint32_t)(P->seed >> 32);
+                const double nd = P->inst->n;
+                const int blocks = (P->R + kQapRepPerBlock - 1) / kQapRepPerBlock;
+                for (int b = 0; b < blocks; ++b)
+                    qit.push_back({nd * nd * nd, make_int2((int)qj.size(), b)});
+                lds_q = std::max(lds_q, qap_sweep_lds_bytes(P->inst->n, cur->nc, stride_q));
+                att_q += (double)P->R * nd * (nd - 1) / 2.0 * len;
+                qj.push_back(J);
+            }
+        }
+        std::stable_sort(kit.begin(), kit.end(), by_cost);
+        std::stable_sort(qit.begin(), qit.end(), by_cost);
+        if (!kj.empty()) {
+            if (lds_k > kLdsBytes)
+                return fail(NMC_ERR_CAPACITY, "batched k-SAT sweep needs %zu bytes of LDS", lds_k);
+            BatchLaunch L;
+            L.what = 0;
+            L.off_jobs = blob.take(kj.size() * sizeof(KsatJob));
+            std::memcpy(blob.host.data() + L.off_jobs, kj.data(), kj.size() * sizeof(KsatJob));
+            L.off_items = blob.take(kit.size() * sizeof(int2));
+            for (size_t t = 0; t < kit.size(); ++t)
+                std::memcpy(blob.host.data() + L.off_items + t * sizeof(int2), &kit[t].second, sizeof(int2));
+            L.n_items = (int32_t)kit.size();
+            L.lds = lds_k;
+            L.block = block_k;
+            L.grid = std::min(L.n_items, ksat_batch_occupancy(block_k, lds_k) * cus);
+            L.attempts = att_k;
+            launches.push_back(L);
+        }
+        if (!qj.empty()) {
+            if (lds_q > kLdsBytes)
+                return fail(NMC_ERR_CAPACITY, "batched QAP sweep needs %zu bytes of LDS", lds_q);
+            BatchLaunch L;
+            L.what = 1;
+            L.off_jobs = blob.take(qj.size() * sizeof(QapJob));
+            std::memcpy(blob.host.data() + L.off_jobs, qj.data(), qj.size() * sizeof(QapJob));
+            L.off_items = blob.take(qit.size() * sizeof(int2));
+            for (size_t t = 0; t < qit.size(); ++t)
+                std::memcpy(blob.host.data() + L.off_items + t * sizeof(int2), &qit[t].second, sizeof(int2));
+            L.n_items = (int32_t)qit.size();
+            L.lds = lds_q;
+            L.grid = std::min(L.n_items, qap_batch_occupancy(lds_q) * cus);
+            L.attempts = att_q;
+            launches.push_back(L);
+        }
+    }
+    return NMC_OK;
+}
+
+int enqueue_plan_launch(nmc_batch *B, const BatchLaunch &L, hipStream_t s) {
+    const uint8_t *d = B->dev;
+    switch (L.what) {
+    case 0:
+        HIP_OR_FAIL(ksat_launch_sweep_batch(reinterpret_cast<const KsatJob *>(d + L.off_jobs),
+                                            reinterpret_cast<const int2 *>(d + L.off_items), L.n_items, L.lds,
+                                            L.block, L.grid, s));
+        break;
+    case 1:
+        HIP_OR_FAIL(qap_launch_sweep_batch(reinterpret_cast<const QapJob *>(d + L.off_jobs),
+                                           reinterpret_cast<const int2 *>(d + L.off_items), L.n_items, L.lds, L.grid,
+                                           s));
+        break;
+    case 2:
+        HIP_OR_FAIL(ksat_launch_backbone_batch(reinterpret_cast<const KsatJob *>(d + L.off_jobs),
+                                               reinterpret_cast<const int2 *>(d + L.off_items), L.n_items, L.thr_num,
+                                               L.thr_den, L.expand, s));
+        break;
+    default:
+        HIP_OR_FAIL(qap_launch_backbone_batch(reinterpret_cast<const QapJob *>(d + L.off_jobs),
+                                              reinterpret_cast<const int2 *>(d + L.off_items), L.n_items, L.thr_num,
+                                              L.thr_den, s));
+        break;
+    }
+    return NMC_OK;
+}
+
+void drop_graph(nmc_batch *B) {
+    if (B->exec) {
+        (void)hipGraphExecDestroy(B->exec);
+        B->exec = nullptr;
+    }
+    B->exec_launches.clear();
+}
+
+int run_plans(nmc_batch *B, const std::vector<nmc_plan> &plans, const int64_t *targets, bool use_graph,
+              hipStream_t s) {
+    const size_t ns = B->sets.size();
+    std::vector<std::vector<SetPhase>> ph(ns);
+    for (size_t i = 0; i < ns; ++i) {
+        const int rc = validate_plan(plans[i], i);
+        if (rc)
+            return rc;
+        ph[i] = plan_phases(plans[i]);
+        const uint64_t total = (uint64_t)plans[i].anneal_sweeps + (uint64_t)plans[i].rounds * plans[i].reanneal_sweeps;
+        if ((uint64_t)B->sets[i]->sweeps_done + total > 0xFFFFFFFFull)
+            return fail(NMC_ERR_INVALID, "set %zu: sweep counter would pass 2^32 - 1", i);
+    }
+    // two passes: sizes first (device base unknown), then the real layout
+    Blob blob;
+    std::vector<BatchLaunch> launches;
+    int rc = build_plans(B, ph, plans, targets, nullptr, blob, launches);
+    if (rc)
+        return rc;
+    if (blob.host.size() > B->cap)
+        drop_graph(B);  // the buffer moves: a captured graph would point at the old one
+    rc = ensure_batch_mem(B, blob.host.size());
+    if (rc)
+        return rc;
+    blob.host.clear();
+    launches.clear();
+    rc = build_plans(B, ph, plans, targets, B->dev, blob, launches);
+    if (rc)
+        return rc;
+    // the descriptors are data: a graph captured for the same launch list
+    // reads this call's upload (ordered before the launch on the stream)
+    HIP_OR_FAIL(hipMemcpyAsync(B->dev, blob.host.data(), blob.host.size(), hipMemcpyHostToDevice, s));
+    double attempts = 0;
+    for (const BatchLaunch &L : launches)
+        attempts += L.attempts;
+    ScopedEvents evs;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (B->profiling) {
+        HIP_OR_FAIL(evs.create(&e0));
+        HIP_OR_FAIL(evs.create(&e1));
+    }
+    if (use_graph) {
+        if (!(B->exec && B->exec_dev == B->dev && B->exec_launches == launches)) {
+            drop_graph(B);
+            if (!B->cap_stream)
+                HIP_OR_FAIL(hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking));
+            HIP_OR_FAIL(hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal));
+            int erc = NMC_OK;
+            for (size_t l = 0; l < launches.size() && !erc; ++l)
+                erc = enqueue_plan_launch(B, launches[l], B->cap_stream);
+            hipGraph_t graph = nullptr;
+            const hipError_t ee = hipStreamEndCapture(B->cap_stream, &graph);
+            if (erc) {
+                if (graph)
+                    (void)hipGraphDestroy(graph);
+                return erc;
+            }
+            if (ee != hipSuccess)
+                return fail(NMC_ERR_DEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(ee));
+            hipGraphExec_t exec = nullptr;
+            const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ei != hipSuccess)
+                return fail(NMC_ERR_DEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(ei));
+            B->exec = exec;
+            B->exec_dev = B->dev;
+            B->exec_launches = launches;
+            B->graph_captures++;
+        } else {
+            B->graph_replays++;
+        }
+        if (B->profiling)
+            HIP_OR_FAIL(hipEventRecord(e0, s));
+        const hipError_t el = hipGraphLaunch(B->exec, s);
+        if (B->profiling && el == hipSuccess)
+            HIP_OR_FAIL(hipEventRecord(e1, s));
+        const hipError_t es = hipStreamSynchronize(s);
+        if (el != hipSuccess || es != hipSuccess) {
+            drop_graph(B);
+            return fail(NMC_ERR_DEVICE, "graph launch failed: %s", hipGetErrorString(el != hipSuccess ? el : es));
+        }
+    } else {
+        if (B->profiling)
+            HIP_OR_FAIL(hipEventRecord(e0, s));
+        for (const BatchLaunch &L : launches) {
+            rc = enqueue_plan_launch(B, L, s);
+            if (rc)
+                return rc;
+        }
+        if (B->profiling)
+            HIP_OR_FAIL(hipEventRecord(e1, s));
+        // the descriptor blob must outlive the kernels that read it
+        HIP_OR_FAIL(hipStreamSynchronize(s));
+    }
+    if (B->profiling) {
+        float ms = 0;
+        HIP_OR_FAIL(hipEventElapsedTime(&ms, e0, e1));
+        B->prof_ms += ms;
+        B->prof_launches += 1;
+        B->prof_attempts += attempts;
+    }
+    for (size_t i = 0; i < ns; ++i) {
+        nmc_replicas *P = B->sets[i];
+        P->sweeps_done += (uint32_t)(plans[i].anneal_sweeps + (int64_t)plans[i].rounds * plans[i].reanneal_sweeps);
+        if (plans[i].rounds > 0)
             P->has_backbone = true;
     }
     return ok();
@@ -2560,10 +2945,12 @@ int nmc_batch_set_members(nmc_batch *B, nmc_replicas *const *sets, int32_t n_set
 void nmc_batch_free(nmc_batch *B) {
     if (!B)
         return;
-    if (B->dev) {
+    if (B->dev || B->exec)
         (void)hipDeviceSynchronize();
+    if (B->exec)
+        (void)hipGraphExecDestroy(B->exec);
+    if (B->dev)
         (void)hipFree(B->dev);
-    }
     if (B->cap_stream)
         (void)hipStreamDestroy(B->cap_stream);
     if (B->lbp_jobs) {
@@ -2660,7 +3047,7 @@ int nmc_batch_anneal(nmc_batch *B, const double *beta, int32_t n_classes, int32_
     if (B->sets.empty())
         return ok();
     try {
-        return run_batch(B, {PhaseSpec{beta, n_classes, n_sweeps, profile}}, {0}, 0, 0, 0, targets, false,
+        return run_batch(B, {PhaseSpec{beta, n_classes, n_sweeps, profile}}, {0}, 0, 0, 0, targets,
                          as_stream(stream));
     } catch (const std::bad_alloc &) {
         return fail(NMC_ERR_CAPACITY, "host allocation failed");
@@ -2706,45 +3093,37 @@ int nmc_batch_estimate_backbone(nmc_batch *B, int32_t thr_num, int32_t thr_den, 
 int nmc_batch_run_plan(nmc_batch *B, const nmc_plan *plan, const int64_t *targets, int32_t use_graph, void *stream) {
     if (!B || !plan)
         return fail(NMC_ERR_INVALID, "NULL argument");
-    if (plan->rounds < 0 || plan->anneal_sweeps < 0 || plan->reanneal_sweeps < 0)
-        return fail(NMC_ERR_INVALID, "negative plan field");
-    if (plan->rounds > 0 && (plan->thr_den <= 0 || plan->thr_num <= 0 || plan->thr_num > plan->thr_den))
-        return fail(NMC_ERR_INVALID, "need 0 < thr_num <= thr_den");
     if (B->sets.empty())
         return ok();
     try {
-        if (plan->chunk_sweeps < 0)
-            return fail(NMC_ERR_INVALID, "chunk_sweeps must be >= 0");
-        // each phase splits into launches of at most chunk_sweeps sweeps, so
-        // every set advances in lockstep; the schedule rows are cut accordingly
-        std::vector<std::vector<double>> pieces;
-        std::vector<PhaseSpec> phases;
-        std::vector<char> bb_before;
-        auto add_phase = [&](const double *beta, int32_t nc, int32_t S, int32_t profile, bool bb) {
-            const int32_t K = plan->chunk_sweeps > 0 ? plan->chunk_sweeps : std::max(S, 1);
-            for (int32_t s0 = 0; s0 < S || (S == 0 && s0 == 0); s0 += K) {
-                const int32_t len = std::min(K, S - s0);
-                std::vector<double> b((size_t)nc * std::max(len, 0));
-                for (int32_t c = 0; c < nc; ++c)
-                    for (int32_t t = 0; t < len; ++t)
-                        b[(size_t)c * len + t] = beta[(size_t)c * S + s0 + t];
-                pieces.push_back(std::move(b));
-                phases.push_back(PhaseSpec{nullptr, nc, std::max(len, 0), profile});
-                bb_before.push_back(bb && s0 == 0);
-                if (S == 0)
-                    break;
-            }
-        };
-        add_phase(plan->anneal_beta, 1, plan->anneal_sweeps, NMC_PROFILE_HOMOGENEOUS, false);
-        for (int32_t r = 0; r < plan->rounds; ++r)
-            add_phase(plan->reanneal_beta, 2, plan->reanneal_sweeps, NMC_PROFILE_BACKBONE, true);
-        for (size_t p = 0; p < phases.size(); ++p)
-            phases[p].beta = pieces[p].data();
-        return run_batch(B, phases, bb_before, plan->thr_num, plan->thr_den, plan->expand ? 1 : 0, targets,
-                         use_graph != 0, as_stream(stream));
+        const std::vector<nmc_plan> plans(B->sets.size(), *plan);
+        return run_plans(B, plans, targets, use_graph != 0, as_stream(stream));
     } catch (const std::bad_alloc &) {
         return fail(NMC_ERR_CAPACITY, "host allocation failed");
     }
+}
+
+int nmc_batch_run(nmc_batch *B, const nmc_plan *plans, const int64_t *targets, int32_t use_graph, void *stream) {
+    if (!B || (!plans && !B->sets.empty()))
+        return fail(NMC_ERR_INVALID, "NULL argument");
+    if (B->sets.empty())
+        return ok();
+    try {
+        const std::vector<nmc_plan> v(plans, plans + B->sets.size());
+        return run_plans(B, v, targets, use_graph != 0, as_stream(stream));
+    } catch (const std::bad_alloc &) {
+        return fail(NMC_ERR_CAPACITY, "host allocation failed");
+    }
+}
+
+int nmc_batch_graph_info(const nmc_batch *B, int64_t *captures, int64_t *replays) {
+    if (!B)
+        return fail(NMC_ERR_INVALID, "NULL batch");
+    if (captures)
+        *captures = B->graph_captures;
+    if (replays)
+        *replays = B->graph_replays;
+    return ok();
 }
 
 int nmc_batch_set_profiling(nmc_batch *B, int32_t enable) {

@@ -149,6 +149,8 @@ _SIGS = {
     "nmc_batch_lbp_backbone": ([_P, _P, _I32, ctypes.POINTER(LbpConfig), _P, _P], ctypes.c_int),
     "nmc_batch_estimate_backbone": ([_P, _I32, _I32, _I32, _P], ctypes.c_int),
     "nmc_batch_run_plan": ([_P, ctypes.POINTER(Plan), _P, _I32, _P], ctypes.c_int),
+    "nmc_batch_run": ([_P, _P, _P, _I32, _P], ctypes.c_int),
+    "nmc_batch_graph_info": ([_P, _P, _P], ctypes.c_int),
     "nmc_batch_set_members": ([_P, _P, _I32], ctypes.c_int),
     "nmc_batch_step": ([_P, _P, _I32, _I32, _I32, _I32, _P, _P], ctypes.c_int),
     "nmc_batch_set_profiling": ([_P, _I32], ctypes.c_int),
@@ -546,6 +548,34 @@ class Batch:
                     int(bool(expand)), int(chunk_sweeps))
         t = self._targets(targets)
         _check(lib().nmc_batch_run_plan(self._h, ctypes.byref(plan), _ptr(t), int(bool(use_graph)), _stream(stream)))
+
+    def run(self, plans, targets=None, use_graph=True, stream=None):
+        """nmc_batch_run: one plan per member set.  Each plan is a dict with
+        anneal_beta (S_a values), rounds, reanneal_beta (2 x S_r: cold row,
+        hot row; may be omitted when rounds = 0) and optionally thr_num,
+        thr_den, expand, chunk_sweeps."""
+        plans = list(plans)
+        if len(plans) != len(self.sets):
+            raise NmcError(-1, f"{len(plans)} plans for {len(self.sets)} sets")
+        keep = []
+        arr = (Plan * max(1, len(plans)))()
+        for i, p in enumerate(plans):
+            a = np.ascontiguousarray(np.asarray(p["anneal_beta"], np.float64).reshape(-1))
+            rb = p.get("reanneal_beta")
+            r = np.ascontiguousarray(np.asarray(rb if rb is not None else np.zeros((2, 0)), np.float64).reshape(2, -1))
+            keep += [a, r]
+            arr[i] = Plan(a.ctypes.data, a.size, int(p.get("rounds", 0)), r.ctypes.data, r.shape[1],
+                          int(p.get("thr_num", 9)), int(p.get("thr_den", 10)), int(bool(p.get("expand", True))),
+                          int(p.get("chunk_sweeps", 0)))
+        t = self._targets(targets)
+        _check(lib().nmc_batch_run(self._h, ctypes.cast(arr, ctypes.c_void_p), _ptr(t), int(bool(use_graph)),
+                                   _stream(stream)))
+
+    def graph_info(self):
+        """(graphs captured, calls that replayed the kept graph)."""
+        c, r = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().nmc_batch_graph_info(self._h, ctypes.byref(c), ctypes.byref(r)))
+        return c.value, r.value
 
     def set_members(self, sets):
         """Replace the member sets (same rules as the constructor)."""

@@ -61,8 +61,9 @@ def test_batched_calls_equal_individual_calls():
     alone = _make(mix)
     batched = _make(mix)
     a_beta, r_beta = _sched()
-    # the QAP sets take their own beta scale; a batch shares one schedule, so
-    # run QAP and k-SAT in separate batches of the same call sequence
+    # nmc_batch_anneal takes one schedule for every set, so the QAP sets (beta
+    # in cost units) get a batch of their own here; one batch with a schedule
+    # per set is nmc_batch_run (test_per_set_plans_mixed_batch)
     groups = {"ksat": [i for i, m in enumerate(mix) if m[0] == "ksat"],
               "qap": [i for i, m in enumerate(mix) if m[0] == "qap"]}
     for kind, idx in groups.items():
@@ -172,3 +173,110 @@ def test_full_batch_of_256_sampled_against_oracle():
         assert (be["best_per_replica"] == orep.best).all()
         assert (be["first_hit"] == orep.first_hit).all()
         assert s_.sweeps_done() == orep.sweeps_done
+
+
+def _own_plans(mix, seed):
+    """A different plan for every set of the mix: own anneal length, beta
+    units and range, rounds, reanneal length, backbone rule and chunk size."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shapes = [(24, 2, 10, 0, (9, 10, True)), (17, 1, 6, 7, (3, 4, False)), (30, 0, 0, 5, (9, 10, True)),
+              (9, 3, 4, 0, (1, 2, True)), (20, 1, 8, 4, (9, 10, False)), (12, 2, 5, 0, (9, 10, True)),
+              (15, 1, 3, 6, (2, 3, False))]
+    plans = []
+    for (kind, _, _, _), (sa, rounds, sr, chunk, (num, den, ex)) in zip(mix, shapes):
+        sc = _scale(kind) * float(rng.uniform(0.7, 1.4))
+        b1 = float(rng.uniform(2.5, 4.5))
+        a = instances.linear_schedule(0.1, b1, sa) * sc
+        r = instances.profile_schedule(np.full(sr, b1), instances.linear_schedule(0.5, b1, sr)) * sc
+        plans.append(dict(anneal_beta=a, rounds=rounds, reanneal_beta=r if rounds else None, thr_num=num,
+                          thr_den=den, expand=ex, chunk_sweeps=chunk))
+    return plans
+
+
+def _run_alone(s, plan, target):
+    s.anneal(plan["anneal_beta"][None, :], target=target)
+    for _ in range(plan["rounds"]):
+        s.estimate_backbone(plan["thr_num"], plan["thr_den"], plan["expand"])
+        if plan["reanneal_beta"].shape[1]:
+            s.reanneal(plan["reanneal_beta"], "backbone", target=target)
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_per_set_plans_mixed_batch(use_graph):
+    """k-SAT and QAP sets, each with its own schedule, in one nmc_batch_run
+    call (one HIP graph when use_graph): every set equals its own call
+    sequence run alone; a second and a third call of the same shape replay
+    the kept graph (the third with other betas and targets)."""
+    say(f"case: per-set plans, 5 k-SAT + 2 QAP, graph={use_graph}")
+    mix = _mix(53)
+    alone = _make(mix)
+    batched = _make(mix)
+    plans = _own_plans(mix, 1)
+    targets = [40, 25, 30, 8, 0, 0, 0]
+    b = nmc.Batch(batched)
+    b.run(plans, targets=targets, use_graph=use_graph)
+    for s, p, t in zip(alone, plans, targets):
+        _run_alone(s, p, t)
+    for x, y in zip(alone, batched):
+        _compare(x, y)
+    b.run(plans, targets=targets, use_graph=use_graph)
+    for s, p, t in zip(alone, plans, targets):
+        _run_alone(s, p, t)
+    plans2 = _own_plans(mix, 2)
+    targets2 = [t + 3 for t in targets]
+    b.run(plans2, targets=targets2, use_graph=use_graph)
+    for s, p, t in zip(alone, plans2, targets2):
+        _run_alone(s, p, t)
+    for x, y in zip(alone, batched):
+        _compare(x, y)
+    assert b.graph_info() == ((1, 2) if use_graph else (0, 0))
+    # another shape (one set's plan longer) captures a new graph
+    plans2[0]["anneal_beta"] = np.concatenate([plans2[0]["anneal_beta"], [1.0]])
+    b.run(plans2, targets=targets2, use_graph=use_graph)
+    for s, p, t in zip(alone, plans2, targets2):
+        _run_alone(s, p, t)
+    for x, y in zip(alone, batched):
+        _compare(x, y)
+    assert b.graph_info() == ((2, 2) if use_graph else (0, 0))
+    b.free()
+
+
+def test_per_set_plans_against_oracle():
+    """One graph over a k-SAT set and a QAP set with different schedules and
+    rounds; both followed by the oracle alone, bit for bit."""
+    say("case: per-set plans vs oracle")
+    n, R = 900, 36
+    cp, lits = instances.gen_ksat(n, "9.8", 4, 71)
+    F, D = instances.gen_qap(31, 72)
+    ks = nmc.Replicas(nmc.Instance.ksat(n, cp, lits).bind(), R, 73)
+    qs = nmc.Replicas(nmc.Instance.qap(F, D).bind(), 20, 74)
+    kp = dict(anneal_beta=instances.linear_schedule(0.1, 4.0, 30), rounds=2,
+              reanneal_beta=instances.profile_schedule(np.full(12, 4.0), instances.linear_schedule(0.5, 4.0, 12)),
+              thr_num=9, thr_den=10, expand=True, chunk_sweeps=8)
+    sc = 3e-4
+    qp = dict(anneal_beta=instances.linear_schedule(0.1, 4.0, 21) * sc, rounds=1,
+              reanneal_beta=instances.profile_schedule(np.full(9, 4.0), instances.linear_schedule(0.5, 4.0, 9)) * sc,
+              thr_num=3, thr_den=4, expand=False, chunk_sweeps=5)
+    b = nmc.Batch([ks, qs])
+    b.run([kp, qp], targets=[35, 0], use_graph=True)
+    ok = oracle.KSat(n, cp, lits)
+    _, order, _ = ok.color(0)
+    ko = oracle.KSatReplicas(ok, R, 73, order, threads=threads())
+    ko.anneal(kp["anneal_beta"][None, :], target=35)
+    for _ in range(2):
+        cls, _ = ko.backbone(9, 10, True)
+        ko.anneal(kp["reanneal_beta"], class_of=cls, target=35)
+    qo = oracle.QapReplicas(oracle.Qap(F, D), 20, 74, threads=threads())
+    qo.anneal(qp["anneal_beta"][None, :], target=0)
+    cls, _ = qo.backbone(3, 4)
+    qo.anneal(qp["reanneal_beta"], class_of=cls, target=0)
+    for s, x, best_x, e, best, fh, sw in ((ks, ko.x, ko.best_x, ko.energy, ko.best, ko.first_hit, ko.sweeps_done),
+                                          (qs, qo.perm, qo.best_perm, qo.cost, qo.best, qo.first_hit,
+                                           qo.sweeps_done)):
+        assert (s.get_state() == x).all()
+        assert (s.get_state("best") == best_x).all()
+        be = s.best_energy()
+        assert (be["energy"] == e).all() and (be["best_per_replica"] == best).all()
+        assert (be["first_hit"] == fh).all()
+        assert s.sweeps_done() == sw
+    b.free()
