@@ -51,19 +51,34 @@ READS_PER_SLOT = 3.0
 READS_PER_VAR = 1.0
 
 
-def ksat_roofline(kt, n_clauses, traffic=None):
+HBM_PEAK = 8.0e12  # bytes/s, published MI355X HBM3E figure
+
+
+def ksat_roofline(kt, n_clauses, acceptance, traffic=None):
     """Roofline of ksat_sweep_kernel from its HIP-event time `kt` on the
-    N-variable, n_clauses-clause k-SAT instance: bound by
-    LDS byte gathers (algorithmic reads per attempt = (3 deg + 1) / 4 against
-    one lane read per bank per clock), with the VALU side beside it."""
+    N-variable, n_clauses-clause k-SAT instance.  Primary (the scope table's
+    measurement model): the per-clause-counter formulation's algorithmic HBM
+    bytes, (deg + 1)(1 + a) per attempt with a the measured acceptance rate,
+    against 8 TB/s.  Beside it the model of this kernel, which keeps the
+    spins in LDS: LDS byte gathers ((3 deg + 1) / 4 per attempt against one
+    lane read per bank per clock) and VALU lane operations."""
     deg_mean = K * n_clauses / N
     att_s = kt["attempts"] / (kt["ms"] / 1000.0)
+    per_att = (deg_mean + 1.0) * (1.0 + acceptance)
+    launches = max(1, kt["launches"])
     reads = att_s * (READS_PER_SLOT * deg_mean + READS_PER_VAR) / 4.0
     ops = att_s * (OPS_PER_SLOT * deg_mean + OPS_PER_VAR) / 4.0
-    return {"bound": "lds", "achieved": reads / 1e12, "peak": LDS_LANE_READS / 1e12,
-            "unit": "T lane-reads/s", "frac": reads / LDS_LANE_READS, "traffic": traffic,
-            "kernel": "ksat_sweep_kernel", "kernel_ms_per_launch": kt["ms"] / max(1, kt["launches"]),
+    hbm = att_s * per_att
+    return {"bound": "hbm", "achieved": hbm / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "frac": hbm / HBM_PEAK, "survey_frac": hbm / HBM_PEAK, "traffic": traffic,
+            "bytes_per_attempt": per_att, "acceptance": acceptance, "mean_degree": deg_mean,
+            "algorithmic_bytes_per_launch": per_att * kt["attempts"] / launches,
+            "model": "(deg + 1)(1 + a) bytes per attempt (per-clause counters and the spin byte, "
+                     "written back on accept) x kernel attempts/s; a = accepted flips / attempts",
+            "kernel": "ksat_sweep_kernel", "kernel_ms_per_launch": kt["ms"] / launches,
             "kernel_attempts_per_s": att_s, "launches": kt["launches"],
+            "lds": {"achieved": reads / 1e12, "peak": LDS_LANE_READS / 1e12, "unit": "T lane-reads/s",
+                    "frac": reads / LDS_LANE_READS},
             "valu": {"achieved": ops / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "T lane-op/s",
                      "frac": ops / PEAK_LANE_OPS}}
 
@@ -110,13 +125,13 @@ def run_path(inst, seed, target, nmc, stream=None, profile=False):
     return rep, be
 
 
-def bench_batch(nmc, torch, seed):
-    """Batched NMC on 256 mixed k-SAT instances (k in {3,4}, N log-uniform in
-    [1000, 20000], replicas 64..512 by N) in one graph-captured plan, against
-    plain simulated annealing launched once per instance."""
+def bench_batch(nmc, torch, seed, n_instances=256):
+    """Batched NMC on mixed k-SAT instances (256 by default; k in {3,4}, N
+    log-uniform in [1000, 20000], replicas 64..512 by N) in one graph-captured
+    plan, against plain simulated annealing launched once per instance."""
     S_A, RND, S_R, CHUNK = 1000, 2, 500, 50
     S_TOT = S_A + RND * S_R
-    mix = instances.batch_mix(256, seed)
+    mix = instances.batch_mix(256, seed)[:n_instances]
     insts = []
     for m in mix:
         cp, lits = instances.gen_ksat(m["n"], m["alpha"], m["k"], m["seed"])
@@ -181,6 +196,13 @@ def bench_batch(nmc, torch, seed):
     out["batched_nmc"] = summarize(wall, attempts, [None if (fh := s.best_energy()["first_hit"])[fh >= 0].size == 0
                                                     else float(fh[fh >= 0].min()) / S_TOT * wall for s in sets])
     bn.free()
+    per, bnm, bsa = out["per_instance_sa"], out["batched_nmc"], out["batched_sa"]
+    out["ttt"] = {"rule": "seconds until every instance has a replica at or below its target (10th percentile of "
+                          "a calibration plain-SA run); one launch per instance is plain SA",
+                  "per_instance_sa_s": per["ttt_all_s"], "batched_sa_s": bsa["ttt_all_s"],
+                  "batched_nmc_s": bnm["ttt_all_s"],
+                  "batched_nmc_speedup": (per["ttt_all_s"] / bnm["ttt_all_s"]
+                                          if per["ttt_all_s"] and bnm["ttt_all_s"] else None)}
     return out
 
 
@@ -202,9 +224,11 @@ def qap_beta_scale(F, D, seed, samples=100000):
     return 1.0 / float(np.median(d))
 
 
-def bench_qap(nmc, torch, seed, sweeps_only=0, sweeps_offset=0):
+def bench_qap(nmc, torch, seed, sweeps_only=0, sweeps_offset=0, curve=0):
     """QAP NMC: n = 100, 4096 replicas, anneal 5000 sweeps of 4950 proposed
-    swaps, then 2 x (frequency backbone -> reanneal 1000)."""
+    swaps, then 2 x (frequency backbone -> reanneal 1000).  curve > 0: the
+    same schedule in launches of `curve` sweeps, each with its acceptance
+    rate and kernel rate (the rate-versus-acceptance curve)."""
     n, Rq, S_A, RND, S_R = 100, 4096, 5000, 2, 1000
     F, D = instances.gen_qap(n, seed)
     sc = qap_beta_scale(F, D, seed + 1)
@@ -216,9 +240,35 @@ def bench_qap(nmc, torch, seed, sweeps_only=0, sweeps_offset=0):
     pairs = n * (n - 1) // 2
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    segments = []
+
+    def seg(beta, profile, start):
+        # one launch; its acceptance and kernel rate
+        rep.kernel_time(reset=True)
+        rep.accept_count(reset=True)
+        if profile:
+            rep.reanneal(beta, "backbone")
+        else:
+            rep.anneal(beta)
+        k = rep.kernel_time()
+        segments.append({"sweep": start, "sweeps": beta.shape[-1],
+                         "beta_units": float(np.atleast_2d(beta)[-1].mean() / sc),
+                         "acceptance": rep.accept_count() / (float(Rq) * pairs * beta.shape[-1]),
+                         "kernel_G_per_s": k["attempts"] / (k["ms"] / 1e3) / 1e9, "kernel_ms": k["ms"]})
+        return k
+
     if sweeps_only:
         rep.anneal(a_beta[None, sweeps_offset:sweeps_offset + sweeps_only])
         S_tot = min(sweeps_only, max(0, S_A - sweeps_offset))
+    elif curve:
+        ms = 0.0
+        for s0 in range(0, S_A, curve):
+            ms += seg(a_beta[None, s0:s0 + curve], False, s0)["ms"]
+        for r in range(RND):
+            rep.estimate_backbone_device(9, 10, False)
+            for s0 in range(0, S_R, curve):
+                ms += seg(r_beta[:, s0:s0 + curve], True, S_A + r * S_R + s0)["ms"]
+        S_tot = S_A + RND * S_R
     else:
         rep.anneal(a_beta[None, :])
         for _ in range(RND):
@@ -227,7 +277,13 @@ def bench_qap(nmc, torch, seed, sweeps_only=0, sweeps_offset=0):
         S_tot = S_A + RND * S_R
     be = rep.best_energy()
     wall = time.perf_counter() - t0
-    kt = rep.kernel_time()
+    if curve:
+        kt = {"ms": sum(x["kernel_ms"] for x in segments), "launches": len(segments),
+              "attempts": float(Rq) * pairs * S_tot}
+        accepted = sum(x["acceptance"] * float(Rq) * pairs * x["sweeps"] for x in segments)
+    else:
+        kt = rep.kernel_time()
+        accepted = rep.accept_count()
     props = float(Rq) * pairs * S_tot
     kps = kt["attempts"] / (kt["ms"] / 1000.0)
     # LDS byte reads per proposal: F[b][k] and the gather D[p_b][p_k] for every k
@@ -237,7 +293,12 @@ def bench_qap(nmc, torch, seed, sweeps_only=0, sweeps_offset=0):
     roofline = {"bound": "lds", "achieved": achieved / 1e12, "peak": LDS_LANE_READS / 1e12,
                 "unit": "T lane-reads/s", "frac": achieved / LDS_LANE_READS, "traffic": None,
                 "kernel": "qap_sweep_kernel", "kernel_ms_per_launch": kt["ms"] / max(1, kt["launches"]),
-                "launches": kt["launches"]}
+                "launches": kt["launches"],
+                # the scope table's model: ~3(n - 2) LDS lane-accesses per proposal
+                # (98 permutation bytes + 196 distance gathers at n = 100) against
+                # one lane access per bank per clock: about 67 G proposals/s
+                "survey_bound_proposals_per_s": LDS_LANE_READS / (3.0 * (n - 2)),
+                "survey_frac": kps * 3.0 * (n - 2) / LDS_LANE_READS}
     if not sweeps_only:
         peaks = measured_peaks(nmc, torch)
         roofline["frac_of_measured_lds_distinct"] = roofline["achieved"] / peaks["lds_distinct_T_per_s"]
@@ -245,7 +306,8 @@ def bench_qap(nmc, torch, seed, sweeps_only=0, sweeps_offset=0):
         roofline["measured_peaks"] = peaks
     return {"proposals": props, "wall_s": wall, "proposals_per_s": props / wall,
             "kernel_ms": kt["ms"], "kernel_proposals_per_s": kps, "roofline": roofline,
-            "beta_unit": sc, "best_cost": be["best"], "sweeps": S_tot}
+            "acceptance": accepted / props, "beta_unit": sc, "best_cost": be["best"], "sweeps": S_tot,
+            "curve": segments or None}
 
 
 LBP_CFG = dict(beta=1.0, lambda0=4.0, lambda_ratio=0.8, lambda_min=1e-3, max_iter=100, tol=1e-8, p_min=-2.0)
@@ -327,7 +389,7 @@ def bench_lbp(nmc, torch, seed):
     bytes_it = LBP_BYTES_PER_EDGE * edges + LBP_BYTES_PER_VAR * nvar
     ms_it = lt["ms"] / max(1, lt["iterations"])
     att = float(R) * N * (S_ANNEAL + ROUNDS * S_RE)
-    roofline = ksat_roofline(kt, M)
+    roofline = ksat_roofline(kt, M, prep.accept_count() / att)
     lbp_roofline = {"bound": "hbm", "achieved": bytes_it / (ms_it / 1000.0) / 1e9, "peak": 8000.0, "unit": "GB/s",
                     "frac": bytes_it / (ms_it / 1000.0) / 8e12, "traffic": None,
                     "kernel": "lbp_var_kernel + lbp_clause_kernel (one message iteration)",
@@ -478,11 +540,12 @@ def bench_apt(nmc, torch, seed, rounds, sweeps_per_round):
     # sweep-kernel time of the tempering rounds from HIP events (separate pass)
     prep = nmc.Replicas(inst, Rp, seed)
     prep.anneal(np.full((1, 50), betas[0]))
+    prep.accept_count(reset=True)
     prep.set_profiling(True)
     prep.pt_run(betas, min(rounds, 500), sweeps_per_round)
     kt = prep.kernel_time()
     rate = acc / np.maximum(att, 1)
-    roofline = ksat_roofline(kt, M)
+    roofline = ksat_roofline(kt, M, prep.accept_count() / (float(Rp) * N * min(rounds, 500) * sweeps_per_round))
     qap = bench_apt_qap(nmc, torch, seed)
     return {"attempts": att_ladder + att_pt, "wall_s": t_ladder + t_pt, "qap": qap,
             "attempts_per_s": (att_ladder + att_pt) / (t_ladder + t_pt),
@@ -497,6 +560,10 @@ def bench_apt(nmc, torch, seed, rounds, sweeps_per_round):
 
 
 SERVE_RATE, SERVE_SECONDS, SERVE_BUDGET_S = 50.0, 60.0, 2.0
+# the default run's short versions of the served, batched and C1 workloads
+SHORT_SERVE_SECONDS = 8.0
+SHORT_BATCH_INSTANCES = 64
+C1_REPEATS = 20
 SERVE_SCHED = (150, 2, 50)  # anneal sweeps, rounds, reanneal sweeps per request
 SERVE_CHUNK = 25
 SERVE_KSAT_GRID = (2000, 4500, 10000, 22400, 50000)
@@ -541,16 +608,24 @@ def serve_calibration(nmc, seed):
     return {"ksat_density": kinfo, "qap_ratio": [q[0] for q in qinfo], "qap_beta_scale": [q[1] for q in qinfo]}
 
 
-def bench_serve(nmc, torch, seed, seconds):
-    """Served NMC: a Poisson stream of k-SAT and QAP requests into the
-    continuous-batching server; latency from submission to the round end
-    where the request reached its target."""
-    from multiprocessing import Pool
+def serve_requests(seed, seconds):
+    """The request stream and its instances.  Generated by a pool of worker
+    processes, so this must run before anything in the process touches the
+    GPU: a process that has initialised HIP must not fork."""
+    from multiprocessing import get_context
 
-    cal = serve_calibration(nmc, seed)
     mix = instances.serve_mix(SERVE_RATE, seconds, seed)
-    with Pool(max(1, min(16, os.cpu_count() or 1))) as pool:
+    with get_context("fork").Pool(max(1, min(16, os.cpu_count() or 1))) as pool:
         data = pool.map(_serve_gen, mix, chunksize=8)
+    return mix, data
+
+
+def bench_serve(nmc, torch, seed, seconds, pre, n_cap=400):
+    """Served NMC: a Poisson stream of k-SAT and QAP requests (`pre`, from
+    serve_requests) into the continuous-batching server; latency from
+    submission to the round end where the request reached its target."""
+    cal = serve_calibration(nmc, seed)
+    mix, data = pre
     lk = np.log(np.asarray(SERVE_KSAT_GRID, np.float64))
     reqs = []
     for m, d in zip(mix, data):
@@ -576,7 +651,7 @@ def bench_serve(nmc, torch, seed, seconds):
                               target=target, budget_s=SERVE_BUDGET_S)
 
     # capacity: the first requests of the stream submitted at once (closed loop)
-    n_cap = min(len(reqs), 400)
+    n_cap = min(len(reqs), n_cap)
     srv = nmc.Server(chunk_sweeps=SERVE_CHUNK, loader_threads=loaders)
     cap_ids = [submit(srv, *q) for q in reqs[:n_cap]]
     srv.wait_idle(300.0)
@@ -631,7 +706,7 @@ def bench_serve(nmc, torch, seed, seconds):
     return out
 
 
-def bench_c1(nmc, torch, seed):
+def bench_c1(nmc, torch, seed, repeats=1):
     """Plain SA on random 4-SAT N = 200, M = 1920, 64 replicas, 1000 sweeps
     (beta 0.1 -> 4.0): the latency of the whole anneal, and the rate per
     busy CU (16 workgroups of 4 replicas) against one CU's LDS read bound
@@ -643,14 +718,22 @@ def bench_c1(nmc, torch, seed):
     sched = instances.linear_schedule(BETA0, BETA1, S)[None, :]
     warm = nmc.Replicas(inst, R, seed + 1)
     warm.anneal(sched[:, :20])
-    rep = nmc.Replicas(inst, R, seed)
-    rep.set_profiling(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    rep.anneal(sched)
-    be = rep.best_energy()
-    wall = time.perf_counter() - t0
-    kt = rep.kernel_time()
+    walls, kms = [], []
+    for k in range(repeats):
+        # one solve: fresh replicas (own seed), the whole anneal, the best energy
+        rep = nmc.Replicas(inst, R, seed + 10 * k)
+        rep.set_profiling(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep.anneal(sched)
+        be = rep.best_energy()
+        walls.append(time.perf_counter() - t0)
+        kms.append(rep.kernel_time()["ms"])
+        if k == 0:
+            be0, kt = be, rep.kernel_time()
+        del rep
+    be = be0
+    wall = walls[0]
     att = float(R) * n * S
     groups = (R + 3) // 4
     deg = K * m / n
@@ -659,7 +742,12 @@ def bench_c1(nmc, torch, seed):
     return {"n_vars": n, "n_clauses": m, "replicas": R, "sweeps": S, "colors": inst.info.n_colors,
             "latency_ms": kt["ms"], "wall_ms": wall * 1e3, "attempts_per_s": att / (kt["ms"] / 1e3),
             "busy_cus": groups, "per_cu_attempts_per_s": per_cu, "cu_lds_bound_attempts_per_s": cu_bound,
-            "frac_of_one_cu": per_cu / cu_bound, "best_energy": int(be["best"])}
+            "frac_of_one_cu": per_cu / cu_bound, "best_energy": int(be["best"]),
+            "repeats": repeats,
+            "latency_p50_ms": float(np.percentile(kms, 50)), "latency_p99_ms": float(np.percentile(kms, 99)),
+            "wall_p50_ms": float(np.percentile(walls, 50)) * 1e3, "wall_p99_ms": float(np.percentile(walls, 99)) * 1e3,
+            "latency_rule": "kernel time of one solve's sweep launch (HIP events); wall = call to best energy "
+                            "read back, per solve with fresh replicas"}
 
 
 def measured_peaks(nmc, torch):
@@ -736,6 +824,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ttt", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default workload only: skip the C1 latency, short batched and short served sections")
     ap.add_argument("--block-threads", type=int, default=0)
     ap.add_argument("--class-cap", type=int, default=CLASS_CAP)
     ap.add_argument("--workload", choices=["nmc", "batch", "qap", "serve", "apt", "lbp", "alg1", "c1"], default="nmc",
@@ -749,6 +839,9 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=SERVE_SECONDS)
     ap.add_argument("--sweeps-only", type=int, default=0,
                     help="only time one homogeneous anneal of this many sweeps (for counter profiles) and exit")
+    ap.add_argument("--qap-curve", type=int, default=0,
+                    help="with --workload qap: run the schedule in launches of this many sweeps and report "
+                         "acceptance and kernel rate per launch")
     ap.add_argument("--sweeps-offset", type=int, default=0,
                     help="with --workload qap --sweeps-only: start that many sweeps into the anneal schedule")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -766,6 +859,14 @@ def main():
     BLOCK_THREADS = args.block_threads
     CLASS_CAP = args.class_cap
 
+    # the serving stream's instances come from a process pool, created before
+    # this process touches the GPU (a HIP-initialised process must not fork)
+    pre_serve = None
+    if args.workload == "serve":
+        pre_serve = serve_requests(instances.DEFAULT_SEED, args.serve_seconds)
+    elif args.workload == "nmc" and not args.sweeps_only and not args.copy_probe_mib and not args.no_extras:
+        pre_serve = serve_requests(instances.DEFAULT_SEED, SHORT_SERVE_SECONDS)
+
     torch.cuda.set_device(0)
     if args.copy_probe_mib:
         # one read + one write of a known byte count, to scale HBM byte counters
@@ -778,7 +879,7 @@ def main():
     stream = torch.cuda.current_stream()
     seed = instances.DEFAULT_SEED
     if args.workload == "qap":
-        res = bench_qap(nmc, torch, seed, args.sweeps_only, args.sweeps_offset)
+        res = bench_qap(nmc, torch, seed, args.sweeps_only, args.sweeps_offset, args.qap_curve)
         print(json.dumps({"metric": "QAP swap proposals/s (whole NMC path)", "value": res["proposals_per_s"],
                           "unit": "proposals/s", "n_gpus": 1, "higher_is_better": True, "dtype": "int32",
                           "data": "synthetic",
@@ -786,7 +887,7 @@ def main():
                           "roofline": res["roofline"], "qap": res}), flush=True)
         return
     if args.workload == "c1":
-        res = bench_c1(nmc, torch, seed)
+        res = bench_c1(nmc, torch, seed, repeats=C1_REPEATS)
         print(json.dumps({"metric": "latency of plain SA, random 4-SAT N=200 M=1920, 64 replicas, 1000 sweeps",
                           "value": res["latency_ms"], "unit": "ms", "n_gpus": 1, "higher_is_better": False,
                           "dtype": "int32", "data": "synthetic",
@@ -822,7 +923,7 @@ def main():
                           "roofline": res["roofline"], "apt": res}), flush=True)
         return
     if args.workload == "serve":
-        res = bench_serve(nmc, torch, seed, args.serve_seconds)
+        res = bench_serve(nmc, torch, seed, args.serve_seconds, pre_serve)
         print(json.dumps({"metric": "served NMC: solves/s and p50/p99 time-to-target", "value": res["all"]["solves_per_s"],
                           "unit": "solves/s", "n_gpus": 1, "higher_is_better": True, "dtype": "int32",
                           "data": "synthetic",
@@ -872,15 +973,17 @@ def main():
     # sweep-kernel time from HIP events on the launch stream (separate pass)
     prep, _ = run_path(inst, seed, -1, nmc, profile=True)
     kt = prep.kernel_time()
+    acceptance = prep.accept_count() / attempts
     bps = counter_bytes_per_sweep()
     sweeps_per_launch = (S_ANNEAL + ROUNDS * S_RE) / (1 + ROUNDS)
-    roofline = ksat_roofline(kt, M, None if bps is None else bps * sweeps_per_launch)
+    roofline = ksat_roofline(kt, M, acceptance, None if bps is None else bps * sweeps_per_launch)
     roofline["traffic_unit"] = "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     del prep
     # the same rates against what the probe kernels reach on this GPU
     peaks = measured_peaks(nmc, torch)
-    roofline["frac_of_measured_lds_random"] = roofline["achieved"] / peaks["lds_random_T_per_s"]
-    roofline["frac_of_measured_lds_distinct"] = roofline["achieved"] / peaks["lds_distinct_T_per_s"]
+    roofline["frac_of_measured_hbm_copy"] = roofline["achieved"] / 1e3 / peaks["hbm_copy_TB_per_s"]
+    roofline["lds"]["frac_of_measured_random"] = roofline["lds"]["achieved"] / peaks["lds_random_T_per_s"]
+    roofline["lds"]["frac_of_measured_distinct"] = roofline["lds"]["achieved"] / peaks["lds_distinct_T_per_s"]
     roofline["valu"]["frac_of_measured"] = roofline["valu"]["achieved"] / peaks["valu_int_T_per_s"]
 
     out = {
@@ -965,6 +1068,28 @@ def main():
             "nmc_lbp_rule": "LBP surrogate backbones in place of the magnetization backbones, same sweeps; "
                             "time interpolated inside the phase holding the first hit",
         }
+
+    if not args.no_extras:
+        # the other workloads of the metric, shortened: C1 solve latency
+        # (p50 / p99 over repeated solves), batched NMC vs one launch per
+        # instance on a reduced C4 batch, and a short C5 served stream
+        c1 = bench_c1(nmc, torch, seed, repeats=C1_REPEATS)
+        out["c1"] = c1
+        print(f"# c1: p50 {c1['latency_p50_ms']:.1f} ms, p99 {c1['latency_p99_ms']:.1f} ms", file=sys.stderr,
+              flush=True)
+        bt = bench_batch(nmc, torch, seed, n_instances=SHORT_BATCH_INSTANCES)
+        out["batch"] = bt
+        print(f"# batch: {bt['ttt']}", file=sys.stderr, flush=True)
+        sv = bench_serve(nmc, torch, seed, SHORT_SERVE_SECONDS, pre_serve, n_cap=150)
+        allr = sv["all"]
+        out["serve"] = {"p50": (allr["time_to_target_s"] or {}).get("p50"),
+                        "p99": (allr["time_to_target_s"] or {}).get("p99"),
+                        "unit": "s, submission to the round end at or below target, solved requests",
+                        "solves_per_s": allr["solves_per_s"], "latency_s": allr["latency_s"],
+                        "requests": sv["requests"], "seconds": SHORT_SERVE_SECONDS,
+                        "offered_load": sv["offered_load"], "ksat": sv["ksat"], "qap": sv["qap"],
+                        "capacity_requests_per_s": sv["capacity_requests_per_s"], "schedule": sv["schedule"]}
+        print(f"# serve: p50 {out['serve']['p50']} p99 {out['serve']['p99']}", file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cp, lits, seed)

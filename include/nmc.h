@@ -457,6 +457,14 @@ int nmc_set_tuning(nmc_replicas *rep, int32_t block_threads);
 int nmc_set_profiling(nmc_replicas *rep, int32_t enable);
 int nmc_kernel_time(nmc_replicas *rep, double *ms, int64_t *launches, double *attempts, int32_t reset);
 
+/* Moves the sweep kernels accepted on this replica set (k-SAT: single-variable
+ * flips; QAP: swaps), summed over every sweep call since creation or the last
+ * reset (reset != 0 zeroes it after the read).  With the attempts of those
+ * calls (k-SAT: R x N per sweep; QAP: R x n(n-1)/2) it gives the mean
+ * acceptance rate.  Each call adds its count at its end (one atomic add per
+ * wave).  Synchronizes the stream. */
+int nmc_accept_count(nmc_replicas *rep, uint64_t *accepted, int32_t reset, void *stream);
+
 /* With profiling enabled, nmc_lbp_backbone brackets the two kernels of every
  * message iteration with HIP events; this returns their summed time (ms) and
  * the iterations timed since the last reset. */

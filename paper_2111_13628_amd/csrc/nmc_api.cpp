@@ -827,10 +827,12 @@ int nmc_replicas_create(nmc_instance *I, int32_t n_replicas, uint64_t seed, void
             k.counts = reinterpret_cast<int32_t *>(b + L.off_counts);
             k.frozen = b + L.off_frozen;
             k.tally = reinterpret_cast<int32_t *>(b + L.off_tally);
+            k.accepted = reinterpret_cast<unsigned long long *>(b + L.off_tally + 32);
             k.n_rep = n_replicas;
             k.n_groups = P->G;
             P->scratch_energy = reinterpret_cast<int32_t *>(b + L.off_scratch);
             HIP_OR_FAIL(hipMemsetAsync(b + L.off_energy, 0, L.off_first_hit + (size_t)P->G * kGroup * 4 - L.off_energy, s));
+            HIP_OR_FAIL(hipMemsetAsync(b + L.off_tally, 0, 64, s));
             HIP_OR_FAIL(ksat_launch_init(I->ksat_dev(), k, key0, key1, s));
         } else {
             QapRepDev &q = P->q;
@@ -842,10 +844,12 @@ int nmc_replicas_create(nmc_instance *I, int32_t n_replicas, uint64_t seed, void
             q.cls = b + L.off_cls;
             q.freq = reinterpret_cast<int32_t *>(b + L.off_counts);
             q.tally = reinterpret_cast<int32_t *>(b + L.off_tally);
+            q.accepted = reinterpret_cast<unsigned long long *>(b + L.off_tally + 32);
             q.rows_hint = b + L.off_hint;
             q.n_rep = n_replicas;
             P->scratch_energy = reinterpret_cast<int32_t *>(b + L.off_scratch);
             HIP_OR_FAIL(hipMemsetAsync(q.rows_hint, 0, (size_t)n_replicas, s));
+            HIP_OR_FAIL(hipMemsetAsync(b + L.off_tally, 0, 64, s));
             HIP_OR_FAIL(qap_launch_init(I->qap_dev(), q, key0, key1, s));
         }
         int rc = reset_after_state(P.get(), s);
@@ -2050,6 +2054,23 @@ int nmc_lbp_kernel_time(nmc_replicas *P, double *ms, int64_t *iterations, int32_
     return ok();
 }
 
+int nmc_accept_count(nmc_replicas *P, uint64_t *accepted, int32_t reset, void *stream) {
+    if (!P || !accepted)
+        return fail(NMC_ERR_INVALID, "NULL argument");
+    const bool ksat = P->inst->kind == NMC_KIND_KSAT;
+    unsigned long long *d = ksat ? P->k.accepted : P->q.accepted;
+    hipStream_t s = as_stream(stream);
+    unsigned long long v = 0;
+    HIP_OR_FAIL(hipMemcpyAsync(&v, d, sizeof v, hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(hipStreamSynchronize(s));
+    *accepted = v;
+    if (reset) {
+        HIP_OR_FAIL(hipMemsetAsync(d, 0, sizeof v, s));
+        HIP_OR_FAIL(hipStreamSynchronize(s));
+    }
+    return ok();
+}
+
 int nmc_kernel_time(nmc_replicas *P, double *ms, int64_t *launches, double *attempts, int32_t reset) {
     if (!P)
         return fail(NMC_ERR_INVALID, "NULL replicas");
@@ -3173,6 +3194,7 @@ nmc_replicas rebased(const nmc_replicas *P, uint8_t *base) {
         C.k.counts = mv(P->k.counts);
         C.k.frozen = mv(P->k.frozen);
         C.k.tally = mv(P->k.tally);
+        C.k.accepted = mv(P->k.accepted);
     } else {
         C.q.perm = mv(P->q.perm);
         C.q.best_perm = mv(P->q.best_perm);
@@ -3182,6 +3204,7 @@ nmc_replicas rebased(const nmc_replicas *P, uint8_t *base) {
         C.q.cls = mv(P->q.cls);
         C.q.freq = mv(P->q.freq);
         C.q.tally = mv(P->q.tally);
+        C.q.accepted = mv(P->q.accepted);
         C.q.rows_hint = mv(P->q.rows_hint);
     }
     C.scratch_energy = mv(P->scratch_energy);

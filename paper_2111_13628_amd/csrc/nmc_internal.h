@@ -58,6 +58,7 @@ struct KsatRepDev {
     int32_t *counts;   // [N] replicas with x_i = 1
     uint8_t *frozen;   // [N]
     int32_t *tally;    // [4] scratch for per-set reductions
+    unsigned long long *accepted;  // [1] moves accepted by the sweep kernels (reset by the host)
     int32_t n_rep, n_groups;
 };
 
@@ -94,6 +95,7 @@ struct QapRepDev {
     uint8_t *cls;       // [n]
     int32_t *freq;      // [n][n]
     int32_t *tally;     // scratch
+    unsigned long long *accepted;  // [1] swaps accepted by the sweep kernels (reset by the host)
     uint8_t *rows_hint; // [R] proposals per step the replica's last sweep chose (0: none yet)
     int32_t n_rep;
 };

@@ -191,6 +191,7 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
     }
     __syncthreads();
 
+    uint32_t n_acc = 0;  // flips this lane accepted in this call
     for (int s = 0; s < C.n_sweeps; ++s) {
         const uint32_t t = C.t0 + (uint32_t)s;
         const uint32_t *tg = tab + (size_t)s * C.sweep_words;
@@ -280,6 +281,7 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
                         flip |= ((need & 8u) && u.w < thr[3]) ? 8u : 0u;
                     }
                     if (flip) {
+                        n_acc += __builtin_popcount(flip);
                         const uint32_t nx = xi ^ flip;
                         lds_store_u8((uint32_t)v, nx);
                         lds_store_u8((uint32_t)(n + v), ~nx & amask);
@@ -352,6 +354,12 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
         R.best[r0 + tid] = best;
         R.first_hit[r0 + tid] = fh;
     }
+    unsigned long long acc_w = n_acc;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        acc_w += __shfl_xor(acc_w, off, 64);
+    if (lane == 0 && acc_w)
+        atomicAdd(R.accepted, acc_w);
 }
 
 // One replica group per workgroup (group = blockIdx.x).

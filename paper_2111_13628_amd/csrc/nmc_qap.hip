@@ -524,6 +524,7 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
     const int word = rep & 3;
 
     long long cost = 0, best = 0;
+    unsigned long long acc_total = 0;  // swaps this wave accepted in this call
     int fh = -1, hint = 0;
     if (active) {
         hint = R.rows_hint[rep];
@@ -561,6 +562,7 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
                 n_acc = rows == 4 ? qap_wave_sweep<4, KPL4, KP>(I, C, F, F8, D, cls, tw, pr, t, group, word, cost)
                                   : qap_wave_sweep1<KPL1, KP>(I, C, F, D, cls, tw, pr, t, group, word, cost);
             }
+            acc_total += (unsigned long long)n_acc;
             if (C.rows == 0) {
                 // acceptance of this sweep: above 3/10 one proposal per step,
                 // below 1/16 eight, else four
@@ -591,6 +593,8 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
             R.first_hit[rep] = fh;
             if (C.rows == 0)
                 R.rows_hint[rep] = (uint8_t)rows;
+            if (acc_total)
+                atomicAdd(R.accepted, acc_total);
         }
     }
 }

@@ -132,6 +132,7 @@ _SIGS = {
     "nmc_set_tuning": ([_P, _I32], ctypes.c_int),
     "nmc_set_profiling": ([_P, _I32], ctypes.c_int),
     "nmc_kernel_time": ([_P, _P, _P, _P, _I32], ctypes.c_int),
+    "nmc_accept_count": ([_P, _P, _I32, _P], ctypes.c_int),
     "nmc_pt_run": ([_P, _P, _I32, _I32, _I32, _I32, _I64, _P, _P, _P], ctypes.c_int),
     "nmc_cluster_flip": ([_P, _P, ctypes.c_double, _I64, _P, _P], ctypes.c_int),
     "nmc_whiten": ([_P, _I32, _P, _P, _P, _P], ctypes.c_int),
@@ -448,6 +449,12 @@ class Replicas:
         _check(lib().nmc_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(launches), ctypes.byref(att),
                                      int(bool(reset))))
         return dict(ms=ms.value, launches=launches.value, attempts=att.value)
+
+    def accept_count(self, reset=False, stream=None):
+        """Moves accepted by the sweep kernels since creation or the last reset."""
+        v = ctypes.c_uint64()
+        _check(lib().nmc_accept_count(self._h, ctypes.byref(v), int(bool(reset)), _stream(stream)))
+        return v.value
 
     def cluster_flip(self, label, beta, target=-1, stream=None):
         """One collective-move sweep over the clusters of `label` (e.g. the

@@ -184,3 +184,28 @@ def test_layout_schedule_does_not_change_results(monkeypatch):
     assert (out[0][0] == out[1][0]).all()
     for key in ("energy", "best_per_replica", "first_hit"):
         assert (out[0][1][key] == out[1][1][key]).all()
+
+
+def test_accept_count_equals_flipped_spins():
+    """Every variable is visited once per sweep, so the flips a sweep accepts
+    are exactly the spins that differ before and after it; the counter of
+    accepted moves must equal that Hamming distance, sweep by sweep, over a
+    schedule from hot (mostly accepted) to cold."""
+    say("case: accepted-move counter, k-SAT")
+    n, R = 700, 37
+    cp, lits = instances.gen_ksat(n, "9.6", 4, 91)
+    rep = nmc.Replicas(nmc.Instance.ksat(n, cp, lits).bind(), R, 92)
+    assert rep.accept_count() == 0
+    betas = instances.linear_schedule(0.05, 5.0, 12)
+    total = 0
+    for b in betas:
+        x0 = rep.get_state()
+        rep.anneal(np.array([[b]]))
+        flips = int((rep.get_state() != x0).sum())
+        got = rep.accept_count(reset=True)
+        assert got == flips, (b, got, flips)
+        total += got
+    assert total > 0 and rep.accept_count() == 0
+    # a multi-sweep call counts its sweeps together
+    rep.anneal(np.full((1, 5), 0.3))
+    assert rep.accept_count() > 0

@@ -119,3 +119,21 @@ def test_qap_largest_n255():
         return
     p.orep.anneal(reanneal_profile(1, sc), class_of=cls)
     p.compare()
+
+
+def test_accept_count_qap():
+    """At beta = 0 every proposal is accepted (threshold 2^32 - 1, which only a
+    word of 2^32 - 1 fails), so a sweep counts every pair of every replica; at
+    a very large beta only non-increasing swaps are taken and the count never
+    exceeds the proposals."""
+    say("case: accepted-move counter, QAP")
+    n, R = 30, 20
+    F, D = instances.gen_qap(n, 93)
+    rep = nmc.Replicas(nmc.Instance.qap(F, D).bind(), R, 94)
+    rep.anneal(np.zeros((1, 3)))
+    assert rep.accept_count(reset=True) == 3 * R * n * (n - 1) // 2
+    rep.anneal(np.full((1, 4), 60.0))
+    cold = rep.accept_count(reset=True)
+    assert 0 <= cold < 4 * R * n * (n - 1) // 2
+    rep.anneal(np.full((1, 4), 1e-4))
+    assert rep.accept_count() > cold
