@@ -429,6 +429,10 @@ int nmc_ksat_load(int32_t n_vars, int32_t n_clauses, const int32_t *clause_ptr, 
         };
         const char *sched_env = std::getenv("NMC_KSAT_BANK_SCHEDULE");
         const bool bank_schedule = !(sched_env && sched_env[0] == '0');
+        // lanes per variable in chunks of small colour classes (results never
+        // depend on it; NMC_KSAT_SPLIT=0 keeps one lane per variable)
+        const char *split_env = std::getenv("NMC_KSAT_SPLIT");
+        const bool split = !(split_env && split_env[0] == '0');
         const bool debug_banks = std::getenv("NMC_DEBUG_BANKS") != nullptr;
         int64_t model_cycles = 0, model_gathers = 0;
         std::vector<int32_t> chunk_var, color_chunk(ncol + 1, 0);
@@ -451,21 +455,30 @@ int nmc_ksat_load(int32_t n_vars, int32_t n_clauses, const int32_t *clause_ptr, 
             });
             for (size_t b = 0; b < vs.size(); b += kChunk) {
                 const size_t e = std::min(vs.size(), b + kChunk);
+                // a chunk of few variables gives each variable L = 2^lg
+                // adjacent lanes (its clauses dealt round-robin over them), so
+                // a lane walks about 1/L of the variable's slots; the lanes'
+                // partial sums are added before the decision
+                int32_t lg = 0;
+                while (split && lg < kMaxSplitLog && (int32_t)(e - b) << (lg + 1) <= kChunk)
+                    ++lg;
+                const int32_t L = 1 << lg;
                 int32_t nslot = 0;
                 for (size_t i = b; i < e; ++i)
-                    nslot = std::max(nslot, vptr[vs[i] + 1] - vptr[vs[i]]);
+                    nslot = std::max(nslot, (vptr[vs[i] + 1] - vptr[vs[i]] + L - 1) / L);
                 nslot = std::max<int32_t>(kSlotUnroll, (int32_t)align_up(nslot, kSlotUnroll));  // padding slots are inert
-                chunk_info.push_back(make_int2(slot_rows, nslot));
+                chunk_info.push_back(make_int2(slot_rows, nslot | (lg << kSplitShift)));
                 slot_rows += nslot;
                 ChunkWork w;
                 w.lanes.resize(kChunk);
                 w.nslot = nslot;
                 int32_t n1[kChunk] = {0};
                 for (size_t i = b; i < e; ++i) {
-                    const int lane = (int)(i - b);
+                    const int lane0 = (int)(i - b) * L;
                     const int32_t v = vs[i];
                     for (int32_t q = vptr[v]; q < vptr[v + 1]; ++q) {
                         const int32_t a = vcl[q], own = vpos[q];
+                        const int lane = lane0 + (q - vptr[v]) % L;
                         ChunkRec r{{ZERO, ZERO, ZERO}, lits[own] < 0 ? 1u : 0u};
                         int k = 0;
                         for (int32_t p = clause_ptr[a]; p < clause_ptr[a + 1]; ++p)
@@ -476,10 +489,13 @@ int nmc_ksat_load(int32_t n_vars, int32_t n_clauses, const int32_t *clause_ptr, 
                     }
                 }
                 work.push_back(std::move(w));
-                // lane word: variable in bits 0..19 and its count of clauses
-                // holding it negated in bits 20..27; -1 = empty lane
-                for (int lane = 0; lane < kChunk; ++lane)
-                    chunk_var.push_back(b + lane < e ? (vs[b + lane] | (n1[lane] << 20)) : -1);
+                // lane word: variable in bits 0..19 and the count of the lane's
+                // records whose own literal is negated in bits 20..27; -1 =
+                // empty lane
+                for (int lane = 0; lane < kChunk; ++lane) {
+                    const size_t i = b + (size_t)(lane / L);
+                    chunk_var.push_back(i < e ? (vs[i] | (n1[lane] << 20)) : -1);
+                }
             }
             color_chunk[c + 1] = (int32_t)chunk_info.size();
         }

@@ -29,6 +29,11 @@ constexpr uint32_t kAddrMask = (1u << kAddrBits) - 1;
 constexpr int kMaxClasses = 8;
 constexpr int kChunk = 64;  // variables per sweep chunk = lanes of one wave
 constexpr int kSlotUnroll = 4;  // clause slots per chunk are padded to a multiple of this
+// A chunk's info word y holds its slot count in bits 0..15 and lg in bits
+// 16..: each variable occupies 2^lg adjacent lanes (lg <= kMaxSplitLog), the
+// first of which (lane % 2^lg == 0) takes the decision.
+constexpr int kSplitShift = 16;
+constexpr int kMaxSplitLog = 4;
 
 // LDS available to one workgroup on gfx950.
 constexpr size_t kLdsBytes = 160 * 1024;
@@ -39,7 +44,7 @@ __host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a -
 struct KsatDev {
     const uint64_t *rec;         // chunk records, [slot-row][64 lanes]
     const int32_t *chunk_var;    // [n_chunks][64] lane word: variable | negated-count << 20, -1 = empty
-    const int2 *chunk_info;      // [n_chunks] (first slot-row, slot count)
+    const int2 *chunk_info;      // [n_chunks] (first slot-row, slot count | lg << kSplitShift)
     const int32_t *color_chunk;  // [n_colors + 1] chunk range of each colour class
     const uint32_t *clause_addr; // [M][4] spin-table addresses of the clause's literals
     const int32_t *var_ptr;      // [N + 1] variable -> clause incidence
@@ -78,6 +83,7 @@ struct SweepCall {
 constexpr int kQapMaxN = 255;
 constexpr int kQapRepPerBlock = 16;   // one replica per wave, 16 waves per workgroup
 constexpr int kQapLowBits = 10;       // low digit of the two-level threshold
+
 
 struct QapDev {
     const uint8_t *F;  // [n][n]

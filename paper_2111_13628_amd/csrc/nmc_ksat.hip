@@ -219,9 +219,12 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
                 if (wave_u & 1)
                     __builtin_amdgcn_s_sleep(2);
                 const int2 info = I.chunk_info[h];
-                const int nslot = __builtin_amdgcn_readfirstlane(info.y);
+                const int nslot = __builtin_amdgcn_readfirstlane(info.y & ((1 << kSplitShift) - 1));
+                const int lg = __builtin_amdgcn_readfirstlane(info.y >> kSplitShift);
                 const int lw = I.chunk_var[(size_t)h * kChunk + lane];
-                const int v = lw < 0 ? -1 : (lw & 0xFFFFF);
+                // with lg > 0 a variable's clauses are spread over 2^lg lanes;
+                // the first of them takes the decision
+                const int v = (lw < 0 || (lane & ((1 << lg) - 1))) ? -1 : (lw & 0xFFFFF);
                 // the variable's class is needed after the slot loop; load it now
                 const int cl = (C.var_cls && v >= 0) ? (int)C.var_cls[v] : 0;
                 const uint4 *rp = reinterpret_cast<const uint4 *>(I.rec) +
@@ -257,7 +260,12 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
                     issue_fence();
                 }
                 const uint32_t nneg = lw < 0 ? 0u : ((uint32_t)lw >> 20) & 0xFFu;
-                acc = 0x80808080u + ((uint32_t)nslot - 2u * nneg) * 0x01010101u - nneg - acc;
+                // the lane's share of the closed form (sums mod 2^32 add up
+                // across lanes: an inert padding slot contributes 0)
+                uint32_t part = ((uint32_t)nslot - 2u * nneg) * 0x01010101u - nneg - acc;
+                for (int off = 1; off < (1 << lg); off <<= 1)
+                    part += (uint32_t)__shfl_xor((int)part, off, 64);
+                acc = 0x80808080u + part;
                 if (v >= 0) {
                     const uint32_t xi = lds_load_u8((uint32_t)v);
                     const uint32_t *T = tl + cl * C.stride;

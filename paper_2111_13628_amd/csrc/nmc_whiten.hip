@@ -59,16 +59,16 @@ __global__ void __launch_bounds__(1024) ksat_whiten_kernel(KsatDev I, const uint
         __syncthreads();
         for (int h = wave; h < I.n_chunks; h += nwaves) {
             const int lw = I.chunk_var[(size_t)h * kChunk + lane];
-            if (lw < 0)
-                continue;
-            const int i = lw & 0xFFFFF;
-            const uint32_t own = tbl[i];
-            const uint32_t xi = own & 0xFFu, si = own >> 8;
-            if (si == amask)
-                continue;
             const int2 info = I.chunk_info[h];
+            const int nslot = info.y & ((1 << kSplitShift) - 1);
+            const int lg = info.y >> kSplitShift;  // a variable's records spread over 2^lg lanes
+            const int i = lw & 0xFFFFF;
+            const uint32_t own = lw < 0 ? 0u : tbl[i];
+            const uint32_t xi = own & 0xFFu, si = own >> 8;
+            // the lanes of one variable agree on skipping it
+            const bool live = lw >= 0 && si != amask;
             uint32_t pinned = 0;
-            for (int s = 0; s < info.y; ++s) {
+            for (int s = 0; live && s < nslot; ++s) {
                 const uint64_t r = rec[((size_t)(info.x / 2 + s / 2) * kChunk + lane) * 2 + (s & 1)];
                 const uint32_t a0 = (uint32_t)r & kAddrMask;
                 const uint32_t a1 = (uint32_t)(r >> kAddrBits) & kAddrMask;
@@ -79,8 +79,10 @@ __global__ void __launch_bounds__(1024) ksat_whiten_kernel(KsatDev I, const uint
                                    lit_state(tbl, a2, n, amask);
                 pinned |= own_true & ~(o & 0xFFu) & ~(o >> 8);
             }
+            for (int off = 1; off < (1 << lg); off <<= 1)
+                pinned |= (uint32_t)__shfl_xor((int)pinned, off, 64);
             const uint32_t ns = si | (~pinned & amask);
-            if (ns != si) {
+            if (live && (lane & ((1 << lg) - 1)) == 0 && ns != si) {
                 tbl[i] = (uint16_t)((ns << 8) | xi);
                 changed = 1;
             }

@@ -186,6 +186,29 @@ def test_layout_schedule_does_not_change_results(monkeypatch):
         assert (out[0][1][key] == out[1][1][key]).all()
 
 
+@pytest.mark.parametrize("n,cap,R", [(200, 0, 64), (900, 16, 21), (300, 1, 8)])
+def test_split_lanes_do_not_change_results(monkeypatch, n, cap, R):
+    """Chunks of small colour classes spread each variable's clauses over
+    several lanes (NMC_KSAT_SPLIT=0 keeps one lane per variable): the partial
+    sums only regroup integer additions, so states, energies, snapshots,
+    backbones and whitening are identical, and both equal the oracle."""
+    say(f"case: split lanes n={n} cap={cap} R={R}")
+    cp, lits = instances.gen_ksat(n, "9.6", 4, 41 + n)
+    beta = instances.linear_schedule(0.1, 4.0, 40)[None, :]
+    out = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("NMC_KSAT_SPLIT", flag)
+        p = KsatPair(n, cp, lits, R, 6, cap=cap)
+        p.anneal(beta, target=5)
+        cls = p.backbone(9, 10, True)
+        p.anneal(reanneal_profile(15), class_of=cls, profile="backbone", target=5)
+        p.compare()
+        out.append((p.rep.get_state(), p.rep.get_state("best"), p.rep.whiten("best", white=True)))
+    assert (out[0][0] == out[1][0]).all() and (out[0][1] == out[1][1]).all()
+    w0, w1 = out[0][2], out[1][2]
+    assert (w0[0] == w1[0]).all() and (w0[1] == w1[1]).all()
+
+
 def test_accept_count_equals_flipped_spins():
     """Every variable is visited once per sweep, so the flips a sweep accepts
     are exactly the spins that differ before and after it; the counter of
