@@ -46,11 +46,25 @@ int ok() {
 }  // namespace
 
 // Proposals per step of the QAP sweep: 0 = chosen per sweep by the kernel;
-// NMC_QAP_ROWS=1, 4 or 8 pins it (for measurements; results do not change).
+// NMC_QAP_ROWS=1, 4 or 8 pins it, 2 pins the table mode, 3 the four
+// replicas per wave (for measurements; results do not change).
 static int32_t qap_rows_setting() {
     const char *e = std::getenv("NMC_QAP_ROWS");
     const int v = e ? std::atoi(e) : 0;
-    return (int32_t)(v == 1 || v == 4 || v == 8 ? v : 0);
+    return (int32_t)(v >= 1 && v <= 4 || v == 8 ? v : 0);
+}
+
+// Whether the per-sweep choice of single-set QAP sweeps may take the table
+// mode (NMC_QAP_TAB=1) or run hot sweeps with 2 or 4 replicas per wave
+// (NMC_QAP_RPW=2 or 4).  For measurements; results do not change.
+static int32_t qap_tab_setting() {
+    const char *e = std::getenv("NMC_QAP_TAB");
+    return (int32_t)(e && e[0] == '1');
+}
+static int32_t qap_quad_setting() {
+    const char *e = std::getenv("NMC_QAP_RPW");  // replicas per wave in hot sweeps: 2 or 4
+    const int v = e ? std::atoi(e) : 0;
+    return (int32_t)(v == 2 || v == 4 ? v : 0);
 }
 
 int nmc::set_last_error(int code, const char *msg) {
@@ -703,7 +717,7 @@ namespace {
 
 struct ReplicaLayout {
     size_t off_xs, off_best_xs, off_energy, off_best, off_first_hit, off_cls, off_counts, off_frozen, off_tally,
-        off_scratch, off_hint, total;
+        off_scratch, off_hint, off_dtab, total;
 };
 
 ReplicaLayout replica_layout(const nmc_instance *I, int32_t R) {
@@ -734,6 +748,7 @@ ReplicaLayout replica_layout(const nmc_instance *I, int32_t R) {
         L.off_tally = ar.take(64);
         L.off_scratch = ar.take((size_t)R * 8);
         L.off_hint = ar.take((size_t)R);
+        L.off_dtab = ar.take((size_t)R * (n * (n - 1) / 2) * 4);  // table-mode swap deltas
     }
     L.total = align_up(ar.size, 256);
     return L;
@@ -862,6 +877,7 @@ int nmc_replicas_create(nmc_instance *I, int32_t n_replicas, uint64_t seed, void
             q.tally = reinterpret_cast<int32_t *>(b + L.off_tally);
             q.accepted = reinterpret_cast<unsigned long long *>(b + L.off_tally + 32);
             q.rows_hint = b + L.off_hint;
+            q.dtab = reinterpret_cast<int32_t *>(b + L.off_dtab);
             q.n_rep = n_replicas;
             P->scratch_energy = reinterpret_cast<int32_t *>(b + L.off_scratch);
             HIP_OR_FAIL(hipMemsetAsync(q.rows_hint, 0, (size_t)n_replicas, s));
@@ -1033,6 +1049,8 @@ static int anneal_impl(nmc_replicas *P, const double *beta, int32_t n_classes, i
         C.target = target;
         C.check_start = 1;
         C.rows = qap_rows_setting();
+        C.tab_allow = qap_tab_setting();
+        C.quad_allow = qap_quad_setting();
         C.key0 = (uint32_t)P->seed;
         C.key1 = (uint32_t)(P->seed >> 32);
         HIP_OR_FAIL(qap_launch_sweep(I->qap_dev(), P->q, C, 256, s));
@@ -1439,6 +1457,8 @@ static int pt_run_impl(nmc_replicas *P, const double *beta, int32_t n_temps, int
             C.target = target;
             C.check_start = 1;
             C.rows = qap_rows_setting();
+            C.tab_allow = qap_tab_setting();
+            C.quad_allow = qap_quad_setting();
             C.key0 = X.key0;
             C.key1 = X.key1;
             C.reps_per_row = chains;
@@ -2318,6 +2338,8 @@ int build_batch(nmc_batch *B, const std::vector<PhaseSpec> &phases, bool with_ba
                 J.C.target = targets ? targets[qidx[j]] : -1;
                 J.C.check_start = 1;
                 J.C.rows = qap_rows_setting();
+                J.C.tab_allow = qap_tab_setting();
+                J.C.quad_allow = qap_quad_setting();
                 J.C.key0 = (uint32_t)P->seed;
                 J.C.key1 = (uint32_t)(P->seed >> 32);
                 std::memcpy(blob.host.data() + bp.off_qjobs + j * sizeof(QapJob), &J, sizeof J);
@@ -2737,6 +2759,8 @@ int build_plans(nmc_batch *B, const std::vector<std::vector<SetPhase>> &ph, cons
                 J.C.target = tg;
                 J.C.check_start = 1;
                 J.C.rows = qap_rows_setting();
+                J.C.tab_allow = qap_tab_setting();
+                J.C.quad_allow = qap_quad_setting();
                 J.C.key0 = (uint32_t)P->seed;
                 J.C.key1 = (uint32_t)(P->seed >> 32);
                 const double nd = P->inst->n;
@@ -3222,6 +3246,7 @@ nmc_replicas rebased(const nmc_replicas *P, uint8_t *base) {
         C.q.tally = mv(P->q.tally);
         C.q.accepted = mv(P->q.accepted);
         C.q.rows_hint = mv(P->q.rows_hint);
+        C.q.dtab = mv(P->q.dtab);
     }
     C.scratch_energy = mv(P->scratch_energy);
     return C;
@@ -3462,6 +3487,8 @@ extern "C" int nmc_batch_step(nmc_batch *B, const nmc_segment *segs, int32_t n_s
                     J.C.target = g.target;
                     J.C.check_start = 1;
                     J.C.rows = qap_rows_setting();
+                    J.C.tab_allow = qap_tab_setting();
+                    J.C.quad_allow = qap_quad_setting();
                     J.C.key0 = (uint32_t)P->seed;
                     J.C.key1 = (uint32_t)(P->seed >> 32);
                     const double nd = P->inst->n;

@@ -84,6 +84,28 @@ constexpr int kQapMaxN = 255;
 constexpr int kQapRepPerBlock = 16;   // one replica per wave, 16 waves per workgroup
 constexpr int kQapLowBits = 10;       // low digit of the two-level threshold
 
+// Per-replica costs, accepted swaps and width choices the 16 waves of a QAP
+// sweep workgroup exchange (four-replicas-per-wave sweeps).
+constexpr size_t kQapQuadBytes = 256;
+// LDS of the QAP sweep workgroup: flow rows in the 16-lane layout (and the
+// 8-lane layout for n <= 112), distances, 16 permutations, classes,
+// n_slots * n_classes threshold rows of `stride` words and the exchange
+// area of the four-replicas-per-wave sweeps; then, when it fits,
+// the table mode's pair list (2 bytes per pair) and per-wave update vectors
+// (4 bytes per facility).
+__host__ __device__ inline int qap_flow_row(int n) { return n <= 64 ? 64 : n <= 112 ? 128 : 256; }
+__host__ __device__ inline size_t qap_base_lds(int n, int rows, int stride) {
+    const size_t nn = (size_t)n * n;
+    return align_up((size_t)n * qap_flow_row(n), 16) + (n <= 112 ? align_up((size_t)n * 128, 16) : 0) +
+           align_up(nn, 16) + kQapRepPerBlock * align_up(n, 4) + align_up(n, 16) +
+           align_up((size_t)rows * stride * sizeof(uint32_t), 16) + kQapQuadBytes;
+}
+__host__ __device__ inline size_t qap_tab_lds(int n) {
+    return align_up((size_t)n * (n - 1), 16) + kQapRepPerBlock * align_up((size_t)n * 4, 16);
+}
+__host__ __device__ inline bool qap_tab_fits(int n, int rows, int stride) {
+    return qap_base_lds(n, rows, stride) + qap_tab_lds(n) <= kLdsBytes;
+}
 
 struct QapDev {
     const uint8_t *F;  // [n][n]
@@ -93,6 +115,7 @@ struct QapDev {
 };
 
 struct QapRepDev {
+    int32_t *dtab;      // [R][n(n-1)/2] swap cost changes of every pair (table mode; rebuilt per launch)
     uint8_t *perm;      // [R][n]
     uint8_t *best_perm; // [R][n]
     int64_t *cost;      // [R]
@@ -115,7 +138,9 @@ struct QapCall {
     int64_t target;
     int32_t check_start;
     uint32_t key0, key1;
-    int32_t rows;          // proposals evaluated per step: 0 = chosen per sweep, else 1, 4 or 8
+    int32_t rows;          // proposals per step: 0 = chosen per sweep, else 1, 4 or 8; 2 = table mode
+    int32_t tab_allow;     // the per-sweep choice may use the table mode (when its LDS fits)
+    int32_t quad_allow;    // the per-sweep choice may run several replicas per wave: 0 no, 2 or 4 per wave
     int32_t reps_per_row;  // > 0: replica r reads table row r / reps_per_row (one [n_classes][stride] block per row)
 };
 

@@ -454,6 +454,394 @@ __device__ __forceinline__ int qap_wave_sweep1(const QapDev &I, const QapCall &C
     return n_acc;
 }
 
+// ---- table mode -----------------------------------------------------------
+//
+// For sweeps where almost every proposal is rejected, each wave keeps its
+// replica's change of cost dC(a, b) for every pair in a table in device
+// memory (pair-index order), so a proposal costs one table read and 64
+// consecutive proposals are judged at once; only an accepted swap (r, s)
+// costs O(n^2) work (the Taillard-style delta update of subsection
+// "Quadratic Assignment Problems"' move evaluation).  With symmetric,
+// zero-diagonal F and D and
+//   a_u = F_ur - F_us,  b_u = D_{p_u p_r} - D_{p_u p_s}   (before the swap),
+// a pair (u, v) disjoint from {r, s} changes by 2 (a_u - a_v)(b_u - b_v):
+// only its k = r, s terms move.  Pairs holding r or s are summed anew
+// against the new assignment.  Decisions, words and counters are those of
+// the other paths (the first accepted proposal of the 64 is applied, the
+// ones after it are judged again), so the result is the sequential one.
+
+__device__ __forceinline__ int pair_index(int a, int b, int n) { return a * (2 * n - a - 1) / 2 + (b - a - 1); }
+
+// Table words are read and written at device scope (the accesses bypass the
+// CU's vector L1 and meet at L2, where the no-return atomic adds of an
+// update are performed), so a wave's reads after its own updates see them.
+__device__ __forceinline__ int tab_ld(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void tab_st(int32_t *p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sum over k of (F[x][k] - F[v][k]) (D[p_v][p_k] - D[p_x][p_k]) over every k
+// except x and v, for this 16-lane row's v, with fx, dx, pk the lane's
+// F[x][k], D[p_x][p_k], p_k (k = q + 16 i; zero flow past n).  Every lane of
+// the row gets the sum.
+template <int KPL, int KP>
+__device__ __forceinline__ int tab_row_sum(const uint8_t *F, const uint8_t *D, int n, int q, int x, int px, int v,
+                                           int pv, const int (&fx)[KPL], const int (&dx)[KPL],
+                                           const int (&pk)[KPL]) {
+    constexpr int RB = 16 * KP;
+    int fv[KPL];
+    flow_row<4, KPL, KP>(F + v * RB, q, fv);
+    const uint8_t *drow = D + pv * n;
+    int part = 0;
+#pragma unroll
+    for (int i = 0; i < KPL; ++i)
+        part += (fx[i] - fv[i]) * ((int)drow[pk[i]] - dx[i]);
+    // the k = x and k = v terms are each -F_xv D_{p_x p_v}
+    if (q == 0)
+        part += 2 * (int)F[x * RB + (v & 15) * KP + (v >> 4)] * (int)D[px * n + pv];
+    return row_allreduce16(part);
+}
+
+template <int KPL, int KP>
+__device__ __forceinline__ void tab_load_row(const uint8_t *F, const uint8_t *D, int n, int q, int x, int px,
+                                             const int (&pk)[KPL], int (&fx)[KPL], int (&dx)[KPL]) {
+    constexpr int RB = 16 * KP;
+    flow_row<4, KPL, KP>(F + x * RB, q, fx);
+#pragma unroll
+    for (int i = 0; i < KPL; ++i)
+        dx[i] = D[px * n + pk[i]];
+}
+
+// Fills the wave's table from its permutation: row a of pairs (a, b), four b
+// per step, one per 16-lane row.
+template <int KPL, int KP>
+__device__ void tab_build(const QapDev &I, const uint8_t *F, const uint8_t *D, const uint8_t *pr, int32_t *dt) {
+    const int n = I.n;
+    const int lane = threadIdx.x & 63, row = lane >> 4, q = lane & 15;
+    int pk[KPL], fa[KPL], da[KPL];
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) {
+        const int k = q + 16 * i;
+        pk[i] = k < n ? pr[k] : 0;
+    }
+    for (int a = 0; a < n - 1; ++a) {
+        const int pa = pr[a];
+        tab_load_row<KPL, KP>(F, D, n, q, a, pa, pk, fa, da);
+        const int base = pair_index(a, a + 1, n) - (a + 1);
+        for (int b0 = a + 1; b0 < n; b0 += 4) {
+            const int b = b0 + row;
+            const bool valid = b < n;
+            const int bb = valid ? b : a + 1;
+            const int sum = tab_row_sum<KPL, KP>(F, D, n, q, a, pa, bb, pr[bb], fa, da, pk);
+            if (valid && q == 0)
+                tab_st(dt + base + b, 2 * sum);
+        }
+    }
+    __threadfence_block();
+}
+
+// The accepted swap (r, s), with pr still holding the old assignment:
+// updates the table, then applies the swap to pr.
+template <int KPL, int KP>
+__device__ void tab_apply(const QapDev &I, const uint8_t *F, const uint8_t *D, uint8_t *pr, const uint16_t *PT,
+                          int32_t *ab, int32_t *dt, int r, int s) {
+    constexpr int RB = 16 * KP;
+    const int n = I.n, npairs = n * (n - 1) / 2;
+    const int lane = threadIdx.x & 63, row = lane >> 4, q = lane & 15;
+    const int pr_r = pr[r], pr_s = pr[s];
+    for (int u = lane; u < n; u += 64) {
+        const int fo = (u & 15) * KP + (u >> 4);  // F[x][u] in the 16-lane flow layout
+        const int au = (int)F[r * RB + fo] - (int)F[s * RB + fo];
+        const int pu = pr[u];
+        const int bu = (int)D[pu * n + pr_r] - (int)D[pu * n + pr_s];
+        ab[u] = (int32_t)(((uint32_t)au & 0xFFFFu) | ((uint32_t)bu << 16));
+    }
+    __threadfence_block();
+    // pairs disjoint from {r, s}: added in place (no-return atomic adds, so
+    // the wave never waits on a table word here)
+    for (int idx = lane; idx < npairs; idx += 64) {
+        const uint32_t uv = PT[idx];
+        const int u = uv & 0xFF, v = uv >> 8;
+        if (u == r || u == s || v == r || v == s)
+            continue;
+        const int xu = ab[u], xv = ab[v];
+        const int dau = __builtin_amdgcn_sbfe(xu, 0, 16) - __builtin_amdgcn_sbfe(xv, 0, 16);
+        const int dbu = __builtin_amdgcn_sbfe(xu, 16, 16) - __builtin_amdgcn_sbfe(xv, 16, 16);
+        const int inc = 2 * dau * dbu;
+        if (inc)
+            atomicAdd(dt + idx, inc);
+    }
+    if (lane == 0) {
+        pr[r] = (uint8_t)pr_s;
+        pr[s] = (uint8_t)pr_r;
+    }
+    __threadfence_block();
+    // pairs holding r or s, summed against the new assignment
+    int pk[KPL], fx[KPL], dx[KPL];
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) {
+        const int k = q + 16 * i;
+        pk[i] = k < n ? pr[k] : 0;
+    }
+#pragma unroll 1
+    for (int w = 0; w < 2; ++w) {
+        const int x = w == 0 ? r : s;
+        const int px = pr[x];
+        tab_load_row<KPL, KP>(F, D, n, q, x, px, pk, fx, dx);
+        for (int v0 = 0; v0 < n; v0 += 4) {
+            const int v = v0 + row;
+            const bool valid = v < n && v != x;
+            const int vv = valid ? v : (x == 0 ? 1 : 0);
+            const int sum = tab_row_sum<KPL, KP>(F, D, n, q, x, px, vv, pr[vv], fx, dx, pk);
+            if (valid && q == 0)
+                tab_st(dt + (x < v ? pair_index(x, v, n) : pair_index(v, x, n)), 2 * sum);
+        }
+    }
+    __threadfence_block();
+}
+
+// One sweep of one replica in table mode; `fresh` says whether the table
+// already holds this permutation's changes (it does after a table-mode
+// sweep of the same launch).  Returns the number of accepted swaps.
+template <int KPL, int KP>
+__device__ __forceinline__ int qap_wave_sweep_tab(const QapDev &I, const QapCall &C, const uint8_t *F,
+                                                  const uint8_t *D, const uint8_t *cls, const uint32_t *tl,
+                                                  uint8_t *pr, const uint16_t *PT, int32_t *ab, int32_t *dt,
+                                                  uint32_t t, uint32_t group, int word, long long &cost,
+                                                  bool &fresh) {
+    const int n = I.n;
+    const int npairs = n * (n - 1) / 2;
+    const int lane = threadIdx.x & 63;
+    const bool one_class = C.n_classes == 1;
+    if (!fresh) {
+        tab_build<KPL, KP>(I, F, D, pr, dt);
+        fresh = true;
+    }
+    int n_acc = 0;
+    uint32_t pbase = 0;
+    uint32_t uw = sweep_word((uint32_t)lane, t, group, word, C.key0, C.key1);
+    uint32_t uw2 = sweep_word(64u + (uint32_t)lane, t, group, word, C.key0, C.key1);
+    // the table words of the next two 64-pair chunks are read ahead (valid
+    // until a swap is applied; then read again from the restart)
+    int p0 = 0;
+    int d1 = lane < npairs ? tab_ld(dt + lane) : 0;
+    int d2 = 64 + lane < npairs ? tab_ld(dt + 64 + lane) : 0;
+    while (p0 < npairs) {
+        const int idx = p0 + lane;
+        const bool valid = idx < npairs;
+        const int d = d1;
+        d1 = d2;
+        d2 = idx + 128 < npairs ? tab_ld(dt + idx + 128) : 0;
+        const int src = idx - (int)pbase;  // 0 .. 126
+        const int sl = (src & 63) << 2;
+        const uint32_t ua = (uint32_t)__builtin_amdgcn_ds_bpermute(sl, (int)uw);
+        const uint32_t ub = (uint32_t)__builtin_amdgcn_ds_bpermute(sl, (int)uw2);
+        const uint32_t u = src < 64 ? ua : ub;
+        bool acc = d <= 0;
+        if (!acc) {
+            int cl = 0;
+            if (!one_class) {
+                const uint32_t uv = PT[valid ? idx : 0];
+                cl = max((int)cls[uv & 0xFF], (int)cls[uv >> 8]);
+            }
+            const uint32_t *T = tl + cl * C.stride;
+            const int h = d >> kQapLowBits, l = d & ((1 << kQapLowBits) - 1);
+            const uint32_t thr = h < I.ha ? (uint32_t)(((uint64_t)T[h] * (uint64_t)T[I.ha + l]) >> 32) : 0u;
+            acc = u < thr;
+        }
+        const uint64_t m = __ballot(acc && valid);
+        if (m == 0) {
+            p0 += 64;
+        } else {
+            const int j = __builtin_ctzll(m);
+            const int pj = p0 + j;
+            cost += __builtin_amdgcn_readlane(d, j);
+            ++n_acc;
+            const uint32_t rs = PT[pj];
+            tab_apply<KPL, KP>(I, F, D, pr, PT, ab, dt, (int)(rs & 0xFF), (int)(rs >> 8));
+            p0 = pj + 1;
+            d1 = p0 + lane < npairs ? tab_ld(dt + p0 + lane) : 0;
+            d2 = p0 + 64 + lane < npairs ? tab_ld(dt + p0 + 64 + lane) : 0;
+        }
+        if (p0 >= (int)pbase + 64) {
+            pbase += 64;
+            uw = uw2;
+            uw2 = sweep_word(pbase + 64u + (uint32_t)lane, t, group, word, C.key0, C.key1);
+        }
+    }
+    return n_acc;
+}
+
+// ---- several replicas per wave --------------------------------------------
+//
+// For sweeps where many proposals are accepted, one wave runs RPW (2 or 4)
+// replicas of one Philox group at once, one per row of 64 / RPW lanes: every
+// replica proposes the same pair at the same step (the lexicographic order),
+// so the walk over pairs, the flow rows and the class lookup are shared, and
+// one generator call per lane gives a row the words of 64 / RPW pairs.  Each
+// row sums its replica's change over k = q, q + 64 / RPW, ... (corrected by
+// 2 F_ab D_{p_a p_b} for the k = a, b terms), decides, and applies its own
+// swap under its own lane mask.  Decisions, words and counters are those of
+// the one-replica paths.  costq / accq: the replicas' costs in and out and
+// their accepted swaps, indexed by local replica.
+
+// Sum over each row of 32 lanes, returned to every lane of the row.
+__device__ __forceinline__ int row_allreduce32(int x) {
+    x = row_allreduce16(x);
+    const auto sw = __builtin_amdgcn_permlane16_swap(x, x, false, false);  // rows 0 <-> 1, 2 <-> 3
+    return (int)sw[0] + (int)sw[1];
+}
+
+// F[b][k] for k = q + LANES i (i < KPL) from the 16-lane flow layout (row b
+// holds F[b][k] at byte (k % 16) * KP + k / 16): for LANES = 32 the lane's
+// bytes are q / 16 + 2 i of its KP-byte segment.
+template <int LANES, int KPL, int KP>
+__device__ __forceinline__ void flow_row_lanes(const uint8_t *row, int q, int (&f)[KPL]) {
+    if constexpr (LANES == 16) {
+        flow_row<4, KPL, KP>(row, q, f);
+    } else {
+        static_assert(LANES == 32 && 2 * KPL <= KP, "flow layout");
+        uint32_t w[KP / 4];
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(row + (q & 15) * KP);
+#pragma unroll
+        for (int j = 0; j < KP / 4; ++j)
+            w[j] = src[j];
+        const int h = q >> 4;
+#pragma unroll
+        for (int i = 0; i < KPL; ++i) {
+            const uint32_t lo = (w[(2 * i) >> 2] >> (8 * ((2 * i) & 3))) & 0xFFu;
+            const uint32_t hi = (w[(2 * i + 1) >> 2] >> (8 * ((2 * i + 1) & 3))) & 0xFFu;
+            f[i] = (int)(h ? hi : lo);
+        }
+    }
+}
+
+template <int RPW, int KPL, int KP>
+__device__ __forceinline__ void qap_multi_sweep(const QapDev &I, const QapCall &C, const uint8_t *F,
+                                                const uint8_t *D, const uint8_t *cls, const uint32_t *tl, uint8_t *P,
+                                                int npad, int w, uint32_t t, uint32_t group, int word0,
+                                                long long *costq, int *accq) {
+    constexpr int LANES = 64 / RPW;
+    constexpr int RB = 16 * KP;
+    const int n = I.n;
+    const int npairs = n * (n - 1) / 2;
+    const int lane = threadIdx.x & 63, row = lane / LANES, q = lane % LANES;
+    const bool one_class = C.n_classes == 1;
+    const int lr = w * RPW + row;  // local replica of this row
+    uint8_t *pr = P + lr * npad;
+    long long cost = costq[lr];
+    int pk[KPL], fa[KPL], da[KPL];
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) {
+        const int k = q + LANES * i;
+        pk[i] = k < n ? pr[k] : 0;
+    }
+    int ar = 0, br = 1;
+    int pa = pr[0], pb = pr[1];
+    flow_row_lanes<LANES, KPL, KP>(F, q, fa);
+#pragma unroll
+    for (int i = 0; i < KPL; ++i)
+        da[i] = D[pa * n + pk[i]];
+    int n_acc = 0;
+    uint32_t pbase = 0;
+    // lane (row, q) holds its replica's word of pair pbase + q
+    uint32_t uw = sweep_word(pbase + (uint32_t)q, t, group, word0 + row, C.key0, C.key1);
+    for (int p0 = 0; p0 < npairs; ++p0) {
+        int an = ar, bn = br;
+        pair_advance(an, bn, n, 1);
+        const bool new_a = an != ar;  // wave-uniform
+        int pbn = pr[bn], pan = pa;
+        int fan[KPL];
+        if (new_a) {
+            pan = pr[an];
+            flow_row_lanes<LANES, KPL, KP>(F + an * RB, q, fan);
+        }
+        int fb[KPL], db[KPL];
+        flow_row_lanes<LANES, KPL, KP>(F + br * RB, q, fb);
+        const uint8_t *drow = D + pb * n;
+        int part = 0;
+#pragma unroll
+        for (int i = 0; i < KPL; ++i) {
+            db[i] = drow[pk[i]];
+            part += (fa[i] - fb[i]) * (db[i] - da[i]);
+        }
+        if (q == 0)
+            part += 2 * (int)F[ar * RB + (br & 15) * KP + (br >> 4)] * (int)D[pa * n + pb];
+        const int dc = 2 * (LANES == 16 ? row_allreduce16(part) : row_allreduce32(part));
+        const uint32_t u = (uint32_t)__builtin_amdgcn_ds_bpermute((row * LANES + (p0 - (int)pbase)) << 2, (int)uw);
+        bool acc = dc <= 0;
+        if (!acc) {
+            const int cl = one_class ? 0 : max((int)cls[ar], (int)cls[br]);
+            const uint32_t *T = tl + cl * C.stride;
+            const int h = dc >> kQapLowBits, l = dc & ((1 << kQapLowBits) - 1);
+            const uint32_t thr = h < I.ha ? (uint32_t)(((uint64_t)T[h] * (uint64_t)T[I.ha + l]) >> 32) : 0u;
+            acc = u < thr;
+        }
+        if (acc) {
+            ++n_acc;
+            cost += dc;
+            if (q == 0) {
+                pr[ar] = (uint8_t)pb;
+                pr[br] = (uint8_t)pa;
+            }
+            // the new row D[p_a][p_k] is the one just gathered, with 0 at k = a
+            // and the old D[p_a][p_b] at k = b (register index k / LANES is
+            // wave-uniform)
+#pragma unroll
+            for (int i = 0; i < KPL; ++i) {
+                const int da_old = da[i];
+                da[i] = db[i];
+                if (i == ar / LANES && q == ar % LANES) {
+                    da[i] = 0;
+                    pk[i] = pb;
+                }
+                if (i == br / LANES && q == br % LANES) {
+                    da[i] = da_old;
+                    pk[i] = pa;
+                }
+            }
+            // locations read ahead that this swap changed
+            if (bn == ar)
+                pbn = pb;
+            else if (bn == br)
+                pbn = pa;
+            if (an == br)
+                pan = pa;
+            const int pa_old = pa;
+            pa = pb;
+            pb = pa_old;
+        }
+        if (new_a) {
+            ar = an;
+            pa = pan;
+#pragma unroll
+            for (int i = 0; i < KPL; ++i) {
+                fa[i] = fan[i];
+                da[i] = D[pa * n + pk[i]];
+            }
+        }
+        br = bn;
+        pb = pbn;
+        if (p0 + 1 == (int)pbase + LANES) {
+            pbase += LANES;
+            uw = sweep_word(pbase + (uint32_t)q, t, group, word0 + row, C.key0, C.key1);
+        }
+    }
+    if (q == 0) {
+        costq[lr] = cost;
+        accq[lr] = n_acc;
+    }
+}
+
+// Sweeps a launch must still hold for a wave to enter the table mode with a
+// table it has to build first (about a quarter of a sweep's work).
+constexpr int kTabMinSweeps = 8;
+// Acceptance below which the per-sweep choice takes the table mode: fewer
+// than npairs / kTabAccDen swaps accepted in the previous sweep.
+constexpr int kTabAccDen = 128;
+
 // n_sweeps sweeps for the 16 replicas of block `blk`, by the whole
 // 1024-thread workgroup, with smem = the workgroup's dynamic LDS block.  Each
 // wave picks, per sweep, eight proposals per step (8 lanes each) when very few
@@ -466,7 +854,10 @@ __device__ __forceinline__ int qap_wave_sweep1(const QapDev &I, const QapCall &C
 // of 16) wave w runs replica 4 (blk + (w / 4) B) + w % 4 for B = n_rep / 16
 // and reads the table row of its quad; otherwise replica 16 blk + w and the
 // block's one row.
-template <int KPL4, int KPL1, int KPL8>
+// MODE selects the optional sweep kinds compiled into the kernel (each adds
+// registers that would otherwise slow the default paths): bit 0 the table
+// mode, bit 1 four replicas per wave.
+template <int KPL4, int KPL1, int KPL8, int MODE>
 __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev &R, const QapCall &C, const int blk,
                                                 const bool mix, uint8_t *smem) {
     constexpr int KP = KPL4 <= 4 ? 4 : KPL4 <= 8 ? 8 : 16;  // flow bytes per lane of a 16-lane row
@@ -487,6 +878,16 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
     uint32_t *tl = (uint32_t *)(cls + align_up(n, 16));
     const int tab_words = C.n_classes * C.stride;
     const int nslots = mix ? kRepPerBlock / 4 : 1;  // table rows held in LDS
+    // table mode: pair list and per-wave update vectors after the thresholds
+    // (present when they fit; the launch sizes LDS with the same rule)
+    const bool tab_ok =
+        (MODE & 1) && qap_tab_fits(n, nslots * C.n_classes, C.stride) && (C.tab_allow || C.rows == 2);
+    uint8_t *QX = (uint8_t *)tl + align_up((size_t)nslots * tab_words * 4, 16);
+    long long *qcost = (long long *)QX;               // [16]
+    int *qacc = (int *)(QX + 16 * sizeof(long long)); // [16]
+    int *qrows = qacc + 16;                           // [16]
+    uint16_t *PT = (uint16_t *)(QX + kQapQuadBytes);
+    int32_t *AB = (int32_t *)((uint8_t *)PT + align_up((size_t)n * (n - 1), 16));
     const int quad_stride = R.n_rep / 4 / 4;        // B quads between a block's slots (mix only)
     // replica of wave (or P row) w
     auto rep_of = [&](int w) { return mix ? 4 * (blk + (w >> 2) * quad_stride) + (w & 3) : blk * kRepPerBlock + w; };
@@ -506,6 +907,14 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
         D[i] = I.D[i];
     for (int i = tid; i < n; i += blockDim.x)
         cls[i] = C.fac_cls ? C.fac_cls[i] : 0;
+    if ((MODE & 1) && tab_ok) {
+        // pair list: entry pair_index(a, b) holds a | b << 8
+        for (int a = tid; a < n - 1; a += blockDim.x) {
+            const int base = pair_index(a, a + 1, n) - (a + 1);
+            for (int b = a + 1; b < n; ++b)
+                PT[base + b] = (uint16_t)(a | (b << 8));
+        }
+    }
     // per-temperature tables (tempering): the replicas of a quad (mix) or of
     // the block share one row
     auto row_of = [&](int slot) {
@@ -536,11 +945,22 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
     }
     __syncthreads();
 
-    // proposals per step: 8 (when the size allows), 4 or 1; the first sweep
-    // of a launch takes what the replica's last sweep chose
-    int rows = C.rows != 0 ? C.rows : (hint == 1 || hint == 8) ? hint : 4;
+    // proposals per step: 8 (when the size allows), 4 or 1, or the table
+    // mode (2); the first sweep of a launch takes what the replica's last
+    // sweep chose (the table mode only when the launch is long enough to
+    // repay building the table)
+    int rows = C.rows == 3 ? 1 : C.rows != 0 ? C.rows : (hint == 1 || hint == 8 || hint == 2) ? hint : 4;
+    if (rows == 2 && !(tab_ok && (C.rows == 2 || C.n_sweeps >= kTabMinSweeps)))
+        rows = 8;
     if (rows == 8 && KPL8 == 0)
         rows = 4;
+    bool fresh = false;  // this wave's table holds its permutation's changes
+    int32_t *dt = R.dtab + (size_t)(active ? rep : 0) * npairs;
+    int32_t *ab = AB + wave * (int)align_up((size_t)n, 4);
+    // every wave's choice for the next sweep: when all 16 replicas take one
+    // proposal per step (or C.rows pins 3), waves 0..3 run them four per wave
+    if ((MODE & 2) && lane == 0)
+        qrows[wave] = active ? rows : 0;
     for (int s = 0; s < C.n_sweeps; ++s) {
         const uint32_t t = C.t0 + (uint32_t)s;
         for (int q = 0; q < nslots; ++q) {
@@ -548,25 +968,61 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
             for (int i = tid; i < tab_words; i += blockDim.x)
                 tl[q * tab_words + i] = tg[i];
         }
+        if ((MODE & 2) && lane == 0 && active)
+            qcost[wave] = cost;
         __syncthreads();
+        bool quad = (MODE & 2) != 0;
+        if constexpr ((MODE & 2) != 0) {
+#pragma unroll
+            for (int w = 0; w < kRepPerBlock; ++w) {
+                const int rw = qrows[w];
+                quad = quad && (C.rows == 3 ? rw != 0 : C.rows == 0 && rw == 1);
+            }
+            if (quad) {
+                // RPW replicas per wave in waves 0 .. 16 / RPW - 1
+                constexpr int RPW = (MODE & 4) ? 4 : 2;
+                constexpr int KPLR = RPW == 4 ? KPL4 : (KPL4 + 1) / 2;
+                if (wave < kRepPerBlock / RPW)
+                    qap_multi_sweep<RPW, KPLR, KP>(I, C, F, D, cls, tl + (mix ? (wave * RPW / 4) * tab_words : 0), P,
+                                                   npad, wave, t, (uint32_t)rep_of(wave * RPW) >> 2,
+                                                   rep_of(wave * RPW) & 3, qcost, qacc);
+                fresh = false;
+                __syncthreads();
+            }
+        }
 
         if (active) {
             int n_acc;
-            if constexpr (KPL8 > 0) {
-                if (rows == 8)
-                    n_acc = qap_wave_sweep<8, KPL8, KP>(I, C, F, F8, D, cls, tw, pr, t, group, word, cost);
-                else
+            if ((MODE & 2) && quad) {
+                cost = qcost[wave];
+                n_acc = qacc[wave];
+            } else if ((MODE & 1) && rows == 2) {
+                if constexpr ((MODE & 1) != 0)
+                    n_acc = qap_wave_sweep_tab<KPL4, KP>(I, C, F, D, cls, tw, pr, PT, ab, dt, t, group, word, cost,
+                                                         fresh);
+            } else {
+                fresh = false;  // the other paths do not keep the table
+                if constexpr (KPL8 > 0) {
+                    if (rows == 8)
+                        n_acc = qap_wave_sweep<8, KPL8, KP>(I, C, F, F8, D, cls, tw, pr, t, group, word, cost);
+                    else
+                        n_acc = rows == 4
+                                    ? qap_wave_sweep<4, KPL4, KP>(I, C, F, F8, D, cls, tw, pr, t, group, word, cost)
+                                    : qap_wave_sweep1<KPL1, KP>(I, C, F, D, cls, tw, pr, t, group, word, cost);
+                } else {
                     n_acc = rows == 4 ? qap_wave_sweep<4, KPL4, KP>(I, C, F, F8, D, cls, tw, pr, t, group, word, cost)
                                       : qap_wave_sweep1<KPL1, KP>(I, C, F, D, cls, tw, pr, t, group, word, cost);
-            } else {
-                n_acc = rows == 4 ? qap_wave_sweep<4, KPL4, KP>(I, C, F, F8, D, cls, tw, pr, t, group, word, cost)
-                                  : qap_wave_sweep1<KPL1, KP>(I, C, F, D, cls, tw, pr, t, group, word, cost);
+                }
             }
             acc_total += (unsigned long long)n_acc;
             if (C.rows == 0) {
                 // acceptance of this sweep: above 3/10 one proposal per step,
-                // below 1/16 eight, else four
+                // below 1/16 eight, else four; below 1/kTabAccDen the table
+                // mode, when its table is current or the launch has sweeps
+                // enough left to repay building it
                 rows = 10 * n_acc > 3 * npairs ? 1 : (16 * n_acc < npairs && KPL8 > 0) ? 8 : 4;
+                if (tab_ok && kTabAccDen * n_acc < npairs && (fresh || C.n_sweeps - s - 1 >= kTabMinSweeps))
+                    rows = 2;
             }
             // sweep end
             bool imp = false;
@@ -581,6 +1037,8 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
                     R.best_perm[(size_t)rep * n + f] = pr[f];
             }
         }
+        if ((MODE & 2) && lane == 0)
+            qrows[wave] = active ? (C.rows == 3 ? 3 : rows) : 0;
         __syncthreads();
     }
 
@@ -615,11 +1073,12 @@ __device__ __forceinline__ void qap_dispatch_kpl(int n, Fn &&fn) {
         fn(integral_constant<int, 16>{}, integral_constant<int, 4>{}, integral_constant<int, 0>{});
 }
 
+template <int MODE>
 __global__ void __launch_bounds__(1024) qap_sweep_kernel(QapDev I, QapRepDev R, QapCall C, bool mix) {
     extern __shared__ __align__(16) uint8_t smem[];
     qap_dispatch_kpl(I.n, [&](auto k4, auto k1, auto k8) {
-        qap_sweep_block<decltype(k4)::value, decltype(k1)::value, decltype(k8)::value>(I, R, C, blockIdx.x, mix,
-                                                                                      smem);
+        qap_sweep_block<decltype(k4)::value, decltype(k1)::value, decltype(k8)::value, MODE>(I, R, C, blockIdx.x,
+                                                                                            mix, smem);
     });
 }
 
@@ -630,8 +1089,8 @@ __global__ void __launch_bounds__(1024) qap_sweep_batch_kernel(const QapJob *job
         const int2 w = items[it];
         const QapJob &J = jobs[w.x];
         qap_dispatch_kpl(J.I.n, [&](auto k4, auto k1, auto k8) {
-            qap_sweep_block<decltype(k4)::value, decltype(k1)::value, decltype(k8)::value>(J.I, J.R, J.C, w.y,
-                                                                                          false, smem);
+            qap_sweep_block<decltype(k4)::value, decltype(k1)::value, decltype(k8)::value, 0>(J.I, J.R, J.C, w.y,
+                                                                                             false, smem);
         });
         __syncthreads();
     }
@@ -703,14 +1162,8 @@ __global__ void qap_tally_kernel(QapRepDev R) {
 
 }  // namespace
 
-// flow row bytes 16 * KP of qap_sweep_block for qap_dispatch_kpl's KPL4
-int qap_flow_row(int n) { return n <= 64 ? 64 : n <= 112 ? 128 : 256; }
-
 size_t qap_sweep_lds_bytes(int n, int n_classes, int stride) {
-    const size_t nn = (size_t)n * n;
-    return align_up((size_t)n * qap_flow_row(n), 16) + (n <= 112 ? align_up((size_t)n * 128, 16) : 0) +
-           align_up(nn, 16) + kRepPerBlock * align_up(n, 4) +
-           align_up(n, 16) + (size_t)n_classes * stride * sizeof(uint32_t);
+    return qap_base_lds(n, n_classes, stride) + (qap_tab_fits(n, n_classes, stride) ? qap_tab_lds(n) : 0);
 }
 
 hipError_t qap_launch_init(const QapDev &I, const QapRepDev &R, uint32_t key0, uint32_t key1, hipStream_t s) {
@@ -739,12 +1192,26 @@ hipError_t qap_launch_sweep(const QapDev &I, const QapRepDev &R, const QapCall &
                      lds_mix <= kLdsBytes;
     const size_t lds = mix ? lds_mix : qap_sweep_lds_bytes(I.n, C.n_classes, C.stride);
     // once per process (thread-safe initialization)
-    static const hipError_t attr = hipFuncSetAttribute((const void *)qap_sweep_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                       (int)kLdsBytes);
+    static const hipError_t attr = [] {
+        hipError_t e = hipSuccess;
+        for (const void *f : {(const void *)qap_sweep_kernel<0>, (const void *)qap_sweep_kernel<1>,
+                              (const void *)qap_sweep_kernel<2>, (const void *)qap_sweep_kernel<6>})
+            if (e == hipSuccess)
+                e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
+        return e;
+    }();
     if (attr != hipSuccess)
         return attr;
     const int blocks = (R.n_rep + kRepPerBlock - 1) / kRepPerBlock;
-    hipLaunchKernelGGL(qap_sweep_kernel, dim3(blocks), dim3(kBlockThreads), lds, s, I, R, C, mix);
+    // the table mode and four replicas per wave are kernels of their own
+    if (C.rows == 2 || C.tab_allow)
+        hipLaunchKernelGGL(qap_sweep_kernel<1>, dim3(blocks), dim3(kBlockThreads), lds, s, I, R, C, mix);
+    else if ((C.rows == 3 || C.quad_allow) && C.quad_allow == 4)
+        hipLaunchKernelGGL(qap_sweep_kernel<6>, dim3(blocks), dim3(kBlockThreads), lds, s, I, R, C, mix);
+    else if (C.rows == 3 || C.quad_allow)
+        hipLaunchKernelGGL(qap_sweep_kernel<2>, dim3(blocks), dim3(kBlockThreads), lds, s, I, R, C, mix);
+    else
+        hipLaunchKernelGGL(qap_sweep_kernel<0>, dim3(blocks), dim3(kBlockThreads), lds, s, I, R, C, mix);
     return hipGetLastError();
 }
 

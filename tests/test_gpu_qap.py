@@ -82,14 +82,16 @@ def test_qap_full_size_n100_r4096_short_schedule():
     p.compare()
 
 
-@pytest.mark.parametrize("rows", ["1", "4", "8", "0"])
+@pytest.mark.parametrize("rows", ["1", "4", "8", "2", "3", "0"])
 def test_qap_every_step_width_matches_oracle(rows, monkeypatch):
     """The number of proposals a wave evaluates per step (pinned to 1, 4 or 8,
-    or chosen per sweep from the acceptance rate) never changes the result:
-    sizes on each side of the width limits, and a schedule that crosses from
-    mostly-accepted to mostly-rejected sweeps inside one call."""
+    to the table mode (2), to four replicas per wave (3, whole workgroups of
+    16 replicas only), or chosen per sweep from the acceptance rate) never
+    changes the result: sizes on each side of the width limits, and a
+    schedule that crosses from mostly-accepted to mostly-rejected sweeps
+    inside one call."""
     monkeypatch.setenv("NMC_QAP_ROWS", rows)
-    for n, R in ((45, 9), (100, 6), (130, 5), (7, 4), (10, 3)):
+    for n, R in ((45, 9), (100, 6), (130, 5), (7, 4), (10, 3), (64, 32), (100, 16), (150, 48), (23, 16)):
         say(f"case: qap width={rows} n={n} R={R}")
         F, D = instances.gen_qap(n, SEED + 3 * n)
         sc = beta_scale(F, D)
@@ -137,3 +139,49 @@ def test_accept_count_qap():
     assert 0 <= cold < 4 * R * n * (n - 1) // 2
     rep.anneal(np.full((1, 4), 1e-4))
     assert rep.accept_count() > cold
+
+
+@pytest.mark.parametrize("n,R", [(31, 17), (100, 20), (150, 6)])
+def test_qap_table_mode_switches_match_oracle(n, R, monkeypatch):
+    """The per-sweep choice enters the table mode once a sweep accepts fewer
+    than 1/128 of the proposals and enough sweeps remain, keeps its table
+    across sweeps, leaves it when the acceptance rises again (a hot reanneal
+    class) and re-enters later; every launch and mode switch stays bit-exact
+    with the oracle, including the best-state snapshots and first hits."""
+    say(f"case: qap table-mode switches n={n} R={R}")
+    monkeypatch.setenv("NMC_QAP_TAB", "1")  # off by default (slower on MI355X)
+    F, D = instances.gen_qap(n, SEED + 7 * n)
+    sc = beta_scale(F, D)
+    p = QapPair(F, D, R, SEED + 2 * n)
+    sched = np.concatenate([np.geomspace(0.05, 6.0, 12), np.full(20, 6.0), np.full(6, 0.3), np.full(14, 8.0)])
+    p.anneal(sched[None, :] * sc, target=0)
+    p.compare()
+    first = int(p.orep.best.min())
+    cls = p.backbone(1, 2)
+    p.anneal(reanneal_profile(16, sc, beta_hot=0.2, beta_end=7.0), profile="backbone", class_of=cls, target=first)
+    p.compare()
+    # a one-sweep launch after table-mode sweeps takes another width
+    p.anneal(np.full((1, 1), 7.0 * sc))
+    p.compare()
+    p.anneal(np.full((1, 12), 7.0 * sc))
+    p.compare()
+    acc = p.rep.accept_count()
+    assert 0 < acc < R * n * (n - 1) // 2 * 90
+
+
+@pytest.mark.parametrize("n,R,rpw", [(40, 32, "2"), (100, 48, "2"), (100, 48, "4"), (130, 16, "2"), (20, 32, "4")])
+def test_qap_multi_replica_waves_match_oracle(n, R, rpw, monkeypatch):
+    """Two or four replicas per wave, chosen per sweep for whole workgroups
+    of hot replicas (NMC_QAP_RPW), switching to one replica per wave as the
+    schedule cools and back for a hot reanneal: bit-exact with the oracle."""
+    say(f"case: qap {rpw} replicas per wave n={n} R={R}")
+    monkeypatch.setenv("NMC_QAP_RPW", rpw)
+    F, D = instances.gen_qap(n, SEED + 5 * n)
+    sc = beta_scale(F, D)
+    p = QapPair(F, D, R, SEED + 3 * n)
+    sched = np.concatenate([np.full(4, 0.05), np.geomspace(0.05, 5.0, 10), np.full(3, 0.1), np.full(3, 5.0)])
+    p.anneal(sched[None, :] * sc, target=0)
+    p.compare()
+    cls = p.backbone(1, 2)
+    p.anneal(reanneal_profile(6, sc, beta_hot=0.05, beta_end=0.2), profile="backbone", class_of=cls)
+    p.compare()
