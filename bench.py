@@ -36,6 +36,7 @@ S_ANNEAL, ROUNDS, S_RE = 2000, 3, 1000
 BETA0, BETA1, BETA_HOT = 0.1, 4.0, 0.5
 CLASS_CAP = 1024
 BLOCK_THREADS = 0
+RPW = 0  # k-SAT replicas per sweep workgroup (0: the library's default, 4)
 # VALU lane-operations the sweep kernel issues per (variable, clause slot) for
 # its 4 replicas, and per variable for the acceptance step, counted in the
 # kernel's instruction stream.
@@ -116,6 +117,8 @@ def run_path(inst, seed, target, nmc, stream=None, profile=False):
     rep = nmc.Replicas(inst, R, seed, stream)
     if BLOCK_THREADS:
         rep.set_tuning(BLOCK_THREADS)
+    if RPW:
+        rep.set_replicas_per_workgroup(RPW)
     rep.set_profiling(profile)
     rep.anneal(instances.linear_schedule(BETA0, BETA1, S_ANNEAL)[None, :], target=target, stream=stream)
     for _ in range(ROUNDS):
@@ -182,13 +185,14 @@ def bench_batch(nmc, torch, seed, n_instances=256):
     out["batched_sa"] = summarize(wall, attempts, [None if (fh := s.best_energy()["first_hit"])[fh >= 0].size == 0
                                                    else float(fh[fh >= 0].min()) / S_TOT * wall for s in sets])
     out["batched_sa"]["block_threads"] = block
+    out["batched_sa"]["sets_with_8_replicas_per_workgroup"] = sum(1 for s in sets if s.replicas_per_workgroup() == 8)
     bt.free()
     del sets
 
     # (3) NMC, all instances in one graph: anneal -> 2 x (backbone -> reanneal)
     sets = make(0)
     bn = nmc.Batch(sets)
-    bn.set_tuning(block)
+    bn.tune(2)  # workgroup size and, per set, 4 or 8 replicas per workgroup
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     bn.run_plan(a_beta, RND, r_beta, 9, 10, True, targets=targets, use_graph=True, chunk_sweeps=CHUNK)
@@ -608,14 +612,19 @@ def serve_calibration(nmc, seed):
     return {"ksat_density": kinfo, "qap_ratio": [q[0] for q in qinfo], "qap_beta_scale": [q[1] for q in qinfo]}
 
 
-def serve_requests(seed, seconds):
-    """The request stream and its instances.  Generated by a pool of worker
-    processes, so this must run before anything in the process touches the
-    GPU: a process that has initialised HIP must not fork."""
+def serve_requests(seed, seconds, procs=16):
+    """The request stream and its instances, generated by `procs` worker
+    processes (in this process when procs <= 1).  The pool must be created
+    before anything in the process touches the GPU: a process that has
+    initialised HIP must not fork.  Under a profiler, whose library every
+    forked child inherits, pass procs = 0."""
+    mix = instances.serve_mix(SERVE_RATE, seconds, seed)
+    procs = min(procs, os.cpu_count() or 1)
+    if procs <= 1:
+        return mix, [_serve_gen(m) for m in mix]
     from multiprocessing import get_context
 
-    mix = instances.serve_mix(SERVE_RATE, seconds, seed)
-    with get_context("fork").Pool(max(1, min(16, os.cpu_count() or 1))) as pool:
+    with get_context("fork").Pool(procs) as pool:
         data = pool.map(_serve_gen, mix, chunksize=8)
     return mix, data
 
@@ -817,7 +826,7 @@ def cpu_baseline(cp, lits, seed):
 
 
 def main():
-    global BLOCK_THREADS, CLASS_CAP
+    global BLOCK_THREADS, CLASS_CAP, R, RPW
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
@@ -827,6 +836,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="default workload only: skip the C1 latency, short batched and short served sections")
     ap.add_argument("--block-threads", type=int, default=0)
+    ap.add_argument("--replicas", type=int, default=R, help="replicas of the N=50000 workload (default 1024)")
+    ap.add_argument("--rpw", type=int, default=0, help="k-SAT replicas per sweep workgroup: 4 or 8 (0: 4)")
     ap.add_argument("--class-cap", type=int, default=CLASS_CAP)
     ap.add_argument("--workload", choices=["nmc", "batch", "qap", "serve", "apt", "lbp", "alg1", "c1"], default="nmc",
                     help="nmc: the N=50000 NMC path (default); batch: 256 mixed instances, batched vs "
@@ -837,6 +848,9 @@ def main():
     ap.add_argument("--pt-rounds", type=int, default=APT_ROUNDS)
     ap.add_argument("--pt-sweeps-per-round", type=int, default=1)
     ap.add_argument("--serve-seconds", type=float, default=SERVE_SECONDS)
+    ap.add_argument("--serve-procs", type=int, default=16,
+                    help="processes generating the served requests' instances (0: in this process, e.g. under "
+                         "a profiler)")
     ap.add_argument("--sweeps-only", type=int, default=0,
                     help="only time one homogeneous anneal of this many sweeps (for counter profiles) and exit")
     ap.add_argument("--qap-curve", type=int, default=0,
@@ -858,14 +872,16 @@ def main():
 
     BLOCK_THREADS = args.block_threads
     CLASS_CAP = args.class_cap
+    R = args.replicas
+    RPW = args.rpw
 
     # the serving stream's instances come from a process pool, created before
     # this process touches the GPU (a HIP-initialised process must not fork)
     pre_serve = None
     if args.workload == "serve":
-        pre_serve = serve_requests(instances.DEFAULT_SEED, args.serve_seconds)
+        pre_serve = serve_requests(instances.DEFAULT_SEED, args.serve_seconds, args.serve_procs)
     elif args.workload == "nmc" and not args.sweeps_only and not args.copy_probe_mib and not args.no_extras:
-        pre_serve = serve_requests(instances.DEFAULT_SEED, SHORT_SERVE_SECONDS)
+        pre_serve = serve_requests(instances.DEFAULT_SEED, SHORT_SERVE_SECONDS, args.serve_procs)
 
     torch.cuda.set_device(0)
     if args.copy_probe_mib:
@@ -947,6 +963,8 @@ def main():
         rep = nmc.Replicas(inst, R, seed)
         if BLOCK_THREADS:
             rep.set_tuning(BLOCK_THREADS)
+        if RPW:
+            rep.set_replicas_per_workgroup(RPW)
         rep.set_profiling(True)
         rep.anneal(instances.linear_schedule(BETA0, BETA1, S_ANNEAL)[None, :args.sweeps_only])
         kt = rep.kernel_time()
@@ -993,9 +1011,9 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int32", "data": "synthetic",
-        "config": {"workload": "NMC random 4-SAT N=50000 alpha=9.9 M=495000, 1024 replicas, "
+        "config": {"workload": f"NMC random 4-SAT N=50000 alpha=9.9 M=495000, {R} replicas, "
                                "anneal 2000 + 3x(backbone + reanneal 1000)",
-                   "n_vars": N, "n_clauses": M, "k": K, "replicas": R,
+                   "n_vars": N, "n_clauses": M, "k": K, "replicas": R, "replicas_per_workgroup": RPW or 4,
                    "sweeps": S_ANNEAL + ROUNDS * S_RE, "class_cap": CLASS_CAP,
                    "colors": inst.info.n_colors, "parallelism": "replicas"},
         "best_energy": last[1]["best"], "replicas_at_zero": last[1]["n_at_zero"],

@@ -449,6 +449,25 @@ int nmc_replicas_info(const nmc_replicas *rep, int32_t *n_replicas, uint64_t *se
  * wave, 16 per 1024-thread workgroup, and ignore it. */
 int nmc_set_tuning(nmc_replicas *rep, int32_t block_threads);
 
+/* k-SAT replicas per sweep workgroup: 4 (0 = default; one group, bits 0..3
+ * of a spin byte in LDS) or 8 (two groups sharing each spin byte, so every
+ * clause record read, address decode and LDS gather serves 8 replicas; half
+ * as many workgroups).  Used by nmc_anneal / nmc_reanneal and batched calls
+ * (not by tempering).  Results never depend on it.  QAP: UNSUPPORTED. */
+int nmc_set_replicas_per_workgroup(nmc_replicas *rep, int32_t reps);
+
+/* The set's current k-SAT sweep workgroup size and replicas per workgroup
+ * (QAP: 0 replicas per workgroup); either output may be NULL. */
+int nmc_get_tuning(const nmc_replicas *rep, int32_t *block_threads, int32_t *reps_per_workgroup);
+
+/* Tunes one k-SAT replica set: times probe_sweeps sweeps on a copy of its
+ * states (the set does not move) for every workgroup size (64 .. 1024) and
+ * then 4 or 8 replicas per workgroup (nmc_batch_tune on a batch of this one
+ * set), keeps the fastest and returns it (outputs optional).
+ * Errors: INVALID, UNSUPPORTED (QAP), DEVICE. */
+int nmc_tune(nmc_replicas *rep, int32_t probe_sweeps, int32_t *block_threads, int32_t *reps_per_workgroup,
+             void *stream);
+
 /* When enabled, every sweep-kernel launch is bracketed by HIP events on the
  * launch stream; nmc_kernel_time() then returns the summed kernel time (ms),
  * the number of sweep-kernel launches and the Metropolis attempts they made
@@ -535,9 +554,15 @@ int nmc_batch_set_members(nmc_batch *batch, nmc_replicas *const *sets, int32_t n
  * depend on it. */
 int nmc_batch_set_tuning(nmc_batch *batch, int32_t block_threads);
 
-/* Time each candidate workgroup size (64, 128, 256, 512, 1024) on probe_sweeps
- * sweeps run on copies of the sets' states (the sets themselves do not move),
- * keep the fastest for this batch and return it in *chosen. */
+/* The autotuner.  On copies of the sets' states (the sets themselves do not
+ * move), probe_sweeps sweeps of every k-SAT set in one batched launch:
+ * (1) for each candidate workgroup size (64, 128, 256, 512, 1024) with 4
+ * replicas per workgroup; the fastest is kept for this batch and returned in
+ * *chosen; (2) then per set, the replicas per workgroup (4, or 8 sharing each
+ * spin byte; nmc_set_replicas_per_workgroup): the sets fall into up to four
+ * classes by work (N x R), and each class in turn takes 8 when that makes the
+ * batched probe at least 2 % faster.  Each set keeps its choice for later
+ * calls.  Results never depend on the tuning. */
 int nmc_batch_tune(nmc_batch *batch, int32_t probe_sweeps, int32_t *chosen, void *stream);
 
 /* nmc_anneal for every set of the batch in one launch per kernel kind: one

@@ -693,6 +693,7 @@ struct nmc_replicas {
     int32_t *scratch_energy = nullptr;  // [4G] or [R] (int64 for QAP)
     bool has_backbone = false;
     int32_t block_threads = 1024;
+    int32_t gpw = 1;  // k-SAT sweep: groups of 4 replicas per workgroup (1 or 2)
     // library-owned threshold / class upload buffer
     uint8_t *tab_dev = nullptr;
     size_t tab_cap = 0;
@@ -1036,6 +1037,7 @@ static int anneal_impl(nmc_replicas *P, const double *beta, int32_t n_classes, i
         C.check_start = 1;
         C.key0 = (uint32_t)P->seed;
         C.key1 = (uint32_t)(P->seed >> 32);
+        C.gpw = P->gpw;
         HIP_OR_FAIL(ksat_launch_sweep(I->ksat_dev(), P->k, C, P->block_threads, s));
     } else {
         QapCall C{};
@@ -1307,6 +1309,29 @@ int nmc_set_tuning(nmc_replicas *P, int32_t block_threads) {
     return ok();
 }
 
+int nmc_set_replicas_per_workgroup(nmc_replicas *P, int32_t reps) {
+    if (!P)
+        return fail(NMC_ERR_INVALID, "NULL replicas");
+    if (P->inst->kind != NMC_KIND_KSAT)
+        return fail(NMC_ERR_UNSUPPORTED, "replicas per workgroup is a k-SAT setting");
+    if (reps == 0)
+        reps = kGroup;
+    if (reps != kGroup && reps != 2 * kGroup)
+        return fail(NMC_ERR_INVALID, "replicas per workgroup must be 4 or 8");
+    P->gpw = reps / kGroup;
+    return ok();
+}
+
+int nmc_get_tuning(const nmc_replicas *P, int32_t *block_threads, int32_t *reps_per_workgroup) {
+    if (!P)
+        return fail(NMC_ERR_INVALID, "NULL replicas");
+    if (block_threads)
+        *block_threads = P->block_threads;
+    if (reps_per_workgroup)
+        *reps_per_workgroup = P->inst->kind == NMC_KIND_KSAT ? P->gpw * kGroup : 0;
+    return ok();
+}
+
 int nmc_set_profiling(nmc_replicas *P, int32_t enable) {
     if (!P)
         return fail(NMC_ERR_INVALID, "NULL replicas");
@@ -1444,6 +1469,7 @@ static int pt_run_impl(nmc_replicas *P, const double *beta, int32_t n_temps, int
             C.key0 = X.key0;
             C.key1 = X.key1;
             C.reps_per_row = chains;
+            C.gpw = 1;  // each sweep workgroup at one temperature
             HIP_OR_FAIL(ksat_launch_sweep(I->ksat_dev(), P->k, C, P->block_threads, s));
         } else {
             QapCall C{};
@@ -2302,9 +2328,10 @@ int build_batch(nmc_batch *B, const std::vector<PhaseSpec> &phases, bool with_ba
                 J.C.check_start = 1;
                 J.C.key0 = (uint32_t)P->seed;
                 J.C.key1 = (uint32_t)(P->seed >> 32);
+                J.C.gpw = P->gpw;
                 std::memcpy(blob.host.data() + bp.off_kjobs + j * sizeof(KsatJob), &J, sizeof J);
-                const double cost = (double)P->inst->n * (P->inst->dmax + 1);
-                for (int g = 0; g < P->G; ++g)
+                const double cost = (double)P->inst->n * (P->inst->dmax + 1) * P->gpw;
+                for (int g = 0; g < (P->G + P->gpw - 1) / P->gpw; ++g)
                     items.push_back({cost, make_int2((int)j, g)});
                 bp.lds_k = std::max(bp.lds_k, ksat_sweep_lds_bytes(P->inst->n, ph.n_classes, stride_k));
                 bp.attempts += (double)P->R * P->inst->n * ph.n_sweeps;
@@ -2738,8 +2765,9 @@ int build_plans(nmc_batch *B, const std::vector<std::vector<SetPhase>> &ph, cons
                 J.C.check_start = 1;
                 J.C.key0 = (uint32_t)P->seed;
                 J.C.key1 = (uint32_t)(P->seed >> 32);
-                const double cost = (double)P->inst->n * (P->inst->dmax + 1);
-                for (int gi = 0; gi < P->G; ++gi)
+                J.C.gpw = P->gpw;
+                const double cost = (double)P->inst->n * (P->inst->dmax + 1) * P->gpw;
+                for (int gi = 0; gi < (P->G + P->gpw - 1) / P->gpw; ++gi)
                     kit.push_back({cost, make_int2((int)kj.size(), gi)});
                 lds_k = std::max(lds_k, ksat_sweep_lds_bytes(P->inst->n, cur->nc, stride_k));
                 att_k += (double)P->R * P->inst->n * len;
@@ -3309,52 +3337,122 @@ extern "C" int nmc_batch_tune(nmc_batch *B, int32_t probe_sweeps, int32_t *chose
         for (auto &c : clones)
             cptr.push_back(&c);
         std::vector<double> beta((size_t)probe_sweeps, 1.0);
-        int best_b = 0;
-        float best_ms = 0;
         int rc = NMC_OK;
         HIP_OR_FAIL(hipEventCreate(&guard.e0));
         HIP_OR_FAIL(hipEventCreate(&guard.e1));
         hipEvent_t e0 = guard.e0, e1 = guard.e1;
-        for (int cand : {64, 128, 256, 512, 1024}) {
-            B->block_threads = cand;
+        // kernel time of probe_sweeps sweeps of every clone, in one batched
+        // launch with the current settings
+        auto time_config = [&](float *ms) -> int {
             Blob blob;
             std::vector<BuiltPhase> built;
             BuiltBackbone bb;
             const std::vector<PhaseSpec> ph{PhaseSpec{beta.data(), 1, probe_sweeps, NMC_PROFILE_HOMOGENEOUS}};
-            rc = build_batch(B, ph, false, nullptr, nullptr, blob, built, bb, &cptr);
-            if (!rc)
-                rc = ensure_batch_mem(B, blob.host.size());
-            if (rc)
-                break;
+            int r = build_batch(B, ph, false, nullptr, nullptr, blob, built, bb, &cptr);
+            if (!r)
+                r = ensure_batch_mem(B, blob.host.size());
+            if (r)
+                return r;
             blob.host.clear();
             built.clear();
-            rc = build_batch(B, ph, false, nullptr, B->dev, blob, built, bb, &cptr);
-            if (rc)
-                break;
+            r = build_batch(B, ph, false, nullptr, B->dev, blob, built, bb, &cptr);
+            if (r)
+                return r;
             HIP_OR_FAIL(hipMemcpyAsync(B->dev, blob.host.data(), blob.host.size(), hipMemcpyHostToDevice, s));
             HIP_OR_FAIL(hipEventRecord(e0, s));
-            rc = enqueue_phase(B, built[0], s);
-            if (rc)
-                break;
+            r = enqueue_phase(B, built[0], s);
+            if (r)
+                return r;
             HIP_OR_FAIL(hipEventRecord(e1, s));
             HIP_OR_FAIL(hipEventSynchronize(e1));
+            HIP_OR_FAIL(hipEventElapsedTime(ms, e0, e1));
+            return NMC_OK;
+        };
+        // (1) the workgroup size, with 4 replicas per workgroup everywhere
+        for (auto &c : clones)
+            c.gpw = 1;
+        int best_b = 0;
+        float best_ms = 0;
+        for (int cand : {64, 128, 256, 512, 1024}) {
+            B->block_threads = cand;
             float ms = 0;
-            HIP_OR_FAIL(hipEventElapsedTime(&ms, e0, e1));
+            rc = time_config(&ms);
+            if (rc)
+                break;
             if (best_b == 0 || ms < best_ms) {
                 best_b = cand;
                 best_ms = ms;
+            }
+        }
+        // (2) replicas per workgroup (4, or 8 sharing each spin byte), per
+        // set: the sets fall into up to four classes by work (N x R), and each
+        // class takes 8 when that makes the whole batch at least 2 % faster
+        std::vector<int> gsel(ks.size(), 1);
+        if (!rc) {
+            B->block_threads = best_b;
+            std::vector<size_t> ord(ks.size());
+            std::iota(ord.begin(), ord.end(), 0);
+            std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) {
+                return (double)ks[a]->inst->n * ks[a]->R < (double)ks[b]->inst->n * ks[b]->R;
+            });
+            const size_t nb = std::min<size_t>(4, ks.size());
+            for (size_t bkt = 0; bkt < nb && !rc; ++bkt) {
+                const size_t lo = ord.size() * bkt / nb, hi = ord.size() * (bkt + 1) / nb;
+                bool any = false;
+                for (size_t i = lo; i < hi; ++i)
+                    if (ks[ord[i]]->G > 1) {
+                        clones[ord[i]].gpw = 2;
+                        any = true;
+                    }
+                if (!any)
+                    continue;
+                float ms = 0;
+                rc = time_config(&ms);
+                if (!rc && ms < 0.98f * best_ms) {
+                    best_ms = ms;
+                    for (size_t i = lo; i < hi; ++i)
+                        gsel[ord[i]] = clones[ord[i]].gpw;
+                } else {
+                    for (size_t i = lo; i < hi; ++i)
+                        clones[ord[i]].gpw = 1;
+                }
             }
         }
         if (rc)
             return rc;
         guard.keep = true;
         B->block_threads = best_b;
+        for (size_t i = 0; i < ks.size(); ++i)
+            ks[i]->gpw = gsel[i];
         if (chosen)
             *chosen = best_b;
         return ok();
     } catch (const std::bad_alloc &) {
         return fail(NMC_ERR_CAPACITY, "host allocation failed");
     }
+}
+
+extern "C" int nmc_tune(nmc_replicas *P, int32_t probe_sweeps, int32_t *block_threads, int32_t *reps_per_workgroup,
+                        void *stream) {
+    if (!P)
+        return fail(NMC_ERR_INVALID, "NULL replicas");
+    if (P->inst->kind != NMC_KIND_KSAT)
+        return fail(NMC_ERR_UNSUPPORTED, "the tuner's settings are k-SAT settings");
+    nmc_batch *B = nullptr;
+    int rc = nmc_batch_create(&P, 1, &B);
+    if (rc)
+        return rc;
+    int32_t chosen = 0;
+    rc = nmc_batch_tune(B, probe_sweeps, &chosen, stream);
+    nmc_batch_free(B);
+    if (rc)
+        return rc;
+    P->block_threads = chosen;
+    if (block_threads)
+        *block_threads = P->block_threads;
+    if (reps_per_workgroup)
+        *reps_per_workgroup = P->gpw * kGroup;
+    return ok();
 }
 
 // ---------------------------------------------------------------------------
@@ -3451,8 +3549,9 @@ extern "C" int nmc_batch_step(nmc_batch *B, const nmc_segment *segs, int32_t n_s
                     J.C.check_start = 1;
                     J.C.key0 = (uint32_t)P->seed;
                     J.C.key1 = (uint32_t)(P->seed >> 32);
-                    const double cost = (double)P->inst->n * (P->inst->dmax + 1);
-                    for (int gi = 0; gi < P->G; ++gi)
+                    J.C.gpw = P->gpw;
+                    const double cost = (double)P->inst->n * (P->inst->dmax + 1) * P->gpw;
+                    for (int gi = 0; gi < (P->G + P->gpw - 1) / P->gpw; ++gi)
                         kit.push_back({cost, make_int2((int)kj.size(), gi)});
                     lds_k = std::max(lds_k, ksat_sweep_lds_bytes(P->inst->n, nc, stride_k));
                     kj.push_back(J);

@@ -77,6 +77,7 @@ struct SweepCall {
     int32_t check_start;
     uint32_t key0, key1;
     int32_t reps_per_row;   // > 0: replica r reads table row r / reps_per_row (one [n_classes][stride] block per row)
+    int32_t gpw;            // groups of 4 replicas per workgroup: 1, or 2 (8 replicas share each spin byte in LDS)
 };
 
 // QAP: permutations as bytes, pair ranks in lexicographic order.

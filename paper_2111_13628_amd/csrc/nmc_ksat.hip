@@ -133,10 +133,29 @@ __global__ void ksat_reset_tallies_kernel(KsatRepDev R) {
     }
 }
 
-// n_sweeps full sweeps of every colour class for the 4 replicas of group g,
-// by the whole workgroup, with smem = the workgroup's dynamic LDS block.
+// One clause slot for the 8 replicas of two groups (spin bytes holding the
+// first group in bits 0..3, the second in bits 4..7): the same record and
+// gathers feed both accumulators.
+__device__ __forceinline__ void slot_step2(uint32_t &a0, uint32_t &a1, uint2 r) {
+    const uint32_t ad0 = r.x & kAddrMask;
+    const uint32_t ad1 = __builtin_amdgcn_alignbit(r.y, r.x, kAddrBits) & kAddrMask;
+    const uint32_t ad2 = __builtin_amdgcn_ubfe(r.y, 2 * kAddrBits - 32, kAddrBits);
+    const uint32_t sm = (uint32_t)__builtin_amdgcn_sbfe(r.y, 3 * kAddrBits - 32, 1);
+    const uint32_t sat = lds_load_u8(ad0) | lds_load_u8(ad1) | lds_load_u8(ad2);
+    a0 = (spread4(sat & 0xFu) ^ sm) + a0;
+    a1 = (spread4(sat >> 4) ^ sm) + a1;
+}
+
+// n_sweeps full sweeps of every colour class for the replicas of item g, by
+// the whole workgroup, with smem = the workgroup's dynamic LDS block.
+// GPW = 1: the 4 replicas of group g.  GPW = 2: the 8 replicas of groups 2g
+// and 2g + 1, held in one spin byte per variable (first group in bits 0..3),
+// so every clause record, address decode and LDS gather serves 8 replicas;
+// the random words and every result are those of the groups run one by one.
+template <int GPW>
 __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &R, const SweepCall &C, const int g,
                                             uint8_t *smem) {
+    constexpr int NR = kGroup * GPW;  // replicas of the item
     const int n = I.n;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & 63, nwaves = nthr >> 6;
@@ -145,22 +164,32 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
 
     uint8_t *xt = smem;
     uint32_t *tl = (uint32_t *)(smem + align_up(2 * n + 2, 16));
-    int *red = (int *)(tl + align_up(tab_words, 4));  // [0..3] dE sums, [4] improved mask
+    int *red = (int *)(tl + align_up(tab_words, 4));  // [0..NR) dE sums, [NR] improved mask
 
-    const int r0 = g * kGroup;
-    const int nact = min(kGroup, R.n_rep - r0);
+    const int g0 = g * GPW;  // first group of the item
+    const int r0 = g0 * kGroup;
+    const int nact = min(NR, R.n_rep - r0);
     const uint32_t amask = (1u << nact) - 1u;
-    // per-temperature tables (tempering): the group's replicas share one row
+    const bool second = GPW == 2 && g0 + 1 < R.n_groups;  // the item's second group exists
+    // per-temperature tables (tempering): the item's replicas share one row
     const uint32_t *tab = C.tab + (C.reps_per_row > 0 ? (size_t)(r0 / C.reps_per_row) * tab_words : 0);
 
-    // spin tables x and not-x from the group's row; rows and tables are
+    // spin tables x and not-x from the group rows; rows and tables are
     // 16-byte aligned when N is a multiple of 16, then moved 16 bytes a lane
-    uint8_t *xg = R.xs + (size_t)g * n;
+    uint8_t *xg = R.xs + (size_t)g0 * n;
     const bool wide = (n & 15) == 0;
     if (wide) {
         const uint32_t m4 = amask * 0x01010101u;
         for (int w = tid; w < n / 16; w += nthr) {
             uint4 b = reinterpret_cast<const uint4 *>(xg)[w];
+            if (GPW == 2 && second) {
+                // the second group's nibbles (values below 16) move to bits 4..7 of each byte
+                const uint4 h = reinterpret_cast<const uint4 *>(xg + n)[w];
+                b.x |= h.x << 4;
+                b.y |= h.y << 4;
+                b.z |= h.z << 4;
+                b.w |= h.w << 4;
+            }
             b.x &= m4;
             b.y &= m4;
             b.z &= m4;
@@ -170,7 +199,10 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
         }
     } else {
         for (int v = tid; v < n; v += nthr) {
-            const uint32_t b = xg[v] & amask;
+            uint32_t b = xg[v];
+            if (GPW == 2 && second)
+                b |= (uint32_t)xg[n + v] << 4;
+            b &= amask;
             xt[v] = (uint8_t)b;
             xt[n + v] = (uint8_t)(~b & amask);
         }
@@ -179,7 +211,7 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
         xt[2 * n] = 0;
         xt[2 * n + 1] = (uint8_t)amask;
     }
-    if (tid < 8)
+    if (tid < 16)
         red[tid] = 0;
     int E = 0, best = 0, fh = -1;
     if (tid < nact) {
@@ -199,7 +231,10 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
             tl[i] = tg[i];
         __syncthreads();
 
-        int d0 = 0, d1 = 0, d2 = 0, d3 = 0;
+        int dsum[NR];
+#pragma unroll
+        for (int j = 0; j < NR; ++j)
+            dsum[j] = 0;
         for (int c = 0; c < I.n_colors; ++c) {
             const int h0 = I.color_chunk[c], h1 = I.color_chunk[c + 1];
             // chunks of a class are sorted by slot count (descending); rounds
@@ -234,25 +269,34 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
                 // Slots come in 16-byte pairs; 8 slots of records are in flight
                 // while 4 are consumed (nslot is a multiple of 4, at least 4; the
                 // pair index is clamped so every load is in bounds).
-                uint32_t acc = 0;
+                uint32_t acc[GPW];
+#pragma unroll
+                for (int k = 0; k < GPW; ++k)
+                    acc[k] = 0;
+                auto step = [&](uint32_t x, uint32_t y) {
+                    if constexpr (GPW == 1)
+                        acc[0] = slot_step(acc[0], make_uint2(x, y));
+                    else
+                        slot_step2(acc[0], acc[GPW - 1], make_uint2(x, y));
+                };
                 const int lastp = nslot / 2 - 1;
                 uint4 q0 = rp[0], q1 = rp[(size_t)min(1, lastp) * kChunk];
                 uint4 q2 = rp[(size_t)min(2, lastp) * kChunk], q3 = rp[(size_t)min(3, lastp) * kChunk];
                 issue_fence();
                 for (int k = 0;; k += 2 * kSlotUnroll) {
-                    acc = slot_step(acc, make_uint2(q0.x, q0.y));
-                    acc = slot_step(acc, make_uint2(q0.z, q0.w));
-                    acc = slot_step(acc, make_uint2(q1.x, q1.y));
-                    acc = slot_step(acc, make_uint2(q1.z, q1.w));
+                    step(q0.x, q0.y);
+                    step(q0.z, q0.w);
+                    step(q1.x, q1.y);
+                    step(q1.z, q1.w);
                     if (k + kSlotUnroll >= nslot)
                         break;
                     q0 = rp[(size_t)min(k / 2 + 4, lastp) * kChunk];
                     q1 = rp[(size_t)min(k / 2 + 5, lastp) * kChunk];
                     issue_fence();
-                    acc = slot_step(acc, make_uint2(q2.x, q2.y));
-                    acc = slot_step(acc, make_uint2(q2.z, q2.w));
-                    acc = slot_step(acc, make_uint2(q3.x, q3.y));
-                    acc = slot_step(acc, make_uint2(q3.z, q3.w));
+                    step(q2.x, q2.y);
+                    step(q2.z, q2.w);
+                    step(q3.x, q3.y);
+                    step(q3.z, q3.w);
                     if (k + 2 * kSlotUnroll >= nslot)
                         break;
                     q2 = rp[(size_t)min(k / 2 + 6, lastp) * kChunk];
@@ -262,41 +306,49 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
                 const uint32_t nneg = lw < 0 ? 0u : ((uint32_t)lw >> 20) & 0xFFu;
                 // the lane's share of the closed form (sums mod 2^32 add up
                 // across lanes: an inert padding slot contributes 0)
-                uint32_t part = ((uint32_t)nslot - 2u * nneg) * 0x01010101u - nneg - acc;
-                for (int off = 1; off < (1 << lg); off <<= 1)
-                    part += (uint32_t)__shfl_xor((int)part, off, 64);
-                acc = 0x80808080u + part;
+#pragma unroll
+                for (int k = 0; k < GPW; ++k) {
+                    uint32_t part = ((uint32_t)nslot - 2u * nneg) * 0x01010101u - nneg - acc[k];
+                    for (int off = 1; off < (1 << lg); off <<= 1)
+                        part += (uint32_t)__shfl_xor((int)part, off, 64);
+                    acc[k] = 0x80808080u + part;
+                }
                 if (v >= 0) {
                     const uint32_t xi = lds_load_u8((uint32_t)v);
                     const uint32_t *T = tl + cl * C.stride;
-                    int de[kGroup];
-                    uint32_t thr[kGroup];
+                    int de[NR];
+                    uint32_t thr[NR];
                     uint32_t flip = 0, need = 0;
 #pragma unroll
-                    for (int j = 0; j < kGroup; ++j) {
-                        const int S = (int)((acc >> (8 * j)) & 0xFFu) - 128;
+                    for (int j = 0; j < NR; ++j) {
+                        const int S = (int)((acc[j >> 2] >> (8 * (j & 3))) & 0xFFu) - 128;
                         de[j] = ((xi >> j) & 1u) ? S : -S;
                         thr[j] = T[max(de[j], 0)];
                         const uint32_t on = (amask >> j) & 1u;
                         flip |= (on & (uint32_t)(de[j] <= 0)) << j;
                         need |= (on & (uint32_t)(de[j] > 0) & (uint32_t)(thr[j] != 0)) << j;
                     }
-                    if (need) {
-                        const uint4 u = philox4x32_10((uint32_t)v, t, (uint32_t)g, kStreamKsatSweep, C.key0, C.key1);
-                        flip |= ((need & 1u) && u.x < thr[0]) ? 1u : 0u;
-                        flip |= ((need & 2u) && u.y < thr[1]) ? 2u : 0u;
-                        flip |= ((need & 4u) && u.z < thr[2]) ? 4u : 0u;
-                        flip |= ((need & 8u) && u.w < thr[3]) ? 8u : 0u;
+#pragma unroll
+                    for (int k = 0; k < GPW; ++k) {
+                        // one generator call per group gives its 4 replicas' words
+                        if ((need >> (4 * k)) & 0xFu) {
+                            const uint4 u = philox4x32_10((uint32_t)v, t, (uint32_t)(g0 + k), kStreamKsatSweep,
+                                                          C.key0, C.key1);
+                            const int b = 4 * k;
+                            flip |= (((need >> b) & 1u) && u.x < thr[b]) ? 1u << b : 0u;
+                            flip |= (((need >> (b + 1)) & 1u) && u.y < thr[b + 1]) ? 2u << b : 0u;
+                            flip |= (((need >> (b + 2)) & 1u) && u.z < thr[b + 2]) ? 4u << b : 0u;
+                            flip |= (((need >> (b + 3)) & 1u) && u.w < thr[b + 3]) ? 8u << b : 0u;
+                        }
                     }
                     if (flip) {
                         n_acc += __builtin_popcount(flip);
                         const uint32_t nx = xi ^ flip;
                         lds_store_u8((uint32_t)v, nx);
                         lds_store_u8((uint32_t)(n + v), ~nx & amask);
-                        d0 += (flip & 1u) ? de[0] : 0;
-                        d1 += (flip & 2u) ? de[1] : 0;
-                        d2 += (flip & 4u) ? de[2] : 0;
-                        d3 += (flip & 8u) ? de[3] : 0;
+#pragma unroll
+                        for (int j = 0; j < NR; ++j)
+                            dsum[j] += ((flip >> j) & 1u) ? de[j] : 0;
                     }
                 }
             }
@@ -304,58 +356,79 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
         }
 
         // sweep end: exact energies, best, first hit, snapshot
-        d0 = wave_sum(d0);
-        d1 = wave_sum(d1);
-        d2 = wave_sum(d2);
-        d3 = wave_sum(d3);
-        if (lane == 0) {
-            if (d0) atomicAdd(&red[0], d0);
-            if (d1) atomicAdd(&red[1], d1);
-            if (d2) atomicAdd(&red[2], d2);
-            if (d3) atomicAdd(&red[3], d3);
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            const int dj = wave_sum(dsum[j]);
+            if (lane == 0 && dj)
+                atomicAdd(&red[j], dj);
         }
         __syncthreads();
         if (tid < nact) {
             E += red[tid];
             if (E < best) {
                 best = E;
-                atomicOr(&red[4], 1 << tid);
+                atomicOr(&red[NR], 1 << tid);
             }
             if (fh < 0 && E <= C.target)
                 fh = (int)(t + 1);
         }
         __syncthreads();
-        const uint32_t imp = (uint32_t)red[4];
+        const uint32_t imp = (uint32_t)red[NR];
         if (imp) {
-            uint8_t *bg = R.best_xs + (size_t)g * n;
-            if (wide) {
-                const uint32_t i4 = imp * 0x01010101u;
-                for (int w = tid; w < n / 16; w += nthr) {
-                    uint4 o = reinterpret_cast<const uint4 *>(bg)[w];
-                    const uint4 c = reinterpret_cast<const uint4 *>(xt)[w];
-                    o.x = (o.x & ~i4) | (c.x & i4);
-                    o.y = (o.y & ~i4) | (c.y & i4);
-                    o.z = (o.z & ~i4) | (c.z & i4);
-                    o.w = (o.w & ~i4) | (c.w & i4);
-                    reinterpret_cast<uint4 *>(bg)[w] = o;
+#pragma unroll
+            for (int k = 0; k < GPW; ++k) {
+                const uint32_t ik = (imp >> (4 * k)) & 0xFu;
+                if (!ik)
+                    continue;
+                uint8_t *bg = R.best_xs + (size_t)(g0 + k) * n;
+                if (wide) {
+                    const uint32_t i4 = ik * 0x01010101u;
+                    for (int w = tid; w < n / 16; w += nthr) {
+                        uint4 o = reinterpret_cast<const uint4 *>(bg)[w];
+                        uint4 c = reinterpret_cast<const uint4 *>(xt)[w];
+                        if (k) {
+                            c.x >>= 4;
+                            c.y >>= 4;
+                            c.z >>= 4;
+                            c.w >>= 4;
+                        }
+                        o.x = (o.x & ~i4) | (c.x & i4);
+                        o.y = (o.y & ~i4) | (c.y & i4);
+                        o.z = (o.z & ~i4) | (c.z & i4);
+                        o.w = (o.w & ~i4) | (c.w & i4);
+                        reinterpret_cast<uint4 *>(bg)[w] = o;
+                    }
+                } else {
+                    for (int v = tid; v < n; v += nthr)
+                        bg[v] = (uint8_t)((bg[v] & ~ik) | ((uint32_t)(xt[v] >> (4 * k)) & ik));
                 }
-            } else {
-                for (int v = tid; v < n; v += nthr)
-                    bg[v] = (uint8_t)((bg[v] & ~imp) | (xt[v] & imp));
             }
         }
         __syncthreads();
-        if (tid < 8)
+        if (tid < 16)
             red[tid] = 0;
     }
 
     __syncthreads();
-    if (wide) {
-        for (int w = tid; w < n / 16; w += nthr)
-            reinterpret_cast<uint4 *>(xg)[w] = reinterpret_cast<const uint4 *>(xt)[w];
-    } else {
-        for (int v = tid; v < n; v += nthr)
-            xg[v] = xt[v];
+#pragma unroll
+    for (int k = 0; k < GPW; ++k) {
+        if (k == 1 && !second)
+            break;
+        uint8_t *xk = xg + (size_t)k * n;
+        if (wide) {
+            for (int w = tid; w < n / 16; w += nthr) {
+                uint4 b = reinterpret_cast<const uint4 *>(xt)[w];
+                if (GPW == 2) {
+                    const uint32_t sh = 4 * k;
+                    b = make_uint4((b.x >> sh) & 0x0F0F0F0Fu, (b.y >> sh) & 0x0F0F0F0Fu, (b.z >> sh) & 0x0F0F0F0Fu,
+                                   (b.w >> sh) & 0x0F0F0F0Fu);
+                }
+                reinterpret_cast<uint4 *>(xk)[w] = b;
+            }
+        } else {
+            for (int v = tid; v < n; v += nthr)
+                xk[v] = GPW == 2 ? (uint8_t)((xt[v] >> (4 * k)) & 0xFu) : xt[v];
+        }
     }
     if (tid < nact) {
         R.energy[r0 + tid] = E;
@@ -370,10 +443,11 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
         atomicAdd(R.accepted, acc_w);
 }
 
-// One replica group per workgroup (group = blockIdx.x).
+// One item (GPW groups of 4 replicas) per workgroup (item = blockIdx.x).
+template <int GPW>
 __global__ void __launch_bounds__(1024) ksat_sweep_kernel(KsatDev I, KsatRepDev R, SweepCall C) {
     extern __shared__ __align__(16) uint8_t smem[];
-    sweep_group(I, R, C, blockIdx.x, smem);
+    sweep_group<GPW>(I, R, C, blockIdx.x, smem);
 }
 
 // Batched launch: many replica sets (jobs) of different instances in one
@@ -385,7 +459,10 @@ __global__ void __launch_bounds__(1024) ksat_sweep_batch_kernel(const KsatJob *j
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int2 w = items[it];
         const KsatJob &J = jobs[w.x];
-        sweep_group(J.I, J.R, J.C, w.y, smem);
+        if (J.C.gpw == 2)
+            sweep_group<2>(J.I, J.R, J.C, w.y, smem);
+        else
+            sweep_group<1>(J.I, J.R, J.C, w.y, smem);
         __syncthreads();
     }
 }
@@ -576,7 +653,7 @@ int grid_for(size_t total, int block) {
 }  // namespace
 
 size_t ksat_sweep_lds_bytes(int n, int n_classes, int stride) {
-    return align_up(2 * (size_t)n + 2, 16) + align_up((size_t)n_classes * stride, 4) * 4 + 8 * sizeof(int);
+    return align_up(2 * (size_t)n + 2, 16) + align_up((size_t)n_classes * stride, 4) * 4 + 16 * sizeof(int);
 }
 
 hipError_t launch_set_status(const SetStatusSrc *src, SetStatus *out, int n_sets, hipStream_t s) {
@@ -615,11 +692,20 @@ hipError_t ksat_launch_sweep(const KsatDev &I, const KsatRepDev &R, const SweepC
                              hipStream_t s) {
     const size_t lds = ksat_sweep_lds_bytes(I.n, C.n_classes, C.stride);
     // once per process (thread-safe initialization)
-    static const hipError_t attr = hipFuncSetAttribute((const void *)ksat_sweep_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                       (int)kLdsBytes);
+    static const hipError_t attr = [] {
+        hipError_t e = hipFuncSetAttribute((const void *)ksat_sweep_kernel<1>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void *)ksat_sweep_kernel<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)kLdsBytes);
+        return e;
+    }();
     if (attr != hipSuccess)
         return attr;
-    hipLaunchKernelGGL(ksat_sweep_kernel, dim3(R.n_groups), dim3(block_threads), lds, s, I, R, C);
+    if (C.gpw == 2)
+        hipLaunchKernelGGL(ksat_sweep_kernel<2>, dim3((R.n_groups + 1) / 2), dim3(block_threads), lds, s, I, R, C);
+    else
+        hipLaunchKernelGGL(ksat_sweep_kernel<1>, dim3(R.n_groups), dim3(block_threads), lds, s, I, R, C);
     return hipGetLastError();
 }
 

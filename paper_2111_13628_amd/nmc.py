@@ -130,6 +130,9 @@ _SIGS = {
     "nmc_set_state": ([_P, _P, _SZ, _U32, _P], ctypes.c_int),
     "nmc_replicas_info": ([_P, _P, _P, _P], ctypes.c_int),
     "nmc_set_tuning": ([_P, _I32], ctypes.c_int),
+    "nmc_set_replicas_per_workgroup": ([_P, _I32], ctypes.c_int),
+    "nmc_get_tuning": ([_P, _P, _P], ctypes.c_int),
+    "nmc_tune": ([_P, _I32, _P, _P, _P], ctypes.c_int),
     "nmc_set_profiling": ([_P, _I32], ctypes.c_int),
     "nmc_kernel_time": ([_P, _P, _P, _P, _I32], ctypes.c_int),
     "nmc_accept_count": ([_P, _P, _I32, _P], ctypes.c_int),
@@ -438,6 +441,21 @@ class Replicas:
 
     def set_tuning(self, block_threads=0):
         _check(lib().nmc_set_tuning(self._h, int(block_threads)))
+
+    def set_replicas_per_workgroup(self, reps=0):
+        """k-SAT sweep workgroups of 4 (default) or 8 replicas."""
+        _check(lib().nmc_set_replicas_per_workgroup(self._h, int(reps)))
+
+    def replicas_per_workgroup(self):
+        r = ctypes.c_int32()
+        _check(lib().nmc_get_tuning(self._h, None, ctypes.byref(r)))
+        return r.value
+
+    def tune(self, probe_sweeps=3, stream=None):
+        """nmc_tune: (workgroup size, replicas per workgroup) chosen and kept."""
+        b, r = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().nmc_tune(self._h, int(probe_sweeps), ctypes.byref(b), ctypes.byref(r), _stream(stream)))
+        return b.value, r.value
 
     def set_profiling(self, enable=True):
         _check(lib().nmc_set_profiling(self._h, int(bool(enable))))

@@ -280,3 +280,29 @@ def test_per_set_plans_against_oracle():
         assert (be["first_hit"] == fh).all()
         assert s.sweeps_done() == sw
     b.free()
+
+
+def test_batch_with_eight_replica_workgroups_equals_alone():
+    """Sets with 8 replicas per workgroup (forced, and as the tuner picks)
+    next to sets with 4, in one batched plan: every set equals its calls run
+    alone with 4 replicas per workgroup."""
+    say("case: batch with 4- and 8-replica workgroups")
+    mix = [m for m in _mix(61) if m[0] == "ksat"]
+    alone = _make(mix)
+    batched = _make(mix)
+    for i, s in enumerate(batched):
+        if i % 2 == 0:
+            s.set_replicas_per_workgroup(8)
+    a_beta, r_beta = _sched()
+    b = nmc.Batch(batched)
+    b.run_plan(a_beta, 1, r_beta, 9, 10, True, targets=4, use_graph=True, chunk_sweeps=8)
+    chosen = b.tune(2)
+    assert chosen in (64, 128, 256, 512, 1024)
+    b.run_plan(a_beta, 1, r_beta, 9, 10, True, targets=4, use_graph=True, chunk_sweeps=8)
+    for s in alone:
+        for _ in range(2):
+            s.anneal(a_beta[None, :], target=4)
+            s.estimate_backbone(9, 10, True)
+            s.reanneal(r_beta, "backbone", target=4)
+    for x, y in zip(alone, batched):
+        _compare(x, y)

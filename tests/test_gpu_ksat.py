@@ -4,6 +4,7 @@ backbone classes."""
 import numpy as np
 import pytest
 
+import oracle
 from gpu_util import KsatPair, say
 from paper_2111_13628_amd import instances, nmc
 
@@ -232,3 +233,62 @@ def test_accept_count_equals_flipped_spins():
     # a multi-sweep call counts its sweeps together
     rep.anneal(np.full((1, 5), 0.3))
     assert rep.accept_count() > 0
+
+
+@pytest.mark.parametrize("n,alpha,k,R,cap", [(300, "9.6", 4, 37, 0), (1200, "4.15", 3, 6, 64), (500, "9.6", 4, 4, 0),
+                                             (2000, "9.9", 4, 64, 0), (160, "9.6", 4, 24, 1), (4096, "9.9", 4, 40, 0)])
+def test_eight_replicas_per_workgroup_matches_oracle(n, alpha, k, R, cap):
+    """Sweep workgroups of 8 replicas (two groups sharing each spin byte in
+    LDS), with ragged and single-group replica counts, split and unsplit
+    chunks: anneal, backbone and reanneal bit-exact with the oracle."""
+    say(f"case: 8 replicas per workgroup n={n} k={k} R={R} cap={cap}")
+    cp, lits = instances.gen_ksat(n, alpha, k, SEED + 3 * n)
+    p = KsatPair(n, cp, lits, R, SEED + 4, cap=cap)
+    p.rep.set_replicas_per_workgroup(8)
+    p.anneal(instances.linear_schedule(0.1, 4.0, 30)[None, :], target=3)
+    p.compare()
+    cls = p.backbone(9, 10, True)
+    p.anneal(reanneal_profile(12), class_of=cls, profile="backbone", target=1)
+    p.compare()
+    rng = np.random.Generator(np.random.PCG64(n))
+    host = rng.integers(0, 3, n).astype(np.uint8)
+    beta3 = np.stack([np.full(5, 3.0), np.full(5, 0.7), np.full(5, 1.9)])
+    p.anneal(beta3, class_of=host)
+    p.compare()
+
+
+def test_eight_replicas_per_workgroup_full_size():
+    """N = 50,000, 2048 replicas: 8 replicas per workgroup equals 4 per
+    workgroup bit for bit on every replica, and the first and last groups
+    equal the oracle; the single-set tuner's choice changes nothing."""
+    say("case: 8 replicas per workgroup, N=50000 R=2048")
+    n, R = 50000, 2048
+    cp, lits = instances.gen_ksat(n, "9.9", 4, SEED)
+    inst = nmc.Instance.ksat(n, cp, lits, 1024).bind()
+    beta = instances.linear_schedule(0.1, 4.0, 2000)[None, :3]
+    a = nmc.Replicas(inst, R, SEED + 9)
+    b = nmc.Replicas(inst, R, SEED + 9)
+    c = nmc.Replicas(inst, R, SEED + 9)
+    b.set_replicas_per_workgroup(8)
+    blk, rpw = c.tune(2)
+    assert blk in (64, 128, 256, 512, 1024) and rpw in (4, 8)
+    for rep in (a, b, c):
+        rep.anneal(beta, target=10000)
+    for other in (b, c):
+        assert (a.get_state() == other.get_state()).all()
+        assert (a.get_state("best") == other.get_state("best")).all()
+        ea, eo = a.best_energy(), other.best_energy()
+        for key in ("energy", "best_per_replica", "first_hit"):
+            assert (ea[key] == eo[key]).all(), key
+    ok = oracle.KSat(n, cp, lits)
+    _, order, _ = ok.color(1024)
+    orep = oracle.KSatReplicas(ok, R, SEED + 9, order, threads=16)
+    for lo, hi in ((0, 8), (R - 8, R)):
+        orep.anneal(beta, target=10000, r_begin=lo, r_end=hi)
+        orep.sweeps_done -= beta.shape[1]
+    x = b.get_state()
+    be = b.best_energy()
+    for lo, hi in ((0, 8), (R - 8, R)):
+        assert (x[lo:hi] == orep.x[lo:hi]).all()
+        assert (be["energy"][lo:hi] == orep.energy[lo:hi]).all()
+        assert (be["first_hit"][lo:hi] == orep.first_hit[lo:hi]).all()
