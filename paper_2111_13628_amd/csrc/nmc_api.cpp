@@ -51,7 +51,7 @@ int ok() {
 static int32_t qap_rows_setting() {
     const char *e = std::getenv("NMC_QAP_ROWS");
     const int v = e ? std::atoi(e) : 0;
-    return (int32_t)(v >= 1 && v <= 4 || v == 8 ? v : 0);
+    return (int32_t)(((v >= 1 && v <= 4) || v == 8) ? v : 0);
 }
 
 // Whether the per-sweep choice of single-set QAP sweeps may take the table

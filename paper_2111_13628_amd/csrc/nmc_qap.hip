@@ -329,127 +329,145 @@ __device__ __forceinline__ int qap_wave_sweep(const QapDev &I, const QapCall &C,
     return n_acc;
 }
 
+// Sum over the wave, returned from lane 63: rotations within each 16-lane
+// row, then row 1 takes row 0's sum and row 3 row 2's (row broadcast of lane
+// 15), then rows 2 and 3 take lane 31's (row broadcast of lane 31).
+__device__ __forceinline__ int wave_sum(int x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false);  // row_ror:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x124, 0xF, 0xF, false);  // row_ror:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x122, 0xF, 0xF, false);  // row_ror:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x121, 0xF, 0xF, false);  // row_ror:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);  // row_bcast:15 into rows 1, 3
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);  // row_bcast:31 into rows 2, 3
+    return __builtin_amdgcn_readlane(x, 63);
+}
+
+__device__ __forceinline__ int lane_set(int v, int l, int x) { return (int)(threadIdx.x & 63) == l ? x : v; }
+
+// Threshold words read through the scalar cache (read-only in the kernel).
+typedef const uint32_t __attribute__((address_space(4))) scalar_u32;
+
+// A pointer the whole wave holds (per-wave data derived from threadIdx.x / 64
+// is uniform, but the compiler cannot see it): taken from the first lane so
+// that loads through it can be scalar.
+__device__ __forceinline__ const uint32_t *wave_uniform(const uint32_t *p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return reinterpret_cast<const uint32_t *>(((uint64_t)hi << 32) | lo);
+}
+
 // One sweep of one replica by one wave, one proposal per step on all 64
-// lanes (KPL facilities per lane, k = lane, lane + 64, ...), for sweeps where
-// most proposals are accepted.  The step's chain is kept short: the next
-// pair's location (and, when a changes, its flow row and location) is read
-// while the current pair is evaluated, and an accepted swap (a, b) updates
-// D[p_a][p_k] from registers: with zero diagonal and symmetric D the new row
-// is D[p_b][p_k] (just gathered) except D[p_b][p_b] = 0 at k = a and
-// D[p_b][p_a] = D[p_a][p_b] (the old value) at k = b.  The lanes holding
-// k = a and k = b add nothing to the sum, which is then the definition's sum
-// over the other k with no correction term (with two facilities per lane the
-// select is cheaper than the one-lane correction and its LDS round trip;
-// with the multi-proposal paths' 7 to 14 per lane it is not).  Same
-// decisions, words and counters as qap_wave_sweep.  Returns the number of accepted swaps.
+// lanes (KPL facilities per lane, k = lane + 64 i), for sweeps where most
+// proposals are accepted.  The permutation lives in the lanes while the sweep
+// runs (p_k in the lane of facility k; a location is a readlane, a swap two
+// lane selects) and goes back to LDS at the end.  Per row a of the pair order
+// each lane keeps F[a][k] and D[p_a][p_k]; a proposal (a, b)
+// reads F[b][k], gathers D[p_b][p_k], and sums (F_ak - F_bk)(D_{p_b p_k} -
+// D_{p_a p_k}) over every k.  With symmetric zero-diagonal F and D the k = a
+// and k = b terms are both -F_ab D_{p_a p_b}, so the definition's sum over the
+// other k is that total plus 2 F_ab D_{p_a p_b}, whose factors b's lane holds.
+// An accepted swap turns the cached row into the one just gathered, with 0 at
+// k = a and the old D_{p_a p_b} at k = b.  Threshold words come through the
+// scalar cache from the sweep's table rows in global memory (tg).  Same
+// decisions, words and counters as qap_wave_sweep.  Returns the number of
+// accepted swaps.
 template <int KPL, int KP>
 __device__ __forceinline__ int qap_wave_sweep1(const QapDev &I, const QapCall &C, const uint8_t *F, const uint8_t *D,
-                                               const uint8_t *cls, const uint32_t *tl, uint8_t *pr, uint32_t t,
+                                               const uint8_t *cls, const uint32_t *tg, uint8_t *pr, uint32_t t,
                                                uint32_t group, int word, long long &cost) {
     constexpr int RB = 16 * KP;
     const int n = I.n;
-    const int npairs = n * (n - 1) / 2;
     const int lane = threadIdx.x & 63;
     const bool one_class = C.n_classes == 1;
-    int pk[KPL], fa[KPL], da[KPL];
+    const int flo = (lane & 15) * KP + (lane >> 4);  // byte of k = lane in a flow row; k + 64 i at + 4 i
+    tg = wave_uniform(tg);
+    int pk[KPL], ck[KPL];
 #pragma unroll
     for (int i = 0; i < KPL; ++i) {
         const int k = lane + 64 * i;
         pk[i] = k < n ? pr[k] : 0;
+        ck[i] = (!one_class && k < n) ? cls[k] : 0;
     }
-    int ar = 0, br = 1;
-    int pa = pr[0], pb = pr[1];
-    flow_row<1, KPL, KP>(F, lane, fa);
-#pragma unroll
-    for (int i = 0; i < KPL; ++i)
-        da[i] = D[pa * n + pk[i]];
-    int n_acc = 0;
+    int n_acc = 0, widx = 0;
     uint32_t pbase = 0;
     uint32_t uw = sweep_word((uint32_t)lane, t, group, word, C.key0, C.key1);
-    for (int p0 = 0; p0 < npairs; ++p0) {
-        // next pair and its reads (the current swap can change them only
-        // through a or b, fixed below)
-        int an = ar, bn = br;
-        pair_advance(an, bn, n, 1);
-        int pbn = pr[bn], pan = pa;
-        int fan[KPL];
-        const bool new_a = an != ar;
-        if (new_a) {
-            pan = pr[an];
-            flow_row<1, KPL, KP>(F + an * RB, lane, fan);
-        }
-        // the current proposal
-        int fb[KPL], db[KPL];
-        flow_row<1, KPL, KP>(F + br * RB, lane, fb);
-        int part = 0;
+    // accepted changes since the last flush into cost: at most 64 proposals,
+    // each |dC| <= 2 (n - 2) 255^2, so the sum fits 32 bits for n <= 255
+    int csum = 0;
+    // rows a in slot SA, pairs (a, b) with b in slot S >= SA: every slot index
+    // is a compile-time constant, so the per-facility arrays stay in registers
 #pragma unroll
-        for (int i = 0; i < KPL; ++i) {
-            db[i] = D[pb * n + pk[i]];
-            // the sum runs over k other than a and b
-            const int k = lane + 64 * i;
-            const int term = (fa[i] - fb[i]) * (db[i] - da[i]);
-            part += (k == ar || k == br) ? 0 : term;
-        }
-        part = row_allreduce16(part);
-        const int dc = 2 * (__builtin_amdgcn_readlane(part, 0) + __builtin_amdgcn_readlane(part, 16) +
-                            __builtin_amdgcn_readlane(part, 32) + __builtin_amdgcn_readlane(part, 48));
-        const uint32_t u = (uint32_t)__builtin_amdgcn_readlane((int)uw, p0 - (int)pbase);
-        bool acc = dc <= 0;
-        if (!acc) {
-            const int cl = one_class ? 0 : max((int)cls[ar], (int)cls[br]);
-            const uint32_t *T = tl + cl * C.stride;
-            const int h = dc >> kQapLowBits, l = dc & ((1 << kQapLowBits) - 1);
-            // the table words are the same for every lane: taking them as
-            // scalars keeps the accept branch a scalar branch
-            const uint32_t thr =
-                h < I.ha ? (uint32_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)T[h]) *
-                                       (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)T[I.ha + l])) >> 32)
-                         : 0u;
-            acc = u < thr;
-        }
-        if (acc) {
-            ++n_acc;
-            cost += dc;
-            if (lane == 0) {
-                pr[ar] = (uint8_t)pb;
-                pr[br] = (uint8_t)pa;
-            }
+    for (int SA = 0; SA < KPL; ++SA) {
+        const int a_end = min(n - 1, 64 * SA + 64);
+        for (int a = 64 * SA; a < a_end; ++a) {
+            const int la = a - 64 * SA;
+            const bool lane_a = lane == la;
+            int pa = __builtin_amdgcn_readlane(pk[SA], la);
+            const int cla = one_class ? 0 : __builtin_amdgcn_readlane(ck[SA], la);
+            int fa[KPL], da[KPL];
 #pragma unroll
             for (int i = 0; i < KPL; ++i) {
-                const int k = lane + 64 * i;
-                const int nd = k == ar ? 0 : k == br ? da[i] : db[i];
-                if (k == ar)
-                    pk[i] = pb;
-                if (k == br)
-                    pk[i] = pa;
-                da[i] = nd;
-            }
-            // locations read ahead that this swap changed
-            if (bn == ar)
-                pbn = pb;
-            else if (bn == br)
-                pbn = pa;
-            if (an == br)
-                pan = pa;
-            const int pa_old = pa;
-            pa = pb;
-            pb = pa_old;
-        }
-        if (new_a) {
-            ar = an;
-            pa = __builtin_amdgcn_readfirstlane(pan);
-#pragma unroll
-            for (int i = 0; i < KPL; ++i) {
-                fa[i] = fan[i];
+                fa[i] = F[a * RB + flo + 4 * i];
                 da[i] = D[pa * n + pk[i]];
             }
+#pragma unroll
+            for (int S = SA; S < KPL; ++S) {
+                const int b_end = min(n, 64 * S + 64);
+                for (int b = max(a + 1, 64 * S); b < b_end; ++b) {
+                    const int lb = b - 64 * S;
+                    const int pb = __builtin_amdgcn_readlane(pk[S], lb);
+                    int db[KPL];
+                    int part = 0;
+#pragma unroll
+                    for (int i = 0; i < KPL; ++i) {
+                        const int fb = F[b * RB + flo + 4 * i];
+                        db[i] = D[pb * n + pk[i]];
+                        part += __mul24(fa[i] - fb, db[i] - da[i]);
+                    }
+                    const int fab = __builtin_amdgcn_readlane(fa[S], lb), dab = __builtin_amdgcn_readlane(da[S], lb);
+                    const int dc = 2 * (wave_sum(part) + 2 * fab * dab);
+                    const uint32_t u = (uint32_t)__builtin_amdgcn_readlane((int)uw, widx);
+                    bool acc = dc <= 0;
+                    if (!acc) {
+                        const int h = dc >> kQapLowBits, l = dc & ((1 << kQapLowBits) - 1);
+                        if (h < I.ha) {
+                            const int cl = one_class ? 0 : max(cla, __builtin_amdgcn_readlane(ck[S], lb));
+                            scalar_u32 *T = (scalar_u32 *)(tg + cl * C.stride);
+                            acc = u < (uint32_t)(((uint64_t)T[h] * (uint64_t)T[I.ha + l]) >> 32);
+                        }
+                    }
+                    if (acc) {
+                        ++n_acc;
+                        csum += dc;
+                        // p_a <-> p_b; the cached row becomes D[p_b][.] with 0 at
+                        // k = a and the old D_{p_a p_b} at k = b
+                        pk[SA] = lane_a ? pb : pk[SA];
+                        pk[S] = lane_set(pk[S], lb, pa);
+#pragma unroll
+                        for (int i = 0; i < KPL; ++i)
+                            da[i] = db[i];
+                        da[SA] = lane_a ? 0 : da[SA];
+                        da[S] = lane_set(da[S], lb, dab);
+                        pa = pb;
+                    }
+                    if (++widx == 64) {
+                        widx = 0;
+                        pbase += 64;
+                        uw = sweep_word(pbase + (uint32_t)lane, t, group, word, C.key0, C.key1);
+                        cost += csum;
+                        csum = 0;
+                    }
+                }
+            }
         }
-        br = bn;
-        pb = __builtin_amdgcn_readfirstlane(pbn);  // locations are wave-uniform
-        if (p0 + 1 == (int)pbase + 64) {
-            pbase += 64;
-            uw = sweep_word(pbase + (uint32_t)lane, t, group, word, C.key0, C.key1);
-        }
+    }
+    cost += csum;
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) {
+        const int k = lane + 64 * i;
+        if (k < n)
+            pr[k] = (uint8_t)pk[i];
     }
     return n_acc;
 }
@@ -963,6 +981,9 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
         qrows[wave] = active ? rows : 0;
     for (int s = 0; s < C.n_sweeps; ++s) {
         const uint32_t t = C.t0 + (uint32_t)s;
+        // this wave's table rows of the sweep in global memory (read through the
+        // scalar cache by the one-proposal path; the LDS copy serves the others)
+        const uint32_t *tgw = row_of(mix ? wave >> 2 : 0) + (size_t)s * C.sweep_words;
         for (int q = 0; q < nslots; ++q) {
             const uint32_t *tg = row_of(q) + (size_t)s * C.sweep_words;
             for (int i = tid; i < tab_words; i += blockDim.x)
@@ -1008,19 +1029,19 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
                     else
                         n_acc = rows == 4
                                     ? qap_wave_sweep<4, KPL4, KP>(I, C, F, F8, D, cls, tw, pr, t, group, word, cost)
-                                    : qap_wave_sweep1<KPL1, KP>(I, C, F, D, cls, tw, pr, t, group, word, cost);
+                                    : qap_wave_sweep1<KPL1, KP>(I, C, F, D, cls, tgw, pr, t, group, word, cost);
                 } else {
                     n_acc = rows == 4 ? qap_wave_sweep<4, KPL4, KP>(I, C, F, F8, D, cls, tw, pr, t, group, word, cost)
-                                      : qap_wave_sweep1<KPL1, KP>(I, C, F, D, cls, tw, pr, t, group, word, cost);
+                                      : qap_wave_sweep1<KPL1, KP>(I, C, F, D, cls, tgw, pr, t, group, word, cost);
                 }
             }
             acc_total += (unsigned long long)n_acc;
             if (C.rows == 0) {
-                // acceptance of this sweep: above 3/10 one proposal per step,
+                // acceptance of this sweep: above 1/8 one proposal per step,
                 // below 1/16 eight, else four; below 1/kTabAccDen the table
                 // mode, when its table is current or the launch has sweeps
                 // enough left to repay building it
-                rows = 10 * n_acc > 3 * npairs ? 1 : (16 * n_acc < npairs && KPL8 > 0) ? 8 : 4;
+                rows = 8 * n_acc > npairs ? 1 : (16 * n_acc < npairs && KPL8 > 0) ? 8 : 4;
                 if (tab_ok && kTabAccDen * n_acc < npairs && (fresh || C.n_sweeps - s - 1 >= kTabMinSweeps))
                     rows = 2;
             }
