@@ -164,8 +164,8 @@ __device__ __forceinline__ void flow_row8(const uint8_t *row, int q, int (&f)[KP
         f[i] = (int)((w[i >> 2] >> (8 * (i & 3))) & 0xFFu);
 }
 
-// One sweep of one replica by one wave.  ROWS proposals are evaluated per
-// step, one per row of LANES = 64 / ROWS lanes; KPL = facilities per lane
+// One sweep of one replica by one wave.  ROWS (4 or 8) proposals are
+// evaluated per step, one per row of LANES = 64 / ROWS lanes; KPL = facilities per lane
 // (k = q, q + LANES, ...), LANES * KPL <= 16 * KP, the flow row length (rows
 // of F padded with zeros, so padding k contribute (0 - 0) * (...) = 0 and no
 // lane needs a bound check).  Each lane keeps, for its k: the location p_k,
@@ -185,7 +185,7 @@ __device__ __forceinline__ int qap_wave_sweep(const QapDev &I, const QapCall &C,
                                               uint32_t t, uint32_t group, int word, long long &cost) {
     constexpr int LANES = 64 / ROWS;
     constexpr int RB = 16 * KP;  // bytes per flow row
-    static_assert(ROWS == 1 || ROWS == 8 || (ROWS == 4 && KPL <= KP), "flow layout");
+    static_assert(ROWS == 8 || (ROWS == 4 && KPL <= KP), "flow layout");
     const int n = I.n;
     const int npairs = n * (n - 1) / 2;
     const int lane = threadIdx.x & 63;
@@ -234,31 +234,24 @@ __device__ __forceinline__ int qap_wave_sweep(const QapDev &I, const QapCall &C,
         else
             flow_row<ROWS, KPL, KP>(F + br * RB, q, fb);
         const uint8_t *drow_b = D + pb * n;
+        // the byte masks restate the ranges the loop-carried values lost, so
+        // that the products stay 24-bit multiplies
         int part = 0;
 #pragma unroll
         for (int i = 0; i < KPL; ++i)
-            part += (fa[i] - fb[i]) * ((int)drow_b[pk[i]] - da[i]);
+            part += __mul24((fa[i] & 0xFF) - fb[i], (int)drow_b[pk[i]] - (da[i] & 0xFF));
         if (q == 0)
             part += 2 * (int)F[ar * RB + (br & 15) * KP + (br >> 4)] * (int)D[pa * n + pb];
         if constexpr (ROWS == 8)
             part = group_allreduce8(part);
         else
             part = row_allreduce16(part);
-        int dc;
-        uint32_t u;
-        if constexpr (ROWS == 1) {
-            dc = 2 * (__builtin_amdgcn_readlane(part, 0) + __builtin_amdgcn_readlane(part, 16) +
-                      __builtin_amdgcn_readlane(part, 32) + __builtin_amdgcn_readlane(part, 48));
-            const int src = p0 - (int)pbase;  // 0 .. 63
-            u = (uint32_t)__builtin_amdgcn_readlane((int)uw, src);
-        } else {
-            dc = 2 * part;
-            const int src = p0 + row - (int)pbase;  // 0 .. 63 + ROWS - 1
-            const int sl = (src & 63) << 2;
-            const uint32_t ua = (uint32_t)__builtin_amdgcn_ds_bpermute(sl, (int)uw);
-            const uint32_t ub = (uint32_t)__builtin_amdgcn_ds_bpermute(sl, (int)uw2);
-            u = src < 64 ? ua : ub;
-        }
+        const int dc = 2 * part;
+        const int src = p0 + row - (int)pbase;  // 0 .. 63 + ROWS - 1
+        const int sl = (src & 63) << 2;
+        const uint32_t ua = (uint32_t)__builtin_amdgcn_ds_bpermute(sl, (int)uw);
+        const uint32_t ub = (uint32_t)__builtin_amdgcn_ds_bpermute(sl, (int)uw2);
+        const uint32_t u = src < 64 ? ua : ub;
         bool acc = dc <= 0;
         if (!acc) {
             const int cl = one_class ? 0 : max((int)cls[ar], (int)cls[br]);
@@ -268,19 +261,12 @@ __device__ __forceinline__ int qap_wave_sweep(const QapDev &I, const QapCall &C,
             acc = u < thr;
         }
         int adv = ROWS, j = -1;
-        if constexpr (ROWS == 1) {
-            if (acc)
-                j = 0;
-        } else {
-            acc = acc && p0 + row < npairs;
-            const uint64_t m = __ballot(acc);
-            uint32_t rows = 0;
-#pragma unroll
-            for (int r = 0; r < ROWS; ++r)
-                rows |= (uint32_t)((m >> (LANES * r)) & 1u) << r;
-            if (rows)
-                j = __builtin_ctz(rows);
-        }
+        acc = acc && p0 + row < npairs;
+        // every lane of a row holds its row's decision, so the first accepted
+        // row starts at the ballot's lowest set bit
+        const uint64_t m = __ballot(acc);
+        if (m)
+            j = (int)__builtin_ctzll(m) / LANES;
         if (j >= 0) {
             adv = j + 1;
             ++n_acc;
@@ -347,6 +333,13 @@ __device__ __forceinline__ int lane_set(int v, int l, int x) { return (int)(thre
 // Threshold words read through the scalar cache (read-only in the kernel).
 typedef const uint32_t __attribute__((address_space(4))) scalar_u32;
 
+// Word at a 32-bit byte offset from a scalar-cache pointer (base plus an
+// unsigned 32-bit offset, the scalar load's own addressing form).
+__device__ __forceinline__ uint32_t scalar_word(scalar_u32 *base, uint32_t byte_off) {
+    typedef const uint8_t __attribute__((address_space(4))) scalar_u8;
+    return *reinterpret_cast<scalar_u32 *>(reinterpret_cast<scalar_u8 *>(base) + byte_off);
+}
+
 // A pointer the whole wave holds (per-wave data derived from threadIdx.x / 64
 // is uniform, but the compiler cannot see it): taken from the first lane so
 // that loads through it can be scalar.
@@ -381,7 +374,7 @@ __device__ __forceinline__ int qap_wave_sweep1(const QapDev &I, const QapCall &C
     const int lane = threadIdx.x & 63;
     const bool one_class = C.n_classes == 1;
     const int flo = (lane & 15) * KP + (lane >> 4);  // byte of k = lane in a flow row; k + 64 i at + 4 i
-    tg = wave_uniform(tg);
+    scalar_u32 *T = (scalar_u32 *)wave_uniform(tg);
     int pk[KPL], ck[KPL];
 #pragma unroll
     for (int i = 0; i < KPL; ++i) {
@@ -433,8 +426,10 @@ __device__ __forceinline__ int qap_wave_sweep1(const QapDev &I, const QapCall &C
                         const int h = dc >> kQapLowBits, l = dc & ((1 << kQapLowBits) - 1);
                         if (h < I.ha) {
                             const int cl = one_class ? 0 : max(cla, __builtin_amdgcn_readlane(ck[S], lb));
-                            scalar_u32 *T = (scalar_u32 *)(tg + cl * C.stride);
-                            acc = u < (uint32_t)(((uint64_t)T[h] * (uint64_t)T[I.ha + l]) >> 32);
+                            const uint32_t row = (uint32_t)(cl * C.stride);
+                            const uint32_t th = scalar_word(T, (row + (uint32_t)h) << 2);
+                            const uint32_t tl = scalar_word(T, (row + (uint32_t)(I.ha + l)) << 2);
+                            acc = u < (uint32_t)(((uint64_t)th * (uint64_t)tl) >> 32);
                         }
                     }
                     if (acc) {
