@@ -375,12 +375,14 @@ __device__ __forceinline__ int qap_wave_sweep1(const QapDev &I, const QapCall &C
     const bool one_class = C.n_classes == 1;
     const int flo = (lane & 15) * KP + (lane >> 4);  // byte of k = lane in a flow row; k + 64 i at + 4 i
     scalar_u32 *T = (scalar_u32 *)wave_uniform(tg);
+    // p_k and the word offset of facility k's class row in the sweep's table
+    // (a pair takes the row of the larger class: the larger offset)
     int pk[KPL], ck[KPL];
 #pragma unroll
     for (int i = 0; i < KPL; ++i) {
         const int k = lane + 64 * i;
         pk[i] = k < n ? pr[k] : 0;
-        ck[i] = (!one_class && k < n) ? cls[k] : 0;
+        ck[i] = (!one_class && k < n) ? cls[k] * C.stride : 0;
     }
     int n_acc = 0, widx = 0;
     uint32_t pbase = 0;
@@ -397,7 +399,7 @@ __device__ __forceinline__ int qap_wave_sweep1(const QapDev &I, const QapCall &C
             const int la = a - 64 * SA;
             const bool lane_a = lane == la;
             int pa = __builtin_amdgcn_readlane(pk[SA], la);
-            const int cla = one_class ? 0 : __builtin_amdgcn_readlane(ck[SA], la);
+            const int cla = __builtin_amdgcn_readlane(ck[SA], la);
             int fa[KPL], da[KPL];
 #pragma unroll
             for (int i = 0; i < KPL; ++i) {
@@ -425,8 +427,7 @@ __device__ __forceinline__ int qap_wave_sweep1(const QapDev &I, const QapCall &C
                     if (!acc) {
                         const int h = dc >> kQapLowBits, l = dc & ((1 << kQapLowBits) - 1);
                         if (h < I.ha) {
-                            const int cl = one_class ? 0 : max(cla, __builtin_amdgcn_readlane(ck[S], lb));
-                            const uint32_t row = (uint32_t)(cl * C.stride);
+                            const uint32_t row = (uint32_t)max(cla, __builtin_amdgcn_readlane(ck[S], lb));
                             const uint32_t th = scalar_word(T, (row + (uint32_t)h) << 2);
                             const uint32_t tl = scalar_word(T, (row + (uint32_t)(I.ha + l)) << 2);
                             acc = u < (uint32_t)(((uint64_t)th * (uint64_t)tl) >> 32);
