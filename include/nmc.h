@@ -211,7 +211,7 @@ int nmc_reanneal(nmc_replicas *rep, const double *beta, int32_t n_classes, int32
  * allocator).  Arguments, results and errors are those of nmc_anneal, with
  * the same bits: the same kernels run, and only the place of the call's
  * threshold tables differs.  The tables (4 bytes per table word: sweeps x
- * classes x (max degree + 1) for k-SAT, x (high-digit entries + 1024) for
+ * classes x (max degree + 1) for k-SAT, x (high-digit entries + 1025) for
  * QAP, rounded up to 256 bytes, plus N or n bytes of class_of for
  * NMC_PROFILE_HOST, rounded up to 256) are uploaded into a fixed device array
  * of the library (nmc_anneal_noalloc_capacity() bytes, one per device, held

@@ -1,6 +1,7 @@
 """Build the HIP library libnmc.so for gfx950 (in-tree, next to this file)."""
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -27,14 +28,23 @@ def build(verbose: bool = False) -> str:
              "-Wall", "-Wno-unused-result", "-I", os.path.join(HERE, "..", "include")]
     build_dir = os.path.join(HERE, "_build")
     os.makedirs(build_dir, exist_ok=True)
+    cmds = []
     for src in SOURCES:
         obj = os.path.join(build_dir, src + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [hipcc()] + flags + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmds.append([hipcc()] + flags + lang + ["-c", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+
+    def compile_one(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
-        objs.append(obj)
+
+    # the sources compile independently: one compiler process per source, at
+    # most as many at once as there are CPUs
+    with concurrent.futures.ThreadPoolExecutor(max_workers=max(1, min(len(cmds), os.cpu_count() or 1, 16))) as ex:
+        for f in [ex.submit(compile_one, c) for c in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs
     if verbose:

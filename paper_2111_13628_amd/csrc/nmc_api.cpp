@@ -61,6 +61,13 @@ static int32_t qap_tab_setting() {
     const char *e = std::getenv("NMC_QAP_TAB");
     return (int32_t)(e && e[0] == '1');
 }
+// NMC_QAP_DSTAR=0 makes the QAP sweeps read both threshold words per
+// proposal instead of comparing against the per-word bound (for measurements;
+// results do not change).
+static int32_t qap_dstar_setting() {
+    const char *e = std::getenv("NMC_QAP_DSTAR");
+    return (int32_t)!(e && e[0] == '0');
+}
 static int32_t qap_quad_setting() {
     const char *e = std::getenv("NMC_QAP_RPW");  // replicas per wave in hot sweeps: 2 or 4
     const int v = e ? std::atoi(e) : 0;
@@ -114,6 +121,41 @@ uint32_t threshold(double beta, int64_t d) {
     if (!(v < 4294967295.0))
         return 0xFFFFFFFFu;
     return static_cast<uint32_t>(std::floor(v));
+}
+
+// Words of one QAP threshold row: the high digit A[0 .. ha), the low digit
+// B[0 .. 1024) and 1 / beta as a float (where the kernels start their search
+// for the acceptance bound of a random word).
+int32_t qap_row_words(int32_t ha) { return ha + (1 << kQapLowBits) + 1; }
+
+// Fills one QAP threshold row for inverse temperature beta: T(d) =
+// (A[d >> 10] B[d & 1023]) >> 32, A[h] = threshold(beta, 1024 h) and B[l] =
+// threshold(beta, l) with A[0] = B[0] = 2^32 - 1, and T = 0 from d = 1024 ha
+// on.  Returns whether T never increases with d: then a random word u has a
+// bound d*(u) with u < T(d) exactly when d < d*(u), which the kernels use in
+// place of the two table reads per proposal.
+bool qap_fill_row(uint32_t *row, double beta, int32_t ha) {
+    constexpr int32_t lo_n = 1 << kQapLowBits;
+    uint32_t *lo = row + ha;
+    row[0] = 0xFFFFFFFFu;
+    for (int32_t h = 1; h < ha; ++h)
+        row[h] = threshold(beta, (int64_t)h << kQapLowBits);
+    lo[0] = 0xFFFFFFFFu;
+    for (int32_t l = 1; l < lo_n; ++l)
+        lo[l] = threshold(beta, l);
+    const float inv = (float)(1.0 / beta);  // beta = 0: +inf
+    std::memcpy(lo + lo_n, &inv, sizeof inv);
+    bool mono = true;
+    for (int32_t l = 1; l < lo_n; ++l)
+        mono = mono && lo[l] <= lo[l - 1];
+    // within a block T follows B; across blocks the last word of block h - 1
+    // must not be below the first of block h
+    for (int32_t h = 1; h < ha; ++h) {
+        const uint64_t last = ((uint64_t)row[h - 1] * lo[lo_n - 1]) >> 32;
+        const uint64_t first = ((uint64_t)row[h] * lo[0]) >> 32;
+        mono = mono && row[h] <= row[h - 1] && first <= last;
+    }
+    return mono;
 }
 
 struct Arena {
@@ -960,7 +1002,7 @@ static int anneal_impl(nmc_replicas *P, const double *beta, int32_t n_classes, i
     }
     hipStream_t s = as_stream(stream);
     const bool ksat = I->kind == NMC_KIND_KSAT;
-    const int32_t stride = ksat ? I->dmax + 1 : I->qap_ha + (1 << kQapLowBits);
+    const int32_t stride = ksat ? I->dmax + 1 : qap_row_words(I->qap_ha);
     const size_t lds = ksat ? ksat_sweep_lds_bytes(I->n, n_classes, stride) : qap_sweep_lds_bytes(I->n, n_classes, stride);
     if (lds > kLdsBytes)
         return fail(NMC_ERR_CAPACITY, "sweep needs %zu bytes of LDS (limit %zu)", lds, kLdsBytes);
@@ -986,6 +1028,7 @@ static int anneal_impl(nmc_replicas *P, const double *beta, int32_t n_classes, i
         up = P->tab_dev;
     }
     std::vector<uint32_t> tab(std::max<size_t>(words, 1));
+    bool mono = true;  // every QAP row's T never increases
     for (int32_t sw = 0; sw < n_sweeps; ++sw)
         for (int32_t c = 0; c < n_classes; ++c) {
             const double b = beta[(size_t)c * n_sweeps + sw];
@@ -995,13 +1038,7 @@ static int anneal_impl(nmc_replicas *P, const double *beta, int32_t n_classes, i
                 for (int32_t d = 1; d < stride; ++d)
                     row[d] = threshold(b, d);
             } else {
-                const int32_t ha = I->qap_ha, lo = 1 << kQapLowBits;
-                row[0] = 0xFFFFFFFFu;
-                for (int32_t h = 1; h < ha; ++h)
-                    row[h] = threshold(b, (int64_t)h << kQapLowBits);
-                row[ha] = 0xFFFFFFFFu;
-                for (int32_t l = 1; l < lo; ++l)
-                    row[ha + l] = threshold(b, l);
+                mono = qap_fill_row(row, b, I->qap_ha) && mono;
             }
         }
     // the upload waits for earlier work on the stream that still reads the
@@ -1053,6 +1090,7 @@ static int anneal_impl(nmc_replicas *P, const double *beta, int32_t n_classes, i
         C.rows = qap_rows_setting();
         C.tab_allow = qap_tab_setting();
         C.quad_allow = qap_quad_setting();
+        C.dstar = mono && qap_dstar_setting();
         C.key0 = (uint32_t)P->seed;
         C.key1 = (uint32_t)(P->seed >> 32);
         HIP_OR_FAIL(qap_launch_sweep(I->qap_dev(), P->q, C, 256, s));
@@ -1371,7 +1409,7 @@ static int pt_run_impl(nmc_replicas *P, const double *beta, int32_t n_temps, int
             return fail(NMC_ERR_INVALID, "the ladder must increase strictly (beta[%d] <= beta[%d])", i, i - 1);
     }
     hipStream_t s = as_stream(stream);
-    const int32_t stride = ksat ? I->dmax + 1 : I->qap_ha + (1 << kQapLowBits);
+    const int32_t stride = ksat ? I->dmax + 1 : qap_row_words(I->qap_ha);
     const size_t lds = ksat ? ksat_sweep_lds_bytes(I->n, 1, stride) : qap_sweep_lds_bytes(I->n, 1, stride);
     if (lds > kLdsBytes)
         return fail(NMC_ERR_CAPACITY, "sweep needs %zu bytes of LDS (limit %zu)", lds, kLdsBytes);
@@ -1380,19 +1418,15 @@ static int pt_run_impl(nmc_replicas *P, const double *beta, int32_t n_temps, int
 
     // sweep thresholds, one row per ladder position
     std::vector<uint32_t> tab((size_t)n_temps * stride);
+    bool mono = true;  // every QAP row's T never increases
     for (int32_t i = 0; i < n_temps; ++i) {
         uint32_t *row = tab.data() + (size_t)i * stride;
-        row[0] = 0xFFFFFFFFu;
         if (ksat) {
+            row[0] = 0xFFFFFFFFu;
             for (int32_t d = 1; d < stride; ++d)
                 row[d] = threshold(beta[i], d);
         } else {
-            const int32_t ha = I->qap_ha;
-            for (int32_t h = 1; h < ha; ++h)
-                row[h] = threshold(beta[i], (int64_t)h << kQapLowBits);
-            row[ha] = 0xFFFFFFFFu;
-            for (int32_t l = 1; l < (1 << kQapLowBits); ++l)
-                row[ha + l] = threshold(beta[i], l);
+            mono = qap_fill_row(row, beta[i], I->qap_ha) && mono;
         }
     }
     // exchange thresholds of every neighbour pair: the high digit runs until
@@ -1485,6 +1519,7 @@ static int pt_run_impl(nmc_replicas *P, const double *beta, int32_t n_temps, int
             C.rows = qap_rows_setting();
             C.tab_allow = qap_tab_setting();
             C.quad_allow = qap_quad_setting();
+            C.dstar = mono && qap_dstar_setting();
             C.key0 = X.key0;
             C.key1 = X.key1;
             C.reps_per_row = chains;
@@ -2268,7 +2303,7 @@ int build_batch(nmc_batch *B, const std::vector<PhaseSpec> &phases, bool with_ba
         stride_k = std::max(stride_k, sets[i]->inst->dmax + 1);
     for (int i : qidx)
         ha = std::max(ha, sets[i]->inst->qap_ha);
-    const int32_t stride_q = ha + (1 << kQapLowBits);
+    const int32_t stride_q = qap_row_words(ha);
     std::vector<nmc_replicas *> ks;
     for (int i : kidx)
         ks.push_back(sets[i]);
@@ -2281,6 +2316,7 @@ int build_batch(nmc_batch *B, const std::vector<PhaseSpec> &phases, bool with_ba
         bp.block_k = block_k;
         // thresholds shared by the phase's jobs of one kind
         size_t off_ktab = 0, off_qtab = 0;
+        bool qmono = true;  // every QAP row's T never increases
         if (!kidx.empty()) {
             off_ktab = blob.take(std::max<size_t>((size_t)ph.n_sweeps * ph.n_classes * stride_k * 4, 4));
             uint32_t *t = reinterpret_cast<uint32_t *>(blob.host.data() + off_ktab);
@@ -2298,13 +2334,7 @@ int build_batch(nmc_batch *B, const std::vector<PhaseSpec> &phases, bool with_ba
                 for (int32_t c = 0; c < ph.n_classes; ++c) {
                     uint32_t *row = reinterpret_cast<uint32_t *>(blob.host.data() + off_qtab) +
                                     ((size_t)sw * ph.n_classes + c) * stride_q;
-                    const double b = ph.beta[(size_t)c * ph.n_sweeps + sw];
-                    row[0] = 0xFFFFFFFFu;
-                    for (int32_t h = 1; h < ha; ++h)
-                        row[h] = threshold(b, (int64_t)h << kQapLowBits);
-                    row[ha] = 0xFFFFFFFFu;
-                    for (int32_t l = 1; l < (1 << kQapLowBits); ++l)
-                        row[ha + l] = threshold(b, l);
+                    qmono = qap_fill_row(row, ph.beta[(size_t)c * ph.n_sweeps + sw], ha) && qmono;
                 }
         }
         // k-SAT jobs and items
@@ -2367,6 +2397,7 @@ int build_batch(nmc_batch *B, const std::vector<PhaseSpec> &phases, bool with_ba
                 J.C.rows = qap_rows_setting();
                 J.C.tab_allow = qap_tab_setting();
                 J.C.quad_allow = qap_quad_setting();
+                J.C.dstar = qmono && qap_dstar_setting();
                 J.C.key0 = (uint32_t)P->seed;
                 J.C.key1 = (uint32_t)(P->seed >> 32);
                 std::memcpy(blob.host.data() + bp.off_qjobs + j * sizeof(QapJob), &J, sizeof J);
@@ -2638,7 +2669,7 @@ int build_plans(nmc_batch *B, const std::vector<std::vector<SetPhase>> &ph, cons
             ha = std::max(ha, P->inst->qap_ha);
         }
     }
-    const int32_t stride_q = ha + (1 << kQapLowBits);
+    const int32_t stride_q = qap_row_words(ha);
     const int block_k = B->block_threads > 0 ? B->block_threads : heuristic_block(ks);
     const int cus = device_cus();
     // stage boundaries
@@ -2654,6 +2685,7 @@ int build_plans(nmc_batch *B, const std::vector<std::vector<SetPhase>> &ph, cons
     std::sort(cut.begin(), cut.end());
     cut.erase(std::unique(cut.begin(), cut.end()), cut.end());
     std::map<std::string, size_t> tab_at;
+    std::map<size_t, bool> tab_mono;  // per QAP table: every row's T never increases
     auto table = [&](bool ksat, const SetPhase &p, int64_t off, int32_t len) -> size_t {
         std::string key(1, ksat ? 'k' : 'q');
         key.push_back((char)p.nc);
@@ -2664,22 +2696,20 @@ int build_plans(nmc_batch *B, const std::vector<std::vector<SetPhase>> &ph, cons
             return it->second;
         const int32_t stride = ksat ? stride_k : stride_q;
         const size_t at = blob.take(std::max<size_t>((size_t)len * p.nc * stride * 4, 4));
+        bool mono = true;
         for (int32_t sw = 0; sw < len; ++sw)
             for (int32_t c = 0; c < p.nc; ++c) {
                 uint32_t *row = reinterpret_cast<uint32_t *>(blob.host.data() + at) + ((size_t)sw * p.nc + c) * stride;
                 const double b = p.beta[(size_t)c * p.len + off + sw];
-                row[0] = 0xFFFFFFFFu;
                 if (ksat) {
+                    row[0] = 0xFFFFFFFFu;
                     for (int32_t d = 1; d < stride_k; ++d)
                         row[d] = threshold(b, d);
                 } else {
-                    for (int32_t h = 1; h < ha; ++h)
-                        row[h] = threshold(b, (int64_t)h << kQapLowBits);
-                    row[ha] = 0xFFFFFFFFu;
-                    for (int32_t l = 1; l < (1 << kQapLowBits); ++l)
-                        row[ha + l] = threshold(b, l);
+                    mono = qap_fill_row(row, b, ha) && mono;
                 }
             }
+        tab_mono[at] = mono;
         tab_at.emplace(std::move(key), at);
         return at;
     };
@@ -2789,6 +2819,7 @@ int build_plans(nmc_batch *B, const std::vector<std::vector<SetPhase>> &ph, cons
                 J.C.rows = qap_rows_setting();
                 J.C.tab_allow = qap_tab_setting();
                 J.C.quad_allow = qap_quad_setting();
+                J.C.dstar = tab_mono[tab] && qap_dstar_setting();
                 J.C.key0 = (uint32_t)P->seed;
                 J.C.key1 = (uint32_t)(P->seed >> 32);
                 const double nd = P->inst->n;
@@ -3498,7 +3529,7 @@ extern "C" int nmc_batch_step(nmc_batch *B, const nmc_segment *segs, int32_t n_s
             else
                 ha = std::max(ha, I->qap_ha);
         }
-        const int32_t stride_q = ha + (1 << kQapLowBits);
+        const int32_t stride_q = qap_row_words(ha);
         std::vector<nmc_replicas *> ks;
         for (size_t i = 0; i < ns; ++i)
             if (segs[i].profile >= 0 && B->sets[i]->inst->kind == NMC_KIND_KSAT)
@@ -3563,15 +3594,9 @@ extern "C" int nmc_batch_step(nmc_batch *B, const nmc_segment *segs, int32_t n_s
                 } else {
                     const size_t off = blob.take((size_t)nc * stride_q * 4);
                     uint32_t *t = reinterpret_cast<uint32_t *>(blob.host.data() + off);
-                    for (int32_t c = 0; c < nc; ++c) {
-                        uint32_t *row = t + (size_t)c * stride_q;
-                        row[0] = 0xFFFFFFFFu;
-                        for (int32_t h = 1; h < ha; ++h)
-                            row[h] = threshold(g.beta[c], (int64_t)h << kQapLowBits);
-                        row[ha] = 0xFFFFFFFFu;
-                        for (int32_t l = 1; l < (1 << kQapLowBits); ++l)
-                            row[ha + l] = threshold(g.beta[c], l);
-                    }
+                    bool mono = true;
+                    for (int32_t c = 0; c < nc; ++c)
+                        mono = qap_fill_row(t + (size_t)c * stride_q, g.beta[c], ha) && mono;
                     QapJob J{};
                     J.I = P->inst->qap_dev();
                     J.I.ha = ha;
@@ -3588,6 +3613,7 @@ extern "C" int nmc_batch_step(nmc_batch *B, const nmc_segment *segs, int32_t n_s
                     J.C.rows = qap_rows_setting();
                     J.C.tab_allow = qap_tab_setting();
                     J.C.quad_allow = qap_quad_setting();
+                    J.C.dstar = mono && qap_dstar_setting();
                     J.C.key0 = (uint32_t)P->seed;
                     J.C.key1 = (uint32_t)(P->seed >> 32);
                     const double nd = P->inst->n;

@@ -131,7 +131,7 @@ struct QapRepDev {
 };
 
 struct QapCall {
-    const uint32_t *tab;   // [n_sweeps][n_classes][ha + 1024]
+    const uint32_t *tab;   // [n_sweeps][n_classes][ha + 1024 + 1]: A, B, then 1 / beta as a float
     const uint8_t *fac_cls;// per-facility class or nullptr
     int32_t n_classes, stride, n_sweeps;
     int32_t sweep_words;   // words between consecutive sweeps' tables (0: one table for all)
@@ -143,6 +143,7 @@ struct QapCall {
     int32_t tab_allow;     // the per-sweep choice may use the table mode (when its LDS fits)
     int32_t quad_allow;    // the per-sweep choice may run several replicas per wave: 0 no, 2 or 4 per wave
     int32_t reps_per_row;  // > 0: replica r reads table row r / reps_per_row (one [n_classes][stride] block per row)
+    int32_t dstar;         // every row's T(d) never increases: decide by the bound d*(u) (else read T per proposal)
 };
 
 // One replica set of a batched launch.

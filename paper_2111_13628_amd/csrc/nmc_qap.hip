@@ -73,6 +73,91 @@ __device__ __forceinline__ uint32_t sweep_word(uint32_t pair, uint32_t t, uint32
     return word == 0 ? u4.x : word == 1 ? u4.y : word == 2 ? u4.z : u4.w;
 }
 
+// Pair (a, b) at index q < n (n - 1) / 2 of the lexicographic order.  Counted
+// from the last pair, m = n (n - 1) / 2 - 1 - q lies in row a = n - 2 - j,
+// where j (j + 1) / 2 <= m < (j + 1) (j + 2) / 2; the float square root
+// gives j up to one step, which the two checks settle.
+__device__ __forceinline__ void pair_at(int q, int n, int &a, int &b) {
+    const int m = n * (n - 1) / 2 - 1 - q;
+    int j = (int)((sqrtf(8.0f * (float)m + 1.0f) - 1.0f) * 0.5f);
+    j += (j + 1) * (j + 2) / 2 <= m;
+    j -= j * (j + 1) / 2 > m;
+    a = n - 2 - j;
+    b = n - 1 - (m - j * (j + 1) / 2);
+}
+
+// Threshold T(d) of a row in LDS (high digit A at [0, ha), low digit B at
+// [ha, ha + 1024)): (A[d >> 10] B[d & 1023]) >> 32, and 0 from d = 1024 ha on.
+__device__ __forceinline__ uint32_t qap_thr(const uint32_t *row, int ha, int d) {
+    const int h = d >> kQapLowBits;
+    return h < ha ? __umulhi(row[h], row[ha + (d & ((1 << kQapLowBits) - 1))]) : 0u;
+}
+
+// The acceptance bound of random word u: the smallest d >= 1 with T(d) <= u.
+// For a row whose T never increases with d (the host checks every row), a
+// proposal with cost change dC is accepted (dC <= 0, or u < T(dC)) exactly
+// when dC < d*(u), so a step compares two integers instead of reading two
+// table words.  The search starts at ceil(ln(2^32 / u) / beta), where
+// 2^32 exp(-beta d) = u, checks that guess and the word before it, and
+// otherwise moves outward in doubling steps and bisects: the result is exact
+// whatever the guess; the guess only saves steps (for all but the smallest u
+// it is right or one off).  1 / beta is the float after the row's B.
+__device__ int qap_dstar(const uint32_t *row, int ha, uint32_t u) {
+    const int dlim = ha << kQapLowBits;  // T(dlim) = 0 <= u
+    const float inv_beta = __uint_as_float(row[ha + (1 << kQapLowBits)]);
+    int e;
+    const float m = frexpf((float)u, &e);  // u = m 2^e, m in [1/2, 1)
+    const float x = ((float)(32 - e) - __log2f(m)) * 0.6931472f * inv_beta;
+    const int g = x < (float)dlim ? max(1, (int)ceilf(x)) : dlim;
+    const uint32_t tg = qap_thr(row, ha, g), tp = qap_thr(row, ha, max(g - 1, 1));
+    int lo, hi;  // T(lo) > u (lo = 0: no d below hi), T(hi) <= u
+    if (tg <= u) {
+        if (g == 1 || tp > u)
+            return g;
+        hi = g - 1;
+        for (int step = 1;; step <<= 1) {
+            lo = max(0, hi - step);
+            if (lo == 0 || qap_thr(row, ha, lo) > u)
+                break;
+            hi = lo;
+        }
+    } else {
+        lo = g;
+        for (int step = 1;; step <<= 1) {
+            hi = min(dlim, lo + step);
+            if (hi == dlim || qap_thr(row, ha, hi) <= u)
+                break;
+            lo = hi;
+        }
+    }
+    while (hi - lo > 1) {
+        const int mid = lo + ((hi - lo) >> 1);
+        if (qap_thr(row, ha, mid) <= u)
+            hi = mid;
+        else
+            lo = mid;
+    }
+    return hi;
+}
+
+// Per lane, for pair index q (clamped to the sweep): with C.dstar the bound
+// d* of the pair's random word u in the table row of the pair's class (HOT if
+// either facility is), else u itself.
+__device__ __forceinline__ uint32_t qap_lane_word(const QapDev &I, const QapCall &C, const uint32_t *tw,
+                                                  const uint8_t *cls, bool one_class, uint32_t q, uint32_t t,
+                                                  uint32_t group, int word) {
+    const uint32_t u = sweep_word(q, t, group, word, C.key0, C.key1);
+    if (!C.dstar)
+        return u;
+    const uint32_t *row = tw;
+    if (!one_class) {
+        int a, b;
+        pair_at(min((int)q, I.n * (I.n - 1) / 2 - 1), I.n, a, b);
+        row += max((int)cls[a], (int)cls[b]) * C.stride;
+    }
+    return (uint32_t)qap_dstar(row, I.ha, u);
+}
+
 __global__ void qap_init_kernel(QapDev I, QapRepDev R, uint32_t key0, uint32_t key1) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= R.n_rep)
@@ -203,8 +288,9 @@ __device__ __forceinline__ int qap_wave_sweep(const QapDev &I, const QapCall &C,
     int cur_a = -1, pa = 0, n_acc = 0;
     bool refresh = false;  // a swap was applied: D[p_a][p_k] is stale
     uint32_t pbase = 0;
-    uint32_t uw = sweep_word((uint32_t)lane, t, group, word, C.key0, C.key1);
-    uint32_t uw2 = sweep_word(64u + (uint32_t)lane, t, group, word, C.key0, C.key1);
+    // lane l: the word (or acceptance bound) of pair pbase + l and of pbase + 64 + l
+    uint32_t uw = qap_lane_word(I, C, tl, cls, one_class, (uint32_t)lane, t, group, word);
+    uint32_t uw2 = qap_lane_word(I, C, tl, cls, one_class, 64u + (uint32_t)lane, t, group, word);
     // locations of this step's b and a, read during the previous step
     // (valid because no swap happened since; re-read after a swap)
     int pb = pr[br], pa_ahead = pr[ar];
@@ -252,13 +338,18 @@ __device__ __forceinline__ int qap_wave_sweep(const QapDev &I, const QapCall &C,
         const uint32_t ua = (uint32_t)__builtin_amdgcn_ds_bpermute(sl, (int)uw);
         const uint32_t ub = (uint32_t)__builtin_amdgcn_ds_bpermute(sl, (int)uw2);
         const uint32_t u = src < 64 ? ua : ub;
-        bool acc = dc <= 0;
-        if (!acc) {
-            const int cl = one_class ? 0 : max((int)cls[ar], (int)cls[br]);
-            const uint32_t *T = tl + cl * C.stride;
-            const int h = dc >> kQapLowBits, l = dc & ((1 << kQapLowBits) - 1);
-            const uint32_t thr = h < I.ha ? (uint32_t)(((uint64_t)T[h] * (uint64_t)T[I.ha + l]) >> 32) : 0u;
-            acc = u < thr;
+        bool acc;
+        if (C.dstar) {
+            acc = dc < (int)u;
+        } else {
+            acc = dc <= 0;
+            if (!acc) {
+                const int cl = one_class ? 0 : max((int)cls[ar], (int)cls[br]);
+                const uint32_t *T = tl + cl * C.stride;
+                const int h = dc >> kQapLowBits, l = dc & ((1 << kQapLowBits) - 1);
+                const uint32_t thr = h < I.ha ? (uint32_t)(((uint64_t)T[h] * (uint64_t)T[I.ha + l]) >> 32) : 0u;
+                acc = u < thr;
+            }
         }
         int adv = ROWS, j = -1;
         acc = acc && p0 + row < npairs;
@@ -309,7 +400,7 @@ __device__ __forceinline__ int qap_wave_sweep(const QapDev &I, const QapCall &C,
         if (p0 >= (int)pbase + 64) {
             pbase += 64;
             uw = uw2;
-            uw2 = sweep_word(pbase + 64u + (uint32_t)lane, t, group, word, C.key0, C.key1);
+            uw2 = qap_lane_word(I, C, tl, cls, one_class, pbase + 64u + (uint32_t)lane, t, group, word);
         }
     }
     return n_acc;
@@ -330,26 +421,6 @@ __device__ __forceinline__ int wave_sum(int x) {
 
 __device__ __forceinline__ int lane_set(int v, int l, int x) { return (int)(threadIdx.x & 63) == l ? x : v; }
 
-// Threshold words read through the scalar cache (read-only in the kernel).
-typedef const uint32_t __attribute__((address_space(4))) scalar_u32;
-
-// Word at a 32-bit byte offset from a scalar-cache pointer (base plus an
-// unsigned 32-bit offset, the scalar load's own addressing form).
-__device__ __forceinline__ uint32_t scalar_word(scalar_u32 *base, uint32_t byte_off) {
-    typedef const uint8_t __attribute__((address_space(4))) scalar_u8;
-    return *reinterpret_cast<scalar_u32 *>(reinterpret_cast<scalar_u8 *>(base) + byte_off);
-}
-
-// A pointer the whole wave holds (per-wave data derived from threadIdx.x / 64
-// is uniform, but the compiler cannot see it): taken from the first lane so
-// that loads through it can be scalar.
-__device__ __forceinline__ const uint32_t *wave_uniform(const uint32_t *p) {
-    const uint64_t v = reinterpret_cast<uint64_t>(p);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
-    return reinterpret_cast<const uint32_t *>(((uint64_t)hi << 32) | lo);
-}
-
 // One sweep of one replica by one wave, one proposal per step on all 64
 // lanes (KPL facilities per lane, k = lane + 64 i), for sweeps where most
 // proposals are accepted.  The permutation lives in the lanes while the sweep
@@ -361,32 +432,29 @@ __device__ __forceinline__ const uint32_t *wave_uniform(const uint32_t *p) {
 // and k = b terms are both -F_ab D_{p_a p_b}, so the definition's sum over the
 // other k is that total plus 2 F_ab D_{p_a p_b}, whose factors b's lane holds.
 // An accepted swap turns the cached row into the one just gathered, with 0 at
-// k = a and the old D_{p_a p_b} at k = b.  Threshold words come through the
-// scalar cache from the sweep's table rows in global memory (tg).  Same
-// decisions, words and counters as qap_wave_sweep.  Returns the number of
-// accepted swaps.
+// k = a and the old D_{p_a p_b} at k = b.  A proposal is accepted when its
+// change is below the acceptance bound d* of its random word (lane l holds
+// the bound of pair pbase + l, from the wave's threshold rows tw in LDS;
+// the call's rows must pass the host's check, C.dstar).  Same decisions,
+// words and counters as qap_wave_sweep.  Returns the number of accepted swaps.
 template <int KPL, int KP>
 __device__ __forceinline__ int qap_wave_sweep1(const QapDev &I, const QapCall &C, const uint8_t *F, const uint8_t *D,
-                                               const uint8_t *cls, const uint32_t *tg, uint8_t *pr, uint32_t t,
+                                               const uint8_t *cls, const uint32_t *tw, uint8_t *pr, uint32_t t,
                                                uint32_t group, int word, long long &cost) {
     constexpr int RB = 16 * KP;
     const int n = I.n;
     const int lane = threadIdx.x & 63;
     const bool one_class = C.n_classes == 1;
     const int flo = (lane & 15) * KP + (lane >> 4);  // byte of k = lane in a flow row; k + 64 i at + 4 i
-    scalar_u32 *T = (scalar_u32 *)wave_uniform(tg);
-    // p_k and the word offset of facility k's class row in the sweep's table
-    // (a pair takes the row of the larger class: the larger offset)
-    int pk[KPL], ck[KPL];
+    int pk[KPL];
 #pragma unroll
     for (int i = 0; i < KPL; ++i) {
         const int k = lane + 64 * i;
         pk[i] = k < n ? pr[k] : 0;
-        ck[i] = (!one_class && k < n) ? cls[k] * C.stride : 0;
     }
     int n_acc = 0, widx = 0;
     uint32_t pbase = 0;
-    uint32_t uw = sweep_word((uint32_t)lane, t, group, word, C.key0, C.key1);
+    uint32_t dsv = qap_lane_word(I, C, tw, cls, one_class, (uint32_t)lane, t, group, word);
     // accepted changes since the last flush into cost: at most 64 proposals,
     // each |dC| <= 2 (n - 2) 255^2, so the sum fits 32 bits for n <= 255
     int csum = 0;
@@ -399,7 +467,6 @@ __device__ __forceinline__ int qap_wave_sweep1(const QapDev &I, const QapCall &C
             const int la = a - 64 * SA;
             const bool lane_a = lane == la;
             int pa = __builtin_amdgcn_readlane(pk[SA], la);
-            const int cla = __builtin_amdgcn_readlane(ck[SA], la);
             int fa[KPL], da[KPL];
 #pragma unroll
             for (int i = 0; i < KPL; ++i) {
@@ -422,18 +489,8 @@ __device__ __forceinline__ int qap_wave_sweep1(const QapDev &I, const QapCall &C
                     }
                     const int fab = __builtin_amdgcn_readlane(fa[S], lb), dab = __builtin_amdgcn_readlane(da[S], lb);
                     const int dc = 2 * (wave_sum(part) + 2 * fab * dab);
-                    const uint32_t u = (uint32_t)__builtin_amdgcn_readlane((int)uw, widx);
-                    bool acc = dc <= 0;
-                    if (!acc) {
-                        const int h = dc >> kQapLowBits, l = dc & ((1 << kQapLowBits) - 1);
-                        if (h < I.ha) {
-                            const uint32_t row = (uint32_t)max(cla, __builtin_amdgcn_readlane(ck[S], lb));
-                            const uint32_t th = scalar_word(T, (row + (uint32_t)h) << 2);
-                            const uint32_t tl = scalar_word(T, (row + (uint32_t)(I.ha + l)) << 2);
-                            acc = u < (uint32_t)(((uint64_t)th * (uint64_t)tl) >> 32);
-                        }
-                    }
-                    if (acc) {
+                    const int ds = __builtin_amdgcn_readlane((int)dsv, widx);
+                    if (dc < ds) {
                         ++n_acc;
                         csum += dc;
                         // p_a <-> p_b; the cached row becomes D[p_b][.] with 0 at
@@ -450,7 +507,7 @@ __device__ __forceinline__ int qap_wave_sweep1(const QapDev &I, const QapCall &C
                     if (++widx == 64) {
                         widx = 0;
                         pbase += 64;
-                        uw = sweep_word(pbase + (uint32_t)lane, t, group, word, C.key0, C.key1);
+                        dsv = qap_lane_word(I, C, tw, cls, one_class, pbase + (uint32_t)lane, t, group, word);
                         cost += csum;
                         csum = 0;
                     }
@@ -977,9 +1034,6 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
         qrows[wave] = active ? rows : 0;
     for (int s = 0; s < C.n_sweeps; ++s) {
         const uint32_t t = C.t0 + (uint32_t)s;
-        // this wave's table rows of the sweep in global memory (read through the
-        // scalar cache by the one-proposal path; the LDS copy serves the others)
-        const uint32_t *tgw = row_of(mix ? wave >> 2 : 0) + (size_t)s * C.sweep_words;
         for (int q = 0; q < nslots; ++q) {
             const uint32_t *tg = row_of(q) + (size_t)s * C.sweep_words;
             for (int i = tid; i < tab_words; i += blockDim.x)
@@ -1023,12 +1077,14 @@ __device__ __forceinline__ void qap_sweep_block(const QapDev &I, const QapRepDev
                     if (rows == 8)
                         n_acc = qap_wave_sweep<8, KPL8, KP>(I, C, F, F8, D, cls, tw, pr, t, group, word, cost);
                     else
-                        n_acc = rows == 4
+                        n_acc = rows == 4 || !C.dstar
                                     ? qap_wave_sweep<4, KPL4, KP>(I, C, F, F8, D, cls, tw, pr, t, group, word, cost)
-                                    : qap_wave_sweep1<KPL1, KP>(I, C, F, D, cls, tgw, pr, t, group, word, cost);
+                                    : qap_wave_sweep1<KPL1, KP>(I, C, F, D, cls, tw, pr, t, group, word, cost);
                 } else {
-                    n_acc = rows == 4 ? qap_wave_sweep<4, KPL4, KP>(I, C, F, F8, D, cls, tw, pr, t, group, word, cost)
-                                      : qap_wave_sweep1<KPL1, KP>(I, C, F, D, cls, tgw, pr, t, group, word, cost);
+                    // (the one-proposal path needs the acceptance bounds)
+                    n_acc = rows == 4 || !C.dstar
+                                ? qap_wave_sweep<4, KPL4, KP>(I, C, F, F8, D, cls, tw, pr, t, group, word, cost)
+                                : qap_wave_sweep1<KPL1, KP>(I, C, F, D, cls, tw, pr, t, group, word, cost);
                 }
             }
             acc_total += (unsigned long long)n_acc;

@@ -185,3 +185,48 @@ def test_qap_multi_replica_waves_match_oracle(n, R, rpw, monkeypatch):
     cls = p.backbone(1, 2)
     p.anneal(reanneal_profile(6, sc, beta_hot=0.05, beta_end=0.2), profile="backbone", class_of=cls)
     p.compare()
+
+
+@pytest.mark.parametrize("rows", ["1", "8", "0"])
+def test_qap_acceptance_bound_extremes(rows, monkeypatch):
+    """The sweeps accept a proposal when its change is below the acceptance
+    bound d*(u) of its random word, found by a search that starts from a
+    float guess: exact whatever the guess.  Schedules at beta = 0 (every
+    threshold 2^32 - 1; the guess is the end of the table), very small and
+    very large beta (the guess far from most words' bounds) and two classes
+    of different beta in one sweep stay bit-exact with the oracle, which reads
+    the thresholds directly."""
+    monkeypatch.setenv("NMC_QAP_ROWS", rows)
+    F, D = instances.gen_qap(41, SEED + 41)
+    sc = beta_scale(F, D)
+    for R, betas in ((7, [0.0, 0.0]), (9, [1e-7 * sc, 1e-4 * sc, 3e-3 * sc]), (6, [50.0 * sc, 1e3 * sc, 1e6 * sc]),
+                     (16, [0.02 * sc, 0.5 * sc, 2.0 * sc, 12.0 * sc])):
+        say(f"case: qap acceptance bound rows={rows} R={R} betas={betas}")
+        p = QapPair(F, D, R, SEED + R)
+        p.anneal(np.array(betas)[None, :], target=0)
+        p.compare()
+    p = QapPair(F, D, 12, SEED + 3)
+    p.anneal(np.geomspace(0.1 * sc, 4.0 * sc, 6)[None, :])
+    cls = (np.arange(41) % 4 == 1).astype(np.uint8)
+    beta = np.stack([np.full(5, 6.0 * sc), np.array([0.0, 1e-6, 0.3, 1.0, 30.0]) * sc])
+    p.anneal(beta, class_of=cls)
+    p.compare()
+
+
+def test_qap_direct_threshold_reads_match_oracle(monkeypatch):
+    """NMC_QAP_DSTAR=0: every proposal reads its two threshold words (the path
+    the library takes when a table row's T is not monotone, which the host
+    checks per row); the per-sweep width choice then never takes the
+    one-proposal path.  Bit-exact with the oracle at the full-size shape's
+    width limits and with two classes."""
+    monkeypatch.setenv("NMC_QAP_DSTAR", "0")
+    for n, R in ((45, 9), (100, 16)):
+        say(f"case: qap direct thresholds n={n} R={R}")
+        F, D = instances.gen_qap(n, SEED + 11 * n)
+        sc = beta_scale(F, D)
+        p = QapPair(F, D, R, SEED + n)
+        p.anneal(np.geomspace(0.05 * sc, 8.0 * sc, 10)[None, :], target=0)
+        p.compare()
+        cls = p.backbone(2, 3)
+        p.anneal(reanneal_profile(4, sc), profile="backbone", class_of=cls)
+        p.compare()
