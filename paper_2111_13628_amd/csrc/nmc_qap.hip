@@ -216,7 +216,8 @@ __global__ void qap_reset_tallies_kernel(QapRepDev R) {
 // Flow matrix layout in LDS: row b holds F[b][k] at byte (k % 16) * KP + k / 16
 // (zero for k >= n), so the KP bytes a lane of a 16-lane row needs
 // (k = q, q + 16, ...) are contiguous and come in one wide read.  Fills
-// f[i] = F[row][k_i] for the lane's k_i = q + (64 / ROWS) * i.
+// f[i] = F[row][k_i] for the lane's k_i = q + (64 / ROWS) * i (the table-mode
+// row sums).
 template <int ROWS, int KPL, int KP>
 __device__ __forceinline__ void flow_row(const uint8_t *row, int q, int (&f)[KPL]) {
     if constexpr (ROWS == 4) {
@@ -239,14 +240,28 @@ __device__ __forceinline__ void flow_row(const uint8_t *row, int q, int (&f)[KPL
 
 // Second flow layout, for eight 8-lane rows: row b holds F[b][q + 8i] at byte
 // q * 16 + i (zero past n), so a lane's 16 bytes come in one 16-byte read.
-template <int KPL>
-__device__ __forceinline__ void flow_row8(const uint8_t *row, int q, int (&f)[KPL]) {
-    static_assert(KPL <= 16, "flow layout");
-    const uint4 v = *reinterpret_cast<const uint4 *>(row + q * 16);
-    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+//
+// Flow row b of a lane of the ROWS-row schemes as KW words, four facilities
+// per word (byte j of word w: facility k_{4w+j} = q + (64 / ROWS)(4w + j)),
+// straight from either layout: the lane's bytes are contiguous in both.
+template <int ROWS, int KW, int KP>
+__device__ __forceinline__ void flow_words(const uint8_t *F, const uint8_t *F8, int b, int q, uint32_t (&w)[KW]) {
+    static_assert(ROWS == 8 ? KW <= 4 : 4 * KW <= KP, "flow layout");
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(ROWS == 8 ? F8 + b * 128 + q * 16 : F + b * 16 * KP + q * KP);
 #pragma unroll
-    for (int i = 0; i < KPL; ++i)
-        f[i] = (int)((w[i >> 2] >> (8 * (i & 3))) & 0xFFu);
+    for (int j = 0; j < KW; ++j)
+        w[j] = src[j];
+}
+
+// Distance bytes drow[p_k] of the lane's facilities 4w .. 4w + 3, packed as
+// one word (0 past the lane's KPL facilities).
+template <int KPL>
+__device__ __forceinline__ uint32_t gather_word(const uint8_t *drow, const int (&pk)[KPL], int w) {
+    uint32_t g[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        g[j] = 4 * w + j < KPL ? (uint32_t)drow[pk[4 * w + j]] : 0u;
+    return __builtin_amdgcn_perm(g[2] | (g[3] << 8), g[0] | (g[1] << 8), 0x05040100u);
 }
 
 // One sweep of one replica by one wave.  ROWS (4 or 8) proposals are
@@ -276,7 +291,11 @@ __device__ __forceinline__ int qap_wave_sweep(const QapDev &I, const QapCall &C,
     const int lane = threadIdx.x & 63;
     const int row = lane / LANES, q = lane % LANES;
     const bool one_class = C.n_classes == 1;
-    int pk[KPL], fa[KPL], da[KPL];
+    // the lane's facilities four to a word: F[a][k] and D[p_a][p_k], and their
+    // products' sum rw (all bytes, so every product is an exact 4-way dot)
+    constexpr int KW = (KPL + 3) / 4;
+    int pk[KPL];
+    uint32_t faw[KW], daw[KW], rw = 0;
 #pragma unroll
     for (int i = 0; i < KPL; ++i) {
         const int k = q + LANES * i;
@@ -298,34 +317,37 @@ __device__ __forceinline__ int qap_wave_sweep(const QapDev &I, const QapCall &C,
         if (ar != cur_a) {
             cur_a = ar;
             pa = pa_ahead;
-            if constexpr (ROWS == 8)
-                flow_row8<KPL>(F8 + ar * 128, q, fa);
-            else
-                flow_row<ROWS, KPL, KP>(F + ar * RB, q, fa);
+            flow_words<ROWS, KW, KP>(F, F8, ar, q, faw);
             refresh = true;
         }
         if (refresh) {
+            rw = 0;
 #pragma unroll
-            for (int i = 0; i < KPL; ++i)
-                da[i] = D[pa * n + pk[i]];
+            for (int w = 0; w < KW; ++w) {
+                daw[w] = gather_word<KPL>(D + pa * n, pk, w);
+                rw = __builtin_amdgcn_udot4(faw[w], daw[w], rw, false);
+            }
             refresh = false;
         }
         // the next step's pairs if no proposal of this step is accepted
         int an = ar, bn = br;
         pair_advance(an, bn, n, ROWS);
         const int pbn = pr[bn], pan = pr[an];
-        int fb[KPL];
-        if constexpr (ROWS == 8)
-            flow_row8<KPL>(F8 + br * 128, q, fb);
-        else
-            flow_row<ROWS, KPL, KP>(F + br * RB, q, fb);
+        uint32_t fbw[KW];
+        flow_words<ROWS, KW, KP>(F, F8, br, q, fbw);
         const uint8_t *drow_b = D + pb * n;
-        // the byte masks restate the ranges the loop-carried values lost, so
-        // that the products stay 24-bit multiplies
-        int part = 0;
+        // sum_k (F_ak - F_bk)(D_{p_b p_k} - D_{p_a p_k}) over the lane's k as
+        // F_a.D_b + F_b.D_a - F_b.D_b - F_a.D_a: four facilities per dot
+        // instruction, in 32-bit words that hold each sum exactly
+        uint32_t x = 0u - rw, y = 0u;
 #pragma unroll
-        for (int i = 0; i < KPL; ++i)
-            part += __mul24((fa[i] & 0xFF) - fb[i], (int)drow_b[pk[i]] - (da[i] & 0xFF));
+        for (int w = 0; w < KW; ++w) {
+            const uint32_t dbw = gather_word<KPL>(drow_b, pk, w);
+            x = __builtin_amdgcn_udot4(faw[w], dbw, x, false);
+            x = __builtin_amdgcn_udot4(fbw[w], daw[w], x, false);
+            y = __builtin_amdgcn_udot4(fbw[w], dbw, y, false);
+        }
+        int part = (int)(x - y);
         if (q == 0)
             part += 2 * (int)F[ar * RB + (br & 15) * KP + (br >> 4)] * (int)D[pa * n + pb];
         if constexpr (ROWS == 8)
