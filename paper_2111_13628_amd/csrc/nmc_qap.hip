@@ -24,6 +24,11 @@
 #include "nmc_internal.h"
 #include "nmc_philox.h"
 
+// The compiler's lane-write intrinsic (v_writelane_b32: src into lane
+// `lane` of old; src and lane wave-uniform), which this toolchain's HIP
+// headers do not name.
+__device__ int nmc_amdgcn_writelane(int src, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
 namespace nmc {
 
 namespace {
@@ -85,6 +90,9 @@ __device__ __forceinline__ void pair_at(int q, int n, int &a, int &b) {
     a = n - 2 - j;
     b = n - 1 - (m - j * (j + 1) / 2);
 }
+
+// x with lane l set to v (l and v wave-uniform).
+__device__ __forceinline__ int lane_write(int x, int l, int v) { return nmc_amdgcn_writelane(v, l, x); }
 
 // Threshold T(d) of a row in LDS (high digit A at [0, ha), low digit B at
 // [ha, ha + 1024)): (A[d >> 10] B[d & 1023]) >> 32, and 0 from d = 1024 ha on.
@@ -441,7 +449,6 @@ __device__ __forceinline__ int wave_sum(int x) {
     return __builtin_amdgcn_readlane(x, 63);
 }
 
-__device__ __forceinline__ int lane_set(int v, int l, int x) { return (int)(threadIdx.x & 63) == l ? x : v; }
 
 // One sweep of one replica by one wave, one proposal per step on all 64
 // lanes (KPL facilities per lane, k = lane + 64 i), for sweeps where most
@@ -487,7 +494,6 @@ __device__ __forceinline__ int qap_wave_sweep1(const QapDev &I, const QapCall &C
         const int a_end = min(n - 1, 64 * SA + 64);
         for (int a = 64 * SA; a < a_end; ++a) {
             const int la = a - 64 * SA;
-            const bool lane_a = lane == la;
             int pa = __builtin_amdgcn_readlane(pk[SA], la);
             int fa[KPL], da[KPL];
 #pragma unroll
@@ -495,6 +501,10 @@ __device__ __forceinline__ int qap_wave_sweep1(const QapDev &I, const QapCall &C
                 fa[i] = F[a * RB + flo + 4 * i];
                 da[i] = D[pa * n + pk[i]];
             }
+            // the cached row's word at k = a: D[p_a][p_a] = 0 when gathered,
+            // the accepted swap's D_{p_a p_b} after an accept (left in place
+            // and taken out of the sum in closed form)
+            int g = 0;
 #pragma unroll
             for (int S = SA; S < KPL; ++S) {
                 const int b_end = min(n, 64 * S + 64);
@@ -509,21 +519,24 @@ __device__ __forceinline__ int qap_wave_sweep1(const QapDev &I, const QapCall &C
                         db[i] = D[pb * n + pk[i]];
                         part += __mul24(fa[i] - fb, db[i] - da[i]);
                     }
+                    // the k = b term is -F_ab D_ab and the k = a term, with g in
+                    // place of D[p_a][p_a] = 0, -F_ab (D_ab - g)
                     const int fab = __builtin_amdgcn_readlane(fa[S], lb), dab = __builtin_amdgcn_readlane(da[S], lb);
-                    const int dc = 2 * (wave_sum(part) + 2 * fab * dab);
+                    const int dc = 2 * (wave_sum(part) + fab * (2 * dab - g));
                     const int ds = __builtin_amdgcn_readlane((int)dsv, widx);
                     if (dc < ds) {
                         ++n_acc;
                         csum += dc;
-                        // p_a <-> p_b; the cached row becomes D[p_b][.] with 0 at
-                        // k = a and the old D_{p_a p_b} at k = b
-                        pk[SA] = lane_a ? pb : pk[SA];
-                        pk[S] = lane_set(pk[S], lb, pa);
+                        // p_a <-> p_b; the cached row becomes D[p_b][.]: the
+                        // gathered row, with the old D_{p_a p_b} at k = b and
+                        // (as g) at k = a
+                        pk[SA] = lane_write(pk[SA], la, pb);
+                        pk[S] = lane_write(pk[S], lb, pa);
 #pragma unroll
                         for (int i = 0; i < KPL; ++i)
                             da[i] = db[i];
-                        da[SA] = lane_a ? 0 : da[SA];
-                        da[S] = lane_set(da[S], lb, dab);
+                        da[S] = lane_write(da[S], lb, dab);
+                        g = dab;
                         pa = pb;
                     }
                     if (++widx == 64) {
