@@ -283,13 +283,13 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
                 uint4 q0 = rp[0], q1 = rp[(size_t)min(1, lastp) * kChunk];
                 uint4 q2 = rp[(size_t)min(2, lastp) * kChunk], q3 = rp[(size_t)min(3, lastp) * kChunk];
                 issue_fence();
-                for (int k = 0;; k += 2 * kSlotUnroll) {
+                // whole groups of 8 slots with one exit, then a tail of 4
+                int k = 0;
+                for (; k + 2 * kSlotUnroll <= nslot; k += 2 * kSlotUnroll) {
                     step(q0.x, q0.y);
                     step(q0.z, q0.w);
                     step(q1.x, q1.y);
                     step(q1.z, q1.w);
-                    if (k + kSlotUnroll >= nslot)
-                        break;
                     q0 = rp[(size_t)min(k / 2 + 4, lastp) * kChunk];
                     q1 = rp[(size_t)min(k / 2 + 5, lastp) * kChunk];
                     issue_fence();
@@ -297,11 +297,15 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
                     step(q2.z, q2.w);
                     step(q3.x, q3.y);
                     step(q3.z, q3.w);
-                    if (k + 2 * kSlotUnroll >= nslot)
-                        break;
                     q2 = rp[(size_t)min(k / 2 + 6, lastp) * kChunk];
                     q3 = rp[(size_t)min(k / 2 + 7, lastp) * kChunk];
                     issue_fence();
+                }
+                if (k < nslot) {
+                    step(q0.x, q0.y);
+                    step(q0.z, q0.w);
+                    step(q1.x, q1.y);
+                    step(q1.z, q1.w);
                 }
                 const uint32_t nneg = lw < 0 ? 0u : ((uint32_t)lw >> 20) & 0xFFu;
                 // the lane's share of the closed form (sums mod 2^32 add up
