@@ -182,6 +182,7 @@ struct nmc_instance {
     // layout offsets into the device arena
     size_t off_rec = 0, off_chunk_var = 0, off_chunk_info = 0, off_color_chunk = 0, off_clause_addr = 0,
            off_var_ptr = 0, off_var_cl = 0;
+    uint32_t rec_bytes = 0;  // size of the record array
     // QAP host data
     int64_t delta_bound = 0;
     int32_t qap_ha = 0;
@@ -201,6 +202,7 @@ struct nmc_instance {
     KsatDev ksat_dev() const {
         KsatDev d{};
         d.rec = reinterpret_cast<const uint64_t *>(dev + off_rec);
+        d.rec_bytes = rec_bytes;
         d.chunk_var = reinterpret_cast<const int32_t *>(dev + off_chunk_var);
         d.chunk_info = reinterpret_cast<const int2 *>(dev + off_chunk_info);
         d.color_chunk = reinterpret_cast<const int32_t *>(dev + off_color_chunk);
@@ -605,6 +607,7 @@ int nmc_ksat_load(int32_t n_vars, int32_t n_clauses, const int32_t *clause_ptr, 
 
         Arena ar;
         I->off_rec = ar.take(rec.size() * 8);
+        I->rec_bytes = (uint32_t)(rec.size() * 8);  // below 2^31: N <= 65534 and degree <= 127
         I->off_chunk_var = ar.take(chunk_var.size() * 4);
         I->off_chunk_info = ar.take(chunk_info.size() * 8);
         I->off_color_chunk = ar.take(color_chunk.size() * 4);

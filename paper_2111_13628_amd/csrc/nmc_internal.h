@@ -50,7 +50,12 @@ struct KsatDev {
     const int32_t *var_ptr;      // [N + 1] variable -> clause incidence
     const int32_t *var_cl;       // [sum deg]
     int32_t n, m, n_colors, n_chunks, dmax;
+    uint32_t rec_bytes;          // size of rec in bytes (the bound of the sweep's buffer loads)
 };
+
+// Buffer resource word 3 (format and type bits) for raw byte-addressed
+// buffer loads on gfx9-family GPUs.
+constexpr int kBufferWord3 = 0x00020000;
 
 // Device view of a k-SAT replica set.
 struct KsatRepDev {

@@ -224,6 +224,9 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
     __syncthreads();
 
     uint32_t n_acc = 0;  // flips this lane accepted in this call
+    // the instance's records (out-of-range offsets would read zeros)
+    const __amdgpu_buffer_rsrc_t recs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint64_t *>(I.rec), 0, (int)I.rec_bytes, kBufferWord3);
     for (int s = 0; s < C.n_sweeps; ++s) {
         const uint32_t t = C.t0 + (uint32_t)s;
         const uint32_t *tg = tab + (size_t)s * C.sweep_words;
@@ -262,8 +265,15 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
                 const int v = (lw < 0 || (lane & ((1 << lg) - 1))) ? -1 : (lw & 0xFFFFF);
                 // the variable's class is needed after the slot loop; load it now
                 const int cl = (C.var_cls && v >= 0) ? (int)C.var_cls[v] : 0;
-                const uint4 *rp = reinterpret_cast<const uint4 *>(I.rec) +
-                                  (size_t)(__builtin_amdgcn_readfirstlane(info.x) / 2) * kChunk + lane;
+                // record row `row` of the chunk (16 bytes a lane) as a buffer
+                // load: the row's byte offset is a scalar operand and the
+                // lane's offset the same register for every row, so no vector
+                // instruction computes a record address
+                const int row0 = __builtin_amdgcn_readfirstlane(info.x) / 2;
+                auto rp = [&](int row) -> uint4 {
+                    return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
+                                                         recs, lane * 16, (row0 + row) * (kChunk * 16), 0));
+                };
                 // acc collects sum over slots of (spread(sat) xor signmask); the
                 // closed form below turns it into 128 + dE-part per byte lane.
                 // Slots come in 16-byte pairs; 8 slots of records are in flight
@@ -280,8 +290,8 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
                         slot_step2(acc[0], acc[GPW - 1], make_uint2(x, y));
                 };
                 const int lastp = nslot / 2 - 1;
-                uint4 q0 = rp[0], q1 = rp[(size_t)min(1, lastp) * kChunk];
-                uint4 q2 = rp[(size_t)min(2, lastp) * kChunk], q3 = rp[(size_t)min(3, lastp) * kChunk];
+                uint4 q0 = rp(0), q1 = rp(min(1, lastp));
+                uint4 q2 = rp(min(2, lastp)), q3 = rp(min(3, lastp));
                 issue_fence();
                 // whole groups of 8 slots with one exit, then a tail of 4
                 int k = 0;
@@ -290,15 +300,15 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
                     step(q0.z, q0.w);
                     step(q1.x, q1.y);
                     step(q1.z, q1.w);
-                    q0 = rp[(size_t)min(k / 2 + 4, lastp) * kChunk];
-                    q1 = rp[(size_t)min(k / 2 + 5, lastp) * kChunk];
+                    q0 = rp(min(k / 2 + 4, lastp));
+                    q1 = rp(min(k / 2 + 5, lastp));
                     issue_fence();
                     step(q2.x, q2.y);
                     step(q2.z, q2.w);
                     step(q3.x, q3.y);
                     step(q3.z, q3.w);
-                    q2 = rp[(size_t)min(k / 2 + 6, lastp) * kChunk];
-                    q3 = rp[(size_t)min(k / 2 + 7, lastp) * kChunk];
+                    q2 = rp(min(k / 2 + 6, lastp));
+                    q3 = rp(min(k / 2 + 7, lastp));
                     issue_fence();
                 }
                 if (k < nslot) {
