@@ -94,6 +94,7 @@ typedef struct nmc_instance_info {
     int32_t max_degree;      /* k-SAT: most clauses on one variable; QAP: n-2 */
     int32_t n_colors;        /* k-SAT: sweep classes of the colouring; QAP: 1 */
     int64_t delta_bound;     /* largest |energy change| of one move */
+    int32_t wide;            /* k-SAT: 1 = wide layout (see nmc_ksat_load), 0 = LDS layout; QAP: 0 */
 } nmc_instance_info;
 
 /* Message of the last failing call on this thread ("" if none). */
@@ -108,7 +109,16 @@ int32_t nmc_version(void);
 /* Load a CNF formula (subsection "4-SAT Problems Near Computational Phase
  * Transitions": k-SAT as a conjunction of clauses, each a disjunction of
  * literals; energy = number of violated clauses).
- *   n_vars      N >= 1 variables, N <= 65534 (spin tables live in LDS)
+ *   n_vars      1 <= N <= 2^24 - 2 variables.  Up to 65534 the sweeps keep
+ *               each group of 4 replicas' spin tables in LDS; above that (or
+ *               with the environment variable NMC_KSAT_WIDE=1 at load) the
+ *               instance takes the wide layout: spins in device memory,
+ *               variable-major, one lane per group of 4 replicas, one
+ *               launch per colour class (same results bit for bit).  Wide
+ *               instances support load, replicas, anneal / reanneal (also
+ *               allocation-free), backbone, best energy, recount and state
+ *               calls; tempering, LBP, whitening, cluster flips, batched
+ *               launches and served requests return UNSUPPORTED for them.
  *   n_clauses   M >= 0
  *   clause_ptr  M+1 offsets into lits, non-decreasing, clause_ptr[0] = 0
  *   lits        DIMACS literals: +(v+1) means x_v, -(v+1) means NOT x_v;
@@ -117,7 +127,8 @@ int32_t nmc_version(void);
  *               that many variables.  The sweep order is the colour-major
  *               order of this colouring (see nmc_instance_order).
  * Errors: INVALID (literal 0 or out of range, repeated variable, empty
- * clause, bad offsets), UNSUPPORTED (clause longer than 4, N > 65534). */
+ * clause, bad offsets), UNSUPPORTED (clause longer than 4, N > 2^24 - 2,
+ * a variable in more than 127 clauses). */
 int nmc_ksat_load(int32_t n_vars, int32_t n_clauses, const int32_t *clause_ptr, const int32_t *lits,
                   int32_t class_cap, nmc_instance **out);
 

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnmc.so")
-SOURCES = ["nmc_api.cpp", "nmc_server.cpp", "nmc_ksat.hip", "nmc_qap.hip", "nmc_pt.hip", "nmc_lbp.hip", "nmc_whiten.hip", "nmc_cflip.hip",
+SOURCES = ["nmc_api.cpp", "nmc_server.cpp", "nmc_ksat.hip", "nmc_ksat_wide.hip", "nmc_qap.hip", "nmc_pt.hip", "nmc_lbp.hip", "nmc_whiten.hip", "nmc_cflip.hip",
            "nmc_probe.hip", "nmc_noalloc.hip"]
 ARCH = os.environ.get("NMC_OFFLOAD_ARCH", "gfx950")
 

@@ -183,6 +183,9 @@ struct nmc_instance {
     size_t off_rec = 0, off_chunk_var = 0, off_chunk_info = 0, off_color_chunk = 0, off_clause_addr = 0,
            off_var_ptr = 0, off_var_cl = 0;
     uint32_t rec_bytes = 0;  // size of the record array
+    // wide layout (spins in device memory; see nmc_ksat_wide.hip)
+    bool wide = false;
+    size_t off_wrec = 0, off_worder = 0, off_wclass = 0;
     // QAP host data
     int64_t delta_bound = 0;
     int32_t qap_ha = 0;
@@ -209,6 +212,10 @@ struct nmc_instance {
         d.clause_addr = reinterpret_cast<const uint32_t *>(dev + off_clause_addr);
         d.var_ptr = reinterpret_cast<const int32_t *>(dev + off_var_ptr);
         d.var_cl = reinterpret_cast<const int32_t *>(dev + off_var_cl);
+        d.wrec = reinterpret_cast<const uint4 *>(dev + off_wrec);
+        d.worder = reinterpret_cast<const int32_t *>(dev + off_worder);
+        d.wclass_ptr = reinterpret_cast<const int32_t *>(dev + off_wclass);
+        d.wide = wide ? 1 : 0;
         d.n = n;
         d.m = m;
         d.n_colors = n_colors;
@@ -389,7 +396,7 @@ extern "C" {
 
 const char *nmc_last_error(void) { return g_err.c_str(); }
 
-int32_t nmc_version(void) { return 100; }
+int32_t nmc_version(void) { return 101; }
 
 int nmc_ksat_load(int32_t n_vars, int32_t n_clauses, const int32_t *clause_ptr, const int32_t *lits,
                   int32_t class_cap, nmc_instance **out) {
@@ -399,8 +406,8 @@ int nmc_ksat_load(int32_t n_vars, int32_t n_clauses, const int32_t *clause_ptr, 
         *out = nullptr;
         if (n_vars < 1)
             return fail(NMC_ERR_INVALID, "n_vars must be >= 1");
-        if (n_vars > kMaxVars)
-            return fail(NMC_ERR_UNSUPPORTED, "n_vars %d exceeds %d", n_vars, kMaxVars);
+        if (n_vars > kMaxWideVars)
+            return fail(NMC_ERR_UNSUPPORTED, "n_vars %d exceeds %d", n_vars, kMaxWideVars);
         if (n_clauses < 0)
             return fail(NMC_ERR_INVALID, "n_clauses must be >= 0");
         if (!clause_ptr || (n_clauses > 0 && !lits))
@@ -434,6 +441,10 @@ int nmc_ksat_load(int32_t n_vars, int32_t n_clauses, const int32_t *clause_ptr, 
         I->kind = NMC_KIND_KSAT;
         I->n = n_vars;
         I->m = n_clauses;
+        // spin tables of more than kMaxVars variables do not fit in LDS;
+        // NMC_KSAT_WIDE=1 takes the wide layout for any size (tests, measurements)
+        const char *wide_env = std::getenv("NMC_KSAT_WIDE");
+        I->wide = n_vars > kMaxVars || (wide_env && wide_env[0] == '1');
         I->energy_bound = n_clauses;
         I->n_lits = clause_ptr[n_clauses];
         I->kmax = kmax;
@@ -497,6 +508,7 @@ int nmc_ksat_load(int32_t n_vars, int32_t n_clauses, const int32_t *clause_ptr, 
         std::vector<int2> chunk_info;
         std::vector<uint64_t> rec;
         int32_t slot_rows = 0;
+        if (!I->wide) {
         // (1) every chunk's lanes and records, (2) placement (chunks are
         // independent: spread over host threads for large instances), (3) the
         // packed record image in chunk order
@@ -597,6 +609,27 @@ int nmc_ksat_load(int32_t n_vars, int32_t n_clauses, const int32_t *clause_ptr, 
         if (debug_banks && model_gathers)
             std::fprintf(stderr, "nmc: %d chunks, %lld slot gathers, modeled %.3f LDS cycles per gather\n",
                          I->n_chunks, (long long)model_gathers, (double)model_cycles / (double)model_gathers);
+        }  // !I->wide
+        // wide layout: per incidence (var_ptr order) the clause's other
+        // literals as spin-table rows (v for x_v, n + 1 + v for NOT x_v, row
+        // n: absent, never true), and whether the variable's own literal is
+        // negated
+        std::vector<uint4> wrec;
+        if (I->wide) {
+            wrec.resize(vcl.size());
+            for (int32_t v = 0; v < n; ++v)
+                for (int32_t q = vptr[v]; q < vptr[v + 1]; ++q) {
+                    const int32_t a = vcl[q], own = vpos[q];
+                    uint32_t w[3] = {(uint32_t)n, (uint32_t)n, (uint32_t)n};
+                    int k = 0;
+                    for (int32_t p = clause_ptr[a]; p < clause_ptr[a + 1]; ++p)
+                        if (p != own) {
+                            const int32_t l = lits[p];
+                            w[k++] = (uint32_t)(std::abs(l) - 1) + (l < 0 ? (uint32_t)n + 1u : 0u);
+                        }
+                    wrec[q] = make_uint4(w[0], w[1], w[2], lits[own] < 0 ? 1u : 0u);
+                }
+        }
 
         std::vector<uint32_t> clause_addr((size_t)m * 4, ZERO);
         for (int32_t a = 0; a < m; ++a) {
@@ -614,6 +647,11 @@ int nmc_ksat_load(int32_t n_vars, int32_t n_clauses, const int32_t *clause_ptr, 
         I->off_clause_addr = ar.take(std::max<size_t>(clause_addr.size() * 4, 16));
         I->off_var_ptr = ar.take(vptr.size() * 4);
         I->off_var_cl = ar.take(std::max<size_t>(vcl.size() * 4, 4));
+        if (I->wide) {
+            I->off_wrec = ar.take(std::max<size_t>(wrec.size() * sizeof(uint4), 16));
+            I->off_worder = ar.take((size_t)n * 4);
+            I->off_wclass = ar.take(I->color_ptr.size() * 4);
+        }
         I->arena_bytes = align_up(ar.size, 256);
         I->image.assign(I->arena_bytes, 0);
         auto put = [&](size_t off, const void *src, size_t bytes) {
@@ -627,6 +665,11 @@ int nmc_ksat_load(int32_t n_vars, int32_t n_clauses, const int32_t *clause_ptr, 
         put(I->off_clause_addr, clause_addr.data(), clause_addr.size() * 4);
         put(I->off_var_ptr, vptr.data(), vptr.size() * 4);
         put(I->off_var_cl, vcl.data(), vcl.size() * 4);
+        if (I->wide) {
+            put(I->off_wrec, wrec.data(), wrec.size() * sizeof(uint4));
+            put(I->off_worder, I->order.data(), (size_t)n * 4);
+            put(I->off_wclass, I->color_ptr.data(), I->color_ptr.size() * 4);
+        }
         *out = I.release();
         return ok();
     } catch (const std::bad_alloc &) {
@@ -696,7 +739,9 @@ int nmc_instance_get_info(const nmc_instance *I, nmc_instance_info *out) {
         out->max_degree = I->dmax;
         out->n_colors = I->n_colors;
         out->delta_bound = I->dmax;
+        out->wide = I->wide ? 1 : 0;
     } else {
+        out->wide = 0;
         out->n_clauses = 0;
         out->max_clause_len = 0;
         out->max_degree = I->n - 2;
@@ -764,6 +809,9 @@ namespace {
 struct ReplicaLayout {
     size_t off_xs, off_best_xs, off_energy, off_best, off_first_hit, off_cls, off_counts, off_frozen, off_tally,
         off_scratch, off_hint, off_dtab, total;
+    // wide k-SAT layout
+    size_t off_wx, off_wnx, off_wbx, off_wdsum, off_wflag;
+    int32_t wgp, wlg;
 };
 
 ReplicaLayout replica_layout(const nmc_instance *I, int32_t R) {
@@ -781,6 +829,20 @@ ReplicaLayout replica_layout(const nmc_instance *I, int32_t R) {
         L.off_frozen = ar.take(I->n);
         L.off_tally = ar.take(64);
         L.off_scratch = ar.take(G * kGroup * 8);
+        if (I->wide) {
+            // rows of a power-of-two size (a row offset is a shift), at least 64
+            int32_t lg = 6;
+            while (((size_t)1 << lg) < G)
+                ++lg;
+            const size_t gp = (size_t)1 << lg, rows = (size_t)I->n + 1;
+            L.wgp = (int32_t)gp;
+            L.wlg = lg;
+            L.off_wx = ar.take(2 * rows * gp);  // spins, then complements
+            L.off_wnx = L.off_wx + rows * gp;
+            L.off_wbx = ar.take(rows * gp);
+            L.off_wdsum = ar.take((size_t)kWideStreams * gp * kGroup * 4);
+            L.off_wflag = ar.take(gp);
+        }
     } else {
         const size_t n = I->n;
         L.off_xs = ar.take((size_t)R * n);
@@ -883,6 +945,10 @@ int nmc_replicas_create(nmc_instance *I, int32_t n_replicas, uint64_t seed, void
         const ReplicaLayout L = replica_layout(I, n_replicas);
         if (bytes < L.total)
             return fail(NMC_ERR_SIZE, "replica buffer has %zu bytes, needs %zu", bytes, L.total);
+        if (I->kind == NMC_KIND_KSAT && I->wide && 2 * ((size_t)I->n + 1) * (size_t)L.wgp >= ((size_t)1 << 31))
+            return fail(NMC_ERR_CAPACITY,
+                        "wide spin tables of %d variables x %d groups exceed 2 GiB (buffer offsets are 32-bit): use "
+                        "fewer replicas per set", I->n, L.wgp);
         std::unique_ptr<nmc_replicas> P(new nmc_replicas());
         P->inst = I;
         P->R = n_replicas;
@@ -907,6 +973,18 @@ int nmc_replicas_create(nmc_instance *I, int32_t n_replicas, uint64_t seed, void
             k.accepted = reinterpret_cast<unsigned long long *>(b + L.off_tally + 32);
             k.n_rep = n_replicas;
             k.n_groups = P->G;
+            if (I->wide) {
+                k.wx = b + L.off_wx;
+                k.wnx = b + L.off_wnx;
+                k.wbx = b + L.off_wbx;
+                k.wdsum = reinterpret_cast<int32_t *>(b + L.off_wdsum);
+                k.wflag = b + L.off_wflag;
+                k.wgp = L.wgp;
+                k.wlg = L.wlg;
+                // the per-stream energy changes start (and end every sweep) at zero
+                HIP_OR_FAIL(hipMemsetAsync(k.wdsum, 0, (size_t)kWideStreams * L.wgp * kGroup * 4, s));
+                HIP_OR_FAIL(hipMemsetAsync(k.wflag, 0, (size_t)L.wgp, s));
+            }
             P->scratch_energy = reinterpret_cast<int32_t *>(b + L.off_scratch);
             HIP_OR_FAIL(hipMemsetAsync(b + L.off_energy, 0, L.off_first_hit + (size_t)P->G * kGroup * 4 - L.off_energy, s));
             HIP_OR_FAIL(hipMemsetAsync(b + L.off_tally, 0, 64, s));
@@ -1006,7 +1084,9 @@ static int anneal_impl(nmc_replicas *P, const double *beta, int32_t n_classes, i
     hipStream_t s = as_stream(stream);
     const bool ksat = I->kind == NMC_KIND_KSAT;
     const int32_t stride = ksat ? I->dmax + 1 : qap_row_words(I->qap_ha);
-    const size_t lds = ksat ? ksat_sweep_lds_bytes(I->n, n_classes, stride) : qap_sweep_lds_bytes(I->n, n_classes, stride);
+    // (wide k-SAT sweeps hold only the threshold rows in LDS)
+    const size_t lds = ksat ? (I->wide ? (size_t)n_classes * stride * 4 : ksat_sweep_lds_bytes(I->n, n_classes, stride))
+                            : qap_sweep_lds_bytes(I->n, n_classes, stride);
     if (lds > kLdsBytes)
         return fail(NMC_ERR_CAPACITY, "sweep needs %zu bytes of LDS (limit %zu)", lds, kLdsBytes);
     if (ksat && I->n > 0 && target > INT32_MAX)
@@ -1078,7 +1158,19 @@ static int anneal_impl(nmc_replicas *P, const double *beta, int32_t n_classes, i
         C.key0 = (uint32_t)P->seed;
         C.key1 = (uint32_t)(P->seed >> 32);
         C.gpw = P->gpw;
-        HIP_OR_FAIL(ksat_launch_sweep(I->ksat_dev(), P->k, C, P->block_threads, s));
+        if (I->wide) {
+            // variable-major spins for the call's sweeps, back to the
+            // group-major state afterwards
+            const KsatDev D = I->ksat_dev();
+            HIP_OR_FAIL(ksat_launch_wide_pack(D, P->k, false, s));
+            std::vector<int32_t> csize(I->n_colors);
+            for (int32_t c = 0; c < I->n_colors; ++c)
+                csize[c] = I->color_ptr[c + 1] - I->color_ptr[c];
+            HIP_OR_FAIL(ksat_launch_wide_sweeps(D, P->k, C, csize.data(), s));
+            HIP_OR_FAIL(ksat_launch_wide_pack(D, P->k, true, s));
+        } else {
+            HIP_OR_FAIL(ksat_launch_sweep(I->ksat_dev(), P->k, C, P->block_threads, s));
+        }
     } else {
         QapCall C{};
         C.tab = reinterpret_cast<const uint32_t *>(up);
@@ -1392,6 +1484,8 @@ static int pt_run_impl(nmc_replicas *P, const double *beta, int32_t n_temps, int
     nmc_instance *I = P->inst;
     if (!I->dev)
         return fail(NMC_ERR_STATE, "instance is not bound");
+    if (I->kind == NMC_KIND_KSAT && I->wide)
+        return fail(NMC_ERR_UNSUPPORTED, "%s is not available for wide k-SAT instances (more than %d variables)", "tempering", kMaxVars);
     const bool ksat = I->kind == NMC_KIND_KSAT;
     if (n_temps < 1 || P->R % n_temps)
         return fail(NMC_ERR_INVALID, "n_temps = %d must be >= 1 and divide the %d replicas", n_temps, P->R);
@@ -1582,6 +1676,8 @@ static int apt_ladder_impl(nmc_replicas *P, double beta_first, double alpha, dou
     nmc_instance *I = P->inst;
     if (!I->dev)
         return fail(NMC_ERR_STATE, "instance is not bound");
+    if (I->kind == NMC_KIND_KSAT && I->wide)
+        return fail(NMC_ERR_UNSUPPORTED, "%s is not available for wide k-SAT instances (more than %d variables)", "the tempering ladder", kMaxVars);
     if (!std::isfinite(beta_first) || beta_first < 0)
         return fail(NMC_ERR_INVALID, "beta_first = %g is not finite and >= 0", beta_first);
     if (!std::isfinite(alpha) || !(alpha > 0))
@@ -1905,6 +2001,8 @@ static int lbp_impl(nmc_replicas *P, int32_t replica, int32_t which, const nmc_l
         return fail(NMC_ERR_STATE, "instance is not bound");
     if (I->kind != NMC_KIND_KSAT)
         return fail(NMC_ERR_UNSUPPORTED, "LBP runs on k-SAT instances");
+    if (I->kind == NMC_KIND_KSAT && I->wide)
+        return fail(NMC_ERR_UNSUPPORTED, "%s is not available for wide k-SAT instances (more than %d variables)", "LBP", kMaxVars);
     if (replica < 0 || replica >= P->R)
         return fail(NMC_ERR_INVALID, "replica %d outside [0, %d)", replica, P->R);
     if (which != NMC_STATE_CURRENT && which != NMC_STATE_BEST)
@@ -1962,6 +2060,8 @@ int nmc_whiten(nmc_replicas *P, int32_t which, int32_t *frozen_out, uint8_t *whi
         return fail(NMC_ERR_STATE, "instance is not bound");
     if (I->kind != NMC_KIND_KSAT)
         return fail(NMC_ERR_UNSUPPORTED, "whitening applies to k-SAT states");
+    if (I->kind == NMC_KIND_KSAT && I->wide)
+        return fail(NMC_ERR_UNSUPPORTED, "%s is not available for wide k-SAT instances (more than %d variables)", "whitening", kMaxVars);
     if (which != NMC_STATE_CURRENT && which != NMC_STATE_BEST)
         return fail(NMC_ERR_INVALID, "which must be NMC_STATE_CURRENT or NMC_STATE_BEST");
     try {
@@ -2009,6 +2109,8 @@ static int cluster_flip_impl(nmc_replicas *P, const int32_t *label, double beta,
         return fail(NMC_ERR_STATE, "instance is not bound");
     if (I->kind != NMC_KIND_KSAT)
         return fail(NMC_ERR_UNSUPPORTED, "cluster flips apply to k-SAT states");
+    if (I->kind == NMC_KIND_KSAT && I->wide)
+        return fail(NMC_ERR_UNSUPPORTED, "%s is not available for wide k-SAT instances (more than %d variables)", "the cluster flip", kMaxVars);
     if (!std::isfinite(beta) || beta < 0)
         return fail(NMC_ERR_INVALID, "beta = %g is not finite and >= 0", beta);
     if ((uint64_t)P->sweeps_done + 1 > 0xFFFFFFFFull)
@@ -3036,6 +3138,10 @@ int nmc_batch_create(nmc_replicas *const *sets, int32_t n_sets, nmc_batch **out)
             for (int32_t j = 0; j < i; ++j)
                 if (sets[j] == sets[i])
                     return fail(NMC_ERR_INVALID, "replica set %d appears twice", i);
+            if (sets[i]->inst->kind == NMC_KIND_KSAT && sets[i]->inst->wide)
+                return fail(NMC_ERR_UNSUPPORTED,
+                            "replica set %d: batched launches are not available for wide k-SAT instances (more than %d "
+                            "variables)", i, kMaxVars);
             B->sets.push_back(sets[i]);
         }
         *out = B.release();
@@ -3056,6 +3162,10 @@ int nmc_batch_set_members(nmc_batch *B, nmc_replicas *const *sets, int32_t n_set
             for (int32_t j = 0; j < i; ++j)
                 if (sets[j] == sets[i])
                     return fail(NMC_ERR_INVALID, "replica set %d appears twice", i);
+            if (sets[i]->inst->kind == NMC_KIND_KSAT && sets[i]->inst->wide)
+                return fail(NMC_ERR_UNSUPPORTED,
+                            "replica set %d: batched launches are not available for wide k-SAT instances (more than %d "
+                            "variables)", i, kMaxVars);
             v.push_back(sets[i]);
         }
         B->sets.swap(v);
@@ -3472,6 +3582,14 @@ extern "C" int nmc_tune(nmc_replicas *P, int32_t probe_sweeps, int32_t *block_th
         return fail(NMC_ERR_INVALID, "NULL replicas");
     if (P->inst->kind != NMC_KIND_KSAT)
         return fail(NMC_ERR_UNSUPPORTED, "the tuner's settings are k-SAT settings");
+    if (P->inst->wide) {
+        // the wide sweeps have no workgroup-shape settings
+        if (block_threads)
+            *block_threads = 0;
+        if (reps_per_workgroup)
+            *reps_per_workgroup = 0;
+        return ok();
+    }
     nmc_batch *B = nullptr;
     int rc = nmc_batch_create(&P, 1, &B);
     if (rc)

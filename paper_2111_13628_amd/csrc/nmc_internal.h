@@ -24,6 +24,17 @@ constexpr int kGroup = 4;
 // Largest variable count: spin-table byte addresses use 17 bits and the
 // "always false" / "always true" entries sit at 2N and 2N+1.
 constexpr int kMaxVars = 65534;
+// Instances above kMaxVars (or loaded with NMC_KSAT_WIDE=1) take the wide
+// layout: spins in device memory, variable-major with one byte per group of
+// 4 replicas and 64 groups per wave (one lane per group).  Literal rows are
+// 31-bit indices, so the wide layout reaches 2^24 variables.
+constexpr int kMaxWideVars = (1 << 24) - 2;
+// Wide sweeps: variables of a colour class are dealt to kWideStreams
+// (workgroup, wave) streams; each stream keeps its replicas' energy changes
+// for the sweep in its own slots.
+constexpr int kWideWaves = 4;
+constexpr int kWideSlices = 1024;
+constexpr int kWideStreams = kWideSlices * kWideWaves;
 constexpr int kAddrBits = 17;
 constexpr uint32_t kAddrMask = (1u << kAddrBits) - 1;
 constexpr int kMaxClasses = 8;
@@ -51,6 +62,12 @@ struct KsatDev {
     const int32_t *var_cl;       // [sum deg]
     int32_t n, m, n_colors, n_chunks, dmax;
     uint32_t rec_bytes;          // size of rec in bytes (the bound of the sweep's buffer loads)
+    // wide layout (wide != 0; rec and the chunk arrays are then empty)
+    const uint4 *wrec;           // [sum deg] per incidence in var_ptr order: the clause's other three
+                                 // literals as row | negated << 31 (row N: absent, never true), own sign
+    const int32_t *worder;       // [N] sweep order (colour-major)
+    const int32_t *wclass_ptr;   // [n_colors + 1] range of each colour class in worder
+    int32_t wide;
 };
 
 // Buffer resource word 3 (format and type bits) for raw byte-addressed
@@ -70,6 +87,15 @@ struct KsatRepDev {
     int32_t *tally;    // [4] scratch for per-set reductions
     unsigned long long *accepted;  // [1] moves accepted by the sweep kernels (reset by the host)
     int32_t n_rep, n_groups;
+    // wide layout: variable-major spin bytes [2 (N + 1)][wgp] (rows 0..N the
+    // spins, row N all zero; rows N+1..2N+1 their complements, wnx = wx +
+    // (N + 1) wgp), the best states [N][wgp]; wgp = 2^wlg >= 64 bytes per row
+    // (the groups, padded); per-stream energy changes [kWideStreams][wgp][4];
+    // per-group masks of the replicas whose best improved in the last sweep
+    uint8_t *wx, *wnx, *wbx;
+    int32_t *wdsum;
+    uint8_t *wflag;
+    int32_t wgp, wlg;
 };
 
 struct SweepCall {
@@ -182,6 +208,9 @@ hipError_t launch_set_status(const SetStatusSrc *src, SetStatus *out, int n_sets
 // ---- launchers (nmc_ksat.hip) ----
 size_t ksat_sweep_lds_bytes(int n, int n_classes, int stride);
 hipError_t ksat_launch_init(const KsatDev &I, const KsatRepDev &R, uint32_t key0, uint32_t key1, hipStream_t s);
+hipError_t ksat_launch_wide_pack(const KsatDev &I, const KsatRepDev &R, bool unpack, hipStream_t s);
+hipError_t ksat_launch_wide_sweeps(const KsatDev &I, const KsatRepDev &R, const SweepCall &C,
+                                   const int32_t *class_size /* host, per colour */, hipStream_t s);
 hipError_t ksat_launch_recount(const KsatDev &I, const uint8_t *xs, int n_groups, int n_rep, int32_t *energy_out,
                                hipStream_t s);
 hipError_t ksat_launch_reset_tallies(const KsatRepDev &R, int n, hipStream_t s);

@@ -1,0 +1,320 @@
+// k-SAT sweeps for instances whose spin tables do not fit in LDS (the wide
+// layout), for gfx950.
+//
+// The same single-variable Metropolis sweep as the LDS kernels (section
+// "Nonequilibrium inhomogeneous sampling over subgraphs"; CNF energy as in
+// subsection "4-SAT Problems Near Computational Phase Transitions"): the
+// colour-major order, the closed form of dE from the OR of each clause's
+// other literals, one generator call per (variable, group of 4 replicas) and
+// the same threshold tables, so the results are bit-identical.  What changes
+// is the mapping: the spins of a launch live in device memory, variable-major
+// ([row][group], one byte per group of 4 replicas; rows 0..N hold x, rows
+// N+1..2N+1 hold NOT x, row N is the absent literal), and a wave takes one
+// variable for 64 groups, one lane per group.  A variable's clause records
+// are then the same for the whole wave (scalar loads), and every literal read
+// is one coalesced 64-byte row segment serving 256 replicas, a buffer load
+// whose row offset is a scalar shift.  No two variables of a colour class share a
+// clause, so one launch per class updates the class's variables
+// concurrently; the launches of a sweep run in order on the stream.
+#include <climits>
+
+#include "nmc_internal.h"
+#include "nmc_philox.h"
+
+namespace nmc {
+
+namespace {
+
+__device__ __forceinline__ uint32_t wide_spread4(uint32_t f) { return (f * 0x00204081u) & 0x01010101u; }
+
+// Byte of group g in table row `row` (rows of 2^lg bytes).
+__device__ __forceinline__ uint32_t row_byte(__amdgpu_buffer_rsrc_t tab, uint32_t row, int lg, int g) {
+    return __builtin_amdgcn_raw_buffer_load_b8(tab, g, (int)(row << lg), 0);
+}
+
+__device__ __forceinline__ uint32_t group_mask(const KsatRepDev &R, int g) {
+    const int nact = g < R.n_groups ? min(kGroup, R.n_rep - g * kGroup) : 0;
+    return (1u << nact) - 1u;
+}
+
+// [G][N] group-major spins (and best states) <-> [N + 1][wgp] variable-major,
+// through 64 x 64 tiles in LDS so both sides move in rows.  Packing also
+// writes the complement rows and the all-zero row N (the absent literal).
+__global__ void __launch_bounds__(256) ksat_wide_pack_kernel(KsatDev I, KsatRepDev R, int unpack) {
+    __shared__ uint8_t tx[64][65], tb[64][65];
+    const int n = I.n, gp = R.wgp;
+    const int v0 = blockIdx.x * 64, g0 = blockIdx.y * 64;
+    if (!unpack) {
+        for (int i = threadIdx.x; i < 64 * 64; i += blockDim.x) {
+            const int gl = i >> 6, vl = i & 63;
+            const int g = g0 + gl, v = v0 + vl;
+            const bool in = g < R.n_groups && v < n;
+            tx[gl][vl] = in ? R.xs[(size_t)g * n + v] : 0;
+            tb[gl][vl] = in ? R.best_xs[(size_t)g * n + v] : 0;
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < 64 * 64; i += blockDim.x) {
+            const int vl = i >> 6, gl = i & 63;
+            const int v = v0 + vl, g = g0 + gl;
+            if (v > n)
+                continue;
+            const size_t o = (size_t)v * gp + g;
+            if (v == n) {
+                R.wx[o] = 0;
+                R.wnx[o] = 0;
+                continue;
+            }
+            const uint32_t am = group_mask(R, g);
+            const uint32_t x = tx[gl][vl] & am;
+            R.wx[o] = (uint8_t)x;
+            R.wnx[o] = (uint8_t)(~x & am);
+            R.wbx[o] = tb[gl][vl];
+        }
+    } else {
+        for (int i = threadIdx.x; i < 64 * 64; i += blockDim.x) {
+            const int vl = i >> 6, gl = i & 63;
+            const int v = v0 + vl, g = g0 + gl;
+            const bool in = v < n;
+            tx[gl][vl] = in ? R.wx[(size_t)v * gp + g] : 0;
+            tb[gl][vl] = in ? R.wbx[(size_t)v * gp + g] : 0;
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < 64 * 64; i += blockDim.x) {
+            const int gl = i >> 6, vl = i & 63;
+            const int g = g0 + gl, v = v0 + vl;
+            if (g < R.n_groups && v < n) {
+                R.xs[(size_t)g * n + v] = tx[gl][vl];
+                R.best_xs[(size_t)g * n + v] = tb[gl][vl];
+            }
+        }
+    }
+}
+
+// Before the first sweep: a replica already at or below the target counts as
+// hit at the call's first sweep index (as in the LDS kernels).
+__global__ void ksat_wide_start_kernel(KsatRepDev R, SweepCall C) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < R.n_rep && C.check_start && R.first_hit[r] < 0 && R.energy[r] <= C.target)
+        R.first_hit[r] = (int)C.t0;
+}
+
+// One colour class c of sweep s.  Workgroup (slice, group block): waves take
+// the class's variables i = stream, stream + kWideStreams, ...; lane = group.
+__global__ void __launch_bounds__(64 * kWideWaves) ksat_wide_class_kernel(KsatDev I, KsatRepDev R, SweepCall C,
+                                                                          int c, int s) {
+    extern __shared__ __align__(16) uint32_t tl[];  // the sweep's threshold rows
+    const int tab_words = C.n_classes * C.stride;
+    const uint32_t *tg = C.tab + (size_t)s * C.sweep_words;
+    for (int i = threadIdx.x; i < tab_words; i += blockDim.x)
+        tl[i] = tg[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int g = blockIdx.y * 64 + lane;
+    const int gp = R.wgp;
+    const uint32_t amask = group_mask(R, g);
+    const int stream = blockIdx.x * kWideWaves + wave;
+    const int lg = R.wlg;
+    // the spin and complement rows, [2 (N + 1)][wgp] bytes from wx
+    const __amdgpu_buffer_rsrc_t tab = __builtin_amdgcn_make_buffer_rsrc(
+        R.wx, 0, (int)(((size_t)2 * (I.n + 1)) << lg), kBufferWord3);
+    // the records, read-only here: through the constant address space they
+    // are scalar loads
+    typedef const uint32_t __attribute__((address_space(4))) c_u32;
+    const c_u32 *rw = (const c_u32 *)I.wrec;
+    auto rec = [&](int q) { return make_uint4(rw[4 * q], rw[4 * q + 1], rw[4 * q + 2], rw[4 * q + 3]); };
+    const int c0 = I.wclass_ptr[c], c1 = I.wclass_ptr[c + 1];
+    const uint32_t t = C.t0 + (uint32_t)s;
+    int dsum[kGroup] = {0, 0, 0, 0};
+    uint32_t n_acc = 0;
+    for (int i = c0 + stream; i < c1; i += kWideStreams) {
+        const int v = __builtin_amdgcn_readfirstlane(I.worder[i]);
+        const int q0 = __builtin_amdgcn_readfirstlane(I.var_ptr[v]);
+        const int q1 = __builtin_amdgcn_readfirstlane(I.var_ptr[v + 1]);
+        const size_t own = (size_t)v * gp + g;
+        const uint32_t xi = row_byte(tab, (uint32_t)v, lg, g);
+        // acc collects sum over the variable's clauses of spread(sat) xor
+        // (own literal negated ? all ones : 0), sat = OR of the clause's
+        // other literals (4 replica bits); nneg counts the negated ones.
+        // Records come four at a time (one scalar load), their twelve rows
+        // as buffer loads issued together.
+        uint32_t acc = 0, nneg = 0;
+        int q = q0;
+        for (; q + 4 <= q1; q += 4) {
+            uint4 r[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                r[k] = rec(q + k);
+            uint32_t b[12];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                b[3 * k] = row_byte(tab, r[k].x, lg, g);
+                b[3 * k + 1] = row_byte(tab, r[k].y, lg, g);
+                b[3 * k + 2] = row_byte(tab, r[k].z, lg, g);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                nneg += r[k].w;
+                acc = (wide_spread4(b[3 * k] | b[3 * k + 1] | b[3 * k + 2]) ^ (0u - r[k].w)) + acc;
+            }
+        }
+        for (; q < q1; ++q) {
+            const uint4 r = rec(q);
+            const uint32_t sat = row_byte(tab, r.x, lg, g) | row_byte(tab, r.y, lg, g) | row_byte(tab, r.z, lg, g);
+            nneg += r.w;
+            acc = (wide_spread4(sat) ^ (0u - r.w)) + acc;
+        }
+        // byte j of 0x80808080 + part = 128 + (clauses of this variable whose
+        // other literals are all false, counted +1 where the variable's own
+        // literal is positive and -1 where negated), for replica j
+        const uint32_t nslot = (uint32_t)(q1 - q0);
+        acc = 0x80808080u + ((nslot - 2u * nneg) * 0x01010101u - nneg - acc);
+        const int cl = C.var_cls ? (int)C.var_cls[v] : 0;
+        const uint32_t *T = tl + cl * C.stride;
+        int de[kGroup];
+        uint32_t thr[kGroup];
+        uint32_t flip = 0, need = 0;
+#pragma unroll
+        for (int j = 0; j < kGroup; ++j) {
+            const int S = (int)((acc >> (8 * j)) & 0xFFu) - 128;
+            de[j] = ((xi >> j) & 1u) ? S : -S;
+            thr[j] = T[max(de[j], 0)];
+            const uint32_t on = (amask >> j) & 1u;
+            flip |= (on & (uint32_t)(de[j] <= 0)) << j;
+            need |= (on & (uint32_t)(de[j] > 0) & (uint32_t)(thr[j] != 0)) << j;
+        }
+        if (need) {
+            const uint4 u = philox4x32_10((uint32_t)v, t, (uint32_t)g, kStreamKsatSweep, C.key0, C.key1);
+            flip |= ((need & 1u) && u.x < thr[0]) ? 1u : 0u;
+            flip |= ((need & 2u) && u.y < thr[1]) ? 2u : 0u;
+            flip |= ((need & 4u) && u.z < thr[2]) ? 4u : 0u;
+            flip |= ((need & 8u) && u.w < thr[3]) ? 8u : 0u;
+        }
+        if (flip) {
+            n_acc += __builtin_popcount(flip);
+            const uint32_t nx = xi ^ flip;
+            R.wx[own] = (uint8_t)nx;
+            R.wnx[own] = (uint8_t)(~nx & amask);
+#pragma unroll
+            for (int j = 0; j < kGroup; ++j)
+                dsum[j] += ((flip >> j) & 1u) ? de[j] : 0;
+        }
+    }
+    // this stream's slots for group g: only this lane of this wave touches
+    // them during a sweep, and the class launches run in order
+    if (dsum[0] | dsum[1] | dsum[2] | dsum[3]) {
+        int4 *slot = reinterpret_cast<int4 *>(R.wdsum) + (size_t)stream * gp + g;
+        int4 d = *slot;
+        d.x += dsum[0];
+        d.y += dsum[1];
+        d.z += dsum[2];
+        d.w += dsum[3];
+        *slot = d;
+    }
+    unsigned long long acc_w = n_acc;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        acc_w += __shfl_xor(acc_w, off, 64);
+    if (lane == 0 && acc_w)
+        atomicAdd(R.accepted, acc_w);
+}
+
+// Sweep end for group g (one workgroup): the streams' energy changes (then
+// cleared), energies, best energies, first hits, and the mask of replicas
+// whose best improved (their best state is copied by the snapshot kernel).
+__global__ void __launch_bounds__(256) ksat_wide_sweep_end_kernel(KsatRepDev R, SweepCall C, uint32_t t) {
+    __shared__ int red[kGroup][256 / 64];
+    const int g = blockIdx.x, gp = R.wgp;
+    int d[kGroup] = {0, 0, 0, 0};
+    for (int st = threadIdx.x; st < kWideStreams; st += blockDim.x) {
+        int4 *slot = reinterpret_cast<int4 *>(R.wdsum) + (size_t)st * gp + g;
+        const int4 v = *slot;
+        if (v.x | v.y | v.z | v.w) {
+            d[0] += v.x;
+            d[1] += v.y;
+            d[2] += v.z;
+            d[3] += v.w;
+            *slot = make_int4(0, 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kGroup; ++j) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+            d[j] += __shfl_xor(d[j], off, 64);
+        if ((threadIdx.x & 63) == 0)
+            red[j][threadIdx.x >> 6] = d[j];
+    }
+    __syncthreads();
+    if (threadIdx.x < kGroup) {
+        const int j = threadIdx.x, r = g * kGroup + j;
+        bool imp = false;
+        if (r < R.n_rep) {
+            int sum = 0;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w)
+                sum += red[j][w];
+            const int E = R.energy[r] + sum;
+            R.energy[r] = E;
+            if (E < R.best[r]) {
+                R.best[r] = E;
+                imp = true;
+            }
+            if (R.first_hit[r] < 0 && E <= C.target)
+                R.first_hit[r] = (int)(t + 1);
+        }
+        // lanes 0..3 of wave 0: gather the 4 bits
+        const uint64_t m = __ballot(imp);
+        if (j == 0)
+            R.wflag[g] = (uint8_t)(m & 0xFu);
+    }
+}
+
+// Best-state snapshot after a sweep: replicas flagged by the sweep end copy
+// their current spins.
+__global__ void ksat_wide_snapshot_kernel(KsatDev I, KsatRepDev R) {
+    const size_t total = (size_t)I.n * R.wgp;
+    for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < total; o += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t m = R.wflag[o % R.wgp];
+        if (m)
+            R.wbx[o] = (uint8_t)((R.wbx[o] & ~m) | (R.wx[o] & m));
+    }
+}
+
+}  // namespace
+
+hipError_t ksat_launch_wide_pack(const KsatDev &I, const KsatRepDev &R, bool unpack, hipStream_t s) {
+    // packing also covers row n (the absent literal)
+    const int nv = I.n + (unpack ? 0 : 1);
+    hipLaunchKernelGGL(ksat_wide_pack_kernel, dim3((nv + 63) / 64, R.wgp / 64), dim3(256), 0, s, I, R,
+                       unpack ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t ksat_launch_wide_sweeps(const KsatDev &I, const KsatRepDev &R, const SweepCall &C,
+                                   const int32_t *class_size, hipStream_t s) {
+    const size_t lds = (size_t)C.n_classes * C.stride * sizeof(uint32_t);
+    static const hipError_t attr = hipFuncSetAttribute((const void *)ksat_wide_class_kernel,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
+    if (attr != hipSuccess)
+        return attr;
+    hipLaunchKernelGGL(ksat_wide_start_kernel, dim3((R.n_rep + 255) / 256), dim3(256), 0, s, R, C);
+    const size_t cells = (size_t)I.n * R.wgp;
+    const int snap_blocks = (int)std::min<size_t>((cells + 255) / 256, 4096);
+    for (int sw = 0; sw < C.n_sweeps; ++sw) {
+        for (int c = 0; c < I.n_colors; ++c) {
+            // no more workgroups than the class has variables for
+            const int cs = class_size[c];
+            const int slices = std::max(1, std::min(kWideSlices, (cs + kWideWaves - 1) / kWideWaves));
+            hipLaunchKernelGGL(ksat_wide_class_kernel, dim3(slices, R.wgp / 64), dim3(64 * kWideWaves), lds, s, I, R,
+                               C, c, sw);
+        }
+        hipLaunchKernelGGL(ksat_wide_sweep_end_kernel, dim3(R.n_groups), dim3(256), 0, s, R, C, C.t0 + (uint32_t)sw);
+        hipLaunchKernelGGL(ksat_wide_snapshot_kernel, dim3(snap_blocks), dim3(256), 0, s, I, R);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace nmc

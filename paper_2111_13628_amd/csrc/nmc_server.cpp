@@ -91,6 +91,14 @@ void loader_main(nmc_server *S) {
                                &q->inst);
         else
             rc = nmc_qap_load(q->r.n, q->flow.data(), q->dist.data(), &q->inst);
+        if (rc == NMC_OK) {
+            // served requests run in batched launches, which take the LDS layout
+            nmc_instance_info info{};
+            rc = nmc_instance_get_info(q->inst, &info);
+            if (rc == NMC_OK && info.wide)
+                rc = nmc::set_last_error(NMC_ERR_UNSUPPORTED,
+                                         "served k-SAT requests need the LDS layout (at most 65534 variables)");
+        }
         if (rc == NMC_OK)
             rc = nmc_footprint(q->inst, q->r.n_replicas, &q->inst_bytes, &q->rep_bytes);
         // the instance holds its own layout from here on

@@ -34,7 +34,7 @@ class NmcError(RuntimeError):
 class InstanceInfo(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("n_items", ctypes.c_int32), ("n_clauses", ctypes.c_int32),
                 ("max_clause_len", ctypes.c_int32), ("max_degree", ctypes.c_int32),
-                ("n_colors", ctypes.c_int32), ("delta_bound", ctypes.c_int64)]
+                ("n_colors", ctypes.c_int32), ("delta_bound", ctypes.c_int64), ("wide", ctypes.c_int32)]
 
 
 class LbpConfig(ctypes.Structure):

@@ -55,7 +55,7 @@ def test_ksat_unsupported():
         _load(6, np.array([0, 5]), np.array([1, 2, 3, 4, 5]))
     assert e.value.code == -6
     with pytest.raises(nmc.NmcError) as e:
-        _load(70000, np.array([0, 1]), np.array([1]))
+        _load((1 << 24) - 1, np.array([0, 1]), np.array([1]))
     assert e.value.code == -6
     # a variable in 128 clauses exceeds the per-variable accumulator range
     cp = np.arange(0, 129 * 2, 2)
@@ -154,3 +154,23 @@ def test_server_validation_without_gpu():
         assert L.nmc_server_poll(h, 12345, ctypes.byref(res)) == -1
     finally:
         L.nmc_server_free(h)
+
+
+def test_ksat_wide_layout_chosen_by_size(monkeypatch):
+    """Above 65534 variables the instance takes the wide layout (spins in
+    device memory); NMC_KSAT_WIDE=1 takes it for any size.  Its replica
+    footprint holds the variable-major spin, complement and best tables."""
+    cp, lits = instances.gen_ksat(70000, "4.2", 3, 5)
+    big = nmc.Instance.ksat(70000, cp, lits)
+    assert big.info.wide == 1 and big.info.n_items == 70000
+    cp, lits = instances.gen_ksat(300, "9.6", 4, 5)
+    small = nmc.Instance.ksat(300, cp, lits)
+    assert small.info.wide == 0
+    monkeypatch.setenv("NMC_KSAT_WIDE", "1")
+    forced = nmc.Instance.ksat(300, cp, lits)
+    assert forced.info.wide == 1
+    # same colouring and sweep order either way
+    assert (forced.order()[0] == small.order()[0]).all() and (forced.order()[1] == small.order()[1]).all()
+    _, rep_small = small.footprint(100)
+    _, rep_wide = forced.footprint(100)
+    assert rep_wide >= rep_small + 3 * 301 * 64
