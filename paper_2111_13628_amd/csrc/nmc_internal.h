@@ -35,6 +35,7 @@ constexpr int kMaxWideVars = (1 << 24) - 2;
 constexpr int kWideWaves = 4;
 constexpr int kWideSlices = 1024;
 constexpr int kWideStreams = kWideSlices * kWideWaves;
+constexpr int kWideGroup = 8;  // clause slots whose records and rows a wide sweep reads at once
 constexpr int kAddrBits = 17;
 constexpr uint32_t kAddrMask = (1u << kAddrBits) - 1;
 constexpr int kMaxClasses = 8;
@@ -90,7 +91,7 @@ struct KsatRepDev {
     // wide layout: variable-major spin bytes [2 (N + 1)][wgp] (rows 0..N the
     // spins, row N all zero; rows N+1..2N+1 their complements, wnx = wx +
     // (N + 1) wgp), the best states [N][wgp]; wgp = 2^wlg >= 64 bytes per row
-    // (the groups, padded); per-stream energy changes [kWideStreams][wgp][4];
+    // (the groups, padded); per-stream energy changes [wgp][kWideStreams][4];
     // per-group masks of the replicas whose best improved in the last sweep
     uint8_t *wx, *wnx, *wbx;
     int32_t *wdsum;

@@ -32,6 +32,33 @@ __device__ __forceinline__ uint32_t row_byte(__amdgpu_buffer_rsrc_t tab, uint32_
     return __builtin_amdgcn_raw_buffer_load_b8(tab, g, (int)(row << lg), 0);
 }
 
+typedef const uint32_t __attribute__((address_space(4))) c_u32;
+
+// Clause slots q .. q + K - 1 of a variable (those at or past q1 are
+// skipped: their record reads stay on the last slot and add nothing).  All
+// K records are read first (scalar loads), then all 3K rows, then summed.
+template <int K>
+__device__ __forceinline__ void wide_slots(const c_u32 *rw, __amdgpu_buffer_rsrc_t tab, int lg, int g, int q, int q1,
+                                           uint32_t &acc, uint32_t &nneg) {
+    uint4 r[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int qk = min(q + k, q1 - 1);
+        r[k] = make_uint4(rw[4 * qk], rw[4 * qk + 1], rw[4 * qk + 2], rw[4 * qk + 3]);
+    }
+    uint32_t b[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        b[k] = row_byte(tab, r[k].x, lg, g) | row_byte(tab, r[k].y, lg, g) | row_byte(tab, r[k].z, lg, g);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (q + k < q1) {
+            nneg += r[k].w;
+            acc = (wide_spread4(b[k]) ^ (0u - r[k].w)) + acc;
+        }
+    }
+}
+
 __device__ __forceinline__ uint32_t group_mask(const KsatRepDev &R, int g) {
     const int nact = g < R.n_groups ? min(kGroup, R.n_rep - g * kGroup) : 0;
     return (1u << nact) - 1u;
@@ -120,9 +147,7 @@ __global__ void __launch_bounds__(64 * kWideWaves) ksat_wide_class_kernel(KsatDe
         R.wx, 0, (int)(((size_t)2 * (I.n + 1)) << lg), kBufferWord3);
     // the records, read-only here: through the constant address space they
     // are scalar loads
-    typedef const uint32_t __attribute__((address_space(4))) c_u32;
-    const c_u32 *rw = (const c_u32 *)I.wrec;
-    auto rec = [&](int q) { return make_uint4(rw[4 * q], rw[4 * q + 1], rw[4 * q + 2], rw[4 * q + 3]); };
+    const c_u32 *rec = (const c_u32 *)I.wrec;
     const int c0 = I.wclass_ptr[c], c1 = I.wclass_ptr[c + 1];
     const uint32_t t = C.t0 + (uint32_t)s;
     int dsum[kGroup] = {0, 0, 0, 0};
@@ -136,34 +161,14 @@ __global__ void __launch_bounds__(64 * kWideWaves) ksat_wide_class_kernel(KsatDe
         // acc collects sum over the variable's clauses of spread(sat) xor
         // (own literal negated ? all ones : 0), sat = OR of the clause's
         // other literals (4 replica bits); nneg counts the negated ones.
-        // Records come four at a time (one scalar load), their twelve rows
-        // as buffer loads issued together.
+        // Records come 16 at a time (scalar loads), their 48 rows as buffer
+        // loads issued together; the tail takes groups of 4.
         uint32_t acc = 0, nneg = 0;
         int q = q0;
-        for (; q + 4 <= q1; q += 4) {
-            uint4 r[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                r[k] = rec(q + k);
-            uint32_t b[12];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                b[3 * k] = row_byte(tab, r[k].x, lg, g);
-                b[3 * k + 1] = row_byte(tab, r[k].y, lg, g);
-                b[3 * k + 2] = row_byte(tab, r[k].z, lg, g);
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                nneg += r[k].w;
-                acc = (wide_spread4(b[3 * k] | b[3 * k + 1] | b[3 * k + 2]) ^ (0u - r[k].w)) + acc;
-            }
-        }
-        for (; q < q1; ++q) {
-            const uint4 r = rec(q);
-            const uint32_t sat = row_byte(tab, r.x, lg, g) | row_byte(tab, r.y, lg, g) | row_byte(tab, r.z, lg, g);
-            nneg += r.w;
-            acc = (wide_spread4(sat) ^ (0u - r.w)) + acc;
-        }
+        for (; q + kWideGroup <= q1; q += kWideGroup)
+            wide_slots<kWideGroup>(rec, tab, lg, g, q, q1, acc, nneg);
+        for (; q < q1; q += 4)
+            wide_slots<4>(rec, tab, lg, g, q, q1, acc, nneg);
         // byte j of 0x80808080 + part = 128 + (clauses of this variable whose
         // other literals are all false, counted +1 where the variable's own
         // literal is positive and -1 where negated), for replica j
@@ -203,7 +208,7 @@ __global__ void __launch_bounds__(64 * kWideWaves) ksat_wide_class_kernel(KsatDe
     // this stream's slots for group g: only this lane of this wave touches
     // them during a sweep, and the class launches run in order
     if (dsum[0] | dsum[1] | dsum[2] | dsum[3]) {
-        int4 *slot = reinterpret_cast<int4 *>(R.wdsum) + (size_t)stream * gp + g;
+        int4 *slot = reinterpret_cast<int4 *>(R.wdsum) + (size_t)g * kWideStreams + stream;
         int4 d = *slot;
         d.x += dsum[0];
         d.y += dsum[1];
@@ -224,10 +229,10 @@ __global__ void __launch_bounds__(64 * kWideWaves) ksat_wide_class_kernel(KsatDe
 // whose best improved (their best state is copied by the snapshot kernel).
 __global__ void __launch_bounds__(256) ksat_wide_sweep_end_kernel(KsatRepDev R, SweepCall C, uint32_t t) {
     __shared__ int red[kGroup][256 / 64];
-    const int g = blockIdx.x, gp = R.wgp;
+    const int g = blockIdx.x;
     int d[kGroup] = {0, 0, 0, 0};
     for (int st = threadIdx.x; st < kWideStreams; st += blockDim.x) {
-        int4 *slot = reinterpret_cast<int4 *>(R.wdsum) + (size_t)st * gp + g;
+        int4 *slot = reinterpret_cast<int4 *>(R.wdsum) + (size_t)g * kWideStreams + st;
         const int4 v = *slot;
         if (v.x | v.y | v.z | v.w) {
             d[0] += v.x;
