@@ -27,19 +27,27 @@ namespace {
 
 __device__ __forceinline__ uint32_t wide_spread4(uint32_t f) { return (f * 0x00204081u) & 0x01010101u; }
 
-// Byte of group g in table row `row` (rows of 2^lg bytes).
-__device__ __forceinline__ uint32_t row_byte(__amdgpu_buffer_rsrc_t tab, uint32_t row, int lg, int g) {
-    return __builtin_amdgcn_raw_buffer_load_b8(tab, g, (int)(row << lg), 0);
+// The GPL bytes of groups g .. g + GPL - 1 (GPL = 1 or 4; g a multiple of
+// GPL) in table row `row`, byte k = group g + k.
+template <int GPL>
+__device__ __forceinline__ uint32_t row_groups(__amdgpu_buffer_rsrc_t tab, uint32_t row, int lg, int g) {
+    if constexpr (GPL == 1)
+        return __builtin_amdgcn_raw_buffer_load_b8(tab, g, (int)(row << lg), 0);
+    else
+        return __builtin_amdgcn_raw_buffer_load_b32(tab, g, (int)(row << lg), 0);
 }
 
 typedef const uint32_t __attribute__((address_space(4))) c_u32;
 
 // Clause slots q .. q + K - 1 of a variable (those at or past q1 are
-// skipped: their record reads stay on the last slot and add nothing).  All
-// K records are read first (scalar loads), then all 3K rows, then summed.
-template <int K>
+// skipped: their record reads stay on the last slot and add nothing) for the
+// lane's GPL groups.  All K records are read first (scalar loads), then all
+// 3K rows, then summed: acc[k] collects, for group g + k, spread(sat) xor
+// (own literal negated ? all ones : 0), sat = OR of the clause's other
+// literals (4 replica bits).
+template <int K, int GPL>
 __device__ __forceinline__ void wide_slots(const c_u32 *rw, __amdgpu_buffer_rsrc_t tab, int lg, int g, int q, int q1,
-                                           uint32_t &acc, uint32_t &nneg) {
+                                           uint32_t (&acc)[GPL], uint32_t &nneg) {
     uint4 r[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -49,12 +57,15 @@ __device__ __forceinline__ void wide_slots(const c_u32 *rw, __amdgpu_buffer_rsrc
     uint32_t b[K];
 #pragma unroll
     for (int k = 0; k < K; ++k)
-        b[k] = row_byte(tab, r[k].x, lg, g) | row_byte(tab, r[k].y, lg, g) | row_byte(tab, r[k].z, lg, g);
+        b[k] = row_groups<GPL>(tab, r[k].x, lg, g) | row_groups<GPL>(tab, r[k].y, lg, g) |
+               row_groups<GPL>(tab, r[k].z, lg, g);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         if (q + k < q1) {
             nneg += r[k].w;
-            acc = (wide_spread4(b[k]) ^ (0u - r[k].w)) + acc;
+#pragma unroll
+            for (int j = 0; j < GPL; ++j)
+                acc[j] = (wide_spread4((b[k] >> (8 * j)) & 0xFFu) ^ (0u - r[k].w)) + acc[j];
         }
     }
 }
@@ -126,7 +137,10 @@ __global__ void ksat_wide_start_kernel(KsatRepDev R, SweepCall C) {
 }
 
 // One colour class c of sweep s.  Workgroup (slice, group block): waves take
-// the class's variables i = stream, stream + kWideStreams, ...; lane = group.
+// the class's variables i = stream, stream + kWideStreams, ...; a lane takes
+// GPL adjacent groups (GPL = 4: one 4-byte row read serves 16 replicas, a
+// quarter of the load instructions of one group per lane).
+template <int GPL>
 __global__ void __launch_bounds__(64 * kWideWaves) ksat_wide_class_kernel(KsatDev I, KsatRepDev R, SweepCall C,
                                                                           int c, int s) {
     extern __shared__ __align__(16) uint32_t tl[];  // the sweep's threshold rows
@@ -137,9 +151,12 @@ __global__ void __launch_bounds__(64 * kWideWaves) ksat_wide_class_kernel(KsatDe
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int g = blockIdx.y * 64 + lane;
+    const int g = (blockIdx.y * 64 + lane) * GPL;  // the lane's first group
     const int gp = R.wgp;
-    const uint32_t amask = group_mask(R, g);
+    uint32_t amask[GPL];
+#pragma unroll
+    for (int k = 0; k < GPL; ++k)
+        amask[k] = group_mask(R, g + k);
     const int stream = blockIdx.x * kWideWaves + wave;
     const int lg = R.wlg;
     // the spin and complement rows, [2 (N + 1)][wgp] bytes from wx
@@ -150,71 +167,91 @@ __global__ void __launch_bounds__(64 * kWideWaves) ksat_wide_class_kernel(KsatDe
     const c_u32 *rec = (const c_u32 *)I.wrec;
     const int c0 = I.wclass_ptr[c], c1 = I.wclass_ptr[c + 1];
     const uint32_t t = C.t0 + (uint32_t)s;
-    int dsum[kGroup] = {0, 0, 0, 0};
+    int dsum[GPL][kGroup];
+#pragma unroll
+    for (int k = 0; k < GPL; ++k)
+        dsum[k][0] = dsum[k][1] = dsum[k][2] = dsum[k][3] = 0;
     uint32_t n_acc = 0;
     for (int i = c0 + stream; i < c1; i += kWideStreams) {
         const int v = __builtin_amdgcn_readfirstlane(I.worder[i]);
         const int q0 = __builtin_amdgcn_readfirstlane(I.var_ptr[v]);
         const int q1 = __builtin_amdgcn_readfirstlane(I.var_ptr[v + 1]);
-        const size_t own = (size_t)v * gp + g;
-        const uint32_t xi = row_byte(tab, (uint32_t)v, lg, g);
-        // acc collects sum over the variable's clauses of spread(sat) xor
-        // (own literal negated ? all ones : 0), sat = OR of the clause's
-        // other literals (4 replica bits); nneg counts the negated ones.
-        // Records come 16 at a time (scalar loads), their 48 rows as buffer
-        // loads issued together; the tail takes groups of 4.
-        uint32_t acc = 0, nneg = 0;
+        const uint32_t xw = row_groups<GPL>(tab, (uint32_t)v, lg, g);
+        // records 8 at a time (their 24 rows read together), then groups of 4
+        uint32_t acc[GPL], nneg = 0;
+#pragma unroll
+        for (int k = 0; k < GPL; ++k)
+            acc[k] = 0;
         int q = q0;
         for (; q + kWideGroup <= q1; q += kWideGroup)
-            wide_slots<kWideGroup>(rec, tab, lg, g, q, q1, acc, nneg);
+            wide_slots<kWideGroup, GPL>(rec, tab, lg, g, q, q1, acc, nneg);
         for (; q < q1; q += 4)
-            wide_slots<4>(rec, tab, lg, g, q, q1, acc, nneg);
-        // byte j of 0x80808080 + part = 128 + (clauses of this variable whose
-        // other literals are all false, counted +1 where the variable's own
-        // literal is positive and -1 where negated), for replica j
+            wide_slots<4, GPL>(rec, tab, lg, g, q, q1, acc, nneg);
         const uint32_t nslot = (uint32_t)(q1 - q0);
-        acc = 0x80808080u + ((nslot - 2u * nneg) * 0x01010101u - nneg - acc);
         const int cl = C.var_cls ? (int)C.var_cls[v] : 0;
         const uint32_t *T = tl + cl * C.stride;
-        int de[kGroup];
-        uint32_t thr[kGroup];
-        uint32_t flip = 0, need = 0;
+        uint32_t nxw = xw;
 #pragma unroll
-        for (int j = 0; j < kGroup; ++j) {
-            const int S = (int)((acc >> (8 * j)) & 0xFFu) - 128;
-            de[j] = ((xi >> j) & 1u) ? S : -S;
-            thr[j] = T[max(de[j], 0)];
-            const uint32_t on = (amask >> j) & 1u;
-            flip |= (on & (uint32_t)(de[j] <= 0)) << j;
-            need |= (on & (uint32_t)(de[j] > 0) & (uint32_t)(thr[j] != 0)) << j;
-        }
-        if (need) {
-            const uint4 u = philox4x32_10((uint32_t)v, t, (uint32_t)g, kStreamKsatSweep, C.key0, C.key1);
-            flip |= ((need & 1u) && u.x < thr[0]) ? 1u : 0u;
-            flip |= ((need & 2u) && u.y < thr[1]) ? 2u : 0u;
-            flip |= ((need & 4u) && u.z < thr[2]) ? 4u : 0u;
-            flip |= ((need & 8u) && u.w < thr[3]) ? 8u : 0u;
-        }
-        if (flip) {
+        for (int k = 0; k < GPL; ++k) {
+            // byte j of 0x80808080 + part = 128 + (clauses of this variable
+            // whose other literals are all false, +1 where the variable's
+            // own literal is positive, -1 where negated), for replica j of
+            // group g + k
+            const uint32_t a = 0x80808080u + ((nslot - 2u * nneg) * 0x01010101u - nneg - acc[k]);
+            const uint32_t xi = (xw >> (8 * k)) & 0xFFu;
+            int de[kGroup];
+            uint32_t thr[kGroup];
+            uint32_t flip = 0, need = 0;
+#pragma unroll
+            for (int j = 0; j < kGroup; ++j) {
+                const int S = (int)((a >> (8 * j)) & 0xFFu) - 128;
+                de[j] = ((xi >> j) & 1u) ? S : -S;
+                thr[j] = T[max(de[j], 0)];
+                const uint32_t on = (amask[k] >> j) & 1u;
+                flip |= (on & (uint32_t)(de[j] <= 0)) << j;
+                need |= (on & (uint32_t)(de[j] > 0) & (uint32_t)(thr[j] != 0)) << j;
+            }
+            if (need) {
+                const uint4 u = philox4x32_10((uint32_t)v, t, (uint32_t)(g + k), kStreamKsatSweep, C.key0, C.key1);
+                flip |= ((need & 1u) && u.x < thr[0]) ? 1u : 0u;
+                flip |= ((need & 2u) && u.y < thr[1]) ? 2u : 0u;
+                flip |= ((need & 4u) && u.z < thr[2]) ? 4u : 0u;
+                flip |= ((need & 8u) && u.w < thr[3]) ? 8u : 0u;
+            }
             n_acc += __builtin_popcount(flip);
-            const uint32_t nx = xi ^ flip;
-            R.wx[own] = (uint8_t)nx;
-            R.wnx[own] = (uint8_t)(~nx & amask);
+            nxw ^= flip << (8 * k);
 #pragma unroll
             for (int j = 0; j < kGroup; ++j)
-                dsum[j] += ((flip >> j) & 1u) ? de[j] : 0;
+                dsum[k][j] += ((flip >> j) & 1u) ? de[j] : 0;
+        }
+        if (nxw != xw) {
+            uint32_t nnx = 0;
+#pragma unroll
+            for (int k = 0; k < GPL; ++k)
+                nnx |= (~(nxw >> (8 * k)) & amask[k]) << (8 * k);
+            const size_t own = (size_t)v * gp + g;
+            if constexpr (GPL == 1) {
+                R.wx[own] = (uint8_t)nxw;
+                R.wnx[own] = (uint8_t)nnx;
+            } else {
+                *reinterpret_cast<uint32_t *>(R.wx + own) = nxw;
+                *reinterpret_cast<uint32_t *>(R.wnx + own) = nnx;
+            }
         }
     }
-    // this stream's slots for group g: only this lane of this wave touches
-    // them during a sweep, and the class launches run in order
-    if (dsum[0] | dsum[1] | dsum[2] | dsum[3]) {
-        int4 *slot = reinterpret_cast<int4 *>(R.wdsum) + (size_t)g * kWideStreams + stream;
-        int4 d = *slot;
-        d.x += dsum[0];
-        d.y += dsum[1];
-        d.z += dsum[2];
-        d.w += dsum[3];
-        *slot = d;
+    // this stream's slots for the lane's groups: only this lane of this wave
+    // touches them during a sweep, and the class launches run in order
+#pragma unroll
+    for (int k = 0; k < GPL; ++k) {
+        if (dsum[k][0] | dsum[k][1] | dsum[k][2] | dsum[k][3]) {
+            int4 *slot = reinterpret_cast<int4 *>(R.wdsum) + (size_t)(g + k) * kWideStreams + stream;
+            int4 d = *slot;
+            d.x += dsum[k][0];
+            d.y += dsum[k][1];
+            d.z += dsum[k][2];
+            d.w += dsum[k][3];
+            *slot = d;
+        }
     }
     unsigned long long acc_w = n_acc;
 #pragma unroll
@@ -298,10 +335,14 @@ hipError_t ksat_launch_wide_pack(const KsatDev &I, const KsatRepDev &R, bool unp
 hipError_t ksat_launch_wide_sweeps(const KsatDev &I, const KsatRepDev &R, const SweepCall &C,
                                    const int32_t *class_size, hipStream_t s) {
     const size_t lds = (size_t)C.n_classes * C.stride * sizeof(uint32_t);
-    static const hipError_t attr = hipFuncSetAttribute((const void *)ksat_wide_class_kernel,
-                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
-    if (attr != hipSuccess)
-        return attr;
+    // four groups per lane once a row holds at least 256 of them
+    const bool quad = R.wgp >= 256;
+    static const hipError_t attr1 = hipFuncSetAttribute((const void *)ksat_wide_class_kernel<1>,
+                                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
+    static const hipError_t attr4 = hipFuncSetAttribute((const void *)ksat_wide_class_kernel<4>,
+                                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
+    if (attr1 != hipSuccess || attr4 != hipSuccess)
+        return attr1 != hipSuccess ? attr1 : attr4;
     hipLaunchKernelGGL(ksat_wide_start_kernel, dim3((R.n_rep + 255) / 256), dim3(256), 0, s, R, C);
     const size_t cells = (size_t)I.n * R.wgp;
     const int snap_blocks = (int)std::min<size_t>((cells + 255) / 256, 4096);
@@ -310,8 +351,12 @@ hipError_t ksat_launch_wide_sweeps(const KsatDev &I, const KsatRepDev &R, const 
             // no more workgroups than the class has variables for
             const int cs = class_size[c];
             const int slices = std::max(1, std::min(kWideSlices, (cs + kWideWaves - 1) / kWideWaves));
-            hipLaunchKernelGGL(ksat_wide_class_kernel, dim3(slices, R.wgp / 64), dim3(64 * kWideWaves), lds, s, I, R,
-                               C, c, sw);
+            if (quad)
+                hipLaunchKernelGGL(ksat_wide_class_kernel<4>, dim3(slices, R.wgp / 256), dim3(64 * kWideWaves), lds, s,
+                                   I, R, C, c, sw);
+            else
+                hipLaunchKernelGGL(ksat_wide_class_kernel<1>, dim3(slices, R.wgp / 64), dim3(64 * kWideWaves), lds, s,
+                                   I, R, C, c, sw);
         }
         hipLaunchKernelGGL(ksat_wide_sweep_end_kernel, dim3(R.n_groups), dim3(256), 0, s, R, C, C.t0 + (uint32_t)sw);
         hipLaunchKernelGGL(ksat_wide_snapshot_kernel, dim3(snap_blocks), dim3(256), 0, s, I, R);

@@ -19,11 +19,13 @@ def reanneal_profile(S, beta_hot=0.5, beta_end=4.0):
 
 
 @pytest.mark.parametrize("n,alpha,k,R,cap", [(300, "9.6", 4, 38, 0), (700, "4.15", 3, 21, 64), (200, "9.6", 4, 4, 0),
-                                             (500, "9.6", 4, 300, 0), (120, "9.6", 4, 9, 1)])
+                                             (500, "9.6", 4, 300, 0), (120, "9.6", 4, 9, 1), (260, "9.6", 4, 1101, 0),
+                                             (150, "4.15", 3, 2048, 0)])
 def test_wide_nmc_rounds_match_oracle(n, alpha, k, R, cap, monkeypatch):
     """anneal -> backbone -> reanneal, twice, on the wide layout: ragged
-    replica counts, more than 64 groups (two lane blocks), 3-SAT with
-    variables of no clause, and one variable per class (cap 1)."""
+    replica counts, more than 64 groups (two lane blocks), rows of 512 groups
+    with four groups per lane (R = 1101: a partial last group; R = 2048),
+    3-SAT with variables of no clause, and one variable per class (cap 1)."""
     monkeypatch.setenv("NMC_KSAT_WIDE", "1")
     say(f"case: wide nmc rounds n={n} k={k} R={R} cap={cap}")
     cp, lits = instances.gen_ksat(n, alpha, k, SEED + n)
