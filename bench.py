@@ -316,11 +316,13 @@ def bench_qap(nmc, torch, seed, sweeps_only=0, sweeps_offset=0, curve=0):
 
 LBP_CFG = dict(beta=1.0, lambda0=4.0, lambda_ratio=0.8, lambda_min=1e-3, max_iter=100, tol=1e-8, p_min=-2.0)
 LBP_THRESHOLDS = ((0.8, 0.6), (0.9, 0.8), (0.95, 0.9))  # (seed, cutoff) per round, raised round by round
-# bytes one message iteration must move per literal slot (edge): u gathered
-# by the variable side, u read and written by the clause side, the field
-# total T gathered by the clause side (8 B each), the variable's edge index
-# and the clause's literal address (4 B each); per variable: clause range,
-# reference spin, T written
+# bytes one message iteration must move per literal slot (edge): each
+# message read by the variable side, read and written by the clause side, the
+# field total T gathered by the clause side (8 B each), the edge's
+# variable-major position and the clause's literal address (4 B each); per
+# variable: clause range, reference spin, T written.  (The library's second,
+# variable-major copy of the messages adds an 8-byte scattered write per edge
+# that this count leaves out.)
 LBP_BYTES_PER_EDGE, LBP_BYTES_PER_VAR = 40, 13
 
 
@@ -759,6 +761,44 @@ def bench_c1(nmc, torch, seed, repeats=1):
                             "read back, per solve with fresh replicas"}
 
 
+def bench_wide(nmc, torch, seed):
+    """The NMC path on a random 4-SAT instance too large for the LDS layout
+    (the wide layout: spins variable-major in device memory, one launch per
+    colour class): N = 1,000,000, alpha 9.9 (M = 9.9 M clauses), no class cap,
+    1024 replicas, anneal 200 + 2 x (backbone + reanneal 100) sweeps.  Whole
+    path by the host clock, sweep launches by HIP events, the energy recount
+    (tables packed, then counted) by the host clock."""
+    n, S_A, RND, S_RW = 1_000_000, 200, 2, 100
+    cp, lits = instances.gen_ksat(n, ALPHA, K, seed)
+    inst = nmc.Instance.ksat(n, cp, lits, 0).bind()
+    warm = nmc.Replicas(inst, R, seed + 1)
+    warm.anneal(instances.linear_schedule(BETA0, BETA1, S_A)[None, :2])
+    warm.recount()
+    del warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rep = nmc.Replicas(inst, R, seed)
+    rep.set_profiling(True)
+    rep.anneal(instances.linear_schedule(BETA0, BETA1, S_A)[None, :])
+    for _ in range(RND):
+        rep.estimate_backbone_device(9, 10, True)
+        rep.reanneal(reanneal_profile(S_RW), "backbone")
+    be = rep.best_energy()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = rep.kernel_time()
+    t0 = time.perf_counter()
+    e = rep.recount()
+    rc_s = time.perf_counter() - t0
+    att = float(R) * n * (S_A + RND * S_RW)
+    return {"n_vars": n, "n_clauses": inst.info.n_clauses, "replicas": R, "colors": inst.info.n_colors,
+            "wide": inst.info.wide, "sweeps": S_A + RND * S_RW, "wall_s": wall, "attempts_per_s": att / wall,
+            "kernel_ms": kt["ms"], "kernel_attempts_per_s": kt["attempts"] / (kt["ms"] / 1e3),
+            "ms_per_sweep": kt["ms"] / (S_A + RND * S_RW), "recount_s": rc_s,
+            "recount_equals_tracked_energy": bool((e == be["energy"]).all()),
+            "best_energy": int(be["best"]), "accepted": rep.accept_count()}
+
+
 def measured_peaks(nmc, torch):
     """Rates that simple, fully occupied kernels reach on this GPU, beside the
     published peaks: LDS byte reads (lanes on distinct banks, and random
@@ -839,12 +879,14 @@ def main():
     ap.add_argument("--replicas", type=int, default=R, help="replicas of the N=50000 workload (default 1024)")
     ap.add_argument("--rpw", type=int, default=0, help="k-SAT replicas per sweep workgroup: 4 or 8 (0: 4)")
     ap.add_argument("--class-cap", type=int, default=CLASS_CAP)
-    ap.add_argument("--workload", choices=["nmc", "batch", "qap", "serve", "apt", "lbp", "alg1", "c1"], default="nmc",
+    ap.add_argument("--workload", choices=["nmc", "batch", "qap", "serve", "apt", "lbp", "alg1", "c1", "wide"],
+                    default="nmc",
                     help="nmc: the N=50000 NMC path (default); batch: 256 mixed instances, batched vs "
                          "per-instance; qap: the n=100 QAP path; serve: Poisson stream into the server; "
                          "apt: adaptive parallel tempering on the N=50000 instance; lbp: NMC with LBP "
                          "surrogate backbones on the N=50000 instance; alg1: tempering -> seeds -> per-seed "
-                         "LBP backbones -> batched inhomogeneous MC and unlearning")
+                         "LBP backbones -> batched inhomogeneous MC and unlearning; wide: the NMC path on a "
+                         "N=1,000,000 instance (the wide layout)")
     ap.add_argument("--pt-rounds", type=int, default=APT_ROUNDS)
     ap.add_argument("--pt-sweeps-per-round", type=int, default=1)
     ap.add_argument("--serve-seconds", type=float, default=SERVE_SECONDS)
@@ -909,6 +951,15 @@ def main():
                           "dtype": "int32", "data": "synthetic",
                           "config": {"workload": "plain SA, random 4-SAT N=200 alpha=9.6, 64 replicas, 1000 sweeps"},
                           "c1": res}), flush=True)
+        return
+    if args.workload == "wide":
+        res = bench_wide(nmc, torch, seed)
+        print(json.dumps({"metric": "spin-flip attempts/s (NMC path, wide layout)", "value": res["attempts_per_s"],
+                          "unit": "attempts/s", "n_gpus": 1, "higher_is_better": True, "dtype": "int32",
+                          "data": "synthetic",
+                          "config": {"workload": f"NMC random 4-SAT N=1000000 alpha=9.9, {R} replicas, anneal 200 + "
+                                                 "2x(backbone + reanneal 100)"},
+                          "wide": res}), flush=True)
         return
     if args.workload == "alg1":
         res = bench_alg1(nmc, torch, seed)

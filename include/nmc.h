@@ -371,8 +371,8 @@ typedef struct nmc_lbp_result {
  * Outputs (each optional, host): class_out [N] bytes, mag_out [N] doubles,
  * corr_out [M] doubles (signed clause moments), label_out [N] int32 (the
  * smallest variable index of the cluster, -1 outside the backbone).
- * Arithmetic is IEEE double.  The workspace (16 bytes per literal slot of
- * the padded 4-per-clause layout, 4 per literal, 8 per clause and about 35
+ * Arithmetic is IEEE double.  The workspace (20 bytes per literal slot of
+ * the padded 4-per-clause layout, 16 per literal, 8 per clause and about 35
  * per variable) is allocated on the first call and kept with the replica
  * set.
  * Errors: INVALID (arguments), STATE (unbound), UNSUPPORTED (QAP), DEVICE. */

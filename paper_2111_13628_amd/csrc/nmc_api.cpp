@@ -882,7 +882,10 @@ int ensure_tab(nmc_replicas *P, size_t bytes) {
 int reset_after_state(nmc_replicas *P, hipStream_t s) {
     nmc_instance *I = P->inst;
     if (I->kind == NMC_KIND_KSAT) {
-        HIP_OR_FAIL(ksat_launch_recount(I->ksat_dev(), P->k.xs, P->G, P->R, P->k.energy, s));
+        if (I->wide)
+            HIP_OR_FAIL(ksat_launch_wide_recount(I->ksat_dev(), P->k, P->k.energy, s));
+        else
+            HIP_OR_FAIL(ksat_launch_recount(I->ksat_dev(), P->k.xs, P->G, P->R, P->k.energy, s));
         HIP_OR_FAIL(ksat_launch_reset_tallies(P->k, I->n, s));
     } else {
         HIP_OR_FAIL(qap_launch_cost(I->qap_dev(), P->q.perm, P->R, P->q.cost, s));
@@ -1323,7 +1326,10 @@ int nmc_recount(nmc_replicas *P, int64_t *energy_out, void *stream) {
         nmc_instance *I = P->inst;
         hipStream_t s = as_stream(stream);
         if (I->kind == NMC_KIND_KSAT) {
-            HIP_OR_FAIL(ksat_launch_recount(I->ksat_dev(), P->k.xs, P->G, P->R, P->scratch_energy, s));
+            if (I->wide)
+                HIP_OR_FAIL(ksat_launch_wide_recount(I->ksat_dev(), P->k, P->scratch_energy, s));
+            else
+                HIP_OR_FAIL(ksat_launch_recount(I->ksat_dev(), P->k.xs, P->G, P->R, P->scratch_energy, s));
             std::vector<int32_t> e(P->R);
             HIP_OR_FAIL(hipMemcpyAsync(e.data(), P->scratch_energy, (size_t)P->R * 4, hipMemcpyDeviceToHost, s));
             HIP_OR_FAIL(hipStreamSynchronize(s));
@@ -1779,10 +1785,13 @@ static int lbp_workspace(LbpRun &r, hipStream_t s) {
     nmc_instance *I = P->inst;
     const int32_t n = I->n, m = I->m;
     Arena ar;
-    const size_t o_u = ar.take((size_t)m * 4 * 8), o_keep = ar.take((size_t)m * 4 * 8), o_T = ar.take((size_t)n * 8);
+    // messages clause-major then variable-major in one block (one copy or
+    // clear covers both), and the block's saved copy
+    const size_t ub = ((size_t)m * 4 + (size_t)I->n_lits) * 8;
+    const size_t o_u = ar.take(ub), o_keep = ar.take(ub), o_T = ar.take((size_t)n * 8);
     const size_t o_mag = ar.take((size_t)n * 8), o_corr = ar.take((size_t)m * 8);
-    const size_t o_ve = ar.take((size_t)I->n_lits * 4), o_s = ar.take((size_t)n);
-    const size_t o_scal = ar.take(64 * 8), o_res = ar.take(24), o_ctl = ar.take(8);
+    const size_t o_ep = ar.take((size_t)m * 4 * 4), o_s = ar.take((size_t)n);
+    const size_t o_scal = ar.take(2 * kLbpDeltaSlots * 8), o_res = ar.take(24), o_ctl = ar.take(8);
     const size_t o_lab = ar.take((size_t)n * 4), o_olab = ar.take((size_t)n * 4), o_size = ar.take((size_t)n * 4);
     const size_t o_seed = ar.take((size_t)n), o_flag = ar.take(4), o_cnt = ar.take(5 * 4);
     const size_t o_job = ar.take(sizeof(LbpJob));
@@ -1800,7 +1809,8 @@ static int lbp_workspace(LbpRun &r, hipStream_t s) {
     W.T = reinterpret_cast<double *>(b + o_T);
     W.mag = reinterpret_cast<double *>(b + o_mag);
     W.corr = reinterpret_cast<double *>(b + o_corr);
-    W.vedge = reinterpret_cast<int32_t *>(b + o_ve);
+    W.uv = W.u + (size_t)m * 4;
+    W.epos = reinterpret_cast<int32_t *>(b + o_ep);
     W.s = reinterpret_cast<int8_t *>(b + o_s);
     W.scal = reinterpret_cast<unsigned long long *>(b + o_scal);
     W.res = reinterpret_cast<double *>(b + o_res);
@@ -1811,7 +1821,7 @@ static int lbp_workspace(LbpRun &r, hipStream_t s) {
     W.seeded = b + o_seed;
     W.flag = reinterpret_cast<int32_t *>(b + o_flag);
     W.counts = reinterpret_cast<int32_t *>(b + o_cnt);
-    r.ubytes = (size_t)m * 4 * 8;
+    r.ubytes = ub;
     (void)o_job;
     return NMC_OK;
 }
@@ -1820,10 +1830,11 @@ static size_t lbp_job_offset(const nmc_instance *I) {
     // the last region of the workspace laid out by lbp_workspace
     Arena ar;
     const int32_t n = I->n, m = I->m;
-    ar.take((size_t)m * 4 * 8), ar.take((size_t)m * 4 * 8), ar.take((size_t)n * 8);
+    const size_t ub = ((size_t)m * 4 + (size_t)I->n_lits) * 8;
+    ar.take(ub), ar.take(ub), ar.take((size_t)n * 8);
     ar.take((size_t)n * 8), ar.take((size_t)m * 8);
-    ar.take((size_t)I->n_lits * 4), ar.take((size_t)n);
-    ar.take(64 * 8), ar.take(24), ar.take(8);
+    ar.take((size_t)m * 4 * 4), ar.take((size_t)n);
+    ar.take(2 * kLbpDeltaSlots * 8), ar.take(24), ar.take(8);
     ar.take((size_t)n * 4), ar.take((size_t)n * 4), ar.take((size_t)n * 4);
     ar.take((size_t)n), ar.take(4), ar.take(5 * 4);
     return ar.take(sizeof(LbpJob));
@@ -1864,7 +1875,7 @@ static int lbp_run_all(std::vector<LbpRun> &runs, const LbpJob *jobs_dev, const 
             if (!r.done) {
                 if (r.ubytes)
                     HIP_OR_FAIL(hipMemcpyAsync(r.keep, r.W.u, r.ubytes, hipMemcpyDeviceToDevice, s));
-                HIP_OR_FAIL(hipMemsetAsync(r.W.scal, 0, 64 * 8, s));
+                HIP_OR_FAIL(hipMemsetAsync(r.W.scal, 0, 2 * kLbpDeltaSlots * 8, s));
                 HIP_OR_FAIL(hipMemsetAsync(r.W.ctl, 0, 8, s));
             }
         int32_t queued = 0;
@@ -1872,7 +1883,7 @@ static int lbp_run_all(std::vector<LbpRun> &runs, const LbpJob *jobs_dev, const 
             const int32_t cnt = std::min(queued ? 16 : 8, c.max_iter - queued);
             if (pe[0])
                 HIP_OR_FAIL(hipEventRecord(pe[0], s));
-            HIP_OR_FAIL(lbp_launch_iterations(jobs_dev, D, lambda, w, c.tol, c.max_iter, cnt, s));
+            HIP_OR_FAIL(lbp_launch_iterations(jobs_dev, D, lambda, w, c.tol, c.max_iter, queued, cnt, s));
             if (pe[1])
                 HIP_OR_FAIL(hipEventRecord(pe[1], s));
             queued += cnt;

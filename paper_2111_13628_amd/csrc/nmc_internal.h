@@ -210,6 +210,9 @@ hipError_t launch_set_status(const SetStatusSrc *src, SetStatus *out, int n_sets
 size_t ksat_sweep_lds_bytes(int n, int n_classes, int stride);
 hipError_t ksat_launch_init(const KsatDev &I, const KsatRepDev &R, uint32_t key0, uint32_t key1, hipStream_t s);
 hipError_t ksat_launch_wide_pack(const KsatDev &I, const KsatRepDev &R, bool unpack, hipStream_t s);
+// energies of every replica of a wide instance from its group-major state
+// (packs the variable-major tables first)
+hipError_t ksat_launch_wide_recount(const KsatDev &I, const KsatRepDev &R, int32_t *energy_out, hipStream_t s);
 hipError_t ksat_launch_wide_sweeps(const KsatDev &I, const KsatRepDev &R, const SweepCall &C,
                                    const int32_t *class_size /* host, per colour */, hipStream_t s);
 hipError_t ksat_launch_recount(const KsatDev &I, const uint8_t *xs, int n_groups, int n_rep, int32_t *energy_out,
@@ -266,12 +269,13 @@ hipError_t pt_launch_moments(const void *energy, int energy_is_64, int n, unsign
 // ---- surrogate-Hamiltonian LBP and backbone growth (nmc_lbp.hip) ----
 // Edges e = 4a + j (literal j of clause a); padded edges are never read.
 struct LbpWork {
-    double *u;                   // [4M] clause-to-variable messages
+    double *u;                   // [4M] clause-to-variable messages, clause-major (edge e = 4a + j)
+    double *uv;                  // [sum deg] sigma_ia u_{a->i}, variable-major (incidence order); u + 4M
     double *T;                   // [N] field totals H_i + sum_a sigma_ia u_{a->i}
     double *mag, *corr;          // [N] <r_i>, [M] clause moments
-    int32_t *vedge;              // [sum deg] edge of each variable incidence, bit 31 = negated literal
+    int32_t *epos;               // [4M] variable-major position of each edge (padding slots unused)
     int8_t *s;                   // [N] reference spins (+1 / -1)
-    unsigned long long *scal;    // [64] bits of the largest |du| of an iteration, by slot
+    unsigned long long *scal;    // [2][64] bits of the largest |du| of an iteration, by parity and slot
     double *res;                 // [0] overlap p, [1] self-overlap q1, [2] last iteration's max |du|
     int32_t *ctl;                // [0] 0 running / 1 converged / 2 out of iterations, [1] iterations
     int32_t *label, *out_label, *size;  // [N]
@@ -290,12 +294,21 @@ struct LbpJob {
 struct LbpDims {
     int n_jobs, max_n, max_m;
 };
+constexpr int kLbpDeltaSlots = 64;
+// convergence decision on iteration iters - 1 of a step, whose largest |du|
+// is in slot set `judge` (-1: none); `clear` (-1: none) is the set the next
+// clause pass fills
+struct LbpJudge {
+    int judge, clear, iters, max_iter;
+    double tol;
+};
 hipError_t lbp_launch_setup(const LbpJob *jobs, const LbpDims &D, double lambda0, hipStream_t s);
 hipError_t lbp_launch_var(const LbpJob *jobs, const LbpDims &D, double lambda, int final_pass, hipStream_t s);
 hipError_t lbp_launch_clause(const LbpJob *jobs, const LbpDims &D, double w, int final_pass, hipStream_t s);
-// `count` gated iterations (variable side, clause side, control) of one step
+// gated iterations first .. first + count - 1 of one step (variable side with
+// the previous iteration's control, clause side; control after the last)
 hipError_t lbp_launch_iterations(const LbpJob *jobs, const LbpDims &D, double lambda, double w, double tol,
-                                 int max_iter, int count, hipStream_t s);
+                                 int max_iter, int first, int count, hipStream_t s);
 hipError_t lbp_launch_overlap(const LbpJob *jobs, const LbpDims &D, hipStream_t s);
 hipError_t lbp_launch_label_init(const LbpJob *jobs, const LbpDims &D, hipStream_t s);
 hipError_t lbp_launch_hook_jump(const LbpJob *jobs, const LbpDims &D, double cut, hipStream_t s);

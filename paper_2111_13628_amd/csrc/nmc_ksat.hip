@@ -125,46 +125,6 @@ __global__ void ksat_recount_kernel(KsatDev I, const uint8_t *xs, int n_rep, int
         energy_out[g * kGroup + tid] = red[tid];
 }
 
-// The same count with the group's spins read from device memory (wide
-// instances, whose spin tables do not fit in LDS): a literal at address a is
-// x[a] (a < N), NOT x[a - N] (a < 2N), or the absent literal (never true).
-__global__ void ksat_recount_global_kernel(KsatDev I, const uint8_t *xs, int n_rep, int32_t *energy_out) {
-    __shared__ int red[kGroup];
-    const int n = I.n, g = blockIdx.x, tid = threadIdx.x;
-    const int nact = min(kGroup, n_rep - g * kGroup);
-    const uint32_t amask = (1u << nact) - 1u;
-    const uint8_t *x = xs + (size_t)g * n;
-    auto lit = [&](uint32_t a) -> uint32_t {
-        return a < (uint32_t)n ? (uint32_t)x[a] & amask
-                               : a < 2u * (uint32_t)n ? ~(uint32_t)x[a - n] & amask : (a == 2u * (uint32_t)n ? 0u : amask);
-    };
-    if (tid < kGroup)
-        red[tid] = 0;
-    __syncthreads();
-    int c0 = 0, c1 = 0, c2 = 0, c3 = 0;
-    for (int a = tid; a < I.m; a += blockDim.x) {
-        const uint4 ad = reinterpret_cast<const uint4 *>(I.clause_addr)[a];
-        const uint32_t f = ~(lit(ad.x) | lit(ad.y) | lit(ad.z) | lit(ad.w)) & amask;
-        c0 += f & 1;
-        c1 += (f >> 1) & 1;
-        c2 += (f >> 2) & 1;
-        c3 += (f >> 3) & 1;
-    }
-    c0 = wave_sum(c0);
-    c1 = wave_sum(c1);
-    c2 = wave_sum(c2);
-    c3 = wave_sum(c3);
-    if ((tid & 63) == 0) {
-        atomicAdd(&red[0], c0);
-        atomicAdd(&red[1], c1);
-        atomicAdd(&red[2], c2);
-        atomicAdd(&red[3], c3);
-    }
-    __syncthreads();
-    if (tid < nact)
-        energy_out[g * kGroup + tid] = red[tid];
-}
-
 __global__ void ksat_reset_tallies_kernel(KsatRepDev R) {
     const int total = R.n_groups * kGroup;
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < total; r += gridDim.x * blockDim.x) {
@@ -723,10 +683,8 @@ hipError_t ksat_launch_init(const KsatDev &I, const KsatRepDev &R, uint32_t key0
 
 hipError_t ksat_launch_recount(const KsatDev &I, const uint8_t *xs, int n_groups, int n_rep, int32_t *energy_out,
                                hipStream_t s) {
-    if (I.wide) {
-        hipLaunchKernelGGL(ksat_recount_global_kernel, dim3(n_groups), dim3(1024), 0, s, I, xs, n_rep, energy_out);
-        return hipGetLastError();
-    }
+    if (I.wide)
+        return hipErrorNotSupported;  // wide instances count from their packed tables
     const size_t lds = align_up(2 * (size_t)I.n + 2, 16) + 16 * sizeof(int);
     // once per process (thread-safe initialization)
     static const hipError_t attr = hipFuncSetAttribute((const void *)ksat_recount_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,

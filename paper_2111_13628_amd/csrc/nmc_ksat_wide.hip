@@ -312,13 +312,86 @@ __global__ void __launch_bounds__(256) ksat_wide_sweep_end_kernel(KsatRepDev R, 
 }
 
 // Best-state snapshot after a sweep: replicas flagged by the sweep end copy
-// their current spins.
+// their current spins, 16 groups per lane (rows are a multiple of 64 groups,
+// so a 16-byte piece never crosses a row).
 __global__ void ksat_wide_snapshot_kernel(KsatDev I, KsatRepDev R) {
-    const size_t total = (size_t)I.n * R.wgp;
+    const size_t total = ((size_t)I.n * R.wgp) >> 4;
+    const uint32_t row16 = (uint32_t)R.wgp >> 4;
+    const uint4 *flag = reinterpret_cast<const uint4 *>(R.wflag);
+    const uint4 *x = reinterpret_cast<const uint4 *>(R.wx);
+    uint4 *best = reinterpret_cast<uint4 *>(R.wbx);
     for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < total; o += (size_t)gridDim.x * blockDim.x) {
-        const uint32_t m = R.wflag[o % R.wgp];
-        if (m)
-            R.wbx[o] = (uint8_t)((R.wbx[o] & ~m) | (R.wx[o] & m));
+        const uint4 m = flag[o & (row16 - 1)];
+        if (m.x | m.y | m.z | m.w) {
+            const uint4 b = best[o], c = x[o];
+            best[o] = make_uint4((b.x & ~m.x) | (c.x & m.x), (b.y & ~m.y) | (c.y & m.y), (b.z & ~m.z) | (c.z & m.z),
+                                 (b.w & ~m.w) | (c.w & m.w));
+        }
+    }
+}
+
+__global__ void ksat_wide_zero_kernel(int32_t *p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        p[i] = 0;
+}
+
+// Energies of every replica from the variable-major tables (freshly packed
+// from the group-major state): a wave takes a run of kRecountRun clauses for
+// 64 groups, one lane per group, reads each clause's four addresses once
+// (scalar loads) and the four literal rows (one coalesced row segment each),
+// and counts the clauses with no true literal per replica.  The workgroup's
+// four waves meet in LDS; workgroups add their counts with integer atomics,
+// so the sums are exact in any order.
+constexpr int kRecountRun = 1024;
+
+__global__ void __launch_bounds__(256) ksat_wide_recount_kernel(KsatDev I, KsatRepDev R, int32_t *energy_out) {
+    __shared__ uint32_t red[256 / 64][64][kGroup];
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int g = blockIdx.y * 64 + lane;
+    const int n = I.n, lg = R.wlg;
+    const __amdgpu_buffer_rsrc_t tab = __builtin_amdgcn_make_buffer_rsrc(
+        R.wx, 0, (int)(((size_t)2 * (n + 1)) << lg), kBufferWord3);
+    const c_u32 *ca = (const c_u32 *)I.clause_addr;
+    const int a0 = (blockIdx.x * 4 + wave) * kRecountRun, a1 = min(a0 + kRecountRun, I.m);
+    // table row of a clause address: x_v at v, NOT x_v at N + 1 + v, the
+    // absent literal at the all-zero row N
+    auto row = [&](uint32_t ad) -> uint32_t {
+        return ad < (uint32_t)n ? ad : ad < 2u * (uint32_t)n ? ad + 1u : (uint32_t)n;
+    };
+    uint32_t c[kGroup] = {0, 0, 0, 0};
+    for (int a = a0; a < a1; a += 4) {
+        uint32_t b[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int ak = min(a + k, a1 - 1);
+            const uint32_t r0 = row(ca[4 * ak]), r1 = row(ca[4 * ak + 1]), r2 = row(ca[4 * ak + 2]),
+                           r3 = row(ca[4 * ak + 3]);
+            b[k] = __builtin_amdgcn_raw_buffer_load_b8(tab, g, (int)(r0 << lg), 0) |
+                   __builtin_amdgcn_raw_buffer_load_b8(tab, g, (int)(r1 << lg), 0) |
+                   __builtin_amdgcn_raw_buffer_load_b8(tab, g, (int)(r2 << lg), 0) |
+                   __builtin_amdgcn_raw_buffer_load_b8(tab, g, (int)(r3 << lg), 0);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (a + k < a1) {
+#pragma unroll
+                for (int j = 0; j < kGroup; ++j)
+                    c[j] += ((b[k] >> j) & 1u) ^ 1u;
+            }
+    }
+#pragma unroll
+    for (int j = 0; j < kGroup; ++j)
+        red[wave][lane][j] = c[j];
+    __syncthreads();
+    if (wave == 0 && g < R.n_groups) {
+#pragma unroll
+        for (int j = 0; j < kGroup; ++j) {
+            const uint32_t sum = red[0][lane][j] + red[1][lane][j] + red[2][lane][j] + red[3][lane][j];
+            const int r = g * kGroup + j;
+            if (r < R.n_rep && sum)
+                atomicAdd(&energy_out[r], (int32_t)sum);
+        }
     }
 }
 
@@ -329,6 +402,18 @@ hipError_t ksat_launch_wide_pack(const KsatDev &I, const KsatRepDev &R, bool unp
     const int nv = I.n + (unpack ? 0 : 1);
     hipLaunchKernelGGL(ksat_wide_pack_kernel, dim3((nv + 63) / 64, R.wgp / 64), dim3(256), 0, s, I, R,
                        unpack ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t ksat_launch_wide_recount(const KsatDev &I, const KsatRepDev &R, int32_t *energy_out, hipStream_t s) {
+    const hipError_t e = ksat_launch_wide_pack(I, R, false, s);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(ksat_wide_zero_kernel, dim3((R.n_rep + 255) / 256), dim3(256), 0, s, energy_out, R.n_rep);
+    const int runs = (I.m + kRecountRun - 1) / kRecountRun;
+    if (runs > 0)
+        hipLaunchKernelGGL(ksat_wide_recount_kernel, dim3((runs + 3) / 4, R.wgp / 64), dim3(256), 0, s, I, R,
+                           energy_out);
     return hipGetLastError();
 }
 
@@ -344,8 +429,8 @@ hipError_t ksat_launch_wide_sweeps(const KsatDev &I, const KsatRepDev &R, const 
     if (attr1 != hipSuccess || attr4 != hipSuccess)
         return attr1 != hipSuccess ? attr1 : attr4;
     hipLaunchKernelGGL(ksat_wide_start_kernel, dim3((R.n_rep + 255) / 256), dim3(256), 0, s, R, C);
-    const size_t cells = (size_t)I.n * R.wgp;
-    const int snap_blocks = (int)std::min<size_t>((cells + 255) / 256, 4096);
+    const size_t pieces = ((size_t)I.n * R.wgp) >> 4;
+    const int snap_blocks = (int)std::min<size_t>((pieces + 255) / 256, 4096);
     for (int sw = 0; sw < C.n_sweeps; ++sw) {
         for (int c = 0; c < I.n_colors; ++c) {
             // no more workgroups than the class has variables for

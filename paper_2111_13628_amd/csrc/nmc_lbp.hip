@@ -15,14 +15,22 @@
 //   u_{a->i} = -1/2 ln[1 - (1 - e^{-2 beta}) prod_{j in da \ i} (1 - tanh h_{j->a}) / 2]
 // The variable kernel (sixteen lanes per variable) writes only T, N doubles
 // that stay in L2; the clause kernel (one thread per clause) forms each h
-// from T and its own u, so no per-edge h is stored and the only scattered
-// access is the variable kernel's gather of u.  The largest |du| of an
+// from T and its own u, so no per-edge h is stored.  Each message is kept
+// twice: clause-major (u, the clause kernel's own contiguous reads and
+// writes) and variable-major with its sign applied (sigma u at the edge's
+// position in the variable's incidence list, written by the clause kernel as
+// one scattered 8-byte store), so the variable kernel's sums read contiguous
+// memory instead of gathering one cache line per 8-byte message.  The largest |du| of an
 // iteration is a workgroup max, then an atomic max over the bit patterns of
-// non-negative doubles into one of 64 slots.  Iterations are queued in
-// batches without host round trips: a one-thread kernel after each iteration
-// decides convergence on the device, and the kernels of the rest of the batch
-// then return at once, so the result is that of checking after every
-// iteration.  Everything is fp64 (8 bytes per edge and message).
+// non-negative doubles into one of 64 slots (two sets of slots, by iteration
+// parity).  Iterations are queued in batches without host round trips: the
+// variable pass of iteration k + 1 first decides on the device whether
+// iteration k converged (every wave reads the 64 slots; one thread records
+// the decision and clears the other set for the coming clause pass), and
+// once stopped the kernels of the rest of the batch return at once, so the
+// result is that of checking after every iteration.  A one-thread kernel
+// decides on the batch's last iteration.  Everything is fp64 (8 bytes per
+// edge and message).
 //
 // Components: labels start as the variable's index; every rigid clause
 // (|moment| >= cutoff) lowers its variables' labels to their minimum
@@ -56,9 +64,9 @@ __device__ __forceinline__ void atomic_max_nonneg(unsigned long long *p, double 
     atomicMax(p, (unsigned long long)__double_as_longlong(v));
 }
 
-// reference spins of one replica, edge list of every variable (edge | sign
-// bit 31, in the order of the variable's clause list) and T = H at lambda0
-// (with u = 0 the first clause pass then sees h = sigma H)
+// reference spins of one replica, the variable-major position of every edge
+// (the variable's incidences in the order of its clause list) and T = H at
+// lambda0 (with u = 0 the first clause pass then sees h = sigma H)
 __global__ void lbp_setup_kernel(const LbpJob *jobs, double lambda0) {
     const LbpJob &J = jobs[blockIdx.y];
     const KsatDev &I = J.I;
@@ -80,8 +88,7 @@ __global__ void lbp_setup_kernel(const LbpJob *jobs, double lambda0) {
             if (ad == (uint32_t)i || ad == (uint32_t)(i + I.n))
                 break;
         }
-        const uint32_t ad = I.clause_addr[(size_t)a * 4 + j];
-        W.vedge[q] = (4 * a + j) | (ad >= (uint32_t)I.n ? (int)0x80000000 : 0);
+        W.epos[4 * a + j] = q;
     }
 }
 
@@ -91,13 +98,43 @@ __global__ void lbp_setup_kernel(const LbpJob *jobs, double lambda0) {
 // butterfly shuffles inside the lane group.  With gated != 0 the launch does
 // nothing once the iteration control has stopped.
 constexpr int kVarLanes = 16;
+constexpr int kDeltaSlots = kLbpDeltaSlots;
+constexpr int kVarRound = 4;
 
-__global__ void lbp_var_kernel(const LbpJob *jobs, double lambda, int final_pass, int gated) {
+__device__ __forceinline__ int lbp_decide(double d, const LbpJudge &G) {
+    return d < G.tol ? 1 : (G.iters >= G.max_iter ? 2 : 0);
+}
+
+__global__ void lbp_var_kernel(const LbpJob *jobs, double lambda, int final_pass, int gated, LbpJudge G) {
     const LbpJob &J = jobs[blockIdx.y];
     const KsatDev &I = J.I;
     const LbpWork &W = J.W;
     if (gated && W.ctl[0])
         return;
+    if (G.judge >= 0) {
+        // the previous iteration's largest |du|: its slots, dealt to the lanes
+        unsigned long long mx = 0;
+        for (int k = threadIdx.x & 63; k < kDeltaSlots; k += 64) {
+            const unsigned long long v = W.scal[G.judge * kDeltaSlots + k];
+            mx = v > mx ? v : mx;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned long long o = __shfl_xor(mx, off, 64);
+            mx = o > mx ? o : mx;
+        }
+        const double d = __longlong_as_double((long long)mx);
+        const int stop = lbp_decide(d, G);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            W.res[2] = d;
+            W.ctl[1] = G.iters;
+            W.ctl[0] = stop;
+        }
+        if (stop)
+            return;
+    }
+    if (G.clear >= 0 && blockIdx.x == 0)
+        for (int k = threadIdx.x; k < kDeltaSlots; k += blockDim.x)
+            W.scal[G.clear * kDeltaSlots + k] = 0ull;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = t / kVarLanes, l = t % kVarLanes;
     const bool live = i < I.n;
@@ -106,10 +143,18 @@ __global__ void lbp_var_kernel(const LbpJob *jobs, double lambda, int final_pass
     if (live) {
         q0 = I.var_ptr[i];
         q1 = I.var_ptr[i + 1];
-        for (int q = q0 + l; q < q1; q += kVarLanes) {
-            const int w = W.vedge[q];
-            const double u = W.u[w & 0x7FFFFFFF];
-            part += w < 0 ? -u : u;
+        const double *su = W.uv;
+        // four signed messages of the lane per round, in flight together;
+        // the lane adds them in incidence order
+        for (int q = q0 + l; q < q1; q += kVarRound * kVarLanes) {
+            double uv[kVarRound];
+#pragma unroll
+            for (int k = 0; k < kVarRound; ++k)
+                uv[k] = q + k * kVarLanes < q1 ? su[q + k * kVarLanes] : 0.0;
+#pragma unroll
+            for (int k = 0; k < kVarRound; ++k)
+                if (q + k * kVarLanes < q1)
+                    part += uv[k];
         }
     }
     for (int off = kVarLanes / 2; off > 0; off >>= 1)
@@ -122,33 +167,29 @@ __global__ void lbp_var_kernel(const LbpJob *jobs, double lambda, int final_pass
         W.mag[i] = tanh(tot);
 }
 
-constexpr int kDeltaSlots = 64;
-
-// iteration control, one thread after each iteration: take the iteration's
-// largest |du| (the 64 slots), clear them for the next, count the
-// iteration, stop on convergence (ctl[0] = 1) or at max_iter (ctl[0] = 2)
-__global__ void lbp_judge_kernel(const LbpJob *jobs, double tol, int max_iter) {
+// iteration control at the end of a batch, one thread: the batch's last
+// iteration's largest |du| (its set of 64 slots), the iteration count, and
+// stop on convergence (ctl[0] = 1) or at max_iter (ctl[0] = 2)
+__global__ void lbp_judge_kernel(const LbpJob *jobs, LbpJudge G) {
     const LbpWork &W = jobs[blockIdx.y].W;
     if (W.ctl[0])
         return;
     unsigned long long mx = 0;
     for (int k = 0; k < kDeltaSlots; ++k) {
-        mx = W.scal[k] > mx ? W.scal[k] : mx;
-        W.scal[k] = 0ull;
+        const unsigned long long v = W.scal[G.judge * kDeltaSlots + k];
+        mx = v > mx ? v : mx;
     }
     const double d = __longlong_as_double((long long)mx);
     W.res[2] = d;
-    const int it = ++W.ctl[1];
-    if (d < tol)
-        W.ctl[0] = 1;
-    else if (it >= max_iter)
-        W.ctl[0] = 2;
+    W.ctl[1] = G.iters;
+    W.ctl[0] = lbp_decide(d, G);
 }
 
 // clause side: h_{j->a} = sigma_j T_{v_j} - u_{a->j}, then the new u for
 // every edge of a and the largest change; with final != 0 the clause moment
 // instead (u unchanged)
-__global__ void __launch_bounds__(256) lbp_clause_kernel(const LbpJob *jobs, double w, int final_pass, int gated) {
+__global__ void __launch_bounds__(256) lbp_clause_kernel(const LbpJob *jobs, double w, int final_pass, int gated,
+                                                         int set) {
     const LbpJob &J = jobs[blockIdx.y];
     const KsatDev &I = J.I;
     const LbpWork &W = J.W;
@@ -158,36 +199,68 @@ __global__ void __launch_bounds__(256) lbp_clause_kernel(const LbpJob *jobs, dou
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     double dmax = 0.0;
     if (a < I.m) {
-        double P[4], t[4], sg[4];
-        int k = 0;
+        // the clause's four addresses and messages as vector loads, then the
+        // four field totals together (a padding slot reads T_0 and drops it)
+        const uint4 ad = *reinterpret_cast<const uint4 *>(I.clause_addr + (size_t)a * 4);
+        double2 *up = reinterpret_cast<double2 *>(W.u + (size_t)a * 4);
+        const double2 u01 = up[0], u23 = up[1];
+        const uint32_t av[4] = {ad.x, ad.y, ad.z, ad.w};
+        const double uo[4] = {u01.x, u01.y, u23.x, u23.y};
+        int k = 4;
+#pragma unroll
+        for (int j = 3; j >= 0; --j)
+            if (av[j] >= 2u * (uint32_t)I.n)
+                k = j;
+        int vj[4];
+        double sg[4], tv[4];
+#pragma unroll
         for (int j = 0; j < 4; ++j) {
-            int v;
-            double sj;
-            if (!decode(I.clause_addr[(size_t)a * 4 + j], I.n, v, sj))
-                break;
-            t[j] = tanh(sj * W.T[v] - W.u[4 * a + j]);
-            P[j] = (1.0 - t[j]) / 2.0;
-            sg[j] = sj;
-            k = j + 1;
+            const bool neg = av[j] >= (uint32_t)I.n;
+            vj[j] = j < k ? (int)(neg ? av[j] - (uint32_t)I.n : av[j]) : 0;
+            sg[j] = neg ? -1.0 : 1.0;
         }
-        if (!final_pass) {
-            for (int j = 0; j < k; ++j) {
-                double prod = 1.0;
-                for (int l = 0; l < k; ++l)
-                    if (l != j)
-                        prod *= P[l];
-                const double un = -0.5 * log(1.0 - w * prod);
-                const double d = fabs(un - W.u[4 * a + j]);
-                dmax = d > dmax ? d : dmax;
-                W.u[4 * a + j] = un;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            tv[j] = W.T[vj[j]];
+        double P[4], t[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (j < k) {
+                t[j] = tanh(sg[j] * tv[j] - uo[j]);
+                P[j] = (1.0 - t[j]) / 2.0;
             }
+        if (!final_pass) {
+            double un[4] = {uo[0], uo[1], uo[2], uo[3]};
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (j < k) {
+                    double prod = 1.0;
+#pragma unroll
+                    for (int l = 0; l < 4; ++l)
+                        if (l < k && l != j)
+                            prod *= P[l];
+                    un[j] = -0.5 * log(1.0 - w * prod);
+                    const double d = fabs(un[j] - uo[j]);
+                    dmax = d > dmax ? d : dmax;
+                }
+            up[0] = make_double2(un[0], un[1]);
+            up[1] = make_double2(un[2], un[3]);
+            // the variable-major copies, sign applied (exact)
+            const int4 ep = *reinterpret_cast<const int4 *>(W.epos + (size_t)a * 4);
+            const int epv[4] = {ep.x, ep.y, ep.z, ep.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (j < k)
+                    W.uv[epv[j]] = sg[j] * un[j];
         } else {
             double sat = 1.0, viol = 1.0, pv = 1.0;
-            for (int j = 0; j < k; ++j) {
-                sat *= sg[j] * t[j];
-                viol *= -sg[j] * P[j];
-                pv *= P[j];
-            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (j < k) {
+                    sat *= sg[j] * t[j];
+                    viol *= -sg[j] * P[j];
+                    pv *= P[j];
+                }
             W.corr[a] = (sat - w * viol) / (1.0 - w * pv);
         }
     }
@@ -203,7 +276,7 @@ __global__ void __launch_bounds__(256) lbp_clause_kernel(const LbpJob *jobs, dou
             for (int k = 1; k < (int)(blockDim.x >> 6); ++k)
                 m = fmax(m, wmax[k]);
             if (m > 0.0)
-                atomic_max_nonneg(&W.scal[blockIdx.x % kDeltaSlots], m);
+                atomic_max_nonneg(&W.scal[set * kDeltaSlots + blockIdx.x % kDeltaSlots], m);
         }
     }
 }
@@ -369,29 +442,37 @@ hipError_t lbp_launch_setup(const LbpJob *jobs, const LbpDims &D, double lambda0
 }
 
 hipError_t lbp_launch_var(const LbpJob *jobs, const LbpDims &D, double lambda, int final_pass, hipStream_t s) {
+    const LbpJudge none{-1, -1, 0, 0, 0.0};
     if (D.max_n > 0)
         hipLaunchKernelGGL(lbp_var_kernel, dim3(blocks(D.max_n * kVarLanes), D.n_jobs), dim3(kLbpThreads), 0, s, jobs,
-                           lambda, final_pass, 0);
+                           lambda, final_pass, 0, none);
     return hipGetLastError();
 }
 
 hipError_t lbp_launch_clause(const LbpJob *jobs, const LbpDims &D, double w, int final_pass, hipStream_t s) {
     if (D.max_m > 0)
         hipLaunchKernelGGL(lbp_clause_kernel, dim3(blocks(D.max_m), D.n_jobs), dim3(kLbpThreads), 0, s, jobs, w,
-                           final_pass, 0);
+                           final_pass, 0, 0);
     return hipGetLastError();
 }
 
 hipError_t lbp_launch_iterations(const LbpJob *jobs, const LbpDims &D, double lambda, double w, double tol,
-                                 int max_iter, int count, hipStream_t s) {
-    for (int k = 0; k < count; ++k) {
+                                 int max_iter, int first, int count, hipStream_t s) {
+    // iteration k: the variable pass (judging iteration k - 1 within the
+    // batch, clearing slot set k & 1), then the clause pass into set k & 1
+    for (int k = first; k < first + count; ++k) {
+        const LbpJudge G{k > first ? (k - 1) & 1 : -1, k & 1, k, max_iter, tol};
         if (D.max_n > 0)
             hipLaunchKernelGGL(lbp_var_kernel, dim3(blocks(D.max_n * kVarLanes), D.n_jobs), dim3(kLbpThreads), 0, s,
-                               jobs, lambda, 0, 1);
+                               jobs, lambda, 0, 1, G);
         if (D.max_m > 0)
             hipLaunchKernelGGL(lbp_clause_kernel, dim3(blocks(D.max_m), D.n_jobs), dim3(kLbpThreads), 0, s, jobs, w, 0,
-                               1);
-        hipLaunchKernelGGL(lbp_judge_kernel, dim3(1, D.n_jobs), dim3(1), 0, s, jobs, tol, max_iter);
+                               1, k & 1);
+    }
+    if (count > 0) {
+        const int last = first + count - 1;
+        hipLaunchKernelGGL(lbp_judge_kernel, dim3(1, D.n_jobs), dim3(1), 0, s, jobs,
+                           LbpJudge{last & 1, -1, last + 1, max_iter, tol});
     }
     return hipGetLastError();
 }
