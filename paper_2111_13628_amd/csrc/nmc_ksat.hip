@@ -21,6 +21,7 @@
 // equals the sequential colour-major order.  The instance (per-variable
 // clause records) streams from L2/MALL, shared by every workgroup.
 #include <climits>
+#include <cstdlib>
 
 #include "nmc_internal.h"
 #include "nmc_philox.h"
@@ -152,7 +153,10 @@ __device__ __forceinline__ void slot_step2(uint32_t &a0, uint32_t &a1, uint2 r) 
 // and 2g + 1, held in one spin byte per variable (first group in bits 0..3),
 // so every clause record, address decode and LDS gather serves 8 replicas;
 // the random words and every result are those of the groups run one by one.
-template <int GPW>
+// STAGED: the instance's records and chunk tables are copied into LDS at the
+// start (instances small enough for them to fit beside the spin tables), so
+// a colour class's loads are LDS reads instead of L2 round trips.
+template <int GPW, bool STAGED = false>
 __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &R, const SweepCall &C, const int g,
                                             uint8_t *smem) {
     constexpr int NR = kGroup * GPW;  // replicas of the item
@@ -213,6 +217,25 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
     }
     if (tid < 16)
         red[tid] = 0;
+    // staged instance: records, chunk descriptors, lane words, class ranges
+    uint4 *s_rec = nullptr;
+    int2 *s_info = nullptr;
+    int *s_var = nullptr, *s_cc = nullptr;
+    if constexpr (STAGED) {
+        uint8_t *st = (uint8_t *)(red + 16);
+        s_rec = (uint4 *)st;
+        s_info = (int2 *)(st + align_up(I.rec_bytes, 16));
+        s_var = (int *)((uint8_t *)s_info + align_up((size_t)I.n_chunks * 8, 16));
+        s_cc = s_var + (size_t)I.n_chunks * kChunk;
+        for (int w = tid; w < (int)(I.rec_bytes / 16); w += nthr)
+            s_rec[w] = reinterpret_cast<const uint4 *>(I.rec)[w];
+        for (int w = tid; w < I.n_chunks; w += nthr)
+            s_info[w] = I.chunk_info[w];
+        for (int w = tid; w < I.n_chunks * kChunk / 4; w += nthr)
+            reinterpret_cast<int4 *>(s_var)[w] = reinterpret_cast<const int4 *>(I.chunk_var)[w];
+        for (int w = tid; w <= I.n_colors; w += nthr)
+            s_cc[w] = I.color_chunk[w];
+    }
     int E = 0, best = 0, fh = -1;
     if (tid < nact) {
         E = R.energy[r0 + tid];
@@ -239,7 +262,7 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
         for (int j = 0; j < NR; ++j)
             dsum[j] = 0;
         for (int c = 0; c < I.n_colors; ++c) {
-            const int h0 = I.color_chunk[c], h1 = I.color_chunk[c + 1];
+            const int h0 = STAGED ? s_cc[c] : I.color_chunk[c], h1 = STAGED ? s_cc[c + 1] : I.color_chunk[c + 1];
             // chunks of a class are sorted by slot count (descending); rounds
             // alternate direction so heavy and light chunks pair up per wave
             const int nch = h1 - h0;
@@ -256,10 +279,10 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
                     __builtin_amdgcn_s_sleep(4);
                 if (wave_u & 1)
                     __builtin_amdgcn_s_sleep(2);
-                const int2 info = I.chunk_info[h];
+                const int2 info = STAGED ? s_info[h] : I.chunk_info[h];
                 const int nslot = __builtin_amdgcn_readfirstlane(info.y & ((1 << kSplitShift) - 1));
                 const int lg = __builtin_amdgcn_readfirstlane(info.y >> kSplitShift);
-                const int lw = I.chunk_var[(size_t)h * kChunk + lane];
+                const int lw = STAGED ? s_var[h * kChunk + lane] : I.chunk_var[(size_t)h * kChunk + lane];
                 // with lg > 0 a variable's clauses are spread over 2^lg lanes;
                 // the first of them takes the decision
                 const int v = (lw < 0 || (lane & ((1 << lg) - 1))) ? -1 : (lw & 0xFFFFF);
@@ -271,6 +294,8 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
                 // instruction computes a record address
                 const int row0 = __builtin_amdgcn_readfirstlane(info.x) / 2;
                 auto rp = [&](int row) -> uint4 {
+                    if constexpr (STAGED)
+                        return s_rec[(row0 + row) * kChunk + lane];
                     return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
                                                          recs, lane * 16, (row0 + row) * (kChunk * 16), 0));
                 };
@@ -293,6 +318,18 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
                 uint4 q0 = rp(0), q1 = rp(min(1, lastp));
                 uint4 q2 = rp(min(2, lastp)), q3 = rp(min(3, lastp));
                 issue_fence();
+                // staged (small, latency-bound) instances draw the group's
+                // random words while the first records load, off the decision's
+                // critical path (the same words: they depend only on the
+                // variable, the sweep and the group)
+                uint4 u_pre = make_uint4(0, 0, 0, 0);
+                if constexpr (STAGED) {
+                    if (v >= 0)
+                        u_pre = philox4x32_10((uint32_t)v, t, (uint32_t)g0, kStreamKsatSweep, C.key0, C.key1);
+                    // an empty register constraint keeps the compiler from
+                    // sinking the computation back to its use
+                    __asm__ volatile("" : "+v"(u_pre.x), "+v"(u_pre.y), "+v"(u_pre.z), "+v"(u_pre.w));
+                }
                 // whole groups of 8 slots with one exit, then a tail of 4
                 int k = 0;
                 for (; k + 2 * kSlotUnroll <= nslot; k += 2 * kSlotUnroll) {
@@ -346,8 +383,9 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
                     for (int k = 0; k < GPW; ++k) {
                         // one generator call per group gives its 4 replicas' words
                         if ((need >> (4 * k)) & 0xFu) {
-                            const uint4 u = philox4x32_10((uint32_t)v, t, (uint32_t)(g0 + k), kStreamKsatSweep,
-                                                          C.key0, C.key1);
+                            const uint4 u = STAGED ? u_pre
+                                                   : philox4x32_10((uint32_t)v, t, (uint32_t)(g0 + k),
+                                                                   kStreamKsatSweep, C.key0, C.key1);
                             const int b = 4 * k;
                             flip |= (((need >> b) & 1u) && u.x < thr[b]) ? 1u << b : 0u;
                             flip |= (((need >> (b + 1)) & 1u) && u.y < thr[b + 1]) ? 2u << b : 0u;
@@ -462,6 +500,13 @@ template <int GPW>
 __global__ void __launch_bounds__(1024) ksat_sweep_kernel(KsatDev I, KsatRepDev R, SweepCall C) {
     extern __shared__ __align__(16) uint8_t smem[];
     sweep_group<GPW>(I, R, C, blockIdx.x, smem);
+}
+
+// The same with the instance staged in LDS (one group of 4 replicas per
+// workgroup).
+__global__ void __launch_bounds__(1024) ksat_sweep_staged_kernel(KsatDev I, KsatRepDev R, SweepCall C) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    sweep_group<1, true>(I, R, C, blockIdx.x, smem);
 }
 
 // Batched launch: many replica sets (jobs) of different instances in one
@@ -670,6 +715,20 @@ size_t ksat_sweep_lds_bytes(int n, int n_classes, int stride) {
     return align_up(2 * (size_t)n + 2, 16) + align_up((size_t)n_classes * stride, 4) * 4 + 16 * sizeof(int);
 }
 
+// LDS of the staged instance (records, chunk descriptors, lane words, class
+// ranges), placed after the block above
+static size_t ksat_staged_bytes(const KsatDev &I) {
+    return align_up(I.rec_bytes, 16) + align_up((size_t)I.n_chunks * 8, 16) + (size_t)I.n_chunks * kChunk * 4 +
+           align_up(((size_t)I.n_colors + 1) * 4, 16);
+}
+
+// small instances take the staged kernel unless NMC_KSAT_STAGE=0 (read at
+// every launch, so a process can compare the two)
+static bool ksat_stage_enabled() {
+    const char *e = std::getenv("NMC_KSAT_STAGE");
+    return !(e && e[0] == '0');
+}
+
 hipError_t launch_set_status(const SetStatusSrc *src, SetStatus *out, int n_sets, hipStream_t s) {
     hipLaunchKernelGGL(set_status_kernel, dim3(n_sets), dim3(256), 0, s, src, out);
     return hipGetLastError();
@@ -718,8 +777,15 @@ hipError_t ksat_launch_sweep(const KsatDev &I, const KsatRepDev &R, const SweepC
     }();
     if (attr != hipSuccess)
         return attr;
+    static const hipError_t attr_staged = hipFuncSetAttribute(
+        (const void *)ksat_sweep_staged_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
+    if (attr_staged != hipSuccess)
+        return attr_staged;
+    const size_t staged = lds + ksat_staged_bytes(I);
     if (C.gpw == 2)
         hipLaunchKernelGGL(ksat_sweep_kernel<2>, dim3((R.n_groups + 1) / 2), dim3(block_threads), lds, s, I, R, C);
+    else if (staged <= kLdsBytes && ksat_stage_enabled())
+        hipLaunchKernelGGL(ksat_sweep_staged_kernel, dim3(R.n_groups), dim3(block_threads), staged, s, I, R, C);
     else
         hipLaunchKernelGGL(ksat_sweep_kernel<1>, dim3(R.n_groups), dim3(block_threads), lds, s, I, R, C);
     return hipGetLastError();

@@ -29,6 +29,24 @@ def test_plain_sa_n200_r64_1000_sweeps():
     p.compare()
 
 
+@pytest.mark.parametrize("stage", ["0", "1"])
+def test_staged_instance_kernel(stage, monkeypatch):
+    """Instances whose records fit in LDS beside the spin tables take the
+    staged kernel (records and chunk tables copied into LDS at the start);
+    NMC_KSAT_STAGE=0 keeps the streamed kernel.  Both bit-exact vs the oracle
+    over an anneal and a backbone reanneal, with a partial replica group."""
+    monkeypatch.setenv("NMC_KSAT_STAGE", stage)
+    say(f"case: staged={stage} n=150 R=22")
+    n = 150
+    cp, lits = instances.gen_ksat(n, "9.6", 4, SEED + 5)
+    p = KsatPair(n, cp, lits, 22, SEED + 6)
+    p.anneal(instances.linear_schedule(0.1, 4.0, 60)[None, :], target=2)
+    p.compare()
+    cls = p.backbone(9, 10, expand=True)
+    p.anneal(reanneal_profile(20), profile="backbone", class_of=cls, target=1)
+    p.compare()
+
+
 @pytest.mark.parametrize("n,alpha,k,R,cap", [(300, "9.6", 4, 38, 0), (700, "4.15", 3, 21, 64),
                                              (2100, "9.9", 4, 12, 128), (120, "9.6", 4, 9, 1)])
 def test_nmc_rounds_ragged(n, alpha, k, R, cap):
