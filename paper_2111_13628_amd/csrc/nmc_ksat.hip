@@ -37,6 +37,26 @@ __device__ __forceinline__ int wave_sum(int v) {
     return v;
 }
 
+// Sum over each group of 2^lg lanes (lg wave-uniform, at most 6), returned to
+// every lane of the group: swaps within quads, the mirrors within half-rows
+// and rows (register moves, no LDS crossbar), then shuffles across rows.
+// Sums mod 2^32, so the order does not matter.
+__device__ __forceinline__ uint32_t lane_group_sum(uint32_t x, int lg) {
+    if (lg >= 1)
+        x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    if (lg >= 2)
+        x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    if (lg >= 3)
+        x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    if (lg >= 4)
+        x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x140, 0xF, 0xF, false);  // row_mirror
+    if (lg >= 5)
+        x += (uint32_t)__shfl_xor((int)x, 16, 64);
+    if (lg >= 6)
+        x += (uint32_t)__shfl_xor((int)x, 32, 64);
+    return x;
+}
+
 __device__ __forceinline__ uint32_t spread4(uint32_t f) {
     // bit j of f (j < 4) -> bit 8j; no carries for f < 16
     return (f * 0x00204081u) & 0x01010101u;
@@ -218,7 +238,7 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
     if (tid < 16)
         red[tid] = 0;
     // staged instance: records, chunk descriptors, lane words, class ranges
-    uint4 *s_rec = nullptr;
+    uint4 *s_rec = nullptr, *s_u = nullptr;
     int2 *s_info = nullptr;
     int *s_var = nullptr, *s_cc = nullptr;
     if constexpr (STAGED) {
@@ -227,6 +247,8 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
         s_info = (int2 *)(st + align_up(I.rec_bytes, 16));
         s_var = (int *)((uint8_t *)s_info + align_up((size_t)I.n_chunks * 8, 16));
         s_cc = s_var + (size_t)I.n_chunks * kChunk;
+        // each variable's random words of the current sweep
+        s_u = (uint4 *)((uint8_t *)s_cc + align_up(((size_t)I.n_colors + 1) * 4, 16));
         for (int w = tid; w < (int)(I.rec_bytes / 16); w += nthr)
             s_rec[w] = reinterpret_cast<const uint4 *>(I.rec)[w];
         for (int w = tid; w < I.n_chunks; w += nthr)
@@ -255,6 +277,15 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
         const uint32_t *tg = tab + (size_t)s * C.sweep_words;
         for (int i = tid; i < tab_words; i += nthr)
             tl[i] = tg[i];
+        if constexpr (STAGED) {
+            // a staged (small, latency-bound) instance draws the sweep's
+            // random words of every variable at once, spread over the whole
+            // workgroup, instead of one dependent generator chain per colour
+            // class (the words depend only on the variable, the sweep and the
+            // group, so drawing them for every variable changes nothing)
+            for (int w = tid; w < n; w += nthr)
+                s_u[w] = philox4x32_10((uint32_t)w, t, (uint32_t)g0, kStreamKsatSweep, C.key0, C.key1);
+        }
         __syncthreads();
 
         int dsum[NR];
@@ -318,18 +349,6 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
                 uint4 q0 = rp(0), q1 = rp(min(1, lastp));
                 uint4 q2 = rp(min(2, lastp)), q3 = rp(min(3, lastp));
                 issue_fence();
-                // staged (small, latency-bound) instances draw the group's
-                // random words while the first records load, off the decision's
-                // critical path (the same words: they depend only on the
-                // variable, the sweep and the group)
-                uint4 u_pre = make_uint4(0, 0, 0, 0);
-                if constexpr (STAGED) {
-                    if (v >= 0)
-                        u_pre = philox4x32_10((uint32_t)v, t, (uint32_t)g0, kStreamKsatSweep, C.key0, C.key1);
-                    // an empty register constraint keeps the compiler from
-                    // sinking the computation back to its use
-                    __asm__ volatile("" : "+v"(u_pre.x), "+v"(u_pre.y), "+v"(u_pre.z), "+v"(u_pre.w));
-                }
                 // whole groups of 8 slots with one exit, then a tail of 4
                 int k = 0;
                 for (; k + 2 * kSlotUnroll <= nslot; k += 2 * kSlotUnroll) {
@@ -360,8 +379,11 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
 #pragma unroll
                 for (int k = 0; k < GPW; ++k) {
                     uint32_t part = ((uint32_t)nslot - 2u * nneg) * 0x01010101u - nneg - acc[k];
-                    for (int off = 1; off < (1 << lg); off <<= 1)
-                        part += (uint32_t)__shfl_xor((int)part, off, 64);
+                    if constexpr (STAGED)
+                        part = lane_group_sum(part, lg);
+                    else
+                        for (int off = 1; off < (1 << lg); off <<= 1)
+                            part += (uint32_t)__shfl_xor((int)part, off, 64);
                     acc[k] = 0x80808080u + part;
                 }
                 if (v >= 0) {
@@ -383,7 +405,7 @@ __device__ __forceinline__ void sweep_group(const KsatDev &I, const KsatRepDev &
                     for (int k = 0; k < GPW; ++k) {
                         // one generator call per group gives its 4 replicas' words
                         if ((need >> (4 * k)) & 0xFu) {
-                            const uint4 u = STAGED ? u_pre
+                            const uint4 u = STAGED ? s_u[v]
                                                    : philox4x32_10((uint32_t)v, t, (uint32_t)(g0 + k),
                                                                    kStreamKsatSweep, C.key0, C.key1);
                             const int b = 4 * k;
@@ -716,10 +738,10 @@ size_t ksat_sweep_lds_bytes(int n, int n_classes, int stride) {
 }
 
 // LDS of the staged instance (records, chunk descriptors, lane words, class
-// ranges), placed after the block above
+// ranges, the sweep's random words per variable), placed after the block above
 static size_t ksat_staged_bytes(const KsatDev &I) {
     return align_up(I.rec_bytes, 16) + align_up((size_t)I.n_chunks * 8, 16) + (size_t)I.n_chunks * kChunk * 4 +
-           align_up(((size_t)I.n_colors + 1) * 4, 16);
+           align_up(((size_t)I.n_colors + 1) * 4, 16) + (size_t)I.n * 16;
 }
 
 // small instances take the staged kernel unless NMC_KSAT_STAGE=0 (read at
