@@ -128,7 +128,7 @@ def run_path(inst, seed, target, nmc, stream=None, profile=False):
     return rep, be
 
 
-def bench_batch(nmc, torch, seed, n_instances=256):
+def bench_batch(nmc, torch, seed, n_instances=256, tune_sweeps=2):
     """Batched NMC on mixed k-SAT instances (256 by default; k in {3,4}, N
     log-uniform in [1000, 20000], replicas 64..512 by N) in one graph-captured
     plan, against plain simulated annealing launched once per instance."""
@@ -150,7 +150,7 @@ def bench_batch(nmc, torch, seed, n_instances=256):
     # targets: 10th percentile of a calibration plain-SA run (other seeds)
     cal = make(7777)
     cb = nmc.Batch(cal)
-    cb.tune(2)
+    cb.tune(tune_sweeps)
     cb.anneal(sa_beta[None, :])
     targets = np.array([int(np.percentile(s.best_energy()["energy"], 10)) for s in cal], np.int64)
     cb.free()
@@ -177,7 +177,7 @@ def bench_batch(nmc, torch, seed, n_instances=256):
     # (2) plain SA, all instances in one batched launch sequence (lockstep chunks)
     sets = make(0)
     bt = nmc.Batch(sets)
-    block = bt.tune(2)
+    block = bt.tune(tune_sweeps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     bt.run_plan(sa_beta, 0, r_beta, 9, 10, True, targets=targets, use_graph=True, chunk_sweeps=CHUNK)
@@ -192,7 +192,7 @@ def bench_batch(nmc, torch, seed, n_instances=256):
     # (3) NMC, all instances in one graph: anneal -> 2 x (backbone -> reanneal)
     sets = make(0)
     bn = nmc.Batch(sets)
-    bn.tune(2)  # workgroup size and, per set, 4 or 8 replicas per workgroup
+    bn.tune(tune_sweeps)  # workgroup size and, per set, 4 or 8 replicas per workgroup
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     bn.run_plan(a_beta, RND, r_beta, 9, 10, True, targets=targets, use_graph=True, chunk_sweeps=CHUNK)
@@ -887,6 +887,8 @@ def main():
                          "surrogate backbones on the N=50000 instance; alg1: tempering -> seeds -> per-seed "
                          "LBP backbones -> batched inhomogeneous MC and unlearning; wide: the NMC path on a "
                          "N=1,000,000 instance (the wide layout)")
+    ap.add_argument("--tune-sweeps", type=int, default=2,
+                    help="with --workload batch: sweeps of each autotuner probe launch")
     ap.add_argument("--pt-rounds", type=int, default=APT_ROUNDS)
     ap.add_argument("--pt-sweeps-per-round", type=int, default=1)
     ap.add_argument("--serve-seconds", type=float, default=SERVE_SECONDS)
@@ -999,7 +1001,7 @@ def main():
                           "serve": res}), flush=True)
         return
     if args.workload == "batch":
-        res = bench_batch(nmc, torch, seed)
+        res = bench_batch(nmc, torch, seed, tune_sweeps=args.tune_sweeps)
         print(json.dumps({"metric": "batched NMC vs one-launch-per-instance plain SA: attempts/s and time-to-target",
                           "value": res["batched_nmc"]["attempts_per_s"], "unit": "attempts/s", "n_gpus": 1,
                           "higher_is_better": True, "dtype": "int32", "data": "synthetic",
