@@ -182,6 +182,10 @@ struct nmc_instance {
     // layout offsets into the device arena
     size_t off_rec = 0, off_chunk_var = 0, off_chunk_info = 0, off_color_chunk = 0, off_clause_addr = 0,
            off_var_ptr = 0, off_var_cl = 0;
+    // LBP clause order (clauses sorted by their smallest variable): the
+    // clauses' literal addresses in that order and each clause's position
+    size_t off_lbp_caddr = 0, off_lbp_pos = 0;
+    std::vector<int32_t> lbp_pos;
     uint32_t rec_bytes = 0;  // size of the record array
     // wide layout (spins in device memory; see nmc_ksat_wide.hip)
     bool wide = false;
@@ -212,6 +216,8 @@ struct nmc_instance {
         d.clause_addr = reinterpret_cast<const uint32_t *>(dev + off_clause_addr);
         d.var_ptr = reinterpret_cast<const int32_t *>(dev + off_var_ptr);
         d.var_cl = reinterpret_cast<const int32_t *>(dev + off_var_cl);
+        d.lbp_caddr = reinterpret_cast<const uint32_t *>(dev + off_lbp_caddr);
+        d.lbp_pos = reinterpret_cast<const int32_t *>(dev + off_lbp_pos);
         d.wrec = reinterpret_cast<const uint4 *>(dev + off_wrec);
         d.worder = reinterpret_cast<const int32_t *>(dev + off_worder);
         d.wclass_ptr = reinterpret_cast<const int32_t *>(dev + off_wclass);
@@ -637,6 +643,30 @@ int nmc_ksat_load(int32_t n_vars, int32_t n_clauses, const int32_t *clause_ptr, 
             for (int32_t p = clause_ptr[a]; p < clause_ptr[a + 1]; ++p)
                 clause_addr[(size_t)a * 4 + k++] = lit_addr(lits[p]);
         }
+        // LBP clause order: a stable counting sort by smallest variable, so
+        // the clauses a workgroup of the clause pass takes share variables
+        // (their field reads and message writes then fall in the same cache
+        // lines); the literal order inside a clause is kept
+        std::vector<uint32_t> lbp_caddr;
+        if (!I->wide) {
+            std::vector<int32_t> first(m), start((size_t)n + 1, 0);
+            for (int32_t a = 0; a < m; ++a) {
+                int32_t mv = n;
+                for (int32_t p = clause_ptr[a]; p < clause_ptr[a + 1]; ++p)
+                    mv = std::min(mv, std::abs(lits[p]) - 1);
+                first[a] = mv;
+                ++start[(size_t)mv + 1];
+            }
+            for (int32_t v = 0; v < n; ++v)
+                start[(size_t)v + 1] += start[v];
+            I->lbp_pos.assign(m, 0);
+            lbp_caddr.assign((size_t)m * 4, ZERO);
+            for (int32_t a = 0; a < m; ++a) {
+                const int32_t t = start[first[a]]++;
+                I->lbp_pos[a] = t;
+                std::memcpy(&lbp_caddr[(size_t)t * 4], &clause_addr[(size_t)a * 4], 16);
+            }
+        }
 
         Arena ar;
         I->off_rec = ar.take(rec.size() * 8);
@@ -647,6 +677,10 @@ int nmc_ksat_load(int32_t n_vars, int32_t n_clauses, const int32_t *clause_ptr, 
         I->off_clause_addr = ar.take(std::max<size_t>(clause_addr.size() * 4, 16));
         I->off_var_ptr = ar.take(vptr.size() * 4);
         I->off_var_cl = ar.take(std::max<size_t>(vcl.size() * 4, 4));
+        if (!I->wide) {
+            I->off_lbp_caddr = ar.take(std::max<size_t>(lbp_caddr.size() * 4, 16));
+            I->off_lbp_pos = ar.take(std::max<size_t>(I->lbp_pos.size() * 4, 4));
+        }
         if (I->wide) {
             I->off_wrec = ar.take(std::max<size_t>(wrec.size() * sizeof(uint4), 16));
             I->off_worder = ar.take((size_t)n * 4);
@@ -665,6 +699,10 @@ int nmc_ksat_load(int32_t n_vars, int32_t n_clauses, const int32_t *clause_ptr, 
         put(I->off_clause_addr, clause_addr.data(), clause_addr.size() * 4);
         put(I->off_var_ptr, vptr.data(), vptr.size() * 4);
         put(I->off_var_cl, vcl.data(), vcl.size() * 4);
+        if (!I->wide) {
+            put(I->off_lbp_caddr, lbp_caddr.data(), lbp_caddr.size() * 4);
+            put(I->off_lbp_pos, I->lbp_pos.data(), I->lbp_pos.size() * 4);
+        }
         if (I->wide) {
             put(I->off_wrec, wrec.data(), wrec.size() * sizeof(uint4));
             put(I->off_worder, I->order.data(), (size_t)n * 4);
@@ -2042,11 +2080,18 @@ static int lbp_impl(nmc_replicas *P, int32_t replica, int32_t which, const nmc_l
         HIP_OR_FAIL(hipMemcpyAsync(class_out, P->k.cls, n, hipMemcpyDeviceToHost, s));
     if (mag_out && n)
         HIP_OR_FAIL(hipMemcpyAsync(mag_out, runs[0].W.mag, (size_t)n * 8, hipMemcpyDeviceToHost, s));
-    if (corr_out && m)
-        HIP_OR_FAIL(hipMemcpyAsync(corr_out, runs[0].W.corr, (size_t)m * 8, hipMemcpyDeviceToHost, s));
+    // the moments are in the LBP clause order on the device
+    std::vector<double> corr_lbp;
+    if (corr_out && m) {
+        corr_lbp.resize(m);
+        HIP_OR_FAIL(hipMemcpyAsync(corr_lbp.data(), runs[0].W.corr, (size_t)m * 8, hipMemcpyDeviceToHost, s));
+    }
     if (label_out && n)
         HIP_OR_FAIL(hipMemcpyAsync(label_out, runs[0].W.out_label, (size_t)n * 4, hipMemcpyDeviceToHost, s));
     HIP_OR_FAIL(hipStreamSynchronize(s));
+    if (corr_out && m)
+        for (int32_t a = 0; a < m; ++a)
+            corr_out[a] = corr_lbp[I->lbp_pos[a]];
     if (res)
         lbp_fill_result(runs[0], *cfg, res);
     return ok();

@@ -61,6 +61,8 @@ struct KsatDev {
     const uint32_t *clause_addr; // [M][4] spin-table addresses of the clause's literals
     const int32_t *var_ptr;      // [N + 1] variable -> clause incidence
     const int32_t *var_cl;       // [sum deg]
+    const uint32_t *lbp_caddr;   // [M][4] clause_addr in the LBP clause order (clauses by smallest variable)
+    const int32_t *lbp_pos;      // [M] position of each clause in the LBP clause order
     int32_t n, m, n_colors, n_chunks, dmax;
     uint32_t rec_bytes;          // size of rec in bytes (the bound of the sweep's buffer loads)
     // wide layout (wide != 0; rec and the chunk arrays are then empty)

@@ -5,9 +5,14 @@
 // Transitions", appendix C; section "Generating backbones of rigid
 // variables").
 //
-// Spins r_i = 2 x_i - 1.  Edge e = 4a + j is literal j of clause a (the
-// clause's spin-table address decodes variable and sign; address 2N pads
-// clauses shorter than 4).  sigma_e = +1 for a positive literal.  With the
+// Spins r_i = 2 x_i - 1.  The clause side works in the instance's LBP clause
+// order (clauses sorted by their smallest variable, so the clauses of one
+// workgroup share variables and their field reads and message writes share
+// cache lines): a below is a position in that order, and edge e = 4a + j is
+// literal j of the clause there (the clause's spin-table address decodes
+// variable and sign; address 2N pads clauses shorter than 4); the variable
+// side keeps each variable's incidences in clause-index order.  sigma_e = +1
+// for a positive literal.  With the
 // field H_i = lambda eps_i s*_i (eps_i = clauses holding i) and the clause
 // weight exp(-2 beta) for a violated clause, one message iteration is
 //   T_i      = H_i + sum_{b in di} sigma_{ib} u_{b->i}           (per variable)
@@ -20,8 +25,8 @@
 // writes) and variable-major with its sign applied (sigma u at the edge's
 // position in the variable's incidence list, written by the clause kernel as
 // one scattered 8-byte store), so the variable kernel's sums read contiguous
-// memory instead of gathering one cache line per 8-byte message.  The largest |du| of an
-// iteration is a workgroup max, then an atomic max over the bit patterns of
+// memory instead of gathering one cache line per 8-byte message.  The largest
+// |du| of an iteration is a workgroup max, then an atomic max over the bit patterns of
 // non-negative doubles into one of 64 slots (two sets of slots, by iteration
 // parity).  Iterations are queued in batches without host round trips: the
 // variable pass of iteration k + 1 first decides on the device whether
@@ -88,7 +93,7 @@ __global__ void lbp_setup_kernel(const LbpJob *jobs, double lambda0) {
             if (ad == (uint32_t)i || ad == (uint32_t)(i + I.n))
                 break;
         }
-        W.epos[4 * a + j] = q;
+        W.epos[4 * I.lbp_pos[a] + j] = q;
     }
 }
 
@@ -201,7 +206,7 @@ __global__ void __launch_bounds__(256) lbp_clause_kernel(const LbpJob *jobs, dou
     if (a < I.m) {
         // the clause's four addresses and messages as vector loads, then the
         // four field totals together (a padding slot reads T_0 and drops it)
-        const uint4 ad = *reinterpret_cast<const uint4 *>(I.clause_addr + (size_t)a * 4);
+        const uint4 ad = *reinterpret_cast<const uint4 *>(I.lbp_caddr + (size_t)a * 4);
         double2 *up = reinterpret_cast<double2 *>(W.u + (size_t)a * 4);
         const double2 u01 = up[0], u23 = up[1];
         const uint32_t av[4] = {ad.x, ad.y, ad.z, ad.w};
@@ -332,7 +337,7 @@ __global__ void lbp_hook_kernel(const LbpJob *jobs, double cut) {
     for (int j = 0; j < 4; ++j) {
         int v;
         double s;
-        if (!decode(I.clause_addr[(size_t)a * 4 + j], I.n, v, s))
+        if (!decode(I.lbp_caddr[(size_t)a * 4 + j], I.n, v, s))
             break;
         vs[k++] = v;
         mn = min(mn, W.label[v]);
@@ -366,7 +371,7 @@ __global__ void lbp_seed_kernel(const LbpJob *jobs, double seed_thr) {
         return;
     int v;
     double s;
-    if (decode(I.clause_addr[(size_t)a * 4], I.n, v, s))
+    if (decode(I.lbp_caddr[(size_t)a * 4], I.n, v, s))
         W.seeded[W.label[v]] = 1;
 }
 
