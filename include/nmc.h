@@ -572,7 +572,8 @@ int nmc_batch_set_tuning(nmc_batch *batch, int32_t block_threads);
  * *chosen; (2) then per set, the replicas per workgroup (4, or 8 sharing each
  * spin byte; nmc_set_replicas_per_workgroup): the sets fall into up to four
  * classes by work (N x R), and each class in turn takes 8 when that makes the
- * batched probe at least 2 % faster.  Each set keeps its choice for later
+ * batched probe at least 1 % faster (each configuration is timed twice and
+ * the shorter time counts).  Each set keeps its choice for later
  * calls.  Results never depend on the tuning. */
 int nmc_batch_tune(nmc_batch *batch, int32_t probe_sweeps, int32_t *chosen, void *stream);
 

@@ -3559,13 +3559,21 @@ extern "C" int nmc_batch_tune(nmc_batch *B, int32_t probe_sweeps, int32_t *chose
             if (r)
                 return r;
             HIP_OR_FAIL(hipMemcpyAsync(B->dev, blob.host.data(), blob.host.size(), hipMemcpyHostToDevice, s));
-            HIP_OR_FAIL(hipEventRecord(e0, s));
-            r = enqueue_phase(B, built[0], s);
-            if (r)
-                return r;
-            HIP_OR_FAIL(hipEventRecord(e1, s));
-            HIP_OR_FAIL(hipEventSynchronize(e1));
-            HIP_OR_FAIL(hipEventElapsedTime(ms, e0, e1));
+            // the shorter of two timed runs (the clones' states move on, so
+            // the second run starts where the first ended)
+            float best = 0;
+            for (int rep = 0; rep < 2; ++rep) {
+                HIP_OR_FAIL(hipEventRecord(e0, s));
+                r = enqueue_phase(B, built[0], s);
+                if (r)
+                    return r;
+                HIP_OR_FAIL(hipEventRecord(e1, s));
+                HIP_OR_FAIL(hipEventSynchronize(e1));
+                float t = 0;
+                HIP_OR_FAIL(hipEventElapsedTime(&t, e0, e1));
+                best = rep == 0 ? t : std::min(best, t);
+            }
+            *ms = best;
             return NMC_OK;
         };
         // (1) the workgroup size, with 4 replicas per workgroup everywhere
@@ -3586,7 +3594,7 @@ extern "C" int nmc_batch_tune(nmc_batch *B, int32_t probe_sweeps, int32_t *chose
         }
         // (2) replicas per workgroup (4, or 8 sharing each spin byte), per
         // set: the sets fall into up to four classes by work (N x R), and each
-        // class takes 8 when that makes the whole batch at least 2 % faster
+        // class takes 8 when that makes the whole batch at least 1 % faster
         std::vector<int> gsel(ks.size(), 1);
         if (!rc) {
             B->block_threads = best_b;
@@ -3608,7 +3616,7 @@ extern "C" int nmc_batch_tune(nmc_batch *B, int32_t probe_sweeps, int32_t *chose
                     continue;
                 float ms = 0;
                 rc = time_config(&ms);
-                if (!rc && ms < 0.98f * best_ms) {
+                if (!rc && ms < 0.99f * best_ms) {
                     best_ms = ms;
                     for (size_t i = lo; i < hi; ++i)
                         gsel[ord[i]] = clones[ord[i]].gpw;
