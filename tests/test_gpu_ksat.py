@@ -29,17 +29,20 @@ def test_plain_sa_n200_r64_1000_sweeps():
     p.compare()
 
 
-@pytest.mark.parametrize("stage", ["0", "1"])
-def test_staged_instance_kernel(stage, monkeypatch):
+@pytest.mark.parametrize("stage,block", [("0", 0), ("1", 0), ("1", 64), ("1", 256)])
+def test_staged_instance_kernel(stage, block, monkeypatch):
     """Instances whose records fit in LDS beside the spin tables take the
     staged kernel (records and chunk tables copied into LDS at the start);
     NMC_KSAT_STAGE=0 keeps the streamed kernel.  Both bit-exact vs the oracle
-    over an anneal and a backbone reanneal, with a partial replica group."""
+    over an anneal and a backbone reanneal, with a partial replica group, at
+    the default workgroup size and at one and four waves per workgroup."""
     monkeypatch.setenv("NMC_KSAT_STAGE", stage)
-    say(f"case: staged={stage} n=150 R=22")
+    say(f"case: staged={stage} block={block} n=150 R=22")
     n = 150
     cp, lits = instances.gen_ksat(n, "9.6", 4, SEED + 5)
     p = KsatPair(n, cp, lits, 22, SEED + 6)
+    if block:
+        p.rep.set_tuning(block)
     p.anneal(instances.linear_schedule(0.1, 4.0, 60)[None, :], target=2)
     p.compare()
     cls = p.backbone(9, 10, expand=True)
