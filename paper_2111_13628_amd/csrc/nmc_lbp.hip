@@ -99,9 +99,11 @@ __global__ void lbp_setup_kernel(const LbpJob *jobs, double lambda0) {
 
 // variable side: T_i; with final != 0 also <r_i> = tanh T_i.  kVarLanes
 // lanes share a variable: each takes every kVarLanes-th incidence
-// (consecutive lanes read consecutive edge words), the partial sums meet by
-// butterfly shuffles inside the lane group.  With gated != 0 the launch does
-// nothing once the iteration control has stopped.
+// (consecutive lanes read consecutive variable-major messages), the partial
+// sums meet by butterfly shuffles inside the lane group.  With gated != 0
+// the launch does nothing once the iteration control has stopped; with
+// G.judge >= 0 it first decides on the previous iteration (see above) and
+// returns without writing T if that iteration ended the step.
 constexpr int kVarLanes = 16;
 constexpr int kDeltaSlots = kLbpDeltaSlots;
 constexpr int kVarRound = 4;
